@@ -1,0 +1,190 @@
+/*
+ * libdopinf: the data-parallel hot path of distributed Operator Inference
+ * (dOpInf, arXiv:2504.14338) on one AMD Instinct MI355X (gfx950).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Pointers without an `_h` suffix are DEVICE pointers; `_h` marks host
+ *    arrays.  All matrices are row-major with an explicit leading dimension.
+ *  - The caller owns every buffer and the stream (`stream` is a hipStream_t
+ *    passed as void*; NULL means the default stream).  The library never
+ *    allocates or frees device memory: scratch comes from a caller-provided
+ *    workspace `ws` of at least the size returned by the matching
+ *    `*_workspace` query, aligned to 256 bytes.
+ *  - Calls only enqueue work on `stream` and return; they do not synchronize
+ *    unless documented (dopinf_reduce with r_req == 0).  Separate streams may
+ *    be used concurrently with separate workspaces.
+ *  - Every call returns a status.  Argument errors return immediately with
+ *    nothing enqueued; the message is available from dopinf_last_error()
+ *    (thread-local).  Data-dependent conditions (non-finite data, a
+ *    non-positive Cholesky pivot, ...) are reported through device-side
+ *    status words that the caller reads after its own synchronization.
+ *
+ * Notation (paper): Q is n x k (rows: degrees of freedom, columns: the k
+ * snapshots), each state variable a contiguous block of rows; r reduced
+ * dimension; s = r(r+1)/2 quadratic terms; d = r + s + 1 operator columns.
+ */
+#ifndef DOPINF_H
+#define DOPINF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes --------------------------------------------------------- */
+#define DOPINF_OK 0
+#define DOPINF_E_ARG 1         /* invalid argument; nothing enqueued          */
+#define DOPINF_E_HIP 2         /* a HIP runtime call or launch failed         */
+#define DOPINF_E_WORKSPACE 3   /* workspace missing or too small               */
+#define DOPINF_E_RANK 4        /* lambda_r <= 0 or r > k                       */
+#define DOPINF_E_NOTSPD 5      /* non-positive Cholesky pivot                  */
+#define DOPINF_E_NONFINITE 6   /* NaN/Inf in data or results                   */
+#define DOPINF_E_NOSTABLE 7    /* no candidate passes the growth bound         */
+#define DOPINF_E_TIMEOUT 8     /* a device-wide barrier exceeded its spin cap  */
+
+/* ---- element types and options -------------------------------------------- */
+#define DOPINF_F64 0
+#define DOPINF_F32 1
+
+#define DOPINF_CENTER 1u  /* subtract each row's temporal mean                */
+#define DOPINF_SCALE 2u   /* divide each variable by its max |centered value|  */
+#define DOPINF_APPLY 4u   /* also overwrite Q with the transformed data        */
+
+#define DOPINF_GRAM_NATIVE 0  /* MFMA in the storage type (F64 or F32)       */
+#define DOPINF_GRAM_BF16X3 1  /* F32 data, split hi+lo bfloat16, 3 products  */
+
+#define DOPINF_MAX_VARS 64
+
+/* Per-candidate outcome written by dopinf_rollout. */
+#define DOPINF_ITEM_PASS 0        /* finite and growth < max_growth            */
+#define DOPINF_ITEM_NONFINITE 1   /* the rollout produced NaN/Inf              */
+#define DOPINF_ITEM_GROWTH 2      /* growth >= max_growth                      */
+#define DOPINF_ITEM_SOLVE 3       /* the regularized solve failed (not SPD)    */
+
+#define DOPINF_ROLLOUT_FULL 1u    /* no early exit: run every state            */
+
+const char* dopinf_last_error(void);
+const char* dopinf_version(void);
+
+/* ---- Step II: centering and scaling (Sec. 3.3) -----------------------------
+ * mean[i]  = (1/k) sum_t Q[i,t]                       (per row, if CENTER)
+ * scale[v] = max over rows i of variable v and all t of |Q[i,t] - mean[i]|
+ *            (if SCALE; 1 otherwise, and 1 with zero_range[v] = 1 when the
+ *            variable is constant).
+ * With APPLY, Q[i,t] <- (Q[i,t] - mean[i]) / scale[v] in place.
+ * Q: n x k, leading dimension ldq >= k, element type `dtype`; statistics are
+ * accumulated in double.  var_rows_h[0..nvars]: host array, var_rows_h[0] = 0,
+ * strictly increasing, var_rows_h[nvars] = n; nvars <= DOPINF_MAX_VARS.
+ * mean: n doubles; scale: nvars doubles; zero_range: nvars ints or NULL. */
+size_t dopinf_preprocess_workspace(int64_t n, int64_t k, int nvars);
+int dopinf_preprocess(void* stream, int dtype, void* Q, int64_t n, int64_t k,
+                      int64_t ldq, int nvars, const int64_t* var_rows_h,
+                      unsigned flags, double* mean, double* scale,
+                      int* zero_range, void* ws, size_t ws_bytes);
+
+/* ---- Step III: Gram matrix D = Qs^T Qs (Eq. (5)) ---------------------------
+ * Qs[i,t] = (Q[i,t] - mean[i]) * (1 / scale[v(i)]) formed on load when mean
+ * and scale are given (either may be NULL: no centering / no scaling).
+ * D: k x k doubles, leading dimension ldd >= k, written in full (symmetric).
+ * algo: DOPINF_GRAM_NATIVE (F64: FP64 MFMA; F32: FP32 MFMA) or
+ * DOPINF_GRAM_BF16X3 (F32 data only).  Reduced-precision forms accumulate in
+ * float over row slabs of at most 512 rows and sum slabs in double.
+ * Deterministic: no floating-point atomics; repeated calls give identical
+ * bits. */
+size_t dopinf_gram_workspace(int dtype, int algo, int64_t n, int64_t k);
+int dopinf_gram(void* stream, int dtype, int algo, const void* Q, int64_t n,
+                int64_t k, int64_t ldq, const double* mean, const double* scale,
+                int nvars, const int64_t* var_rows_h, double* D, int64_t ldd,
+                void* ws, size_t ws_bytes);
+
+/* Cross Gram C = X^T Y (the same kernel, no triangle symmetry): X is n x mx,
+ * Y is n x my (float64, leading dimensions ldx, ldy), C is mx x my (ldc).
+ * Used to project snapshots that are not part of D onto the reduced
+ * coordinates through Eq. (8) without forming the basis. */
+size_t dopinf_cross_gram_workspace(int64_t n, int64_t mx, int64_t my);
+int dopinf_cross_gram(void* stream, const double* X, int64_t ldx,
+                      const double* Y, int64_t ldy, int64_t n, int64_t mx,
+                      int64_t my, double* C, int64_t ldc, void* ws,
+                      size_t ws_bytes);
+
+/* ---- Step III: eigenpairs and basis-free reduced data (Eqs. (6)-(9)) ------
+ * D (k x k, symmetric, ldd) is read, not modified.
+ * lambda[0..k): all eigenvalues of D in descending order.
+ * Qhat: r x k (ldqh >= k) = Lambda_r^{1/2} U_r^T, i.e. T_r^T D (Eq. (8));
+ * Tr (NULL or k x r, ldtr >= r) = U_r Lambda_r^{-1/2}.
+ * Each eigenvector u_j is signed so that its largest-magnitude entry is
+ * positive (lowest index on a tie); when the two largest magnitudes agree
+ * to 1e-8 relative with opposite signs, the sign of sum_t (t+1) u_t decides.
+ * r_req > 0: r = r_req (no host synchronization).  r_req == 0: r is the
+ * smallest value whose retained energy (Eq. (9)) exceeds tau; the call then
+ * synchronizes `stream`.  r must be <= r_max (capacity of Qhat / Tr).
+ * r_out_h (host, may be NULL) receives r.  info (device int) receives
+ * DOPINF_OK, DOPINF_E_RANK (lambda_r <= k * 2^-52 * lambda_1, i.e. numerically
+ * zero), DOPINF_E_NONFINITE or
+ * DOPINF_E_TIMEOUT. */
+size_t dopinf_reduce_workspace(int64_t k, int r_max);
+int dopinf_reduce(void* stream, const double* D, int64_t k, int64_t ldd,
+                  int r_req, double tau, int r_max, int* r_out_h,
+                  double* lambda, double* Tr, int64_t ldtr, double* Qhat,
+                  int64_t ldqh, int* info, void* ws, size_t ws_bytes);
+
+/* ---- Step IV: regularized operator inference (Eqs. (11)-(13)) ------------
+ * For every reduced size r_g in r_list_h[0..n_r) (group g uses the first r_g
+ * rows of Qhat, r x k, ldqh) and every pair p in [0, n_pairs):
+ *   Dhat = [Qhat_1^T | quad(Qhat_1^T) | 1],  Qhat_1 = Qhat[:, 0:k-1],
+ *   Qhat_2 = Qhat[:, 1:k], quad() the non-redundant products in the order
+ *   (0,0),(0,1),...,(0,r-1),(1,1),...,
+ *   (Dhat^T Dhat + diag(beta1_h[p] x r, beta2_h[p] x s, beta1_h[p])) O^T
+ *     = Dhat^T Qhat_2^T,
+ * solved by Cholesky.  O = [A | H | c] (r_g x d_g, row-major) is stored at
+ * O + dopinf_operator_offset(n_r, r_list_h, n_pairs, g*n_pairs + p):
+ * groups in r_list order, pairs inside a group in the given order.
+ * status[item] (device ints, n_r * n_pairs) = DOPINF_OK or DOPINF_E_NOTSPD.
+ * r_g >= 1, k >= 2, n_pairs >= 1. */
+size_t dopinf_operator_offset(int n_r, const int* r_list_h, int n_pairs,
+                              int item);
+size_t dopinf_infer_workspace(int64_t k, int n_r, const int* r_list_h,
+                              int n_pairs);
+int dopinf_infer(void* stream, const double* Qhat, int64_t ldqh, int64_t k,
+                 int n_r, const int* r_list_h, int n_pairs,
+                 const double* beta1_h, const double* beta2_h, double* O,
+                 int* status, void* ws, size_t ws_bytes);
+
+/* ---- Step IV: ROM rollouts, scoring and selection (Sec. 3.5) -------------
+ * For every item of dopinf_infer's layout: qt_0 = Qhat[0:r_g, 0],
+ * qt_{t+1} = A qt_t + H quad(qt_t) + c for n_states states (qt_0 included).
+ * train_err[item] = max_{t < k_train} ||qt_t - qhat_t|| / ||qhat_t||;
+ * growth[item]    = max_{t,i} |qt_t[i] - m_i| / max_{t<k_train,i} |qhat_t[i] - m_i|
+ *                   with m the temporal mean of Qhat[0:r_g, 0:k_train];
+ * outcome[item]   = DOPINF_ITEM_*: pass iff every state is finite and
+ *                   growth < max_growth.  Without DOPINF_ROLLOUT_FULL a
+ *                   rollout stops as soon as its outcome is decided to be a
+ *                   failure (selection is unchanged; train_err/growth then
+ *                   hold the values reached so far).
+ * solve_status (NULL or dopinf_infer's status): items with a failed solve
+ * are not rolled out (outcome DOPINF_ITEM_SOLVE).
+ * best[g] (device ints, n_r): item index (within the whole layout) of the
+ * smallest train_err among passing items of group g, the first in layout
+ * order on ties, -1 if none passes.
+ * traj (NULL or n_states x r_g per item at
+ * dopinf_traj_offset(n_r, r_list_h, n_pairs, n_states, item)): the states,
+ * time-major; states after an early exit are NaN. */
+size_t dopinf_traj_offset(int n_r, const int* r_list_h, int n_pairs,
+                          int n_states, int item);
+size_t dopinf_rollout_workspace(int n_r, const int* r_list_h, int n_pairs,
+                                int64_t k_train);
+int dopinf_rollout(void* stream, int n_r, const int* r_list_h, int n_pairs,
+                   const double* O, const double* Qhat, int64_t ldqh,
+                   int64_t k_train, int n_states, double max_growth,
+                   unsigned flags, const int* solve_status, double* traj,
+                   double* train_err, double* growth, int* outcome, int* best,
+                   void* ws, size_t ws_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DOPINF_H */

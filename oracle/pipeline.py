@@ -129,12 +129,15 @@ def reduce_basis_free(lam, U, r):
 
     Qhat = T_r^T D (Eq. (8)) equals Lambda_r^{1/2} U_r^T exactly because
     D U_r = U_r Lambda_r (Eq. (6)); the second form is used (READING) and the
-    first is checked as an invariant.  Raises if lambda_r <= 0.
+    first is checked as an invariant.
+
+    READING: T_r needs lambda_r > 0; an eigenvalue at or below the rounding
+    level of the spectrum, k * u * lambda_1, counts as zero and is rejected.
     """
     if r < 1 or r > len(lam):
         raise ValueError("r out of range")
-    if not lam[r - 1] > 0:
-        raise ValueError("lambda_r <= 0: r exceeds the numerical rank of D")
+    if not lam[r - 1] > len(lam) * np.finfo(np.float64).eps * lam[0]:
+        raise ValueError("lambda_r is numerically zero: r exceeds the numerical rank of D")
     Ur = U[:, :r]
     Tr = Ur * (lam[:r] ** -0.5)[None, :]
     Qhat = (np.sqrt(lam[:r])[:, None]) * Ur.T

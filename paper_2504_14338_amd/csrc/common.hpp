@@ -1,0 +1,93 @@
+// Shared helpers of libdopinf: status codes, the thread-local error message,
+// argument checks and 64-lane wavefront reductions for gfx950.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/dopinf.h"
+
+namespace dopinf {
+
+// ---- error state ---------------------------------------------------------
+
+void set_error(const char* fmt, ...);
+int fail(int code, const char* fmt, ...);
+
+#define DOPINF_HIP(call)                                                        \
+  do {                                                                          \
+    hipError_t e_ = (call);                                                     \
+    if (e_ != hipSuccess)                                                       \
+      return ::dopinf::fail(DOPINF_E_HIP, "%s failed: %s (%s:%d)", #call,       \
+                            hipGetErrorString(e_), __FILE__, __LINE__);         \
+  } while (0)
+
+#define DOPINF_LAUNCHED()                                                       \
+  do {                                                                          \
+    hipError_t e_ = hipGetLastError();                                          \
+    if (e_ != hipSuccess)                                                       \
+      return ::dopinf::fail(DOPINF_E_HIP, "kernel launch failed: %s (%s:%d)",   \
+                            hipGetErrorString(e_), __FILE__, __LINE__);         \
+  } while (0)
+
+#define DOPINF_REQUIRE(cond, ...)                                               \
+  do {                                                                          \
+    if (!(cond)) return ::dopinf::fail(DOPINF_E_ARG, __VA_ARGS__);              \
+  } while (0)
+
+// ---- workspace carving -----------------------------------------------------
+
+// Bump allocator over a caller-provided workspace; every block 256-B aligned.
+struct Carver {
+  char* base;
+  size_t used = 0;
+  size_t cap;
+  Carver(void* b, size_t c) : base(static_cast<char*>(b)), cap(c) {}
+  template <class T>
+  T* take(size_t count) {
+    size_t off = (used + 255) & ~size_t(255);
+    used = off + count * sizeof(T);
+    return base ? reinterpret_cast<T*>(base + off) : nullptr;
+  }
+  bool ok() const { return used <= cap; }
+};
+
+inline size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// ---- device helpers --------------------------------------------------------
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Block-wide sum; every thread gets the total.  `red` holds >= nwaves doubles.
+// Summation order is fixed (wave tree, then waves in index order).
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  constexpr int NW = NT / 64;
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) t += red[i];
+  return t;
+}
+
+__device__ __forceinline__ bool finite_d(double x) { return isfinite(x); }
+
+}  // namespace dopinf

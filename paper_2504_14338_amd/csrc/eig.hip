@@ -1,0 +1,722 @@
+// Step III of dOpInf (arXiv:2504.14338, Sec. 3.4): eigenpairs of the Gram
+// matrix D (Eq. (6)), the retained-energy rank (Eq. (9)) and the reduced data
+// Qhat = Lambda_r^{1/2} U_r^T = T_r^T D (Eq. (8)) without the POD basis.
+//
+// Pipeline on one GPU (all float64):
+//  1. Householder reduction D = P T P^T to symmetric tridiagonal T, as ONE
+//     cooperative persistent kernel: workgroup g owns rows g, g+P, g+2P, ...
+//     of the trailing matrix (kept in LDS when they fit, else in the
+//     workspace).  Per column j: the owner of row j forms the reflector, a
+//     device-wide barrier publishes it, every workgroup forms its entries of
+//     p = tau * A v plus a partial v^T p, a second barrier, then every
+//     workgroup applies the rank-2 update A -= v w^T + w v^T to its rows.
+//  2. All k eigenvalues of T by multisection: one wave per eigenvalue, the
+//     64 lanes evaluate Sturm counts at 64 interior points per round.
+//  3. The top r eigenvectors of T by inverse iteration with partial-pivoting
+//     LU of T - lambda I; eigenvalues closer than 1e-10 ||T|| are treated as
+//     a cluster and orthogonalized against each other inside the iteration.
+//  4. Back-transformation u = P z (reflectors applied in reverse order), one
+//     workgroup per vector with z in LDS.
+//  5. Sign rule and Qhat / T_r formation.
+#include "common.hpp"
+
+namespace dopinf {
+namespace {
+
+constexpr int TNT = 256;            // threads of the tridiagonalization kernel
+constexpr int TCH = 8;              // rows reduced together in phase 2
+constexpr long kSpinLimit = 1L << 26;
+
+// ---------------------------------------------------------------------------
+// device-wide barrier for a cooperative launch (all workgroups resident)
+// ---------------------------------------------------------------------------
+__device__ bool grid_barrier(unsigned* bar, unsigned nblocks, unsigned& gen, int* abort_flag) {
+  __shared__ int ok_sh;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned target = (gen + 1) * nblocks;
+    long spins = 0;
+    int ok = 1;
+    while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(1);
+      if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 || ++spins > kSpinLimit) {
+        __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+    }
+    __threadfence();
+    ok_sh = ok;
+  }
+  __syncthreads();
+  ++gen;
+  return ok_sh != 0;
+}
+
+__global__ void zero_words_kernel(unsigned* p, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+// ---------------------------------------------------------------------------
+// 1. tridiagonalization
+// ---------------------------------------------------------------------------
+struct TridArgs {
+  const double* D;  // input, ldd
+  int64_t ldd;
+  double* A;        // workspace k x k: rows owned in global mode; row j = v_j
+  int64_t k;
+  int P;
+  int in_lds;
+  int rows_max;     // max rows owned by one workgroup
+  double* d;        // k diagonal
+  double* e;        // k-1 off-diagonal
+  double* tau;      // k
+  double* p;        // k
+  double* part;     // P
+  unsigned* bar;
+  int* abort_flag;
+};
+
+__global__ __launch_bounds__(TNT) void sytrd_kernel(TridArgs a) {
+  extern __shared__ double lds_rows[];
+  __shared__ double red[TNT / 64][TCH];
+  __shared__ double bc[4];
+  const int g = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int64_t k = a.k;
+  const int P = a.P;
+  unsigned gen = 0;
+
+  auto row_ptr = [&](int q) -> double* {
+    const int64_t i = g + int64_t(q) * P;
+    return a.in_lds ? (lds_rows + int64_t(q) * k) : (a.A + i * k);
+  };
+  const int nown = int((k - g + P - 1) / P) > 0 ? int((k - g + P - 1) / P) : 0;
+
+  // load owned rows of D
+  for (int q = 0; q < nown; ++q) {
+    const int64_t i = g + int64_t(q) * P;
+    double* dst = row_ptr(q);
+    for (int64_t l = tid; l < k; l += TNT) dst[l] = a.D[i * a.ldd + l];
+  }
+  __syncthreads();
+
+  for (int64_t j = 0; j + 1 < k; ++j) {
+    // ---- phase 1: reflector of row j (owned by g == j % P) ----------------
+    if (j % P == g) {
+      const int q = int(j / P);
+      double* row = row_ptr(q);
+      double ss = 0.0;
+      for (int64_t l = j + 2 + tid; l < k; l += TNT) ss += row[l] * row[l];
+      ss = block_sum<TNT>(ss, &red[0][0]);
+      const double alpha = row[j + 1];
+      __syncthreads();  // row may alias v_j's storage: read alpha before it is overwritten
+      double beta, tj, scal;
+      if (ss == 0.0) {
+        beta = alpha;
+        tj = 0.0;
+        scal = 0.0;
+      } else {
+        beta = -copysign(sqrt(alpha * alpha + ss), alpha);
+        tj = (beta - alpha) / beta;
+        scal = 1.0 / (alpha - beta);
+      }
+      double* vout = a.A + j * k;  // v_j lives in row j of the workspace
+      for (int64_t l = j + 2 + tid; l < k; l += TNT) {
+        const double x = (tj == 0.0) ? 0.0 : row[l] * scal;
+        vout[l] = x;
+        if (a.in_lds) row[l] = x;
+      }
+      if (tid == 0) {
+        vout[j + 1] = 1.0;
+        a.d[j] = row[j];
+        a.e[j] = beta;
+        a.tau[j] = tj;
+      }
+    }
+    if (!grid_barrier(a.bar, P, gen, a.abort_flag)) return;
+    const double tj = __hip_atomic_load(&a.tau[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (tj == 0.0) continue;
+    const double* v = a.A + j * k;
+
+    // ---- phase 2: p_i = tau * A[i, j+1:] . v[j+1:] for owned rows i > j --
+    double mypart = 0.0;
+    const int q0 = int((j + 1 - g + P - 1) / P) > 0 ? int((j + 1 - g + P - 1) / P) : 0;  // first owned row > j
+    for (int qb = q0; qb < nown; qb += TCH) {
+      const int nq = min(TCH, nown - qb);
+      double acc[TCH];
+#pragma unroll
+      for (int u = 0; u < TCH; ++u) acc[u] = 0.0;
+      for (int64_t l = j + 1 + tid; l < k; l += TNT) {
+        const double vl = v[l];
+#pragma unroll
+        for (int u = 0; u < TCH; ++u)
+          if (u < nq) acc[u] += row_ptr(qb + u)[l] * vl;
+      }
+#pragma unroll
+      for (int u = 0; u < TCH; ++u) acc[u] = wave_sum(acc[u]);
+      __syncthreads();
+      if ((tid & 63) == 0) {
+#pragma unroll
+        for (int u = 0; u < TCH; ++u) red[tid >> 6][u] = acc[u];
+      }
+      __syncthreads();
+      if (tid == 0) {
+        for (int u = 0; u < nq; ++u) {
+          double sacc = 0.0;
+#pragma unroll
+          for (int ww = 0; ww < TNT / 64; ++ww) sacc += red[ww][u];
+          const int64_t i = g + int64_t(qb + u) * P;
+          const double pi = tj * sacc;
+          a.p[i] = pi;
+          mypart += v[i] * pi;
+        }
+      }
+    }
+    if (tid == 0) a.part[g] = mypart;
+    if (!grid_barrier(a.bar, P, gen, a.abort_flag)) return;
+
+    // ---- phase 3: rank-2 update of owned rows ------------------------------
+    if (tid == 0) {
+      double s = 0.0;
+      for (int q = 0; q < P; ++q) s += a.part[q];
+      bc[0] = 0.5 * tj * s;
+    }
+    __syncthreads();
+    const double K = bc[0];
+    for (int q = q0; q < nown; ++q) {
+      const int64_t i = g + int64_t(q) * P;
+      double* row = row_ptr(q);
+      const double vi = v[i];
+      const double wi = a.p[i] - K * vi;
+      for (int64_t l = j + 1 + tid; l < k; l += TNT) {
+        const double vl = v[l];
+        const double wl = a.p[l] - K * vl;
+        row[l] -= vi * wl + wi * vl;
+      }
+    }
+    __syncthreads();
+  }
+  if (k >= 1 && (k - 1) % P == g) {
+    const double* row = row_ptr(int((k - 1) / P));
+    if (tid == 0) {
+      a.d[k - 1] = row[k - 1];
+      a.tau[k - 1] = 0.0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 2. eigenvalues of T by multisection (one wave per eigenvalue)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int sturm_count(const double* d, const double* e2, int64_t k, double x, double pivmin) {
+  int cnt = 0;
+  double q = d[0] - x;
+  if (fabs(q) <= pivmin) q = -pivmin;
+  cnt += (q < 0.0);
+  for (int64_t i = 1; i < k; ++i) {
+    q = (d[i] - x) - e2[i - 1] / q;
+    if (fabs(q) <= pivmin) q = -pivmin;
+    cnt += (q < 0.0);
+  }
+  return cnt;
+}
+
+__global__ void tri_prep_kernel(const double* d, const double* e, int64_t k, double* e2, double* bounds) {
+  // bounds[0] = gl, bounds[1] = gu, bounds[2] = pivmin, bounds[3] = tnorm,
+  // bounds[4] = nonfinite flag.  One block.
+  __shared__ double red[4];
+  double gl = INFINITY, gu = -INFINITY, emax = 0.0, bad = 0.0;
+  for (int64_t i = threadIdx.x; i < k; i += blockDim.x) {
+    const double el = (i > 0) ? fabs(e[i - 1]) : 0.0;
+    const double er = (i + 1 < k) ? fabs(e[i]) : 0.0;
+    gl = fmin(gl, d[i] - el - er);
+    gu = fmax(gu, d[i] + el + er);
+    if (i + 1 < k) {
+      e2[i] = e[i] * e[i];
+      emax = fmax(emax, e2[i]);
+    }
+    if (!isfinite(d[i]) || (i + 1 < k && !isfinite(e[i]))) bad = 1.0;
+  }
+  auto bred = [&](double v, bool mx) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      double w = __shfl_xor(v, o, 64);
+      v = mx ? fmax(v, w) : fmin(v, w);
+    }
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = red[0];
+    for (int i = 1; i < int(blockDim.x / 64); ++i) r = mx ? fmax(r, red[i]) : fmin(r, red[i]);
+    return r;
+  };
+  gl = bred(gl, false);
+  gu = bred(gu, true);
+  emax = bred(emax, true);
+  bad = bred(bad, true);
+  if (threadIdx.x == 0) {
+    const double tnorm = fmax(fabs(gl), fabs(gu));
+    const double eps = 2.220446049250313e-16;
+    const double safemin = 2.2250738585072014e-308;
+    const double pad = 2.0 * eps * tnorm * double(k) + 2.0 * safemin;
+    bounds[0] = gl - pad;
+    bounds[1] = gu + pad;
+    bounds[2] = safemin * fmax(1.0, emax);
+    bounds[3] = tnorm;
+    bounds[4] = bad;
+  }
+}
+
+// lambda_desc[k-1-m] = m-th smallest eigenvalue
+__global__ __launch_bounds__(256) void tri_bisect_kernel(const double* d, const double* e2, int64_t k,
+                                                         const double* bounds, double* lambda_desc) {
+  const int64_t m = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (m >= k) return;
+  double lo = bounds[0], hi = bounds[1];
+  const double pivmin = bounds[2];
+  const double tnorm = bounds[3];
+  const double eps = 2.220446049250313e-16;
+  for (int it = 0; it < 64; ++it) {
+    const double width = hi - lo;
+    if (width <= 2.0 * eps * fmax(fabs(lo), fabs(hi)) + pivmin || width <= 4.0 * eps * eps * tnorm) break;
+    const double x = lo + width * double(lane + 1) / 65.0;
+    const int c = sturm_count(d, e2, k, x, pivmin);
+    // largest lane with count <= m moves lo; smallest lane with count > m moves hi
+    const unsigned long long below = __ballot(c <= m);
+    const unsigned long long above = __ballot(c > m);
+    double nlo = lo, nhi = hi;
+    if (below) {
+      const int lb = 63 - __clzll(below);
+      nlo = __shfl(x, lb, 64);
+    }
+    if (above) {
+      const int la = __ffsll(above) - 1;
+      nhi = __shfl(x, la, 64);
+    }
+    if (nlo == lo && nhi == hi) break;  // no progress representable
+    lo = nlo;
+    hi = nhi;
+  }
+  if (lane == 0) lambda_desc[k - 1 - m] = 0.5 * (lo + hi);
+}
+
+// ---------------------------------------------------------------------------
+// 3. inverse iteration for the top r eigenvectors of T
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double hash_unit(uint64_t x) {
+  // SplitMix64 finalizer (Steele, Lea, Flood 2014) mapped to [-1, 1)
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  x ^= x >> 31;
+  return double(x >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
+// One thread per cluster of the top-r eigenvalues (descending order).
+// Scratch per thread: u0, u1, u2, mult (k each) and swap flags (k bytes).
+__global__ void tri_invit_kernel(const double* d, const double* e, int64_t k, int r, const double* lambda_desc,
+                                 const double* bounds, double* Z /* r x k */, double* scratch,
+                                 unsigned char* swaps) {
+  const int j0 = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j0 >= r) return;
+  const double tnorm = bounds[3];
+  const double eps = 2.220446049250313e-16;
+  const double ctol = 1e-10 * fmax(tnorm, 1e-300);
+  if (j0 > 0 && fabs(lambda_desc[j0 - 1] - lambda_desc[j0]) <= ctol) return;  // not first of its cluster
+  int j1 = j0 + 1;
+  while (j1 < r && fabs(lambda_desc[j1 - 1] - lambda_desc[j1]) <= ctol) ++j1;
+
+  double* u0 = scratch + size_t(j0) * 4 * k;
+  double* u1 = u0 + k;
+  double* u2 = u1 + k;
+  double* mu = u2 + k;
+  unsigned char* sw = swaps + size_t(j0) * k;
+  const double piv_floor = eps * fmax(tnorm, 1e-300);
+
+  for (int j = j0; j < j1; ++j) {
+    const double lam = lambda_desc[j];
+    // LU with partial pivoting of T - lam I (rows i, i+1 at elimination step i)
+    double x = d[0] - lam;            // current row, column i
+    double y = (k > 1) ? e[0] : 0.0;  // current row, column i+1
+    for (int64_t i = 0; i + 1 < k; ++i) {
+      const double sub = e[i];                 // row i+1, column i
+      const double dn = d[i + 1] - lam;        // row i+1, column i+1
+      const double sup = (i + 2 < k) ? e[i + 1] : 0.0;  // row i+1, column i+2
+      if (fabs(sub) > fabs(x)) {
+        // pivot row = row i+1
+        const double m = x / sub;
+        u0[i] = sub;
+        u1[i] = dn;
+        u2[i] = sup;
+        mu[i] = m;
+        sw[i] = 1;
+        x = y - m * dn;
+        y = -m * sup;
+      } else {
+        double piv = x;
+        if (fabs(piv) < piv_floor) piv = copysign(piv_floor, piv == 0.0 ? 1.0 : piv);
+        const double m = sub / piv;
+        u0[i] = piv;
+        u1[i] = y;
+        u2[i] = 0.0;
+        mu[i] = m;
+        sw[i] = 0;
+        x = dn - m * y;
+        y = sup;
+      }
+    }
+    {
+      double piv = x;
+      if (fabs(piv) < piv_floor) piv = copysign(piv_floor, piv == 0.0 ? 1.0 : piv);
+      u0[k - 1] = piv;
+      u1[k - 1] = 0.0;
+      u2[k - 1] = 0.0;
+    }
+    for (int64_t i = 0; i < k; ++i)
+      if (fabs(u0[i]) < piv_floor) u0[i] = copysign(piv_floor, u0[i] == 0.0 ? 1.0 : u0[i]);
+
+    double* z = Z + size_t(j) * k;
+    for (int64_t i = 0; i < k; ++i) z[i] = hash_unit(uint64_t(i) * 1315423911ull + uint64_t(j) * 2654435761ull + 7);
+    for (int it = 0; it < 5; ++it) {
+      // orthogonalize against earlier members of the cluster (modified Gram-Schmidt)
+      for (int p = j0; p < j; ++p) {
+        const double* zp = Z + size_t(p) * k;
+        double dot = 0.0;
+        for (int64_t i = 0; i < k; ++i) dot += zp[i] * z[i];
+        for (int64_t i = 0; i < k; ++i) z[i] -= dot * zp[i];
+      }
+      // forward: apply the row swaps and multipliers
+      for (int64_t i = 0; i + 1 < k; ++i) {
+        if (sw[i]) {
+          const double t = z[i];
+          z[i] = z[i + 1];
+          z[i + 1] = t;
+        }
+        z[i + 1] -= mu[i] * z[i];
+      }
+      // backward: upper triangular with two super-diagonals
+      z[k - 1] = z[k - 1] / u0[k - 1];
+      if (k > 1) z[k - 2] = (z[k - 2] - u1[k - 2] * z[k - 1]) / u0[k - 2];
+      for (int64_t i = k - 3; i >= 0; --i) z[i] = (z[i] - u1[i] * z[i + 1] - u2[i] * z[i + 2]) / u0[i];
+      // normalize (scale first to avoid overflow)
+      double amax = 0.0;
+      for (int64_t i = 0; i < k; ++i) amax = fmax(amax, fabs(z[i]));
+      if (!(amax > 0.0) || !isfinite(amax)) amax = 1.0;
+      double nrm = 0.0;
+      for (int64_t i = 0; i < k; ++i) {
+        z[i] /= amax;
+        nrm += z[i] * z[i];
+      }
+      nrm = sqrt(nrm);
+      for (int64_t i = 0; i < k; ++i) z[i] /= nrm;
+    }
+    for (int p = j0; p < j; ++p) {  // final orthogonalization in the cluster
+      const double* zp = Z + size_t(p) * k;
+      double dot = 0.0;
+      for (int64_t i = 0; i < k; ++i) dot += zp[i] * z[i];
+      for (int64_t i = 0; i < k; ++i) z[i] -= dot * zp[i];
+      double nrm = 0.0;
+      for (int64_t i = 0; i < k; ++i) nrm += z[i] * z[i];
+      nrm = sqrt(nrm);
+      for (int64_t i = 0; i < k; ++i) z[i] /= nrm;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 4. back-transformation u = H_0 H_1 ... H_{k-3} z (one workgroup per vector)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void backtransform_kernel(const double* A /* row j: v_j */, const double* tau,
+                                                            int64_t k, double* Z /* r x k in/out */) {
+  extern __shared__ double zs[];
+  __shared__ double red[4];
+  double* zg = Z + size_t(blockIdx.x) * k;
+  for (int64_t i = threadIdx.x; i < k; i += 256) zs[i] = zg[i];
+  __syncthreads();
+  for (int64_t j = k - 2; j >= 0; --j) {
+    const double tj = tau[j];
+    if (tj == 0.0) continue;
+    const double* v = A + j * k;
+    double s = 0.0;
+    for (int64_t l = j + 1 + threadIdx.x; l < k; l += 256) s += v[l] * zs[l];
+    s = block_sum<256>(s, red);
+    const double f = tj * s;
+    for (int64_t l = j + 1 + threadIdx.x; l < k; l += 256) zs[l] -= f * v[l];
+    __syncthreads();
+  }
+  for (int64_t i = threadIdx.x; i < k; i += 256) zg[i] = zs[i];
+}
+
+// ---------------------------------------------------------------------------
+// 5. sign rule, Qhat = sqrt(lambda_j) u_j^T, T_r = u_j / sqrt(lambda_j)
+// ---------------------------------------------------------------------------
+struct Top2 {
+  double a1;
+  int64_t i1;
+  double a2;
+  int64_t i2;
+};
+
+__device__ __forceinline__ bool better(double a, int64_t i, double b, int64_t j) {
+  return a > b || (a == b && i < j);
+}
+
+__device__ __forceinline__ Top2 merge2(Top2 x, Top2 y) {
+  Top2 r;
+  if (better(x.a1, x.i1, y.a1, y.i1)) {
+    r.a1 = x.a1;
+    r.i1 = x.i1;
+    if (better(x.a2, x.i2, y.a1, y.i1)) {
+      r.a2 = x.a2;
+      r.i2 = x.i2;
+    } else {
+      r.a2 = y.a1;
+      r.i2 = y.i1;
+    }
+  } else {
+    r.a1 = y.a1;
+    r.i1 = y.i1;
+    if (better(y.a2, y.i2, x.a1, x.i1)) {
+      r.a2 = y.a2;
+      r.i2 = y.i2;
+    } else {
+      r.a2 = x.a1;
+      r.i2 = x.i1;
+    }
+  }
+  return r;
+}
+
+__global__ __launch_bounds__(256) void form_qhat_kernel(const double* Z /* r x k eigenvectors */, int64_t k, int r,
+                                                        const double* lambda_desc, double* Qhat, int64_t ldqh,
+                                                        double* Tr, int64_t ldtr, int* info) {
+  __shared__ Top2 tops[4];
+  __shared__ double red[4];
+  __shared__ double bc;
+  const int j = blockIdx.x;
+  const double* u = Z + size_t(j) * k;
+  Top2 t{-1.0, INT64_MAX, -1.0, INT64_MAX};
+  for (int64_t i = threadIdx.x; i < k; i += 256) {
+    Top2 c{fabs(u[i]), i, -1.0, INT64_MAX};
+    t = merge2(t, c);
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    Top2 other;
+    other.a1 = __shfl_xor(t.a1, o, 64);
+    other.i1 = __shfl_xor(t.i1, o, 64);
+    other.a2 = __shfl_xor(t.a2, o, 64);
+    other.i2 = __shfl_xor(t.i2, o, 64);
+    t = merge2(t, other);
+  }
+  if ((threadIdx.x & 63) == 0) tops[threadIdx.x >> 6] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    Top2 b = tops[0];
+    for (int w = 1; w < 4; ++w) b = merge2(b, tops[w]);
+    double sg = (u[b.i1] >= 0.0) ? 1.0 : -1.0;
+    bc = sg;
+    if (b.i2 != INT64_MAX && (b.a1 - b.a2) <= 1e-8 * b.a1 && u[b.i1] * u[b.i2] < 0.0) bc = 2.0;  // near tie
+  }
+  __syncthreads();
+  double sg = bc;
+  if (sg == 2.0) {
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < k; i += 256) s += double(i + 1) * u[i];
+    s = block_sum<256>(s, red);
+    sg = (s >= 0.0) ? 1.0 : -1.0;
+  }
+  const double lam = lambda_desc[j];
+  // an eigenvalue at or below k * u * lambda_1 is numerically zero
+  if (threadIdx.x == 0 && !(lam > double(k) * 2.220446049250313e-16 * lambda_desc[0])) atomicMax(info, DOPINF_E_RANK);
+  const double sl = sqrt(lam);
+  const double isl = 1.0 / sl;
+  for (int64_t i = threadIdx.x; i < k; i += 256) {
+    const double ui = sg * u[i];
+    Qhat[size_t(j) * ldqh + i] = sl * ui;
+    if (Tr) Tr[i * ldtr + j] = ui * isl;
+  }
+}
+
+__global__ void finite_check_kernel(const double* bounds, const int* abort_flag, int* info) {
+  if (threadIdx.x == 0) {
+    int v = DOPINF_OK;
+    if (bounds[4] != 0.0) v = DOPINF_E_NONFINITE;
+    if (*abort_flag) v = DOPINF_E_TIMEOUT;
+    *info = v;
+  }
+}
+
+__global__ void energy_rank_kernel(const double* lambda_desc, int64_t k, double tau, int* r_out) {
+  if (threadIdx.x != 0) return;
+  double total = 0.0;
+  for (int64_t i = 0; i < k; ++i) total += lambda_desc[i];
+  double c = 0.0;
+  int64_t r = k;
+  for (int64_t i = 0; i < k; ++i) {
+    c += lambda_desc[i];
+    if (c / total > tau) {
+      r = i + 1;
+      break;
+    }
+  }
+  *r_out = int(r);
+}
+
+struct EigPlan {
+  int P;
+  int in_lds;
+  int rows_max;
+  size_t lds_bytes;
+};
+
+int plan_sytrd(int64_t k, EigPlan& pl) {
+  int dev = 0;
+  DOPINF_HIP(hipGetDevice(&dev));
+  int ncu = 0, coop = 0;
+  DOPINF_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  DOPINF_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+  if (!coop) return fail(DOPINF_E_HIP, "device does not support cooperative launches");
+  int maxlds = 0;
+  DOPINF_HIP(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  int P = ncu;
+  if (P > k) P = int(k);
+  if (P < 1) P = 1;
+  pl.P = P;
+  pl.rows_max = int((k + P - 1) / P);
+  const size_t need = size_t(pl.rows_max) * size_t(k) * sizeof(double);
+  const size_t static_lds = 2048;
+  pl.in_lds = (need + static_lds <= size_t(maxlds)) ? 1 : 0;
+  pl.lds_bytes = pl.in_lds ? need : 0;
+  if (pl.in_lds) {
+    DOPINF_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(sytrd_kernel),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, int(pl.lds_bytes)));
+  }
+  int nb = 0;
+  DOPINF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sytrd_kernel, TNT, pl.lds_bytes));
+  if (nb < 1) return fail(DOPINF_E_HIP, "tridiagonalization kernel cannot be resident");
+  return DOPINF_OK;
+}
+
+struct EigWs {
+  double* A;
+  double* d;
+  double* e;
+  double* e2;
+  double* tau;
+  double* p;
+  double* part;
+  double* bounds;
+  double* Z;
+  double* scratch;
+  unsigned char* swaps;
+  unsigned* words;  // [0] barrier, [1] abort, [2] r_out
+};
+
+EigWs carve_eig(void* ws, size_t bytes, int64_t k, int r_max, int P, Carver& c) {
+  (void)bytes;
+  EigWs w;
+  w.A = c.take<double>(size_t(k) * k);
+  w.d = c.take<double>(size_t(k));
+  w.e = c.take<double>(size_t(k));
+  w.e2 = c.take<double>(size_t(k));
+  w.tau = c.take<double>(size_t(k));
+  w.p = c.take<double>(size_t(k));
+  w.part = c.take<double>(size_t(P > 0 ? P : 1024));
+  w.bounds = c.take<double>(8);
+  w.Z = c.take<double>(size_t(r_max) * k);
+  w.scratch = c.take<double>(size_t(r_max) * 4 * k);
+  w.swaps = c.take<unsigned char>(size_t(r_max) * k);
+  w.words = c.take<unsigned>(8);
+  (void)ws;
+  return w;
+}
+
+}  // namespace
+}  // namespace dopinf
+
+using namespace dopinf;
+
+extern "C" size_t dopinf_reduce_workspace(int64_t k, int r_max) {
+  if (k <= 0 || r_max <= 0) return 0;
+  Carver c(nullptr, 0);
+  carve_eig(nullptr, 0, k, r_max, 1024, c);
+  return c.used;
+}
+
+extern "C" int dopinf_reduce(void* stream, const double* D, int64_t k, int64_t ldd, int r_req, double tau,
+                             int r_max, int* r_out_h, double* lambda, double* Tr, int64_t ldtr, double* Qhat,
+                             int64_t ldqh, int* info, void* ws, size_t ws_bytes) {
+  DOPINF_REQUIRE(D && lambda && Qhat && info, "D, lambda, Qhat and info must be non-NULL");
+  DOPINF_REQUIRE(k >= 1 && ldd >= k && ldqh >= k, "need k >= 1, ldd >= k, ldqh >= k");
+  DOPINF_REQUIRE(k <= 65536, "k > 65536 is not supported");
+  DOPINF_REQUIRE(r_max >= 1 && r_max <= k, "need 1 <= r_max <= k");
+  DOPINF_REQUIRE(r_req >= 0 && r_req <= r_max, "need 0 <= r_req <= r_max");
+  DOPINF_REQUIRE(r_req > 0 || (tau > 0.0 && tau < 1.0), "energy threshold tau must be in (0, 1)");
+  DOPINF_REQUIRE(!Tr || ldtr >= r_max, "ldtr must be >= r_max");
+  const size_t need = dopinf_reduce_workspace(k, r_max);
+  if (!ws || ws_bytes < need) return fail(DOPINF_E_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  EigPlan pl{};
+  int rc = plan_sytrd(k, pl);
+  if (rc) return rc;
+  Carver c(ws, ws_bytes);
+  EigWs w = carve_eig(ws, ws_bytes, k, r_max, 1024, c);
+
+  zero_words_kernel<<<1, 64, 0, st>>>(w.words, 8);
+  DOPINF_LAUNCHED();
+  TridArgs ta{};
+  ta.D = D;
+  ta.ldd = ldd;
+  ta.A = w.A;
+  ta.k = k;
+  ta.P = pl.P;
+  ta.in_lds = pl.in_lds;
+  ta.rows_max = pl.rows_max;
+  ta.d = w.d;
+  ta.e = w.e;
+  ta.tau = w.tau;
+  ta.p = w.p;
+  ta.part = w.part;
+  ta.bar = w.words;
+  ta.abort_flag = reinterpret_cast<int*>(w.words + 1);
+  void* args[] = {&ta};
+  DOPINF_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(sytrd_kernel), dim3(pl.P), dim3(TNT), args,
+                                        unsigned(pl.lds_bytes), st));
+  tri_prep_kernel<<<1, 256, 0, st>>>(w.d, w.e, k, w.e2, w.bounds);
+  DOPINF_LAUNCHED();
+  tri_bisect_kernel<<<unsigned((k + 3) / 4), 256, 0, st>>>(w.d, w.e2, k, w.bounds, lambda);
+  DOPINF_LAUNCHED();
+  finite_check_kernel<<<1, 64, 0, st>>>(w.bounds, reinterpret_cast<int*>(w.words + 1), info);
+  DOPINF_LAUNCHED();
+
+  int r = r_req;
+  if (r == 0) {
+    int* r_dev = reinterpret_cast<int*>(w.words + 2);
+    energy_rank_kernel<<<1, 64, 0, st>>>(lambda, k, tau, r_dev);
+    DOPINF_LAUNCHED();
+    int r_h = 0;
+    DOPINF_HIP(hipMemcpyAsync(&r_h, r_dev, sizeof(int), hipMemcpyDeviceToHost, st));
+    DOPINF_HIP(hipStreamSynchronize(st));
+    if (r_h > r_max) return fail(DOPINF_E_RANK, "energy criterion needs r = %d > r_max = %d", r_h, r_max);
+    r = r_h;
+  }
+  if (r_out_h) *r_out_h = r;
+  tri_invit_kernel<<<unsigned((r + 63) / 64), 64, 0, st>>>(w.d, w.e, k, r, lambda, w.bounds, w.Z, w.scratch,
+                                                          w.swaps);
+  DOPINF_LAUNCHED();
+  const size_t zl = size_t(k) * sizeof(double);
+  if (zl > 65536)
+    DOPINF_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(backtransform_kernel),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, int(zl)));
+  backtransform_kernel<<<unsigned(r), 256, zl, st>>>(w.A, w.tau, k, w.Z);
+  DOPINF_LAUNCHED();
+  form_qhat_kernel<<<unsigned(r), 256, 0, st>>>(w.Z, k, r, lambda, Qhat, ldqh, Tr, ldtr, info);
+  DOPINF_LAUNCHED();
+  return DOPINF_OK;
+}

@@ -1,0 +1,423 @@
+// Step III of dOpInf (arXiv:2504.14338, Sec. 3.4): the Gram matrix
+// D = Qs^T Qs of a tall-skinny snapshot matrix (Eq. (5)), and the cross Gram
+// X^T Y used to project snapshots through Eq. (8).
+//
+// Design (gfx950):
+//  * D is cut into 128 x 128 tiles; only the lower triangle of tiles is
+//    computed (symmetry) and mirrored by the reduction.
+//  * The n rows are cut into splits (split-K).  Splits never straddle a state
+//    variable, so each workgroup applies one scale factor on load.  One
+//    workgroup = (tile, split); the grid holds ~8k workgroups so the 256 CUs
+//    see ~17 waves of work and a small tail.
+//  * Workgroup: 4 waves in a 2 x 2 arrangement, each owning a 64 x 64
+//    sub-tile = 4 x 4 MFMA blocks of v_mfma_f64_16x16x4 (FP64 accumulate).
+//    Row panels of KC rows of both column blocks are staged through LDS,
+//    double-buffered: global loads of stage s+1 are in flight while stage s
+//    feeds the matrix cores.  Centering (x - mean_i) and scaling (* 1/s_v)
+//    are applied while staging, so Q is read as stored and never rewritten.
+//  * XCD-aware order: consecutive workgroup ids go round-robin to the 8 XCDs;
+//    ids are mapped so that each XCD walks through its own splits with all
+//    tiles of a split together, i.e. the tiles running on one XCD share the
+//    same rows and re-read them from that XCD's L2.
+//  * Each (tile, split) writes its partial tile to the workspace; a second
+//    kernel sums the partials in fixed split order (deterministic, no float
+//    atomics) and writes both triangles.
+#include "common.hpp"
+
+namespace dopinf {
+int check_var_rows(int64_t n, int nvars, const int64_t* var_rows_h);
+
+namespace {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+constexpr int BT = 128;     // tile edge
+constexpr int NTH = 256;    // threads per workgroup
+constexpr int KC = 16;      // rows per LDS stage (FP64)
+constexpr int PAD = 2;      // LDS row padding (doubles)
+constexpr int LDR = BT + PAD;
+
+struct SplitPlan {
+  int nvars;
+  int nsplit;
+  int xcd_map;
+  int64_t row0[DOPINF_MAX_VARS + 1];
+  int split0[DOPINF_MAX_VARS + 1];
+};
+
+struct GramArgs {
+  const double* X;
+  int64_t ldx;
+  const double* Y;
+  int64_t ldy;
+  int64_t mx, my;
+  int tiles_y;     // tiles along Y (rectangular mode)
+  int ntiles;
+  int triangle;    // X == Y: lower triangle of tiles only
+  const double* mean;   // may be null
+  const double* scale;  // may be null
+  double* part;
+};
+
+__device__ __forceinline__ void tile_coords(const GramArgs& g, int t, int& I, int& J) {
+  if (g.triangle) {
+    // t = I(I+1)/2 + J, 0 <= J <= I
+    int i = int((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while ((i + 1) * (i + 2) / 2 <= t) ++i;
+    while (i * (i + 1) / 2 > t) --i;
+    I = i;
+    J = t - i * (i + 1) / 2;
+  } else {
+    I = t / g.tiles_y;
+    J = t % g.tiles_y;
+  }
+}
+
+__device__ __forceinline__ void split_range(const SplitPlan& sp, int s, int64_t& lo, int64_t& hi, int& v) {
+  int vv = 0;
+  while (vv + 1 < sp.nvars && s >= sp.split0[vv + 1]) ++vv;
+  const int nv = sp.split0[vv + 1] - sp.split0[vv];
+  const int64_t rows = sp.row0[vv + 1] - sp.row0[vv];
+  int64_t chunk = (rows + nv - 1) / nv;
+  chunk = (chunk + KC - 1) / KC * KC;
+  lo = sp.row0[vv] + int64_t(s - sp.split0[vv]) * chunk;
+  hi = min(sp.row0[vv + 1], lo + chunk);
+  if (lo > hi) lo = hi;
+  v = vv;
+}
+
+// Load 8 consecutive doubles of one panel row into registers, transformed.
+__device__ __forceinline__ void load_row8(const double* __restrict__ P, int64_t ld, int64_t row, int64_t hi,
+                                          int64_t col, int64_t mcols, bool vec_ok, double mu, double inv,
+                                          bool xf, double (&r)[8]) {
+  if (row < hi) {
+    const double* p = P + row * ld + col;
+    if (vec_ok && col + 8 <= mcols) {
+      const double2* p2 = reinterpret_cast<const double2*>(p);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        double2 w = p2[u];
+        r[2 * u] = w.x;
+        r[2 * u + 1] = w.y;
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) r[u] = (col + u < mcols) ? p[u] : 0.0;
+    }
+    if (xf) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) r[u] = (col + u < mcols) ? (r[u] - mu) * inv : 0.0;
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) r[u] = 0.0;
+  }
+}
+
+__global__ __launch_bounds__(NTH, 2) void gram_f64_mfma_kernel(GramArgs g, SplitPlan sp) {
+  __shared__ double As[2][KC][LDR];
+  __shared__ double Bs[2][KC][LDR];
+
+  int t, s;
+  {
+    const int bid = blockIdx.x;
+    if (sp.xcd_map) {
+      const int xcd = bid & 7;
+      const int local = bid >> 3;
+      s = (local / g.ntiles) * 8 + xcd;
+      t = local % g.ntiles;
+    } else {
+      s = bid / g.ntiles;
+      t = bid % g.ntiles;
+    }
+  }
+  int I, J;
+  tile_coords(g, t, I, J);
+  int64_t lo, hi;
+  int v;
+  split_range(sp, s, lo, hi, v);
+  const bool diag = g.triangle && (I == J);
+  const int64_t a0 = int64_t(I) * BT, b0 = int64_t(J) * BT;
+  const bool xf = (g.mean != nullptr) || (g.scale != nullptr);
+  const double inv = g.scale ? 1.0 / g.scale[v] : 1.0;
+  const bool vecx = ((g.ldx & 1) == 0) && ((reinterpret_cast<uintptr_t>(g.X) & 15) == 0);
+  const bool vecy = ((g.ldy & 1) == 0) && ((reinterpret_cast<uintptr_t>(g.Y) & 15) == 0);
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = tid >> 6;
+  const int wm = w >> 1, wn = w & 1;
+  const int lrow = tid >> 4;          // staging: panel row 0..15
+  const int lcol = (tid & 15) * 8;    // staging: first of 8 columns
+
+  dbl4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+
+  const int64_t nst = (hi - lo + KC - 1) / KC;
+  double ra[8], rb[8];
+
+  auto fetch = [&](int64_t st) {
+    const int64_t row = lo + st * KC + lrow;
+    const double mu = (g.mean && row < hi) ? g.mean[row] : 0.0;
+    load_row8(g.X, g.ldx, row, hi, a0 + lcol, g.mx, vecx, mu, inv, xf, ra);
+    if (!diag) load_row8(g.Y, g.ldy, row, hi, b0 + lcol, g.my, vecy, mu, inv, xf, rb);
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) As[buf][lrow][lcol + u] = ra[u];
+    if (!diag) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) Bs[buf][lrow][lcol + u] = rb[u];
+    }
+  };
+
+  if (nst > 0) {
+    fetch(0);
+    stash(0);
+  }
+  __syncthreads();
+  for (int64_t st = 0; st < nst; ++st) {
+    const int buf = int(st & 1);
+    if (st + 1 < nst) fetch(st + 1);
+    const double(*Bp)[LDR] = diag ? As[buf] : Bs[buf];
+#pragma unroll
+    for (int kk = 0; kk < KC / 4; ++kk) {
+      const int krow = kk * 4 + (lane >> 4);
+      const int cm = lane & 15;
+      double af[4], bf[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) af[i] = As[buf][krow][wm * 64 + i * 16 + cm];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bf[j] = Bp[krow][wn * 64 + j * 16 + cm];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+    }
+    if (st + 1 < nst) stash(buf ^ 1);
+    __syncthreads();
+  }
+
+  // partial tile: row index from X's column block, column index from Y's
+  double* out = g.part + (size_t(s) * g.ntiles + t) * (BT * BT);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        // v_mfma_f64_16x16x4: lane l, element e holds row (l / 16) + 4 e, column l % 16
+        const int rr = wm * 64 + i * 16 + (lane >> 4) + 4 * e;
+        const int cc = wn * 64 + j * 16 + (lane & 15);
+        out[rr * BT + cc] = acc[i][j][e];
+      }
+}
+
+// Sum partial tiles over splits in fixed order and write C (both triangles
+// for the symmetric case).
+__global__ __launch_bounds__(256) void gram_reduce_kernel(const double* __restrict__ part, int nsplit,
+                                                          int ntiles, int tiles_y, int triangle, int64_t mx,
+                                                          int64_t my, double* __restrict__ C, int64_t ldc) {
+  const int t = blockIdx.x;
+  const int rr = blockIdx.y * 2 + (threadIdx.x >> 7);
+  const int cc = threadIdx.x & 127;
+  int I, J;
+  if (triangle) {
+    int i = int((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while ((i + 1) * (i + 2) / 2 <= t) ++i;
+    while (i * (i + 1) / 2 > t) --i;
+    I = i;
+    J = t - i * (i + 1) / 2;
+  } else {
+    I = t / tiles_y;
+    J = t % tiles_y;
+  }
+  const int64_t a = int64_t(I) * BT + rr, b = int64_t(J) * BT + cc;
+  if (a >= mx || b >= my) return;
+  if (triangle && I == J && rr < cc) return;
+  double sum = 0.0;
+  const size_t stride = size_t(ntiles) * BT * BT;
+  const double* p = part + size_t(t) * BT * BT + size_t(rr) * BT + cc;
+  for (int s = 0; s < nsplit; ++s) sum += p[s * stride];
+  C[a * ldc + b] = sum;
+  if (triangle) C[b * ldc + a] = sum;
+}
+
+int choose_splits(int64_t n, int ntiles) {
+  int target = (8192 + ntiles - 1) / ntiles;
+  int64_t max_by_rows = n / 256;
+  if (max_by_rows < 1) max_by_rows = 1;
+  if (target > max_by_rows) target = int(max_by_rows);
+  if (target >= 8) target = target / 8 * 8;
+  if (target < 1) target = 1;
+  return target;
+}
+
+SplitPlan make_plan(int64_t n, int nvars, const int64_t* var_rows_h, int nsplit_target) {
+  SplitPlan sp{};
+  sp.nvars = nvars;
+  int acc = 0;
+  for (int v = 0; v < nvars; ++v) {
+    sp.row0[v] = var_rows_h[v];
+    sp.split0[v] = acc;
+    const int64_t rows = var_rows_h[v + 1] - var_rows_h[v];
+    int nv = int((double(nsplit_target) * double(rows) / double(n)) + 0.5);
+    if (nv < 1) nv = 1;
+    const int64_t max_nv = (rows + KC - 1) / KC;
+    if (nv > max_nv) nv = int(max_nv);
+    acc += nv;
+  }
+  sp.row0[nvars] = var_rows_h[nvars];
+  sp.split0[nvars] = acc;
+  sp.nsplit = acc;
+  sp.xcd_map = (acc % 8 == 0) ? 1 : 0;
+  return sp;
+}
+
+int tiles_of(int64_t m) { return int((m + BT - 1) / BT); }
+
+size_t part_bytes(int nsplit, int ntiles) { return size_t(nsplit) * ntiles * BT * BT * sizeof(double); }
+
+int run_gram(hipStream_t st, GramArgs g, const SplitPlan& sp, double* C, int64_t ldc, int tiles_y) {
+  g.tiles_y = tiles_y;
+  dim3 grid(unsigned(sp.nsplit) * unsigned(g.ntiles));
+  gram_f64_mfma_kernel<<<grid, NTH, 0, st>>>(g, sp);
+  DOPINF_LAUNCHED();
+  dim3 rgrid(unsigned(g.ntiles), BT / 2);
+  gram_reduce_kernel<<<rgrid, 256, 0, st>>>(g.part, sp.nsplit, g.ntiles, tiles_y, g.triangle, g.mx, g.my, C, ldc);
+  DOPINF_LAUNCHED();
+  return DOPINF_OK;
+}
+
+}  // namespace
+
+// Symmetric Gram of an n x m float64 matrix (used by Step IV's data Gram as
+// well): D = Xs^T Xs with the optional per-row / per-variable transform.
+int gram_f64_internal(hipStream_t st, const double* X, int64_t n, int64_t m, int64_t ldx, const double* mean,
+                      const double* scale, int nvars, const int64_t* var_rows_h, double* D, int64_t ldd,
+                      void* ws, size_t ws_bytes) {
+  const int T = tiles_of(m);
+  const int ntiles = T * (T + 1) / 2;
+  int64_t one_var[2] = {0, n};
+  if (!var_rows_h) {
+    nvars = 1;
+    var_rows_h = one_var;
+  }
+  SplitPlan sp = make_plan(n, nvars, var_rows_h, choose_splits(n, ntiles));
+  if (ws_bytes < part_bytes(sp.nsplit, ntiles) || !ws)
+    return fail(DOPINF_E_WORKSPACE, "gram workspace of %zu bytes needed, %zu given", part_bytes(sp.nsplit, ntiles),
+                ws_bytes);
+  GramArgs g{};
+  g.X = X;
+  g.ldx = ldx;
+  g.Y = X;
+  g.ldy = ldx;
+  g.mx = m;
+  g.my = m;
+  g.ntiles = ntiles;
+  g.triangle = 1;
+  g.mean = mean;
+  g.scale = scale;
+  g.part = static_cast<double*>(ws);
+  return run_gram(st, g, sp, D, ldd, T);
+}
+
+size_t gram_f64_workspace_internal(int64_t n, int64_t m, int nvars) {
+  const int T = tiles_of(m);
+  const int ntiles = T * (T + 1) / 2;
+  // per-variable rounding can add at most nvars splits
+  return part_bytes(choose_splits(n, ntiles) + nvars + 8, ntiles);
+}
+
+}  // namespace dopinf
+
+using namespace dopinf;
+
+namespace dopinf {
+size_t cross_gram_workspace_internal(int64_t n, int64_t mx, int64_t my);
+}
+
+size_t gram_lowp_workspace(int algo, int64_t n, int64_t k);
+int gram_lowp(hipStream_t st, int algo, const float* Q, int64_t n, int64_t k, int64_t ldq, const double* mean,
+              const double* scale, int nvars, const int64_t* var_rows_h, double* D, int64_t ldd, void* ws,
+              size_t ws_bytes);
+
+extern "C" size_t dopinf_gram_workspace(int dtype, int algo, int64_t n, int64_t k) {
+  if (n <= 0 || k <= 0) return 0;
+  if (dtype == DOPINF_F64) return gram_f64_workspace_internal(n, k, DOPINF_MAX_VARS);
+  return gram_lowp_workspace(algo, n, k);
+}
+
+extern "C" int dopinf_gram(void* stream, int dtype, int algo, const void* Q, int64_t n, int64_t k, int64_t ldq,
+                           const double* mean, const double* scale, int nvars, const int64_t* var_rows_h,
+                           double* D, int64_t ldd, void* ws, size_t ws_bytes) {
+  DOPINF_REQUIRE(Q && D, "Q and D must be non-NULL");
+  DOPINF_REQUIRE(n >= 1 && k >= 1 && ldq >= k && ldd >= k, "need n >= 1, k >= 1, ldq >= k, ldd >= k");
+  DOPINF_REQUIRE(k <= (int64_t(1) << 20), "k too large");
+  if (scale) {
+    int rc = check_var_rows(n, nvars, var_rows_h);
+    if (rc) return rc;
+  } else if (var_rows_h) {
+    int rc = check_var_rows(n, nvars, var_rows_h);
+    if (rc) return rc;
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (dtype == DOPINF_F64) {
+    DOPINF_REQUIRE(algo == DOPINF_GRAM_NATIVE, "float64 data supports DOPINF_GRAM_NATIVE only");
+    return gram_f64_internal(st, static_cast<const double*>(Q), n, k, ldq, mean, scale, scale ? nvars : 0,
+                             scale ? var_rows_h : nullptr, D, ldd, ws, ws_bytes);
+  }
+  DOPINF_REQUIRE(dtype == DOPINF_F32, "dtype must be DOPINF_F64 or DOPINF_F32");
+  DOPINF_REQUIRE(algo == DOPINF_GRAM_NATIVE || algo == DOPINF_GRAM_BF16X3, "unknown gram algorithm");
+  return gram_lowp(st, algo, static_cast<const float*>(Q), n, k, ldq, mean, scale, scale ? nvars : 0,
+                   scale ? var_rows_h : nullptr, D, ldd, ws, ws_bytes);
+}
+
+extern "C" size_t dopinf_cross_gram_workspace(int64_t n, int64_t mx, int64_t my) {
+  if (n <= 0 || mx <= 0 || my <= 0) return 0;
+  return cross_gram_workspace_internal(n, mx, my);
+}
+
+namespace dopinf {
+
+int cross_gram_internal(hipStream_t st, const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t n,
+                        int64_t mx, int64_t my, double* C, int64_t ldc, void* ws, size_t ws_bytes) {
+  const int ty = tiles_of(my);
+  const int ntiles = tiles_of(mx) * ty;
+  int64_t one_var[2] = {0, n};
+  SplitPlan sp = make_plan(n, 1, one_var, choose_splits(n, ntiles));
+  if (!ws || ws_bytes < part_bytes(sp.nsplit, ntiles))
+    return fail(DOPINF_E_WORKSPACE, "cross gram workspace of %zu bytes needed, %zu given",
+                part_bytes(sp.nsplit, ntiles), ws_bytes);
+  GramArgs g{};
+  g.X = X;
+  g.ldx = ldx;
+  g.Y = Y;
+  g.ldy = ldy;
+  g.mx = mx;
+  g.my = my;
+  g.ntiles = ntiles;
+  g.triangle = 0;
+  g.part = static_cast<double*>(ws);
+  return run_gram(st, g, sp, C, ldc, ty);
+}
+
+size_t cross_gram_workspace_internal(int64_t n, int64_t mx, int64_t my) {
+  const int ntiles = tiles_of(mx) * tiles_of(my);
+  return part_bytes(choose_splits(n, ntiles) + 8, ntiles);
+}
+
+}  // namespace dopinf
+
+extern "C" int dopinf_cross_gram(void* stream, const double* X, int64_t ldx, const double* Y, int64_t ldy,
+                                 int64_t n, int64_t mx, int64_t my, double* C, int64_t ldc, void* ws,
+                                 size_t ws_bytes) {
+  DOPINF_REQUIRE(X && Y && C, "X, Y and C must be non-NULL");
+  DOPINF_REQUIRE(n >= 1 && mx >= 1 && my >= 1 && ldx >= mx && ldy >= my && ldc >= my,
+                 "need n, mx, my >= 1 and ldx >= mx, ldy >= my, ldc >= my");
+  return cross_gram_internal(static_cast<hipStream_t>(stream), X, ldx, Y, ldy, n, mx, my, C, ldc, ws, ws_bytes);
+}

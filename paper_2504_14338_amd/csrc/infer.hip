@@ -1,0 +1,678 @@
+// Step IV of dOpInf (arXiv:2504.14338, Sec. 3.5): the regularized operator
+// inference problem of Eq. (12) on the data of Eq. (13), for one or many
+// (r, beta1, beta2) candidates.
+//
+// Design:
+//  * One data matrix E = [Qhat_1^T | quad(Qhat_1^T) | 1 | Qhat_2^T] is built
+//    at the largest requested r and its Gram G_E = E^T E is formed by the
+//    Step III Gram kernel.  For a smaller r, Dhat^T Dhat and Dhat^T Qhat_2^T
+//    are index-submatrices of G_E (the same dot products), so one Gram serves
+//    every reduced size.
+//  * The normal matrix is factored in the permuted column order
+//    [quadratic (s) | linear (r), constant (1)].  Its leading s x s block
+//    G_qq + beta2 I depends on beta2 only, so its Cholesky factor L, the
+//    solves [W | y] = L^{-1} [G_ql | B_q] and [P | Z] = L^{-T} [W | y], and
+//    the products W^T [W | y] are computed once per (r, beta2).  Each pair
+//    then factors the small Schur complement
+//       S = G_ll + beta1 I - W^T W           ((r+1) x (r+1))
+//    solves S X_l = B_l - W^T y and recovers X_q = Z - P X_l.  This is
+//    Cholesky factorization of the same matrix under a symmetric permutation.
+//  * The s x s factorization is blocked right-looking (64-wide panels): a
+//    diagonal-block kernel also inverts its 64 x 64 triangle, a panel kernel
+//    solves the rows below, and the trailing update runs on FP64 MFMA tiles.
+//    Triangular solves then reduce to products with the stored diagonal
+//    inverses.
+#include <vector>
+
+#include "common.hpp"
+
+namespace dopinf {
+int gram_f64_internal(hipStream_t st, const double* X, int64_t n, int64_t m, int64_t ldx, const double* mean,
+                      const double* scale, int nvars, const int64_t* var_rows_h, double* D, int64_t ldd, void* ws,
+                      size_t ws_bytes);
+size_t gram_f64_workspace_internal(int64_t n, int64_t m, int nvars);
+int cross_gram_internal(hipStream_t st, const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t n,
+                        int64_t mx, int64_t my, double* C, int64_t ldc, void* ws, size_t ws_bytes);
+size_t cross_gram_workspace_internal(int64_t n, int64_t mx, int64_t my);
+
+namespace {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+constexpr int NB = 64;         // panel width of the blocked Cholesky
+constexpr int UCHUNK = 32;     // beta2 groups factored together
+
+__host__ __device__ inline int64_t nquad(int64_t r) { return r * (r + 1) / 2; }
+__host__ __device__ inline int64_t ncols(int64_t r) { return r + nquad(r) + 1; }
+
+// column of E for the quadratic feature (i, j), i <= j, at r_max
+__device__ __forceinline__ int64_t qcol_max(int i, int j, int rmax) {
+  return rmax + int64_t(i) * rmax - int64_t(i) * (i - 1) / 2 + (j - i);
+}
+
+// (i, j) of quadratic index q in the ordering (0,0),(0,1),..,(0,r-1),(1,1),..
+__device__ __forceinline__ void qpair(int64_t q, int r, int& i, int& j) {
+  int ii = 0;
+  int64_t off = 0;
+  while (off + (r - ii) <= q) {
+    off += r - ii;
+    ++ii;
+  }
+  i = ii;
+  j = ii + int(q - off);
+}
+
+// ---------------------------------------------------------------------------
+// E = [Qhat_1^T | quad(Qhat_1^T) | 1 | Qhat_2^T] at r_max, (k-1) x m, ld lde
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void assemble_kernel(const double* __restrict__ Qhat, int64_t ldqh, int64_t k,
+                                                       int rmax, double* __restrict__ E, int64_t lde) {
+  const int64_t c = blockIdx.y;                    // column of E
+  const int64_t t = int64_t(blockIdx.x) * 256 + threadIdx.x;  // row (time index of Qhat_1)
+  if (t >= k - 1) return;
+  const int64_t s = nquad(rmax);
+  const int64_t d = rmax + s + 1;
+  double v;
+  if (c < rmax) {
+    v = Qhat[c * ldqh + t];
+  } else if (c < rmax + s) {
+    int i, j;
+    qpair(c - rmax, rmax, i, j);
+    v = Qhat[int64_t(i) * ldqh + t] * Qhat[int64_t(j) * ldqh + t];
+  } else if (c == rmax + s) {
+    v = 1.0;
+  } else {
+    v = Qhat[(c - d) * ldqh + t + 1];
+  }
+  E[t * lde + c] = v;
+}
+
+// ---------------------------------------------------------------------------
+// per (r, beta2) group: gather the quadratic block and right-hand sides
+//   L[u]  (s x s, lower, ld s)   = G_qq + beta2_u I
+//   R[u]  (s x (2r+1), ld 2r+1)  = [G_ql | G_q,rhs]
+// ---------------------------------------------------------------------------
+struct GroupGeom {
+  int r, rmax;
+  int64_t s, m;  // m = leading dimension of G_E
+  int64_t dmax;
+};
+
+__device__ __forceinline__ int64_t gcol_q(const GroupGeom& g, int64_t q) {
+  int i, j;
+  qpair(q, g.r, i, j);
+  return qcol_max(i, j, g.rmax);
+}
+// linear/constant index c in [0, r]: c < r linear column c, c == r constant
+__device__ __forceinline__ int64_t gcol_l(const GroupGeom& g, int c) {
+  return (c < g.r) ? c : (g.rmax + nquad(g.rmax));
+}
+__device__ __forceinline__ int64_t gcol_rhs(const GroupGeom& g, int c) { return g.dmax + c; }
+
+__global__ __launch_bounds__(256) void gather_qq_kernel(const double* __restrict__ GE, GroupGeom geo,
+                                                        const double* __restrict__ beta2u, double* __restrict__ L,
+                                                        double* __restrict__ R) {
+  const int u = blockIdx.z;
+  const int64_t a = blockIdx.y;
+  const int64_t s = geo.s;
+  const int64_t ca = gcol_q(geo, a);
+  const double* grow = GE + ca * geo.m;
+  double* Lu = L + size_t(u) * s * s;
+  const double b2 = beta2u[u];
+  for (int64_t b = int64_t(blockIdx.x) * 256 + threadIdx.x; b <= a; b += int64_t(gridDim.x) * 256) {
+    double v = grow[gcol_q(geo, b)];
+    if (b == a) v += b2;
+    Lu[a * s + b] = v;
+  }
+  const int w = 2 * geo.r + 1;
+  double* Ru = R + size_t(u) * s * w;
+  if (blockIdx.x == 0) {
+    for (int c = threadIdx.x; c < w; c += 256) {
+      const int64_t col = (c <= geo.r) ? gcol_l(geo, c) : gcol_rhs(geo, c - geo.r - 1);
+      Ru[a * w + c] = grow[col];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// blocked Cholesky (lower, row-major, ld n), batched over blockIdx.z / .y
+// ---------------------------------------------------------------------------
+// Diagonal block at jb: factor in LDS, write L_jj and its inverse.
+__global__ __launch_bounds__(256) void potf2_kernel(double* __restrict__ A, int64_t n, int64_t jb,
+                                                    double* __restrict__ Linv, int* __restrict__ fail_flag) {
+  __shared__ double T[NB][NB + 1];
+  __shared__ double Ti[NB][NB + 1];
+  __shared__ int bad;
+  const int u = blockIdx.x;
+  double* Au = A + size_t(u) * n * n;
+  const int nb = int(min<int64_t>(NB, n - jb));
+  for (int e = threadIdx.x; e < NB * NB; e += 256) {
+    const int i = e / NB, j = e % NB;
+    double v = 0.0;
+    if (i < nb && j <= i) v = Au[(jb + i) * n + jb + j];
+    else if (i == j) v = 1.0;  // identity padding beyond the matrix
+    T[i][j] = v;
+  }
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  for (int c = 0; c < NB; ++c) {
+    if (threadIdx.x == 0) {
+      double piv = T[c][c];
+      if (!(piv > 0.0) || !isfinite(piv)) {
+        bad = 1;
+        piv = 1.0;
+      }
+      T[c][c] = sqrt(piv);
+    }
+    __syncthreads();
+    const double dc = T[c][c];
+    for (int i = c + 1 + threadIdx.x; i < NB; i += 256) T[i][c] /= dc;
+    __syncthreads();
+    const int rem = NB - c - 1;
+    for (int e = threadIdx.x; e < rem * rem; e += 256) {
+      const int i = c + 1 + e / rem, l = c + 1 + e % rem;
+      if (l <= i) T[i][l] -= T[i][c] * T[l][c];
+    }
+    __syncthreads();
+  }
+  // inverse of the lower triangle: column c by forward substitution
+  if (threadIdx.x < NB) {
+    const int c = threadIdx.x;
+    for (int i = 0; i < NB; ++i) {
+      double v;
+      if (i < c) {
+        v = 0.0;
+      } else {
+        double s = (i == c) ? 1.0 : 0.0;
+        for (int p = c; p < i; ++p) s -= T[i][p] * Ti[p][c];
+        v = s / T[i][i];
+      }
+      Ti[i][c] = v;
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < NB * NB; e += 256) {
+    const int i = e / NB, j = e % NB;
+    if (i < nb && j <= i) Au[(jb + i) * n + jb + j] = T[i][j];
+    Linv[(size_t(u) * ((n + NB - 1) / NB) + jb / NB) * NB * NB + e] = Ti[i][j];
+  }
+  if (threadIdx.x == 0 && bad) fail_flag[u] = 1;
+}
+
+// Rows below the diagonal block: A[i, jb:jb+nb] <- A[i, jb:jb+nb] L_jj^{-T}
+// = A[i, :] Linv^T, one thread per row.
+__global__ __launch_bounds__(256) void panel_kernel(double* __restrict__ A, int64_t n, int64_t jb,
+                                                    const double* __restrict__ Linv) {
+  __shared__ double Li[NB][NB + 1];
+  const int u = blockIdx.y;
+  double* Au = A + size_t(u) * n * n;
+  const double* Lu = Linv + (size_t(u) * ((n + NB - 1) / NB) + jb / NB) * NB * NB;
+  for (int e = threadIdx.x; e < NB * NB; e += 256) Li[e / NB][e % NB] = Lu[e];
+  __syncthreads();
+  const int64_t i = jb + NB + int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int nb = int(min<int64_t>(NB, n - jb));
+  double x[NB];
+#pragma unroll
+  for (int p = 0; p < NB; ++p) x[p] = (p < nb) ? Au[i * n + jb + p] : 0.0;
+  for (int c = 0; c < nb; ++c) {
+    double s = 0.0;
+#pragma unroll
+    for (int p = 0; p < NB; ++p) s += x[p] * Li[c][p];
+    Au[i * n + jb + c] = s;
+  }
+}
+
+// Trailing update on FP64 MFMA: A[i][l] -= sum_p L[i][jb+p] L[l][jb+p] for
+// i >= l >= jb+NB, 64 x 64 tiles (lower triangle of tiles), 4 waves of 32 x 32.
+__global__ __launch_bounds__(256) void syrk_update_kernel(double* __restrict__ A, int64_t n, int64_t jb) {
+  __shared__ double Pa[NB][NB + 2];
+  __shared__ double Pb[NB][NB + 2];
+  const int u = blockIdx.y;
+  double* Au = A + size_t(u) * n * n;
+  const int64_t j1 = jb + NB;
+  const int t = blockIdx.x;
+  int I = int((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((I + 1) * (I + 2) / 2 <= t) ++I;
+  while (I * (I + 1) / 2 > t) --I;
+  const int J = t - I * (I + 1) / 2;
+  const int64_t r0 = j1 + int64_t(I) * 64, c0 = j1 + int64_t(J) * 64;
+  for (int e = threadIdx.x; e < 64 * NB; e += 256) {
+    const int rr = e / NB, p = e % NB;
+    Pa[rr][p] = (r0 + rr < n) ? Au[(r0 + rr) * n + jb + p] : 0.0;
+    Pb[rr][p] = (c0 + rr < n) ? Au[(c0 + rr) * n + jb + p] : 0.0;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wm = w >> 1, wn = w & 1;
+  dbl4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int kk = 0; kk < NB / 4; ++kk) {
+    const int p = kk * 4 + (lane >> 4);
+    double af[2], bf[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) af[i] = Pa[wm * 32 + i * 16 + (lane & 15)][p];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) bf[j] = Pb[wn * 32 + j * 16 + (lane & 15)][p];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t row = r0 + wm * 32 + i * 16 + (lane >> 4) + 4 * e;  // MFMA f64 output layout
+        const int64_t col = c0 + wn * 32 + j * 16 + (lane & 15);
+        if (row < n && col <= row) Au[row * n + col] -= acc[i][j][e];
+      }
+}
+
+// ---------------------------------------------------------------------------
+// triangular solves with the factored L (row-major lower, ld n) and its
+// diagonal-block inverses.  X is n x w (ld w), one workgroup per (item, 32
+// columns); forward: L X = B, backward: L^T X = B.
+// ---------------------------------------------------------------------------
+template <bool TRANS>
+__global__ __launch_bounds__(256) void trsm_kernel(const double* __restrict__ L, int64_t n,
+                                                   const double* __restrict__ Linv, double* __restrict__ X,
+                                                   int64_t w) {
+  __shared__ double Li[NB][NB + 1];
+  __shared__ double Y[NB][33];
+  const int u = blockIdx.y;
+  const double* Lu = L + size_t(u) * n * n;
+  const int64_t nblk = (n + NB - 1) / NB;
+  const double* Liu = Linv + size_t(u) * nblk * NB * NB;
+  double* Xu = X + size_t(u) * n * w;
+  const int64_t c0 = int64_t(blockIdx.x) * 32;
+  const int il = threadIdx.x >> 2;       // row within block (0..63)
+  const int cs = (threadIdx.x & 3) * 8;  // 8 columns
+  for (int64_t bi = 0; bi < nblk; ++bi) {
+    const int64_t J = TRANS ? (nblk - 1 - bi) : bi;
+    const int64_t jb = J * NB;
+    const int64_t i = jb + il;
+    double acc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+    if (i < n) {
+      if (!TRANS) {
+        for (int64_t p = 0; p < jb; ++p) {
+          const double l = Lu[i * n + p];
+          const double* xp = Xu + p * w + c0 + cs;
+#pragma unroll
+          for (int q = 0; q < 8; ++q)
+            if (c0 + cs + q < w) acc[q] += l * xp[q];
+        }
+      } else {
+        for (int64_t p = jb + NB; p < n; ++p) {
+          const double l = Lu[p * n + i];
+          const double* xp = Xu + p * w + c0 + cs;
+#pragma unroll
+          for (int q = 0; q < 8; ++q)
+            if (c0 + cs + q < w) acc[q] += l * xp[q];
+        }
+      }
+    }
+    for (int e = threadIdx.x; e < NB * NB; e += 256) Li[e / NB][e % NB] = Liu[J * NB * NB + e];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int64_t c = c0 + cs + q;
+      Y[il][cs + q] = (i < n && c < w) ? Xu[i * w + c] - acc[q] : 0.0;
+    }
+    __syncthreads();
+    if (i < n) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int64_t c = c0 + cs + q;
+        if (c >= w) continue;
+        double s = 0.0;
+        if (!TRANS) {
+          for (int p = 0; p <= il; ++p) s += Li[il][p] * Y[p][cs + q];
+        } else {
+          for (int p = il; p < NB; ++p) s += Li[p][il] * Y[p][cs + q];
+        }
+        Xu[i * w + c] = s;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// per pair: Schur complement solve and operator write-out
+// CV[u] = W^T [W | y] ((r+1) x (2r+1)); R2[u] = [P | Z] (s x (2r+1))
+// ---------------------------------------------------------------------------
+struct PairArgs {
+  const double* GE;
+  GroupGeom geo;
+  const double* CV;
+  const double* R2;
+  const int* ufail;
+  const int* pair_u;     // pair -> local u index (within the chunk), -1: not in chunk
+  const double* beta1;   // per pair
+  double* O;             // group base, pair stride r*d
+  int* status;           // group base
+  int n_pairs;
+};
+
+__global__ __launch_bounds__(256) void pair_solve_kernel(PairArgs a) {
+  extern __shared__ double sm[];
+  const int p = blockIdx.x;
+  const int u = a.pair_u[p];
+  if (u < 0) return;
+  const GroupGeom& g = a.geo;
+  const int r = g.r;
+  const int r1 = r + 1;
+  const int w = 2 * r + 1;
+  const int64_t s = g.s;
+  const int64_t d = ncols(r);
+  double* S = sm;               // r1 x r1
+  double* X = sm + r1 * r1;     // r1 x r  (rhs, then solution)
+  __shared__ int bad;
+  const double* CVu = a.CV + size_t(u) * r1 * w;
+  const double b1 = a.beta1[p];
+  for (int e = threadIdx.x; e < r1 * r1; e += 256) {
+    const int i = e / r1, j = e % r1;
+    double v = a.GE[gcol_l(g, i) * g.m + gcol_l(g, j)] - CVu[i * w + j];
+    if (i == j) v += b1;
+    S[e] = v;
+  }
+  for (int e = threadIdx.x; e < r1 * r; e += 256) {
+    const int i = e / r, c = e % r;
+    X[e] = a.GE[gcol_l(g, i) * g.m + gcol_rhs(g, c)] - CVu[i * w + r1 + c];
+  }
+  if (threadIdx.x == 0) bad = a.ufail[u];
+  __syncthreads();
+  // Cholesky of S (right-looking, in LDS)
+  for (int c = 0; c < r1; ++c) {
+    if (threadIdx.x == 0) {
+      double piv = S[c * r1 + c];
+      if (!(piv > 0.0) || !isfinite(piv)) {
+        bad = 1;
+        piv = 1.0;
+      }
+      S[c * r1 + c] = sqrt(piv);
+    }
+    __syncthreads();
+    const double dc = S[c * r1 + c];
+    for (int i = c + 1 + threadIdx.x; i < r1; i += 256) S[i * r1 + c] /= dc;
+    __syncthreads();
+    const int rem = r1 - c - 1;
+    for (int e = threadIdx.x; e < rem * rem; e += 256) {
+      const int i = c + 1 + e / rem, l = c + 1 + e % rem;
+      if (l <= i) S[i * r1 + l] -= S[i * r1 + c] * S[l * r1 + c];
+    }
+    __syncthreads();
+  }
+  // forward then backward substitution, columns in parallel
+  for (int c = threadIdx.x; c < r; c += 256) {
+    for (int i = 0; i < r1; ++i) {
+      double v = X[i * r + c];
+      for (int q = 0; q < i; ++q) v -= S[i * r1 + q] * X[q * r + c];
+      X[i * r + c] = v / S[i * r1 + i];
+    }
+    for (int i = r1 - 1; i >= 0; --i) {
+      double v = X[i * r + c];
+      for (int q = i + 1; q < r1; ++q) v -= S[q * r1 + i] * X[q * r + c];
+      X[i * r + c] = v / S[i * r1 + i];
+    }
+  }
+  __syncthreads();
+  double* Op = a.O + size_t(p) * r * d;
+  // linear and constant columns of O = X^T
+  for (int e = threadIdx.x; e < r * r1; e += 256) {
+    const int i = e / r1, c = e % r1;   // O row i, permuted column c
+    const int64_t col = (c < r) ? c : (r + s);
+    Op[i * d + col] = X[c * r + i];
+  }
+  // quadratic columns: X_q = Z - P X_l
+  const double* R2u = a.R2 + size_t(u) * s * w;
+  for (int64_t q = threadIdx.x; q < s; q += 256) {
+    const double* prow = R2u + q * w;
+    for (int i = 0; i < r; ++i) {
+      double v = prow[r1 + i];
+      for (int c = 0; c < r1; ++c) v -= prow[c] * X[c * r + i];
+      Op[i * d + r + q] = v;
+    }
+  }
+  if (threadIdx.x == 0) a.status[p] = bad ? DOPINF_E_NOTSPD : DOPINF_OK;
+}
+
+__global__ void zero_ints_kernel(int* p, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+__global__ void copy_kernel(const double* __restrict__ a, double* __restrict__ b, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) b[i] = a[i];
+}
+
+// ---------------------------------------------------------------------------
+// host-side planning
+// ---------------------------------------------------------------------------
+struct InferLayout {
+  int rmax;
+  int64_t smax, dmax, m, lde, km1;
+  size_t e_off, g_off, gram_off, gram_bytes;
+  size_t chunk_off;  // per-chunk storage start
+  size_t l_bytes, r_bytes, linv_bytes, cv_bytes;  // per u, at rmax
+  size_t cg_bytes;   // cross gram partials
+  size_t misc_off;
+  size_t total;
+};
+
+InferLayout layout(int64_t k, int n_r, const int* r_list, int n_pairs) {
+  InferLayout L{};
+  int rmax = 0;
+  for (int g = 0; g < n_r; ++g) rmax = r_list[g] > rmax ? r_list[g] : rmax;
+  L.rmax = rmax;
+  L.smax = nquad(rmax);
+  L.dmax = ncols(rmax);
+  L.m = L.dmax + rmax;
+  L.lde = (L.m + 1) / 2 * 2;
+  L.km1 = k - 1;
+  Carver c(nullptr, 0);
+  c.take<double>(size_t(L.km1) * L.lde);
+  L.e_off = 0;
+  L.g_off = c.used;
+  c.take<double>(size_t(L.m) * L.m);
+  L.gram_off = (c.used + 255) & ~size_t(255);
+  L.gram_bytes = gram_f64_workspace_internal(L.km1, L.m, 1);
+  c.take<char>(L.gram_bytes);
+  const int64_t s = L.smax, w = 2 * rmax + 1, nblk = (s + NB - 1) / NB;
+  L.l_bytes = size_t(s) * s * sizeof(double);
+  L.r_bytes = size_t(s) * w * sizeof(double);
+  L.linv_bytes = size_t(nblk) * NB * NB * sizeof(double);
+  L.cv_bytes = size_t(rmax + 1) * w * sizeof(double);
+  L.cg_bytes = 0;
+  for (int g = 0; g < n_r; ++g) {
+    const int64_t rg = r_list[g];
+    const size_t b = cross_gram_workspace_internal(nquad(rg), rg + 1, 2 * rg + 1);
+    if (b > L.cg_bytes) L.cg_bytes = b;
+  }
+  const int uc = n_pairs < UCHUNK ? n_pairs : UCHUNK;
+  L.chunk_off = (c.used + 255) & ~size_t(255);
+  c.take<char>(uc * L.l_bytes);
+  c.take<char>(uc * L.r_bytes);
+  c.take<char>(uc * L.r_bytes);
+  c.take<char>(uc * L.linv_bytes);
+  c.take<char>(uc * L.cv_bytes);
+  c.take<char>(L.cg_bytes);
+  L.misc_off = (c.used + 255) & ~size_t(255);
+  c.take<double>(size_t(uc));       // beta2 per u
+  c.take<int>(size_t(uc));          // fail flag per u
+  c.take<int>(size_t(n_pairs));     // pair -> u
+  c.take<double>(size_t(n_pairs));  // beta1 per pair
+  L.total = c.used;
+  return L;
+}
+
+}  // namespace
+}  // namespace dopinf
+
+using namespace dopinf;
+
+extern "C" size_t dopinf_operator_offset(int n_r, const int* r_list_h, int n_pairs, int item) {
+  if (n_r <= 0 || !r_list_h || n_pairs <= 0 || item < 0) return 0;
+  size_t off = 0;
+  for (int g = 0; g < n_r; ++g) {
+    const size_t per = size_t(r_list_h[g]) * size_t(ncols(r_list_h[g]));
+    if (item < (g + 1) * n_pairs) return off + size_t(item - g * n_pairs) * per;
+    off += per * size_t(n_pairs);
+  }
+  return off;
+}
+
+extern "C" size_t dopinf_infer_workspace(int64_t k, int n_r, const int* r_list_h, int n_pairs) {
+  if (k < 2 || n_r <= 0 || !r_list_h || n_pairs <= 0) return 0;
+  return layout(k, n_r, r_list_h, n_pairs).total;
+}
+
+extern "C" int dopinf_infer(void* stream, const double* Qhat, int64_t ldqh, int64_t k, int n_r, const int* r_list_h,
+                            int n_pairs, const double* beta1_h, const double* beta2_h, double* O, int* status,
+                            void* ws, size_t ws_bytes) {
+  DOPINF_REQUIRE(Qhat && O && status && r_list_h && beta1_h && beta2_h, "NULL argument");
+  DOPINF_REQUIRE(k >= 2 && ldqh >= k, "need k >= 2 and ldqh >= k");
+  DOPINF_REQUIRE(n_r >= 1 && n_pairs >= 1, "need n_r >= 1 and n_pairs >= 1");
+  for (int g = 0; g < n_r; ++g) DOPINF_REQUIRE(r_list_h[g] >= 1 && r_list_h[g] <= 512, "r must be in [1, 512]");
+  for (int p = 0; p < n_pairs; ++p)
+    DOPINF_REQUIRE(beta1_h[p] >= 0.0 && beta2_h[p] >= 0.0, "regularization parameters must be >= 0");
+  const InferLayout L = layout(k, n_r, r_list_h, n_pairs);
+  if (!ws || ws_bytes < L.total) return fail(DOPINF_E_WORKSPACE, "workspace of %zu bytes needed, %zu given", L.total, ws_bytes);
+  int dev = 0, maxlds = 0;
+  DOPINF_HIP(hipGetDevice(&dev));
+  DOPINF_HIP(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  {
+    const size_t need = size_t(L.rmax + 1) * (2 * L.rmax + 1) * sizeof(double) + 1024;
+    DOPINF_REQUIRE(need <= size_t(maxlds), "r too large for the per-pair LDS solve");
+    if (need > 65536)
+      DOPINF_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(pair_solve_kernel),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(need)));
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws);
+  double* E = reinterpret_cast<double*>(base + L.e_off);
+  double* GE = reinterpret_cast<double*>(base + L.g_off);
+
+  // E and its Gram
+  {
+    dim3 grid(unsigned((L.km1 + 255) / 256), unsigned(L.m));
+    assemble_kernel<<<grid, 256, 0, st>>>(Qhat, ldqh, k, L.rmax, E, L.lde);
+    DOPINF_LAUNCHED();
+    int rc = gram_f64_internal(st, E, L.km1, L.m, L.lde, nullptr, nullptr, 0, nullptr, GE, L.m,
+                               base + L.gram_off, L.gram_bytes);
+    if (rc) return rc;
+  }
+
+  // distinct beta2 values (exact equality), in first-appearance order
+  std::vector<double> b2u;
+  std::vector<int> pair_uid(n_pairs);
+  for (int p = 0; p < n_pairs; ++p) {
+    int id = -1;
+    for (size_t q = 0; q < b2u.size(); ++q)
+      if (b2u[q] == beta2_h[p]) {
+        id = int(q);
+        break;
+      }
+    if (id < 0) {
+      id = int(b2u.size());
+      b2u.push_back(beta2_h[p]);
+    }
+    pair_uid[p] = id;
+  }
+  const int n_u = int(b2u.size());
+  const int uc = n_pairs < UCHUNK ? n_pairs : UCHUNK;
+
+  char* ch = base + L.chunk_off;
+  Carver mc(base + L.misc_off, ws_bytes - L.misc_off);
+  double* b2dev = mc.take<double>(size_t(uc));
+  int* ufail = mc.take<int>(size_t(uc));
+  int* pair_u = mc.take<int>(size_t(n_pairs));
+  double* b1dev = mc.take<double>(size_t(n_pairs));
+  DOPINF_HIP(hipMemcpyAsync(b1dev, beta1_h, sizeof(double) * n_pairs, hipMemcpyHostToDevice, st));
+
+  std::vector<int> pu(n_pairs);
+  for (int g = 0; g < n_r; ++g) {
+    GroupGeom geo{};
+    geo.r = r_list_h[g];
+    geo.rmax = L.rmax;
+    geo.s = nquad(geo.r);
+    geo.m = L.m;
+    geo.dmax = L.dmax;
+    const int64_t s = geo.s, w = 2 * geo.r + 1, r1 = geo.r + 1;
+    const int64_t nblk = (s + NB - 1) / NB;
+    // per-u storage at this r (packed tighter than at rmax)
+    const size_t lb = size_t(s) * s * sizeof(double), rb = size_t(s) * w * sizeof(double);
+    const size_t lib = size_t(nblk) * NB * NB * sizeof(double), cvb = size_t(r1) * w * sizeof(double);
+    double* Lq = reinterpret_cast<double*>(ch);
+    double* R = reinterpret_cast<double*>(ch + uc * lb);
+    double* R2 = reinterpret_cast<double*>(ch + uc * (lb + rb));
+    double* Linv = reinterpret_cast<double*>(ch + uc * (lb + 2 * rb));
+    double* CV = reinterpret_cast<double*>(ch + uc * (lb + 2 * rb + lib));
+    char* cgws = ch + uc * (lb + 2 * rb + lib + cvb);
+    const size_t cgb = cross_gram_workspace_internal(s, r1, w);
+    const size_t op_base = dopinf_operator_offset(n_r, r_list_h, n_pairs, g * n_pairs);
+
+    for (int u0 = 0; u0 < n_u; u0 += uc) {
+      const int nu = (n_u - u0) < uc ? (n_u - u0) : uc;
+      for (int p = 0; p < n_pairs; ++p) pu[p] = (pair_uid[p] >= u0 && pair_uid[p] < u0 + nu) ? pair_uid[p] - u0 : -1;
+      DOPINF_HIP(hipMemcpyAsync(b2dev, b2u.data() + u0, sizeof(double) * nu, hipMemcpyHostToDevice, st));
+      DOPINF_HIP(hipMemcpyAsync(pair_u, pu.data(), sizeof(int) * n_pairs, hipMemcpyHostToDevice, st));
+      // hipMemcpyAsync from pageable host memory returns after staging, so the
+      // host vectors may be reused in the next iteration.
+      zero_ints_kernel<<<1, 256, 0, st>>>(ufail, uc);
+      DOPINF_LAUNCHED();
+      {
+        dim3 grid(unsigned((s + 255) / 256 > 64 ? 64 : (s + 255) / 256), unsigned(s), unsigned(nu));
+        gather_qq_kernel<<<grid, 256, 0, st>>>(GE, geo, b2dev, Lq, R);
+        DOPINF_LAUNCHED();
+      }
+      for (int64_t jb = 0; jb < s; jb += NB) {
+        potf2_kernel<<<nu, 256, 0, st>>>(Lq, s, jb, Linv, ufail);
+        DOPINF_LAUNCHED();
+        const int64_t rest = s - jb - NB;
+        if (rest > 0) {
+          panel_kernel<<<dim3(unsigned((rest + 255) / 256), unsigned(nu)), 256, 0, st>>>(Lq, s, jb, Linv);
+          DOPINF_LAUNCHED();
+          const int64_t tt = (rest + 63) / 64;
+          syrk_update_kernel<<<dim3(unsigned(tt * (tt + 1) / 2), unsigned(nu)), 256, 0, st>>>(Lq, s, jb);
+          DOPINF_LAUNCHED();
+        }
+      }
+      const unsigned cchunks = unsigned((w + 31) / 32);
+      trsm_kernel<false><<<dim3(cchunks, unsigned(nu)), 256, 0, st>>>(Lq, s, Linv, R, w);
+      DOPINF_LAUNCHED();
+      copy_kernel<<<1024, 256, 0, st>>>(R, R2, int64_t(nu) * s * w);
+      DOPINF_LAUNCHED();
+      trsm_kernel<true><<<dim3(cchunks, unsigned(nu)), 256, 0, st>>>(Lq, s, Linv, R2, w);
+      DOPINF_LAUNCHED();
+      for (int u = 0; u < nu; ++u) {
+        int rc = cross_gram_internal(st, R + size_t(u) * s * w, w, R + size_t(u) * s * w, w, s, r1, w,
+                                     CV + size_t(u) * r1 * w, w, cgws, cgb);
+        if (rc) return rc;
+      }
+      PairArgs pa{};
+      pa.GE = GE;
+      pa.geo = geo;
+      pa.CV = CV;
+      pa.R2 = R2;
+      pa.ufail = ufail;
+      pa.pair_u = pair_u;
+      pa.beta1 = b1dev;
+      pa.O = O + op_base;
+      pa.status = status + g * n_pairs;
+      pa.n_pairs = n_pairs;
+      const size_t smem = size_t(r1) * (r1 + geo.r) * sizeof(double);
+      pair_solve_kernel<<<n_pairs, 256, smem, st>>>(pa);
+      DOPINF_LAUNCHED();
+    }
+  }
+  return DOPINF_OK;
+}

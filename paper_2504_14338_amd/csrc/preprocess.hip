@@ -1,0 +1,212 @@
+// Step II of dOpInf (arXiv:2504.14338, Sec. 3.3): per-row temporal mean and
+// per-variable max-abs scale of the centered snapshots.
+//
+// HBM-bound: one wavefront streams one row (k contiguous elements, coalesced
+// 512-B loads per wave instruction), holds it in registers when k <= 64*NV,
+// and reduces sum and max |x - mean| across the 64 lanes.  Per-variable maxima
+// come from a deterministic two-stage max over the per-row maxima (max is
+// exact, so the result is independent of order).
+#include "common.hpp"
+
+namespace dopinf {
+namespace {
+
+constexpr int kRowsPerBlock = 4;  // one 64-lane wave per row
+
+template <class T>
+__device__ __forceinline__ double ld(const T* p) { return static_cast<double>(*p); }
+
+// NV > 0: the row is kept in registers (k <= 64*NV); NV == 0: re-read.
+template <class T, int NV>
+__global__ __launch_bounds__(256) void row_stats_kernel(
+    const T* __restrict__ Q, int64_t n, int64_t k, int64_t ldq, int center,
+    double* __restrict__ mean, double* __restrict__ rowmax) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = int64_t(blockIdx.x) * kRowsPerBlock + (threadIdx.x >> 6);
+  if (row >= n) return;
+  const T* q = Q + row * ldq;
+  double mu = 0.0;
+  double m = 0.0;
+  if constexpr (NV > 0) {
+    double v[NV];
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+      int64_t t = lane + 64 * j;
+      v[j] = (t < k) ? ld(q + t) : 0.0;
+      s += v[j];
+    }
+    s = wave_sum(s);
+    mu = center ? s / static_cast<double>(k) : 0.0;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+      int64_t t = lane + 64 * j;
+      if (t < k) m = fmax(m, fabs(v[j] - mu));
+    }
+  } else {
+    double s = 0.0;
+    for (int64_t t = lane; t < k; t += 64) s += ld(q + t);
+    s = wave_sum(s);
+    mu = center ? s / static_cast<double>(k) : 0.0;
+    for (int64_t t = lane; t < k; t += 64) m = fmax(m, fabs(ld(q + t) - mu));
+  }
+  m = wave_max(m);
+  if (lane == 0) {
+    mean[row] = mu;
+    rowmax[row] = m;
+  }
+}
+
+struct VarRanges {
+  int nvars;
+  int64_t row0[DOPINF_MAX_VARS + 1];
+  int chunk0[DOPINF_MAX_VARS + 1];  // prefix sum of chunks per variable
+};
+
+constexpr int kChunkRows = 16384;
+
+__device__ __forceinline__ int find_var(const VarRanges& vr, int chunk) {
+  int v = 0;
+  while (v + 1 < vr.nvars && chunk >= vr.chunk0[v + 1]) ++v;
+  return v;
+}
+
+// Stage 1: max of rowmax over one chunk of rows of one variable.
+__global__ __launch_bounds__(256) void var_max_partial_kernel(
+    const double* __restrict__ rowmax, VarRanges vr, double* __restrict__ part) {
+  __shared__ double red[4];
+  const int c = blockIdx.x;
+  const int v = find_var(vr, c);
+  const int64_t lo = vr.row0[v] + int64_t(c - vr.chunk0[v]) * kChunkRows;
+  const int64_t hi = min(vr.row0[v + 1], lo + kChunkRows);
+  double m = 0.0;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += 256) m = fmax(m, rowmax[i]);
+  m = wave_max(m);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) part[c] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+// Stage 2: one wave per variable; zero range -> scale 1 and a flag.
+__global__ void var_max_final_kernel(const double* __restrict__ part, VarRanges vr,
+                                     int do_scale, double* __restrict__ scale,
+                                     int* __restrict__ zero_range) {
+  const int v = blockIdx.x;
+  double m = 0.0;
+  for (int c = vr.chunk0[v] + threadIdx.x; c < vr.chunk0[v + 1]; c += 64) m = fmax(m, part[c]);
+  m = wave_max(m);
+  if (threadIdx.x == 0) {
+    int zr = 0;
+    double s = 1.0;
+    if (do_scale) {
+      if (m == 0.0) {
+        zr = 1;
+      } else {
+        s = m;  // NaN propagates: fmax drops NaN, so a NaN row gives a finite max
+      }
+    }
+    scale[v] = s;
+    if (zero_range) zero_range[v] = zr;
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void apply_kernel(T* __restrict__ Q, int64_t n, int64_t k,
+                                                    int64_t ldq, const double* __restrict__ mean,
+                                                    const double* __restrict__ scale, VarRanges vr) {
+  const int64_t row = int64_t(blockIdx.x) * kRowsPerBlock + (threadIdx.x >> 6);
+  if (row >= n) return;
+  int v = 0;
+  while (v + 1 < vr.nvars && row >= vr.row0[v + 1]) ++v;
+  const double mu = mean[row];
+  const double s = scale[v];
+  T* q = Q + row * ldq;
+  for (int64_t t = threadIdx.x & 63; t < k; t += 64) q[t] = static_cast<T>((ld(q + t) - mu) / s);
+}
+
+VarRanges make_ranges(int nvars, const int64_t* var_rows_h) {
+  VarRanges vr{};
+  vr.nvars = nvars;
+  int c = 0;
+  for (int v = 0; v <= nvars; ++v) {
+    vr.row0[v] = var_rows_h[v];
+    vr.chunk0[v] = c;
+    if (v < nvars) c += int((var_rows_h[v + 1] - var_rows_h[v] + kChunkRows - 1) / kChunkRows);
+  }
+  return vr;
+}
+
+template <class T>
+void launch_row_stats(hipStream_t st, const T* Q, int64_t n, int64_t k, int64_t ldq, int center,
+                      double* mean, double* rowmax) {
+  dim3 grid(unsigned((n + kRowsPerBlock - 1) / kRowsPerBlock));
+  if (k <= 64 * 8)
+    row_stats_kernel<T, 8><<<grid, 256, 0, st>>>(Q, n, k, ldq, center, mean, rowmax);
+  else if (k <= 64 * 16)
+    row_stats_kernel<T, 16><<<grid, 256, 0, st>>>(Q, n, k, ldq, center, mean, rowmax);
+  else if (k <= 64 * 32)
+    row_stats_kernel<T, 32><<<grid, 256, 0, st>>>(Q, n, k, ldq, center, mean, rowmax);
+  else
+    row_stats_kernel<T, 0><<<grid, 256, 0, st>>>(Q, n, k, ldq, center, mean, rowmax);
+}
+
+}  // namespace
+
+int check_var_rows(int64_t n, int nvars, const int64_t* var_rows_h) {
+  DOPINF_REQUIRE(nvars >= 1 && nvars <= DOPINF_MAX_VARS, "nvars must be in [1, %d]", DOPINF_MAX_VARS);
+  DOPINF_REQUIRE(var_rows_h != nullptr, "var_rows_h is NULL");
+  DOPINF_REQUIRE(var_rows_h[0] == 0 && var_rows_h[nvars] == n, "var_rows_h must start at 0 and end at n");
+  for (int v = 0; v < nvars; ++v)
+    DOPINF_REQUIRE(var_rows_h[v + 1] > var_rows_h[v], "var_rows_h must be strictly increasing");
+  return DOPINF_OK;
+}
+
+}  // namespace dopinf
+
+using namespace dopinf;
+
+extern "C" size_t dopinf_preprocess_workspace(int64_t n, int64_t /*k*/, int nvars) {
+  if (n <= 0 || nvars <= 0) return 0;
+  Carver c(nullptr, 0);
+  c.take<double>(size_t(n));
+  c.take<double>(size_t(n / kChunkRows + nvars + 1));
+  return c.used;
+}
+
+extern "C" int dopinf_preprocess(void* stream, int dtype, void* Q, int64_t n, int64_t k, int64_t ldq,
+                                 int nvars, const int64_t* var_rows_h, unsigned flags, double* mean,
+                                 double* scale, int* zero_range, void* ws, size_t ws_bytes) {
+  DOPINF_REQUIRE(dtype == DOPINF_F64 || dtype == DOPINF_F32, "dtype must be DOPINF_F64 or DOPINF_F32");
+  DOPINF_REQUIRE(Q && mean && scale, "Q, mean and scale must be non-NULL");
+  DOPINF_REQUIRE(n >= 1 && k >= 1 && ldq >= k, "need n >= 1, k >= 1, ldq >= k");
+  DOPINF_REQUIRE((flags & ~7u) == 0, "unknown flag bits");
+  int rc = check_var_rows(n, nvars, var_rows_h);
+  if (rc) return rc;
+  const size_t need = dopinf_preprocess_workspace(n, k, nvars);
+  if (!ws || ws_bytes < need)
+    return fail(DOPINF_E_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Carver c(ws, ws_bytes);
+  double* rowmax = c.take<double>(size_t(n));
+  double* part = c.take<double>(size_t(n / kChunkRows + nvars + 1));
+  VarRanges vr = make_ranges(nvars, var_rows_h);
+  const int center = (flags & DOPINF_CENTER) ? 1 : 0;
+  if (dtype == DOPINF_F64)
+    launch_row_stats(st, static_cast<const double*>(Q), n, k, ldq, center, mean, rowmax);
+  else
+    launch_row_stats(st, static_cast<const float*>(Q), n, k, ldq, center, mean, rowmax);
+  DOPINF_LAUNCHED();
+  var_max_partial_kernel<<<vr.chunk0[nvars], 256, 0, st>>>(rowmax, vr, part);
+  DOPINF_LAUNCHED();
+  var_max_final_kernel<<<nvars, 64, 0, st>>>(part, vr, (flags & DOPINF_SCALE) ? 1 : 0, scale, zero_range);
+  DOPINF_LAUNCHED();
+  if (flags & DOPINF_APPLY) {
+    dim3 grid(unsigned((n + kRowsPerBlock - 1) / kRowsPerBlock));
+    if (dtype == DOPINF_F64)
+      apply_kernel<double><<<grid, 256, 0, st>>>(static_cast<double*>(Q), n, k, ldq, mean, scale, vr);
+    else
+      apply_kernel<float><<<grid, 256, 0, st>>>(static_cast<float*>(Q), n, k, ldq, mean, scale, vr);
+    DOPINF_LAUNCHED();
+  }
+  return DOPINF_OK;
+}

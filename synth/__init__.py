@@ -206,10 +206,17 @@ def c2_snapshots(modes: WaveModes, noise_var: float = 1e-8, seed: int = 2,
     gen.manual_seed(int(seed))
     psi = torch.from_numpy(modes.temporal(np.arange(t0, t0 + k))).to(device)
     coef = torch.from_numpy(modes.amp * modes.sigma).to(device)
+    kap = torch.from_numpy(modes.kappa.astype(np.float64)).to(device)
+    cosm = torch.from_numpy(modes.sp_kind == 1).to(device)
+    wts = torch.from_numpy(modes.weights.T.copy()).to(device)   # nvars x n_modes
     std = math.sqrt(noise_var)
     for r0 in range(0, n, chunk_rows):
         r1 = min(n, r0 + chunk_rows)
-        phi = torch.from_numpy(modes.spatial(np.arange(r0, r1))).to(device)
+        rows = torch.arange(r0, r1, device=device, dtype=torch.int64)
+        jj = (rows % modes.ncell).to(torch.float64)
+        ph = (2.0 * math.pi / modes.ncell) * torch.outer(jj, kap)
+        phi = torch.where(cosm[None, :], torch.cos(ph), torch.sin(ph))
+        phi *= math.sqrt(2.0 / modes.ncell) * wts[rows // modes.ncell]
         blk = Q[r0:r1]
         if std > 0:
             blk.normal_(0.0, std, generator=gen)

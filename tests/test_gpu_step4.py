@@ -1,0 +1,197 @@
+"""GPU parity of Step IV (regularized operator inference, rollouts, scoring
+and selection) against the CPU oracle, through the C ABI.
+
+Operator tolerance: two correct float64 solvers of the regularized normal
+equations differ by about u * kappa(M).  The oracle measures that spread on
+each system by solving it twice (LU as in the paper's listing, Cholesky), and
+the GPU must agree within max(1e-10, 10 * spread).
+"""
+import numpy as np
+import pytest
+
+import oracle as orc
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def op_tol(G, B, r, b1, b2):
+    O_lu = orc.solve_operators(G, B, r, b1, b2, method="lu")
+    O_ch = orc.solve_operators(G, B, r, b1, b2, method="cholesky")
+    return max(1e-10, 10 * rel(O_ch, O_lu)), O_lu
+
+
+@pytest.fixture(scope="module")
+def c1_qhat(gpu_lib):
+    dp = gpu_lib
+    Q, var_rows, sysq, V = synth.c1_snapshots(seed=1)
+    Qd = dev(Q)
+    mean, scale, _ = dp.preprocess(Qd, var_rows)
+    D = dp.gram(Qd, mean, scale, var_rows)
+    lam, Tr, Qhat, info, r = dp.reduce(D, r=10)
+    assert int(info.item()) == 0
+    return Qhat.contiguous(), Q, var_rows
+
+
+def test_infer_single_pair_c1(gpu_lib, c1_qhat):
+    dp = gpu_lib
+    Qhat, Q, var_rows = c1_qhat
+    O, status, views = dp.infer(Qhat, [10], [1e-6], [1e-4])
+    assert status.cpu().numpy().tolist() == [0]
+    Qh = Qhat.cpu().numpy()
+    _, G, B = orc.opinf_data(Qh)
+    tol, O_ref = op_tol(G, B, 10, 1e-6, 1e-4)
+    assert rel(views[0][0].cpu().numpy(), O_ref) <= tol
+
+
+def test_infer_grid_of_sizes_and_pairs(gpu_lib, c1_qhat):
+    dp = gpu_lib
+    Qhat, _, _ = c1_qhat
+    Qh = Qhat.cpu().numpy()
+    r_list = [3, 6, 10]
+    b1 = [1e-8, 1e-8, 1e-4, 1e-4, 1e-2, 1e-2]
+    b2 = [1e-6, 1e-1, 1e-6, 1e-1, 1e-6, 1e-1]
+    O, status, views = dp.infer(Qhat, r_list, b1, b2)
+    assert np.all(status.cpu().numpy() == 0)
+    for g, r in enumerate(r_list):
+        _, G, B = orc.opinf_data(Qh[:r])
+        for p in range(len(b1)):
+            tol, O_ref = op_tol(G, B, r, b1[p], b2[p])
+            assert rel(views[g][p].cpu().numpy(), O_ref) <= tol, (r, p)
+
+
+def test_infer_exact_recovery(gpu_lib):
+    # a known quadratic ROM's own trajectory as reduced data: at beta = 0 the
+    # operators are recovered (up to u * kappa(G), kappa ~ 1e11 here)
+    dp = gpu_lib
+    sysq = synth.c1_system(seed=21, r=3, k=20, rho=0.9, h_fro=0.2, c_var=1e-2)
+    O, status, views = dp.infer(dev(sysq.q), [3], [0.0], [0.0])
+    assert int(status.item()) == 0
+    A, H, c = orc.split_operators(views[0][0].cpu().numpy(), 3)
+    Hn = np.stack([sysq.H[:, i * 3 + j] + (sysq.H[:, j * 3 + i] if j != i else 0.0)
+                   for i in range(3) for j in range(i, 3)], axis=1)
+    assert np.max(np.abs(A - sysq.A)) < 1e-6
+    assert np.max(np.abs(H - Hn)) < 1e-6
+    assert np.max(np.abs(c - sysq.c)) < 1e-6
+
+
+def test_infer_reports_breakdown(gpu_lib):
+    dp = gpu_lib
+    rng = np.random.default_rng(3)
+    Qh = rng.standard_normal((3, 50))
+    Qh[1] = 0.0          # a mode that is identically zero: singular normal matrix at beta = 0
+    O, status, _ = dp.infer(dev(Qh), [3], [0.0, 1e-3], [0.0, 1e-3])
+    assert status.cpu().numpy().tolist() == [dp.E_NOTSPD, 0]
+
+
+def test_rollout_parity_given_operators(gpu_lib, c1_qhat):
+    dp = gpu_lib
+    Qhat, _, _ = c1_qhat
+    Qh = Qhat.cpu().numpy()
+    r_list = [4, 10]
+    b1 = [1e-6, 1e-2]
+    b2 = [1e-4, 1e-1]
+    O, status, views = dp.infer(Qhat, r_list, b1, b2)
+    n_states = 1200
+    out = dp.rollout(O, Qhat, r_list, 2, n_states, max_growth=1.2, solve_status=status, keep_traj=True, full=True)
+    te = out["train_err"].cpu().numpy()
+    gr = out["growth"].cpu().numpy()
+    oc = out["outcome"].cpu().numpy()
+    for g, r in enumerate(r_list):
+        for p in range(2):
+            Og = views[g][p].cpu().numpy()
+            Qt = orc.rollout(Og, r, Qh[:r, 0], n_states)
+            fin, e, gg, ok = orc.score(Qt, Qh[:r], Qh.shape[1], 1.2)
+            it = g * 2 + p
+            traj = out["traj_views"][g][p].cpu().numpy().T
+            if fin:
+                scale = np.max(np.abs(Qt))
+                assert np.max(np.abs(traj - Qt)) <= 1e-9 * scale, (r, p)
+                assert te[it] == pytest.approx(e, rel=1e-8, abs=1e-14)
+                assert gr[it] == pytest.approx(gg, rel=1e-10)
+                assert (oc[it] == dp.ITEM_PASS) == ok
+            else:
+                assert oc[it] == dp.ITEM_NONFINITE
+    best = out["best"].cpu().numpy()
+    for g, r in enumerate(r_list):
+        cand = [(te[g * 2 + p], g * 2 + p) for p in range(2) if oc[g * 2 + p] == dp.ITEM_PASS]
+        assert best[g] == (min(cand)[1] if cand else -1)
+
+
+def test_rollout_hand_cases_and_failure_modes(gpu_lib):
+    import torch
+    dp = gpu_lib
+    # r = 1: q+ = 0.5 q + 0.25 q^2 + 0.1 from q0 = 2; second item unstable (q+ = 2 q)
+    O = torch.tensor([0.5, 0.25, 0.1, 2.0, 0.0, 0.0], dtype=torch.float64, device="cuda")
+    Qhat = torch.tensor([[2.0, 2.1, 2.2525, 2.0]], dtype=torch.float64, device="cuda")
+    out = dp.rollout(O, Qhat, [1], 2, 3, max_growth=1.2, keep_traj=True, full=True)
+    tr = out["traj_views"][0][0].cpu().numpy()[:, 0]
+    assert tr[1] == pytest.approx(2.1, abs=1e-15)
+    assert tr[2] == pytest.approx(1.05 + 0.25 * 2.1 ** 2 + 0.1, abs=1e-15)
+    assert out["outcome"].cpu().numpy().tolist()[1] == dp.ITEM_GROWTH
+    # early exit decides the same outcome and marks the unrun states NaN
+    out2 = dp.rollout(O, Qhat, [1], 2, 50, max_growth=1.2, keep_traj=True)
+    assert out2["outcome"].cpu().numpy().tolist()[1] == dp.ITEM_GROWTH
+    assert np.isnan(out2["traj_views"][0][1].cpu().numpy()[-1, 0])
+    # r = 2 hand case: columns [A | H(0,0) H(0,1) H(1,1) | c]
+    O2 = torch.tensor([[0.5, 0.0, 1.0, 0.0, 0.0, 0.0], [0.0, 0.25, 0.0, 2.0, 0.0, 1.0]],
+                      dtype=torch.float64, device="cuda").reshape(-1)
+    Qh2 = torch.tensor([[1.0, 1.5], [2.0, 5.5]], dtype=torch.float64, device="cuda")
+    o2 = dp.rollout(O2, Qh2, [2], 1, 2, keep_traj=True, full=True)
+    assert np.array_equal(o2["traj_views"][0][0].cpu().numpy()[1], [1.5, 5.5])
+    assert o2["train_err"].item() == 0.0
+    # a non-finite rollout
+    O3 = torch.tensor([1e200, 1e200, 0.0], dtype=torch.float64, device="cuda")
+    o3 = dp.rollout(O3, Qhat, [1], 1, 10, full=True)
+    assert o3["outcome"].item() == dp.ITEM_NONFINITE
+    assert o3["best"].item() == -1
+
+
+def test_selection_ties_pick_first(gpu_lib, c1_qhat):
+    dp = gpu_lib
+    Qhat, _, _ = c1_qhat
+    O, status, views = dp.infer(Qhat, [5], [1e-3, 1e-3, 1e-3], [1e-2, 1e-2, 1e-2])
+    out = dp.rollout(O, Qhat, [5], 3, 1200, solve_status=status)
+    te = out["train_err"].cpu().numpy()
+    assert te[0] == te[1] == te[2]
+    if out["outcome"].cpu().numpy()[0] == dp.ITEM_PASS:
+        assert out["best"].item() == 0
+
+
+def test_small_sweep_matches_oracle(gpu_lib, c1_qhat):
+    dp = gpu_lib
+    Qhat, _, _ = c1_qhat
+    Qh = Qhat.cpu().numpy()
+    B1 = synth.logspace_points(-10, 0, 4)
+    B2 = synth.logspace_points(-4, 4, 4)
+    b1 = [x for x in B1 for _ in B2]
+    b2 = [y for _ in B1 for y in B2]
+    r_list = [4, 8]
+    O, status, views = dp.infer(Qhat, r_list, b1, b2)
+    out = dp.rollout(O, Qhat, r_list, len(b1), 1200, solve_status=status)
+    ref = orc.sweep(Qh, r_list, list(B1), list(B2), 1200)
+    te = out["train_err"].cpu().numpy()
+    oc = out["outcome"].cpu().numpy()
+    for it in range(len(ref["r"])):
+        if ref["passed"][it]:
+            assert oc[it] == dp.ITEM_PASS or abs(ref["growth"][it] - 1.2) < 1e-6
+            assert te[it] == pytest.approx(ref["train_err"][it], rel=1e-6)
+    best = out["best"].cpu().numpy()
+    for g in range(len(r_list)):
+        rb = ref["best"][g]
+        if rb < 0:
+            assert best[g] == -1
+        else:
+            gi = best[g]
+            # a different pick is only allowed between near-ties
+            assert abs(te[gi] - ref["train_err"][g * len(b1) + rb]) <= 1e-6 * ref["train_err"][g * len(b1) + rb]
