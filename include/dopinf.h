@@ -183,6 +183,75 @@ int dopinf_rollout(void* stream, int n_r, const int* r_list_h, int n_pairs,
                    double* train_err, double* growth, int* outcome, int* best,
                    void* ws, size_t ws_bytes);
 
+
+/* ---- Learned closure of the discrete ROM (an addition to the paper) --------
+ * g: R^r -> R^r, an MLP r -> 128 -> 128 -> r with GELU (error-function form),
+ * corrects the one-step ROM map of Eq. (11): q_{t+1} = f_ROM(q_t) + g(q_t).
+ * Parameters are float32, packed as [W1 (128 x r) | b1 (128) | W2 (128 x 128)
+ * | b2 (128) | W3 (r x 128) | b3 (r)], row-major; dopinf_closure_param_count
+ * gives their number (0 when r is outside [1, 64]).  Standardization `norm`
+ * (4r doubles) = [mean_x | std_x | mean_y | std_y] per mode (population std,
+ * 0 -> 1).  Standardized inputs, weights and hidden activations are rounded
+ * to bfloat16 (nearest even) before each product; sums are float32.
+ * Initial weights are an input (the caller draws them). */
+int64_t dopinf_closure_param_count(int r);
+
+/* R[t, :] = Qhat[:, t+1] - f_ROM(Qhat[:, t]), t = 0 .. k-2; O is r x d
+ * (dopinf_infer's layout), Qhat r x k (ldqh), R (k-1) x r row-major. */
+int dopinf_rom_residuals(void* stream, const double* O, int r,
+                         const double* Qhat, int64_t ldqh, int64_t k,
+                         double* R);
+
+/* Per-mode statistics of inputs X and targets Y (N x r row-major). */
+int dopinf_closure_norms(void* stream, int r, const double* X,
+                         const double* Y, int64_t N, double* norm);
+
+/* Minibatch Adam (Kingma & Ba 2015) on the mean squared error of the
+ * standardized targets.  Epoch e visits row (a*i + c) mod N at position i,
+ * a = max(1, (e*2654435761 + 1) mod N) advanced to the next value coprime with
+ * N, c = (e*40503 + 17) mod N; minibatches are consecutive runs of `batch`
+ * (<= 256) positions.  params: in = initial, out = trained; norm: out;
+ * adam_m, adam_v: P floats each (zeroed by the call); loss_log (NULL or
+ * `epochs` floats): mean loss per epoch.  One workgroup runs the whole
+ * training on `stream`. */
+size_t dopinf_closure_fit_workspace(int r, int64_t N);
+int dopinf_closure_fit(void* stream, int r, const double* X, const double* Y,
+                       int64_t N, int epochs, int batch, double lr,
+                       double beta1, double beta2, double eps, float* params,
+                       double* norm, float* adam_m, float* adam_v,
+                       float* loss_log, void* ws, size_t ws_bytes);
+
+/* Gradient (packed like params) and mean loss of one batch of N <= 256 rows;
+ * uses dopinf_closure_fit_workspace(r, N). */
+int dopinf_closure_grad(void* stream, int r, const float* params,
+                        const double* norm, const double* X, const double* Y,
+                        int64_t N, float* grad, float* loss, void* ws,
+                        size_t ws_bytes);
+
+/* G (NULL or N x r) = g(X) in physical units; gmax (NULL or one double) =
+ * max over rows of ||g(x_row)||_2. */
+size_t dopinf_closure_eval_workspace(int64_t N);
+int dopinf_closure_eval(void* stream, int r, const float* params,
+                        const double* norm, const double* X, int64_t N,
+                        double* G, double* gmax, void* ws, size_t ws_bytes);
+
+/* M rollouts of n_states states from q0 (M x r): q_{t+1} = f_ROM(q_t) + g(q_t).
+ * Once ||g(q_t)|| > threshold (or is not finite) rollout m latches to the plain
+ * ROM for the rest of the horizon; fallback_at[m] = that t, or -1.
+ * threshold <= 0 runs the plain ROM (params / norm may be NULL).
+ * Qref (r x k_ref, ldref) is the reference: err[m] = max_{t<k_ref}
+ * ||q_t - Qref[:, t]|| / ||Qref[:, t]||; growth[m] = max_{t,i} |q_t[i] - m_i| /
+ * max_{t,i} |Qref[i, t] - m_i| (m: temporal mean of Qref); outcome[m] as in
+ * dopinf_rollout.  traj: NULL or M x n_states x r. */
+size_t dopinf_closure_rollout_workspace(int r);
+int dopinf_closure_rollout(void* stream, int r, const double* O,
+                           const float* params, const double* norm,
+                           double threshold, const double* q0, int64_t M,
+                           int n_states, const double* Qref, int64_t ldref,
+                           int64_t k_ref, double max_growth, double* traj,
+                           double* err, double* growth, int* outcome,
+                           int* fallback_at, void* ws, size_t ws_bytes);
+
 #ifdef __cplusplus
 }
 #endif

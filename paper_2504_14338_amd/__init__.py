@@ -17,7 +17,8 @@ __all__ = [
     "GRAM_NATIVE", "GRAM_BF16X3", "ITEM_PASS", "ITEM_NONFINITE",
     "ITEM_GROWTH", "ITEM_SOLVE", "preprocess", "gram", "cross_gram",
     "reduce", "infer", "operator_offset", "rollout", "traj_offset",
-    "n_quad", "lib_path",
+    "n_quad", "lib_path", "closure_param_count", "rom_residuals", "closure_fit", "closure_norms",
+    "closure_grad", "closure_eval", "closure_rollout",
 ]
 
 OK, E_ARG, E_HIP, E_WORKSPACE, E_RANK, E_NOTSPD, E_NONFINITE, E_NOSTABLE, E_TIMEOUT = range(9)
@@ -60,6 +61,18 @@ _SIGS = {
     "dopinf_rollout_workspace": ([_i32, _vp, _i32, _i64], _sz),
     "dopinf_rollout": ([_vp, _i32, _vp, _i32, _vp, _vp, _i64, _i64, _i32, _f64, _u32, _vp, _vp, _vp, _vp, _vp, _vp,
                         _vp, _sz], _i32),
+    "dopinf_closure_param_count": ([_i32], _i64),
+    "dopinf_rom_residuals": ([_vp, _vp, _i32, _vp, _i64, _i64, _vp], _i32),
+    "dopinf_closure_fit_workspace": ([_i32, _i64], _sz),
+    "dopinf_closure_fit": ([_vp, _i32, _vp, _vp, _i64, _i32, _i32, _f64, _f64, _f64, _f64, _vp, _vp, _vp, _vp, _vp,
+                            _vp, _sz], _i32),
+    "dopinf_closure_norms": ([_vp, _i32, _vp, _vp, _i64, _vp], _i32),
+    "dopinf_closure_grad": ([_vp, _i32, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _sz], _i32),
+    "dopinf_closure_eval_workspace": ([_i64], _sz),
+    "dopinf_closure_eval": ([_vp, _i32, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _sz], _i32),
+    "dopinf_closure_rollout_workspace": ([_i32], _sz),
+    "dopinf_closure_rollout": ([_vp, _i32, _vp, _vp, _vp, _f64, _vp, _i64, _i32, _vp, _i64, _i64, _f64, _vp, _vp, _vp,
+                                _vp, _vp, _vp, _sz], _i32),
 }
 
 
@@ -308,3 +321,98 @@ def rollout(O, Qhat, r_list, n_pairs, n_states, k_train=None, max_growth=1.2, so
             views.append(row)
         out["traj_views"] = views
     return out
+
+
+# ------------------------------------------------------- learned closure ---
+def closure_param_count(r):
+    return int(load().dopinf_closure_param_count(int(r)))
+
+
+def rom_residuals(O, Qhat):
+    """rho_t = qhat_{t+1} - f_ROM(qhat_t) for t = 0..k-2; O is r x d."""
+    torch = _torch()
+    lib = load()
+    r, k = Qhat.shape
+    R = torch.empty((k - 1, r), dtype=torch.float64, device=Qhat.device)
+    _check(lib.dopinf_rom_residuals(_stream(Qhat.device), _ptr(O.contiguous()), r, _ptr(Qhat),
+                                    _rowmajor(Qhat, "Qhat"), k, _ptr(R)))
+    return R
+
+
+def closure_fit(X, Y, params0, epochs, batch=256, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    """Train the MLP closure on (X, Y) rows (N x r float64).  Returns
+    (params float32, norm float64 [mx|sx|my|sy], loss per epoch float32)."""
+    torch = _torch()
+    lib = load()
+    N, r = X.shape
+    dev = X.device
+    P = closure_param_count(r)
+    params = params0.to(device=dev, dtype=torch.float32).contiguous().clone()
+    if params.numel() != P:
+        raise ValueError(f"closure with r={r} has {P} parameters, got {params.numel()}")
+    norm = torch.empty(4 * r, dtype=torch.float64, device=dev)
+    m = torch.empty(P, dtype=torch.float32, device=dev)
+    v = torch.empty(P, dtype=torch.float32, device=dev)
+    log = torch.empty(max(epochs, 1), dtype=torch.float32, device=dev)
+    ws = _ws(lib.dopinf_closure_fit_workspace(r, N), dev)
+    _check(lib.dopinf_closure_fit(_stream(dev), r, _ptr(X.contiguous()), _ptr(Y.contiguous()), N, int(epochs),
+                                  int(batch), float(lr), float(beta1), float(beta2), float(eps), _ptr(params),
+                                  _ptr(norm), _ptr(m), _ptr(v), _ptr(log), _ptr(ws), ws.numel()))
+    return params, norm, log[:epochs]
+
+
+def closure_norms(X, Y):
+    torch = _torch()
+    N, r = X.shape
+    norm = torch.empty(4 * r, dtype=torch.float64, device=X.device)
+    _check(load().dopinf_closure_norms(_stream(X.device), r, _ptr(X.contiguous()), _ptr(Y.contiguous()), N,
+                                       _ptr(norm)))
+    return norm
+
+
+def closure_grad(params, norm, X, Y):
+    """Gradient (float32, packed like params) and loss of one batch (N <= 256)."""
+    torch = _torch()
+    lib = load()
+    N, r = X.shape
+    dev = X.device
+    g = torch.empty(closure_param_count(r), dtype=torch.float32, device=dev)
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    ws = _ws(lib.dopinf_closure_fit_workspace(r, N), dev)
+    _check(lib.dopinf_closure_grad(_stream(dev), r, _ptr(params), _ptr(norm), _ptr(X.contiguous()),
+                                   _ptr(Y.contiguous()), N, _ptr(g), _ptr(loss), _ptr(ws), ws.numel()))
+    return g, loss
+
+
+def closure_eval(params, norm, X):
+    """g(x) rows (float64, physical units) and max ||g(x_row)||."""
+    torch = _torch()
+    lib = load()
+    N, r = X.shape
+    dev = X.device
+    G = torch.empty((N, r), dtype=torch.float64, device=dev)
+    gmax = torch.empty(1, dtype=torch.float64, device=dev)
+    ws = _ws(lib.dopinf_closure_eval_workspace(N), dev)
+    _check(lib.dopinf_closure_eval(_stream(dev), r, _ptr(params), _ptr(norm), _ptr(X.contiguous()), N, _ptr(G),
+                                   _ptr(gmax), _ptr(ws), ws.numel()))
+    return G, gmax
+
+
+def closure_rollout(O, params, norm, threshold, q0, n_states, Qref, max_growth=1.2, keep_traj=False):
+    """Ensemble rollouts q_{t+1} = f_ROM(q_t) + g(q_t) (threshold <= 0: plain ROM)."""
+    torch = _torch()
+    lib = load()
+    M, r = q0.shape
+    dev = q0.device
+    k_ref = Qref.shape[1]
+    traj = torch.empty((M, n_states, r), dtype=torch.float64, device=dev) if keep_traj else None
+    err = torch.empty(M, dtype=torch.float64, device=dev)
+    gr = torch.empty(M, dtype=torch.float64, device=dev)
+    oc = torch.empty(M, dtype=torch.int32, device=dev)
+    fb = torch.empty(M, dtype=torch.int32, device=dev)
+    ws = _ws(lib.dopinf_closure_rollout_workspace(r), dev)
+    _check(lib.dopinf_closure_rollout(_stream(dev), r, _ptr(O.contiguous()), _ptr(params), _ptr(norm),
+                                      float(threshold), _ptr(q0.contiguous()), M, int(n_states), _ptr(Qref),
+                                      _rowmajor(Qref, "Qref"), k_ref, float(max_growth), _ptr(traj), _ptr(err),
+                                      _ptr(gr), _ptr(oc), _ptr(fb), _ptr(ws), ws.numel()))
+    return {"traj": traj, "err": err, "growth": gr, "outcome": oc, "fallback_at": fb}

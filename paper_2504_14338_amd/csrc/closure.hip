@@ -1,0 +1,847 @@
+// Learned closure for the discrete quadratic ROM of Eq. (11) (arXiv:2504.14338
+// gives the ROM; the closure is an addition of this library):
+//   q_{t+1} = f_ROM(q_t) + g(q_t),   g: R^r -> R^r, r -> 128 -> 128 -> r, GELU,
+// trained on the ROM's one-step residuals of the reduced training data.
+//
+// Arithmetic: standardized inputs, weights and hidden activations are rounded
+// to bfloat16 (round to nearest even) before each product; products and sums
+// are float32 (bf16 x bf16 products are exact in float32); biases, master
+// weights and Adam state are float32; the ROM part is float64.
+//
+// Kernels:
+//  * residual_kernel      rho_t = qhat_{t+1} - f_ROM(qhat_t)
+//  * norm_kernel          per-mode mean / population std of inputs and targets
+//  * train_kernel         ONE persistent workgroup of 1024 threads runs every
+//                         epoch: per minibatch forward, backward (weight
+//                         gradients register-blocked from LDS tiles), Adam.
+//  * grad_kernel          one forward/backward over a batch (gradient checks)
+//  * eval_kernel          g(x) for a batch of states and max ||g||
+//  * closure_rollout_kernel  16 rollouts per workgroup: MLP and ROM per step,
+//                         latched fallback to the plain ROM when ||g|| exceeds
+//                         the threshold, growth / error / finiteness scores.
+#include "common.hpp"
+
+namespace dopinf {
+namespace {
+
+constexpr int H = 128;       // hidden width
+constexpr int TT = 1024;     // trainer threads
+constexpr int BMAX = 256;    // largest minibatch
+constexpr int RG = 16;       // rollouts (or eval rows) per workgroup
+constexpr int ET = 256;      // eval / rollout threads
+constexpr int BT = 16;       // minibatch rows per LDS tile in the backward pass
+
+__host__ __device__ inline int64_t nquad(int64_t r) { return r * (r + 1) / 2; }
+__host__ __device__ inline int64_t ncols(int64_t r) { return r + nquad(r) + 1; }
+
+struct Off {
+  int64_t w1, b1, w2, b2, w3, b3, P;
+  __host__ __device__ explicit Off(int r) {
+    w1 = 0;
+    b1 = int64_t(H) * r;
+    w2 = b1 + H;
+    b2 = w2 + int64_t(H) * H;
+    w3 = b2 + H;
+    b3 = w3 + int64_t(r) * H;
+    P = b3 + r;
+  }
+};
+
+__device__ __forceinline__ unsigned short bf16_bits(float f) {
+  unsigned int u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return static_cast<unsigned short>((u >> 16) | 0x40);
+  const unsigned int lsb = (u >> 16) & 1u;
+  u += 0x7fffu + lsb;
+  return static_cast<unsigned short>(u >> 16);
+}
+__device__ __forceinline__ float bf16f(float f) { return __uint_as_float(unsigned(bf16_bits(f)) << 16); }
+__device__ __forceinline__ float wb(const unsigned short* W, int64_t i) { return __uint_as_float(unsigned(W[i]) << 16); }
+__device__ __forceinline__ float gelu_f(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad_f(float x) {
+  return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.39894228040143268f;
+}
+
+// bf16 copies of the three weight matrices: [W1 (H x r) | W2 (H x H) | W3 (r x H)]
+__device__ void load_wb(const float* __restrict__ p, int r, unsigned short* Wb, int tid, int nt) {
+  const Off o(r);
+  const int64_t n1 = int64_t(H) * r, n2 = int64_t(H) * H, n3 = int64_t(r) * H;
+  for (int64_t e = tid; e < n1; e += nt) Wb[e] = bf16_bits(p[o.w1 + e]);
+  for (int64_t e = tid; e < n2; e += nt) Wb[n1 + e] = bf16_bits(p[o.w2 + e]);
+  for (int64_t e = tid; e < n3; e += nt) Wb[n1 + n2 + e] = bf16_bits(p[o.w3 + e]);
+}
+
+// forward for R rows of standardized bf16-valued inputs x (R x r)
+template <int NT>
+__device__ void mlp_fwd(int R, int r, const unsigned short* Wb, const float* __restrict__ p, const float* x, float* z1,
+                        float* a1, float* z2, float* a2, float* out, int tid) {
+  const Off o(r);
+  const unsigned short* W1 = Wb;
+  const unsigned short* W2 = Wb + int64_t(H) * r;
+  const unsigned short* W3 = W2 + int64_t(H) * H;
+  for (int e = tid; e < R * H; e += NT) {
+    const int b = e / H, j = e % H;
+    float acc = p[o.b1 + j];
+    for (int i = 0; i < r; ++i) acc += wb(W1, int64_t(j) * r + i) * x[b * r + i];
+    if (z1) z1[e] = acc;
+    a1[e] = bf16f(gelu_f(acc));
+  }
+  __syncthreads();
+  for (int e = tid; e < R * H; e += NT) {
+    const int b = e / H, j = e % H;
+    float acc = p[o.b2 + j];
+    for (int k = 0; k < H; ++k) acc += wb(W2, int64_t(j) * H + k) * a1[b * H + k];
+    if (z2) z2[e] = acc;
+    a2[e] = bf16f(gelu_f(acc));
+  }
+  __syncthreads();
+  for (int e = tid; e < R * r; e += NT) {
+    const int b = e / r, i = e % r;
+    float acc = p[o.b3 + i];
+    for (int j = 0; j < H; ++j) acc += wb(W3, int64_t(i) * H + j) * a2[b * H + j];
+    out[e] = acc;
+  }
+  __syncthreads();
+}
+
+struct Scratch {  // trainer / gradient activations, each BMAX rows
+  float *x, *y, *z1, *a1, *z2, *a2, *out, *dout, *dz2, *dz1;
+};
+
+// Load standardized (x, bf16) and (y, float) rows idx(b) into s.x / s.y.
+template <int NT>
+__device__ void load_batch(int R, int r, const double* __restrict__ X, const double* __restrict__ Y,
+                           const double* __restrict__ norm, const int64_t* idx, int64_t base, Scratch s, int tid) {
+  for (int e = tid; e < R * r; e += NT) {
+    const int b = e / r, i = e % r;
+    const int64_t row = idx ? idx[b] : base + b;
+    s.x[e] = bf16f(static_cast<float>((X[row * r + i] - norm[i]) / norm[r + i]));
+    if (Y) s.y[e] = static_cast<float>((Y[row * r + i] - norm[2 * r + i]) / norm[3 * r + i]);
+  }
+  __syncthreads();
+}
+
+// Backward of the mean squared error; gradients are ADDED to G.  Returns the
+// batch loss (mean over R*r) to every thread.
+template <int NT>
+__device__ float mlp_bwd(int R, int r, const unsigned short* Wb, Scratch s, float* G, float* tile, float* red, int tid) {
+  const Off o(r);
+  const unsigned short* W2 = Wb + int64_t(H) * r;
+  const unsigned short* W3 = W2 + int64_t(H) * H;
+  const float scale = 2.0f / float(R * r);
+  float lsum = 0.f;
+  for (int e = tid; e < R * r; e += NT) {
+    const float d = s.out[e] - s.y[e];
+    lsum += d * d;
+    s.dout[e] = scale * d;
+  }
+  // block sum of the loss
+  lsum = wave_sum(double(lsum));
+  __syncthreads();
+  if ((tid & 63) == 0) red[tid >> 6] = lsum;
+  __syncthreads();
+  float loss = 0.f;
+  for (int w = 0; w < NT / 64; ++w) loss += red[w];
+  loss /= float(R * r);
+  // dz2 = (dout W3) * gelu'(z2)
+  for (int e = tid; e < R * H; e += NT) {
+    const int b = e / H, j = e % H;
+    float acc = 0.f;
+    for (int i = 0; i < r; ++i) acc += s.dout[b * r + i] * wb(W3, int64_t(i) * H + j);
+    s.dz2[e] = acc * gelu_grad_f(s.z2[e]);
+  }
+  __syncthreads();
+  // dz1 = (dz2 W2) * gelu'(z1)
+  for (int e = tid; e < R * H; e += NT) {
+    const int b = e / H, k = e % H;
+    float acc = 0.f;
+    for (int j = 0; j < H; ++j) acc += s.dz2[b * H + j] * wb(W2, int64_t(j) * H + k);
+    s.dz1[e] = acc * gelu_grad_f(s.z1[e]);
+  }
+  __syncthreads();
+  // weight gradients: sums over the batch, tiles of BT rows staged in LDS
+  //   dW2 = dz2^T a1 (4 x 4 register blocks), dW3 = dout^T a2, dW1 = dz1^T x
+  const int jb = (tid / 32) * 4, kb = (tid % 32) * 4;  // dW2 block (NT == 1024)
+  float g2[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) g2[a][c] = 0.f;
+  float g3[8], g1[8], gb[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int q = 0; q < 8; ++q) g3[q] = g1[q] = 0.f;
+  float* Tdz2 = tile;                 // BT x H
+  float* Ta1 = tile + BT * H;         // BT x H
+  float* Tdo = Ta1 + BT * H;          // BT x r
+  float* Ta2 = Tdo + BT * 128;        // BT x H
+  float* Tdz1 = Ta2 + BT * H;         // BT x H
+  float* Tx = Tdz1 + BT * H;          // BT x r
+  for (int b0 = 0; b0 < R; b0 += BT) {
+    const int nb = min(BT, R - b0);
+    __syncthreads();
+    for (int e = tid; e < BT * H; e += NT) {
+      const int b = e / H;
+      const bool ok = b < nb;
+      Tdz2[e] = ok ? s.dz2[(b0 + b) * H + e % H] : 0.f;
+      Ta1[e] = ok ? s.a1[(b0 + b) * H + e % H] : 0.f;
+      Ta2[e] = ok ? s.a2[(b0 + b) * H + e % H] : 0.f;
+      Tdz1[e] = ok ? s.dz1[(b0 + b) * H + e % H] : 0.f;
+    }
+    for (int e = tid; e < BT * r; e += NT) {
+      const int b = e / r;
+      const bool ok = b < nb;
+      Tdo[(e / r) * 128 + e % r] = ok ? s.dout[(b0 + b) * r + e % r] : 0.f;
+      Tx[e] = ok ? s.x[(b0 + b) * r + e % r] : 0.f;
+    }
+    __syncthreads();
+    for (int b = 0; b < nb; ++b) {
+      float dv[4], av[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) dv[a] = Tdz2[b * H + jb + a];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) av[c] = Ta1[b * H + kb + c];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) g2[a][c] += dv[a] * av[c];
+    }
+    // dW3 (r x H) and dW1 (H x r): thread handles entries e = tid + NT*q
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = tid + NT * q;
+      if (e < r * H) {
+        const int i = e / H, j = e % H;  // dW3[i][j]
+        float acc = 0.f;
+        for (int b = 0; b < nb; ++b) acc += Tdo[b * 128 + i] * Ta2[b * H + j];
+        g3[q] += acc;
+        const int j1 = e / r, i1 = e % r;  // dW1[j1][i1]
+        float acc1 = 0.f;
+        for (int b = 0; b < nb; ++b) acc1 += Tdz1[b * H + j1] * Tx[b * r + i1];
+        g1[q] += acc1;
+      }
+    }
+    // bias gradients: db1 (H), db2 (H), db3 (r)
+    if (tid < H) {
+      float a = 0.f, c = 0.f;
+      for (int b = 0; b < nb; ++b) {
+        a += Tdz1[b * H + tid];
+        c += Tdz2[b * H + tid];
+      }
+      gb[0] += a;
+      gb[1] += c;
+    } else if (tid < H + r) {
+      float a = 0.f;
+      for (int b = 0; b < nb; ++b) a += Tdo[b * 128 + (tid - H)];
+      gb[2] += a;
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) G[o.w2 + int64_t(jb + a) * H + kb + c] += g2[a][c];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int e = tid + NT * q;
+    if (e < r * H) {
+      G[o.w3 + e] += g3[q];
+      G[o.w1 + e] += g1[q];
+    }
+  }
+  if (tid < H) {
+    G[o.b1 + tid] += gb[0];
+    G[o.b2 + tid] += gb[1];
+  } else if (tid < H + r) {
+    G[o.b3 + tid - H] += gb[2];
+  }
+  __syncthreads();
+  return loss;
+}
+
+__device__ int64_t gcd64(int64_t a, int64_t b) {
+  while (b) {
+    const int64_t t = a % b;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+
+// visiting order of epoch e: i -> (a i + c) mod N, a advanced to be coprime with N
+__device__ void epoch_coeffs(int64_t N, int64_t e, int64_t& a, int64_t& c) {
+  if (N == 1) {
+    a = 1;
+    c = 0;
+    return;
+  }
+  a = int64_t((uint64_t(e) * 2654435761ull + 1ull) % uint64_t(N));
+  if (a == 0) a = 1;
+  while (gcd64(a, N) != 1) a = (a + 1 < N) ? a + 1 : 1;
+  c = int64_t((uint64_t(e) * 40503ull + 17ull) % uint64_t(N));
+}
+
+struct TrainArgs {
+  int r;
+  const double* X;
+  const double* Y;
+  int64_t N;
+  int epochs, batch;
+  float lr, beta1, beta2, eps;
+  float* params;
+  const double* norm;
+  float* m;
+  float* v;
+  float* G;
+  float* loss_log;
+  int64_t* idx;
+  Scratch s;
+};
+
+__global__ __launch_bounds__(TT) void train_kernel(TrainArgs a) {
+  extern __shared__ unsigned char smem[];
+  __shared__ float red[TT / 64];
+  const int tid = threadIdx.x;
+  const int r = a.r;
+  const Off o(r);
+  unsigned short* Wb = reinterpret_cast<unsigned short*>(smem);
+  float* tile = reinterpret_cast<float*>(smem + round_up(size_t(o.P - 2 * H - r) * 2, 16));
+  for (int64_t e = tid; e < o.P; e += TT) {
+    a.m[e] = 0.f;
+    a.v[e] = 0.f;
+    a.G[e] = 0.f;
+  }
+  int64_t step = 0;
+  for (int ep = 0; ep < a.epochs; ++ep) {
+    int64_t ca, cc;
+    epoch_coeffs(a.N, ep, ca, cc);
+    double ltot = 0.0;
+    for (int64_t s0 = 0; s0 < a.N; s0 += a.batch) {
+      const int R = int(min<int64_t>(a.batch, a.N - s0));
+      __syncthreads();
+      for (int b = tid; b < R; b += TT) a.idx[b] = (ca * (s0 + b) + cc) % a.N;
+      load_wb(a.params, r, Wb, tid, TT);
+      __syncthreads();
+      load_batch<TT>(R, r, a.X, a.Y, a.norm, a.idx, 0, a.s, tid);
+      mlp_fwd<TT>(R, r, Wb, a.params, a.s.x, a.s.z1, a.s.a1, a.s.z2, a.s.a2, a.s.out, tid);
+      const float loss = mlp_bwd<TT>(R, r, Wb, a.s, a.G, tile, red, tid);
+      ltot += double(loss) * R;
+      ++step;
+      // Adam (Kingma & Ba 2015): bias corrections in double
+      const float c1 = static_cast<float>(1.0 - pow(double(a.beta1), double(step)));
+      const float c2 = static_cast<float>(1.0 - pow(double(a.beta2), double(step)));
+      for (int64_t e = tid; e < o.P; e += TT) {
+        const float g = a.G[e];
+        const float mm = a.beta1 * a.m[e] + (1.0f - a.beta1) * g;
+        const float vv = a.beta2 * a.v[e] + (1.0f - a.beta2) * g * g;
+        a.m[e] = mm;
+        a.v[e] = vv;
+        a.params[e] -= a.lr * (mm / c1) / (sqrtf(vv / c2) + a.eps);
+        a.G[e] = 0.f;
+      }
+    }
+    if (tid == 0 && a.loss_log) a.loss_log[ep] = static_cast<float>(ltot / double(a.N));
+  }
+}
+
+struct GradArgs {
+  int r;
+  const double* X;
+  const double* Y;
+  int64_t N;
+  const float* params;
+  const double* norm;
+  float* G;
+  float* loss;
+  Scratch s;
+};
+
+// gradient of the mean loss over N <= BMAX rows
+__global__ __launch_bounds__(TT) void grad_kernel(GradArgs a) {
+  extern __shared__ unsigned char smem[];
+  __shared__ float red[TT / 64];
+  const int tid = threadIdx.x;
+  const int r = a.r;
+  const Off o(r);
+  unsigned short* Wb = reinterpret_cast<unsigned short*>(smem);
+  float* tile = reinterpret_cast<float*>(smem + round_up(size_t(o.P - 2 * H - r) * 2, 16));
+  for (int64_t e = tid; e < o.P; e += TT) a.G[e] = 0.f;
+  load_wb(a.params, r, Wb, tid, TT);
+  __syncthreads();
+  double ltot = 0.0;
+  {  // N <= BMAX: one batch, the gradient of its mean loss
+    const int R = int(a.N);
+    load_batch<TT>(R, r, a.X, a.Y, a.norm, nullptr, 0, a.s, tid);
+    mlp_fwd<TT>(R, r, Wb, a.params, a.s.x, a.s.z1, a.s.a1, a.s.z2, a.s.a2, a.s.out, tid);
+    ltot = double(mlp_bwd<TT>(R, r, Wb, a.s, a.G, tile, red, tid)) * R;
+  }
+  if (tid == 0) *a.loss = static_cast<float>(ltot / double(a.N));
+}
+
+// per-mode statistics of X and Y (N x r each): norm = [mx | sx | my | sy]
+__global__ void norm_kernel(const double* __restrict__ X, const double* __restrict__ Y, int64_t N, int r,
+                            double* __restrict__ norm) {
+  __shared__ double red[4];
+  const int i = blockIdx.x % r;
+  const bool isy = blockIdx.x >= r;
+  const double* A = isy ? Y : X;
+  double s = 0.0;
+  for (int64_t t = threadIdx.x; t < N; t += 256) s += A[t * r + i];
+  s = block_sum<256>(s, red);
+  const double m = s / double(N);
+  double q = 0.0;
+  for (int64_t t = threadIdx.x; t < N; t += 256) {
+    const double d = A[t * r + i] - m;
+    q += d * d;
+  }
+  q = block_sum<256>(q, red);
+  double sd = sqrt(q / double(N));
+  if (!(sd > 0.0)) sd = 1.0;
+  if (threadIdx.x == 0) {
+    norm[(isy ? 2 : 0) * r + i] = m;
+    norm[(isy ? 3 : 1) * r + i] = sd;
+  }
+}
+
+// rho_t = qhat_{t+1} - f_ROM(qhat_t): one workgroup per t
+__global__ __launch_bounds__(256) void residual_kernel(const double* __restrict__ O, int r,
+                                                       const double* __restrict__ Qhat, int64_t ldqh, int64_t k,
+                                                       double* __restrict__ R) {
+  extern __shared__ double fsh[];
+  const int64_t t = blockIdx.x;
+  const int64_t s = nquad(r), d = ncols(r);
+  for (int64_t c = threadIdx.x; c < d; c += 256) {
+    double v;
+    if (c < r) {
+      v = Qhat[c * ldqh + t];
+    } else if (c < r + s) {
+      int ii = 0;
+      int64_t off = 0, q = c - r;
+      while (off + (r - ii) <= q) {
+        off += r - ii;
+        ++ii;
+      }
+      const int jj = ii + int(q - off);
+      v = Qhat[int64_t(ii) * ldqh + t] * Qhat[int64_t(jj) * ldqh + t];
+    } else {
+      v = 1.0;
+    }
+    fsh[c] = v;
+  }
+  __syncthreads();
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int i = w; i < r; i += 4) {
+    double acc = 0.0;
+    for (int64_t c = lane; c < d; c += 64) acc += O[int64_t(i) * d + c] * fsh[c];
+    acc = wave_sum(acc);
+    if (lane == 0) R[t * r + i] = Qhat[int64_t(i) * ldqh + t + 1] - acc;
+  }
+}
+
+// g(x) for RG rows per workgroup, physical units; gnorm[row] = ||g(x_row)||
+__global__ __launch_bounds__(ET) void eval_kernel(int r, const float* __restrict__ p, const double* __restrict__ norm,
+                                                  const double* __restrict__ X, int64_t N, double* __restrict__ Gout,
+                                                  double* __restrict__ gnorm) {
+  extern __shared__ unsigned char smem[];
+  const Off o(r);
+  unsigned short* Wb = reinterpret_cast<unsigned short*>(smem);
+  float* x = reinterpret_cast<float*>(smem + round_up(size_t(o.P - 2 * H - r) * 2, 16));
+  float* a1 = x + RG * r;
+  float* a2 = a1 + RG * H;
+  float* out = a2 + RG * H;
+  const int tid = threadIdx.x;
+  const int64_t row0 = int64_t(blockIdx.x) * RG;
+  const int R = int(min<int64_t>(RG, N - row0));
+  load_wb(p, r, Wb, tid, ET);
+  for (int e = tid; e < RG * r; e += ET) {
+    const int b = e / r, i = e % r;
+    x[e] = (b < R) ? bf16f(static_cast<float>((X[(row0 + b) * r + i] - norm[i]) / norm[r + i])) : 0.f;
+  }
+  __syncthreads();
+  mlp_fwd<ET>(RG, r, Wb, p, x, nullptr, a1, nullptr, a2, out, tid);
+  for (int b = tid / 64; b < R; b += ET / 64) {
+    double n2 = 0.0;
+    for (int i = tid % 64; i < r; i += 64) {
+      const double g = double(out[b * r + i]) * norm[3 * r + i] + norm[2 * r + i];
+      if (Gout) Gout[(row0 + b) * r + i] = g;
+      n2 += g * g;
+    }
+    n2 = wave_sum(n2);
+    if (tid % 64 == 0) gnorm[row0 + b] = sqrt(n2);
+  }
+}
+
+__global__ void max_kernel(const double* __restrict__ v, int64_t n, double* __restrict__ out) {
+  __shared__ double red[4];
+  double m = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) m = fmax(m, v[i]);
+  m = wave_max(m);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) *out = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+struct CRollArgs {
+  int r;
+  const double* O;
+  const float* p;
+  const double* norm;
+  double threshold;  // <= 0: closure off
+  const double* q0;  // M x r
+  int64_t M;
+  int n_states;
+  const double* Qref;  // r x k_ref (ld ldref): error reference and growth statistics
+  int64_t ldref, k_ref;
+  const double* mean;  // r, temporal mean of Qref
+  const double* maxdev;
+  double max_growth;
+  double* traj;  // M x n_states x r or null
+  double* err;
+  double* growth;
+  int* outcome;
+  int* fallback_at;
+};
+
+__global__ __launch_bounds__(ET) void closure_rollout_kernel(CRollArgs a) {
+  extern __shared__ unsigned char smem[];
+  const int r = a.r;
+  const Off o(r);
+  const int64_t s = nquad(r), d = ncols(r);
+  const int tid = threadIdx.x;
+  unsigned short* Wb = reinterpret_cast<unsigned short*>(smem);
+  unsigned char* cur = smem + round_up(size_t(o.P - 2 * H - r) * 2, 16);
+  float* x = reinterpret_cast<float*>(cur);
+  cur += round_up(size_t(RG) * r * 4, 16);
+  float* a1 = reinterpret_cast<float*>(cur);
+  cur += size_t(RG) * H * 4;
+  float* a2 = reinterpret_cast<float*>(cur);
+  cur += size_t(RG) * H * 4;
+  float* out = reinterpret_cast<float*>(cur);
+  cur += round_up(size_t(RG) * r * 4, 16);
+  double* q = reinterpret_cast<double*>(cur);
+  cur += size_t(RG) * r * 8;
+  double* qn = reinterpret_cast<double*>(cur);
+  cur += size_t(RG) * r * 8;
+  double* mean = reinterpret_cast<double*>(cur);
+  cur += size_t(r) * 8;
+  double* stat = reinterpret_cast<double*>(cur);  // per rollout: err2max, devmax, gnorm
+  cur += size_t(RG) * 3 * 8;
+  int* flag = reinterpret_cast<int*>(cur);  // per rollout: latched step (-1), state (0 live, 1 nonfinite)
+  cur += size_t(RG) * 2 * 4;
+  unsigned short* qi = reinterpret_cast<unsigned short*>(cur);
+  unsigned short* qj = qi + s;
+
+  const int64_t m0 = int64_t(blockIdx.x) * RG;
+  const int R = int(min<int64_t>(RG, a.M - m0));
+  const bool use_g = a.threshold > 0.0;
+  if (use_g) load_wb(a.p, r, Wb, tid, ET);
+  for (int64_t c = tid; c < s; c += ET) {
+    int ii = 0;
+    int64_t off = 0;
+    while (off + (r - ii) <= c) {
+      off += r - ii;
+      ++ii;
+    }
+    qi[c] = static_cast<unsigned short>(ii);
+    qj[c] = static_cast<unsigned short>(ii + (c - off));
+  }
+  for (int e = tid; e < RG * r; e += ET) q[e] = (e / r < R) ? a.q0[(m0 + e / r) * r + e % r] : 0.0;
+  for (int i = tid; i < r; i += ET) mean[i] = a.mean[i];
+  for (int b = tid; b < RG; b += ET) {
+    stat[b * 3 + 0] = 0.0;
+    stat[b * 3 + 1] = 0.0;
+    flag[b * 2 + 0] = -1;
+    flag[b * 2 + 1] = 0;
+  }
+  __syncthreads();
+  double maxdev = 0.0;
+  for (int i = 0; i < r; ++i) maxdev = fmax(maxdev, a.maxdev[i]);
+
+  for (int t = 0; t < a.n_states; ++t) {
+    // ---- score state t (one wave per rollout) ----
+    for (int b = tid / 64; b < R; b += ET / 64) {
+      const int lane = tid % 64;
+      double e2 = 0.0, n2 = 0.0, dv = 0.0, bad = 0.0;
+      for (int i = lane; i < r; i += 64) {
+        const double xv = q[b * r + i];
+        if (!isfinite(xv)) bad = 1.0;
+        dv = fmax(dv, fabs(xv - mean[i]));
+        if (t < a.k_ref) {
+          const double h = a.Qref[int64_t(i) * a.ldref + t];
+          e2 += (xv - h) * (xv - h);
+          n2 += h * h;
+        }
+        if (a.traj) a.traj[((m0 + b) * a.n_states + t) * r + i] = xv;
+      }
+      e2 = wave_sum(e2);
+      n2 = wave_sum(n2);
+      dv = wave_max(dv);
+      bad = wave_max(bad);
+      if (lane == 0) {
+        if (bad != 0.0) flag[b * 2 + 1] = 1;
+        stat[b * 3 + 1] = fmax(stat[b * 3 + 1], dv);
+        if (t < a.k_ref) stat[b * 3 + 0] = fmax(stat[b * 3 + 0], e2 / n2);
+      }
+    }
+    __syncthreads();
+    if (t + 1 == a.n_states) break;
+    // ---- closure g(q_t) on the RG states ----
+    if (use_g) {
+      for (int e = tid; e < RG * r; e += ET) {
+        const int i = e % r;
+        const double xv = q[e];
+        x[e] = bf16f(static_cast<float>((isfinite(xv) ? xv : 0.0) - a.norm[i]) / static_cast<float>(a.norm[r + i]));
+      }
+      __syncthreads();
+      mlp_fwd<ET>(RG, r, Wb, a.p, x, nullptr, a1, nullptr, a2, out, tid);
+      for (int b = tid / 64; b < R; b += ET / 64) {
+        double n2 = 0.0;
+        for (int i = tid % 64; i < r; i += 64) {
+          const double g = double(out[b * r + i]) * a.norm[3 * r + i] + a.norm[2 * r + i];
+          n2 += g * g;
+        }
+        n2 = wave_sum(n2);
+        if (tid % 64 == 0) {
+          stat[b * 3 + 2] = sqrt(n2);
+          if (flag[b * 2] < 0 && !(sqrt(n2) <= a.threshold)) flag[b * 2] = t;  // latch
+        }
+      }
+      __syncthreads();
+    }
+    // ---- ROM step: qn[b][i] = O[i, :] . [q_b | quad(q_b) | 1] ----
+    for (int e = tid; e < R * r; e += ET) {
+      const int b = e / r, i = e % r;
+      const double* qb = q + b * r;
+      const double* Oi = a.O + int64_t(i) * d;
+      double acc = Oi[d - 1];
+      for (int c = 0; c < r; ++c) acc += Oi[c] * qb[c];
+      for (int64_t c = 0; c < s; ++c) acc += Oi[r + c] * (qb[qi[c]] * qb[qj[c]]);
+      if (use_g && flag[b * 2] < 0) acc += double(out[e]) * a.norm[3 * r + i] + a.norm[2 * r + i];
+      qn[e] = acc;
+    }
+    __syncthreads();
+    for (int e = tid; e < R * r; e += ET) q[e] = qn[e];
+    __syncthreads();
+  }
+  for (int b = tid; b < R; b += ET) {
+    const int64_t m = m0 + b;
+    const bool nonfinite = flag[b * 2 + 1] != 0;
+    const double gr = stat[b * 3 + 1] / maxdev;
+    a.err[m] = nonfinite ? NAN : sqrt(stat[b * 3 + 0]);
+    a.growth[m] = nonfinite ? NAN : gr;
+    a.outcome[m] = nonfinite ? DOPINF_ITEM_NONFINITE : (gr < a.max_growth ? DOPINF_ITEM_PASS : DOPINF_ITEM_GROWTH);
+    a.fallback_at[m] = flag[b * 2];
+  }
+}
+
+__global__ __launch_bounds__(256) void ref_stats_kernel(const double* __restrict__ Q, int64_t ld, int64_t k,
+                                                        double* __restrict__ mean, double* __restrict__ maxdev) {
+  __shared__ double red[4];
+  const int i = blockIdx.x;
+  const double* q = Q + int64_t(i) * ld;
+  double s = 0.0;
+  for (int64_t t = threadIdx.x; t < k; t += 256) s += q[t];
+  s = block_sum<256>(s, red);
+  const double m = s / double(k);
+  double mx = 0.0;
+  for (int64_t t = threadIdx.x; t < k; t += 256) mx = fmax(mx, fabs(q[t] - m));
+  mx = wave_max(mx);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    mean[i] = m;
+    maxdev[i] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  }
+}
+
+size_t wb_bytes(int r) { return round_up(size_t(Off(r).P - 2 * H - r) * 2, 16); }
+size_t train_lds(int r) { return wb_bytes(r) + size_t(BT) * (4 * H + 128 + r) * 4; }
+size_t eval_lds(int r) { return wb_bytes(r) + round_up(size_t(RG) * r * 4, 16) + size_t(RG) * 2 * H * 4 + round_up(size_t(RG) * r * 4, 16); }
+size_t roll_lds(int r) {
+  return eval_lds(r) + size_t(RG) * r * 8 * 2 + size_t(r) * 8 + size_t(RG) * 3 * 8 + size_t(RG) * 2 * 4 +
+         size_t(nquad(r)) * 4 + 64;
+}
+
+Scratch carve_scratch(Carver& c, int r) {
+  Scratch s;
+  s.x = c.take<float>(size_t(BMAX) * r);
+  s.y = c.take<float>(size_t(BMAX) * r);
+  s.z1 = c.take<float>(size_t(BMAX) * H);
+  s.a1 = c.take<float>(size_t(BMAX) * H);
+  s.z2 = c.take<float>(size_t(BMAX) * H);
+  s.a2 = c.take<float>(size_t(BMAX) * H);
+  s.out = c.take<float>(size_t(BMAX) * r);
+  s.dout = c.take<float>(size_t(BMAX) * r);
+  s.dz2 = c.take<float>(size_t(BMAX) * H);
+  s.dz1 = c.take<float>(size_t(BMAX) * H);
+  return s;
+}
+
+int set_lds(const void* fn, size_t bytes) {
+  int dev = 0, maxlds = 0;
+  DOPINF_HIP(hipGetDevice(&dev));
+  DOPINF_HIP(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  if (bytes + 1024 > size_t(maxlds)) return fail(DOPINF_E_ARG, "closure needs %zu bytes of LDS, %d available", bytes, maxlds);
+  if (bytes > 65536) DOPINF_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes)));
+  return DOPINF_OK;
+}
+
+}  // namespace
+}  // namespace dopinf
+
+using namespace dopinf;
+
+extern "C" int64_t dopinf_closure_param_count(int r) { return (r >= 1 && r <= 64) ? Off(r).P : 0; }
+
+extern "C" int dopinf_rom_residuals(void* stream, const double* O, int r, const double* Qhat, int64_t ldqh, int64_t k,
+                                    double* R) {
+  DOPINF_REQUIRE(O && Qhat && R, "NULL argument");
+  DOPINF_REQUIRE(r >= 1 && r <= 512 && k >= 2 && ldqh >= k, "need 1 <= r <= 512, k >= 2, ldqh >= k");
+  const size_t lds = size_t(ncols(r)) * sizeof(double);
+  int rc = set_lds(reinterpret_cast<const void*>(residual_kernel), lds);
+  if (rc) return rc;
+  residual_kernel<<<unsigned(k - 1), 256, lds, static_cast<hipStream_t>(stream)>>>(O, r, Qhat, ldqh, k, R);
+  DOPINF_LAUNCHED();
+  return DOPINF_OK;
+}
+
+extern "C" size_t dopinf_closure_fit_workspace(int r, int64_t /*N*/) {
+  if (r < 1 || r > 64) return 0;
+  Carver c(nullptr, 0);
+  carve_scratch(c, r);
+  c.take<float>(size_t(Off(r).P));
+  c.take<int64_t>(BMAX);
+  return c.used;
+}
+
+extern "C" int dopinf_closure_fit(void* stream, int r, const double* X, const double* Y, int64_t N, int epochs,
+                                  int batch, double lr, double beta1, double beta2, double eps, float* params,
+                                  double* norm, float* adam_m, float* adam_v, float* loss_log, void* ws,
+                                  size_t ws_bytes) {
+  DOPINF_REQUIRE(X && Y && params && norm && adam_m && adam_v, "NULL argument");
+  DOPINF_REQUIRE(r >= 1 && r <= 64, "closure supports 1 <= r <= 64");
+  DOPINF_REQUIRE(N >= 1 && epochs >= 0 && batch >= 1 && batch <= BMAX, "need N >= 1, epochs >= 0, 1 <= batch <= 256");
+  DOPINF_REQUIRE(lr > 0 && beta1 >= 0 && beta1 < 1 && beta2 >= 0 && beta2 < 1 && eps > 0, "invalid Adam settings");
+  const size_t need = dopinf_closure_fit_workspace(r, N);
+  if (!ws || ws_bytes < need) return fail(DOPINF_E_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int rc = set_lds(reinterpret_cast<const void*>(train_kernel), train_lds(r));
+  if (rc) return rc;
+  Carver c(ws, ws_bytes);
+  TrainArgs a{};
+  a.s = carve_scratch(c, r);
+  a.G = c.take<float>(size_t(Off(r).P));
+  a.idx = c.take<int64_t>(BMAX);
+  a.r = r;
+  a.X = X;
+  a.Y = Y;
+  a.N = N;
+  a.epochs = epochs;
+  a.batch = batch;
+  a.lr = float(lr);
+  a.beta1 = float(beta1);
+  a.beta2 = float(beta2);
+  a.eps = float(eps);
+  a.params = params;
+  a.norm = norm;
+  a.m = adam_m;
+  a.v = adam_v;
+  a.loss_log = loss_log;
+  norm_kernel<<<2 * r, 256, 0, st>>>(X, Y, N, r, norm);
+  DOPINF_LAUNCHED();
+  train_kernel<<<1, TT, train_lds(r), st>>>(a);
+  DOPINF_LAUNCHED();
+  return DOPINF_OK;
+}
+
+extern "C" int dopinf_closure_norms(void* stream, int r, const double* X, const double* Y, int64_t N, double* norm) {
+  DOPINF_REQUIRE(X && Y && norm && r >= 1 && r <= 64 && N >= 1, "invalid argument");
+  norm_kernel<<<2 * r, 256, 0, static_cast<hipStream_t>(stream)>>>(X, Y, N, r, norm);
+  DOPINF_LAUNCHED();
+  return DOPINF_OK;
+}
+
+extern "C" int dopinf_closure_grad(void* stream, int r, const float* params, const double* norm, const double* X,
+                                   const double* Y, int64_t N, float* grad, float* loss, void* ws, size_t ws_bytes) {
+  DOPINF_REQUIRE(params && norm && X && Y && grad && loss, "NULL argument");
+  DOPINF_REQUIRE(r >= 1 && r <= 64 && N >= 1 && N <= BMAX, "need 1 <= r <= 64 and 1 <= N <= 256");
+  const size_t need = dopinf_closure_fit_workspace(r, N);
+  if (!ws || ws_bytes < need) return fail(DOPINF_E_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+  int rc = set_lds(reinterpret_cast<const void*>(grad_kernel), train_lds(r));
+  if (rc) return rc;
+  Carver c(ws, ws_bytes);
+  GradArgs a{};
+  a.s = carve_scratch(c, r);
+  a.r = r;
+  a.X = X;
+  a.Y = Y;
+  a.N = N;
+  a.params = params;
+  a.norm = norm;
+  a.G = grad;
+  a.loss = loss;
+  grad_kernel<<<1, TT, train_lds(r), static_cast<hipStream_t>(stream)>>>(a);
+  DOPINF_LAUNCHED();
+  return DOPINF_OK;
+}
+
+extern "C" size_t dopinf_closure_eval_workspace(int64_t N) { return N > 0 ? round_up(size_t(N) * 8, 256) : 0; }
+
+extern "C" int dopinf_closure_eval(void* stream, int r, const float* params, const double* norm, const double* X,
+                                   int64_t N, double* G, double* gmax, void* ws, size_t ws_bytes) {
+  DOPINF_REQUIRE(params && norm && X && (G || gmax), "NULL argument");
+  DOPINF_REQUIRE(r >= 1 && r <= 64 && N >= 1, "need 1 <= r <= 64, N >= 1");
+  if (!ws || ws_bytes < dopinf_closure_eval_workspace(N)) return fail(DOPINF_E_WORKSPACE, "workspace too small");
+  int rc = set_lds(reinterpret_cast<const void*>(eval_kernel), eval_lds(r));
+  if (rc) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  double* gn = static_cast<double*>(ws);
+  eval_kernel<<<unsigned((N + RG - 1) / RG), ET, eval_lds(r), st>>>(r, params, norm, X, N, G, gn);
+  DOPINF_LAUNCHED();
+  if (gmax) {
+    max_kernel<<<1, 256, 0, st>>>(gn, N, gmax);
+    DOPINF_LAUNCHED();
+  }
+  return DOPINF_OK;
+}
+
+extern "C" size_t dopinf_closure_rollout_workspace(int r) { return r > 0 ? round_up(size_t(2 * r) * 8, 256) : 0; }
+
+extern "C" int dopinf_closure_rollout(void* stream, int r, const double* O, const float* params, const double* norm,
+                                      double threshold, const double* q0, int64_t M, int n_states, const double* Qref,
+                                      int64_t ldref, int64_t k_ref, double max_growth, double* traj, double* err,
+                                      double* growth, int* outcome, int* fallback_at, void* ws, size_t ws_bytes) {
+  DOPINF_REQUIRE(O && q0 && Qref && err && growth && outcome && fallback_at, "NULL argument");
+  DOPINF_REQUIRE(threshold <= 0.0 || (params && norm), "params and norm are needed when the closure is on");
+  DOPINF_REQUIRE(r >= 1 && r <= 64 && M >= 1 && n_states >= 1 && k_ref >= 1 && ldref >= k_ref && max_growth > 0,
+                 "invalid sizes");
+  if (!ws || ws_bytes < dopinf_closure_rollout_workspace(r)) return fail(DOPINF_E_WORKSPACE, "workspace too small");
+  int rc = set_lds(reinterpret_cast<const void*>(closure_rollout_kernel), roll_lds(r));
+  if (rc) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  double* mean = static_cast<double*>(ws);
+  double* maxdev = mean + r;
+  ref_stats_kernel<<<r, 256, 0, st>>>(Qref, ldref, k_ref, mean, maxdev);
+  DOPINF_LAUNCHED();
+  CRollArgs a{};
+  a.r = r;
+  a.O = O;
+  a.p = params;
+  a.norm = norm;
+  a.threshold = threshold;
+  a.q0 = q0;
+  a.M = M;
+  a.n_states = n_states;
+  a.Qref = Qref;
+  a.ldref = ldref;
+  a.k_ref = k_ref;
+  a.mean = mean;
+  a.maxdev = maxdev;
+  a.max_growth = max_growth;
+  a.traj = traj;
+  a.err = err;
+  a.growth = growth;
+  a.outcome = outcome;
+  a.fallback_at = fallback_at;
+  closure_rollout_kernel<<<unsigned((M + RG - 1) / RG), ET, roll_lds(r), st>>>(a);
+  DOPINF_LAUNCHED();
+  return DOPINF_OK;
+}

@@ -56,7 +56,7 @@ struct Carver {
   bool ok() const { return used <= cap; }
 };
 
-inline size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+__host__ __device__ inline size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // ---- device helpers --------------------------------------------------------
 

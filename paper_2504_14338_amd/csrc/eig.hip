@@ -13,8 +13,9 @@
 //  2. All k eigenvalues of T by multisection: one wave per eigenvalue, the
 //     64 lanes evaluate Sturm counts at 64 interior points per round.
 //  3. The top r eigenvectors of T by inverse iteration with partial-pivoting
-//     LU of T - lambda I; eigenvalues closer than 1e-10 ||T|| are treated as
-//     a cluster and orthogonalized against each other inside the iteration.
+//     LU of T - lambda I (one wave per cluster, factors in LDS); eigenvalues
+//     closer than 1e-10 ||T|| form a cluster whose vectors are orthogonalized
+//     against each other inside the iteration.
 //  4. Back-transformation u = P z (reflectors applied in reverse order), one
 //     workgroup per vector with z in LDS.
 //  5. Sign rule and Qhat / T_r formation.
@@ -25,34 +26,62 @@ namespace {
 
 constexpr int TNT = 256;            // threads of the tridiagonalization kernel
 constexpr int TCH = 8;              // rows reduced together in phase 2
-constexpr long kSpinLimit = 1L << 26;
+constexpr long kSpinLimit = 1L << 30;  // polls before a barrier gives up (seconds)
 
 // ---------------------------------------------------------------------------
-// device-wide barrier for a cooperative launch (all workgroups resident)
+// Cross-workgroup communication of the persistent kernel.  All data shared
+// between workgroups (reflectors, p, partial sums, flags) is written and read
+// with relaxed device-scope atomics, which are coherent across the XCDs'
+// L2 caches; a writer drains its memory counter (s_waitcnt) before it
+// signals, so no cache-wide release/acquire fences are needed.
 // ---------------------------------------------------------------------------
-__device__ bool grid_barrier(unsigned* bar, unsigned nblocks, unsigned& gen, int* abort_flag) {
+__device__ __forceinline__ void st_dev(double* p, double v) {
+  __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), static_cast<unsigned long long>(__double_as_longlong(v)),
+                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_dev(const double* p) {
+  return __longlong_as_double(static_cast<long long>(__hip_atomic_load(
+      reinterpret_cast<unsigned long long*>(const_cast<double*>(p)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
+}
+__device__ __forceinline__ unsigned ld_flag(unsigned* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Spin (thread 0) until *p >= target; false if the abort flag was raised or
+// the spin cap was hit (then the abort flag is raised for everybody).
+__device__ bool wait_ge(unsigned* p, unsigned target, int* abort_flag) {
   __shared__ int ok_sh;
-  __syncthreads();
   if (threadIdx.x == 0) {
-    __threadfence();
-    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned target = (gen + 1) * nblocks;
     long spins = 0;
     int ok = 1;
-    while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      __builtin_amdgcn_s_sleep(1);
-      if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 || ++spins > kSpinLimit) {
-        __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        ok = 0;
-        break;
+    while (ld_flag(p) < target) {
+      if ((++spins & 255) == 0) {
+        if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 || spins > kSpinLimit) {
+          __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ok = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
       }
     }
-    __threadfence();
     ok_sh = ok;
   }
   __syncthreads();
-  ++gen;
   return ok_sh != 0;
+}
+
+// all threads: drain this workgroup's stores, then thread 0 performs `op`
+__device__ __forceinline__ void drain_then_sync() {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+}
+
+// device-wide barrier: arrive, wait for all nblocks arrivals of this round
+__device__ bool grid_barrier(unsigned* bar, unsigned nblocks, unsigned& gen, int* abort_flag) {
+  drain_then_sync();
+  if (threadIdx.x == 0) __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  ++gen;
+  return wait_ge(bar, gen * nblocks, abort_flag);
 }
 
 __global__ void zero_words_kernel(unsigned* p, int n) {
@@ -74,11 +103,45 @@ struct TridArgs {
   double* d;        // k diagonal
   double* e;        // k-1 off-diagonal
   double* tau;      // k
-  double* p;        // k
-  double* part;     // P
-  unsigned* bar;
+  double* p;        // 2 x k (double-buffered by column parity)
+  double* part;     // 2 x P
+  unsigned* bar;    // barrier counter
+  unsigned* vflag;  // number of published reflectors
   int* abort_flag;
 };
+
+// Householder reflector of row j (owned by this workgroup): publishes v_j
+// (row j of A, v_j[j+1] = 1), tau_j, d_j, e_j, then raises vflag to j+1.
+__device__ void make_reflector(const TridArgs& a, double* row, int64_t j, double* red) {
+  const int64_t k = a.k;
+  const int tid = threadIdx.x;
+  double ss = 0.0;
+  for (int64_t l = j + 2 + tid; l < k; l += TNT) ss += row[l] * row[l];
+  ss = block_sum<TNT>(ss, red);
+  const double alpha = row[j + 1];
+  double beta, tj, scal;
+  if (ss == 0.0) {
+    beta = alpha;
+    tj = 0.0;
+    scal = 0.0;
+  } else {
+    beta = -copysign(sqrt(alpha * alpha + ss), alpha);
+    tj = (beta - alpha) / beta;
+    scal = 1.0 / (alpha - beta);
+  }
+  const double dj = row[j];
+  __syncthreads();  // row may alias v_j's storage: everything read before it is overwritten
+  double* vout = a.A + j * k;
+  for (int64_t l = j + 2 + tid; l < k; l += TNT) st_dev(vout + l, (tj == 0.0) ? 0.0 : row[l] * scal);
+  if (tid == 0) {
+    st_dev(vout + j + 1, 1.0);
+    st_dev(a.tau + j, tj);
+    a.d[j] = dj;
+    a.e[j] = beta;
+  }
+  drain_then_sync();
+  if (tid == 0) __hip_atomic_store(a.vflag, unsigned(j + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 __global__ __launch_bounds__(TNT) void sytrd_kernel(TridArgs a) {
   extern __shared__ double lds_rows[];
@@ -96,62 +159,39 @@ __global__ __launch_bounds__(TNT) void sytrd_kernel(TridArgs a) {
   };
   const int nown = int((k - g + P - 1) / P) > 0 ? int((k - g + P - 1) / P) : 0;
 
-  // load owned rows of D
-  for (int q = 0; q < nown; ++q) {
+  for (int q = 0; q < nown; ++q) {  // load owned rows of D
     const int64_t i = g + int64_t(q) * P;
     double* dst = row_ptr(q);
     for (int64_t l = tid; l < k; l += TNT) dst[l] = a.D[i * a.ldd + l];
   }
   __syncthreads();
+  if (k >= 2 && g == 0) make_reflector(a, row_ptr(0), 0, &red[0][0]);
 
   for (int64_t j = 0; j + 1 < k; ++j) {
-    // ---- phase 1: reflector of row j (owned by g == j % P) ----------------
-    if (j % P == g) {
-      const int q = int(j / P);
-      double* row = row_ptr(q);
-      double ss = 0.0;
-      for (int64_t l = j + 2 + tid; l < k; l += TNT) ss += row[l] * row[l];
-      ss = block_sum<TNT>(ss, &red[0][0]);
-      const double alpha = row[j + 1];
-      __syncthreads();  // row may alias v_j's storage: read alpha before it is overwritten
-      double beta, tj, scal;
-      if (ss == 0.0) {
-        beta = alpha;
-        tj = 0.0;
-        scal = 0.0;
-      } else {
-        beta = -copysign(sqrt(alpha * alpha + ss), alpha);
-        tj = (beta - alpha) / beta;
-        scal = 1.0 / (alpha - beta);
-      }
-      double* vout = a.A + j * k;  // v_j lives in row j of the workspace
-      for (int64_t l = j + 2 + tid; l < k; l += TNT) {
-        const double x = (tj == 0.0) ? 0.0 : row[l] * scal;
-        vout[l] = x;
-        if (a.in_lds) row[l] = x;
-      }
-      if (tid == 0) {
-        vout[j + 1] = 1.0;
-        a.d[j] = row[j];
-        a.e[j] = beta;
-        a.tau[j] = tj;
-      }
-    }
-    if (!grid_barrier(a.bar, P, gen, a.abort_flag)) return;
-    const double tj = __hip_atomic_load(&a.tau[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (tj == 0.0) continue;
+    if (!wait_ge(a.vflag, unsigned(j + 1), a.abort_flag)) return;  // v_j published
+    const double tj = ld_dev(a.tau + j);
     const double* v = a.A + j * k;
-
+    const int par = int(j & 1);
+    double* pj = a.p + par * k;
+    double* partj = a.part + par * P;
+    const int q0 = int((j + 1 - g + P - 1) / P) > 0 ? int((j + 1 - g + P - 1) / P) : 0;  // first owned row > j
+    const bool owns_next = (j + 2 < k) && ((j + 1) % P == g);
+    if (tj == 0.0) {  // H_j = I: nothing to update.  The barrier keeps every
+      // workgroup within one column of the others, which the double-buffered
+      // p / partial sums rely on.
+      if (!grid_barrier(a.bar, P, gen, a.abort_flag)) return;
+      if (owns_next) make_reflector(a, row_ptr(int((j + 1) / P)), j + 1, &red[0][0]);
+      continue;
+    }
     // ---- phase 2: p_i = tau * A[i, j+1:] . v[j+1:] for owned rows i > j --
     double mypart = 0.0;
-    const int q0 = int((j + 1 - g + P - 1) / P) > 0 ? int((j + 1 - g + P - 1) / P) : 0;  // first owned row > j
     for (int qb = q0; qb < nown; qb += TCH) {
       const int nq = min(TCH, nown - qb);
       double acc[TCH];
 #pragma unroll
       for (int u = 0; u < TCH; ++u) acc[u] = 0.0;
       for (int64_t l = j + 1 + tid; l < k; l += TNT) {
-        const double vl = v[l];
+        const double vl = ld_dev(v + l);
 #pragma unroll
         for (int u = 0; u < TCH; ++u)
           if (u < nq) acc[u] += row_ptr(qb + u)[l] * vl;
@@ -171,33 +211,44 @@ __global__ __launch_bounds__(TNT) void sytrd_kernel(TridArgs a) {
           for (int ww = 0; ww < TNT / 64; ++ww) sacc += red[ww][u];
           const int64_t i = g + int64_t(qb + u) * P;
           const double pi = tj * sacc;
-          a.p[i] = pi;
-          mypart += v[i] * pi;
+          st_dev(pj + i, pi);
+          mypart += ld_dev(v + i) * pi;
         }
       }
     }
-    if (tid == 0) a.part[g] = mypart;
-    if (!grid_barrier(a.bar, P, gen, a.abort_flag)) return;
+    if (tid == 0) st_dev(partj + g, mypart);
+    if (!grid_barrier(a.bar, P, gen, a.abort_flag)) return;  // p complete
 
-    // ---- phase 3: rank-2 update of owned rows ------------------------------
-    if (tid == 0) {
+    // ---- K = tau/2 * v^T p, partial sums reduced in a fixed order ----------
+    {
       double s = 0.0;
-      for (int q = 0; q < P; ++q) s += a.part[q];
-      bc[0] = 0.5 * tj * s;
+      for (int q = tid; q < P; q += TNT) s += ld_dev(partj + q);
+      s = block_sum<TNT>(s, &red[0][0]);
+      if (tid == 0) bc[0] = 0.5 * tj * s;
+      __syncthreads();
     }
-    __syncthreads();
     const double K = bc[0];
-    for (int q = q0; q < nown; ++q) {
+    // ---- phase 3: rank-2 update; the next reflector's row goes first ------
+    auto update_row = [&](int q) {
       const int64_t i = g + int64_t(q) * P;
       double* row = row_ptr(q);
-      const double vi = v[i];
-      const double wi = a.p[i] - K * vi;
+      const double vi = ld_dev(v + i);
+      const double wi = ld_dev(pj + i) - K * vi;
       for (int64_t l = j + 1 + tid; l < k; l += TNT) {
-        const double vl = v[l];
-        const double wl = a.p[l] - K * vl;
+        const double vl = ld_dev(v + l);
+        const double wl = ld_dev(pj + l) - K * vl;
         row[l] -= vi * wl + wi * vl;
       }
+    };
+    int qn = -1;
+    if (owns_next) {
+      qn = int((j + 1) / P);
+      update_row(qn);
+      __syncthreads();
+      make_reflector(a, row_ptr(qn), j + 1, &red[0][0]);
     }
+    for (int q = q0; q < nown; ++q)
+      if (q != qn) update_row(q);
     __syncthreads();
   }
   if (k >= 1 && (k - 1) % P == g) {
@@ -317,13 +368,18 @@ __device__ __forceinline__ double hash_unit(uint64_t x) {
   return double(x >> 11) * (2.0 / 9007199254740992.0) - 1.0;
 }
 
-// One thread per cluster of the top-r eigenvalues (descending order).
-// Scratch per thread: u0, u1, u2, mult (k each) and swap flags (k bytes).
-__global__ void tri_invit_kernel(const double* d, const double* e, int64_t k, int r, const double* lambda_desc,
-                                 const double* bounds, double* Z /* r x k */, double* scratch,
-                                 unsigned char* swaps) {
-  const int j0 = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j0 >= r) return;
+// One wave per cluster of the top-r eigenvalues (descending order).  The LU
+// factors of T - lambda I (u0, u1, u2, multipliers, swaps) and the iterate
+// live in LDS when they fit (LDS_MODE), else in a per-cluster global scratch;
+// the recurrences run on lane 0, reductions use the whole wave.
+template <bool LDS_MODE>
+__global__ __launch_bounds__(64) void tri_invit_kernel(const double* d, const double* e, int64_t k, int r,
+                                                       const double* lambda_desc, const double* bounds,
+                                                       double* Z /* r x k */, double* scratch,
+                                                       unsigned char* swaps) {
+  extern __shared__ double lds[];
+  const int j0 = blockIdx.x;
+  const int lane = threadIdx.x;
   const double tnorm = bounds[3];
   const double eps = 2.220446049250313e-16;
   const double ctol = 1e-10 * fmax(tnorm, 1e-300);
@@ -331,100 +387,125 @@ __global__ void tri_invit_kernel(const double* d, const double* e, int64_t k, in
   int j1 = j0 + 1;
   while (j1 < r && fabs(lambda_desc[j1 - 1] - lambda_desc[j1]) <= ctol) ++j1;
 
-  double* u0 = scratch + size_t(j0) * 4 * k;
+  double* base = LDS_MODE ? lds : scratch + size_t(j0) * 5 * k;
+  double* u0 = base;
   double* u1 = u0 + k;
   double* u2 = u1 + k;
   double* mu = u2 + k;
-  unsigned char* sw = swaps + size_t(j0) * k;
+  double* z = mu + k;
+  unsigned char* sw = LDS_MODE ? reinterpret_cast<unsigned char*>(z + k) : swaps + size_t(j0) * k;
   const double piv_floor = eps * fmax(tnorm, 1e-300);
 
   for (int j = j0; j < j1; ++j) {
     const double lam = lambda_desc[j];
-    // LU with partial pivoting of T - lam I (rows i, i+1 at elimination step i)
-    double x = d[0] - lam;            // current row, column i
-    double y = (k > 1) ? e[0] : 0.0;  // current row, column i+1
-    for (int64_t i = 0; i + 1 < k; ++i) {
-      const double sub = e[i];                 // row i+1, column i
-      const double dn = d[i + 1] - lam;        // row i+1, column i+1
-      const double sup = (i + 2 < k) ? e[i + 1] : 0.0;  // row i+1, column i+2
-      if (fabs(sub) > fabs(x)) {
-        // pivot row = row i+1
-        const double m = x / sub;
-        u0[i] = sub;
-        u1[i] = dn;
-        u2[i] = sup;
-        mu[i] = m;
-        sw[i] = 1;
-        x = y - m * dn;
-        y = -m * sup;
-      } else {
-        double piv = x;
-        if (fabs(piv) < piv_floor) piv = copysign(piv_floor, piv == 0.0 ? 1.0 : piv);
-        const double m = sub / piv;
-        u0[i] = piv;
-        u1[i] = y;
-        u2[i] = 0.0;
-        mu[i] = m;
-        sw[i] = 0;
-        x = dn - m * y;
-        y = sup;
+    if (lane == 0) {
+      // LU with partial pivoting of T - lam I (rows i, i+1 at elimination step i)
+      double x = d[0] - lam;
+      double y = (k > 1) ? e[0] : 0.0;
+      for (int64_t i = 0; i + 1 < k; ++i) {
+        const double sub = e[i];
+        const double dn = d[i + 1] - lam;
+        const double sup = (i + 2 < k) ? e[i + 1] : 0.0;
+        if (fabs(sub) > fabs(x)) {
+          const double m = x / sub;
+          u0[i] = sub;
+          u1[i] = dn;
+          u2[i] = sup;
+          mu[i] = m;
+          sw[i] = 1;
+          x = y - m * dn;
+          y = -m * sup;
+        } else {
+          double piv = x;
+          if (fabs(piv) < piv_floor) piv = copysign(piv_floor, piv == 0.0 ? 1.0 : piv);
+          const double m = sub / piv;
+          u0[i] = piv;
+          u1[i] = y;
+          u2[i] = 0.0;
+          mu[i] = m;
+          sw[i] = 0;
+          x = dn - m * y;
+          y = sup;
+        }
       }
-    }
-    {
       double piv = x;
       if (fabs(piv) < piv_floor) piv = copysign(piv_floor, piv == 0.0 ? 1.0 : piv);
       u0[k - 1] = piv;
       u1[k - 1] = 0.0;
       u2[k - 1] = 0.0;
     }
-    for (int64_t i = 0; i < k; ++i)
+    __syncthreads();
+    for (int64_t i = lane; i < k; i += 64) {
       if (fabs(u0[i]) < piv_floor) u0[i] = copysign(piv_floor, u0[i] == 0.0 ? 1.0 : u0[i]);
-
-    double* z = Z + size_t(j) * k;
-    for (int64_t i = 0; i < k; ++i) z[i] = hash_unit(uint64_t(i) * 1315423911ull + uint64_t(j) * 2654435761ull + 7);
+      z[i] = hash_unit(uint64_t(i) * 1315423911ull + uint64_t(j) * 2654435761ull + 7);
+    }
+    __syncthreads();
     for (int it = 0; it < 5; ++it) {
       // orthogonalize against earlier members of the cluster (modified Gram-Schmidt)
       for (int p = j0; p < j; ++p) {
         const double* zp = Z + size_t(p) * k;
         double dot = 0.0;
-        for (int64_t i = 0; i < k; ++i) dot += zp[i] * z[i];
-        for (int64_t i = 0; i < k; ++i) z[i] -= dot * zp[i];
+        for (int64_t i = lane; i < k; i += 64) dot += zp[i] * z[i];
+        dot = wave_sum(dot);
+        for (int64_t i = lane; i < k; i += 64) z[i] -= dot * zp[i];
+        __syncthreads();
       }
-      // forward: apply the row swaps and multipliers
-      for (int64_t i = 0; i + 1 < k; ++i) {
-        if (sw[i]) {
-          const double t = z[i];
-          z[i] = z[i + 1];
-          z[i + 1] = t;
+      if (lane == 0) {
+        double zc = z[0];
+        for (int64_t i = 0; i + 1 < k; ++i) {  // row swaps and multipliers
+          double zn = z[i + 1];
+          if (sw[i]) {
+            const double t = zc;
+            zc = zn;
+            zn = t;
+          }
+          z[i] = zc;
+          zc = zn - mu[i] * zc;
         }
-        z[i + 1] -= mu[i] * z[i];
+        z[k - 1] = zc;
+        // back substitution, two super-diagonals
+        double x2 = 0.0, x1 = z[k - 1] / u0[k - 1];
+        z[k - 1] = x1;
+        for (int64_t i = k - 2; i >= 0; --i) {
+          const double xi = (z[i] - u1[i] * x1 - u2[i] * x2) / u0[i];
+          z[i] = xi;
+          x2 = x1;
+          x1 = xi;
+        }
       }
-      // backward: upper triangular with two super-diagonals
-      z[k - 1] = z[k - 1] / u0[k - 1];
-      if (k > 1) z[k - 2] = (z[k - 2] - u1[k - 2] * z[k - 1]) / u0[k - 2];
-      for (int64_t i = k - 3; i >= 0; --i) z[i] = (z[i] - u1[i] * z[i + 1] - u2[i] * z[i + 2]) / u0[i];
-      // normalize (scale first to avoid overflow)
+      __syncthreads();
       double amax = 0.0;
-      for (int64_t i = 0; i < k; ++i) amax = fmax(amax, fabs(z[i]));
+      for (int64_t i = lane; i < k; i += 64) amax = fmax(amax, fabs(z[i]));
+      amax = wave_max(amax);
       if (!(amax > 0.0) || !isfinite(amax)) amax = 1.0;
       double nrm = 0.0;
-      for (int64_t i = 0; i < k; ++i) {
-        z[i] /= amax;
-        nrm += z[i] * z[i];
+      for (int64_t i = lane; i < k; i += 64) {
+        const double v = z[i] / amax;
+        z[i] = v;
+        nrm += v * v;
       }
-      nrm = sqrt(nrm);
-      for (int64_t i = 0; i < k; ++i) z[i] /= nrm;
+      nrm = sqrt(wave_sum(nrm));
+      for (int64_t i = lane; i < k; i += 64) z[i] /= nrm;
+      __syncthreads();
     }
     for (int p = j0; p < j; ++p) {  // final orthogonalization in the cluster
       const double* zp = Z + size_t(p) * k;
       double dot = 0.0;
-      for (int64_t i = 0; i < k; ++i) dot += zp[i] * z[i];
-      for (int64_t i = 0; i < k; ++i) z[i] -= dot * zp[i];
+      for (int64_t i = lane; i < k; i += 64) dot += zp[i] * z[i];
+      dot = wave_sum(dot);
       double nrm = 0.0;
-      for (int64_t i = 0; i < k; ++i) nrm += z[i] * z[i];
-      nrm = sqrt(nrm);
-      for (int64_t i = 0; i < k; ++i) z[i] /= nrm;
+      for (int64_t i = lane; i < k; i += 64) {
+        const double v = z[i] - dot * zp[i];
+        z[i] = v;
+        nrm += v * v;
+      }
+      nrm = sqrt(wave_sum(nrm));
+      for (int64_t i = lane; i < k; i += 64) z[i] /= nrm;
+      __syncthreads();
     }
+    double* zo = Z + size_t(j) * k;
+    for (int64_t i = lane; i < k; i += 64) zo[i] = z[i];
+    __syncthreads();
   }
 }
 
@@ -615,7 +696,7 @@ struct EigWs {
   double* Z;
   double* scratch;
   unsigned char* swaps;
-  unsigned* words;  // [0] barrier, [1] abort, [2] r_out
+  unsigned* words;  // [0] barrier, [1] abort, [2] r_out, [3] published reflectors
 };
 
 EigWs carve_eig(void* ws, size_t bytes, int64_t k, int r_max, int P, Carver& c) {
@@ -626,11 +707,11 @@ EigWs carve_eig(void* ws, size_t bytes, int64_t k, int r_max, int P, Carver& c) 
   w.e = c.take<double>(size_t(k));
   w.e2 = c.take<double>(size_t(k));
   w.tau = c.take<double>(size_t(k));
-  w.p = c.take<double>(size_t(k));
-  w.part = c.take<double>(size_t(P > 0 ? P : 1024));
+  w.p = c.take<double>(size_t(2 * k));
+  w.part = c.take<double>(size_t(2 * (P > 0 ? P : 1024)));
   w.bounds = c.take<double>(8);
   w.Z = c.take<double>(size_t(r_max) * k);
-  w.scratch = c.take<double>(size_t(r_max) * 4 * k);
+  w.scratch = c.take<double>(size_t(r_max) * 5 * k);
   w.swaps = c.take<unsigned char>(size_t(r_max) * k);
   w.words = c.take<unsigned>(8);
   (void)ws;
@@ -684,6 +765,7 @@ extern "C" int dopinf_reduce(void* stream, const double* D, int64_t k, int64_t l
   ta.p = w.p;
   ta.part = w.part;
   ta.bar = w.words;
+  ta.vflag = w.words + 3;
   ta.abort_flag = reinterpret_cast<int*>(w.words + 1);
   void* args[] = {&ta};
   DOPINF_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(sytrd_kernel), dim3(pl.P), dim3(TNT), args,
@@ -707,9 +789,21 @@ extern "C" int dopinf_reduce(void* stream, const double* D, int64_t k, int64_t l
     r = r_h;
   }
   if (r_out_h) *r_out_h = r;
-  tri_invit_kernel<<<unsigned((r + 63) / 64), 64, 0, st>>>(w.d, w.e, k, r, lambda, w.bounds, w.Z, w.scratch,
-                                                          w.swaps);
-  DOPINF_LAUNCHED();
+  {
+    int maxlds = 0, devi = 0;
+    DOPINF_HIP(hipGetDevice(&devi));
+    DOPINF_HIP(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, devi));
+    const size_t lb = size_t(k) * (5 * sizeof(double) + 1) + 64;
+    if (lb <= size_t(maxlds)) {
+      if (lb > 65536)
+        DOPINF_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(tri_invit_kernel<true>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(lb)));
+      tri_invit_kernel<true><<<unsigned(r), 64, lb, st>>>(w.d, w.e, k, r, lambda, w.bounds, w.Z, w.scratch, w.swaps);
+    } else {
+      tri_invit_kernel<false><<<unsigned(r), 64, 0, st>>>(w.d, w.e, k, r, lambda, w.bounds, w.Z, w.scratch, w.swaps);
+    }
+    DOPINF_LAUNCHED();
+  }
   const size_t zl = size_t(k) * sizeof(double);
   if (zl > 65536)
     DOPINF_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(backtransform_kernel),

@@ -23,11 +23,15 @@
 //    kernel sums the partials in fixed split order (deterministic, no float
 //    atomics) and writes both triangles.
 #include "common.hpp"
+#include "gram_plan.hpp"
 
 namespace dopinf {
 int check_var_rows(int64_t n, int nvars, const int64_t* var_rows_h);
 
 namespace {
+
+using gramplan::SplitPlan;
+using gramplan::choose_splits;
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
@@ -36,14 +40,6 @@ constexpr int NTH = 256;    // threads per workgroup
 constexpr int KC = 16;      // rows per LDS stage (FP64)
 constexpr int PAD = 2;      // LDS row padding (doubles)
 constexpr int LDR = BT + PAD;
-
-struct SplitPlan {
-  int nvars;
-  int nsplit;
-  int xcd_map;
-  int64_t row0[DOPINF_MAX_VARS + 1];
-  int split0[DOPINF_MAX_VARS + 1];
-};
 
 struct GramArgs {
   const double* X;
@@ -61,29 +57,11 @@ struct GramArgs {
 
 __device__ __forceinline__ void tile_coords(const GramArgs& g, int t, int& I, int& J) {
   if (g.triangle) {
-    // t = I(I+1)/2 + J, 0 <= J <= I
-    int i = int((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-    while ((i + 1) * (i + 2) / 2 <= t) ++i;
-    while (i * (i + 1) / 2 > t) --i;
-    I = i;
-    J = t - i * (i + 1) / 2;
+    gramplan::tri_coords(t, I, J);
   } else {
     I = t / g.tiles_y;
     J = t % g.tiles_y;
   }
-}
-
-__device__ __forceinline__ void split_range(const SplitPlan& sp, int s, int64_t& lo, int64_t& hi, int& v) {
-  int vv = 0;
-  while (vv + 1 < sp.nvars && s >= sp.split0[vv + 1]) ++vv;
-  const int nv = sp.split0[vv + 1] - sp.split0[vv];
-  const int64_t rows = sp.row0[vv + 1] - sp.row0[vv];
-  int64_t chunk = (rows + nv - 1) / nv;
-  chunk = (chunk + KC - 1) / KC * KC;
-  lo = sp.row0[vv] + int64_t(s - sp.split0[vv]) * chunk;
-  hi = min(sp.row0[vv + 1], lo + chunk);
-  if (lo > hi) lo = hi;
-  v = vv;
 }
 
 // Load 8 consecutive doubles of one panel row into registers, transformed.
@@ -135,7 +113,7 @@ __global__ __launch_bounds__(NTH, 2) void gram_f64_mfma_kernel(GramArgs g, Split
   tile_coords(g, t, I, J);
   int64_t lo, hi;
   int v;
-  split_range(sp, s, lo, hi, v);
+  gramplan::split_range(sp, s, KC, lo, hi, v);
   const bool diag = g.triangle && (I == J);
   const int64_t a0 = int64_t(I) * BT, b0 = int64_t(J) * BT;
   const bool xf = (g.mean != nullptr) || (g.scale != nullptr);
@@ -227,11 +205,7 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(const double* __restri
   const int cc = threadIdx.x & 127;
   int I, J;
   if (triangle) {
-    int i = int((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-    while ((i + 1) * (i + 2) / 2 <= t) ++i;
-    while (i * (i + 1) / 2 > t) --i;
-    I = i;
-    J = t - i * (i + 1) / 2;
+    gramplan::tri_coords(t, I, J);
   } else {
     I = t / tiles_y;
     J = t % tiles_y;
@@ -245,37 +219,6 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(const double* __restri
   for (int s = 0; s < nsplit; ++s) sum += p[s * stride];
   C[a * ldc + b] = sum;
   if (triangle) C[b * ldc + a] = sum;
-}
-
-int choose_splits(int64_t n, int ntiles) {
-  int target = (8192 + ntiles - 1) / ntiles;
-  int64_t max_by_rows = n / 256;
-  if (max_by_rows < 1) max_by_rows = 1;
-  if (target > max_by_rows) target = int(max_by_rows);
-  if (target >= 8) target = target / 8 * 8;
-  if (target < 1) target = 1;
-  return target;
-}
-
-SplitPlan make_plan(int64_t n, int nvars, const int64_t* var_rows_h, int nsplit_target) {
-  SplitPlan sp{};
-  sp.nvars = nvars;
-  int acc = 0;
-  for (int v = 0; v < nvars; ++v) {
-    sp.row0[v] = var_rows_h[v];
-    sp.split0[v] = acc;
-    const int64_t rows = var_rows_h[v + 1] - var_rows_h[v];
-    int nv = int((double(nsplit_target) * double(rows) / double(n)) + 0.5);
-    if (nv < 1) nv = 1;
-    const int64_t max_nv = (rows + KC - 1) / KC;
-    if (nv > max_nv) nv = int(max_nv);
-    acc += nv;
-  }
-  sp.row0[nvars] = var_rows_h[nvars];
-  sp.split0[nvars] = acc;
-  sp.nsplit = acc;
-  sp.xcd_map = (acc % 8 == 0) ? 1 : 0;
-  return sp;
 }
 
 int tiles_of(int64_t m) { return int((m + BT - 1) / BT); }
@@ -295,6 +238,14 @@ int run_gram(hipStream_t st, GramArgs g, const SplitPlan& sp, double* C, int64_t
 
 }  // namespace
 
+int gram_reduce_launch(hipStream_t st, const double* part, int nsplit, int ntiles, int tiles_y, int triangle,
+                       int64_t mx, int64_t my, double* C, int64_t ldc) {
+  dim3 rgrid(unsigned(ntiles), BT / 2);
+  gram_reduce_kernel<<<rgrid, 256, 0, st>>>(part, nsplit, ntiles, tiles_y, triangle, mx, my, C, ldc);
+  DOPINF_LAUNCHED();
+  return DOPINF_OK;
+}
+
 // Symmetric Gram of an n x m float64 matrix (used by Step IV's data Gram as
 // well): D = Xs^T Xs with the optional per-row / per-variable transform.
 int gram_f64_internal(hipStream_t st, const double* X, int64_t n, int64_t m, int64_t ldx, const double* mean,
@@ -307,7 +258,7 @@ int gram_f64_internal(hipStream_t st, const double* X, int64_t n, int64_t m, int
     nvars = 1;
     var_rows_h = one_var;
   }
-  SplitPlan sp = make_plan(n, nvars, var_rows_h, choose_splits(n, ntiles));
+  SplitPlan sp = gramplan::make_plan(n, nvars, var_rows_h, choose_splits(n, ntiles), KC);
   if (ws_bytes < part_bytes(sp.nsplit, ntiles) || !ws)
     return fail(DOPINF_E_WORKSPACE, "gram workspace of %zu bytes needed, %zu given", part_bytes(sp.nsplit, ntiles),
                 ws_bytes);
@@ -389,7 +340,7 @@ int cross_gram_internal(hipStream_t st, const double* X, int64_t ldx, const doub
   const int ty = tiles_of(my);
   const int ntiles = tiles_of(mx) * ty;
   int64_t one_var[2] = {0, n};
-  SplitPlan sp = make_plan(n, 1, one_var, choose_splits(n, ntiles));
+  SplitPlan sp = gramplan::make_plan(n, 1, one_var, choose_splits(n, ntiles), KC);
   if (!ws || ws_bytes < part_bytes(sp.nsplit, ntiles))
     return fail(DOPINF_E_WORKSPACE, "cross gram workspace of %zu bytes needed, %zu given",
                 part_bytes(sp.nsplit, ntiles), ws_bytes);

@@ -137,52 +137,49 @@ __global__ __launch_bounds__(256) void gather_qq_kernel(const double* __restrict
 // ---------------------------------------------------------------------------
 // blocked Cholesky (lower, row-major, ld n), batched over blockIdx.z / .y
 // ---------------------------------------------------------------------------
-// Diagonal block at jb: factor in LDS, write L_jj and its inverse.
-__global__ __launch_bounds__(256) void potf2_kernel(double* __restrict__ A, int64_t n, int64_t jb,
-                                                    double* __restrict__ Linv, int* __restrict__ fail_flag) {
+// Diagonal block at jb: factor in LDS with one wave (no workgroup barriers
+// beyond the wave), write L_jj and the inverse of its triangle.
+__global__ __launch_bounds__(64) void potf2_kernel(double* __restrict__ A, int64_t n, int64_t jb,
+                                                   double* __restrict__ Linv, int* __restrict__ fail_flag) {
   __shared__ double T[NB][NB + 1];
   __shared__ double Ti[NB][NB + 1];
-  __shared__ int bad;
   const int u = blockIdx.x;
+  const int lane = threadIdx.x;
   double* Au = A + size_t(u) * n * n;
   const int nb = int(min<int64_t>(NB, n - jb));
-  for (int e = threadIdx.x; e < NB * NB; e += 256) {
-    const int i = e / NB, j = e % NB;
+  for (int j = 0; j < NB; ++j) {  // lane = row
+    const int i = lane;
     double v = 0.0;
     if (i < nb && j <= i) v = Au[(jb + i) * n + jb + j];
     else if (i == j) v = 1.0;  // identity padding beyond the matrix
     T[i][j] = v;
   }
-  if (threadIdx.x == 0) bad = 0;
+  int bad = 0;
   __syncthreads();
   for (int c = 0; c < NB; ++c) {
-    if (threadIdx.x == 0) {
-      double piv = T[c][c];
-      if (!(piv > 0.0) || !isfinite(piv)) {
-        bad = 1;
-        piv = 1.0;
-      }
-      T[c][c] = sqrt(piv);
+    double piv = T[c][c];
+    if (!(piv > 0.0) || !isfinite(piv)) {
+      bad = 1;
+      piv = 1.0;
+    }
+    const double dc = sqrt(piv);
+    const int i = lane;
+    double lic = 0.0;
+    if (i > c) {
+      lic = T[i][c] / dc;
+      T[i][c] = lic;
     }
     __syncthreads();
-    const double dc = T[c][c];
-    for (int i = c + 1 + threadIdx.x; i < NB; i += 256) T[i][c] /= dc;
-    __syncthreads();
-    const int rem = NB - c - 1;
-    for (int e = threadIdx.x; e < rem * rem; e += 256) {
-      const int i = c + 1 + e / rem, l = c + 1 + e % rem;
-      if (l <= i) T[i][l] -= T[i][c] * T[l][c];
-    }
+    if (i == c) T[c][c] = dc;
+    if (i > c)
+      for (int l = c + 1; l <= i; ++l) T[i][l] -= lic * T[l][c];
     __syncthreads();
   }
-  // inverse of the lower triangle: column c by forward substitution
-  if (threadIdx.x < NB) {
-    const int c = threadIdx.x;
+  {  // inverse of the lower triangle: lane c computes column c
+    const int c = lane;
     for (int i = 0; i < NB; ++i) {
-      double v;
-      if (i < c) {
-        v = 0.0;
-      } else {
+      double v = 0.0;
+      if (i >= c) {
         double s = (i == c) ? 1.0 : 0.0;
         for (int p = c; p < i; ++p) s -= T[i][p] * Ti[p][c];
         v = s / T[i][i];
@@ -191,12 +188,13 @@ __global__ __launch_bounds__(256) void potf2_kernel(double* __restrict__ A, int6
     }
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < NB * NB; e += 256) {
-    const int i = e / NB, j = e % NB;
+  double* Lo = Linv + (size_t(u) * ((n + NB - 1) / NB) + jb / NB) * NB * NB;
+  for (int j = 0; j < NB; ++j) {
+    const int i = lane;
     if (i < nb && j <= i) Au[(jb + i) * n + jb + j] = T[i][j];
-    Linv[(size_t(u) * ((n + NB - 1) / NB) + jb / NB) * NB * NB + e] = Ti[i][j];
+    Lo[i * NB + j] = Ti[i][j];
   }
-  if (threadIdx.x == 0 && bad) fail_flag[u] = 1;
+  if (lane == 0 && bad) fail_flag[u] = 1;
 }
 
 // Rows below the diagonal block: A[i, jb:jb+nb] <- A[i, jb:jb+nb] L_jj^{-T}
@@ -277,72 +275,112 @@ __global__ __launch_bounds__(256) void syrk_update_kernel(double* __restrict__ A
 
 // ---------------------------------------------------------------------------
 // triangular solves with the factored L (row-major lower, ld n) and its
-// diagonal-block inverses.  X is n x w (ld w), one workgroup per (item, 32
-// columns); forward: L X = B, backward: L^T X = B.
+// diagonal-block inverses, right-looking: one launch per 64-row block J.
+// Forward (L X = B):   Y_J = Linv_JJ X_J, then X_T -= L_TJ Y_J for T > J.
+// Backward (L^T X = B): Y_J = Linv_JJ^T X_J, then X_T -= L_JT^T Y_J, T < J.
+// X (n x w, ld w) holds the right-hand sides and is consumed; Y_J goes to Yout.
+// Workgroup = (row tile T or the diagonal block, 32 columns, item).
 // ---------------------------------------------------------------------------
 template <bool TRANS>
-__global__ __launch_bounds__(256) void trsm_kernel(const double* __restrict__ L, int64_t n,
-                                                   const double* __restrict__ Linv, double* __restrict__ X,
-                                                   int64_t w) {
+__global__ __launch_bounds__(256) void trsm_step_kernel(const double* __restrict__ L, int64_t n,
+                                                        const double* __restrict__ Linv, double* __restrict__ X,
+                                                        double* __restrict__ Yout, int64_t w, int64_t J) {
   __shared__ double Li[NB][NB + 1];
-  __shared__ double Y[NB][33];
-  const int u = blockIdx.y;
+  __shared__ double Yb[NB][33];
+  __shared__ double Lt[NB][NB + 1];
+  const int u = blockIdx.z;
   const double* Lu = L + size_t(u) * n * n;
   const int64_t nblk = (n + NB - 1) / NB;
-  const double* Liu = Linv + size_t(u) * nblk * NB * NB;
+  const double* Liu = Linv + (size_t(u) * nblk + J) * NB * NB;
   double* Xu = X + size_t(u) * n * w;
-  const int64_t c0 = int64_t(blockIdx.x) * 32;
-  const int il = threadIdx.x >> 2;       // row within block (0..63)
-  const int cs = (threadIdx.x & 3) * 8;  // 8 columns
-  for (int64_t bi = 0; bi < nblk; ++bi) {
-    const int64_t J = TRANS ? (nblk - 1 - bi) : bi;
-    const int64_t jb = J * NB;
+  double* Yu = Yout + size_t(u) * n * w;
+  const int64_t c0 = int64_t(blockIdx.y) * 32;
+  const int il = threadIdx.x >> 2;       // row within a 64-row block
+  const int cs = (threadIdx.x & 3) * 8;  // 8 of the 32 columns
+  const int64_t jb = J * NB;
+  // target tile: blockIdx.x == 0 is the diagonal block, else the T-th other block
+  int64_t T;
+  if (!TRANS) T = J + int64_t(blockIdx.x);
+  else T = int64_t(blockIdx.x) == 0 ? J : int64_t(blockIdx.x) - 1;
+  for (int e = threadIdx.x; e < NB * NB; e += 256) Li[e / NB][e % NB] = Liu[e];
+  {
     const int64_t i = jb + il;
-    double acc[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) acc[q] = 0.0;
-    if (i < n) {
-      if (!TRANS) {
-        for (int64_t p = 0; p < jb; ++p) {
-          const double l = Lu[i * n + p];
-          const double* xp = Xu + p * w + c0 + cs;
-#pragma unroll
-          for (int q = 0; q < 8; ++q)
-            if (c0 + cs + q < w) acc[q] += l * xp[q];
-        }
-      } else {
-        for (int64_t p = jb + NB; p < n; ++p) {
-          const double l = Lu[p * n + i];
-          const double* xp = Xu + p * w + c0 + cs;
-#pragma unroll
-          for (int q = 0; q < 8; ++q)
-            if (c0 + cs + q < w) acc[q] += l * xp[q];
-        }
-      }
-    }
-    for (int e = threadIdx.x; e < NB * NB; e += 256) Li[e / NB][e % NB] = Liu[J * NB * NB + e];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int64_t c = c0 + cs + q;
-      Y[il][cs + q] = (i < n && c < w) ? Xu[i * w + c] - acc[q] : 0.0;
+      Yb[il][cs + q] = (i < n && c < w) ? Xu[i * w + c] : 0.0;
     }
-    __syncthreads();
+  }
+  if (blockIdx.x != 0) {  // the L block that couples T and J
+    const int64_t tb = T * NB;
+    for (int e = threadIdx.x; e < NB * NB; e += 256) {
+      const int a = e / NB, b = e % NB;
+      double v = 0.0;
+      if (!TRANS) {
+        if (tb + a < n && jb + b < n) v = Lu[(tb + a) * n + jb + b];   // L_TJ[a][b]
+      } else {
+        if (jb + a < n && tb + b < n) v = Lu[(jb + a) * n + tb + b];   // L_JT[a][b]
+      }
+      Lt[a][b] = v;
+    }
+  }
+  __syncthreads();
+  // Y_J = Linv X_J (forward) or Linv^T X_J (backward), 8 outputs per thread
+  double y[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) y[q] = 0.0;
+  for (int p = 0; p < NB; ++p) {
+    const double l = TRANS ? Li[p][il] : Li[il][p];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) y[q] += l * Yb[p][cs + q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 8; ++q) Yb[il][cs + q] = y[q];
+  __syncthreads();
+  if (blockIdx.x == 0) {
+    const int64_t i = jb + il;
     if (i < n) {
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const int64_t c = c0 + cs + q;
-        if (c >= w) continue;
-        double s = 0.0;
-        if (!TRANS) {
-          for (int p = 0; p <= il; ++p) s += Li[il][p] * Y[p][cs + q];
-        } else {
-          for (int p = il; p < NB; ++p) s += Li[p][il] * Y[p][cs + q];
-        }
-        Xu[i * w + c] = s;
+        if (c < w) Yu[i * w + c] = Yb[il][cs + q];
       }
     }
-    __syncthreads();
+    return;
   }
+  // X_T -= L_TJ Y_J  (forward)  or  X_T -= L_JT^T Y_J  (backward)
+  const int64_t i = T * NB + il;
+  if (i >= n) return;
+  double acc[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+  for (int p = 0; p < NB; ++p) {
+    const double l = TRANS ? Lt[p][il] : Lt[il][p];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] += l * Yb[p][cs + q];
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int64_t c = c0 + cs + q;
+    if (c < w) Xu[i * w + c] -= acc[q];
+  }
+}
+
+int trsm_run(hipStream_t st, bool trans, const double* L, int64_t n, const double* Linv, double* X, double* Yout,
+             int64_t w, int nu) {
+  const int64_t nblk = (n + NB - 1) / NB;
+  const unsigned cch = unsigned((w + 31) / 32);
+  for (int64_t b = 0; b < nblk; ++b) {
+    const int64_t J = trans ? (nblk - 1 - b) : b;
+    const unsigned ntile = unsigned(trans ? (J + 1) : (nblk - J));  // diagonal + coupled tiles
+    if (!trans)
+      trsm_step_kernel<false><<<dim3(ntile, cch, unsigned(nu)), 256, 0, st>>>(L, n, Linv, X, Yout, w, J);
+    else
+      trsm_step_kernel<true><<<dim3(ntile, cch, unsigned(nu)), 256, 0, st>>>(L, n, Linv, X, Yout, w, J);
+    DOPINF_LAUNCHED();
+  }
+  return DOPINF_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -432,14 +470,22 @@ __global__ __launch_bounds__(256) void pair_solve_kernel(PairArgs a) {
     const int64_t col = (c < r) ? c : (r + s);
     Op[i * d + col] = X[c * r + i];
   }
-  // quadratic columns: X_q = Z - P X_l
+  // quadratic columns: X_q = Z - P X_l, rows of [P | Z] staged through LDS in
+  // tiles that reuse the Schur factor's space (no longer needed)
   const double* R2u = a.R2 + size_t(u) * s * w;
-  for (int64_t q = threadIdx.x; q < s; q += 256) {
-    const double* prow = R2u + q * w;
-    for (int i = 0; i < r; ++i) {
+  const int tile = (r1 * r1) / w;  // >= 1 since r1^2 >= 2 r + 1
+  double* Pt = S;
+  for (int64_t q0 = 0; q0 < s; q0 += tile) {
+    const int nq = int(min<int64_t>(tile, s - q0));
+    __syncthreads();
+    for (int e = threadIdx.x; e < nq * w; e += 256) Pt[e] = R2u[q0 * w + e];
+    __syncthreads();
+    for (int e = threadIdx.x; e < nq * r; e += 256) {
+      const int i = e / nq, qq = e % nq;  // consecutive threads -> consecutive q
+      const double* prow = Pt + qq * w;
       double v = prow[r1 + i];
       for (int c = 0; c < r1; ++c) v -= prow[c] * X[c * r + i];
-      Op[i * d + r + q] = v;
+      Op[int64_t(i) * d + r + q0 + qq] = v;
     }
   }
   if (threadIdx.x == 0) a.status[p] = bad ? DOPINF_E_NOTSPD : DOPINF_OK;
@@ -500,6 +546,7 @@ InferLayout layout(int64_t k, int n_r, const int* r_list, int n_pairs) {
   const int uc = n_pairs < UCHUNK ? n_pairs : UCHUNK;
   L.chunk_off = (c.used + 255) & ~size_t(255);
   c.take<char>(uc * L.l_bytes);
+  c.take<char>(uc * L.r_bytes);
   c.take<char>(uc * L.r_bytes);
   c.take<char>(uc * L.r_bytes);
   c.take<char>(uc * L.linv_bytes);
@@ -614,9 +661,10 @@ extern "C" int dopinf_infer(void* stream, const double* Qhat, int64_t ldqh, int6
     double* Lq = reinterpret_cast<double*>(ch);
     double* R = reinterpret_cast<double*>(ch + uc * lb);
     double* R2 = reinterpret_cast<double*>(ch + uc * (lb + rb));
-    double* Linv = reinterpret_cast<double*>(ch + uc * (lb + 2 * rb));
-    double* CV = reinterpret_cast<double*>(ch + uc * (lb + 2 * rb + lib));
-    char* cgws = ch + uc * (lb + 2 * rb + lib + cvb);
+    double* Rt = reinterpret_cast<double*>(ch + uc * (lb + 2 * rb));
+    double* Linv = reinterpret_cast<double*>(ch + uc * (lb + 3 * rb));
+    double* CV = reinterpret_cast<double*>(ch + uc * (lb + 3 * rb + lib));
+    char* cgws = ch + uc * (lb + 3 * rb + lib + cvb);
     const size_t cgb = cross_gram_workspace_internal(s, r1, w);
     const size_t op_base = dopinf_operator_offset(n_r, r_list_h, n_pairs, g * n_pairs);
 
@@ -635,7 +683,7 @@ extern "C" int dopinf_infer(void* stream, const double* Qhat, int64_t ldqh, int6
         DOPINF_LAUNCHED();
       }
       for (int64_t jb = 0; jb < s; jb += NB) {
-        potf2_kernel<<<nu, 256, 0, st>>>(Lq, s, jb, Linv, ufail);
+        potf2_kernel<<<nu, 64, 0, st>>>(Lq, s, jb, Linv, ufail);
         DOPINF_LAUNCHED();
         const int64_t rest = s - jb - NB;
         if (rest > 0) {
@@ -646,13 +694,14 @@ extern "C" int dopinf_infer(void* stream, const double* Qhat, int64_t ldqh, int6
           DOPINF_LAUNCHED();
         }
       }
-      const unsigned cchunks = unsigned((w + 31) / 32);
-      trsm_kernel<false><<<dim3(cchunks, unsigned(nu)), 256, 0, st>>>(Lq, s, Linv, R, w);
+      // [W | y] = L^{-1} [G_ql | B_q] into R2 (R consumed), then
+      // [P | Z] = L^{-T} [W | y]: copy to R, solve into R2 ... so keep [W | y]:
+      int rc2 = trsm_run(st, false, Lq, s, Linv, R, R2, w, nu);  // R2 = [W | y]
+      if (rc2) return rc2;
+      copy_kernel<<<1024, 256, 0, st>>>(R2, R, int64_t(nu) * s * w);  // R = [W | y]
       DOPINF_LAUNCHED();
-      copy_kernel<<<1024, 256, 0, st>>>(R, R2, int64_t(nu) * s * w);
-      DOPINF_LAUNCHED();
-      trsm_kernel<true><<<dim3(cchunks, unsigned(nu)), 256, 0, st>>>(Lq, s, Linv, R2, w);
-      DOPINF_LAUNCHED();
+      rc2 = trsm_run(st, true, Lq, s, Linv, R2, Rt, w, nu);  // Rt = [P | Z] (R2 consumed)
+      if (rc2) return rc2;
       for (int u = 0; u < nu; ++u) {
         int rc = cross_gram_internal(st, R + size_t(u) * s * w, w, R + size_t(u) * s * w, w, s, r1, w,
                                      CV + size_t(u) * r1 * w, w, cgws, cgb);
@@ -662,7 +711,7 @@ extern "C" int dopinf_infer(void* stream, const double* Qhat, int64_t ldqh, int6
       pa.GE = GE;
       pa.geo = geo;
       pa.CV = CV;
-      pa.R2 = R2;
+      pa.R2 = Rt;
       pa.ufail = ufail;
       pa.pair_u = pair_u;
       pa.beta1 = b1dev;

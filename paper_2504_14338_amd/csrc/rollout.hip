@@ -15,8 +15,9 @@
 namespace dopinf {
 namespace {
 
-constexpr int RT = 256;   // threads per rollout workgroup
-constexpr int RPW = 4;    // operator rows reduced together by one wave
+constexpr int RT = 1024;  // threads per rollout workgroup (16 waves)
+constexpr int RPW = 2;    // operator rows reduced together by one wave
+constexpr int CU8 = 8;    // independent operator loads per lane per row in flight
 
 __host__ __device__ inline int64_t nquad(int64_t r) { return r * (r + 1) / 2; }
 __host__ __device__ inline int64_t ncols(int64_t r) { return r + nquad(r) + 1; }
@@ -178,11 +179,27 @@ __global__ __launch_bounds__(RT) void rollout_kernel(RollArgs a) {
     if (tid == 0) f[d - 1] = 1.0;
     __syncthreads();
     // ---- next state: q_{t+1}[i] = O[i, :] . f ----
+    // each wave owns rows w*RPW + 16*RPW*m; per lane CU8 x RPW loads are issued
+    // before their FMAs so that enough L2 traffic is in flight per CU
     for (int i0 = w * RPW; i0 < r; i0 += (RT / 64) * RPW) {
       double acc[RPW];
 #pragma unroll
       for (int u = 0; u < RPW; ++u) acc[u] = 0.0;
-      for (int64_t c = lane; c < d; c += 64) {
+      int64_t c = lane;
+      for (; c + 64 * (CU8 - 1) < d; c += 64 * CU8) {
+        double ov[RPW][CU8];
+#pragma unroll
+        for (int u = 0; u < RPW; ++u)
+#pragma unroll
+          for (int q = 0; q < CU8; ++q) ov[u][q] = (i0 + u < r) ? Op[int64_t(i0 + u) * d + c + 64 * q] : 0.0;
+#pragma unroll
+        for (int q = 0; q < CU8; ++q) {
+          const double fc = f[c + 64 * q];
+#pragma unroll
+          for (int u = 0; u < RPW; ++u) acc[u] += ov[u][q] * fc;
+        }
+      }
+      for (; c < d; c += 64) {
         const double fc = f[c];
 #pragma unroll
         for (int u = 0; u < RPW; ++u)

@@ -35,6 +35,8 @@ __all__ = [
     "c2_snapshots",
     "quad_trajectory",
     "logspace_points",
+    "mlp_init",
+    "perturbed_states",
 ]
 
 
@@ -231,3 +233,21 @@ def logspace_points(lo_exp: float, hi_exp: float, num: int) -> np.ndarray:
     if num == 1:
         return np.array([10.0 ** lo_exp])
     return np.array([10.0 ** (lo_exp + (hi_exp - lo_exp) * i / (num - 1)) for i in range(num)])
+
+
+def mlp_init(r: int, hidden: int = 128, seed: int = 5) -> np.ndarray:
+    """Initial closure parameters (float32, packed [W1|b1|W2|b2|W3|b3]):
+    weights U(-1/sqrt(fan_in), 1/sqrt(fan_in)), biases zero."""
+    rng = np.random.default_rng([seed, 11])
+    parts = []
+    for fan_out, fan_in in ((hidden, r), (hidden, hidden), (r, hidden)):
+        b = 1.0 / math.sqrt(fan_in)
+        parts.append(rng.uniform(-b, b, size=fan_out * fan_in))
+        parts.append(np.zeros(fan_out))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def perturbed_states(q0: np.ndarray, M: int, std: float = 0.05, seed: int = 5) -> np.ndarray:
+    """M copies of q0 plus N(0, std^2) noise (M x r)."""
+    rng = np.random.default_rng([seed, 13])
+    return q0[None, :] + std * rng.standard_normal((M, q0.shape[0]))

@@ -1,0 +1,51 @@
+"""The C-ABI library loads without a GPU and exports every symbol that
+include/dopinf.h declares (no compute call is made here)."""
+import ctypes
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    txt = open(os.path.join(ROOT, "include", "dopinf.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(dopinf_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_header_symbols_are_exported():
+    import paper_2504_14338_amd as dp
+    lib = ctypes.CDLL(dp.lib_path())
+    names = declared_functions()
+    assert len(names) >= 20
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    # every declared call has a ctypes signature in the binding
+    assert set(names) <= set(dp._SIGS), set(names) - set(dp._SIGS)
+
+
+def test_host_only_queries():
+    import paper_2504_14338_amd as dp
+    lib = dp.load()
+    assert lib.dopinf_version().decode().startswith("dopinf")
+    r = (ctypes.c_int * 2)(2, 3)
+    # operator layout: group-major, r*d per item
+    assert lib.dopinf_operator_offset(2, r, 2, 1) == 2 * 6
+    assert lib.dopinf_operator_offset(2, r, 2, 2) == 2 * (2 * 6)
+    assert lib.dopinf_operator_offset(2, r, 2, 3) == 2 * (2 * 6) + 3 * 10
+    assert lib.dopinf_closure_param_count(40) == 128 * 40 + 128 + 128 * 128 + 128 + 40 * 128 + 40
+    assert lib.dopinf_closure_param_count(65) == 0
+    assert lib.dopinf_gram_workspace(0, 0, 1000, 100) > 0
+
+
+def test_argument_errors_enqueue_nothing():
+    import paper_2504_14338_amd as dp
+    lib = dp.load()
+    # invalid sizes are rejected before any device work
+    rc = lib.dopinf_gram(None, 0, 0, ctypes.c_void_p(8), 0, 10, 10, None, None, 1, None, ctypes.c_void_p(8), 10,
+                         None, 0)
+    assert rc == dp.E_ARG
+    assert "n >= 1" in lib.dopinf_last_error().decode()
+    rc = lib.dopinf_reduce(None, ctypes.c_void_p(8), 10, 10, 20, 0.9, 5, None, ctypes.c_void_p(8), None, 0,
+                           ctypes.c_void_p(8), 10, ctypes.c_void_p(8), None, 0)
+    assert rc == dp.E_ARG

@@ -1,0 +1,136 @@
+"""GPU parity of the learned closure (MLP correction of the ROM) against the
+closure oracle, through the C ABI.
+
+Tolerances: the GPU sums in float32 (oracle: float64) on identical
+bfloat16-rounded operands; a float32 sum of K terms differs by ~u32*sqrt(K)
+relative (~1e-6 for K = 128).  A rare flip of one hidden activation's
+bfloat16 rounding (when the float32 and float64 pre-activations straddle a
+bfloat16 midpoint, probability ~2.5e-5 per activation) changes the result by
+up to 2^-8 of one activation's contribution; the bounds below (1e-4 on
+gradients and outputs) cover a few such flips.
+"""
+import numpy as np
+import pytest
+
+import oracle as orc
+import oracle.closure as cl
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+@pytest.fixture(scope="module")
+def rom10(gpu_lib):
+    dp = gpu_lib
+    Q, var_rows, _, _ = synth.c1_snapshots(seed=1)
+    Qd = dev(Q)
+    mean, scale, _ = dp.preprocess(Qd, var_rows)
+    lam, Tr, Qhat, info, r = dp.reduce(dp.gram(Qd, mean, scale, var_rows), r=10)
+    Qh = Qhat.contiguous()
+    O, status, views = dp.infer(Qh, [10], [1e-6], [1e-4])
+    return Qh, views[0][0].contiguous()
+
+
+def test_residuals_parity(gpu_lib, rom10):
+    dp = gpu_lib
+    Qh, O = rom10
+    R = dp.rom_residuals(O, Qh).cpu().numpy()
+    Rref = cl.residuals(O.cpu().numpy(), 10, Qh.cpu().numpy())
+    scale = np.max(np.abs(Qh.cpu().numpy()))
+    assert np.max(np.abs(R - Rref)) <= 1e-12 * scale * 100
+
+
+def test_norms_grad_and_eval_parity(gpu_lib, rom10):
+    import torch
+    dp = gpu_lib
+    Qh, O = rom10
+    X = Qh[:, :-1].T.contiguous()
+    Y = dp.rom_residuals(O, Qh)
+    Xh, Yh = X.cpu().numpy(), Y.cpu().numpy()
+    norm = dp.closure_norms(X, Y).cpu().numpy()
+    mx, sx, my, sy = cl.standardization(Xh, Yh)
+    # means can be ~1e-11 (OpInf's constant term absorbs the mean residual):
+    # compare them against the spread, the deviations relatively
+    assert np.all(np.abs(norm[:10] - mx) <= 1e-13 * sx)
+    assert np.all(np.abs(norm[20:30] - my) <= 1e-13 * sy)
+    assert np.allclose(norm[10:20], sx, rtol=1e-12) and np.allclose(norm[30:40], sy, rtol=1e-12)
+    p = synth.mlp_init(10, seed=3)
+    pd = torch.from_numpy(p).cuda()
+    nd = torch.from_numpy(norm).cuda()
+    rows = slice(0, 200)
+    g, loss = dp.closure_grad(pd, nd, X[rows].contiguous(), Y[rows].contiguous())
+    xn = (Xh[rows] - mx) / sx
+    yn = (Yh[rows] - my) / sy
+    loss_ref, g_ref = cl.loss_and_grad(p.astype(np.float64), xn, yn, 10)
+    assert float(loss.item()) == pytest.approx(loss_ref, rel=1e-5)
+    assert rel(g.cpu().numpy(), g_ref) <= 1e-4
+    G, gmax = dp.closure_eval(pd, nd, X)
+    G_ref = cl.closure_eval(p.astype(np.float64), (mx, sx, my, sy), Xh, 10)
+    assert rel(G.cpu().numpy(), G_ref) <= 1e-4
+    assert float(gmax.item()) == pytest.approx(np.max(np.linalg.norm(G_ref, axis=1)), rel=1e-4)
+
+
+def test_closure_rollout_plain_and_latched(gpu_lib, rom10):
+    import torch
+    dp = gpu_lib
+    Qh, O = rom10
+    Oh, Qhh = O.cpu().numpy(), Qh.cpu().numpy()
+    q0 = np.ascontiguousarray(Qhh[:, :8].T)   # training states as initial conditions
+    p = torch.from_numpy(synth.mlp_init(10, seed=4)).cuda()
+    norm = torch.from_numpy(np.concatenate([np.zeros(10), np.ones(10), np.zeros(10), np.ones(10)])).cuda()
+    # threshold <= 0: plain ROM, matches the oracle rollout
+    out = dp.closure_rollout(O, p, norm, 0.0, dev(q0), 120, Qh, keep_traj=True)
+    for m in range(8):
+        ref = orc.rollout(Oh, 10, q0[m], 120)
+        assert np.all(np.isfinite(ref))
+        tr = out["traj"][m].cpu().numpy().T
+        assert np.max(np.abs(tr - ref)) <= 1e-10 * np.max(np.abs(ref))
+    assert np.all(out["fallback_at"].cpu().numpy() == -1)
+    # a tiny threshold latches every rollout at step 0: again the plain ROM
+    out2 = dp.closure_rollout(O, p, norm, 1e-300, dev(q0), 120, Qh, keep_traj=True)
+    assert np.all(out2["fallback_at"].cpu().numpy() == 0)
+    assert torch.equal(out2["traj"], out["traj"])
+    # closure on: first steps match the oracle's closure rollout
+    ph = p.cpu().numpy().astype(np.float64)
+    normh = (np.zeros(10), np.ones(10), np.zeros(10), np.ones(10))
+    out3 = dp.closure_rollout(O, p, norm, 1e9, dev(q0[:2]), 6, Qh, keep_traj=True)
+    for m in range(2):
+        ref, lat = cl.closure_rollout(Oh, 10, ph, normh, 1e9, q0[m], 6)
+        assert lat == -1
+        tr = out3["traj"][m].cpu().numpy().T
+        assert rel(tr, ref) <= 1e-4
+
+
+def test_training_learns_a_smooth_correction(gpu_lib, rom10):
+    # The small configuration is an exact quadratic system, so its ROM
+    # residuals are noise; train on a smooth, learnable target instead.
+    import torch
+    dp = gpu_lib
+    Qh, O = rom10
+    X = Qh[:, :-1].T.contiguous()
+    rng = np.random.default_rng(7)
+    Xh = X.cpu().numpy()
+    Wt = rng.standard_normal((10, 10))
+    Yh = 0.01 * np.tanh(((Xh - Xh.mean(0)) / Xh.std(0)) @ Wt)
+    Y = dev(Yh)
+    p0 = torch.from_numpy(synth.mlp_init(10, seed=5))
+    params, norm, log = dp.closure_fit(X, Y, p0, epochs=80, batch=128, lr=2e-3)
+    log = log.cpu().numpy()
+    assert np.all(np.isfinite(log)) and log[-1] < 0.2 * log[0]
+    # first epoch against the oracle's training (trajectory parity is only
+    # expected over the first few steps)
+    p_ref, _, log_ref = cl.fit(p0.numpy().astype(np.float64), Xh, Yh, 10, epochs=1, batch=128, lr=2e-3)
+    assert log[0] == pytest.approx(log_ref[0], rel=1e-3)
+    G, gmax = dp.closure_eval(params, norm, X)
+    res_plain = float(torch.sqrt(torch.mean(Y * Y)).item())
+    res_closed = float(torch.sqrt(torch.mean((Y - G) ** 2)).item())
+    assert res_closed < 0.5 * res_plain
