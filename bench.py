@@ -165,7 +165,7 @@ def mixed_bench(dp, torch, Q, var_rows, ref_qhat, ref_lam, t_fp64_ms):
     out = {}
     refq = ref_qhat.cpu().numpy()
     refl = ref_lam.cpu().numpy()
-    for name, algo in (("fp32", dp.GRAM_NATIVE), ("bf16x3", dp.GRAM_BF16X3)):
+    for name, algo in (("fp32", dp.GRAM_NATIVE), ("bf16x3", dp.GRAM_BF16X3), ("bf16x6", dp.GRAM_BF16X6)):
         timer = Timer(torch)
         try:
             for _ in range(3):
@@ -194,6 +194,62 @@ def mixed_bench(dp, torch, Q, var_rows, ref_qhat, ref_lam, t_fp64_ms):
     return out
 
 
+def closure_bench(dp, torch, dev, epochs=200):
+    """Learned closure at r = 40 on the wave data (4 x 250,000 cells, k = 2000):
+    residuals of the r = 40 ROM, training, 1024 perturbed 4000-state rollouts
+    with fallback, and the gain on held-out snapshots (t = 2000..3999, projected
+    through Eq. (8) with the training statistics)."""
+    import numpy as np
+    import synth
+    r, k, n_states, M = 40, 2000, 4000, 1024
+    m = synth.c2_modes(nvars=4, ncell=250_000, k=k, seed=2)
+    var_rows = [0, 250_000, 500_000, 750_000, 1_000_000]
+    Q = synth.c2_snapshots(m, noise_var=1e-8, seed=2, device=dev)
+    Qt = synth.c2_snapshots(m, noise_var=1e-8, seed=3, device=dev, t0=k)
+    mean, scale, _ = dp.preprocess(Q, var_rows)
+    D = dp.gram(Q, mean, scale, var_rows)
+    lam, Tr, Qhat, info, _ = dp.reduce(D, r=r)
+    Qh = Qhat.contiguous()
+    O, status, views = dp.infer(Qh, [r], [1e-2], [1e8])
+    Op = views[0][0].contiguous()
+    C = dp.cross_gram(Q, Qt, mean=mean, scale=scale, var_rows=var_rows)
+    Qh_test = dp.cross_gram(Tr.contiguous(), C)                      # r x k_test
+    del Q, Qt, C, D
+    timer = Timer(torch)
+    X = Qh[:, :-1].T.contiguous()
+    Y = timer.run("residuals", lambda: dp.rom_residuals(Op, Qh))
+    p0 = torch.from_numpy(synth.mlp_init(r, seed=5))
+    params, norm, log = timer.run("train", lambda: dp.closure_fit(X, Y, p0, epochs=epochs, batch=256, lr=1e-3))
+    _, gmax = dp.closure_eval(params, norm, X)
+    thr = 3.0 * float(gmax.item())
+    q0 = torch.from_numpy(synth.perturbed_states(Qh[:, 0].cpu().numpy(), M, std=0.05, seed=5)).to(dev)
+    out_c = timer.run("rollout_closure", lambda: dp.closure_rollout(Op, params, norm, thr, q0, n_states, Qh))
+    out_p = timer.run("rollout_plain", lambda: dp.closure_rollout(Op, params, norm, 0.0, q0, n_states, Qh))
+    # held-out one-step residuals and rollout error against the projection
+    Rt = dp.rom_residuals(Op, Qh_test)
+    Gt, _ = dp.closure_eval(params, norm, Qh_test[:, :-1].T.contiguous())
+    rms_plain = float(torch.sqrt(torch.mean(Rt * Rt)).item())
+    rms_closed = float(torch.sqrt(torch.mean((Rt - Gt) ** 2)).item())
+    q0t = Qh_test[:, 0].reshape(1, r).contiguous()
+    e_c = dp.closure_rollout(Op, params, norm, thr, q0t, k, Qh_test)
+    e_p = dp.closure_rollout(Op, params, norm, 0.0, q0t, k, Qh_test)
+    oc_c, oc_p = out_c["outcome"].cpu().numpy(), out_p["outcome"].cpu().numpy()
+    fb = out_c["fallback_at"].cpu().numpy()
+    lg = log.cpu().numpy()
+    return {
+        "r": r, "epochs": epochs, "train_ms": timer.ms("train"), "train_ms_per_epoch": timer.ms("train") / epochs,
+        "loss_first_last": [float(lg[0]), float(lg[-1])],
+        "rollouts": M, "n_states": n_states,
+        "rollout_closure_ms": timer.ms("rollout_closure"), "rollout_plain_ms": timer.ms("rollout_plain"),
+        "threshold": thr,
+        "heldout_residual_rms": {"plain": rms_plain, "closure": rms_closed},
+        "heldout_rollout_err": {"plain": float(e_p["err"].item()), "closure": float(e_c["err"].item())},
+        "stable_fraction": {"plain": float(np.mean(oc_p == 0)), "closure": float(np.mean(oc_c == 0))},
+        "fallback_fraction": float(np.mean(fb >= 0)),
+        "flops_per_step_per_state": {"rom_fp64": 2 * r * (r + r * (r + 1) // 2 + 1), "mlp": 2 * (128 * r * 2 + 128 * 128)},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -201,6 +257,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-extras", action="store_true", help="skip sweep, mixed and CPU legs")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first copy 1 GiB device-to-device (reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the multi-GPU sharding is "
@@ -215,6 +273,13 @@ def main():
         sys.exit(1)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_calibration:
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 1 GiB read + 1 GiB written by one copy kernel")
+        del src, dst
     m, Q, var_rows = make_c2(torch, dev)
     n, k = Q.shape
     torch.cuda.synchronize()
@@ -291,6 +356,12 @@ def main():
             line["cpu_baseline"] = cpu_baseline(Q, var_rows, args.cpu_seconds)
         except Exception as e:
             line["cpu_baseline"] = {"error": repr(e)}
+        del Q, res
+        torch.cuda.empty_cache()
+        try:
+            line["closure"] = closure_bench(dp, torch, dev)
+        except Exception as e:
+            line["closure"] = {"error": repr(e)}
     print(json.dumps(line), flush=True)
 
 

@@ -55,6 +55,7 @@ extern "C" {
 
 #define DOPINF_GRAM_NATIVE 0  /* MFMA in the storage type (F64 or F32)       */
 #define DOPINF_GRAM_BF16X3 1  /* F32 data, split hi+lo bfloat16, 3 products  */
+#define DOPINF_GRAM_BF16X6 2  /* F32 data, split hi+mid+lo bfloat16, 6 products */
 
 #define DOPINF_MAX_VARS 64
 
@@ -89,9 +90,11 @@ int dopinf_preprocess(void* stream, int dtype, void* Q, int64_t n, int64_t k,
  * Qs[i,t] = (Q[i,t] - mean[i]) * (1 / scale[v(i)]) formed on load when mean
  * and scale are given (either may be NULL: no centering / no scaling).
  * D: k x k doubles, leading dimension ldd >= k, written in full (symmetric).
- * algo: DOPINF_GRAM_NATIVE (F64: FP64 MFMA; F32: FP32 MFMA) or
- * DOPINF_GRAM_BF16X3 (F32 data only).  Reduced-precision forms accumulate in
- * float over row slabs of at most 512 rows and sum slabs in double.
+ * algo: DOPINF_GRAM_NATIVE (F64: FP64 MFMA; F32: FP32 MFMA),
+ * DOPINF_GRAM_BF16X3 or DOPINF_GRAM_BF16X6 (F32 data only).  The reduced-
+ * precision forms first pack the transformed data (rounded to float32, split
+ * into bfloat16 parts) into the workspace, then accumulate in float over row
+ * slabs of at most 512 rows and sum slabs in double.
  * Deterministic: no floating-point atomics; repeated calls give identical
  * bits. */
 size_t dopinf_gram_workspace(int dtype, int algo, int64_t n, int64_t k);
@@ -102,13 +105,17 @@ int dopinf_gram(void* stream, int dtype, int algo, const void* Q, int64_t n,
 
 /* Cross Gram C = X^T Y (the same kernel, no triangle symmetry): X is n x mx,
  * Y is n x my (float64, leading dimensions ldx, ldy), C is mx x my (ldc).
- * Used to project snapshots that are not part of D onto the reduced
- * coordinates through Eq. (8) without forming the basis. */
+ * With mean / scale (each may be NULL; var_rows_h as above when scale is
+ * given) both operands are transformed on load with the SAME per-row mean and
+ * per-variable scale, e.g. held-out snapshots centered and scaled with the
+ * training statistics, so that T_r^T (Qs^T Qs_test) projects them onto the
+ * reduced coordinates through Eq. (8) without forming the basis. */
 size_t dopinf_cross_gram_workspace(int64_t n, int64_t mx, int64_t my);
 int dopinf_cross_gram(void* stream, const double* X, int64_t ldx,
                       const double* Y, int64_t ldy, int64_t n, int64_t mx,
-                      int64_t my, double* C, int64_t ldc, void* ws,
-                      size_t ws_bytes);
+                      int64_t my, const double* mean, const double* scale,
+                      int nvars, const int64_t* var_rows_h, double* C,
+                      int64_t ldc, void* ws, size_t ws_bytes);
 
 /* ---- Step III: eigenpairs and basis-free reduced data (Eqs. (6)-(9)) ------
  * D (k x k, symmetric, ldd) is read, not modified.

@@ -14,7 +14,7 @@ import numpy as np
 
 __all__ = [
     "load", "DopinfError", "CENTER", "SCALE", "APPLY", "F64", "F32",
-    "GRAM_NATIVE", "GRAM_BF16X3", "ITEM_PASS", "ITEM_NONFINITE",
+    "GRAM_NATIVE", "GRAM_BF16X3", "GRAM_BF16X6", "ITEM_PASS", "ITEM_NONFINITE",
     "ITEM_GROWTH", "ITEM_SOLVE", "preprocess", "gram", "cross_gram",
     "reduce", "infer", "operator_offset", "rollout", "traj_offset",
     "n_quad", "lib_path", "closure_param_count", "rom_residuals", "closure_fit", "closure_norms",
@@ -24,7 +24,7 @@ __all__ = [
 OK, E_ARG, E_HIP, E_WORKSPACE, E_RANK, E_NOTSPD, E_NONFINITE, E_NOSTABLE, E_TIMEOUT = range(9)
 F64, F32 = 0, 1
 CENTER, SCALE, APPLY = 1, 2, 4
-GRAM_NATIVE, GRAM_BF16X3 = 0, 1
+GRAM_NATIVE, GRAM_BF16X3, GRAM_BF16X6 = 0, 1, 2
 ITEM_PASS, ITEM_NONFINITE, ITEM_GROWTH, ITEM_SOLVE = 0, 1, 2, 3
 ROLLOUT_FULL = 1
 
@@ -51,7 +51,8 @@ _SIGS = {
     "dopinf_gram_workspace": ([_i32, _i32, _i64, _i64], _sz),
     "dopinf_gram": ([_vp, _i32, _i32, _vp, _i64, _i64, _i64, _vp, _vp, _i32, _vp, _vp, _i64, _vp, _sz], _i32),
     "dopinf_cross_gram_workspace": ([_i64, _i64, _i64], _sz),
-    "dopinf_cross_gram": ([_vp, _vp, _i64, _vp, _i64, _i64, _i64, _i64, _vp, _i64, _vp, _sz], _i32),
+    "dopinf_cross_gram": ([_vp, _vp, _i64, _vp, _i64, _i64, _i64, _i64, _vp, _vp, _i32, _vp, _vp, _i64, _vp, _sz],
+                          _i32),
     "dopinf_reduce_workspace": ([_i64, _i32], _sz),
     "dopinf_reduce": ([_vp, _vp, _i64, _i64, _i32, _f64, _i32, _vp, _vp, _vp, _i64, _vp, _i64, _vp, _vp, _sz], _i32),
     "dopinf_operator_offset": ([_i32, _vp, _i32, _i32], _sz),
@@ -198,8 +199,9 @@ def gram(Q, mean=None, scale=None, var_rows=None, algo=GRAM_NATIVE, out=None):
     return D
 
 
-def cross_gram(X, Y, out=None):
-    """C = X^T Y for float64 X (n x mx), Y (n x my)."""
+def cross_gram(X, Y, out=None, mean=None, scale=None, var_rows=None):
+    """C = Xs^T Ys for float64 X (n x mx), Y (n x my); with mean / scale both
+    are centered and scaled on load with the same statistics."""
     torch = _torch()
     lib = load()
     n, mx = X.shape
@@ -208,10 +210,14 @@ def cross_gram(X, Y, out=None):
         raise ValueError("X and Y need the same number of rows")
     dev = X.device
     Cm = out if out is not None else torch.empty((mx, my), dtype=torch.float64, device=dev)
+    if var_rows is None:
+        var_rows = [0, n]
+    vr, vrp = _host_i64(var_rows)
     nb = lib.dopinf_cross_gram_workspace(n, mx, my)
     ws = _ws(nb, dev)
     _check(lib.dopinf_cross_gram(_stream(dev), _ptr(X), _rowmajor(X, "X"), _ptr(Y), _rowmajor(Y, "Y"), n, mx, my,
-                                 _ptr(Cm), _rowmajor(Cm, "C"), _ptr(ws), ws.numel()))
+                                 _ptr(mean), _ptr(scale), len(vr) - 1, vrp, _ptr(Cm), _rowmajor(Cm, "C"), _ptr(ws),
+                                 ws.numel()))
     return Cm
 
 

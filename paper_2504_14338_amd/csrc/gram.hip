@@ -323,7 +323,8 @@ extern "C" int dopinf_gram(void* stream, int dtype, int algo, const void* Q, int
                              scale ? var_rows_h : nullptr, D, ldd, ws, ws_bytes);
   }
   DOPINF_REQUIRE(dtype == DOPINF_F32, "dtype must be DOPINF_F64 or DOPINF_F32");
-  DOPINF_REQUIRE(algo == DOPINF_GRAM_NATIVE || algo == DOPINF_GRAM_BF16X3, "unknown gram algorithm");
+  DOPINF_REQUIRE(algo == DOPINF_GRAM_NATIVE || algo == DOPINF_GRAM_BF16X3 || algo == DOPINF_GRAM_BF16X6,
+                 "unknown gram algorithm");
   return gram_lowp(st, algo, static_cast<const float*>(Q), n, k, ldq, mean, scale, scale ? nvars : 0,
                    scale ? var_rows_h : nullptr, D, ldd, ws, ws_bytes);
 }
@@ -336,11 +337,16 @@ extern "C" size_t dopinf_cross_gram_workspace(int64_t n, int64_t mx, int64_t my)
 namespace dopinf {
 
 int cross_gram_internal(hipStream_t st, const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t n,
-                        int64_t mx, int64_t my, double* C, int64_t ldc, void* ws, size_t ws_bytes) {
+                        int64_t mx, int64_t my, double* C, int64_t ldc, void* ws, size_t ws_bytes,
+                        const double* mean, const double* scale, int nvars, const int64_t* var_rows_h) {
   const int ty = tiles_of(my);
   const int ntiles = tiles_of(mx) * ty;
   int64_t one_var[2] = {0, n};
-  SplitPlan sp = gramplan::make_plan(n, 1, one_var, choose_splits(n, ntiles), KC);
+  if (!var_rows_h || nvars < 1) {
+    nvars = 1;
+    var_rows_h = one_var;
+  }
+  SplitPlan sp = gramplan::make_plan(n, nvars, var_rows_h, choose_splits(n, ntiles), KC);
   if (!ws || ws_bytes < part_bytes(sp.nsplit, ntiles))
     return fail(DOPINF_E_WORKSPACE, "cross gram workspace of %zu bytes needed, %zu given",
                 part_bytes(sp.nsplit, ntiles), ws_bytes);
@@ -353,22 +359,30 @@ int cross_gram_internal(hipStream_t st, const double* X, int64_t ldx, const doub
   g.my = my;
   g.ntiles = ntiles;
   g.triangle = 0;
+  g.mean = mean;
+  g.scale = scale;
   g.part = static_cast<double*>(ws);
   return run_gram(st, g, sp, C, ldc, ty);
 }
 
 size_t cross_gram_workspace_internal(int64_t n, int64_t mx, int64_t my) {
   const int ntiles = tiles_of(mx) * tiles_of(my);
-  return part_bytes(choose_splits(n, ntiles) + 8, ntiles);
+  return part_bytes(choose_splits(n, ntiles) + DOPINF_MAX_VARS + 8, ntiles);
 }
 
 }  // namespace dopinf
 
 extern "C" int dopinf_cross_gram(void* stream, const double* X, int64_t ldx, const double* Y, int64_t ldy,
-                                 int64_t n, int64_t mx, int64_t my, double* C, int64_t ldc, void* ws,
+                                 int64_t n, int64_t mx, int64_t my, const double* mean, const double* scale,
+                                 int nvars, const int64_t* var_rows_h, double* C, int64_t ldc, void* ws,
                                  size_t ws_bytes) {
   DOPINF_REQUIRE(X && Y && C, "X, Y and C must be non-NULL");
   DOPINF_REQUIRE(n >= 1 && mx >= 1 && my >= 1 && ldx >= mx && ldy >= my && ldc >= my,
                  "need n, mx, my >= 1 and ldx >= mx, ldy >= my, ldc >= my");
-  return cross_gram_internal(static_cast<hipStream_t>(stream), X, ldx, Y, ldy, n, mx, my, C, ldc, ws, ws_bytes);
+  if (scale || var_rows_h) {
+    int rc = check_var_rows(n, nvars, var_rows_h);
+    if (rc) return rc;
+  }
+  return cross_gram_internal(static_cast<hipStream_t>(stream), X, ldx, Y, ldy, n, mx, my, C, ldc, ws, ws_bytes,
+                             mean, scale, scale ? nvars : 0, scale ? var_rows_h : nullptr);
 }

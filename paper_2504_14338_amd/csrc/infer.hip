@@ -32,7 +32,8 @@ int gram_f64_internal(hipStream_t st, const double* X, int64_t n, int64_t m, int
                       size_t ws_bytes);
 size_t gram_f64_workspace_internal(int64_t n, int64_t m, int nvars);
 int cross_gram_internal(hipStream_t st, const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t n,
-                        int64_t mx, int64_t my, double* C, int64_t ldc, void* ws, size_t ws_bytes);
+                        int64_t mx, int64_t my, double* C, int64_t ldc, void* ws, size_t ws_bytes,
+                        const double* mean, const double* scale, int nvars, const int64_t* var_rows_h);
 size_t cross_gram_workspace_internal(int64_t n, int64_t mx, int64_t my);
 
 namespace {
@@ -704,7 +705,7 @@ extern "C" int dopinf_infer(void* stream, const double* Qhat, int64_t ldqh, int6
       if (rc2) return rc2;
       for (int u = 0; u < nu; ++u) {
         int rc = cross_gram_internal(st, R + size_t(u) * s * w, w, R + size_t(u) * s * w, w, s, r1, w,
-                                     CV + size_t(u) * r1 * w, w, cgws, cgb);
+                                     CV + size_t(u) * r1 * w, w, cgws, cgb, nullptr, nullptr, 0, nullptr);
         if (rc) return rc;
       }
       PairArgs pa{};

@@ -10,6 +10,9 @@ arithmetic:
   * BF16X3: x = hi + lo + delta with |delta| <= 2^-16 |x|; dropping lo*lo and
     the delta terms leaves <= 3 * 2^-16 ~ 4.6e-5 relative error per product,
     plus the float32 slab accumulation.  Bound used: 2e-4.
+  * BF16X6: x = hi + mid + lo + delta with |delta| <= 2^-24 |x|; the dropped
+    products (mid*lo, lo*mid, lo*lo and the delta terms) are <= ~4 * 2^-24
+    relative, below the float32 slab accumulation: bound as FP32, 3e-5.
 """
 import numpy as np
 import pytest
@@ -21,6 +24,7 @@ pytestmark = pytest.mark.gpu
 
 FP32_TOL = 3e-5
 BF16X3_TOL = 2e-4
+TOLS = {"native": FP32_TOL, "bf16x3": BF16X3_TOL, "bf16x6": FP32_TOL}
 
 
 def rel(a, b):
@@ -28,11 +32,11 @@ def rel(a, b):
 
 
 @pytest.mark.parametrize("n,k,nvars", [(8192, 600, 2), (3001, 130, 3), (777, 64, 1)])
-@pytest.mark.parametrize("algo_name", ["native", "bf16x3"])
+@pytest.mark.parametrize("algo_name", ["native", "bf16x3", "bf16x6"])
 def test_lowp_gram_parity(gpu_lib, n, k, nvars, algo_name):
     import torch
     dp = gpu_lib
-    algo = dp.GRAM_NATIVE if algo_name == "native" else dp.GRAM_BF16X3
+    algo = {"native": dp.GRAM_NATIVE, "bf16x3": dp.GRAM_BF16X3, "bf16x6": dp.GRAM_BF16X6}[algo_name]
     rng = np.random.default_rng(n + k)
     Q = (rng.standard_normal((n, k)) * np.linspace(0.3, 3.0, k)[None, :] + 0.7).astype(np.float32)
     var_rows = np.linspace(0, n, nvars + 1).astype(np.int64)
@@ -42,7 +46,7 @@ def test_lowp_gram_parity(gpu_lib, n, k, nvars, algo_name):
     _, _, Qs, _ = orc.preprocess(Q.astype(np.float64), var_rows)
     Dref = orc.gram(Qs)
     assert np.array_equal(D, D.T)
-    tol = FP32_TOL if algo_name == "native" else BF16X3_TOL
+    tol = TOLS[algo_name]
     assert rel(D, Dref) <= tol
     # diagonal entries are sums of squares: relative accuracy per entry
     assert np.max(np.abs(np.diag(D) - np.diag(Dref)) / np.diag(Dref)) <= 4 * tol
@@ -54,7 +58,7 @@ def test_lowp_gram_deterministic_and_reduced_data(gpu_lib):
     Q, var_rows, _, _ = synth.c1_snapshots(seed=1)
     Q32 = torch.from_numpy(Q.astype(np.float32)).cuda()
     mean, scale, _ = dp.preprocess(Q32, var_rows)
-    for algo, tol in ((dp.GRAM_NATIVE, FP32_TOL), (dp.GRAM_BF16X3, BF16X3_TOL)):
+    for algo, tol in ((dp.GRAM_NATIVE, FP32_TOL), (dp.GRAM_BF16X3, BF16X3_TOL), (dp.GRAM_BF16X6, FP32_TOL)):
         D1 = dp.gram(Q32, mean, scale, var_rows, algo=algo)
         D2 = dp.gram(Q32, mean, scale, var_rows, algo=algo)
         assert torch.equal(D1, D2)

@@ -160,3 +160,26 @@ def test_reduce_rank_error_flag(gpu_lib):
     X[:, 0] = 1.0                   # rank-1 Gram
     lam, Tr, Qhat, info, r = dp.reduce(dp.gram(dev(X)), r=3)
     assert int(info.item()) == dp.E_RANK
+
+
+def test_cross_gram_with_training_statistics(gpu_lib):
+    # held-out snapshots centered / scaled with the training statistics,
+    # projected through Eq. (8): Qhat_test = T_r^T (Qs^T Qs_test)
+    dp = gpu_lib
+    rng = np.random.default_rng(15)
+    n, k, kt = 900, 40, 25
+    var_rows = [0, 300, 900]
+    Q = rng.standard_normal((n, k)) * 2 + 1
+    Qt = rng.standard_normal((n, kt)) * 2 + 1
+    mu, s, Qs, _ = orc.preprocess(Q, var_rows)
+    Qts = (Qt - mu[:, None]).copy()
+    Qts[:300] /= s[0]
+    Qts[300:] /= s[1]
+    mean, scale, _ = dp.preprocess(dev(Q), var_rows)
+    C = dp.cross_gram(dev(Q), dev(Qt), mean=mean, scale=scale, var_rows=var_rows).cpu().numpy()
+    assert rel(C, Qs.T @ Qts) < 1e-12
+    D = dp.gram(dev(Q), mean, scale, var_rows)
+    lam, Tr, Qhat, info, r = dp.reduce(D, r=5)
+    P = dp.cross_gram(Tr.contiguous(), dev(C)).cpu().numpy()   # T_r^T C
+    Vr = Qs @ Tr.cpu().numpy()                                 # explicit basis, for the check only
+    assert rel(P, Vr.T @ Qts) < 1e-10
