@@ -330,7 +330,7 @@ def main():
             "unit": "TFLOP/s",
             "frac": round(gram_tf / FP64_PEAK, 4),
             "traffic": None,
-            "kernel": "gram_f64_mfma_kernel (+ its split reduction)",
+            "kernel": "gram_f64_dma_kernel (+ its split reduction)",
             "per_launch_flops": gram_flops,
         },
         "preprocess_GBps": round(n * k * 8 / (phases["preprocess"] * 1e-3) / 1e9, 1),

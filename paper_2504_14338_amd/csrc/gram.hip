@@ -6,15 +6,21 @@
 //  * D is cut into 128 x 128 tiles; only the lower triangle of tiles is
 //    computed (symmetry) and mirrored by the reduction.
 //  * The n rows are cut into splits (split-K).  Splits never straddle a state
-//    variable, so each workgroup applies one scale factor on load.  One
-//    workgroup = (tile, split); the grid holds ~8k workgroups so the 256 CUs
-//    see ~17 waves of work and a small tail.
+//    variable, so one scale factor 1/s_v^2 applies to a whole partial tile.
+//    One workgroup = (tile, split); the grid holds ~8k workgroups so the 256
+//    CUs see ~15 rounds of work and a small tail.
 //  * Workgroup: 4 waves in a 2 x 2 arrangement, each owning a 64 x 64
-//    sub-tile = 4 x 4 MFMA blocks of v_mfma_f64_16x16x4 (FP64 accumulate).
-//    Row panels of KC rows of both column blocks are staged through LDS,
-//    double-buffered: global loads of stage s+1 are in flight while stage s
-//    feeds the matrix cores.  Centering (x - mean_i) and scaling (* 1/s_v)
-//    are applied while staging, so Q is read as stored and never rewritten.
+//    sub-tile = 4 x 4 blocks of v_mfma_f64_16x16x4 (FP64 accumulate).
+//  * Main kernel (rows 16-byte aligned): panel rows go from HBM straight into
+//    LDS with buffer loads in LDS-DMA mode (no register staging).  A buffer
+//    descriptor spans one row, so columns past the row and rows past the split
+//    read as zero; the per-row temporal means travel the same way.  Two LDS
+//    stages of 16 rows; the loads of stage s+1 are in flight while stage s
+//    feeds the matrix cores.  Centering (x - mean_i) is applied to the
+//    fragments as they leave LDS, so Q is read as stored and never rewritten.
+//    75.8 KB of LDS per workgroup: two workgroups share a CU.
+//  * Fallback kernel (any alignment): the same tiling with register-staged
+//    loads, centering and scaling applied while staging.
 //  * XCD-aware order: consecutive workgroup ids go round-robin to the 8 XCDs;
 //    ids are mapped so that each XCD walks through its own splits with all
 //    tiles of a split together, i.e. the tiles running on one XCD share the
@@ -195,6 +201,169 @@ __global__ __launch_bounds__(NTH, 2) void gram_f64_mfma_kernel(GramArgs g, Split
       }
 }
 
+// ---- LDS-DMA kernel ---------------------------------------------------------
+
+constexpr int DKC = 16;                          // rows per LDS stage
+constexpr int DPD = 144;                         // LDS row pitch (doubles)
+constexpr int DSLOT = 2 * DKC * DPD + 4 * 32;    // A rows, B rows, 32 means per wave
+constexpr int DRPW = DKC / 4;                    // panel rows loaded per wave per stage
+
+#define DOPINF_LDS(p) ((__attribute__((address_space(3))) void*)(p))
+
+// Buffer descriptor over [p, p + nbytes): reads past nbytes return zero.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t span_rsrc(const void* p, int64_t nbytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, int(nbytes), 0x00020000);
+}
+
+// Wait until at most N vector-memory operations of this wave are in flight.
+template <int N>
+__device__ __forceinline__ void wait_vmem() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
+
+// Workgroup barrier that does not drain outstanding LDS-DMA loads (the
+// explicit wait above decides what must have landed).
+__device__ __forceinline__ void barrier_only() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+template <bool DIAG, bool XF>
+__device__ __forceinline__ void dma_tile(const GramArgs& g, int64_t lo, int64_t hi, int64_t a0, int64_t b0, double* lds,
+                                         dbl4 (&acc)[4][4]) {
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
+  const int wm = w >> 1, wn = w & 1;
+  const int64_t nst = (hi - lo + DKC - 1) / DKC;
+  const uint32_t offa = uint32_t((a0 + 2 * lane) * 8);
+  const uint32_t offb = uint32_t((b0 + 2 * lane) * 8);
+  const uint32_t offm = uint32_t(lane) * 4;
+  const int64_t bytes_x = g.ldx * 8, bytes_y = g.ldy * 8;
+
+  auto issue = [&](int64_t st) {
+    double* sl = lds + (st & 1) * DSLOT;
+    const int64_t r0 = lo + st * DKC;
+#pragma unroll
+    for (int q = 0; q < DRPW; ++q) {
+      const int r = w * DRPW + q;
+      const int64_t row = r0 + r;
+      const bool in = row < hi;
+      const int64_t rr = in ? row : lo;
+      const __amdgpu_buffer_rsrc_t ra = span_rsrc(g.X + rr * g.ldx, in ? bytes_x : 0);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, DOPINF_LDS(sl + r * DPD), 16, offa, 0, 0, 0);
+      if (!DIAG) {
+        const __amdgpu_buffer_rsrc_t rb = span_rsrc(g.Y + rr * g.ldy, in ? bytes_y : 0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, DOPINF_LDS(sl + (DKC + r) * DPD), 16, offb, 0, 0, 0);
+      }
+    }
+    if (XF) {
+      // lane l brings half of mean[r0 + l / 2]; rows past the split read as 0
+      const int64_t nm = (hi - r0) < 32 ? (hi - r0) : 32;
+      const __amdgpu_buffer_rsrc_t rmu = span_rsrc(g.mean + r0, nm * 8);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rmu, DOPINF_LDS(sl + 2 * DKC * DPD + w * 32), 4, offm, 0, 0, 0);
+    }
+  };
+
+  // waves whose 64 x 64 block lies wholly above the diagonal have nothing to add
+  bool active = true;
+  if (DIAG) active = (a0 + wm * 64 + 63) >= (b0 + wn * 64);
+
+  if (nst > 0) issue(0);
+  for (int64_t st = 0; st < nst; ++st) {
+    wait_vmem<0>();
+    barrier_only();
+    if (st + 1 < nst) issue(st + 1);
+    if (!active) continue;
+    const double* sl = lds + (st & 1) * DSLOT;
+    const double* As = sl;
+    const double* Bs = DIAG ? sl : sl + DKC * DPD;
+    const double* Ms = sl + 2 * DKC * DPD + w * 32;
+#pragma unroll
+    for (int kk = 0; kk < DKC / 4; ++kk) {
+      const int krow = kk * 4 + (lane >> 4);
+      const int cm = lane & 15;
+      const double mu = XF ? Ms[krow] : 0.0;
+      double af[4], bf[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) af[i] = As[krow * DPD + wm * 64 + i * 16 + cm] - mu;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bf[j] = Bs[krow * DPD + wn * 64 + j * 16 + cm] - mu;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+    }
+  }
+}
+
+__global__ __launch_bounds__(NTH, 2) void gram_f64_dma_kernel(GramArgs g, SplitPlan sp) {
+  __shared__ double lds[2 * DSLOT];
+  int t, s;
+  {
+    const int bid = blockIdx.x;
+    if (sp.xcd_map) {
+      const int xcd = bid & 7;
+      const int local = bid >> 3;
+      s = (local / g.ntiles) * 8 + xcd;
+      t = local % g.ntiles;
+    } else {
+      s = bid / g.ntiles;
+      t = bid % g.ntiles;
+    }
+  }
+  int I, J;
+  tile_coords(g, t, I, J);
+  int64_t lo, hi;
+  int v;
+  gramplan::split_range(sp, s, DKC, lo, hi, v);
+  const bool diag = g.triangle && (I == J);
+  const int64_t a0 = int64_t(I) * BT, b0 = int64_t(J) * BT;
+
+  dbl4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+
+  if (g.mean) {
+    if (diag) dma_tile<true, true>(g, lo, hi, a0, b0, lds, acc);
+    else dma_tile<false, true>(g, lo, hi, a0, b0, lds, acc);
+  } else {
+    if (diag) dma_tile<true, false>(g, lo, hi, a0, b0, lds, acc);
+    else dma_tile<false, false>(g, lo, hi, a0, b0, lds, acc);
+  }
+
+  // both operands carry 1/s_v: the partial tile takes 1/s_v^2
+  double f = 1.0;
+  if (g.scale) {
+    const double sv = g.scale[v];
+    f = 1.0 / (sv * sv);
+  }
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int wm = w >> 1, wn = w & 1;
+  double* out = g.part + (size_t(s) * g.ntiles + t) * (BT * BT);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        // v_mfma_f64_16x16x4: lane l, element e holds row (l / 16) + 4 e, column l % 16
+        const int rr = wm * 64 + i * 16 + (lane >> 4) + 4 * e;
+        const int cc = wn * 64 + j * 16 + (lane & 15);
+        out[rr * BT + cc] = acc[i][j][e] * f;
+      }
+}
+
+// The LDS-DMA kernel needs 16-byte aligned rows and descriptor-sized row spans.
+bool dma_ok(const double* P, int64_t ld) {
+  return (reinterpret_cast<uintptr_t>(P) & 15) == 0 && (ld & 1) == 0 && ld * 8 < (int64_t(1) << 31);
+}
+
 // Sum partial tiles over splits in fixed order and write C (both triangles
 // for the symmetric case).
 __global__ __launch_bounds__(256) void gram_reduce_kernel(const double* __restrict__ part, int nsplit,
@@ -228,7 +397,10 @@ size_t part_bytes(int nsplit, int ntiles) { return size_t(nsplit) * ntiles * BT 
 int run_gram(hipStream_t st, GramArgs g, const SplitPlan& sp, double* C, int64_t ldc, int tiles_y) {
   g.tiles_y = tiles_y;
   dim3 grid(unsigned(sp.nsplit) * unsigned(g.ntiles));
-  gram_f64_mfma_kernel<<<grid, NTH, 0, st>>>(g, sp);
+  if (dma_ok(g.X, g.ldx) && dma_ok(g.Y, g.ldy))
+    gram_f64_dma_kernel<<<grid, NTH, 0, st>>>(g, sp);
+  else
+    gram_f64_mfma_kernel<<<grid, NTH, 0, st>>>(g, sp);
   DOPINF_LAUNCHED();
   dim3 rgrid(unsigned(g.ntiles), BT / 2);
   gram_reduce_kernel<<<rgrid, 256, 0, st>>>(g.part, sp.nsplit, g.ntiles, tiles_y, g.triangle, g.mx, g.my, C, ldc);

@@ -66,6 +66,59 @@ def test_preprocess_ragged_padded_f32_apply(gpu_lib):
     assert np.allclose(s32.cpu().numpy(), ss32, rtol=1e-13)
 
 
+def padded_view(A, ld, off):
+    """Device view of A (n x m) with row stride ld and a start offset of `off`
+    elements inside a NaN-filled flat buffer: odd ld or off = 1 breaks the
+    16-byte row alignment."""
+    import torch
+    n, m = A.shape
+    flat = np.full(off + n * ld, np.nan)
+    flat[off:].reshape(n, ld)[:, :m] = A
+    buf = torch.from_numpy(flat).cuda()
+    return buf[off:].view(n, ld)[:, :m]
+
+
+@pytest.mark.parametrize("ldx,ldy,off", [(132, 72, 0), (131, 70, 0), (132, 72, 1)])
+def test_cross_gram_paths_with_statistics(gpu_lib, ldx, ldy, off):
+    # even leading dimensions on 16-byte aligned rows take the LDS-DMA kernel,
+    # odd ones or an 8-byte offset take the register-staged one; both must match
+    # the oracle's centered and scaled product, and NaN padding must not leak
+    dp = gpu_lib
+    rng = np.random.default_rng(16 + ldx + off)
+    n, mx, my = 1037, 131, 70
+    var_rows = [0, 400, 1037]
+    X = rng.standard_normal((n, mx)) * 3 + 2
+    Y = rng.standard_normal((n, my)) * 3 + 2
+    Xd = padded_view(X, ldx, off)
+    Yd = padded_view(Y, ldy, 0)
+    mu, s, Xs, _ = orc.preprocess(X, var_rows)
+    Ys = (Y - mu[:, None]).copy()
+    Ys[:400] /= s[0]
+    Ys[400:] /= s[1]
+    mean, scale, _ = dp.preprocess(dev(X), var_rows)
+    C = dp.cross_gram(Xd, Yd, mean=mean, scale=scale, var_rows=var_rows).cpu().numpy()
+    assert np.all(np.isfinite(C))
+    assert rel(C, Xs.T @ Ys) < 1e-12
+    C0 = dp.cross_gram(Xd, Yd).cpu().numpy()
+    assert rel(C0, X.T @ Y) < 1e-12
+
+
+@pytest.mark.parametrize("ld,off", [(602, 0), (601, 0), (602, 1)])
+def test_gram_paths_nan_padding(gpu_lib, ld, off):
+    # symmetric Gram through both kernels, 3 variables, ragged last tile
+    dp = gpu_lib
+    rng = np.random.default_rng(ld + off)
+    n, k = 4099, 600
+    var_rows = [0, 1000, 3000, 4099]
+    Q = rng.standard_normal((n, k)) * np.linspace(0.5, 2.0, k)[None, :] + 1.5
+    Qd = padded_view(Q, ld, off)
+    mean, scale, _ = dp.preprocess(dev(Q), var_rows)
+    D = dp.gram(Qd, mean, scale, var_rows).cpu().numpy()
+    _, _, Qs, _ = orc.preprocess(Q, var_rows)
+    assert np.all(np.isfinite(D)) and np.array_equal(D, D.T)
+    assert rel(D, orc.gram(Qs)) <= 1e-12
+
+
 def test_cross_gram_layout_and_ragged_tiles(gpu_lib):
     # X != Y catches any transposition of the matrix-core lane layout
     dp = gpu_lib
