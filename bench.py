@@ -71,6 +71,27 @@ class Timer:
         self.acc = {}
 
 
+def measured_traffic():
+    """HBM bytes per launch of the Gram kernel from the committed counter
+    record (two rocprofv3 --pmc passes, FETCH_SIZE and WRITE_SIZE, scaled by a
+    1 GiB copy); None when the kernel sources changed since the counters were
+    taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "gram_f64_dma_n4e6_k2000_hbm_traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+        h = hashlib.sha256()
+        for src in rec["sources"]:
+            with open(os.path.join(ROOT, src), "rb") as f:
+                h.update(f.read())
+        if h.hexdigest() != rec["sources_sha256"]:
+            return None
+        return int(rec["bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def make_c2(torch, dev):
     import synth
     m = synth.c2_modes(nvars=4, ncell=1_000_000, k=2000, n_modes=200, n_pairs=60, decay=40.0, seed=2)
@@ -329,7 +350,8 @@ def main():
             "peak": FP64_PEAK,
             "unit": "TFLOP/s",
             "frac": round(gram_tf / FP64_PEAK, 4),
-            "traffic": None,
+            "traffic": measured_traffic(),
+            "traffic_unit": "bytes per launch (HBM read + write, rocprofv3 counters)",
             "kernel": "gram_f64_dma_kernel (+ its split reduction)",
             "per_launch_flops": gram_flops,
         },
