@@ -64,8 +64,10 @@ extern "C" {
 #define DOPINF_ITEM_NONFINITE 1   /* the rollout produced NaN/Inf              */
 #define DOPINF_ITEM_GROWTH 2      /* growth >= max_growth                      */
 #define DOPINF_ITEM_SOLVE 3       /* the regularized solve failed (not SPD)    */
+#define DOPINF_ITEM_TIMEOUT 4     /* a multi-workgroup rollout gave up waiting */
 
 #define DOPINF_ROLLOUT_FULL 1u    /* no early exit: run every state            */
+#define DOPINF_ROLLOUT_ONE_WG 2u  /* one workgroup per item even for few items */
 
 const char* dopinf_last_error(void);
 const char* dopinf_version(void);
@@ -173,6 +175,10 @@ int dopinf_infer(void* stream, const double* Qhat, int64_t ldqh, int64_t k,
  *                   hold the values reached so far).
  * solve_status (NULL or dopinf_infer's status): items with a failed solve
  * are not rolled out (outcome DOPINF_ITEM_SOLVE).
+ * Few items (n_r * n_pairs small) are rolled out by teams of workgroups that
+ * keep the operator rows on chip and exchange the state every step; a team
+ * whose exchange does not complete within seconds gives up with outcome
+ * DOPINF_ITEM_TIMEOUT (and train_err = growth = NaN).
  * best[g] (device ints, n_r): item index (within the whole layout) of the
  * smallest train_err among passing items of group g, the first in layout
  * order on ties, -1 if none passes.

@@ -15,7 +15,7 @@ import numpy as np
 __all__ = [
     "load", "DopinfError", "CENTER", "SCALE", "APPLY", "F64", "F32",
     "GRAM_NATIVE", "GRAM_BF16X3", "GRAM_BF16X6", "ITEM_PASS", "ITEM_NONFINITE",
-    "ITEM_GROWTH", "ITEM_SOLVE", "preprocess", "gram", "cross_gram",
+    "ITEM_GROWTH", "ITEM_SOLVE", "ITEM_TIMEOUT", "preprocess", "gram", "cross_gram",
     "reduce", "infer", "operator_offset", "rollout", "traj_offset",
     "n_quad", "lib_path", "closure_param_count", "rom_residuals", "closure_fit", "closure_norms",
     "closure_grad", "closure_eval", "closure_rollout",
@@ -25,8 +25,9 @@ OK, E_ARG, E_HIP, E_WORKSPACE, E_RANK, E_NOTSPD, E_NONFINITE, E_NOSTABLE, E_TIME
 F64, F32 = 0, 1
 CENTER, SCALE, APPLY = 1, 2, 4
 GRAM_NATIVE, GRAM_BF16X3, GRAM_BF16X6 = 0, 1, 2
-ITEM_PASS, ITEM_NONFINITE, ITEM_GROWTH, ITEM_SOLVE = 0, 1, 2, 3
+ITEM_PASS, ITEM_NONFINITE, ITEM_GROWTH, ITEM_SOLVE, ITEM_TIMEOUT = 0, 1, 2, 3, 4
 ROLLOUT_FULL = 1
+ROLLOUT_ONE_WG = 2
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
@@ -293,8 +294,9 @@ def traj_offset(r_list, n_pairs, n_states, item):
 
 
 def rollout(O, Qhat, r_list, n_pairs, n_states, k_train=None, max_growth=1.2, solve_status=None,
-            keep_traj=False, full=False):
-    """Roll out, score and select.  Returns dict of device tensors."""
+            keep_traj=False, full=False, one_wg=False):
+    """Roll out, score and select.  Returns dict of device tensors.  Few items
+    are rolled out by teams of workgroups unless one_wg is set."""
     torch = _torch()
     lib = load()
     dev = O.device
@@ -313,7 +315,7 @@ def rollout(O, Qhat, r_list, n_pairs, n_states, k_train=None, max_growth=1.2, so
     nb = lib.dopinf_rollout_workspace(len(rl), rlp, n_pairs, k_train)
     ws = _ws(nb, dev)
     _check(lib.dopinf_rollout(_stream(dev), len(rl), rlp, n_pairs, _ptr(O), _ptr(Qhat), _rowmajor(Qhat, "Qhat"),
-                              k_train, n_states, float(max_growth), ROLLOUT_FULL if full else 0,
+                              k_train, n_states, float(max_growth), (ROLLOUT_FULL if full else 0) | (ROLLOUT_ONE_WG if one_wg else 0),
                               _ptr(solve_status), _ptr(traj), _ptr(te), _ptr(gr), _ptr(oc), _ptr(best), _ptr(ws),
                               ws.numel()))
     out = {"train_err": te, "growth": gr, "outcome": oc, "best": best, "traj": traj}

@@ -20,68 +20,21 @@
 //     workgroup per vector with z in LDS.
 //  5. Sign rule and Qhat / T_r formation.
 #include "common.hpp"
+#include "xwg_sync.hpp"
 
 namespace dopinf {
 namespace {
 
 constexpr int TNT = 256;            // threads of the tridiagonalization kernel
 constexpr int TCH = 8;              // rows reduced together in phase 2
-constexpr long kSpinLimit = 1L << 30;  // polls before a barrier gives up (seconds)
 
-// ---------------------------------------------------------------------------
-// Cross-workgroup communication of the persistent kernel.  All data shared
-// between workgroups (reflectors, p, partial sums, flags) is written and read
-// with relaxed device-scope atomics, which are coherent across the XCDs'
-// L2 caches; a writer drains its memory counter (s_waitcnt) before it
-// signals, so no cache-wide release/acquire fences are needed.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ void st_dev(double* p, double v) {
-  __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), static_cast<unsigned long long>(__double_as_longlong(v)),
-                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ double ld_dev(const double* p) {
-  return __longlong_as_double(static_cast<long long>(__hip_atomic_load(
-      reinterpret_cast<unsigned long long*>(const_cast<double*>(p)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
-}
-__device__ __forceinline__ unsigned ld_flag(unsigned* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
+using xwg::drain_then_sync;
+using xwg::ld_dev;
+using xwg::st_dev;
+using xwg::wait_ge;
 
-// Spin (thread 0) until *p >= target; false if the abort flag was raised or
-// the spin cap was hit (then the abort flag is raised for everybody).
-__device__ bool wait_ge(unsigned* p, unsigned target, int* abort_flag) {
-  __shared__ int ok_sh;
-  if (threadIdx.x == 0) {
-    long spins = 0;
-    int ok = 1;
-    while (ld_flag(p) < target) {
-      if ((++spins & 255) == 0) {
-        if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 || spins > kSpinLimit) {
-          __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          ok = 0;
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-      }
-    }
-    ok_sh = ok;
-  }
-  __syncthreads();
-  return ok_sh != 0;
-}
-
-// all threads: drain this workgroup's stores, then thread 0 performs `op`
-__device__ __forceinline__ void drain_then_sync() {
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
-}
-
-// device-wide barrier: arrive, wait for all nblocks arrivals of this round
-__device__ bool grid_barrier(unsigned* bar, unsigned nblocks, unsigned& gen, int* abort_flag) {
-  drain_then_sync();
-  if (threadIdx.x == 0) __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  ++gen;
-  return wait_ge(bar, gen * nblocks, abort_flag);
+__device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned nblocks, unsigned& gen, int* abort_flag) {
+  return xwg::team_barrier(bar, nblocks, gen, abort_flag);
 }
 
 __global__ void zero_words_kernel(unsigned* p, int n) {

@@ -2,15 +2,28 @@
 // quadratic ROM of Eq. (11) over the trial horizon, the training error, the
 // growth bound and the selection of the best candidate.
 //
-// One workgroup rolls out one candidate: the state and the feature vector
-// [q, quad(q), 1] live in LDS, the operator rows stream from L2 (each wave
-// reduces several rows at a time), and the score (finiteness, running
-// maximum of the relative training error, running maximum deviation from the
-// training mean) is accumulated while stepping, so the trajectory never has
-// to be stored.  A candidate stops as soon as its failure is certain: the
-// growth statistic is a running maximum, so crossing the bound (or meeting a
-// non-finite value) is final and the selection is unchanged.
+// Many candidates (the regularization sweep): one workgroup rolls out one
+// candidate: the state and the feature vector [q, quad(q), 1] live in LDS,
+// the operator rows stream from L2 (each wave reduces several rows at a
+// time).
+//
+// Few candidates (the plain run): a team of P co-resident workgroups rolls
+// out one candidate.  Wave w of team member p owns operator row p*8 + w and
+// keeps it in registers for the whole rollout, so no operator byte moves
+// after the start; every step each member builds the features of the full
+// state in LDS, forms its 8 next-state entries, publishes them with
+// device-scope stores and meets the others at a counter barrier, then reads
+// the full next state back.
+//
+// In both forms the score (finiteness, running maximum of the relative
+// training error, running maximum deviation from the training mean) is
+// accumulated while stepping, so the trajectory never has to be stored, and a
+// candidate stops as soon as its failure is certain: the growth statistic is
+// a running maximum, so crossing the bound (or meeting a non-finite value) is
+// final and the selection is unchanged.  Team members score the same state
+// with the same code and so take the same decision without talking.
 #include "common.hpp"
+#include "xwg_sync.hpp"
 
 namespace dopinf {
 namespace {
@@ -224,6 +237,181 @@ __global__ __launch_bounds__(RT) void rollout_kernel(RollArgs a) {
   }
 }
 
+// ---- team rollout -------------------------------------------------------------
+
+constexpr int TW = 8;     // waves per team workgroup = operator rows per member
+constexpr int TNT = TW * 64;
+constexpr int TNJ_MAX = 64;  // operator entries per lane: d <= 64 * 64
+
+struct TeamArgs {
+  RollArgs a;
+  int P;              // members per team
+  double* xbuf;       // per item: 2 x r exchange slots
+  unsigned* bar;      // per item: step counter
+  int* abort_flag;
+};
+
+__global__ void zero_u32_kernel(unsigned* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+template <int TNJ>
+__global__ __launch_bounds__(TNT) void rollout_team_kernel(TeamArgs ta) {
+  extern __shared__ double sm[];
+  const RollArgs& a = ta.a;
+  const int item = blockIdx.x / ta.P;
+  const int pm = blockIdx.x % ta.P;
+  const int r = a.r;
+  const int64_t s = a.s, d = a.d;
+  const int64_t dpad = int64_t(TNJ) * 64;
+  double* f = sm;                  // dpad features [q | quad(q) | 1 | 0...]
+  double* mean = f + dpad;         // r
+  unsigned short* qi = reinterpret_cast<unsigned short*>(mean + r);
+  unsigned short* qj = qi + s;
+  __shared__ double red[TW][4];
+  __shared__ int stop_sh;
+  __shared__ double dev0_sh;
+
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int row = pm * TW + w;
+  const int i_lo = pm * TW;
+  const int i_hi = (i_lo + TW < r) ? i_lo + TW : r;
+  const double* Op = a.O + size_t(item) * r * d;
+  double* trj = a.traj ? a.traj + size_t(item) * a.n_states * r : nullptr;
+  double* xb = ta.xbuf + size_t(item) * 2 * r;
+  unsigned* bar = ta.bar + item;
+
+  if (a.solve_status && a.solve_status[item] != DOPINF_OK) {
+    if (pm == 0 && tid == 0) {
+      a.outcome[item] = DOPINF_ITEM_SOLVE;
+      a.train_err[item] = NAN;
+      a.growth[item] = NAN;
+    }
+    if (trj)
+      for (int64_t e = tid; e < int64_t(a.n_states) * (i_hi - i_lo); e += TNT)
+        trj[(e / (i_hi - i_lo)) * r + i_lo + e % (i_hi - i_lo)] = NAN;
+    return;
+  }
+  for (int64_t c = tid; c < s; c += TNT) {
+    int ii = 0;
+    int64_t off = 0;
+    while (off + (r - ii) <= c) {
+      off += r - ii;
+      ++ii;
+    }
+    qi[c] = static_cast<unsigned short>(ii);
+    qj[c] = static_cast<unsigned short>(ii + (c - off));
+  }
+  for (int64_t c = d + tid; c < dpad; c += TNT) f[c] = 0.0;
+  for (int i = tid; i < r; i += TNT) {
+    mean[i] = a.mean[i];
+    f[i] = a.Qhat[int64_t(i) * a.ldqh];
+  }
+  if (tid == 0) {
+    double md = 0.0;
+    for (int i = 0; i < r; ++i) md = fmax(md, a.maxdev[i]);
+    dev0_sh = md;
+  }
+  // this wave's operator row, resident in registers for the whole rollout
+  double o[TNJ];
+#pragma unroll
+  for (int j = 0; j < TNJ; ++j) {
+    const int64_t c = lane + 64 * j;
+    o[j] = (row < r && c < d) ? Op[int64_t(row) * d + c] : 0.0;
+  }
+  __syncthreads();
+  const double maxdev = dev0_sh;
+
+  double run_err = 0.0, run_dev = 0.0;
+  int oc = DOPINF_ITEM_PASS;
+  int t_done = a.n_states;
+  unsigned gen = 0;
+  // training snapshot of the state being scored, fetched one step ahead
+  double h = (tid < r && 0 < a.k_train) ? a.Qhat[int64_t(tid) * a.ldqh] : 0.0;
+  for (int t = 0; t < a.n_states; ++t) {
+    double e2 = 0.0, n2 = 0.0, dv = 0.0, bad = 0.0;
+    if (tid < r) {
+      const double x = f[tid];
+      if (!isfinite(x)) bad = 1.0;
+      dv = fabs(x - mean[tid]);
+      if (t < a.k_train) {
+        e2 = (x - h) * (x - h);
+        n2 = h * h;
+      }
+      if (trj && tid >= i_lo && tid < i_hi) trj[int64_t(t) * r + tid] = x;
+    }
+    e2 = wave_sum(e2);
+    n2 = wave_sum(n2);
+    dv = wave_max(dv);
+    bad = wave_max(bad);
+    if (lane == 0) {
+      red[w][0] = e2;
+      red[w][1] = n2;
+      red[w][2] = dv;
+      red[w][3] = bad;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double E2 = 0.0, N2 = 0.0, DV = 0.0, BAD = 0.0;
+      for (int q = 0; q < TW; ++q) {
+        E2 += red[q][0];
+        N2 += red[q][1];
+        DV = fmax(DV, red[q][2]);
+        BAD = fmax(BAD, red[q][3]);
+      }
+      int stop = 0;
+      if (BAD != 0.0) {
+        oc = DOPINF_ITEM_NONFINITE;
+        stop = 1;
+      } else {
+        run_dev = fmax(run_dev, DV);
+        if (t < a.k_train) run_err = fmax(run_err, E2 / N2);
+        if (run_dev / maxdev >= a.max_growth && oc == DOPINF_ITEM_PASS) {
+          oc = DOPINF_ITEM_GROWTH;
+          if (!a.full) stop = 1;
+        }
+      }
+      stop_sh = stop;
+    }
+    __syncthreads();
+    if (stop_sh) {
+      t_done = t + 1;
+      break;
+    }
+    if (t + 1 == a.n_states) break;
+    // features of state t
+    for (int64_t c = tid; c < s; c += TNT) f[r + c] = f[qi[c]] * f[qj[c]];
+    if (tid == 0) f[d - 1] = 1.0;
+    __syncthreads();
+    // this wave's entry of the next state
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < TNJ; ++j) acc += o[j] * f[lane + 64 * j];
+    acc = wave_sum(acc);
+    double* slot = xb + ((t + 1) & 1) * r;
+    if (lane == 0 && row < r) xwg::st_dev(slot + row, acc);
+    // next training snapshot, in flight during the barrier
+    h = (tid < r && t + 1 < a.k_train) ? a.Qhat[int64_t(tid) * a.ldqh + t + 1] : 0.0;
+    if (!xwg::team_barrier(bar, unsigned(ta.P), gen, ta.abort_flag)) {
+      oc = DOPINF_ITEM_TIMEOUT;
+      t_done = t + 1;
+      break;
+    }
+    if (tid < r) f[tid] = xwg::ld_dev(slot + tid);
+    __syncthreads();
+  }
+  if (trj)
+    for (int64_t e = tid; e < int64_t(a.n_states - t_done) * (i_hi - i_lo); e += TNT)
+      trj[(t_done + e / (i_hi - i_lo)) * r + i_lo + e % (i_hi - i_lo)] = NAN;
+  if (pm == 0 && tid == 0) {
+    const bool nan_out = (oc == DOPINF_ITEM_NONFINITE) || (oc == DOPINF_ITEM_TIMEOUT);
+    a.outcome[item] = oc;
+    a.train_err[item] = nan_out ? NAN : sqrt(run_err);
+    a.growth[item] = nan_out ? NAN : run_dev / maxdev;
+  }
+}
+
 // best[g] = argmin train_err over passing items of group g (first on ties)
 __global__ void select_kernel(const double* __restrict__ train_err, const int* __restrict__ outcome, int n_pairs,
                               int* __restrict__ best) {
@@ -258,15 +446,42 @@ extern "C" size_t dopinf_traj_offset(int n_r, const int* r_list_h, int n_pairs, 
   return off;
 }
 
-extern "C" size_t dopinf_rollout_workspace(int n_r, const int* r_list_h, int /*n_pairs*/, int64_t /*k_train*/) {
-  if (n_r <= 0 || !r_list_h) return 0;
-  int rmax = 0;
-  for (int g = 0; g < n_r; ++g) rmax = r_list_h[g] > rmax ? r_list_h[g] : rmax;
+namespace dopinf {
+namespace {
+
+// Team form for group of size r with n_pairs items: co-resident teams of
+// ceil(r / 8) workgroups while the teams fit on the chip at once.
+constexpr int kTeamMaxWorkgroups = 128;
+int team_size(int r, int n_pairs, unsigned flags) {
+  if (flags & DOPINF_ROLLOUT_ONE_WG) return 0;
+  if (ncols(r) > int64_t(64) * TNJ_MAX) return 0;
+  const int P = (r + TW - 1) / TW;
+  return (int64_t(P) * n_pairs <= kTeamMaxWorkgroups) ? P : 0;
+}
+
+struct RollWs {
+  double* mean;
+  double* maxdev;
+  double* xbuf;
+  unsigned* words;   // n_pairs counters + abort flag
+};
+
+RollWs carve_group(Carver& c, int r, int n_pairs) {
+  RollWs w;
+  w.mean = c.take<double>(size_t(r));
+  w.maxdev = c.take<double>(size_t(r));
+  w.xbuf = c.take<double>(size_t(n_pairs) * 2 * size_t(r));
+  w.words = c.take<unsigned>(size_t(n_pairs) + 1);
+  return w;
+}
+
+}  // namespace
+}  // namespace dopinf
+
+extern "C" size_t dopinf_rollout_workspace(int n_r, const int* r_list_h, int n_pairs, int64_t /*k_train*/) {
+  if (n_r <= 0 || !r_list_h || n_pairs <= 0) return 0;
   Carver c(nullptr, 0);
-  for (int g = 0; g < n_r; ++g) {
-    c.take<double>(size_t(rmax));
-    c.take<double>(size_t(rmax));
-  }
+  for (int g = 0; g < n_r; ++g) carve_group(c, r_list_h[g] > 0 ? r_list_h[g] : 1, n_pairs);
   return c.used;
 }
 
@@ -278,7 +493,7 @@ extern "C" int dopinf_rollout(void* stream, int n_r, const int* r_list_h, int n_
   DOPINF_REQUIRE(n_r >= 1 && n_pairs >= 1 && n_states >= 1, "need n_r, n_pairs, n_states >= 1");
   DOPINF_REQUIRE(k_train >= 1 && ldqh >= k_train, "need k_train >= 1 and ldqh >= k_train");
   DOPINF_REQUIRE(max_growth > 0.0, "max_growth must be > 0");
-  DOPINF_REQUIRE((flags & ~DOPINF_ROLLOUT_FULL) == 0, "unknown flag bits");
+  DOPINF_REQUIRE((flags & ~(DOPINF_ROLLOUT_FULL | DOPINF_ROLLOUT_ONE_WG)) == 0, "unknown flag bits");
   for (int g = 0; g < n_r; ++g) DOPINF_REQUIRE(r_list_h[g] >= 1 && r_list_h[g] <= 512, "r must be in [1, 512]");
   const size_t need = dopinf_rollout_workspace(n_r, r_list_h, n_pairs, k_train);
   if (!ws || ws_bytes < need) return fail(DOPINF_E_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
@@ -290,8 +505,9 @@ extern "C" int dopinf_rollout(void* stream, int n_r, const int* r_list_h, int n_
   for (int g = 0; g < n_r; ++g) {
     const int r = r_list_h[g];
     const int64_t s = nquad(r), d = ncols(r);
-    double* mean = c.take<double>(size_t(r > 0 ? r : 1));
-    double* maxdev = c.take<double>(size_t(r > 0 ? r : 1));
+    const RollWs w = carve_group(c, r, n_pairs);
+    double* mean = w.mean;
+    double* maxdev = w.maxdev;
     train_stats_kernel<<<r, 256, 0, st>>>(Qhat, ldqh, k_train, mean, maxdev);
     DOPINF_LAUNCHED();
     const size_t smem = size_t(d + 2 * r) * sizeof(double) + size_t(2 * s) * sizeof(unsigned short) + 64;
@@ -317,8 +533,34 @@ extern "C" int dopinf_rollout(void* stream, int n_r, const int* r_list_h, int n_
     ra.train_err = train_err + g * n_pairs;
     ra.growth = growth + g * n_pairs;
     ra.outcome = outcome + g * n_pairs;
-    rollout_kernel<<<n_pairs, RT, smem, st>>>(ra);
-    DOPINF_LAUNCHED();
+    const int P = team_size(r, n_pairs, flags);
+    bool launched = false;
+    if (P > 0) {
+      const int tnj = (d <= 64 * 32) ? 32 : 64;
+      const size_t tsm = size_t(int64_t(tnj) * 64 + r) * sizeof(double) + size_t(2 * s) * sizeof(unsigned short) + 64;
+      zero_u32_kernel<<<(n_pairs + 1 + 255) / 256, 256, 0, st>>>(w.words, n_pairs + 1);
+      DOPINF_LAUNCHED();
+      TeamArgs ta{};
+      ta.a = ra;
+      ta.P = P;
+      ta.xbuf = w.xbuf;
+      ta.bar = w.words;
+      ta.abort_flag = reinterpret_cast<int*>(w.words + n_pairs);
+      void* args[] = {&ta};
+      // co-residency of the team members is what the counter barrier needs;
+      // if the runtime cannot promise it, the one-workgroup form runs instead
+      const void* kern = (tnj == 32) ? reinterpret_cast<const void*>(rollout_team_kernel<32>)
+                                     : reinterpret_cast<const void*>(rollout_team_kernel<64>);
+      if (hipLaunchCooperativeKernel(kern, dim3(unsigned(n_pairs * P)), dim3(TNT), args, unsigned(tsm), st) ==
+          hipSuccess)
+        launched = true;
+      else
+        (void)hipGetLastError();
+    }
+    if (!launched) {
+      rollout_kernel<<<n_pairs, RT, smem, st>>>(ra);
+      DOPINF_LAUNCHED();
+    }
   }
   select_kernel<<<n_r, 64, 0, st>>>(train_err, outcome, n_pairs, best);
   DOPINF_LAUNCHED();

@@ -94,7 +94,8 @@ def test_infer_reports_breakdown(gpu_lib):
     assert status.cpu().numpy().tolist() == [dp.E_NOTSPD, 0]
 
 
-def test_rollout_parity_given_operators(gpu_lib, c1_qhat):
+@pytest.mark.parametrize("one_wg", [False, True])
+def test_rollout_parity_given_operators(one_wg, gpu_lib, c1_qhat):
     dp = gpu_lib
     Qhat, _, _ = c1_qhat
     Qh = Qhat.cpu().numpy()
@@ -103,7 +104,7 @@ def test_rollout_parity_given_operators(gpu_lib, c1_qhat):
     b2 = [1e-4, 1e-1]
     O, status, views = dp.infer(Qhat, r_list, b1, b2)
     n_states = 1200
-    out = dp.rollout(O, Qhat, r_list, 2, n_states, max_growth=1.2, solve_status=status, keep_traj=True, full=True)
+    out = dp.rollout(O, Qhat, r_list, 2, n_states, max_growth=1.2, solve_status=status, keep_traj=True, full=True, one_wg=one_wg)
     te = out["train_err"].cpu().numpy()
     gr = out["growth"].cpu().numpy()
     oc = out["outcome"].cpu().numpy()
@@ -128,47 +129,50 @@ def test_rollout_parity_given_operators(gpu_lib, c1_qhat):
         assert best[g] == (min(cand)[1] if cand else -1)
 
 
-def test_rollout_hand_cases_and_failure_modes(gpu_lib):
+@pytest.mark.parametrize("one_wg", [False, True])
+def test_rollout_hand_cases_and_failure_modes(one_wg, gpu_lib):
     import torch
     dp = gpu_lib
     # r = 1: q+ = 0.5 q + 0.25 q^2 + 0.1 from q0 = 2; second item unstable (q+ = 2 q)
     O = torch.tensor([0.5, 0.25, 0.1, 2.0, 0.0, 0.0], dtype=torch.float64, device="cuda")
     Qhat = torch.tensor([[2.0, 2.1, 2.2525, 2.0]], dtype=torch.float64, device="cuda")
-    out = dp.rollout(O, Qhat, [1], 2, 3, max_growth=1.2, keep_traj=True, full=True)
+    out = dp.rollout(O, Qhat, [1], 2, 3, max_growth=1.2, keep_traj=True, full=True, one_wg=one_wg)
     tr = out["traj_views"][0][0].cpu().numpy()[:, 0]
     assert tr[1] == pytest.approx(2.1, abs=1e-15)
     assert tr[2] == pytest.approx(1.05 + 0.25 * 2.1 ** 2 + 0.1, abs=1e-15)
     assert out["outcome"].cpu().numpy().tolist()[1] == dp.ITEM_GROWTH
     # early exit decides the same outcome and marks the unrun states NaN
-    out2 = dp.rollout(O, Qhat, [1], 2, 50, max_growth=1.2, keep_traj=True)
+    out2 = dp.rollout(O, Qhat, [1], 2, 50, max_growth=1.2, keep_traj=True, one_wg=one_wg)
     assert out2["outcome"].cpu().numpy().tolist()[1] == dp.ITEM_GROWTH
     assert np.isnan(out2["traj_views"][0][1].cpu().numpy()[-1, 0])
     # r = 2 hand case: columns [A | H(0,0) H(0,1) H(1,1) | c]
     O2 = torch.tensor([[0.5, 0.0, 1.0, 0.0, 0.0, 0.0], [0.0, 0.25, 0.0, 2.0, 0.0, 1.0]],
                       dtype=torch.float64, device="cuda").reshape(-1)
     Qh2 = torch.tensor([[1.0, 1.5], [2.0, 5.5]], dtype=torch.float64, device="cuda")
-    o2 = dp.rollout(O2, Qh2, [2], 1, 2, keep_traj=True, full=True)
+    o2 = dp.rollout(O2, Qh2, [2], 1, 2, keep_traj=True, full=True, one_wg=one_wg)
     assert np.array_equal(o2["traj_views"][0][0].cpu().numpy()[1], [1.5, 5.5])
     assert o2["train_err"].item() == 0.0
     # a non-finite rollout
     O3 = torch.tensor([1e200, 1e200, 0.0], dtype=torch.float64, device="cuda")
-    o3 = dp.rollout(O3, Qhat, [1], 1, 10, full=True)
+    o3 = dp.rollout(O3, Qhat, [1], 1, 10, full=True, one_wg=one_wg)
     assert o3["outcome"].item() == dp.ITEM_NONFINITE
     assert o3["best"].item() == -1
 
 
-def test_selection_ties_pick_first(gpu_lib, c1_qhat):
+@pytest.mark.parametrize("one_wg", [False, True])
+def test_selection_ties_pick_first(one_wg, gpu_lib, c1_qhat):
     dp = gpu_lib
     Qhat, _, _ = c1_qhat
     O, status, views = dp.infer(Qhat, [5], [1e-3, 1e-3, 1e-3], [1e-2, 1e-2, 1e-2])
-    out = dp.rollout(O, Qhat, [5], 3, 1200, solve_status=status)
+    out = dp.rollout(O, Qhat, [5], 3, 1200, solve_status=status, one_wg=one_wg)
     te = out["train_err"].cpu().numpy()
     assert te[0] == te[1] == te[2]
     if out["outcome"].cpu().numpy()[0] == dp.ITEM_PASS:
         assert out["best"].item() == 0
 
 
-def test_small_sweep_matches_oracle(gpu_lib, c1_qhat):
+@pytest.mark.parametrize("one_wg", [False, True])
+def test_small_sweep_matches_oracle(one_wg, gpu_lib, c1_qhat):
     dp = gpu_lib
     Qhat, _, _ = c1_qhat
     Qh = Qhat.cpu().numpy()
@@ -178,7 +182,7 @@ def test_small_sweep_matches_oracle(gpu_lib, c1_qhat):
     b2 = [y for _ in B1 for y in B2]
     r_list = [4, 8]
     O, status, views = dp.infer(Qhat, r_list, b1, b2)
-    out = dp.rollout(O, Qhat, r_list, len(b1), 1200, solve_status=status)
+    out = dp.rollout(O, Qhat, r_list, len(b1), 1200, solve_status=status, one_wg=one_wg)
     ref = orc.sweep(Qh, r_list, list(B1), list(B2), 1200)
     te = out["train_err"].cpu().numpy()
     oc = out["outcome"].cpu().numpy()
@@ -195,3 +199,41 @@ def test_small_sweep_matches_oracle(gpu_lib, c1_qhat):
             gi = best[g]
             # a different pick is only allowed between near-ties
             assert abs(te[gi] - ref["train_err"][g * len(b1) + rb]) <= 1e-6 * ref["train_err"][g * len(b1) + rb]
+
+
+@pytest.mark.parametrize("r", [20, 60])
+def test_team_rollout_partial_member_matches_oracle(gpu_lib, r):
+    # r = 20 and 60 leave the last team member with 4 of its 8 rows
+    import torch
+    dp = gpu_lib
+    rng = np.random.default_rng(r)
+    k = 300
+    # a stable linear-dominant ROM with small quadratic terms, from the oracle's layout
+    s = r * (r + 1) // 2
+    A = np.diag(rng.uniform(0.90, 0.99, r)) + 1e-3 * rng.standard_normal((r, r))
+    H = 1e-4 * rng.standard_normal((r, s))
+    c = 1e-3 * rng.standard_normal(r)
+    Og = np.hstack([A, H, c[:, None]])
+    q0 = rng.standard_normal(r)
+    Qh = orc.rollout(Og, r, q0, k) + 1e-3 * rng.standard_normal((r, k))
+    Qh[:, 0] = q0
+    O = torch.from_numpy(Og.ravel().copy()).cuda()
+    Qhat = torch.from_numpy(Qh.copy()).cuda()
+    n_states = 700
+    Qt = orc.rollout(Og, r, q0, n_states)
+    fin, e, gg, ok = orc.score(Qt, Qh, k, 1.2)
+    outs = [dp.rollout(O, Qhat, [r], 1, n_states, keep_traj=True, full=True, one_wg=f) for f in (False, True)]
+    scale = np.max(np.abs(Qt))
+    for out in outs:
+        traj = out["traj_views"][0][0].cpu().numpy().T
+        assert np.max(np.abs(traj - Qt)) <= 1e-10 * scale
+        assert out["train_err"].item() == pytest.approx(e, rel=1e-8)
+        assert out["growth"].item() == pytest.approx(gg, rel=1e-10)
+        assert (out["outcome"].item() == dp.ITEM_PASS) == ok
+    # early exit with a growth failure: same outcome, NaN after the exit
+    O2 = torch.from_numpy(np.hstack([1.5 * np.eye(r), np.zeros((r, s)), np.zeros((r, 1))]).ravel().copy()).cuda()
+    for f in (False, True):
+        o2 = dp.rollout(O2, Qhat, [r], 1, n_states, keep_traj=True, one_wg=f)
+        assert o2["outcome"].item() == dp.ITEM_GROWTH
+        tr = o2["traj_views"][0][0].cpu().numpy()
+        assert np.isnan(tr[-1]).all() and np.isfinite(tr[0]).all()
