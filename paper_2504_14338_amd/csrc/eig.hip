@@ -213,6 +213,144 @@ __global__ __launch_bounds__(TNT) void sytrd_kernel(TridArgs a) {
   }
 }
 
+// Same reduction with the owned rows in LDS and each thread's slice of v_j
+// and w_j = p_j - K v_j held in registers for the whole column: v and p are
+// read from global memory once per column (one parallel round of loads each)
+// instead of once per owned row, and the owned rows' v_i, p_i sit in LDS.
+// Thread t handles the columns l = j + 1 + t + TNT m, m < NM (k <= NM TNT).
+template <int NM>
+__global__ __launch_bounds__(TNT) void sytrd_reg_kernel(TridArgs a) {
+  extern __shared__ double lds_rows[];
+  __shared__ double red[TNT / 64][TCH];
+  __shared__ double bc[4];
+  const int g = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int64_t k = a.k;
+  const int P = a.P;
+  unsigned gen = 0;
+  double* vown = lds_rows + int64_t(a.rows_max) * k;   // v_i of owned rows
+  double* pown = vown + a.rows_max;                    // p_i of owned rows
+
+  auto row_ptr = [&](int q) -> double* { return lds_rows + int64_t(q) * k; };
+  const int nown = int((k - g + P - 1) / P) > 0 ? int((k - g + P - 1) / P) : 0;
+
+  for (int q = 0; q < nown; ++q) {
+    const int64_t i = g + int64_t(q) * P;
+    double* dst = row_ptr(q);
+    for (int64_t l = tid; l < k; l += TNT) dst[l] = a.D[i * a.ldd + l];
+  }
+  __syncthreads();
+  if (k >= 2 && g == 0) make_reflector(a, row_ptr(0), 0, &red[0][0]);
+
+  for (int64_t j = 0; j + 1 < k; ++j) {
+    if (!wait_ge(a.vflag, unsigned(j + 1), a.abort_flag)) return;  // v_j published
+    const double tj = ld_dev(a.tau + j);
+    const double* v = a.A + j * k;
+    const int par = int(j & 1);
+    double* pj = a.p + par * k;
+    double* partj = a.part + par * P;
+    const int q0 = int((j + 1 - g + P - 1) / P) > 0 ? int((j + 1 - g + P - 1) / P) : 0;  // first owned row > j
+    const bool owns_next = (j + 2 < k) && ((j + 1) % P == g);
+    if (tj == 0.0) {  // H_j = I: nothing to update (the barrier keeps the columns in step)
+      if (!grid_barrier(a.bar, P, gen, a.abort_flag)) return;
+      if (owns_next) make_reflector(a, row_ptr(int((j + 1) / P)), j + 1, &red[0][0]);
+      continue;
+    }
+    // this thread's entries of v_j; owned rows keep theirs in LDS
+    double vr[NM];
+#pragma unroll
+    for (int m = 0; m < NM; ++m) {
+      const int64_t l = j + 1 + tid + int64_t(TNT) * m;
+      vr[m] = (l < k) ? ld_dev(v + l) : 0.0;
+      if (l < k && l >= g && (l - g) % P == 0) vown[(l - g) / P] = vr[m];
+    }
+    __syncthreads();
+    // ---- p_i = tau * A[i, j+1:] . v[j+1:] for owned rows i > j ----------------
+    double mypart = 0.0;
+    for (int qb = q0; qb < nown; qb += TCH) {
+      const int nq = min(TCH, nown - qb);
+      double acc[TCH];
+#pragma unroll
+      for (int u = 0; u < TCH; ++u) acc[u] = 0.0;
+#pragma unroll
+      for (int m = 0; m < NM; ++m) {
+        const int64_t l = j + 1 + tid + int64_t(TNT) * m;
+        if (l < k) {
+#pragma unroll
+          for (int u = 0; u < TCH; ++u)
+            if (u < nq) acc[u] += row_ptr(qb + u)[l] * vr[m];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < TCH; ++u) acc[u] = wave_sum(acc[u]);
+      __syncthreads();
+      if ((tid & 63) == 0) {
+#pragma unroll
+        for (int u = 0; u < TCH; ++u) red[tid >> 6][u] = acc[u];
+      }
+      __syncthreads();
+      if (tid < nq) {
+        double sacc = 0.0;
+#pragma unroll
+        for (int ww = 0; ww < TNT / 64; ++ww) sacc += red[ww][tid];
+        const int q = qb + tid;
+        const double pi = tj * sacc;
+        st_dev(pj + g + int64_t(q) * P, pi);
+        pown[q] = pi;
+      }
+      __syncthreads();
+      if (tid == 0)
+        for (int u = 0; u < nq; ++u) mypart += vown[qb + u] * pown[qb + u];
+    }
+    if (tid == 0) st_dev(partj + g, mypart);
+    if (!grid_barrier(a.bar, P, gen, a.abort_flag)) return;  // p complete
+
+    // ---- K = tau/2 * v^T p, partial sums reduced in a fixed order ----------
+    {
+      double sp = 0.0;
+      for (int q = tid; q < P; q += TNT) sp += ld_dev(partj + q);
+      sp = block_sum<TNT>(sp, &red[0][0]);
+      if (tid == 0) bc[0] = 0.5 * tj * sp;
+      __syncthreads();
+    }
+    const double K = bc[0];
+    double wr[NM];
+#pragma unroll
+    for (int m = 0; m < NM; ++m) {
+      const int64_t l = j + 1 + tid + int64_t(TNT) * m;
+      wr[m] = (l < k) ? ld_dev(pj + l) - K * vr[m] : 0.0;
+    }
+    // ---- rank-2 update; the next reflector's row goes first ----------------
+    auto update_row = [&](int q) {
+      double* row = row_ptr(q);
+      const double vi = vown[q];
+      const double wi = pown[q] - K * vi;
+#pragma unroll
+      for (int m = 0; m < NM; ++m) {
+        const int64_t l = j + 1 + tid + int64_t(TNT) * m;
+        if (l < k) row[l] -= vi * wr[m] + wi * vr[m];
+      }
+    };
+    int qn = -1;
+    if (owns_next) {
+      qn = int((j + 1) / P);
+      update_row(qn);
+      __syncthreads();
+      make_reflector(a, row_ptr(qn), j + 1, &red[0][0]);
+    }
+    for (int q = q0; q < nown; ++q)
+      if (q != qn) update_row(q);
+    __syncthreads();
+  }
+  if (k >= 1 && (k - 1) % P == g) {
+    const double* row = row_ptr(int((k - 1) / P));
+    if (tid == 0) {
+      a.d[k - 1] = row[k - 1];
+      a.tau[k - 1] = 0.0;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // 2. eigenvalues of T by multisection (one wave per eigenvalue)
 // ---------------------------------------------------------------------------
@@ -607,6 +745,7 @@ struct EigPlan {
   int in_lds;
   int rows_max;
   size_t lds_bytes;
+  const void* kern;
 };
 
 int plan_sytrd(int64_t k, EigPlan& pl) {
@@ -627,12 +766,19 @@ int plan_sytrd(int64_t k, EigPlan& pl) {
   const size_t static_lds = 2048;
   pl.in_lds = (need + static_lds <= size_t(maxlds)) ? 1 : 0;
   pl.lds_bytes = pl.in_lds ? need : 0;
-  if (pl.in_lds) {
-    DOPINF_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(sytrd_kernel),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, int(pl.lds_bytes)));
+  pl.kern = reinterpret_cast<const void*>(sytrd_kernel);
+  // rows in LDS plus the owned rows' v_i, p_i: register form for k <= 16 TNT
+  const size_t need_reg = need + 2 * size_t(pl.rows_max) * sizeof(double);
+  if (k <= 16 * TNT && need_reg + static_lds <= size_t(maxlds)) {
+    pl.in_lds = 1;
+    pl.lds_bytes = need_reg;
+    pl.kern = (k <= 8 * TNT) ? reinterpret_cast<const void*>(sytrd_reg_kernel<8>)
+                             : reinterpret_cast<const void*>(sytrd_reg_kernel<16>);
   }
+  if (pl.in_lds)
+    DOPINF_HIP(hipFuncSetAttribute(pl.kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(pl.lds_bytes)));
   int nb = 0;
-  DOPINF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sytrd_kernel, TNT, pl.lds_bytes));
+  DOPINF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pl.kern, TNT, pl.lds_bytes));
   if (nb < 1) return fail(DOPINF_E_HIP, "tridiagonalization kernel cannot be resident");
   return DOPINF_OK;
 }
@@ -721,8 +867,7 @@ extern "C" int dopinf_reduce(void* stream, const double* D, int64_t k, int64_t l
   ta.vflag = w.words + 3;
   ta.abort_flag = reinterpret_cast<int*>(w.words + 1);
   void* args[] = {&ta};
-  DOPINF_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(sytrd_kernel), dim3(pl.P), dim3(TNT), args,
-                                        unsigned(pl.lds_bytes), st));
+  DOPINF_HIP(hipLaunchCooperativeKernel(pl.kern, dim3(pl.P), dim3(TNT), args, unsigned(pl.lds_bytes), st));
   tri_prep_kernel<<<1, 256, 0, st>>>(w.d, w.e, k, w.e2, w.bounds);
   DOPINF_LAUNCHED();
   tri_bisect_kernel<<<unsigned((k + 3) / 4), 256, 0, st>>>(w.d, w.e2, k, w.bounds, lambda);
