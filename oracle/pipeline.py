@@ -8,7 +8,7 @@ from __future__ import annotations
 import numpy as np
 
 __all__ = [
-    "temporal_mean", "variable_scales", "preprocess", "gram", "eig_desc",
+    "temporal_mean", "variable_scales", "apply_statistics", "preprocess", "gram", "eig_desc",
     "fix_signs", "energy_rank", "reduce_basis_free", "qhat_by_projection",
     "quad_features", "quad_pairs", "n_quad", "opinf_data", "regularizer",
     "solve_operators", "split_operators", "rollout", "train_error",
@@ -50,6 +50,14 @@ def variable_scales(Qc, var_rows):
     return s, zero_range
 
 
+def apply_statistics(Q, mu, s_rows):
+    """(Q - mu 1^T) / s, row by row, for given row means mu and per-row scale
+    factors s_rows (each row carries its variable's s_v): the transform of
+    Sec. 3.3 with division, as in its listing."""
+    Q = np.asarray(Q, dtype=np.float64)
+    return (Q - np.asarray(mu, dtype=np.float64)[:, None]) / np.asarray(s_rows, dtype=np.float64)[:, None]
+
+
 def preprocess(Q, var_rows, center=True, scale=True):
     """Step II: returns (mu, s, Qs, zero_range) with Qs = (Q - mu 1^T) / s_v.
 
@@ -62,9 +70,8 @@ def preprocess(Q, var_rows, center=True, scale=True):
         s, zr = variable_scales(Qc, var_rows)
     else:
         s, zr = np.ones(len(var_rows) - 1), []
-    Qs = Qc.copy()
-    for v in range(len(var_rows) - 1):
-        Qs[var_rows[v]:var_rows[v + 1], :] /= s[v]
+    s_rows = np.repeat(s, np.diff(np.asarray(var_rows)))
+    Qs = apply_statistics(Q, mu, s_rows)
     return mu, s, Qs, zr
 
 
