@@ -10,13 +10,18 @@
 // Two passes:
 //  1. pack: one HBM-bound pass applies centering and scaling (in float64,
 //     then rounded), splits into bfloat16 parts where needed, and writes the
-//     parts in a K-blocked layout [row block of 32][column][32 rows], zero
-//     padded.  Every later load of an element (about k/128 times) is then a
-//     plain copy instead of a transform.
+//     parts in a K-blocked layout [row block of 32][column][32 rows].  Inside
+//     a column the 32 values are placed so that the matrix-core fragments
+//     can be read from LDS without bank conflicts: FP32 puts rows g, g+4, ...,
+//     g+28 next to each other (one lane's eight k-steps) and XORs the 16-byte
+//     slot index with column bits 1-3; bfloat16 parts XOR the slot of eight
+//     consecutive rows with column bits 2-3.
 //  2. MFMA: 128 x 128 lower-triangle tiles, split-K over row blocks, 4 waves x
-//     (4 x 4 blocks of 16 x 16), one 32-row block per LDS stage copied from
-//     the packed layout (contiguous 128 x 32 chunks), double buffered;
-//     float32 accumulation over slabs of 512 rows, slabs added into float64
+//     (4 x 4 blocks of 16 x 16).  A row block of a 128-column panel is one
+//     contiguous chunk (16 KB FP32, 8 KB per bfloat16 part) that goes from
+//     HBM straight into LDS by LDS-DMA buffer loads, double buffered (the
+//     loads of block b+1 fly while block b feeds the matrix cores); float32
+//     accumulation over slabs of 512 rows, slabs added into float64
 //     accumulators; split partials summed in float64 by the shared kernel.
 #include "common.hpp"
 #include "gram_plan.hpp"
@@ -35,8 +40,6 @@ constexpr int BT = 128;
 constexpr int NTH = 256;
 constexpr int KB = 32;           // rows per packed block = rows per LDS stage
 constexpr int SLAB_STAGES = 16;  // 512 rows accumulated in float32 before the float64 add
-constexpr int LDC16 = KB + 8;    // LDS column stride (bf16 elements): 80 bytes
-constexpr int LDC32 = KB + 4;    // LDS column stride (floats): 144 bytes
 
 __device__ __forceinline__ unsigned short bf16_rn_bits(float f) {
   unsigned int u = __float_as_uint(f);
@@ -61,6 +64,20 @@ struct PackArgs {
   unsigned short* p2;     // lo (x6)
 };
 
+// Place of row rr of a 32-row block inside column cc of the packed layout.
+// FP32: the four rows {g, g+4, ..., g+28} of k-step lane group g become
+// positions 8g..8g+7; the eight 16-byte slots of the column are XORed with
+// (cc >> 1) & 7.  bfloat16: the four 16-byte slots of eight rows are XORed
+// with (cc >> 2) & 3.  Sixteen consecutive columns reading the same logical
+// slot then hit sixteen different 16-byte bank groups.
+__host__ __device__ inline int pos_f32(int rr, int cc) {
+  const int p = (rr & 3) * 8 + (rr >> 2);
+  return (((p >> 2) ^ ((cc >> 1) & 7)) << 2) | (p & 3);
+}
+__host__ __device__ inline int pos_b16(int rr, int cc) {
+  return (((rr >> 3) ^ ((cc >> 2) & 3)) << 3) | (rr & 7);
+}
+
 // One workgroup packs a 32-row block x 128 columns: reads rows (coalesced),
 // transposes through LDS, writes [col][32] chunks (coalesced).
 __global__ __launch_bounds__(256) void pack_kernel(PackArgs a) {
@@ -82,11 +99,11 @@ __global__ __launch_bounds__(256) void pack_kernel(PackArgs a) {
     tile[rr][cc] = v;
   }
   __syncthreads();
-  // output element (col cc, row rr) at ((blk * kp + c0 + cc) * 32 + rr)
+  // output element (col cc, row rr) at ((blk * kp + c0 + cc) * 32 + pos(rr, cc))
   for (int e = tid; e < KB * BT; e += 256) {
     const int cc = e / KB, rr = e % KB;
     const float x = tile[rr][cc];
-    const size_t o = (size_t(blk) * a.kp + c0 + cc) * KB + rr;
+    const size_t o = (size_t(blk) * a.kp + c0 + cc) * KB + (a.algo == 0 ? pos_f32(rr, cc) : pos_b16(rr, cc));
     if (a.algo == 0) {
       a.pf[o] = x;
     } else {
@@ -115,14 +132,149 @@ struct MmaArgs {
 // f32 16x16 MFMA output layout: lane l, element e -> row 4 (l / 16) + e, column l % 16
 __device__ __forceinline__ int out_row(int lane, int e) { return 4 * (lane >> 4) + e; }
 
-template <int ALGO>
-__global__ __launch_bounds__(NTH, 1) void gram_packed_kernel(MmaArgs g) {
-  constexpr int NPART = ALGO == 0 ? 1 : (ALGO == 1 ? 2 : 3);
-  constexpr size_t F32_STAGE = size_t(2) * BT * LDC32 * sizeof(float);              // A and B panels
-  constexpr size_t B16_STAGE = size_t(2) * NPART * BT * LDC16 * sizeof(unsigned short);
-  constexpr size_t STAGE = ALGO == 0 ? F32_STAGE : B16_STAGE;
-  __shared__ __attribute__((aligned(16))) unsigned char smem[2 * STAGE];
+#define DOPINF_LDS(p) ((__attribute__((address_space(3))) void*)(p))
 
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t span_rsrc(const void* p, int nbytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, nbytes, 0x00020000);
+}
+
+template <int N>
+__device__ __forceinline__ void wait_vmem() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
+
+__device__ __forceinline__ void barrier_only() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+template <int ALGO>
+struct PackedGeom {
+  static constexpr int NPART = ALGO == 0 ? 1 : (ALGO == 1 ? 2 : 3);
+  static constexpr int ELT = ALGO == 0 ? 4 : 2;
+  static constexpr int COLB = KB * ELT;             // bytes of one column of a block
+  static constexpr int PANEL = BT * COLB;           // bytes of one panel part of a block
+  static constexpr int CHUNKS = PANEL / 1024;       // 1 KB LDS-DMA chunks per panel part
+  static constexpr int STAGE = 2 * NPART * PANEL;   // A and B panels, all parts
+};
+
+template <int ALGO, bool DIAG>
+__device__ __forceinline__ void packed_tile(const MmaArgs& g, int64_t b_lo, int64_t nst, int64_t a0, int64_t c0,
+                                            unsigned char* smem, flt4 (&acc)[4][4], double (&acc64)[4][4][4]) {
+  using Gm = PackedGeom<ALGO>;
+  constexpr int NPART = Gm::NPART;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
+  const int wm = w >> 1, wn = w & 1;
+  const uint32_t voff = uint32_t(lane) * 16;
+
+  // chunk q of panel part (part, side) of block blk -> LDS slot
+  auto issue = [&](int64_t st) {
+    unsigned char* S = smem + (st & 1) * Gm::STAGE;
+    const int64_t blk = b_lo + st;
+#pragma unroll
+    for (int part = 0; part < NPART; ++part) {
+      const unsigned char* P = reinterpret_cast<const unsigned char*>(
+          ALGO == 0 ? static_cast<const void*>(g.pf)
+                    : static_cast<const void*>(part == 0 ? g.p0 : (part == 1 ? g.p1 : g.p2)));
+      const unsigned char* rowblk = P + size_t(blk) * size_t(g.kp) * Gm::COLB;
+#pragma unroll
+      for (int side = 0; side < (DIAG ? 1 : 2); ++side) {
+        const int64_t col0 = side == 0 ? a0 : c0;
+        const unsigned char* src = rowblk + size_t(col0) * Gm::COLB;
+        unsigned char* dst = S + (side * NPART + part) * Gm::PANEL;
+        // the wave's share of the panel's chunks
+#pragma unroll
+        for (int q = w; q < Gm::CHUNKS; q += 4) {
+          const __amdgpu_buffer_rsrc_t rs = span_rsrc(src + q * 1024, 1024);
+          __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, DOPINF_LDS(dst + q * 1024), 16, voff, 0, 0, 0);
+        }
+      }
+    }
+  };
+
+  const int cm = lane & 15;
+  const int gq = lane >> 4;
+  if (nst > 0) issue(0);
+  for (int64_t st = 0; st < nst; ++st) {
+    wait_vmem<0>();
+    barrier_only();
+    if (st + 1 < nst) issue(st + 1);
+    const unsigned char* S = smem + (st & 1) * Gm::STAGE;
+    const unsigned char* SA = S;
+    const unsigned char* SB = DIAG ? S : S + NPART * Gm::PANEL;
+    if constexpr (ALGO == 0) {
+      // lane group gq holds rows gq, gq+4, ..., gq+28 of its column in slots 2gq, 2gq+1
+      const int h = (cm >> 1) & 7;
+      const int o0 = 16 * ((2 * gq) ^ h), o1 = 16 * ((2 * gq + 1) ^ h);
+      flt4 af[4][2], bf[4][2];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const unsigned char* colp = SA + (wm * 64 + i * 16 + cm) * Gm::COLB;
+        af[i][0] = *reinterpret_cast<const flt4*>(colp + o0);
+        af[i][1] = *reinterpret_cast<const flt4*>(colp + o1);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const unsigned char* colp = SB + (wn * 64 + j * 16 + cm) * Gm::COLB;
+        bf[j][0] = *reinterpret_cast<const flt4*>(colp + o0);
+        bf[j][1] = *reinterpret_cast<const flt4*>(colp + o1);
+      }
+#pragma unroll
+      for (int kk = 0; kk < KB / 4; ++kk)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][kk >> 2][kk & 3], bf[j][kk >> 2][kk & 3],
+                                                            acc[i][j], 0, 0, 0);
+    } else {
+      const int o = 16 * (gq ^ ((cm >> 2) & 3));
+      bf16x8 a[NPART][4], b[NPART][4];
+#pragma unroll
+      for (int q = 0; q < NPART; ++q) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          a[q][i] = __builtin_bit_cast(
+              bf16x8, *reinterpret_cast<const us8*>(SA + q * Gm::PANEL + (wm * 64 + i * 16 + cm) * Gm::COLB + o));
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          b[q][j] = __builtin_bit_cast(
+              bf16x8, *reinterpret_cast<const us8*>(SB + q * Gm::PANEL + (wn * 64 + j * 16 + cm) * Gm::COLB + o));
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          // smallest products first
+          if constexpr (ALGO == 2) {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2][i], b[0][j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[2][j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[1][j], acc[i][j], 0, 0, 0);
+          }
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[0][j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[1][j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[0][j], acc[i][j], 0, 0, 0);
+        }
+    }
+    if ((st + 1) % SLAB_STAGES == 0 || st + 1 == nst) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) acc64[i][j][e] += static_cast<double>(acc[i][j][e]);
+          acc[i][j] = flt4{0.f, 0.f, 0.f, 0.f};
+        }
+    }
+  }
+}
+
+template <int ALGO>
+__global__ __launch_bounds__(NTH, ALGO == 2 ? 1 : 2) void gram_packed_kernel(MmaArgs g) {
+  __shared__ __attribute__((aligned(16))) unsigned char smem[2 * PackedGeom<ALGO>::STAGE];
   int t, s;
   {
     const int bid = blockIdx.x;
@@ -143,11 +295,6 @@ __global__ __launch_bounds__(NTH, 1) void gram_packed_kernel(MmaArgs g) {
   const int64_t nst = b_hi > b_lo ? b_hi - b_lo : 0;
   const int64_t a0 = int64_t(I) * BT, c0 = int64_t(J) * BT;
 
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int w = tid >> 6;
-  const int wm = w >> 1, wn = w & 1;
-
   flt4 acc[4][4];
   double acc64[4][4][4];
 #pragma unroll
@@ -158,130 +305,14 @@ __global__ __launch_bounds__(NTH, 1) void gram_packed_kernel(MmaArgs g) {
 #pragma unroll
       for (int e = 0; e < 4; ++e) acc64[i][j][e] = 0.0;
     }
+  if (I == J)
+    packed_tile<ALGO, true>(g, b_lo, nst, a0, c0, smem, acc, acc64);
+  else
+    packed_tile<ALGO, false>(g, b_lo, nst, a0, c0, smem, acc, acc64);
 
-  // staging: each panel part is a contiguous chunk of 128 columns x 32 rows;
-  // thread -> (column tid / 2, half of the 32 rows) = 16 bytes per bf16 part
-  // load (or 64 bytes per float32 part)
-  uint4 ra[NPART][4], rb[NPART][4];  // FP32: 4 x 16 B per panel; bf16: 2 x 16 B per part
-  const int scol = tid >> 1;          // 0..127
-  const int shalf = tid & 1;          // rows 0..15 or 16..31
-  auto fetch = [&](int64_t st) {
-    const int64_t blk = b_lo + st;
-#pragma unroll
-    for (int q = 0; q < NPART; ++q) {
-      if constexpr (ALGO == 0) {
-        const float* base = g.pf + (size_t(blk) * g.kp) * KB;
-        const uint4* pa = reinterpret_cast<const uint4*>(base + (a0 + scol) * KB + shalf * 16);
-        const uint4* pb = reinterpret_cast<const uint4*>(base + (c0 + scol) * KB + shalf * 16);
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          ra[q][u] = pa[u];
-          rb[q][u] = pb[u];
-        }
-      } else {
-        const unsigned short* P = q == 0 ? g.p0 : (q == 1 ? g.p1 : g.p2);
-        const unsigned short* base = P + (size_t(blk) * g.kp) * KB;
-        ra[q][0] = *reinterpret_cast<const uint4*>(base + (a0 + scol) * KB + shalf * 8);
-        ra[q][1] = *reinterpret_cast<const uint4*>(base + (a0 + scol) * KB + 16 + shalf * 8);
-        rb[q][0] = *reinterpret_cast<const uint4*>(base + (c0 + scol) * KB + shalf * 8);
-        rb[q][1] = *reinterpret_cast<const uint4*>(base + (c0 + scol) * KB + 16 + shalf * 8);
-      }
-    }
-  };
-  auto stash = [&](int buf) {
-    unsigned char* S = smem + size_t(buf) * STAGE;
-    if constexpr (ALGO == 0) {
-      float* A = reinterpret_cast<float*>(S);
-      float* B = A + BT * LDC32;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        *reinterpret_cast<uint4*>(A + scol * LDC32 + shalf * 16 + 4 * u) = ra[0][u];
-        *reinterpret_cast<uint4*>(B + scol * LDC32 + shalf * 16 + 4 * u) = rb[0][u];
-      }
-    } else {
-      unsigned short* base = reinterpret_cast<unsigned short*>(S);
-#pragma unroll
-      for (int q = 0; q < NPART; ++q) {
-        unsigned short* A = base + size_t(q) * BT * LDC16;
-        unsigned short* B = base + size_t(NPART + q) * BT * LDC16;
-        *reinterpret_cast<uint4*>(A + scol * LDC16 + shalf * 8) = ra[q][0];
-        *reinterpret_cast<uint4*>(A + scol * LDC16 + 16 + shalf * 8) = ra[q][1];
-        *reinterpret_cast<uint4*>(B + scol * LDC16 + shalf * 8) = rb[q][0];
-        *reinterpret_cast<uint4*>(B + scol * LDC16 + 16 + shalf * 8) = rb[q][1];
-      }
-    }
-  };
-
-  if (nst > 0) {
-    fetch(0);
-    stash(0);
-  }
-  __syncthreads();
-  for (int64_t st = 0; st < nst; ++st) {
-    const int buf = int(st & 1);
-    if (st + 1 < nst) fetch(st + 1);
-    const unsigned char* S = smem + size_t(buf) * STAGE;
-    const int cm = lane & 15;
-    if constexpr (ALGO == 0) {
-      const float* A = reinterpret_cast<const float*>(S);
-      const float* B = A + BT * LDC32;
-#pragma unroll
-      for (int kk = 0; kk < KB / 4; ++kk) {
-        const int krow = kk * 4 + (lane >> 4);
-        float af[4], bf[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) af[i] = A[(wm * 64 + i * 16 + cm) * LDC32 + krow];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) bf[j] = B[(wn * 64 + j * 16 + cm) * LDC32 + krow];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bf[j], acc[i][j], 0, 0, 0);
-      }
-    } else {
-      const unsigned short* base = reinterpret_cast<const unsigned short*>(S);
-      const int kq = (lane >> 4) * 8;
-      bf16x8 a[NPART][4], b[NPART][4];
-#pragma unroll
-      for (int q = 0; q < NPART; ++q) {
-        const unsigned short* A = base + size_t(q) * BT * LDC16;
-        const unsigned short* B = base + size_t(NPART + q) * BT * LDC16;
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-          a[q][i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const us8*>(A + (wm * 64 + i * 16 + cm) * LDC16 + kq));
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-          b[q][j] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const us8*>(B + (wn * 64 + j * 16 + cm) * LDC16 + kq));
-      }
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          // smallest products first
-          if constexpr (ALGO == 2) {
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2][i], b[0][j], acc[i][j], 0, 0, 0);
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[2][j], acc[i][j], 0, 0, 0);
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[1][j], acc[i][j], 0, 0, 0);
-          }
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[0][j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[1][j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[0][j], acc[i][j], 0, 0, 0);
-        }
-    }
-    if (st + 1 < nst) stash(buf ^ 1);
-    if ((st + 1) % SLAB_STAGES == 0 || st + 1 == nst) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-#pragma unroll
-          for (int e = 0; e < 4; ++e) acc64[i][j][e] += static_cast<double>(acc[i][j][e]);
-          acc[i][j] = flt4{0.f, 0.f, 0.f, 0.f};
-        }
-    }
-    __syncthreads();
-  }
-
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int wm = w >> 1, wn = w & 1;
   double* out = g.part + (size_t(s) * g.ntiles + t) * (BT * BT);
 #pragma unroll
   for (int i = 0; i < 4; ++i)
