@@ -16,7 +16,7 @@
 //                         gradients register-blocked from LDS tiles), Adam.
 //  * grad_kernel          one forward/backward over a batch (gradient checks)
 //  * eval_kernel          g(x) for a batch of states and max ||g||
-//  * closure_rollout_kernel  16 rollouts per workgroup: MLP and ROM per step,
+//  * closure_rollout_kernel  4 rollouts per workgroup: MLP and ROM per step,
 //                         latched fallback to the plain ROM when ||g|| exceeds
 //                         the threshold, growth / error / finiteness scores.
 #include "common.hpp"
@@ -30,6 +30,10 @@ constexpr int BMAX = 256;    // largest minibatch
 constexpr int RG = 16;       // rollouts (or eval rows) per workgroup
 constexpr int ET = 256;      // eval / rollout threads
 constexpr int BT = 16;       // minibatch rows per LDS tile in the backward pass
+
+typedef float flt4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short us8 __attribute__((ext_vector_type(8)));
 
 __host__ __device__ inline int64_t nquad(int64_t r) { return r * (r + 1) / 2; }
 __host__ __device__ inline int64_t ncols(int64_t r) { return r + nquad(r) + 1; }
@@ -499,40 +503,108 @@ struct CRollArgs {
   int* fallback_at;
 };
 
-__global__ __launch_bounds__(ET) void closure_rollout_kernel(CRollArgs a) {
-  extern __shared__ unsigned char smem[];
+// ---- closure rollouts ------------------------------------------------------
+// CR (4, or 2 when the operator streams) states per workgroup of CT threads
+// (8 waves).  The MLP runs on the matrix
+// cores (v_mfma_f32_16x16x32_bf16, the CR states padded to 16 rows): the bf16
+// weights sit in LDS row-major with rows padded by 8 elements so that the 16
+// lanes reading one operand column hit 16 different bank groups; activations
+// are rounded to bf16 exactly where the trainer rounds them.  The features
+// [q | quad(q) | 1 | 0...] of the CR states sit in LDS; wave w owns ROM rows
+// w, w+8, ..., and, when RES is set (r <= 40, d <= 1024), keeps them in
+// registers for the whole rollout, so the operator is read once; otherwise
+// its rows stream from L2, coalesced.
+constexpr int CR_RES = 4;      // states per workgroup when the operator is resident (r <= 40)
+constexpr int CR_STREAM = 2;   // states per workgroup otherwise (LDS holds their features)
+constexpr int CT = 512;        // threads per workgroup
+constexpr int CW = CT / 64;    // waves
+constexpr int RES_ROWS = 5;    // rows per wave kept in registers (r <= 40)
+constexpr int RES_NJ = 16;     // columns per lane kept in registers (d <= 1024)
+constexpr int MPAD = 8;        // bf16 padding per LDS row of an MFMA operand
+
+struct RollLds {  // byte offsets into the rollout kernel's LDS
+  int r, rp, rp16, p1, p2;    // K of layer 1 padded to 32, N of layer 3 padded to 16, row pitches
+  int64_t dpad;
+  size_t w1, w2, w3, xa, a1a, a2a, F, q, qn, mean, stat, gout, flag, qi, total;
+  __host__ __device__ RollLds(int rr, int CR) {
+    r = rr;
+    rp = int(round_up(size_t(r), 32));
+    rp16 = int(round_up(size_t(r), 16));
+    p1 = rp + MPAD;
+    p2 = H + MPAD;
+    dpad = int64_t(round_up(size_t(ncols(r)), 64));
+    size_t o = 0;
+    w1 = o; o += round_up(size_t(H) * p1 * 2, 16);        // W1 [H][p1]
+    w2 = o; o += round_up(size_t(H) * p2 * 2, 16);        // W2 [H][p2]
+    w3 = o; o += round_up(size_t(rp16) * p2 * 2, 16);     // W3 [rp16][p2]
+    xa = o; o += round_up(size_t(16) * p1 * 2, 16);       // x  [16][p1]
+    a1a = o; o += round_up(size_t(16) * p2 * 2, 16);      // a1 [16][p2]
+    a2a = o; o += round_up(size_t(16) * p2 * 2, 16);      // a2 [16][p2]
+    F = o; o += size_t(CR) * dpad * 8;
+    q = o; o += size_t(CR) * r * 8;
+    qn = o; o += size_t(CR) * r * 8;
+    mean = o; o += size_t(r) * 8;
+    stat = o; o += size_t(CR) * 2 * 8;
+    gout = o; o += round_up(size_t(CR) * r * 4, 16);
+    flag = o; o += size_t(CR) * 2 * 4;
+    qi = o; o += size_t(2) * nquad(r) * 2;
+    total = round_up(o, 16) + 64;
+  }
+};
+
+// One 16x16 output block of a 16-row layer: C = A (16 x K) . W^T, with W
+// row-major [N][pitch] and A row-major [16][pitch], K a multiple of 32.
+__device__ __forceinline__ flt4 mlp_block(const unsigned short* A, int pa, const unsigned short* W, int pw, int n0,
+                                          int K, int lane) {
+  flt4 c = {0.f, 0.f, 0.f, 0.f};
+  const int m = lane & 15, kq = (lane >> 4) * 8;
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    const bf16x8 av = __builtin_bit_cast(bf16x8, *reinterpret_cast<const us8*>(A + m * pa + k0 + kq));
+    const bf16x8 bv = __builtin_bit_cast(bf16x8, *reinterpret_cast<const us8*>(W + (n0 + m) * pw + k0 + kq));
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c, 0, 0, 0);
+  }
+  return c;  // lane l, element e: row 4 (l / 16) + e, column n0 + l % 16
+}
+
+template <bool RES>
+__global__ __launch_bounds__(CT) void closure_rollout_kernel(CRollArgs a) {
+  constexpr int CR = RES ? CR_RES : CR_STREAM;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int r = a.r;
   const Off o(r);
+  const RollLds L(r, CR);
   const int64_t s = nquad(r), d = ncols(r);
-  const int tid = threadIdx.x;
-  unsigned short* Wb = reinterpret_cast<unsigned short*>(smem);
-  unsigned char* cur = smem + round_up(size_t(o.P - 2 * H - r) * 2, 16);
-  float* x = reinterpret_cast<float*>(cur);
-  cur += round_up(size_t(RG) * r * 4, 16);
-  float* a1 = reinterpret_cast<float*>(cur);
-  cur += size_t(RG) * H * 4;
-  float* a2 = reinterpret_cast<float*>(cur);
-  cur += size_t(RG) * H * 4;
-  float* out = reinterpret_cast<float*>(cur);
-  cur += round_up(size_t(RG) * r * 4, 16);
-  double* q = reinterpret_cast<double*>(cur);
-  cur += size_t(RG) * r * 8;
-  double* qn = reinterpret_cast<double*>(cur);
-  cur += size_t(RG) * r * 8;
-  double* mean = reinterpret_cast<double*>(cur);
-  cur += size_t(r) * 8;
-  double* stat = reinterpret_cast<double*>(cur);  // per rollout: err2max, devmax, gnorm
-  cur += size_t(RG) * 3 * 8;
-  int* flag = reinterpret_cast<int*>(cur);  // per rollout: latched step (-1), state (0 live, 1 nonfinite)
-  cur += size_t(RG) * 2 * 4;
-  unsigned short* qi = reinterpret_cast<unsigned short*>(cur);
+  const int64_t dpad = L.dpad;
+  const int NJ = int(dpad / 64);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  unsigned short* W1 = reinterpret_cast<unsigned short*>(smem + L.w1);
+  unsigned short* W2 = reinterpret_cast<unsigned short*>(smem + L.w2);
+  unsigned short* W3 = reinterpret_cast<unsigned short*>(smem + L.w3);
+  unsigned short* XA = reinterpret_cast<unsigned short*>(smem + L.xa);
+  unsigned short* A1 = reinterpret_cast<unsigned short*>(smem + L.a1a);
+  unsigned short* A2 = reinterpret_cast<unsigned short*>(smem + L.a2a);
+  double* F = reinterpret_cast<double*>(smem + L.F);
+  double* q = reinterpret_cast<double*>(smem + L.q);
+  double* qn = reinterpret_cast<double*>(smem + L.qn);
+  double* mean = reinterpret_cast<double*>(smem + L.mean);
+  double* stat = reinterpret_cast<double*>(smem + L.stat);  // per state: err2max, devmax
+  float* gout = reinterpret_cast<float*>(smem + L.gout);
+  int* flag = reinterpret_cast<int*>(smem + L.flag);         // per state: latched step (-1), non-finite (0/1)
+  unsigned short* qi = reinterpret_cast<unsigned short*>(smem + L.qi);
   unsigned short* qj = qi + s;
 
-  const int64_t m0 = int64_t(blockIdx.x) * RG;
-  const int R = int(min<int64_t>(RG, a.M - m0));
+  const int64_t m0 = int64_t(blockIdx.x) * CR;
+  const int R = int(min<int64_t>(CR, a.M - m0));
   const bool use_g = a.threshold > 0.0;
-  if (use_g) load_wb(a.p, r, Wb, tid, ET);
-  for (int64_t c = tid; c < s; c += ET) {
+  // zero everything the MLP reads (padding rows and columns stay zero), then the weights
+  for (size_t e = tid; e < (L.F - L.w1) / 2; e += CT) W1[e] = 0;
+  __syncthreads();
+  if (use_g) {
+    for (int64_t e = tid; e < int64_t(H) * r; e += CT) W1[(e / r) * L.p1 + e % r] = bf16_bits(a.p[o.w1 + e]);
+    for (int64_t e = tid; e < int64_t(H) * H; e += CT) W2[(e / H) * L.p2 + e % H] = bf16_bits(a.p[o.w2 + e]);
+    for (int64_t e = tid; e < int64_t(r) * H; e += CT) W3[(e / H) * L.p2 + e % H] = bf16_bits(a.p[o.w3 + e]);
+  }
+  for (int64_t c = tid; c < s; c += CT) {
     int ii = 0;
     int64_t off = 0;
     while (off + (r - ii) <= c) {
@@ -542,89 +614,162 @@ __global__ __launch_bounds__(ET) void closure_rollout_kernel(CRollArgs a) {
     qi[c] = static_cast<unsigned short>(ii);
     qj[c] = static_cast<unsigned short>(ii + (c - off));
   }
-  for (int e = tid; e < RG * r; e += ET) q[e] = (e / r < R) ? a.q0[(m0 + e / r) * r + e % r] : 0.0;
-  for (int i = tid; i < r; i += ET) mean[i] = a.mean[i];
-  for (int b = tid; b < RG; b += ET) {
-    stat[b * 3 + 0] = 0.0;
-    stat[b * 3 + 1] = 0.0;
+  for (int64_t e = tid; e < int64_t(CR) * dpad; e += CT) F[e] = 0.0;
+  for (int e = tid; e < CR * r; e += CT) q[e] = (e / r < R) ? a.q0[(m0 + e / r) * r + e % r] : 0.0;
+  for (int i = tid; i < r; i += CT) mean[i] = a.mean[i];
+  for (int b = tid; b < CR; b += CT) {
+    stat[b * 2 + 0] = 0.0;
+    stat[b * 2 + 1] = 0.0;
     flag[b * 2 + 0] = -1;
     flag[b * 2 + 1] = 0;
+  }
+  // resident operator rows: wave w owns rows w + 8u
+  double orow[RES ? RES_ROWS : 1][RES ? RES_NJ : 1];
+  if constexpr (RES) {
+#pragma unroll
+    for (int u = 0; u < RES_ROWS; ++u)
+#pragma unroll
+      for (int j = 0; j < RES_NJ; ++j) {
+        const int i = w + CW * u;
+        const int64_t c = lane + 64 * j;
+        orow[u][j] = (i < r && c < d) ? a.O[int64_t(i) * d + c] : 0.0;
+      }
   }
   __syncthreads();
   double maxdev = 0.0;
   for (int i = 0; i < r; ++i) maxdev = fmax(maxdev, a.maxdev[i]);
 
+  // reference snapshot of the state being scored (lane i < r), one step ahead
+  double href = (lane < r && 0 < a.k_ref) ? a.Qref[int64_t(lane) * a.ldref] : 0.0;
   for (int t = 0; t < a.n_states; ++t) {
-    // ---- score state t (one wave per rollout) ----
-    for (int b = tid / 64; b < R; b += ET / 64) {
-      const int lane = tid % 64;
+    // ---- score state t: one wave per state (r <= 64: one mode per lane) ----
+    if (w < R) {
+      const int b = w;
       double e2 = 0.0, n2 = 0.0, dv = 0.0, bad = 0.0;
-      for (int i = lane; i < r; i += 64) {
-        const double xv = q[b * r + i];
+      if (lane < r) {
+        const double xv = q[b * r + lane];
         if (!isfinite(xv)) bad = 1.0;
-        dv = fmax(dv, fabs(xv - mean[i]));
+        dv = fabs(xv - mean[lane]);
         if (t < a.k_ref) {
-          const double h = a.Qref[int64_t(i) * a.ldref + t];
-          e2 += (xv - h) * (xv - h);
-          n2 += h * h;
+          e2 = (xv - href) * (xv - href);
+          n2 = href * href;
         }
-        if (a.traj) a.traj[((m0 + b) * a.n_states + t) * r + i] = xv;
+        if (a.traj) a.traj[((m0 + b) * a.n_states + t) * r + lane] = xv;
       }
-      e2 = wave_sum(e2);
-      n2 = wave_sum(n2);
-      dv = wave_max(dv);
-      bad = wave_max(bad);
+      e2 = wave_sum_dpp(e2);
+      n2 = wave_sum_dpp(n2);
+      dv = wave_max_dpp(dv);
+      bad = wave_max_dpp(bad);
       if (lane == 0) {
         if (bad != 0.0) flag[b * 2 + 1] = 1;
-        stat[b * 3 + 1] = fmax(stat[b * 3 + 1], dv);
-        if (t < a.k_ref) stat[b * 3 + 0] = fmax(stat[b * 3 + 0], e2 / n2);
+        stat[b * 2 + 1] = fmax(stat[b * 2 + 1], dv);
+        if (t < a.k_ref) stat[b * 2 + 0] = fmax(stat[b * 2 + 0], e2 / n2);
       }
     }
-    __syncthreads();
     if (t + 1 == a.n_states) break;
-    // ---- closure g(q_t) on the RG states ----
-    if (use_g) {
-      for (int e = tid; e < RG * r; e += ET) {
-        const int i = e % r;
-        const double xv = q[e];
-        x[e] = bf16f(static_cast<float>((isfinite(xv) ? xv : 0.0) - a.norm[i]) / static_cast<float>(a.norm[r + i]));
-      }
-      __syncthreads();
-      mlp_fwd<ET>(RG, r, Wb, a.p, x, nullptr, a1, nullptr, a2, out, tid);
-      for (int b = tid / 64; b < R; b += ET / 64) {
-        double n2 = 0.0;
-        for (int i = tid % 64; i < r; i += 64) {
-          const double g = double(out[b * r + i]) * a.norm[3 * r + i] + a.norm[2 * r + i];
-          n2 += g * g;
-        }
-        n2 = wave_sum(n2);
-        if (tid % 64 == 0) {
-          stat[b * 3 + 2] = sqrt(n2);
-          if (flag[b * 2] < 0 && !(sqrt(n2) <= a.threshold)) flag[b * 2] = t;  // latch
-        }
-      }
-      __syncthreads();
+    href = (lane < r && t + 1 < a.k_ref) ? a.Qref[int64_t(lane) * a.ldref + t + 1] : 0.0;
+    // ---- features of the CR states ----
+    for (int e = tid; e < CR * r; e += CT) F[(e / r) * dpad + e % r] = q[e];
+    for (int64_t e = tid; e < int64_t(CR) * s; e += CT) {
+      const int b = int(e / s);
+      const int64_t c = e % s;
+      F[b * dpad + r + c] = q[b * r + qi[c]] * q[b * r + qj[c]];
     }
-    // ---- ROM step: qn[b][i] = O[i, :] . [q_b | quad(q_b) | 1] ----
-    for (int e = tid; e < R * r; e += ET) {
-      const int b = e / r, i = e % r;
-      const double* qb = q + b * r;
-      const double* Oi = a.O + int64_t(i) * d;
-      double acc = Oi[d - 1];
-      for (int c = 0; c < r; ++c) acc += Oi[c] * qb[c];
-      for (int64_t c = 0; c < s; ++c) acc += Oi[r + c] * (qb[qi[c]] * qb[qj[c]]);
-      if (use_g && flag[b * 2] < 0) acc += double(out[e]) * a.norm[3 * r + i] + a.norm[2 * r + i];
-      qn[e] = acc;
+    if (tid < CR) F[tid * dpad + d - 1] = 1.0;
+    // ---- closure g(q_t) on the matrix cores ----
+    if (use_g) {
+      for (int e = tid; e < CR * r; e += CT) {
+        const int b = e / r, i = e % r;
+        const double xv = q[e];
+        XA[b * L.p1 + i] =
+            bf16_bits(static_cast<float>((isfinite(xv) ? xv : 0.0) - a.norm[i]) / static_cast<float>(a.norm[r + i]));
+      }
+      __syncthreads();
+      {  // layer 1: wave w -> hidden units 16w .. 16w+15
+        const flt4 c = mlp_block(XA, L.p1, W1, L.p1, 16 * w, L.rp, lane);
+        if (lane < 16)
+#pragma unroll
+          for (int e = 0; e < CR; ++e) A1[e * L.p2 + 16 * w + lane] = bf16_bits(gelu_f(c[e] + a.p[o.b1 + 16 * w + lane]));
+      }
+      __syncthreads();
+      {  // layer 2
+        const flt4 c = mlp_block(A1, L.p2, W2, L.p2, 16 * w, H, lane);
+        if (lane < 16)
+#pragma unroll
+          for (int e = 0; e < CR; ++e) A2[e * L.p2 + 16 * w + lane] = bf16_bits(gelu_f(c[e] + a.p[o.b2 + 16 * w + lane]));
+      }
+      __syncthreads();
+      if (16 * w < r) {  // layer 3: wave w -> outputs 16w .. 16w+15
+        const flt4 c = mlp_block(A2, L.p2, W3, L.p2, 16 * w, H, lane);
+        const int i = 16 * w + lane;
+        if (lane < 16 && i < r)
+#pragma unroll
+          for (int e = 0; e < CR; ++e) gout[e * r + i] = c[e] + a.p[o.b3 + i];
+      }
+      __syncthreads();
+      if (w < R) {
+        const int b = w;
+        double n2 = 0.0;
+        if (lane < r) {
+          const double g = double(gout[b * r + lane]) * a.norm[3 * r + lane] + a.norm[2 * r + lane];
+          n2 = g * g;
+        }
+        n2 = wave_sum_dpp(n2);
+        if (lane == 0 && flag[b * 2] < 0 && !(sqrt(n2) <= a.threshold)) flag[b * 2] = t;  // latch
+      }
     }
     __syncthreads();
-    for (int e = tid; e < R * r; e += ET) q[e] = qn[e];
+    // ---- ROM step: qn[b][i] = O[i, :] . F[b] (+ g) ----
+    auto finish = [&](double acc, int b, int i) {
+      acc = wave_sum_dpp(acc);
+      if (lane == 0) {
+        if (use_g && flag[b * 2] < 0) acc += double(gout[b * r + i]) * a.norm[3 * r + i] + a.norm[2 * r + i];
+        qn[b * r + i] = acc;
+      }
+    };
+    if constexpr (RES) {
+      // fully unrolled so the resident rows stay in registers; each feature
+      // value is read once and feeds the wave's rows
+#pragma unroll
+      for (int b = 0; b < CR; ++b) {
+        double acc[RES_ROWS];
+#pragma unroll
+        for (int u = 0; u < RES_ROWS; ++u) acc[u] = 0.0;
+#pragma unroll
+        for (int j = 0; j < RES_NJ; ++j)
+          if (j < NJ) {  // stay inside row b of F
+            const double fv = F[b * dpad + lane + 64 * j];
+#pragma unroll
+            for (int u = 0; u < RES_ROWS; ++u) acc[u] += orow[u][j] * fv;
+          }
+#pragma unroll
+        for (int u = 0; u < RES_ROWS; ++u)
+          if (w + CW * u < r) finish(acc[u], b, w + CW * u);  // wave-uniform
+      }
+    } else {
+      for (int u = 0; u < (r + CW - 1) / CW; ++u) {
+        const int i = w + CW * u;
+        if (i >= r) break;  // wave-uniform
+#pragma unroll
+        for (int b = 0; b < CR; ++b) {
+          double acc = 0.0;
+          for (int j = 0; j < NJ; ++j) {
+            const int64_t c = lane + 64 * j;
+            if (c < d) acc += a.O[int64_t(i) * d + c] * F[b * dpad + c];
+          }
+          finish(acc, b, i);
+        }
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < CR * r; e += CT) q[e] = qn[e];
     __syncthreads();
   }
-  for (int b = tid; b < R; b += ET) {
+  for (int b = tid; b < R; b += CT) {
     const int64_t m = m0 + b;
     const bool nonfinite = flag[b * 2 + 1] != 0;
-    const double gr = stat[b * 3 + 1] / maxdev;
-    a.err[m] = nonfinite ? NAN : sqrt(stat[b * 3 + 0]);
+    const double gr = stat[b * 2 + 1] / maxdev;
+    a.err[m] = nonfinite ? NAN : sqrt(stat[b * 2 + 0]);
     a.growth[m] = nonfinite ? NAN : gr;
     a.outcome[m] = nonfinite ? DOPINF_ITEM_NONFINITE : (gr < a.max_growth ? DOPINF_ITEM_PASS : DOPINF_ITEM_GROWTH);
     a.fallback_at[m] = flag[b * 2];
@@ -655,10 +800,7 @@ __global__ __launch_bounds__(256) void ref_stats_kernel(const double* __restrict
 size_t wb_bytes(int r) { return round_up(size_t(Off(r).P - 2 * H - r) * 2, 16); }
 size_t train_lds(int r) { return wb_bytes(r) + size_t(BT) * (4 * H + 128 + r) * 4; }
 size_t eval_lds(int r) { return wb_bytes(r) + round_up(size_t(RG) * r * 4, 16) + size_t(RG) * 2 * H * 4 + round_up(size_t(RG) * r * 4, 16); }
-size_t roll_lds(int r) {
-  return eval_lds(r) + size_t(RG) * r * 8 * 2 + size_t(r) * 8 + size_t(RG) * 3 * 8 + size_t(RG) * 2 * 4 +
-         size_t(nquad(r)) * 4 + 64;
-}
+size_t roll_lds(int r, bool res) { return RollLds(r, res ? CR_RES : CR_STREAM).total; }
 
 Scratch carve_scratch(Carver& c, int r) {
   Scratch s;
@@ -814,7 +956,10 @@ extern "C" int dopinf_closure_rollout(void* stream, int r, const double* O, cons
   DOPINF_REQUIRE(r >= 1 && r <= 64 && M >= 1 && n_states >= 1 && k_ref >= 1 && ldref >= k_ref && max_growth > 0,
                  "invalid sizes");
   if (!ws || ws_bytes < dopinf_closure_rollout_workspace(r)) return fail(DOPINF_E_WORKSPACE, "workspace too small");
-  int rc = set_lds(reinterpret_cast<const void*>(closure_rollout_kernel), roll_lds(r));
+  const bool res = (r <= CW * RES_ROWS) && (ncols(r) <= 64 * RES_NJ);
+  const void* kern = res ? reinterpret_cast<const void*>(closure_rollout_kernel<true>)
+                         : reinterpret_cast<const void*>(closure_rollout_kernel<false>);
+  int rc = set_lds(kern, roll_lds(r, res));
   if (rc) return rc;
   hipStream_t st = static_cast<hipStream_t>(stream);
   double* mean = static_cast<double*>(ws);
@@ -841,7 +986,10 @@ extern "C" int dopinf_closure_rollout(void* stream, int r, const double* O, cons
   a.growth = growth;
   a.outcome = outcome;
   a.fallback_at = fallback_at;
-  closure_rollout_kernel<<<unsigned((M + RG - 1) / RG), ET, roll_lds(r), st>>>(a);
+  if (res)
+    closure_rollout_kernel<true><<<unsigned((M + CR_RES - 1) / CR_RES), CT, roll_lds(r, true), st>>>(a);
+  else
+    closure_rollout_kernel<false><<<unsigned((M + CR_STREAM - 1) / CR_STREAM), CT, roll_lds(r, false), st>>>(a);
   DOPINF_LAUNCHED();
   return DOPINF_OK;
 }

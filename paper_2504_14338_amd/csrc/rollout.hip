@@ -388,7 +388,7 @@ __global__ __launch_bounds__(TNT) void rollout_team_kernel(TeamArgs ta) {
     double acc = 0.0;
 #pragma unroll
     for (int j = 0; j < TNJ; ++j) acc += o[j] * f[lane + 64 * j];
-    acc = wave_sum(acc);
+    acc = wave_sum_dpp(acc);
     double* slot = xb + ((t + 1) & 1) * r;
     if (lane == 0 && row < r) xwg::st_dev(slot + row, acc);
     // next training snapshot, in flight during the barrier

@@ -137,3 +137,33 @@ def test_training_learns_a_smooth_correction(gpu_lib, rom10):
     res_plain = float(torch.sqrt(torch.mean(Y * Y)).item())
     res_closed = float(torch.sqrt(torch.mean((Y - G) ** 2)).item())
     assert res_closed < 0.5 * res_plain
+
+
+def test_closure_rollout_streamed_operator_r48(gpu_lib):
+    # r = 48 > 40: the operator rows stream from L2 and a workgroup holds two
+    # states; plain rollouts match the oracle's, the closure's first steps
+    # match the oracle's closure rollout
+    import torch
+    dp = gpu_lib
+    r = 48
+    rng = np.random.default_rng(48)
+    s = r * (r + 1) // 2
+    A = np.diag(rng.uniform(0.90, 0.99, r)) + 1e-3 * rng.standard_normal((r, r))
+    Og = np.hstack([A, 1e-4 * rng.standard_normal((r, s)), 1e-3 * rng.standard_normal((r, 1))])
+    q0 = rng.standard_normal((5, r))
+    Qref = orc.rollout(Og, r, q0[0], 50)
+    O = dev(Og)
+    p = torch.from_numpy(synth.mlp_init(r, seed=6)).cuda()
+    normh = (np.zeros(r), np.ones(r), np.zeros(r), np.ones(r))
+    norm = dev(np.concatenate(normh))
+    out = dp.closure_rollout(O, p, norm, 0.0, dev(q0), 50, dev(Qref), keep_traj=True)
+    for m in range(5):
+        ref = orc.rollout(Og, r, q0[m], 50)
+        tr = out["traj"][m].cpu().numpy().T
+        assert np.max(np.abs(tr - ref)) <= 1e-10 * np.max(np.abs(ref))
+    out2 = dp.closure_rollout(O, p, norm, 1e9, dev(q0), 6, dev(Qref), keep_traj=True)
+    ph = p.cpu().numpy().astype(np.float64)
+    for m in range(5):
+        ref, lat = cl.closure_rollout(Og, r, ph, normh, 1e9, q0[m], 6)
+        assert lat == -1
+        assert rel(out2["traj"][m].cpu().numpy().T, ref) <= 1e-4
