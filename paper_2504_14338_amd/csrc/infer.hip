@@ -275,110 +275,137 @@ __global__ __launch_bounds__(256) void syrk_update_kernel(double* __restrict__ A
 }
 
 // ---------------------------------------------------------------------------
-// triangular solves with the factored L (row-major lower, ld n) and its
-// diagonal-block inverses, right-looking: one launch per 64-row block J.
-// Forward (L X = B):   Y_J = Linv_JJ X_J, then X_T -= L_TJ Y_J for T > J.
-// Backward (L^T X = B): Y_J = Linv_JJ^T X_J, then X_T -= L_JT^T Y_J, T < J.
-// X (n x w, ld w) holds the right-hand sides and is consumed; Y_J goes to Yout.
-// Workgroup = (row tile T or the diagonal block, 32 columns, item).
+// Triangular solves with the factored L (row-major lower, ld n) and its
+// diagonal-block inverses, right-looking, per 64-row block J:
+//   forward  (L Y = X):   Y_J = Linv_J X_J,    then X_T -= L_TJ Y_J   (T > J)
+//   backward (L^T Y = X): Y_J = Linv_J^T X_J,  then X_T -= L_JT^T Y_J (T < J)
+// X (n x w, ld w) holds the right-hand sides and is consumed; Y_J goes to
+// Yout.  Both steps are 64 x 64 x 64 products on FP64 MFMA tiles with A and
+// B staged in LDS: the diagonal solve once per (item, 64 columns), the update
+// once per (coupled block row, 64 columns, item).
 // ---------------------------------------------------------------------------
+constexpr int TP = NB + 2;  // LDS pitch of the solve tiles
+
+// acc += A . B for the wave's 32 x 32 quarter (2 x 2 blocks of 16 x 16)
+__device__ __forceinline__ void tile_mma64(const double (*A)[TP], const double (*B)[TP], dbl4 (&acc)[2][2], int lane,
+                                           int wm, int wn) {
+#pragma unroll 4
+  for (int kk = 0; kk < NB / 4; ++kk) {
+    const int p = kk * 4 + (lane >> 4);
+    double af[2], bf[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) af[i] = A[wm * 32 + i * 16 + (lane & 15)][p];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) bf[j] = B[p][wn * 32 + j * 16 + (lane & 15)];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+  }
+}
+
+// stage rows [r0, r0+64) x columns [c0, c0+64) of an n x w row-major matrix (zero outside)
+__device__ __forceinline__ void stage_rhs(double (*B)[TP], const double* __restrict__ X, int64_t n, int64_t w,
+                                          int64_t r0, int64_t c0) {
+  for (int e = threadIdx.x; e < NB * NB; e += 256) {
+    const int a = e / NB, c = e % NB;
+    B[a][c] = (r0 + a < n && c0 + c < w) ? X[(r0 + a) * w + c0 + c] : 0.0;
+  }
+}
+
 template <bool TRANS>
-__global__ __launch_bounds__(256) void trsm_step_kernel(const double* __restrict__ L, int64_t n,
-                                                        const double* __restrict__ Linv, double* __restrict__ X,
-                                                        double* __restrict__ Yout, int64_t w, int64_t J) {
-  __shared__ double Li[NB][NB + 1];
-  __shared__ double Yb[NB][33];
-  __shared__ double Lt[NB][NB + 1];
+__global__ __launch_bounds__(256) void trsm_diag_kernel(const double* __restrict__ Linv, int64_t n,
+                                                        const double* __restrict__ X, double* __restrict__ Y,
+                                                        int64_t w, int64_t J) {
+  __shared__ double A[NB][TP];
+  __shared__ double B[NB][TP];
+  const int u = blockIdx.y;
+  const int64_t nblk = (n + NB - 1) / NB;
+  const double* Li = Linv + (size_t(u) * nblk + J) * NB * NB;
+  const double* Xu = X + size_t(u) * n * w;
+  double* Yu = Y + size_t(u) * n * w;
+  const int64_t c0 = int64_t(blockIdx.x) * NB, jb = J * NB;
+  for (int e = threadIdx.x; e < NB * NB; e += 256) {
+    const int a = e / NB, b = e % NB;
+    A[a][b] = TRANS ? Li[b * NB + a] : Li[a * NB + b];
+  }
+  stage_rhs(B, Xu, n, w, jb, c0);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, wm = wv >> 1, wn = wv & 1;
+  dbl4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+  tile_mma64(A, B, acc, lane, wm, wn);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t row = jb + wm * 32 + i * 16 + (lane >> 4) + 4 * e;  // MFMA f64 output layout
+        const int64_t col = c0 + wn * 32 + j * 16 + (lane & 15);
+        if (row < n && col < w) Yu[row * w + col] = acc[i][j][e];
+      }
+}
+
+template <bool TRANS>
+__global__ __launch_bounds__(256) void trsm_update_kernel(const double* __restrict__ L, int64_t n,
+                                                          double* __restrict__ X, const double* __restrict__ Y,
+                                                          int64_t w, int64_t J) {
+  __shared__ double A[NB][TP];
+  __shared__ double B[NB][TP];
   const int u = blockIdx.z;
   const double* Lu = L + size_t(u) * n * n;
-  const int64_t nblk = (n + NB - 1) / NB;
-  const double* Liu = Linv + (size_t(u) * nblk + J) * NB * NB;
   double* Xu = X + size_t(u) * n * w;
-  double* Yu = Yout + size_t(u) * n * w;
-  const int64_t c0 = int64_t(blockIdx.y) * 32;
-  const int il = threadIdx.x >> 2;       // row within a 64-row block
-  const int cs = (threadIdx.x & 3) * 8;  // 8 of the 32 columns
-  const int64_t jb = J * NB;
-  // target tile: blockIdx.x == 0 is the diagonal block, else the T-th other block
-  int64_t T;
-  if (!TRANS) T = J + int64_t(blockIdx.x);
-  else T = int64_t(blockIdx.x) == 0 ? J : int64_t(blockIdx.x) - 1;
-  for (int e = threadIdx.x; e < NB * NB; e += 256) Li[e / NB][e % NB] = Liu[e];
-  {
-    const int64_t i = jb + il;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int64_t c = c0 + cs + q;
-      Yb[il][cs + q] = (i < n && c < w) ? Xu[i * w + c] : 0.0;
-    }
+  const double* Yu = Y + size_t(u) * n * w;
+  const int64_t T = TRANS ? int64_t(blockIdx.x) : J + 1 + int64_t(blockIdx.x);
+  const int64_t tb = T * NB, jb = J * NB, c0 = int64_t(blockIdx.y) * NB;
+  for (int e = threadIdx.x; e < NB * NB; e += 256) {  // A[a][b]: coefficient of Y_J row b in X_T row a
+    const int a = e / NB, b = e % NB;
+    double v = 0.0;
+    if (tb + a < n && jb + b < n) v = TRANS ? Lu[(jb + b) * n + tb + a] : Lu[(tb + a) * n + jb + b];
+    A[a][b] = v;
   }
-  if (blockIdx.x != 0) {  // the L block that couples T and J
-    const int64_t tb = T * NB;
-    for (int e = threadIdx.x; e < NB * NB; e += 256) {
-      const int a = e / NB, b = e % NB;
-      double v = 0.0;
-      if (!TRANS) {
-        if (tb + a < n && jb + b < n) v = Lu[(tb + a) * n + jb + b];   // L_TJ[a][b]
-      } else {
-        if (jb + a < n && tb + b < n) v = Lu[(jb + a) * n + tb + b];   // L_JT[a][b]
+  stage_rhs(B, Yu, n, w, jb, c0);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, wm = wv >> 1, wn = wv & 1;
+  dbl4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+  tile_mma64(A, B, acc, lane, wm, wn);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t row = tb + wm * 32 + i * 16 + (lane >> 4) + 4 * e;
+        const int64_t col = c0 + wn * 32 + j * 16 + (lane & 15);
+        if (row < n && col < w) Xu[row * w + col] -= acc[i][j][e];
       }
-      Lt[a][b] = v;
-    }
-  }
-  __syncthreads();
-  // Y_J = Linv X_J (forward) or Linv^T X_J (backward), 8 outputs per thread
-  double y[8];
-#pragma unroll
-  for (int q = 0; q < 8; ++q) y[q] = 0.0;
-  for (int p = 0; p < NB; ++p) {
-    const double l = TRANS ? Li[p][il] : Li[il][p];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) y[q] += l * Yb[p][cs + q];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < 8; ++q) Yb[il][cs + q] = y[q];
-  __syncthreads();
-  if (blockIdx.x == 0) {
-    const int64_t i = jb + il;
-    if (i < n) {
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int64_t c = c0 + cs + q;
-        if (c < w) Yu[i * w + c] = Yb[il][cs + q];
-      }
-    }
-    return;
-  }
-  // X_T -= L_TJ Y_J  (forward)  or  X_T -= L_JT^T Y_J  (backward)
-  const int64_t i = T * NB + il;
-  if (i >= n) return;
-  double acc[8];
-#pragma unroll
-  for (int q = 0; q < 8; ++q) acc[q] = 0.0;
-  for (int p = 0; p < NB; ++p) {
-    const double l = TRANS ? Lt[p][il] : Lt[il][p];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) acc[q] += l * Yb[p][cs + q];
-  }
-#pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const int64_t c = c0 + cs + q;
-    if (c < w) Xu[i * w + c] -= acc[q];
-  }
 }
 
 int trsm_run(hipStream_t st, bool trans, const double* L, int64_t n, const double* Linv, double* X, double* Yout,
              int64_t w, int nu) {
   const int64_t nblk = (n + NB - 1) / NB;
-  const unsigned cch = unsigned((w + 31) / 32);
+  const unsigned nch = unsigned((w + NB - 1) / NB);
   for (int64_t b = 0; b < nblk; ++b) {
     const int64_t J = trans ? (nblk - 1 - b) : b;
-    const unsigned ntile = unsigned(trans ? (J + 1) : (nblk - J));  // diagonal + coupled tiles
+    const unsigned ntrail = unsigned(trans ? J : (nblk - 1 - J));  // coupled block rows
     if (!trans)
-      trsm_step_kernel<false><<<dim3(ntile, cch, unsigned(nu)), 256, 0, st>>>(L, n, Linv, X, Yout, w, J);
+      trsm_diag_kernel<false><<<dim3(nch, unsigned(nu)), 256, 0, st>>>(Linv, n, X, Yout, w, J);
     else
-      trsm_step_kernel<true><<<dim3(ntile, cch, unsigned(nu)), 256, 0, st>>>(L, n, Linv, X, Yout, w, J);
+      trsm_diag_kernel<true><<<dim3(nch, unsigned(nu)), 256, 0, st>>>(Linv, n, X, Yout, w, J);
+    DOPINF_LAUNCHED();
+    if (ntrail == 0) continue;
+    if (!trans)
+      trsm_update_kernel<false><<<dim3(ntrail, nch, unsigned(nu)), 256, 0, st>>>(L, n, X, Yout, w, J);
+    else
+      trsm_update_kernel<true><<<dim3(ntrail, nch, unsigned(nu)), 256, 0, st>>>(L, n, X, Yout, w, J);
     DOPINF_LAUNCHED();
   }
   return DOPINF_OK;
