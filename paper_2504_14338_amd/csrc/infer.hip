@@ -140,62 +140,62 @@ __global__ __launch_bounds__(256) void gather_qq_kernel(const double* __restrict
 // ---------------------------------------------------------------------------
 // Diagonal block at jb: factor in LDS with one wave (no workgroup barriers
 // beyond the wave), write L_jj and the inverse of its triangle.
-__global__ __launch_bounds__(64) void potf2_kernel(double* __restrict__ A, int64_t n, int64_t jb,
-                                                   double* __restrict__ Linv, int* __restrict__ fail_flag) {
+__global__ __launch_bounds__(256) void potf2_kernel(double* __restrict__ A, int64_t n, int64_t jb,
+                                                    double* __restrict__ Linv, int* __restrict__ fail_flag) {
   __shared__ double T[NB][NB + 1];
   __shared__ double Ti[NB][NB + 1];
+  __shared__ int bad;
   const int u = blockIdx.x;
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x;
   double* Au = A + size_t(u) * n * n;
   const int nb = int(min<int64_t>(NB, n - jb));
-  for (int j = 0; j < NB; ++j) {  // lane = row
-    const int i = lane;
+  for (int e = tid; e < NB * NB; e += 256) {
+    const int i = e / NB, j = e % NB;
     double v = 0.0;
     if (i < nb && j <= i) v = Au[(jb + i) * n + jb + j];
     else if (i == j) v = 1.0;  // identity padding beyond the matrix
     T[i][j] = v;
+    Ti[i][j] = (i == j) ? 1.0 : 0.0;
   }
-  int bad = 0;
+  if (tid == 0) bad = 0;
   __syncthreads();
+  // right-looking Cholesky of the 64 x 64 block
   for (int c = 0; c < NB; ++c) {
-    double piv = T[c][c];
-    if (!(piv > 0.0) || !isfinite(piv)) {
-      bad = 1;
-      piv = 1.0;
+    const double piv = T[c][c];
+    const bool okp = (piv > 0.0) && isfinite(piv);
+    const double dc = sqrt(okp ? piv : 1.0);
+    __syncthreads();
+    if (tid == 0) {
+      T[c][c] = dc;
+      if (!okp) bad = 1;
     }
-    const double dc = sqrt(piv);
-    const int i = lane;
-    double lic = 0.0;
-    if (i > c) {
-      lic = T[i][c] / dc;
-      T[i][c] = lic;
+    if (tid > c && tid < NB) T[tid][c] /= dc;
+    __syncthreads();
+    const int rem = NB - 1 - c;
+    for (int e = tid; e < rem * rem; e += 256) {
+      const int i = c + 1 + e / rem, l = c + 1 + e % rem;
+      if (l <= i) T[i][l] -= T[i][c] * T[l][c];
     }
     __syncthreads();
-    if (i == c) T[c][c] = dc;
-    if (i > c)
-      for (int l = c + 1; l <= i; ++l) T[i][l] -= lic * T[l][c];
+  }
+  // inverse of the triangle: T Ti = I, right-looking over rows
+  for (int i = 0; i < NB; ++i) {
+    if (tid <= i) Ti[i][tid] /= T[i][i];
+    __syncthreads();
+    const int rem = NB - 1 - i, cols = i + 1;
+    for (int e = tid; e < rem * cols; e += 256) {
+      const int q = i + 1 + e / cols, c = e % cols;
+      Ti[q][c] -= T[q][i] * Ti[i][c];
+    }
     __syncthreads();
   }
-  {  // inverse of the lower triangle: lane c computes column c
-    const int c = lane;
-    for (int i = 0; i < NB; ++i) {
-      double v = 0.0;
-      if (i >= c) {
-        double s = (i == c) ? 1.0 : 0.0;
-        for (int p = c; p < i; ++p) s -= T[i][p] * Ti[p][c];
-        v = s / T[i][i];
-      }
-      Ti[i][c] = v;
-    }
-  }
-  __syncthreads();
   double* Lo = Linv + (size_t(u) * ((n + NB - 1) / NB) + jb / NB) * NB * NB;
-  for (int j = 0; j < NB; ++j) {
-    const int i = lane;
+  for (int e = tid; e < NB * NB; e += 256) {
+    const int i = e / NB, j = e % NB;
     if (i < nb && j <= i) Au[(jb + i) * n + jb + j] = T[i][j];
-    Lo[i * NB + j] = Ti[i][j];
+    Lo[e] = Ti[i][j];
   }
-  if (lane == 0 && bad) fail_flag[u] = 1;
+  if (tid == 0 && bad) fail_flag[u] = 1;
 }
 
 // Rows below the diagonal block: A[i, jb:jb+nb] <- A[i, jb:jb+nb] L_jj^{-T}
@@ -425,6 +425,7 @@ struct PairArgs {
   const double* beta1;   // per pair
   double* O;             // group base, pair stride r*d
   int* status;           // group base
+  double* XL;            // per pair: X_l ((r+1) x r), for the quadratic columns
   int n_pairs;
 };
 
@@ -477,20 +478,27 @@ __global__ __launch_bounds__(256) void pair_solve_kernel(PairArgs a) {
     }
     __syncthreads();
   }
-  // forward then backward substitution, columns in parallel
-  for (int c = threadIdx.x; c < r; c += 256) {
-    for (int i = 0; i < r1; ++i) {
-      double v = X[i * r + c];
-      for (int q = 0; q < i; ++q) v -= S[i * r1 + q] * X[q * r + c];
-      X[i * r + c] = v / S[i * r1 + i];
+  // forward (L Y = X) then backward (L^T X = Y) substitution, right-looking:
+  // each step scales one row (all r columns at once) and updates the rest
+  for (int i = 0; i < r1; ++i) {
+    for (int c = threadIdx.x; c < r; c += 256) X[i * r + c] /= S[i * r1 + i];
+    __syncthreads();
+    const int rem = r1 - 1 - i;
+    for (int e = threadIdx.x; e < rem * r; e += 256) {
+      const int q = i + 1 + e / r, c = e % r;
+      X[q * r + c] -= S[q * r1 + i] * X[i * r + c];
     }
-    for (int i = r1 - 1; i >= 0; --i) {
-      double v = X[i * r + c];
-      for (int q = i + 1; q < r1; ++q) v -= S[q * r1 + i] * X[q * r + c];
-      X[i * r + c] = v / S[i * r1 + i];
-    }
+    __syncthreads();
   }
-  __syncthreads();
+  for (int i = r1 - 1; i >= 0; --i) {
+    for (int c = threadIdx.x; c < r; c += 256) X[i * r + c] /= S[i * r1 + i];
+    __syncthreads();
+    for (int e = threadIdx.x; e < i * r; e += 256) {
+      const int q = e / r, c = e % r;
+      X[q * r + c] -= S[i * r1 + q] * X[i * r + c];
+    }
+    __syncthreads();
+  }
   double* Op = a.O + size_t(p) * r * d;
   // linear and constant columns of O = X^T
   for (int e = threadIdx.x; e < r * r1; e += 256) {
@@ -498,25 +506,64 @@ __global__ __launch_bounds__(256) void pair_solve_kernel(PairArgs a) {
     const int64_t col = (c < r) ? c : (r + s);
     Op[i * d + col] = X[c * r + i];
   }
-  // quadratic columns: X_q = Z - P X_l, rows of [P | Z] staged through LDS in
-  // tiles that reuse the Schur factor's space (no longer needed)
-  const double* R2u = a.R2 + size_t(u) * s * w;
-  const int tile = (r1 * r1) / w;  // >= 1 since r1^2 >= 2 r + 1
-  double* Pt = S;
-  for (int64_t q0 = 0; q0 < s; q0 += tile) {
-    const int nq = int(min<int64_t>(tile, s - q0));
-    __syncthreads();
-    for (int e = threadIdx.x; e < nq * w; e += 256) Pt[e] = R2u[q0 * w + e];
-    __syncthreads();
-    for (int e = threadIdx.x; e < nq * r; e += 256) {
-      const int i = e / nq, qq = e % nq;  // consecutive threads -> consecutive q
-      const double* prow = Pt + qq * w;
-      double v = prow[r1 + i];
-      for (int c = 0; c < r1; ++c) v -= prow[c] * X[c * r + i];
-      Op[int64_t(i) * d + r + q0 + qq] = v;
-    }
-  }
+  // X_l for the quadratic columns X_q = Z - P X_l (opq_kernel)
+  double* XLp = a.XL + size_t(p) * r1 * r;
+  for (int e = threadIdx.x; e < r1 * r; e += 256) XLp[e] = X[e];
   if (threadIdx.x == 0) a.status[p] = bad ? DOPINF_E_NOTSPD : DOPINF_OK;
+}
+
+// Quadratic columns of O for every pair: O[i][r + q] = Z[q][i] - sum_c P[q][c] X_l[c][i]
+// with [P | Z] = R2 of the pair's beta2 group.  Workgroup = (64 quadratic
+// columns, 64 modes, pair); FP64 MFMA over K = r + 1 in chunks of 64; the tile
+// goes through LDS so that rows of O are written contiguously.
+__global__ __launch_bounds__(256) void opq_kernel(PairArgs a) {
+  __shared__ double At[NB][TP];
+  __shared__ double Bt[NB][TP];
+  const int p = blockIdx.y;
+  const int u = a.pair_u[p];
+  if (u < 0) return;
+  const int r = a.geo.r, r1 = r + 1, w = 2 * r + 1;
+  const int64_t s = a.geo.s, d = ncols(r);
+  const int64_t q0 = int64_t(blockIdx.x) * NB;
+  const int i0 = int(blockIdx.z) * NB;
+  const double* R2u = a.R2 + size_t(u) * s * w;
+  const double* XLp = a.XL + size_t(p) * r1 * r;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, wm = wv >> 1, wn = wv & 1;
+  dbl4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < r1; k0 += NB) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < NB * NB; e += 256) {
+      const int a_ = e / NB, b_ = e % NB;
+      At[a_][b_] = (q0 + a_ < s && k0 + b_ < r1) ? R2u[(q0 + a_) * w + k0 + b_] : 0.0;        // P[q][c]
+      Bt[a_][b_] = (k0 + a_ < r1 && i0 + b_ < r) ? XLp[(k0 + a_) * r + i0 + b_] : 0.0;       // X_l[c][i]
+    }
+    __syncthreads();
+    tile_mma64(At, Bt, acc, lane, wm, wn);
+  }
+  __syncthreads();
+  // C[q][i] -> At[i][q] (transposed) for row-contiguous writes of O
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int qq = wm * 32 + i * 16 + (lane >> 4) + 4 * e;  // MFMA f64 output layout
+        const int ii = wn * 32 + j * 16 + (lane & 15);
+        At[ii][qq] = acc[i][j][e];
+      }
+  __syncthreads();
+  double* Op = a.O + size_t(p) * r * d;
+  for (int e = threadIdx.x; e < NB * NB; e += 256) {
+    const int ii = e / NB, qq = e % NB;
+    const int i = i0 + ii;
+    const int64_t q = q0 + qq;
+    if (i < r && q < s) Op[int64_t(i) * d + r + q] = R2u[q * w + r1 + i] - At[ii][qq];
+  }
 }
 
 __global__ void zero_ints_kernel(int* p, int64_t n) {
@@ -585,6 +632,7 @@ InferLayout layout(int64_t k, int n_r, const int* r_list, int n_pairs) {
   c.take<int>(size_t(uc));          // fail flag per u
   c.take<int>(size_t(n_pairs));     // pair -> u
   c.take<double>(size_t(n_pairs));  // beta1 per pair
+  c.take<double>(size_t(n_pairs) * (rmax + 1) * rmax);  // X_l per pair
   L.total = c.used;
   return L;
 }
@@ -671,6 +719,7 @@ extern "C" int dopinf_infer(void* stream, const double* Qhat, int64_t ldqh, int6
   int* ufail = mc.take<int>(size_t(uc));
   int* pair_u = mc.take<int>(size_t(n_pairs));
   double* b1dev = mc.take<double>(size_t(n_pairs));
+  double* XL = mc.take<double>(size_t(n_pairs) * (L.rmax + 1) * L.rmax);
   DOPINF_HIP(hipMemcpyAsync(b1dev, beta1_h, sizeof(double) * n_pairs, hipMemcpyHostToDevice, st));
 
   std::vector<int> pu(n_pairs);
@@ -711,7 +760,7 @@ extern "C" int dopinf_infer(void* stream, const double* Qhat, int64_t ldqh, int6
         DOPINF_LAUNCHED();
       }
       for (int64_t jb = 0; jb < s; jb += NB) {
-        potf2_kernel<<<nu, 64, 0, st>>>(Lq, s, jb, Linv, ufail);
+        potf2_kernel<<<nu, 256, 0, st>>>(Lq, s, jb, Linv, ufail);
         DOPINF_LAUNCHED();
         const int64_t rest = s - jb - NB;
         if (rest > 0) {
@@ -746,8 +795,12 @@ extern "C" int dopinf_infer(void* stream, const double* Qhat, int64_t ldqh, int6
       pa.O = O + op_base;
       pa.status = status + g * n_pairs;
       pa.n_pairs = n_pairs;
+      pa.XL = XL;
       const size_t smem = size_t(r1) * (r1 + geo.r) * sizeof(double);
       pair_solve_kernel<<<n_pairs, 256, smem, st>>>(pa);
+      DOPINF_LAUNCHED();
+      opq_kernel<<<dim3(unsigned((s + NB - 1) / NB), unsigned(n_pairs), unsigned((geo.r + NB - 1) / NB)), 256, 0,
+                   st>>>(pa);
       DOPINF_LAUNCHED();
     }
   }
