@@ -152,12 +152,22 @@ def cpu_baseline(Q, var_rows, budget_s):
 
 
 def sweep_bench(dp, torch, Qhat80, reps=1):
+    """The regularization sweep over every (r, beta1, beta2): block-column
+    widths picked by the autotuner, then the sweep captured into one graph and
+    replayed (the headline rate); the eager calls are timed beside it."""
     import synth
     B1 = synth.logspace_points(-10, -2, 32)
     B2 = synth.logspace_points(-8, 0, 32)
     b1 = [x for x in B1 for _ in B2]
     b2 = [y for _ in B1 for y in B2]
     r_list = [20, 40, 60, 80]
+    n_items = len(r_list) * len(b1)
+    t0 = time.perf_counter()
+    _, _, _, tune_ms = dp.autotune_infer(Qhat80, r_list, b1, b2)
+    torch.cuda.synchronize()
+    t_tune = time.perf_counter() - t0
+    chosen = {r: {"cholesky": dp.tune_get(dp.TUNE_CHOL_KB, dp.n_quad(r)),
+                  "solve": dp.tune_get(dp.TUNE_TRSM_KB, dp.n_quad(r))} for r in r_list}
     timer = Timer(torch)
     res = None
     for _ in range(reps + 1):  # first pass warms up
@@ -165,15 +175,43 @@ def sweep_bench(dp, torch, Qhat80, reps=1):
         O, status, _ = timer.run("infer", lambda: dp.infer(Qhat80, r_list, b1, b2))
         res = timer.run("rollout", lambda: dp.rollout(O, Qhat80, r_list, len(b1), 4000, solve_status=status))
     t_inf, t_roll = timer.ms("infer"), timer.ms("rollout")
-    n_items = len(r_list) * len(b1)
     oc = res["outcome"].cpu().numpy()
+    t0 = time.perf_counter()
+    sw = dp.Sweep(Qhat80, r_list, b1, b2, 4000)
+    t_capture = time.perf_counter() - t0
+    try:
+        cur = torch.cuda.current_stream()
+        times = []
+        for _ in range(reps + 2):  # first replay warms up
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(cur)
+            sw.launch(cur)
+            e1.record(cur)
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        t_graph = min(times[1:])
+        same_best = sw.best.cpu().numpy().tolist() == res["best"].cpu().numpy().tolist()
+        oc_graph = sw.outcome.cpu().numpy()
+    finally:
+        sw.close()
     return {
-        "solves_per_s": n_items / ((t_inf + t_roll) * 1e-3),
+        "solves_per_s": n_items / (t_graph * 1e-3),
         "items": n_items,
-        "infer_ms": t_inf,
-        "rollout_ms": t_roll,
+        "graph_ms": t_graph,
+        "eager_infer_ms": t_inf,
+        "eager_rollout_ms": t_roll,
+        "eager_solves_per_s": n_items / ((t_inf + t_roll) * 1e-3),
+        "block_widths": chosen,
+        "autotune_ms": {str(r): {"cholesky": [round(float(x), 3) for x in tune_ms[g, 0]],
+                                 "solve": [round(float(x), 3) for x in tune_ms[g, 1]]} for g, r in enumerate(r_list)},
+        "autotune_candidates": dp.autotune_candidates(),
+        "autotune_s": round(t_tune, 2),
+        "capture_s": round(t_capture, 2),
         "passing": int((oc == dp.ITEM_PASS).sum()),
+        "passing_graph": int((oc_graph == dp.ITEM_PASS).sum()),
         "best": res["best"].cpu().numpy().tolist(),
+        "graph_best_matches_eager": same_best,
     }
 
 

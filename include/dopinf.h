@@ -196,6 +196,67 @@ int dopinf_rollout(void* stream, int n_r, const int* r_list_h, int n_pairs,
                    double* train_err, double* growth, int* outcome, int* best,
                    void* ws, size_t ws_bytes);
 
+/* ---- Tuned launch parameters and the autotuner (batched form) ------------
+ * The regularization sweep of Sec. 3.5 (every (r, beta1, beta2) of a grid)
+ * factors G_qq + beta2 I (s x s, s = r(r+1)/2) once per distinct beta2 with
+ * a blocked Cholesky, and solves triangular systems with that factor; both
+ * are blocked in block columns whose width is a launch parameter: wider
+ * blocks read the trailing matrix or the right-hand sides fewer times,
+ * narrower ones start the trailing work sooner.  A process-wide table holds
+ * the widths per s (untuned sizes use 256):
+ *   DOPINF_TUNE_CHOL_KB  the Cholesky's block-column width,
+ *   DOPINF_TUNE_TRSM_KB  the triangular solves' block-column depth.
+ * dopinf_tune_set: value = width (multiple of 64 in [64, 4096]) or 0 to
+ *   clear; returns DOPINF_E_ARG for an unknown parameter or a bad value.
+ * dopinf_tune_get: the stored width, 0 when untuned.
+ * dopinf_autotune_candidates: the widths the autotuner tries (the same list
+ *   for both parameters); writes up to max_values of them to values_h (may
+ *   be NULL) and returns their number.
+ * dopinf_autotune_infer: dopinf_infer with the same arguments and results,
+ *   preceded by the autotuner: for every group, on its first beta2 chunk,
+ *   every Cholesky width is timed, then every solve depth; the fastest are
+ *   stored for that s.  The stream is synchronized while timing.  times_h
+ *   (NULL or n_r x 2 x candidates floats, ms): per group the Cholesky
+ *   timings, then the solve timings (0 where a group had nothing to time). */
+#define DOPINF_TUNE_CHOL_KB 1
+#define DOPINF_TUNE_TRSM_KB 2
+int dopinf_tune_set(int param, int64_t key, int value);
+int dopinf_tune_get(int param, int64_t key);
+int dopinf_autotune_candidates(int param, int* values_h, int max_values);
+int dopinf_autotune_infer(void* stream, const double* Qhat, int64_t ldqh,
+                          int64_t k, int n_r, const int* r_list_h,
+                          int n_pairs, const double* beta1_h,
+                          const double* beta2_h, double* O, int* status,
+                          void* ws, size_t ws_bytes, float* times_h);
+
+/* ---- The sweep as one captured graph (batched form, Sec. 3.5) ------------
+ * dopinf_sweep_create validates the arguments as dopinf_infer and
+ * dopinf_rollout do, uploads the beta tables into the workspace, optionally
+ * runs the autotuner (flags & DOPINF_SWEEP_AUTOTUNE), then captures the
+ * kernels of dopinf_infer followed by those of dopinf_rollout (one workgroup
+ * per item, no trajectories) on `stream` into a graph and instantiates it.
+ * Nothing of the sweep runs during capture.  `stream` must not be the null
+ * stream.  dopinf_sweep_launch replays the whole sweep on any stream: it
+ * reads Qhat at replay time and overwrites O, status, train_err, growth,
+ * outcome and best, exactly as the eager calls would.  The caller keeps
+ * every buffer named at creation (and ws, of dopinf_sweep_workspace bytes)
+ * alive and unchanged in size until dopinf_sweep_destroy; replays of one
+ * sweep must not overlap.  The stream is synchronized before create returns.
+ */
+#define DOPINF_SWEEP_AUTOTUNE 1u
+typedef struct dopinf_sweep_s* dopinf_sweep_t;
+size_t dopinf_sweep_workspace(int64_t k, int n_r, const int* r_list_h,
+                              int n_pairs);
+int dopinf_sweep_create(void* stream, const double* Qhat, int64_t ldqh,
+                        int64_t k, int n_r, const int* r_list_h, int n_pairs,
+                        const double* beta1_h, const double* beta2_h,
+                        int n_states, double max_growth, unsigned flags,
+                        double* O, int* status, double* train_err,
+                        double* growth, int* outcome, int* best, void* ws,
+                        size_t ws_bytes, dopinf_sweep_t* sweep_out);
+int dopinf_sweep_launch(dopinf_sweep_t sweep, void* stream);
+int dopinf_sweep_destroy(dopinf_sweep_t sweep);
+
 
 /* ---- Learned closure of the discrete ROM (an addition to the paper) --------
  * g: R^r -> R^r, an MLP r -> 128 -> 128 -> r with GELU (error-function form),

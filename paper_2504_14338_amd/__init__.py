@@ -18,7 +18,8 @@ __all__ = [
     "ITEM_GROWTH", "ITEM_SOLVE", "ITEM_TIMEOUT", "preprocess", "gram", "cross_gram",
     "reduce", "infer", "operator_offset", "rollout", "traj_offset",
     "n_quad", "lib_path", "closure_param_count", "rom_residuals", "closure_fit", "closure_norms",
-    "closure_grad", "closure_eval", "closure_rollout",
+    "closure_grad", "closure_eval", "closure_rollout", "TUNE_CHOL_KB", "tune_set", "tune_get",
+    "autotune_candidates", "autotune_infer", "Sweep", "TUNE_TRSM_KB",
 ]
 
 OK, E_ARG, E_HIP, E_WORKSPACE, E_RANK, E_NOTSPD, E_NONFINITE, E_NOSTABLE, E_TIMEOUT = range(9)
@@ -28,6 +29,9 @@ GRAM_NATIVE, GRAM_BF16X3, GRAM_BF16X6 = 0, 1, 2
 ITEM_PASS, ITEM_NONFINITE, ITEM_GROWTH, ITEM_SOLVE, ITEM_TIMEOUT = 0, 1, 2, 3, 4
 ROLLOUT_FULL = 1
 ROLLOUT_ONE_WG = 2
+TUNE_CHOL_KB = 1
+TUNE_TRSM_KB = 2
+SWEEP_AUTOTUNE = 1
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
@@ -63,6 +67,15 @@ _SIGS = {
     "dopinf_rollout_workspace": ([_i32, _vp, _i32, _i64], _sz),
     "dopinf_rollout": ([_vp, _i32, _vp, _i32, _vp, _vp, _i64, _i64, _i32, _f64, _u32, _vp, _vp, _vp, _vp, _vp, _vp,
                         _vp, _sz], _i32),
+    "dopinf_tune_set": ([_i32, _i64, _i32], _i32),
+    "dopinf_tune_get": ([_i32, _i64], _i32),
+    "dopinf_autotune_candidates": ([_i32, _vp, _i32], _i32),
+    "dopinf_autotune_infer": ([_vp, _vp, _i64, _i64, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _vp], _i32),
+    "dopinf_sweep_workspace": ([_i64, _i32, _vp, _i32], _sz),
+    "dopinf_sweep_create": ([_vp, _vp, _i64, _i64, _i32, _vp, _i32, _vp, _vp, _i32, _f64, _u32, _vp, _vp, _vp, _vp,
+                             _vp, _vp, _vp, _sz, _vp], _i32),
+    "dopinf_sweep_launch": ([_vp, _vp], _i32),
+    "dopinf_sweep_destroy": ([_vp], _i32),
     "dopinf_closure_param_count": ([_i32], _i64),
     "dopinf_rom_residuals": ([_vp, _vp, _i32, _vp, _i64, _i64, _vp], _i32),
     "dopinf_closure_fit_workspace": ([_i32, _i64], _sz),
@@ -329,6 +342,138 @@ def rollout(O, Qhat, r_list, n_pairs, n_states, k_train=None, max_growth=1.2, so
             views.append(row)
         out["traj_views"] = views
     return out
+
+
+# ------------------------------------------ tuning and the captured sweep ---
+def tune_set(param, key, value):
+    """Store a launch parameter (value 0 clears it) for problem size `key`."""
+    _check(load().dopinf_tune_set(int(param), int(key), int(value)))
+
+
+def tune_get(param, key):
+    return int(load().dopinf_tune_get(int(param), int(key)))
+
+
+def autotune_candidates(param=TUNE_CHOL_KB):
+    lib = load()
+    n = lib.dopinf_autotune_candidates(int(param), None, 0)
+    if n < 0:
+        _check(n)
+    vals = (C.c_int * n)()
+    lib.dopinf_autotune_candidates(int(param), vals, n)
+    return [int(v) for v in vals]
+
+
+def autotune_infer(Qhat, r_list, beta1, beta2):
+    """infer() preceded by the autotuner: for every group the Cholesky widths
+    and then the triangular-solve depths are timed and the fastest stored per
+    factorization size.  Returns (O, status, views, times) with times (ms) an
+    n_r x 2 x candidates array (Cholesky, solve)."""
+    torch = _torch()
+    lib = load()
+    dev = Qhat.device
+    k = Qhat.shape[1]
+    rl, rlp = _host_i32(r_list)
+    b1, b1p = _host_f64(beta1)
+    b2, b2p = _host_f64(beta2)
+    n_pairs = len(b1)
+    if len(b2) != n_pairs:
+        raise ValueError("beta1 and beta2 must have the same length")
+    ncand = len(autotune_candidates(TUNE_CHOL_KB))
+    times = np.zeros(len(rl) * 2 * ncand, dtype=np.float32)
+    n_items = len(rl) * n_pairs
+    O = torch.empty(lib.dopinf_operator_offset(len(rl), rlp, n_pairs, n_items), dtype=torch.float64, device=dev)
+    status = torch.empty(n_items, dtype=torch.int32, device=dev)
+    nb = lib.dopinf_infer_workspace(k, len(rl), rlp, n_pairs)
+    ws = _ws(nb, dev)
+    _check(lib.dopinf_autotune_infer(_stream(dev), _ptr(Qhat), _rowmajor(Qhat, "Qhat"), k, len(rl), rlp, n_pairs, b1p,
+                                     b2p, _ptr(O), _ptr(status), _ptr(ws), ws.numel(),
+                                     times.ctypes.data_as(C.c_void_p)))
+    return O, status, _operator_views(O, rl, rlp, n_pairs), times.reshape(len(rl), 2, ncand)
+
+
+def _operator_views(O, rl, rlp, n_pairs):
+    lib = load()
+    views = []
+    for g, r in enumerate(rl):
+        d = int(r) + n_quad(int(r)) + 1
+        row = []
+        for p in range(n_pairs):
+            off = lib.dopinf_operator_offset(len(rl), rlp, n_pairs, g * n_pairs + p)
+            row.append(O[off:off + int(r) * d].view(int(r), d))
+        views.append(row)
+    return views
+
+
+class Sweep:
+    """The regularization sweep (dopinf_infer + dopinf_rollout over every
+    (r, beta1, beta2) item) captured once into a graph; launch() replays it.
+
+    The outputs (O, status, views, train_err, growth, outcome, best) and the
+    workspace are allocated here and stay fixed; Qhat is read at every
+    replay, so new reduced data of the same shape may be written into it.
+    Capture needs a stream other than the null stream: by default a new one.
+    """
+
+    def __init__(self, Qhat, r_list, beta1, beta2, n_states, max_growth=1.2, autotune=False, stream=None):
+        torch = _torch()
+        lib = load()
+        dev = Qhat.device
+        self.Qhat = Qhat
+        k = Qhat.shape[1]
+        self._rl, rlp = _host_i32(r_list)
+        self._rlp = rlp
+        b1, b1p = _host_f64(beta1)
+        b2, b2p = _host_f64(beta2)
+        n_pairs = len(b1)
+        if len(b2) != n_pairs:
+            raise ValueError("beta1 and beta2 must have the same length")
+        n_r = len(self._rl)
+        n_items = n_r * n_pairs
+        self.n_pairs = n_pairs
+        total = lib.dopinf_operator_offset(n_r, rlp, n_pairs, n_items)
+        self.O = torch.empty(total, dtype=torch.float64, device=dev)
+        self.status = torch.empty(n_items, dtype=torch.int32, device=dev)
+        self.train_err = torch.empty(n_items, dtype=torch.float64, device=dev)
+        self.growth = torch.empty(n_items, dtype=torch.float64, device=dev)
+        self.outcome = torch.empty(n_items, dtype=torch.int32, device=dev)
+        self.best = torch.empty(n_r, dtype=torch.int32, device=dev)
+        nb = lib.dopinf_sweep_workspace(k, n_r, rlp, n_pairs)
+        self._ws = _ws(nb, dev)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=dev)
+        handle = C.c_void_p()
+        _check(lib.dopinf_sweep_create(C.c_void_p(self.stream.cuda_stream), _ptr(Qhat), _rowmajor(Qhat, "Qhat"), k,
+                                       n_r, rlp, n_pairs, b1p, b2p, int(n_states), float(max_growth),
+                                       SWEEP_AUTOTUNE if autotune else 0, _ptr(self.O), _ptr(self.status),
+                                       _ptr(self.train_err), _ptr(self.growth), _ptr(self.outcome), _ptr(self.best),
+                                       _ptr(self._ws), self._ws.numel(), C.byref(handle)))
+        self._h = handle
+        self.views = []
+        for g, r in enumerate(self._rl):
+            d = int(r) + n_quad(int(r)) + 1
+            row = []
+            for p in range(n_pairs):
+                off = lib.dopinf_operator_offset(n_r, rlp, n_pairs, g * n_pairs + p)
+                row.append(self.O[off:off + int(r) * d].view(int(r), d))
+            self.views.append(row)
+
+    def launch(self, stream=None):
+        """Replay the sweep on `stream` (default: the capture stream)."""
+        if self._h is None:
+            raise RuntimeError("sweep is closed")
+        st = self.stream if stream is None else stream
+        _check(load().dopinf_sweep_launch(self._h, C.c_void_p(st.cuda_stream)))
+
+    def close(self):
+        if self._h is not None:
+            _check(load().dopinf_sweep_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ------------------------------------------------------- learned closure ---

@@ -18,6 +18,12 @@ namespace dopinf {
 void set_error(const char* fmt, ...);
 int fail(int code, const char* fmt, ...);
 
+// ---- tuned launch parameters (tune.cpp) ------------------------------------
+namespace tune {
+int get(int param, int64_t key);  // 0 when untuned
+void set(int param, int64_t key, int value);
+}  // namespace tune
+
 #define DOPINF_HIP(call)                                                        \
   do {                                                                          \
     hipError_t e_ = (call);                                                     \

@@ -22,6 +22,7 @@
 //    solves the rows below, and the trailing update runs on FP64 MFMA tiles.
 //    Triangular solves then reduce to products with the stored diagonal
 //    inverses.
+#include <algorithm>
 #include <vector>
 
 #include "common.hpp"
@@ -222,26 +223,35 @@ __global__ __launch_bounds__(256) void panel_kernel(double* __restrict__ A, int6
   }
 }
 
-// Trailing update on FP64 MFMA: A[i][l] -= sum_p L[i][jb+p] L[l][jb+p] for
-// i >= l >= jb+NB, 64 x 64 tiles (lower triangle of tiles), 4 waves of 32 x 32.
-__global__ __launch_bounds__(256) void syrk_update_kernel(double* __restrict__ A, int64_t n, int64_t jb) {
+// Update on FP64 MFMA from the factored columns [a0, a0 + K):
+//   A[i][l] -= sum_{a0 <= p < a0+K} L[i][p] L[l][p]   for c_lo <= l < c_hi, l <= i < n,
+// on 64 x 64 tiles (4 waves of 32 x 32) of the trapezoid of rows [c_lo, n) and
+// columns [c_lo, c_hi); K is consumed in 64-wide slabs staged through LDS.
+// With c_hi = n this is the trailing update of the lower triangle.
+__global__ __launch_bounds__(256) void syrk_update_kernel(double* __restrict__ A, int64_t n, int64_t a0, int64_t K,
+                                                          int64_t c_lo, int64_t c_hi) {
   __shared__ double Pa[NB][NB + 2];
   __shared__ double Pb[NB][NB + 2];
   const int u = blockIdx.y;
   double* Au = A + size_t(u) * n * n;
-  const int64_t j1 = jb + NB;
+  const int TR = int((n - c_lo + 63) / 64), TC = int((c_hi - c_lo + 63) / 64);
   const int t = blockIdx.x;
-  int I = int((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-  while ((I + 1) * (I + 2) / 2 <= t) ++I;
-  while (I * (I + 1) / 2 > t) --I;
-  const int J = t - I * (I + 1) / 2;
-  const int64_t r0 = j1 + int64_t(I) * 64, c0 = j1 + int64_t(J) * 64;
-  for (int e = threadIdx.x; e < 64 * NB; e += 256) {
-    const int rr = e / NB, p = e % NB;
-    Pa[rr][p] = (r0 + rr < n) ? Au[(r0 + rr) * n + jb + p] : 0.0;
-    Pb[rr][p] = (c0 + rr < n) ? Au[(c0 + rr) * n + jb + p] : 0.0;
+  int I, J;
+  if (TC >= TR) {
+    I = int((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while ((I + 1) * (I + 2) / 2 <= t) ++I;
+    while (I * (I + 1) / 2 > t) --I;
+    J = t - I * (I + 1) / 2;
+  } else {  // a few tile columns: column J holds tiles J .. TR-1
+    int rem = t;
+    J = 0;
+    while (rem >= TR - J) {
+      rem -= TR - J;
+      ++J;
+    }
+    I = J + rem;
   }
-  __syncthreads();
+  const int64_t r0 = c_lo + int64_t(I) * 64, c0 = c_lo + int64_t(J) * 64;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wm = w >> 1, wn = w & 1;
   dbl4 acc[2][2];
@@ -249,18 +259,29 @@ __global__ __launch_bounds__(256) void syrk_update_kernel(double* __restrict__ A
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+  for (int64_t kc = 0; kc < K; kc += NB) {
+    const int64_t kw = min<int64_t>(NB, K - kc);
+    for (int e = threadIdx.x; e < 64 * NB; e += 256) {
+      const int rr = e / NB, p = e % NB;
+      const int64_t col = a0 + kc + p;
+      Pa[rr][p] = (r0 + rr < n && p < kw) ? Au[(r0 + rr) * n + col] : 0.0;
+      Pb[rr][p] = (c0 + rr < n && p < kw) ? Au[(c0 + rr) * n + col] : 0.0;
+    }
+    __syncthreads();
 #pragma unroll 4
-  for (int kk = 0; kk < NB / 4; ++kk) {
-    const int p = kk * 4 + (lane >> 4);
-    double af[2], bf[2];
+    for (int kk = 0; kk < NB / 4; ++kk) {
+      const int p = kk * 4 + (lane >> 4);
+      double af[2], bf[2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) af[i] = Pa[wm * 32 + i * 16 + (lane & 15)][p];
+      for (int i = 0; i < 2; ++i) af[i] = Pa[wm * 32 + i * 16 + (lane & 15)][p];
 #pragma unroll
-    for (int j = 0; j < 2; ++j) bf[j] = Pb[wn * 32 + j * 16 + (lane & 15)][p];
+      for (int j = 0; j < 2; ++j) bf[j] = Pb[wn * 32 + j * 16 + (lane & 15)][p];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
   }
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -270,19 +291,64 @@ __global__ __launch_bounds__(256) void syrk_update_kernel(double* __restrict__ A
       for (int e = 0; e < 4; ++e) {
         const int64_t row = r0 + wm * 32 + i * 16 + (lane >> 4) + 4 * e;  // MFMA f64 output layout
         const int64_t col = c0 + wn * 32 + j * 16 + (lane & 15);
-        if (row < n && col <= row) Au[row * n + col] -= acc[i][j][e];
+        if (row < n && col <= row && col < c_hi) Au[row * n + col] -= acc[i][j][e];
       }
+}
+
+// number of 64 x 64 tiles of the update region of syrk_update_kernel
+inline int64_t syrk_tiles(int64_t n, int64_t c_lo, int64_t c_hi) {
+  const int64_t TR = (n - c_lo + 63) / 64, TC = (c_hi - c_lo + 63) / 64;
+  if (TC >= TR) return TR * (TR + 1) / 2;
+  return TC * TR - TC * (TC - 1) / 2;
+}
+
+// Blocked Cholesky of nu matrices (s x s, row-major, lower triangle used) in
+// place.  Block columns of width kb (a multiple of NB): inside a block column
+// the 64-wide panels are factored left to right and each updates only the
+// rest of its block column; the columns right of the block column then take
+// one update of depth kb.  kb = NB is the plain right-looking algorithm;
+// larger kb reads and writes the trailing matrix kb / NB times less often.
+int cholesky_run(hipStream_t st, double* Lq, int64_t s, double* Linv, int* ufail, int nu, int64_t kb) {
+  for (int64_t cb = 0; cb < s; cb += kb) {
+    const int64_t ce = std::min<int64_t>(cb + kb, s);
+    for (int64_t jb = cb; jb < ce; jb += NB) {
+      potf2_kernel<<<nu, 256, 0, st>>>(Lq, s, jb, Linv, ufail);
+      DOPINF_LAUNCHED();
+      const int64_t rest = s - jb - NB;
+      if (rest <= 0) continue;
+      panel_kernel<<<dim3(unsigned((rest + 255) / 256), unsigned(nu)), 256, 0, st>>>(Lq, s, jb, Linv);
+      DOPINF_LAUNCHED();
+      if (jb + NB < ce) {
+        const int64_t nt = syrk_tiles(s, jb + NB, ce);
+        syrk_update_kernel<<<dim3(unsigned(nt), unsigned(nu)), 256, 0, st>>>(Lq, s, jb, NB, jb + NB, ce);
+        DOPINF_LAUNCHED();
+      }
+    }
+    if (ce < s) {
+      const int64_t nt = syrk_tiles(s, ce, s);
+      syrk_update_kernel<<<dim3(unsigned(nt), unsigned(nu)), 256, 0, st>>>(Lq, s, cb, ce - cb, ce, s);
+      DOPINF_LAUNCHED();
+    }
+  }
+  return DOPINF_OK;
 }
 
 // ---------------------------------------------------------------------------
 // Triangular solves with the factored L (row-major lower, ld n) and its
-// diagonal-block inverses, right-looking, per 64-row block J:
-//   forward  (L Y = X):   Y_J = Linv_J X_J,    then X_T -= L_TJ Y_J   (T > J)
-//   backward (L^T Y = X): Y_J = Linv_J^T X_J,  then X_T -= L_JT^T Y_J (T < J)
-// X (n x w, ld w) holds the right-hand sides and is consumed; Y_J goes to
-// Yout.  Both steps are 64 x 64 x 64 products on FP64 MFMA tiles with A and
-// B staged in LDS: the diagonal solve once per (item, 64 columns), the update
-// once per (coupled block row, 64 columns, item).
+// diagonal-block inverses, per 64-row block J:
+//   forward  (L Y = X):   Y_J = Linv_J X_J,    and X_T -= L_TJ Y_J   (T > J)
+//   backward (L^T Y = X): Y_J = Linv_J^T X_J,  and X_T -= L_JT^T Y_J (T < J)
+// X holds the right-hand sides and is consumed; Y goes to Yout.  The blocks
+// are taken in block columns of kb rows: inside one, each solved block
+// updates only the rest of the block column; the blocks outside then take a
+// single update of depth kb (fewer passes over X than one update per block).
+// All products run on FP64 MFMA tiles (64 x 64 output, 4 waves of 32 x 32)
+// with both operands staged in LDS.
+//
+// Right-hand sides of group g (one factor L_g): cnt[g] matrices of n x w,
+// row-major, stored one after the other from entry e0[g]; the tiles see them
+// as one n x (cnt[g] w) matrix, so several items that share a factor fill
+// the 64-wide column tiles.  NULL tables mean one matrix per group.
 // ---------------------------------------------------------------------------
 constexpr int TP = NB + 2;  // LDS pitch of the solve tiles
 
@@ -304,122 +370,174 @@ __device__ __forceinline__ void tile_mma64(const double (*A)[TP], const double (
   }
 }
 
-// stage rows [r0, r0+64) x columns [c0, c0+64) of an n x w row-major matrix (zero outside)
-__device__ __forceinline__ void stage_rhs(double (*B)[TP], const double* __restrict__ X, int64_t n, int64_t w,
-                                          int64_t r0, int64_t c0) {
-  for (int e = threadIdx.x; e < NB * NB; e += 256) {
-    const int a = e / NB, c = e % NB;
-    B[a][c] = (r0 + a < n && c0 + c < w) ? X[(r0 + a) * w + c0 + c] : 0.0;
-  }
+struct RhsMap {
+  const int* e0;   // per group: first matrix (NULL: g)
+  const int* cnt;  // per group: matrices (NULL: 1)
+  int64_t w;       // columns per matrix
+};
+
+// offset of element (row 0, virtual column vcol) of group g, or -1 past the end
+__device__ __forceinline__ int64_t rhs_offset(const RhsMap& m, int g, int64_t n, int64_t vcol) {
+  const int e0 = m.e0 ? m.e0[g] : g;
+  const int cnt = m.cnt ? m.cnt[g] : 1;
+  if (vcol >= int64_t(cnt) * m.w) return -1;
+  return (e0 + vcol / m.w) * n * m.w + vcol % m.w;
 }
 
+__device__ __forceinline__ void zero_acc(dbl4 (&acc)[2][2]) {
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+}
+
+// Y rows of block J = Linv_J (or its transpose) times X rows of block J.
+// Workgroup = (64 virtual columns, group).
 template <bool TRANS>
 __global__ __launch_bounds__(256) void trsm_diag_kernel(const double* __restrict__ Linv, int64_t n,
                                                         const double* __restrict__ X, double* __restrict__ Y,
-                                                        int64_t w, int64_t J) {
+                                                        RhsMap m, int64_t J) {
   __shared__ double A[NB][TP];
   __shared__ double B[NB][TP];
-  const int u = blockIdx.y;
+  const int g = blockIdx.y;
+  const int64_t c0 = int64_t(blockIdx.x) * NB;
+  if (rhs_offset(m, g, n, c0) < 0) return;  // tile wholly past the group's columns
   const int64_t nblk = (n + NB - 1) / NB;
-  const double* Li = Linv + (size_t(u) * nblk + J) * NB * NB;
-  const double* Xu = X + size_t(u) * n * w;
-  double* Yu = Y + size_t(u) * n * w;
-  const int64_t c0 = int64_t(blockIdx.x) * NB, jb = J * NB;
+  const double* Li = Linv + (size_t(g) * nblk + J) * NB * NB;
+  const int64_t jb = J * NB, w = m.w;
   for (int e = threadIdx.x; e < NB * NB; e += 256) {
     const int a = e / NB, b = e % NB;
     A[a][b] = TRANS ? Li[b * NB + a] : Li[a * NB + b];
   }
-  stage_rhs(B, Xu, n, w, jb, c0);
+  {
+    const int c = threadIdx.x % NB;  // fixed per thread (256 is a multiple of 64)
+    const int64_t off = rhs_offset(m, g, n, c0 + c);
+    for (int a = threadIdx.x / NB; a < NB; a += 256 / NB)
+      B[a][c] = (off >= 0 && jb + a < n) ? X[off + (jb + a) * w] : 0.0;
+  }
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, wm = wv >> 1, wn = wv & 1;
   dbl4 acc[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+  zero_acc(acc);
   tile_mma64(A, B, acc, lane, wm, wn);
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int j = 0; j < 2; ++j) {
+    const int64_t off = rhs_offset(m, g, n, c0 + wn * 32 + j * 16 + (lane & 15));
+    if (off < 0) continue;
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int64_t row = jb + wm * 32 + i * 16 + (lane >> 4) + 4 * e;  // MFMA f64 output layout
-        const int64_t col = c0 + wn * 32 + j * 16 + (lane & 15);
-        if (row < n && col < w) Yu[row * w + col] = acc[i][j][e];
+        if (row < n) Y[off + row * w] = acc[i][j][e];
       }
+  }
 }
 
+// X rows of block T0 + blockIdx.x -= (coefficients of Y rows [k0, k1)) Y[k0:k1]:
+// forward  coefficient of Y row k in X row i: L[i][k];
+// backward coefficient: L[k][i].  K is consumed in 64-row slabs.
+// Workgroup = (block row, 64 virtual columns, group).
 template <bool TRANS>
 __global__ __launch_bounds__(256) void trsm_update_kernel(const double* __restrict__ L, int64_t n,
                                                           double* __restrict__ X, const double* __restrict__ Y,
-                                                          int64_t w, int64_t J) {
+                                                          RhsMap m, int64_t T0, int64_t k0, int64_t k1) {
   __shared__ double A[NB][TP];
   __shared__ double B[NB][TP];
-  const int u = blockIdx.z;
-  const double* Lu = L + size_t(u) * n * n;
-  double* Xu = X + size_t(u) * n * w;
-  const double* Yu = Y + size_t(u) * n * w;
-  const int64_t T = TRANS ? int64_t(blockIdx.x) : J + 1 + int64_t(blockIdx.x);
-  const int64_t tb = T * NB, jb = J * NB, c0 = int64_t(blockIdx.y) * NB;
-  for (int e = threadIdx.x; e < NB * NB; e += 256) {  // A[a][b]: coefficient of Y_J row b in X_T row a
-    const int a = e / NB, b = e % NB;
-    double v = 0.0;
-    if (tb + a < n && jb + b < n) v = TRANS ? Lu[(jb + b) * n + tb + a] : Lu[(tb + a) * n + jb + b];
-    A[a][b] = v;
-  }
-  stage_rhs(B, Yu, n, w, jb, c0);
-  __syncthreads();
+  const int g = blockIdx.z;
+  const int64_t c0 = int64_t(blockIdx.y) * NB;
+  if (rhs_offset(m, g, n, c0) < 0) return;
+  const double* Lg = L + size_t(g) * n * n;
+  const int64_t tb = (T0 + int64_t(blockIdx.x)) * NB, w = m.w;
+  const int c = threadIdx.x % NB;
+  const int64_t offc = rhs_offset(m, g, n, c0 + c);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, wm = wv >> 1, wn = wv & 1;
   dbl4 acc[2][2];
+  zero_acc(acc);
+  for (int64_t kb = k0; kb < k1; kb += NB) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < NB * NB; e += 256) {  // A[a][p]: coefficient of Y row kb+p in X row tb+a
+      // consecutive threads read consecutive elements of a row of L
+      const int a = TRANS ? e % NB : e / NB, p = TRANS ? e / NB : e % NB;
+      double v = 0.0;
+      if (tb + a < n && kb + p < k1) v = TRANS ? Lg[(kb + p) * n + tb + a] : Lg[(tb + a) * n + kb + p];
+      A[a][p] = v;
+    }
+    for (int p = threadIdx.x / NB; p < NB; p += 256 / NB)
+      B[p][c] = (offc >= 0 && kb + p < k1) ? Y[offc + (kb + p) * w] : 0.0;
+    __syncthreads();
+    tile_mma64(A, B, acc, lane, wm, wn);
+  }
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int j = 0; j < 2; ++j) {
+    const int64_t off = rhs_offset(m, g, n, c0 + wn * 32 + j * 16 + (lane & 15));
+    if (off < 0) continue;
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
-  tile_mma64(A, B, acc, lane, wm, wn);
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int64_t row = tb + wm * 32 + i * 16 + (lane >> 4) + 4 * e;
-        const int64_t col = c0 + wn * 32 + j * 16 + (lane & 15);
-        if (row < n && col < w) Xu[row * w + col] -= acc[i][j][e];
+        if (row < n) X[off + row * w] -= acc[i][j][e];
       }
+  }
 }
 
+// ng groups, each with at most max_cols virtual columns; block columns of kb
+// rows (a multiple of NB)
 int trsm_run(hipStream_t st, bool trans, const double* L, int64_t n, const double* Linv, double* X, double* Yout,
-             int64_t w, int nu) {
-  const int64_t nblk = (n + NB - 1) / NB;
-  const unsigned nch = unsigned((w + NB - 1) / NB);
-  for (int64_t b = 0; b < nblk; ++b) {
-    const int64_t J = trans ? (nblk - 1 - b) : b;
-    const unsigned ntrail = unsigned(trans ? J : (nblk - 1 - J));  // coupled block rows
+             RhsMap m, int64_t max_cols, int ng, int64_t kb) {
+  const int64_t nblk = (n + NB - 1) / NB, kbb = kb / NB;
+  const unsigned nct = unsigned((max_cols + NB - 1) / NB);
+  auto diag = [&](int64_t J) -> int {
     if (!trans)
-      trsm_diag_kernel<false><<<dim3(nch, unsigned(nu)), 256, 0, st>>>(Linv, n, X, Yout, w, J);
+      trsm_diag_kernel<false><<<dim3(nct, unsigned(ng)), 256, 0, st>>>(Linv, n, X, Yout, m, J);
     else
-      trsm_diag_kernel<true><<<dim3(nch, unsigned(nu)), 256, 0, st>>>(Linv, n, X, Yout, w, J);
+      trsm_diag_kernel<true><<<dim3(nct, unsigned(ng)), 256, 0, st>>>(Linv, n, X, Yout, m, J);
     DOPINF_LAUNCHED();
-    if (ntrail == 0) continue;
+    return DOPINF_OK;
+  };
+  // X blocks [t0, t1) -= coefficients x Y rows [k0, k1)
+  auto update = [&](int64_t t0, int64_t t1, int64_t k0, int64_t k1) -> int {
+    if (t1 <= t0) return DOPINF_OK;
+    const dim3 grid(unsigned(t1 - t0), nct, unsigned(ng));
     if (!trans)
-      trsm_update_kernel<false><<<dim3(ntrail, nch, unsigned(nu)), 256, 0, st>>>(L, n, X, Yout, w, J);
+      trsm_update_kernel<false><<<grid, 256, 0, st>>>(L, n, X, Yout, m, t0, k0, std::min<int64_t>(k1, n));
     else
-      trsm_update_kernel<true><<<dim3(ntrail, nch, unsigned(nu)), 256, 0, st>>>(L, n, X, Yout, w, J);
+      trsm_update_kernel<true><<<grid, 256, 0, st>>>(L, n, X, Yout, m, t0, k0, std::min<int64_t>(k1, n));
     DOPINF_LAUNCHED();
+    return DOPINF_OK;
+  };
+  int rc = DOPINF_OK;
+  if (!trans) {
+    for (int64_t cb = 0; cb < nblk && !rc; cb += kbb) {
+      const int64_t ce = std::min(cb + kbb, nblk);
+      for (int64_t J = cb; J < ce && !rc; ++J) {
+        rc = diag(J);
+        if (!rc) rc = update(J + 1, ce, J * NB, (J + 1) * NB);
+      }
+      if (!rc) rc = update(ce, nblk, cb * NB, ce * NB);
+    }
+  } else {
+    for (int64_t ce = nblk; ce > 0 && !rc; ce -= kbb) {
+      const int64_t cb = std::max<int64_t>(0, ce - kbb);
+      for (int64_t J = ce - 1; J >= cb && !rc; --J) {
+        rc = diag(J);
+        if (!rc) rc = update(cb, J, J * NB, (J + 1) * NB);
+      }
+      if (!rc) rc = update(0, cb, cb * NB, ce * NB);
+    }
   }
-  return DOPINF_OK;
+  return rc;
 }
 
 // ---------------------------------------------------------------------------
 // per pair: Schur complement solve and operator write-out
-// CV[u] = W^T [W | y] ((r+1) x (2r+1)); R2[u] = [P | Z] (s x (2r+1))
+// CV[u] = W^T [W | y] ((r+1) x (2r+1))
 // ---------------------------------------------------------------------------
 struct PairArgs {
   const double* GE;
   GroupGeom geo;
   const double* CV;
-  const double* R2;
   const int* ufail;
   const int* pair_u;     // pair -> local u index (within the chunk), -1: not in chunk
   const double* beta1;   // per pair
@@ -512,18 +630,35 @@ __global__ __launch_bounds__(256) void pair_solve_kernel(PairArgs a) {
   if (threadIdx.x == 0) a.status[p] = bad ? DOPINF_E_NOTSPD : DOPINF_OK;
 }
 
-// Quadratic columns of O for every pair: O[i][r + q] = Z[q][i] - sum_c P[q][c] X_l[c][i]
-// with [P | Z] = R2 of the pair's beta2 group.  Workgroup = (64 quadratic
-// columns, 64 modes, pair); FP64 MFMA over K = r + 1 in chunks of 64; the tile
-// goes through LDS so that rows of O are written contiguously.
-__global__ __launch_bounds__(256) void opq_kernel(PairArgs a) {
+// Quadratic columns of O, by back substitution per pair:
+//   L^T X_q = v,   v = y - W X_l   (s x r),
+// with [W | y] = R2 of the pair's beta2 group.  (Forming X_q = Z - P X_l from
+// precomputed P = L^{-T} W, Z = L^{-T} y is cheaper but cancels |P| |X_l| down
+// to |X_q| and is not backward stable.)  Pairs are batched in the order
+// border[b] (grouped by beta2 group), V and X_q are s x r per batch entry.
+struct QuadArgs {
+  const double* R2;     // [W | y] per u, s x (2r+1)
+  const double* XL;     // per pair: X_l ((r+1) x r)
+  const int* border;    // batch entry -> pair
+  const int* pair_u;    // pair -> u within the chunk
+  double* V;            // per batch entry: v, then (other buffer) X_q
+  const double* Xq;
+  double* O;            // group base, pair stride r*d
+  int64_t s;
+  int r;
+};
+
+// v = y - W X_l: workgroup = (64 quadratic rows, batch entry, 64 modes),
+// FP64 MFMA over K = r + 1 in chunks of 64
+__global__ __launch_bounds__(256) void vq_kernel(QuadArgs a) {
   __shared__ double At[NB][TP];
   __shared__ double Bt[NB][TP];
-  const int p = blockIdx.y;
+  const int bt = blockIdx.y;
+  const int p = a.border[bt];
   const int u = a.pair_u[p];
   if (u < 0) return;
-  const int r = a.geo.r, r1 = r + 1, w = 2 * r + 1;
-  const int64_t s = a.geo.s, d = ncols(r);
+  const int r = a.r, r1 = r + 1, w = 2 * r + 1;
+  const int64_t s = a.s;
   const int64_t q0 = int64_t(blockIdx.x) * NB;
   const int i0 = int(blockIdx.z) * NB;
   const double* R2u = a.R2 + size_t(u) * s * w;
@@ -538,32 +673,113 @@ __global__ __launch_bounds__(256) void opq_kernel(PairArgs a) {
     __syncthreads();
     for (int e = threadIdx.x; e < NB * NB; e += 256) {
       const int a_ = e / NB, b_ = e % NB;
-      At[a_][b_] = (q0 + a_ < s && k0 + b_ < r1) ? R2u[(q0 + a_) * w + k0 + b_] : 0.0;        // P[q][c]
-      Bt[a_][b_] = (k0 + a_ < r1 && i0 + b_ < r) ? XLp[(k0 + a_) * r + i0 + b_] : 0.0;       // X_l[c][i]
+      At[a_][b_] = (q0 + a_ < s && k0 + b_ < r1) ? R2u[(q0 + a_) * w + k0 + b_] : 0.0;   // W[q][c]
+      Bt[a_][b_] = (k0 + a_ < r1 && i0 + b_ < r) ? XLp[(k0 + a_) * r + i0 + b_] : 0.0;  // X_l[c][i]
     }
     __syncthreads();
     tile_mma64(At, Bt, acc, lane, wm, wn);
   }
-  __syncthreads();
-  // C[q][i] -> At[i][q] (transposed) for row-contiguous writes of O
+  double* Vb = a.V + size_t(bt) * s * r;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int qq = wm * 32 + i * 16 + (lane >> 4) + 4 * e;  // MFMA f64 output layout
-        const int ii = wn * 32 + j * 16 + (lane & 15);
-        At[ii][qq] = acc[i][j][e];
+        const int64_t q = q0 + wm * 32 + i * 16 + (lane >> 4) + 4 * e;  // MFMA f64 output layout
+        const int ii = i0 + wn * 32 + j * 16 + (lane & 15);
+        if (q < s && ii < r) Vb[q * r + ii] = R2u[q * w + r1 + ii] - acc[i][j][e];
       }
+}
+
+// O[i][r + q] = X_q[q][i], transposed through LDS so that rows of O are
+// written contiguously; workgroup = (64 quadratic columns, batch entry, 64 modes)
+__global__ __launch_bounds__(256) void oq_kernel(QuadArgs a) {
+  __shared__ double T[NB][NB + 1];
+  const int bt = blockIdx.y;
+  const int p = a.border[bt];
+  if (a.pair_u[p] < 0) return;
+  const int r = a.r;
+  const int64_t s = a.s, d = ncols(r);
+  const int64_t q0 = int64_t(blockIdx.x) * NB;
+  const int i0 = int(blockIdx.z) * NB;
+  const double* Xb = a.Xq + size_t(bt) * s * r;
+  for (int e = threadIdx.x; e < NB * NB; e += 256) {
+    const int qq = e / NB, ii = e % NB;
+    if (q0 + qq < s && i0 + ii < r) T[ii][qq] = Xb[(q0 + qq) * r + i0 + ii];
+  }
   __syncthreads();
   double* Op = a.O + size_t(p) * r * d;
   for (int e = threadIdx.x; e < NB * NB; e += 256) {
     const int ii = e / NB, qq = e % NB;
-    const int i = i0 + ii;
-    const int64_t q = q0 + qq;
-    if (i < r && q < s) Op[int64_t(i) * d + r + q] = R2u[q * w + r1 + i] - At[ii][qq];
+    if (q0 + qq < s && i0 + ii < r) Op[int64_t(i0 + ii) * d + r + q0 + qq] = T[ii][qq];
   }
+}
+
+// CV[u] = W^T [W | y] for every u of a chunk, R[u] = [W | y] (s x w, w = 2r + 1,
+// W = its first r + 1 columns).  Workgroup = (64 x 64 output tile, row split,
+// u): FP64 MFMA over 64-row slabs of R staged through LDS; each split writes a
+// partial tile and cv_reduce_kernel sums the splits in a fixed order.
+constexpr int CV_SPLIT_MAX = 8;
+
+__global__ __launch_bounds__(256) void cv_partial_kernel(const double* __restrict__ R, int64_t s, int r1, int w,
+                                                         int nspl, double* __restrict__ part) {
+  __shared__ double At[NB][TP];  // At[a][p] = W[k0 + p][i0 + a]
+  __shared__ double Bt[NB][TP];  // Bt[p][b] = R[k0 + p][c0 + b]
+  const int tcols = (w + NB - 1) / NB;
+  const int i0 = int(blockIdx.x / tcols) * NB, c0 = int(blockIdx.x % tcols) * NB;
+  const int sp = blockIdx.y, u = blockIdx.z;
+  const int64_t chunk = ((s + nspl - 1) / nspl + NB - 1) / NB * NB;
+  const int64_t lo = int64_t(sp) * chunk, hi = min<int64_t>(s, lo + chunk);
+  const double* Ru = R + size_t(u) * s * w;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, wm = wv >> 1, wn = wv & 1;
+  dbl4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+  for (int64_t k0 = lo; k0 < hi; k0 += NB) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < NB * NB; e += 256) {
+      const int p_ = e / NB, a_ = e % NB;
+      const bool in = k0 + p_ < hi;
+      At[a_][p_] = (in && i0 + a_ < r1) ? Ru[(k0 + p_) * w + i0 + a_] : 0.0;
+      Bt[p_][a_] = (in && c0 + a_ < w) ? Ru[(k0 + p_) * w + c0 + a_] : 0.0;
+    }
+    __syncthreads();
+    tile_mma64(At, Bt, acc, lane, wm, wn);
+  }
+  double* Pp = part + (size_t(u) * nspl + sp) * size_t(r1) * w;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = i0 + wm * 32 + i * 16 + (lane >> 4) + 4 * e;  // MFMA f64 output layout
+        const int col = c0 + wn * 32 + j * 16 + (lane & 15);
+        if (row < r1 && col < w) Pp[size_t(row) * w + col] = acc[i][j][e];
+      }
+}
+
+__global__ void cv_reduce_kernel(const double* __restrict__ part, int64_t per, int nspl, int64_t total,
+                                 double* __restrict__ CV) {
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < total; i += int64_t(gridDim.x) * 256) {
+    const int64_t u = i / per, e = i % per;
+    const double* pp = part + size_t(u) * nspl * per + e;
+    double acc = 0.0;
+    for (int sp = 0; sp < nspl; ++sp) acc += pp[size_t(sp) * per];
+    CV[i] = acc;
+  }
+}
+
+int cv_splits(int64_t s, int r1, int w, int nu) {
+  const int tiles = ((r1 + NB - 1) / NB) * ((w + NB - 1) / NB);
+  int n = 2048 / (tiles * nu);
+  const int64_t slabs = (s + NB - 1) / NB;
+  if (n > slabs) n = int(slabs);
+  if (n > CV_SPLIT_MAX) n = CV_SPLIT_MAX;
+  return n < 1 ? 1 : n;
 }
 
 __global__ void zero_ints_kernel(int* p, int64_t n) {
@@ -579,14 +795,30 @@ __global__ void copy_kernel(const double* __restrict__ a, double* __restrict__ b
 // host-side planning
 // ---------------------------------------------------------------------------
 struct InferLayout {
-  int rmax;
+  int rmax, uc;
   int64_t smax, dmax, m, lde, km1;
   size_t e_off, g_off, gram_off, gram_bytes;
   size_t chunk_off;  // per-chunk storage start
   size_t l_bytes, r_bytes, linv_bytes, cv_bytes;  // per u, at rmax
-  size_t cg_bytes;   // cross gram partials
+  size_t part_bytes;  // CV split partials of one chunk
+  size_t vq_bytes;    // per pair: v, and X_q, s x r at rmax
   size_t misc_off;
   size_t total;
+};
+
+// Every table the kernels read from host data (beta values, the pair -> beta2
+// group map of every chunk) has a fixed place in the workspace, written once
+// by infer_upload; infer_enqueue then issues kernels only, so a stream capture
+// of it replays without host memory.
+struct MiscPtrs {
+  double* b2dev;  // distinct beta2 values (n_u <= n_pairs)
+  int* ufail;     // per u of a chunk
+  int* pair_u;    // per chunk: pair -> u within the chunk, -1 outside
+  int* border;    // per chunk: batch entry -> pair (pairs of the chunk, by u)
+  int* ue0;       // per chunk: first batch entry of u
+  int* ucnt;      // per chunk: batch entries of u
+  double* b1dev;  // per pair
+  double* XL;     // per pair: X_l ((r+1) x r)
 };
 
 InferLayout layout(int64_t k, int n_r, const int* r_list, int n_pairs) {
@@ -594,6 +826,7 @@ InferLayout layout(int64_t k, int n_r, const int* r_list, int n_pairs) {
   int rmax = 0;
   for (int g = 0; g < n_r; ++g) rmax = r_list[g] > rmax ? r_list[g] : rmax;
   L.rmax = rmax;
+  L.uc = n_pairs < UCHUNK ? n_pairs : UCHUNK;
   L.smax = nquad(rmax);
   L.dmax = ncols(rmax);
   L.m = L.dmax + rmax;
@@ -612,32 +845,383 @@ InferLayout layout(int64_t k, int n_r, const int* r_list, int n_pairs) {
   L.r_bytes = size_t(s) * w * sizeof(double);
   L.linv_bytes = size_t(nblk) * NB * NB * sizeof(double);
   L.cv_bytes = size_t(rmax + 1) * w * sizeof(double);
-  L.cg_bytes = 0;
-  for (int g = 0; g < n_r; ++g) {
-    const int64_t rg = r_list[g];
-    const size_t b = cross_gram_workspace_internal(nquad(rg), rg + 1, 2 * rg + 1);
-    if (b > L.cg_bytes) L.cg_bytes = b;
-  }
-  const int uc = n_pairs < UCHUNK ? n_pairs : UCHUNK;
+  L.part_bytes = size_t(L.uc) * CV_SPLIT_MAX * L.cv_bytes;
+  L.vq_bytes = size_t(s) * rmax * sizeof(double);
+  const int uc = L.uc;
   L.chunk_off = (c.used + 255) & ~size_t(255);
   c.take<char>(uc * L.l_bytes);
   c.take<char>(uc * L.r_bytes);
   c.take<char>(uc * L.r_bytes);
-  c.take<char>(uc * L.r_bytes);
   c.take<char>(uc * L.linv_bytes);
   c.take<char>(uc * L.cv_bytes);
-  c.take<char>(L.cg_bytes);
+  c.take<char>(L.part_bytes);
+  c.take<char>(size_t(n_pairs) * L.vq_bytes);
+  c.take<char>(size_t(n_pairs) * L.vq_bytes);
   L.misc_off = (c.used + 255) & ~size_t(255);
-  c.take<double>(size_t(uc));       // beta2 per u
-  c.take<int>(size_t(uc));          // fail flag per u
-  c.take<int>(size_t(n_pairs));     // pair -> u
-  c.take<double>(size_t(n_pairs));  // beta1 per pair
+  const int max_chunks = (n_pairs + uc - 1) / uc;
+  c.take<double>(size_t(n_pairs));                    // distinct beta2
+  c.take<int>(size_t(uc));                            // fail flag per u
+  c.take<int>(size_t(max_chunks) * n_pairs);          // pair -> u, per chunk
+  c.take<int>(size_t(max_chunks) * n_pairs);          // batch entry -> pair, per chunk
+  c.take<int>(size_t(max_chunks) * uc);               // first batch entry per u, per chunk
+  c.take<int>(size_t(max_chunks) * uc);               // batch entries per u, per chunk
+  c.take<double>(size_t(n_pairs));                    // beta1 per pair
   c.take<double>(size_t(n_pairs) * (rmax + 1) * rmax);  // X_l per pair
   L.total = c.used;
   return L;
 }
 
+MiscPtrs misc_ptrs(const InferLayout& L, void* ws, int n_pairs) {
+  Carver mc(static_cast<char*>(ws) + L.misc_off, L.total - L.misc_off);
+  MiscPtrs m{};
+  const int max_chunks = (n_pairs + L.uc - 1) / L.uc;
+  m.b2dev = mc.take<double>(size_t(n_pairs));
+  m.ufail = mc.take<int>(size_t(L.uc));
+  m.pair_u = mc.take<int>(size_t(max_chunks) * n_pairs);
+  m.border = mc.take<int>(size_t(max_chunks) * n_pairs);
+  m.ue0 = mc.take<int>(size_t(max_chunks) * L.uc);
+  m.ucnt = mc.take<int>(size_t(max_chunks) * L.uc);
+  m.b1dev = mc.take<double>(size_t(n_pairs));
+  m.XL = mc.take<double>(size_t(n_pairs) * (L.rmax + 1) * L.rmax);
+  return m;
+}
+
+struct InferPlan {
+  InferLayout L;
+  int64_t k;
+  int n_r, n_pairs;
+  std::vector<int> r_list;
+  std::vector<double> beta1, b2u;  // per pair; distinct beta2 in first-appearance order
+  std::vector<int> pu;             // n_chunks x n_pairs
+  std::vector<int> border;         // n_chunks x n_pairs (the first nbc[c] entries used)
+  std::vector<int> ue0, ucnt;      // n_chunks x uc
+  std::vector<int> nbc, npu_max;   // per chunk: pairs, most pairs of one u
+  int n_u, n_chunks;
+};
+
+// block-column widths of the s x s Cholesky and of the triangular solves
+// with its factor: the tuned values, else the defaults
+int64_t chol_kb(int64_t s) {
+  const int v = tune::get(DOPINF_TUNE_CHOL_KB, s);
+  return v > 0 ? v : 4 * NB;
+}
+int64_t trsm_kb(int64_t s) {
+  const int v = tune::get(DOPINF_TUNE_TRSM_KB, s);
+  return v > 0 ? v : 4 * NB;
+}
+
+int infer_plan(int64_t k, int64_t ldqh, int n_r, const int* r_list_h, int n_pairs, const double* beta1_h,
+               const double* beta2_h, size_t ws_bytes, const void* ws, InferPlan& P) {
+  DOPINF_REQUIRE(r_list_h && beta1_h && beta2_h, "NULL argument");
+  DOPINF_REQUIRE(k >= 2 && ldqh >= k, "need k >= 2 and ldqh >= k");
+  DOPINF_REQUIRE(n_r >= 1 && n_pairs >= 1, "need n_r >= 1 and n_pairs >= 1");
+  for (int g = 0; g < n_r; ++g) DOPINF_REQUIRE(r_list_h[g] >= 1 && r_list_h[g] <= 512, "r must be in [1, 512]");
+  for (int p = 0; p < n_pairs; ++p)
+    DOPINF_REQUIRE(beta1_h[p] >= 0.0 && beta2_h[p] >= 0.0, "regularization parameters must be >= 0");
+  P.L = layout(k, n_r, r_list_h, n_pairs);
+  if (!ws || ws_bytes < P.L.total)
+    return fail(DOPINF_E_WORKSPACE, "workspace of %zu bytes needed, %zu given", P.L.total, ws_bytes);
+  int dev = 0, maxlds = 0;
+  DOPINF_HIP(hipGetDevice(&dev));
+  DOPINF_HIP(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  {
+    const size_t need = size_t(P.L.rmax + 1) * (2 * P.L.rmax + 1) * sizeof(double) + 1024;
+    DOPINF_REQUIRE(need <= size_t(maxlds), "r too large for the per-pair LDS solve");
+    if (need > 65536)
+      DOPINF_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(pair_solve_kernel),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(need)));
+  }
+  P.k = k;
+  P.n_r = n_r;
+  P.n_pairs = n_pairs;
+  P.r_list.assign(r_list_h, r_list_h + n_r);
+  P.beta1.assign(beta1_h, beta1_h + n_pairs);
+  // distinct beta2 values (exact equality), in first-appearance order
+  std::vector<int> pair_uid(n_pairs);
+  P.b2u.clear();
+  for (int p = 0; p < n_pairs; ++p) {
+    int id = -1;
+    for (size_t q = 0; q < P.b2u.size(); ++q)
+      if (P.b2u[q] == beta2_h[p]) {
+        id = int(q);
+        break;
+      }
+    if (id < 0) {
+      id = int(P.b2u.size());
+      P.b2u.push_back(beta2_h[p]);
+    }
+    pair_uid[p] = id;
+  }
+  P.n_u = int(P.b2u.size());
+  const int uc = P.L.uc;
+  P.n_chunks = (P.n_u + uc - 1) / uc;
+  P.pu.assign(size_t(P.n_chunks) * n_pairs, -1);
+  P.border.assign(size_t(P.n_chunks) * n_pairs, 0);
+  P.ue0.assign(size_t(P.n_chunks) * uc, 0);
+  P.ucnt.assign(size_t(P.n_chunks) * uc, 0);
+  P.nbc.assign(P.n_chunks, 0);
+  P.npu_max.assign(P.n_chunks, 0);
+  for (int c = 0; c < P.n_chunks; ++c) {
+    const int u0 = c * uc;
+    for (int p = 0; p < n_pairs; ++p)
+      if (pair_uid[p] >= u0 && pair_uid[p] < u0 + uc) P.pu[size_t(c) * n_pairs + p] = pair_uid[p] - u0;
+    // batch order: by u, then by pair, so that entries sharing a factor are adjacent
+    int nb = 0;
+    for (int u = 0; u < uc; ++u) {
+      P.ue0[size_t(c) * uc + u] = nb;
+      for (int p = 0; p < n_pairs; ++p)
+        if (P.pu[size_t(c) * n_pairs + p] == u) P.border[size_t(c) * n_pairs + nb++] = p;
+      const int cnt = nb - P.ue0[size_t(c) * uc + u];
+      P.ucnt[size_t(c) * uc + u] = cnt;
+      if (cnt > P.npu_max[c]) P.npu_max[c] = cnt;
+    }
+    P.nbc[c] = nb;
+  }
+  return DOPINF_OK;
+}
+
+// Host tables into the workspace.  hipMemcpyAsync from pageable memory
+// returns once the source has been staged, so the plan may be dropped after.
+int infer_upload(hipStream_t st, const InferPlan& P, void* ws) {
+  const MiscPtrs m = misc_ptrs(P.L, ws, P.n_pairs);
+  DOPINF_HIP(hipMemcpyAsync(m.b2dev, P.b2u.data(), sizeof(double) * P.n_u, hipMemcpyHostToDevice, st));
+  DOPINF_HIP(hipMemcpyAsync(m.pair_u, P.pu.data(), sizeof(int) * P.pu.size(), hipMemcpyHostToDevice, st));
+  DOPINF_HIP(hipMemcpyAsync(m.border, P.border.data(), sizeof(int) * P.border.size(), hipMemcpyHostToDevice, st));
+  DOPINF_HIP(hipMemcpyAsync(m.ue0, P.ue0.data(), sizeof(int) * P.ue0.size(), hipMemcpyHostToDevice, st));
+  DOPINF_HIP(hipMemcpyAsync(m.ucnt, P.ucnt.data(), sizeof(int) * P.ucnt.size(), hipMemcpyHostToDevice, st));
+  DOPINF_HIP(hipMemcpyAsync(m.b1dev, P.beta1.data(), sizeof(double) * P.n_pairs, hipMemcpyHostToDevice, st));
+  return DOPINF_OK;
+}
+
+// E and its Gram G_E
+int infer_gram(hipStream_t st, const InferPlan& P, const double* Qhat, int64_t ldqh, void* ws) {
+  const InferLayout& L = P.L;
+  char* base = static_cast<char*>(ws);
+  double* E = reinterpret_cast<double*>(base + L.e_off);
+  double* GE = reinterpret_cast<double*>(base + L.g_off);
+  dim3 grid(unsigned((L.km1 + 255) / 256), unsigned(L.m));
+  assemble_kernel<<<grid, 256, 0, st>>>(Qhat, ldqh, P.k, L.rmax, E, L.lde);
+  DOPINF_LAUNCHED();
+  return gram_f64_internal(st, E, L.km1, L.m, L.lde, nullptr, nullptr, 0, nullptr, GE, L.m, base + L.gram_off,
+                           L.gram_bytes);
+}
+
+struct ChunkBufs {
+  GroupGeom geo;
+  int64_t s, w, r1;
+  double *Lq, *R, *R2, *Linv, *CV, *part, *V, *Xq;
+};
+
+ChunkBufs chunk_bufs(const InferPlan& P, int g, void* ws) {
+  const InferLayout& L = P.L;
+  ChunkBufs b{};
+  b.geo.r = P.r_list[g];
+  b.geo.rmax = L.rmax;
+  b.geo.s = nquad(b.geo.r);
+  b.geo.m = L.m;
+  b.geo.dmax = L.dmax;
+  b.s = b.geo.s;
+  b.w = 2 * b.geo.r + 1;
+  b.r1 = b.geo.r + 1;
+  const int uc = L.uc;
+  // per-u storage at this r (packed tighter than at rmax)
+  const int64_t nblk = (b.s + NB - 1) / NB;
+  char* ch = static_cast<char*>(ws) + L.chunk_off;
+  Carver cc(ch, ~size_t(0));
+  b.Lq = cc.take<double>(size_t(uc) * b.s * b.s);
+  b.R = cc.take<double>(size_t(uc) * b.s * b.w);
+  b.R2 = cc.take<double>(size_t(uc) * b.s * b.w);
+  b.Linv = cc.take<double>(size_t(uc) * nblk * NB * NB);
+  b.CV = cc.take<double>(size_t(uc) * b.r1 * b.w);
+  b.part = cc.take<double>(size_t(uc) * CV_SPLIT_MAX * b.r1 * b.w);
+  b.V = cc.take<double>(size_t(P.n_pairs) * b.s * b.geo.r);
+  b.Xq = cc.take<double>(size_t(P.n_pairs) * b.s * b.geo.r);
+  return b;
+}
+
+// the chunk's beta2 groups: G_qq + beta2 I gathered and factored with block
+// columns of width kb
+int chunk_factor(hipStream_t st, const InferPlan& P, const ChunkBufs& b, int c, int nu, int64_t kb, void* ws) {
+  const MiscPtrs m = misc_ptrs(P.L, ws, P.n_pairs);
+  const double* GE = reinterpret_cast<const double*>(static_cast<char*>(ws) + P.L.g_off);
+  zero_ints_kernel<<<1, 256, 0, st>>>(m.ufail, P.L.uc);
+  DOPINF_LAUNCHED();
+  dim3 grid(unsigned((b.s + 255) / 256 > 64 ? 64 : (b.s + 255) / 256), unsigned(b.s), unsigned(nu));
+  gather_qq_kernel<<<grid, 256, 0, st>>>(GE, b.geo, m.b2dev + size_t(c) * P.L.uc, b.Lq, b.R);
+  DOPINF_LAUNCHED();
+  return cholesky_run(st, b.Lq, b.s, b.Linv, m.ufail, nu, kb);
+}
+
+// [W | y] = L^{-1} [G_ql | B_q], CV = W^T [W | y], and per pair the Schur
+// complement solve for X_l (linear and constant columns of O, and XL)
+int chunk_linear(hipStream_t st, const InferPlan& P, const ChunkBufs& b, int g, int c, int nu, int64_t kb, double* O,
+                 int* status, void* ws) {
+  const MiscPtrs m = misc_ptrs(P.L, ws, P.n_pairs);
+  const double* GE = reinterpret_cast<const double*>(static_cast<char*>(ws) + P.L.g_off);
+  const int64_t s = b.s, w = b.w, r1 = b.r1;
+  int rc = trsm_run(st, false, b.Lq, s, b.Linv, b.R, b.R2, RhsMap{nullptr, nullptr, w}, w, nu, kb);
+  if (rc) return rc;
+  {
+    const int nspl = cv_splits(s, int(r1), int(w), nu);
+    const unsigned tiles = unsigned(((r1 + NB - 1) / NB) * ((w + NB - 1) / NB));
+    cv_partial_kernel<<<dim3(tiles, unsigned(nspl), unsigned(nu)), 256, 0, st>>>(b.R2, s, int(r1), int(w), nspl,
+                                                                               b.part);
+    DOPINF_LAUNCHED();
+    const int64_t total = int64_t(nu) * r1 * w;
+    cv_reduce_kernel<<<unsigned((total + 255) / 256), 256, 0, st>>>(b.part, r1 * w, nspl, total, b.CV);
+    DOPINF_LAUNCHED();
+  }
+  PairArgs pa{};
+  pa.GE = GE;
+  pa.geo = b.geo;
+  pa.CV = b.CV;
+  pa.ufail = m.ufail;
+  pa.pair_u = m.pair_u + size_t(c) * P.n_pairs;
+  pa.beta1 = m.b1dev;
+  pa.O = O + dopinf_operator_offset(P.n_r, P.r_list.data(), P.n_pairs, g * P.n_pairs);
+  pa.status = status + g * P.n_pairs;
+  pa.n_pairs = P.n_pairs;
+  pa.XL = m.XL;
+  const size_t smem = size_t(r1) * (r1 + b.geo.r) * sizeof(double);
+  pair_solve_kernel<<<P.n_pairs, 256, smem, st>>>(pa);
+  DOPINF_LAUNCHED();
+  return DOPINF_OK;
+}
+
+QuadArgs quad_args(const InferPlan& P, const ChunkBufs& b, int g, int c, double* O, void* ws) {
+  const MiscPtrs m = misc_ptrs(P.L, ws, P.n_pairs);
+  QuadArgs qa{};
+  qa.R2 = b.R2;
+  qa.XL = m.XL;
+  qa.border = m.border + size_t(c) * P.n_pairs;
+  qa.pair_u = m.pair_u + size_t(c) * P.n_pairs;
+  qa.V = b.V;
+  qa.Xq = b.Xq;
+  qa.O = O ? O + dopinf_operator_offset(P.n_r, P.r_list.data(), P.n_pairs, g * P.n_pairs) : nullptr;
+  qa.s = b.s;
+  qa.r = b.geo.r;
+  return qa;
+}
+
+dim3 quad_grid(const InferPlan& P, const ChunkBufs& b, int c) {
+  return dim3(unsigned((b.s + NB - 1) / NB), unsigned(P.nbc[c]), unsigned((b.geo.r + NB - 1) / NB));
+}
+
+// v = y - W X_l per pair, then L^T X_q = v with the pairs of each beta2 group
+// side by side as one right-hand side
+int chunk_quad_solve(hipStream_t st, const InferPlan& P, const ChunkBufs& b, int g, int c, int nu, int64_t kb,
+                     void* ws) {
+  const MiscPtrs m = misc_ptrs(P.L, ws, P.n_pairs);
+  const QuadArgs qa = quad_args(P, b, g, c, nullptr, ws);
+  vq_kernel<<<quad_grid(P, b, c), 256, 0, st>>>(qa);
+  DOPINF_LAUNCHED();
+  const RhsMap rm{m.ue0 + size_t(c) * P.L.uc, m.ucnt + size_t(c) * P.L.uc, b.geo.r};
+  return trsm_run(st, true, b.Lq, b.s, b.Linv, b.V, b.Xq, rm, int64_t(P.npu_max[c]) * b.geo.r, nu, kb);
+}
+
+int infer_enqueue(hipStream_t st, const InferPlan& P, const double* Qhat, int64_t ldqh, double* O, int* status,
+                  void* ws) {
+  int rc = infer_gram(st, P, Qhat, ldqh, ws);
+  if (rc) return rc;
+  const int uc = P.L.uc;
+  for (int g = 0; g < P.n_r; ++g) {
+    const ChunkBufs b = chunk_bufs(P, g, ws);
+    const int64_t kc = chol_kb(b.s), kt = trsm_kb(b.s);
+    for (int c = 0; c < P.n_chunks; ++c) {
+      const int nu = (P.n_u - c * uc) < uc ? (P.n_u - c * uc) : uc;
+      rc = chunk_factor(st, P, b, c, nu, kc, ws);
+      if (!rc) rc = chunk_linear(st, P, b, g, c, nu, kt, O, status, ws);
+      if (rc) return rc;
+      if (P.nbc[c] == 0) continue;
+      rc = chunk_quad_solve(st, P, b, g, c, nu, kt, ws);
+      if (rc) return rc;
+      oq_kernel<<<quad_grid(P, b, c), 256, 0, st>>>(quad_args(P, b, g, c, O, ws));
+      DOPINF_LAUNCHED();
+    }
+  }
+  return DOPINF_OK;
+}
+
 }  // namespace
+
+// Candidate block-column widths, for the beta2-group Cholesky and for the
+// triangular solves with its factor.
+constexpr int kKbCand[] = {64, 128, 256, 512};
+constexpr int kNumKbCand = 4;
+
+// Minimum over two timed runs of fn (after one warm-up run) on stream st.
+template <class F>
+int time_min(hipStream_t st, hipEvent_t e0, hipEvent_t e1, F&& fn, float& out) {
+  out = -1.f;
+  for (int rep = 0; rep < 3; ++rep) {
+    DOPINF_HIP(hipEventRecord(e0, st));
+    const int rc = fn();
+    if (rc) return rc;
+    DOPINF_HIP(hipEventRecord(e1, st));
+    DOPINF_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    DOPINF_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (rep > 0 && (out < 0.f || ms < out)) out = ms;
+  }
+  return DOPINF_OK;
+}
+
+// For every group, on the first beta2 chunk with the sweep's own data: time
+// the factorization (gather + Cholesky) at every width and keep the fastest;
+// then, with that factor, time the per-pair back substitution (v rebuilt
+// every run, since the solve consumes it) at every depth and keep the
+// fastest.  The stored values are then used by the complete infer that ends
+// the call.
+int infer_autotune(hipStream_t st, const InferPlan& P, const double* Qhat, int64_t ldqh, double* O, int* status,
+                   void* ws, float* times_h) {
+  int rc = infer_upload(st, P, ws);
+  if (!rc) rc = infer_gram(st, P, Qhat, ldqh, ws);
+  if (rc) return rc;
+  hipEvent_t e0, e1;
+  DOPINF_HIP(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(DOPINF_E_HIP, "hipEventCreate failed");
+  }
+  const int uc = P.L.uc;
+  const int nu = P.n_u < uc ? P.n_u : uc;
+  for (int g = 0; g < P.n_r && !rc; ++g) {
+    const ChunkBufs b = chunk_bufs(P, g, ws);
+    float* tg = times_h ? times_h + size_t(g) * 2 * kNumKbCand : nullptr;
+    int best = 0;
+    float best_t = 0.f;
+    for (int ci = 0; ci < kNumKbCand && !rc; ++ci) {
+      float t = 0.f;
+      rc = time_min(st, e0, e1, [&] { return chunk_factor(st, P, b, 0, nu, kKbCand[ci], ws); }, t);
+      if (tg) tg[ci] = t;
+      if (!rc && (best == 0 || t < best_t)) {
+        best = kKbCand[ci];
+        best_t = t;
+      }
+    }
+    if (rc) break;
+    tune::set(DOPINF_TUNE_CHOL_KB, b.s, best);
+    rc = chunk_factor(st, P, b, 0, nu, best, ws);
+    if (!rc) rc = chunk_linear(st, P, b, g, 0, nu, trsm_kb(b.s), O, status, ws);
+    if (rc || P.nbc[0] == 0) continue;
+    best = 0;
+    for (int ci = 0; ci < kNumKbCand && !rc; ++ci) {
+      float t = 0.f;
+      rc = time_min(st, e0, e1, [&] { return chunk_quad_solve(st, P, b, g, 0, nu, kKbCand[ci], ws); }, t);
+      if (tg) tg[kNumKbCand + ci] = t;
+      if (!rc && (best == 0 || t < best_t)) {
+        best = kKbCand[ci];
+        best_t = t;
+      }
+    }
+    if (!rc) tune::set(DOPINF_TUNE_TRSM_KB, b.s, best);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (!rc) rc = infer_enqueue(st, P, Qhat, ldqh, O, status, ws);
+  return rc;
+}
+
 }  // namespace dopinf
 
 using namespace dopinf;
@@ -661,148 +1245,108 @@ extern "C" size_t dopinf_infer_workspace(int64_t k, int n_r, const int* r_list_h
 extern "C" int dopinf_infer(void* stream, const double* Qhat, int64_t ldqh, int64_t k, int n_r, const int* r_list_h,
                             int n_pairs, const double* beta1_h, const double* beta2_h, double* O, int* status,
                             void* ws, size_t ws_bytes) {
-  DOPINF_REQUIRE(Qhat && O && status && r_list_h && beta1_h && beta2_h, "NULL argument");
-  DOPINF_REQUIRE(k >= 2 && ldqh >= k, "need k >= 2 and ldqh >= k");
-  DOPINF_REQUIRE(n_r >= 1 && n_pairs >= 1, "need n_r >= 1 and n_pairs >= 1");
-  for (int g = 0; g < n_r; ++g) DOPINF_REQUIRE(r_list_h[g] >= 1 && r_list_h[g] <= 512, "r must be in [1, 512]");
-  for (int p = 0; p < n_pairs; ++p)
-    DOPINF_REQUIRE(beta1_h[p] >= 0.0 && beta2_h[p] >= 0.0, "regularization parameters must be >= 0");
-  const InferLayout L = layout(k, n_r, r_list_h, n_pairs);
-  if (!ws || ws_bytes < L.total) return fail(DOPINF_E_WORKSPACE, "workspace of %zu bytes needed, %zu given", L.total, ws_bytes);
-  int dev = 0, maxlds = 0;
-  DOPINF_HIP(hipGetDevice(&dev));
-  DOPINF_HIP(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-  {
-    const size_t need = size_t(L.rmax + 1) * (2 * L.rmax + 1) * sizeof(double) + 1024;
-    DOPINF_REQUIRE(need <= size_t(maxlds), "r too large for the per-pair LDS solve");
-    if (need > 65536)
-      DOPINF_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(pair_solve_kernel),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(need)));
-  }
+  DOPINF_REQUIRE(Qhat && O && status, "NULL argument");
+  InferPlan P;
+  int rc = infer_plan(k, ldqh, n_r, r_list_h, n_pairs, beta1_h, beta2_h, ws_bytes, ws, P);
+  if (rc) return rc;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  char* base = static_cast<char*>(ws);
-  double* E = reinterpret_cast<double*>(base + L.e_off);
-  double* GE = reinterpret_cast<double*>(base + L.g_off);
+  rc = infer_upload(st, P, ws);
+  if (rc) return rc;
+  return infer_enqueue(st, P, Qhat, ldqh, O, status, ws);
+}
 
-  // E and its Gram
-  {
-    dim3 grid(unsigned((L.km1 + 255) / 256), unsigned(L.m));
-    assemble_kernel<<<grid, 256, 0, st>>>(Qhat, ldqh, k, L.rmax, E, L.lde);
-    DOPINF_LAUNCHED();
-    int rc = gram_f64_internal(st, E, L.km1, L.m, L.lde, nullptr, nullptr, 0, nullptr, GE, L.m,
-                               base + L.gram_off, L.gram_bytes);
+extern "C" int dopinf_autotune_infer(void* stream, const double* Qhat, int64_t ldqh, int64_t k, int n_r,
+                                     const int* r_list_h, int n_pairs, const double* beta1_h, const double* beta2_h,
+                                     double* O, int* status, void* ws, size_t ws_bytes, float* times_h) {
+  DOPINF_REQUIRE(Qhat && O && status, "NULL argument");
+  InferPlan P;
+  int rc = infer_plan(k, ldqh, n_r, r_list_h, n_pairs, beta1_h, beta2_h, ws_bytes, ws, P);
+  if (rc) return rc;
+  return infer_autotune(static_cast<hipStream_t>(stream), P, Qhat, ldqh, O, status, ws, times_h);
+}
+
+extern "C" int dopinf_autotune_candidates(int param, int* values_h, int max_values) {
+  DOPINF_REQUIRE(param == DOPINF_TUNE_CHOL_KB || param == DOPINF_TUNE_TRSM_KB, "unknown tuning parameter %d", param);
+  for (int i = 0; i < kNumKbCand && i < max_values && values_h; ++i) values_h[i] = kKbCand[i];
+  return kNumKbCand;
+}
+
+// ---------------------------------------------------------------------------
+// the sweep (infer + rollout) as one instantiated graph
+// ---------------------------------------------------------------------------
+struct dopinf_sweep_s {
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
+extern "C" size_t dopinf_sweep_workspace(int64_t k, int n_r, const int* r_list_h, int n_pairs) {
+  const size_t a = dopinf_infer_workspace(k, n_r, r_list_h, n_pairs);
+  const size_t b = dopinf_rollout_workspace(n_r, r_list_h, n_pairs, k);
+  if (!a || !b) return 0;
+  return round_up(a, 256) + b;
+}
+
+extern "C" int dopinf_sweep_create(void* stream, const double* Qhat, int64_t ldqh, int64_t k, int n_r,
+                                   const int* r_list_h, int n_pairs, const double* beta1_h, const double* beta2_h,
+                                   int n_states, double max_growth, unsigned flags, double* O, int* status,
+                                   double* train_err, double* growth, int* outcome, int* best, void* ws,
+                                   size_t ws_bytes, dopinf_sweep_t* sweep_out) {
+  DOPINF_REQUIRE(sweep_out, "NULL sweep_out");
+  *sweep_out = nullptr;
+  DOPINF_REQUIRE(stream, "the null stream cannot be captured; pass a stream created by the caller");
+  DOPINF_REQUIRE(Qhat && O && status && train_err && growth && outcome && best, "NULL argument");
+  DOPINF_REQUIRE((flags & ~DOPINF_SWEEP_AUTOTUNE) == 0, "unknown flag bits");
+  DOPINF_REQUIRE(n_states >= 1 && max_growth > 0.0, "need n_states >= 1 and max_growth > 0");
+  const size_t need = dopinf_sweep_workspace(k, n_r, r_list_h, n_pairs);
+  DOPINF_REQUIRE(need > 0, "invalid sizes");
+  if (!ws || ws_bytes < need) return fail(DOPINF_E_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+  const size_t ia = round_up(dopinf_infer_workspace(k, n_r, r_list_h, n_pairs), 256);
+  char* wsi = static_cast<char*>(ws);
+  char* wsr = wsi + ia;
+  InferPlan P;
+  int rc = infer_plan(k, ldqh, n_r, r_list_h, n_pairs, beta1_h, beta2_h, ia, wsi, P);
+  if (rc) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (flags & DOPINF_SWEEP_AUTOTUNE) {
+    rc = infer_autotune(st, P, Qhat, ldqh, O, status, wsi, nullptr);
     if (rc) return rc;
   }
-
-  // distinct beta2 values (exact equality), in first-appearance order
-  std::vector<double> b2u;
-  std::vector<int> pair_uid(n_pairs);
-  for (int p = 0; p < n_pairs; ++p) {
-    int id = -1;
-    for (size_t q = 0; q < b2u.size(); ++q)
-      if (b2u[q] == beta2_h[p]) {
-        id = int(q);
-        break;
-      }
-    if (id < 0) {
-      id = int(b2u.size());
-      b2u.push_back(beta2_h[p]);
-    }
-    pair_uid[p] = id;
+  rc = infer_upload(st, P, wsi);
+  if (rc) return rc;
+  DOPINF_HIP(hipStreamSynchronize(st));
+  DOPINF_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+  rc = infer_enqueue(st, P, Qhat, ldqh, O, status, wsi);
+  if (!rc)
+    rc = dopinf_rollout(stream, n_r, r_list_h, n_pairs, O, Qhat, ldqh, k, n_states, max_growth, DOPINF_ROLLOUT_ONE_WG,
+                        status, nullptr, train_err, growth, outcome, best, wsr, ws_bytes - ia);
+  hipGraph_t graph = nullptr;
+  const hipError_t ec = hipStreamEndCapture(st, &graph);
+  if (rc || ec != hipSuccess) {
+    if (ec == hipSuccess && graph) (void)hipGraphDestroy(graph);
+    (void)hipGetLastError();
+    return rc ? rc : fail(DOPINF_E_HIP, "hipStreamEndCapture failed: %s", hipGetErrorString(ec));
   }
-  const int n_u = int(b2u.size());
-  const int uc = n_pairs < UCHUNK ? n_pairs : UCHUNK;
-
-  char* ch = base + L.chunk_off;
-  Carver mc(base + L.misc_off, ws_bytes - L.misc_off);
-  double* b2dev = mc.take<double>(size_t(uc));
-  int* ufail = mc.take<int>(size_t(uc));
-  int* pair_u = mc.take<int>(size_t(n_pairs));
-  double* b1dev = mc.take<double>(size_t(n_pairs));
-  double* XL = mc.take<double>(size_t(n_pairs) * (L.rmax + 1) * L.rmax);
-  DOPINF_HIP(hipMemcpyAsync(b1dev, beta1_h, sizeof(double) * n_pairs, hipMemcpyHostToDevice, st));
-
-  std::vector<int> pu(n_pairs);
-  for (int g = 0; g < n_r; ++g) {
-    GroupGeom geo{};
-    geo.r = r_list_h[g];
-    geo.rmax = L.rmax;
-    geo.s = nquad(geo.r);
-    geo.m = L.m;
-    geo.dmax = L.dmax;
-    const int64_t s = geo.s, w = 2 * geo.r + 1, r1 = geo.r + 1;
-    const int64_t nblk = (s + NB - 1) / NB;
-    // per-u storage at this r (packed tighter than at rmax)
-    const size_t lb = size_t(s) * s * sizeof(double), rb = size_t(s) * w * sizeof(double);
-    const size_t lib = size_t(nblk) * NB * NB * sizeof(double), cvb = size_t(r1) * w * sizeof(double);
-    double* Lq = reinterpret_cast<double*>(ch);
-    double* R = reinterpret_cast<double*>(ch + uc * lb);
-    double* R2 = reinterpret_cast<double*>(ch + uc * (lb + rb));
-    double* Rt = reinterpret_cast<double*>(ch + uc * (lb + 2 * rb));
-    double* Linv = reinterpret_cast<double*>(ch + uc * (lb + 3 * rb));
-    double* CV = reinterpret_cast<double*>(ch + uc * (lb + 3 * rb + lib));
-    char* cgws = ch + uc * (lb + 3 * rb + lib + cvb);
-    const size_t cgb = cross_gram_workspace_internal(s, r1, w);
-    const size_t op_base = dopinf_operator_offset(n_r, r_list_h, n_pairs, g * n_pairs);
-
-    for (int u0 = 0; u0 < n_u; u0 += uc) {
-      const int nu = (n_u - u0) < uc ? (n_u - u0) : uc;
-      for (int p = 0; p < n_pairs; ++p) pu[p] = (pair_uid[p] >= u0 && pair_uid[p] < u0 + nu) ? pair_uid[p] - u0 : -1;
-      DOPINF_HIP(hipMemcpyAsync(b2dev, b2u.data() + u0, sizeof(double) * nu, hipMemcpyHostToDevice, st));
-      DOPINF_HIP(hipMemcpyAsync(pair_u, pu.data(), sizeof(int) * n_pairs, hipMemcpyHostToDevice, st));
-      // hipMemcpyAsync from pageable host memory returns after staging, so the
-      // host vectors may be reused in the next iteration.
-      zero_ints_kernel<<<1, 256, 0, st>>>(ufail, uc);
-      DOPINF_LAUNCHED();
-      {
-        dim3 grid(unsigned((s + 255) / 256 > 64 ? 64 : (s + 255) / 256), unsigned(s), unsigned(nu));
-        gather_qq_kernel<<<grid, 256, 0, st>>>(GE, geo, b2dev, Lq, R);
-        DOPINF_LAUNCHED();
-      }
-      for (int64_t jb = 0; jb < s; jb += NB) {
-        potf2_kernel<<<nu, 256, 0, st>>>(Lq, s, jb, Linv, ufail);
-        DOPINF_LAUNCHED();
-        const int64_t rest = s - jb - NB;
-        if (rest > 0) {
-          panel_kernel<<<dim3(unsigned((rest + 255) / 256), unsigned(nu)), 256, 0, st>>>(Lq, s, jb, Linv);
-          DOPINF_LAUNCHED();
-          const int64_t tt = (rest + 63) / 64;
-          syrk_update_kernel<<<dim3(unsigned(tt * (tt + 1) / 2), unsigned(nu)), 256, 0, st>>>(Lq, s, jb);
-          DOPINF_LAUNCHED();
-        }
-      }
-      // [W | y] = L^{-1} [G_ql | B_q] into R2 (R consumed), then
-      // [P | Z] = L^{-T} [W | y]: copy to R, solve into R2 ... so keep [W | y]:
-      int rc2 = trsm_run(st, false, Lq, s, Linv, R, R2, w, nu);  // R2 = [W | y]
-      if (rc2) return rc2;
-      copy_kernel<<<1024, 256, 0, st>>>(R2, R, int64_t(nu) * s * w);  // R = [W | y]
-      DOPINF_LAUNCHED();
-      rc2 = trsm_run(st, true, Lq, s, Linv, R2, Rt, w, nu);  // Rt = [P | Z] (R2 consumed)
-      if (rc2) return rc2;
-      for (int u = 0; u < nu; ++u) {
-        int rc = cross_gram_internal(st, R + size_t(u) * s * w, w, R + size_t(u) * s * w, w, s, r1, w,
-                                     CV + size_t(u) * r1 * w, w, cgws, cgb, nullptr, nullptr, 0, nullptr);
-        if (rc) return rc;
-      }
-      PairArgs pa{};
-      pa.GE = GE;
-      pa.geo = geo;
-      pa.CV = CV;
-      pa.R2 = Rt;
-      pa.ufail = ufail;
-      pa.pair_u = pair_u;
-      pa.beta1 = b1dev;
-      pa.O = O + op_base;
-      pa.status = status + g * n_pairs;
-      pa.n_pairs = n_pairs;
-      pa.XL = XL;
-      const size_t smem = size_t(r1) * (r1 + geo.r) * sizeof(double);
-      pair_solve_kernel<<<n_pairs, 256, smem, st>>>(pa);
-      DOPINF_LAUNCHED();
-      opq_kernel<<<dim3(unsigned((s + NB - 1) / NB), unsigned(n_pairs), unsigned((geo.r + NB - 1) / NB)), 256, 0,
-                   st>>>(pa);
-      DOPINF_LAUNCHED();
-    }
+  hipGraphExec_t exec = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (ei != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return fail(DOPINF_E_HIP, "hipGraphInstantiate failed: %s", hipGetErrorString(ei));
   }
+  *sweep_out = new dopinf_sweep_s{graph, exec};
+  return DOPINF_OK;
+}
+
+extern "C" int dopinf_sweep_launch(dopinf_sweep_t sweep, void* stream) {
+  DOPINF_REQUIRE(sweep && sweep->exec, "NULL sweep");
+  DOPINF_HIP(hipGraphLaunch(sweep->exec, static_cast<hipStream_t>(stream)));
+  return DOPINF_OK;
+}
+
+extern "C" int dopinf_sweep_destroy(dopinf_sweep_t sweep) {
+  if (!sweep) return DOPINF_OK;
+  const hipError_t a = sweep->exec ? hipGraphExecDestroy(sweep->exec) : hipSuccess;
+  const hipError_t b = sweep->graph ? hipGraphDestroy(sweep->graph) : hipSuccess;
+  delete sweep;
+  if (a != hipSuccess || b != hipSuccess) return fail(DOPINF_E_HIP, "destroying the sweep graph failed");
   return DOPINF_OK;
 }

@@ -49,3 +49,35 @@ def test_argument_errors_enqueue_nothing():
     rc = lib.dopinf_reduce(None, ctypes.c_void_p(8), 10, 10, 20, 0.9, 5, None, ctypes.c_void_p(8), None, 0,
                            ctypes.c_void_p(8), 10, ctypes.c_void_p(8), None, 0)
     assert rc == dp.E_ARG
+
+
+def test_tuning_table_and_sweep_argument_checks():
+    import paper_2504_14338_amd as dp
+    lib = dp.load()
+    cands = dp.autotune_candidates(dp.TUNE_CHOL_KB)
+    assert cands == sorted(cands) and all(c % 64 == 0 for c in cands)
+    key = 123457
+    assert dp.tune_get(dp.TUNE_CHOL_KB, key) == 0
+    dp.tune_set(dp.TUNE_CHOL_KB, key, 192)
+    assert dp.tune_get(dp.TUNE_CHOL_KB, key) == 192
+    dp.tune_set(dp.TUNE_CHOL_KB, key, 0)
+    assert dp.tune_get(dp.TUNE_CHOL_KB, key) == 0
+    for bad in (63, 100, 8192):
+        assert lib.dopinf_tune_set(dp.TUNE_CHOL_KB, key, bad) == dp.E_ARG
+    assert lib.dopinf_tune_set(99, key, 64) == dp.E_ARG
+    dp.tune_set(dp.TUNE_TRSM_KB, key, 512)
+    assert dp.tune_get(dp.TUNE_TRSM_KB, key) == 512 and dp.tune_get(dp.TUNE_CHOL_KB, key) == 0
+    dp.tune_set(dp.TUNE_TRSM_KB, key, 0)
+    assert dp.autotune_candidates(dp.TUNE_TRSM_KB) == cands
+    assert lib.dopinf_autotune_candidates(99, None, 0) == dp.E_ARG
+    # the null stream is refused before anything is enqueued
+    r = (ctypes.c_int * 1)(10)
+    b = (ctypes.c_double * 1)(1e-3)
+    h = ctypes.c_void_p()
+    p = ctypes.c_void_p(256)
+    rc = lib.dopinf_sweep_create(None, p, 100, 100, 1, r, 1, b, b, 10, 1.2, 0, p, p, p, p, p, p, p, 1 << 30,
+                                 ctypes.byref(h))
+    assert rc == dp.E_ARG and "null stream" in lib.dopinf_last_error().decode()
+    assert h.value is None
+    assert lib.dopinf_sweep_destroy(None) == dp.OK
+    assert lib.dopinf_sweep_workspace(100, 1, r, 1) >= lib.dopinf_infer_workspace(100, 1, r, 1)
