@@ -318,6 +318,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device-to-device (reference for the HBM byte counters)")
+    ap.add_argument("--leg", choices=["all", "sweep"], default="all",
+                    help="sweep: only the regularization sweep on reduced data of the same input "
+                         "(prints its JSON object; for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the multi-GPU sharding is "
@@ -343,6 +346,15 @@ def main():
     n, k = Q.shape
     torch.cuda.synchronize()
     log(f"input ready: {n} x {k} float64")
+    if args.leg == "sweep":
+        mean, scale, _ = dp.preprocess(Q, var_rows)
+        D = dp.gram(Q, mean, scale, var_rows)
+        del Q
+        _, _, Qh80, _, _ = dp.reduce(D, r=80, want_tr=False)
+        torch.cuda.synchronize()
+        log("reduced data at r = 80 ready")
+        print(json.dumps({"sweep": sweep_bench(dp, torch, Qh80.contiguous(), reps=max(1, args.steps))}), flush=True)
+        return
 
     timer = Timer(torch)
     for _ in range(args.warmup):

@@ -223,116 +223,6 @@ __global__ __launch_bounds__(256) void panel_kernel(double* __restrict__ A, int6
   }
 }
 
-// Update on FP64 MFMA from the factored columns [a0, a0 + K):
-//   A[i][l] -= sum_{a0 <= p < a0+K} L[i][p] L[l][p]   for c_lo <= l < c_hi, l <= i < n,
-// on 64 x 64 tiles (4 waves of 32 x 32) of the trapezoid of rows [c_lo, n) and
-// columns [c_lo, c_hi); K is consumed in 64-wide slabs staged through LDS.
-// With c_hi = n this is the trailing update of the lower triangle.
-__global__ __launch_bounds__(256) void syrk_update_kernel(double* __restrict__ A, int64_t n, int64_t a0, int64_t K,
-                                                          int64_t c_lo, int64_t c_hi) {
-  __shared__ double Pa[NB][NB + 2];
-  __shared__ double Pb[NB][NB + 2];
-  const int u = blockIdx.y;
-  double* Au = A + size_t(u) * n * n;
-  const int TR = int((n - c_lo + 63) / 64), TC = int((c_hi - c_lo + 63) / 64);
-  const int t = blockIdx.x;
-  int I, J;
-  if (TC >= TR) {
-    I = int((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-    while ((I + 1) * (I + 2) / 2 <= t) ++I;
-    while (I * (I + 1) / 2 > t) --I;
-    J = t - I * (I + 1) / 2;
-  } else {  // a few tile columns: column J holds tiles J .. TR-1
-    int rem = t;
-    J = 0;
-    while (rem >= TR - J) {
-      rem -= TR - J;
-      ++J;
-    }
-    I = J + rem;
-  }
-  const int64_t r0 = c_lo + int64_t(I) * 64, c0 = c_lo + int64_t(J) * 64;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int wm = w >> 1, wn = w & 1;
-  dbl4 acc[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
-  for (int64_t kc = 0; kc < K; kc += NB) {
-    const int64_t kw = min<int64_t>(NB, K - kc);
-    for (int e = threadIdx.x; e < 64 * NB; e += 256) {
-      const int rr = e / NB, p = e % NB;
-      const int64_t col = a0 + kc + p;
-      Pa[rr][p] = (r0 + rr < n && p < kw) ? Au[(r0 + rr) * n + col] : 0.0;
-      Pb[rr][p] = (c0 + rr < n && p < kw) ? Au[(c0 + rr) * n + col] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int kk = 0; kk < NB / 4; ++kk) {
-      const int p = kk * 4 + (lane >> 4);
-      double af[2], bf[2];
-#pragma unroll
-      for (int i = 0; i < 2; ++i) af[i] = Pa[wm * 32 + i * 16 + (lane & 15)][p];
-#pragma unroll
-      for (int j = 0; j < 2; ++j) bf[j] = Pb[wn * 32 + j * 16 + (lane & 15)][p];
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int64_t row = r0 + wm * 32 + i * 16 + (lane >> 4) + 4 * e;  // MFMA f64 output layout
-        const int64_t col = c0 + wn * 32 + j * 16 + (lane & 15);
-        if (row < n && col <= row && col < c_hi) Au[row * n + col] -= acc[i][j][e];
-      }
-}
-
-// number of 64 x 64 tiles of the update region of syrk_update_kernel
-inline int64_t syrk_tiles(int64_t n, int64_t c_lo, int64_t c_hi) {
-  const int64_t TR = (n - c_lo + 63) / 64, TC = (c_hi - c_lo + 63) / 64;
-  if (TC >= TR) return TR * (TR + 1) / 2;
-  return TC * TR - TC * (TC - 1) / 2;
-}
-
-// Blocked Cholesky of nu matrices (s x s, row-major, lower triangle used) in
-// place.  Block columns of width kb (a multiple of NB): inside a block column
-// the 64-wide panels are factored left to right and each updates only the
-// rest of its block column; the columns right of the block column then take
-// one update of depth kb.  kb = NB is the plain right-looking algorithm;
-// larger kb reads and writes the trailing matrix kb / NB times less often.
-int cholesky_run(hipStream_t st, double* Lq, int64_t s, double* Linv, int* ufail, int nu, int64_t kb) {
-  for (int64_t cb = 0; cb < s; cb += kb) {
-    const int64_t ce = std::min<int64_t>(cb + kb, s);
-    for (int64_t jb = cb; jb < ce; jb += NB) {
-      potf2_kernel<<<nu, 256, 0, st>>>(Lq, s, jb, Linv, ufail);
-      DOPINF_LAUNCHED();
-      const int64_t rest = s - jb - NB;
-      if (rest <= 0) continue;
-      panel_kernel<<<dim3(unsigned((rest + 255) / 256), unsigned(nu)), 256, 0, st>>>(Lq, s, jb, Linv);
-      DOPINF_LAUNCHED();
-      if (jb + NB < ce) {
-        const int64_t nt = syrk_tiles(s, jb + NB, ce);
-        syrk_update_kernel<<<dim3(unsigned(nt), unsigned(nu)), 256, 0, st>>>(Lq, s, jb, NB, jb + NB, ce);
-        DOPINF_LAUNCHED();
-      }
-    }
-    if (ce < s) {
-      const int64_t nt = syrk_tiles(s, ce, s);
-      syrk_update_kernel<<<dim3(unsigned(nt), unsigned(nu)), 256, 0, st>>>(Lq, s, cb, ce - cb, ce, s);
-      DOPINF_LAUNCHED();
-    }
-  }
-  return DOPINF_OK;
-}
-
 // ---------------------------------------------------------------------------
 // Triangular solves with the factored L (row-major lower, ld n) and its
 // diagonal-block inverses, per 64-row block J:
@@ -434,52 +324,229 @@ __global__ __launch_bounds__(256) void trsm_diag_kernel(const double* __restrict
   }
 }
 
-// X rows of block T0 + blockIdx.x -= (coefficients of Y rows [k0, k1)) Y[k0:k1]:
-// forward  coefficient of Y row k in X row i: L[i][k];
-// backward coefficient: L[k][i].  K is consumed in 64-row slabs.
-// Workgroup = (block row, 64 virtual columns, group).
+// Deep update of the triangular solves on 128 x 128 tiles:
+//   X[i][c] -= sum_{k in [k0, k1)} C(i, k) Y[k][c],   r_lo <= i < r_hi,
+// with C(i, k) = L[k][i] for the backward solve (TRANS: rows of L are
+// contiguous in i) and L[i][k] for the forward solve (staged transposed).
+// Workgroup = (128 virtual columns, 128 rows, group); 4 waves of 64 x 64
+// (4 x 4 FP64 MFMA blocks each); K in slabs of 16 rows, double-buffered in
+// LDS, the next slab's loads in flight while the current one is multiplied.
+constexpr int UT = 128;      // output tile edge
+constexpr int UK = 16;       // K slab
+constexpr int UP = UT + 4;   // LDS pitch in doubles
+
+__device__ __forceinline__ void mma_slab128(const double (*As)[UP], const double (*Bs)[UP], dbl4 (&acc)[4][4],
+                                            int lane, int wm, int wn) {
+#pragma unroll
+  for (int kk = 0; kk < UK / 4; ++kk) {
+    const int k = kk * 4 + (lane >> 4);
+    double af[4], bf[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) af[i] = As[k][wm * 64 + i * 16 + (lane & 15)];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) bf[j] = Bs[k][wn * 64 + j * 16 + (lane & 15)];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+  }
+}
+
 template <bool TRANS>
-__global__ __launch_bounds__(256) void trsm_update_kernel(const double* __restrict__ L, int64_t n,
-                                                          double* __restrict__ X, const double* __restrict__ Y,
-                                                          RhsMap m, int64_t T0, int64_t k0, int64_t k1) {
-  __shared__ double A[NB][TP];
-  __shared__ double B[NB][TP];
+__global__ __launch_bounds__(256, 2) void trsm_update_t128_kernel(const double* __restrict__ L, int64_t n,
+                                                               double* __restrict__ X, const double* __restrict__ Y,
+                                                               RhsMap m, int64_t r_lo, int64_t r_hi, int64_t k0,
+                                                               int64_t k1) {
+  __shared__ double As[2][UK][UP];
+  __shared__ double Bs[2][UK][UP];
   const int g = blockIdx.z;
-  const int64_t c0 = int64_t(blockIdx.y) * NB;
-  if (rhs_offset(m, g, n, c0) < 0) return;
+  const int64_t c0 = int64_t(blockIdx.x) * UT;
+  if (rhs_offset(m, g, n, c0) < 0) return;  // tile wholly past the group's columns
+  const int64_t tb = r_lo + int64_t(blockIdx.y) * UT;
   const double* Lg = L + size_t(g) * n * n;
-  const int64_t tb = (T0 + int64_t(blockIdx.x)) * NB, w = m.w;
-  const int c = threadIdx.x % NB;
-  const int64_t offc = rhs_offset(m, g, n, c0 + c);
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, wm = wv >> 1, wn = wv & 1;
-  dbl4 acc[2][2];
-  zero_acc(acc);
-  for (int64_t kb = k0; kb < k1; kb += NB) {
-    __syncthreads();
-    for (int e = threadIdx.x; e < NB * NB; e += 256) {  // A[a][p]: coefficient of Y row kb+p in X row tb+a
-      // consecutive threads read consecutive elements of a row of L
-      const int a = TRANS ? e % NB : e / NB, p = TRANS ? e / NB : e % NB;
-      double v = 0.0;
-      if (tb + a < n && kb + p < k1) v = TRANS ? Lg[(kb + p) * n + tb + a] : Lg[(tb + a) * n + kb + p];
-      A[a][p] = v;
+  const int64_t w = m.w;
+  // B loader: thread -> one column c of the tile, K rows kr0 + 2q.
+  // A loader (TRANS): the same pattern over rows i; (forward): thread -> K
+  // offset kl, rows ml + 16q, so that 16 threads read 16 consecutive k of a row.
+  const int lc = threadIdx.x % UT, kr0 = threadIdx.x / UT;
+  const int kl = threadIdx.x % UK, ml = threadIdx.x / UK;
+  const bool arow = tb + lc < r_hi;
+  const int64_t boff = rhs_offset(m, g, n, c0 + lc);
+  double ra[UK / 2], rb[UK / 2];
+  auto load = [&](int64_t kb) {
+#pragma unroll
+    for (int q = 0; q < UK / 2; ++q) {
+      const int64_t k = kb + kr0 + 2 * q;
+      const bool kin = k < k1;
+      if (TRANS) {
+        ra[q] = (kin && arow) ? Lg[k * n + tb + lc] : 0.0;
+      } else {
+        const int64_t ka = kb + kl, row = tb + ml + 16 * q;
+        ra[q] = (ka < k1 && row < r_hi) ? Lg[row * n + ka] : 0.0;
+      }
+      rb[q] = (kin && boff >= 0) ? Y[boff + k * w] : 0.0;
     }
-    for (int p = threadIdx.x / NB; p < NB; p += 256 / NB)
-      B[p][c] = (offc >= 0 && kb + p < k1) ? Y[offc + (kb + p) * w] : 0.0;
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < UK / 2; ++q) {
+      if (TRANS)
+        As[buf][kr0 + 2 * q][lc] = ra[q];
+      else
+        As[buf][kl][ml + 16 * q] = ra[q];
+      Bs[buf][kr0 + 2 * q][lc] = rb[q];
+    }
+  };
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, wm = wv >> 1, wn = wv & 1;
+  dbl4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+  load(k0);
+  store(0);
+  __syncthreads();
+  int buf = 0;
+  for (int64_t kb = k0; kb < k1; kb += UK) {
+    const bool more = kb + UK < k1;
+    if (more) load(kb + UK);
+    mma_slab128(As[buf], Bs[buf], acc, lane, wm, wn);
+    if (more) store(buf ^ 1);
     __syncthreads();
-    tile_mma64(A, B, acc, lane, wm, wn);
+    buf ^= 1;
   }
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int64_t off = rhs_offset(m, g, n, c0 + wn * 32 + j * 16 + (lane & 15));
+  for (int j = 0; j < 4; ++j) {
+    const int64_t off = rhs_offset(m, g, n, c0 + wn * 64 + j * 16 + (lane & 15));
     if (off < 0) continue;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int64_t row = tb + wm * 32 + i * 16 + (lane >> 4) + 4 * e;
-        if (row < n) X[off + row * w] -= acc[i][j][e];
+        const int64_t row = tb + wm * 64 + i * 16 + (lane >> 4) + 4 * e;  // MFMA f64 output layout
+        if (row < r_hi) X[off + row * w] -= acc[i][j][e];
       }
   }
+}
+
+// The Cholesky's update from the factored columns [a0, a0 + K) on 128 x 128
+// tiles: A[i][l] -= sum_{a0 <= p < a0+K} L[i][p] L[l][p] for c_lo <= l < c_hi,
+// l <= i < n (with c_hi = n the trailing update of the lower triangle), over
+// the trapezoid of rows [c_lo, n) and columns [c_lo, c_hi).  Both operands
+// are rows of L (contiguous in p); they are staged transposed (K-major) into
+// the double-buffered LDS slabs of mma_slab128.  A diagonal tile loads its
+// rows once.
+__global__ __launch_bounds__(256, 2) void syrk_update128_kernel(double* __restrict__ A, int64_t n, int64_t a0, int64_t K,
+                                                             int64_t c_lo, int64_t c_hi) {
+  __shared__ double As[2][UK][UP];
+  __shared__ double Bs[2][UK][UP];
+  const int u = blockIdx.y;
+  double* Au = A + size_t(u) * n * n;
+  const int TR = int((n - c_lo + UT - 1) / UT), TC = int((c_hi - c_lo + UT - 1) / UT);
+  const int t = blockIdx.x;
+  int I, J;
+  if (TC >= TR) {
+    I = int((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while ((I + 1) * (I + 2) / 2 <= t) ++I;
+    while (I * (I + 1) / 2 > t) --I;
+    J = t - I * (I + 1) / 2;
+  } else {
+    int rem = t;
+    J = 0;
+    while (rem >= TR - J) {
+      rem -= TR - J;
+      ++J;
+    }
+    I = J + rem;
+  }
+  const bool diag = (I == J);
+  const int64_t r0 = c_lo + int64_t(I) * UT, cc0 = c_lo + int64_t(J) * UT;
+  const int64_t k1 = a0 + K;
+  // loader: thread -> K offset kl, rows ml + 16 q
+  const int kl = threadIdx.x % UK, ml = threadIdx.x / UK;
+  double ra[UT / 16], rb[UT / 16];
+  auto load = [&](int64_t kb) {
+    const int64_t k = kb + kl;
+    const bool kin = k < k1;
+#pragma unroll
+    for (int q = 0; q < UT / 16; ++q) {
+      const int64_t ra_row = r0 + ml + 16 * q, rb_row = cc0 + ml + 16 * q;
+      ra[q] = (kin && ra_row < n) ? Au[ra_row * n + k] : 0.0;
+      if (!diag) rb[q] = (kin && rb_row < n) ? Au[rb_row * n + k] : 0.0;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < UT / 16; ++q) {
+      As[buf][kl][ml + 16 * q] = ra[q];
+      if (!diag) Bs[buf][kl][ml + 16 * q] = rb[q];
+    }
+  };
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, wm = wv >> 1, wn = wv & 1;
+  dbl4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+  load(a0);
+  store(0);
+  __syncthreads();
+  int buf = 0;
+  for (int64_t kb = a0; kb < k1; kb += UK) {
+    const bool more = kb + UK < k1;
+    if (more) load(kb + UK);
+    mma_slab128(As[buf], diag ? As[buf] : Bs[buf], acc, lane, wm, wn);
+    if (more) store(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t row = r0 + wm * 64 + i * 16 + (lane >> 4) + 4 * e;  // MFMA f64 output layout
+        const int64_t col = cc0 + wn * 64 + j * 16 + (lane & 15);
+        if (row < n && col <= row && col < c_hi) Au[row * n + col] -= acc[i][j][e];
+      }
+}
+
+inline int64_t syrk_tiles128(int64_t n, int64_t c_lo, int64_t c_hi) {
+  const int64_t TR = (n - c_lo + UT - 1) / UT, TC = (c_hi - c_lo + UT - 1) / UT;
+  if (TC >= TR) return TR * (TR + 1) / 2;
+  return TC * TR - TC * (TC - 1) / 2;
+}
+
+// Blocked Cholesky of nu matrices (s x s, row-major, lower triangle used) in
+// place.  Block columns of width kb (a multiple of NB): inside a block column
+// the 64-wide panels are factored left to right and each updates only the
+// rest of its block column; the columns right of the block column then take
+// one update of depth kb.  kb = NB is the plain right-looking algorithm;
+// larger kb reads and writes the trailing matrix kb / NB times less often.
+int cholesky_run(hipStream_t st, double* Lq, int64_t s, double* Linv, int* ufail, int nu, int64_t kb) {
+  for (int64_t cb = 0; cb < s; cb += kb) {
+    const int64_t ce = std::min<int64_t>(cb + kb, s);
+    for (int64_t jb = cb; jb < ce; jb += NB) {
+      potf2_kernel<<<nu, 256, 0, st>>>(Lq, s, jb, Linv, ufail);
+      DOPINF_LAUNCHED();
+      const int64_t rest = s - jb - NB;
+      if (rest <= 0) continue;
+      panel_kernel<<<dim3(unsigned((rest + 255) / 256), unsigned(nu)), 256, 0, st>>>(Lq, s, jb, Linv);
+      DOPINF_LAUNCHED();
+      if (jb + NB < ce) {
+        const int64_t nt = syrk_tiles128(s, jb + NB, ce);
+        syrk_update128_kernel<<<dim3(unsigned(nt), unsigned(nu)), 256, 0, st>>>(Lq, s, jb, NB, jb + NB, ce);
+        DOPINF_LAUNCHED();
+      }
+    }
+    if (ce < s) {
+      const int64_t nt = syrk_tiles128(s, ce, s);
+      syrk_update128_kernel<<<dim3(unsigned(nt), unsigned(nu)), 256, 0, st>>>(Lq, s, cb, ce - cb, ce, s);
+      DOPINF_LAUNCHED();
+    }
+  }
+  return DOPINF_OK;
 }
 
 // ng groups, each with at most max_cols virtual columns; block columns of kb
@@ -499,11 +566,12 @@ int trsm_run(hipStream_t st, bool trans, const double* L, int64_t n, const doubl
   // X blocks [t0, t1) -= coefficients x Y rows [k0, k1)
   auto update = [&](int64_t t0, int64_t t1, int64_t k0, int64_t k1) -> int {
     if (t1 <= t0) return DOPINF_OK;
-    const dim3 grid(unsigned(t1 - t0), nct, unsigned(ng));
+    const int64_t r_lo = t0 * NB, r_hi = std::min<int64_t>(t1 * NB, n);
+    const dim3 g128(unsigned((max_cols + UT - 1) / UT), unsigned((r_hi - r_lo + UT - 1) / UT), unsigned(ng));
     if (!trans)
-      trsm_update_kernel<false><<<grid, 256, 0, st>>>(L, n, X, Yout, m, t0, k0, std::min<int64_t>(k1, n));
+      trsm_update_t128_kernel<false><<<g128, 256, 0, st>>>(L, n, X, Yout, m, r_lo, r_hi, k0, std::min<int64_t>(k1, n));
     else
-      trsm_update_kernel<true><<<grid, 256, 0, st>>>(L, n, X, Yout, m, t0, k0, std::min<int64_t>(k1, n));
+      trsm_update_t128_kernel<true><<<g128, 256, 0, st>>>(L, n, X, Yout, m, r_lo, r_hi, k0, std::min<int64_t>(k1, n));
     DOPINF_LAUNCHED();
     return DOPINF_OK;
   };
