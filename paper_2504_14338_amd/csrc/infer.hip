@@ -53,15 +53,19 @@ __device__ __forceinline__ int64_t qcol_max(int i, int j, int rmax) {
 }
 
 // (i, j) of quadratic index q in the ordering (0,0),(0,1),..,(0,r-1),(1,1),..
+// Row i starts at off(i) = i r - i (i - 1) / 2; i is the largest root bound of
+// off(i) <= q, taken from the quadratic formula and corrected by +-1 steps.
 __device__ __forceinline__ void qpair(int64_t q, int r, int& i, int& j) {
-  int ii = 0;
-  int64_t off = 0;
-  while (off + (r - ii) <= q) {
-    off += r - ii;
-    ++ii;
-  }
-  i = ii;
-  j = ii + int(q - off);
+  auto off = [r](int64_t ii) { return ii * r - ii * (ii - 1) / 2; };
+  const double b = 2.0 * r + 1.0;
+  const double disc = b * b - 8.0 * double(q);
+  int64_t ii = int64_t((b - sqrt(disc > 0.0 ? disc : 0.0)) * 0.5);
+  if (ii < 0) ii = 0;
+  if (ii > r - 1) ii = r - 1;
+  while (ii + 1 <= r - 1 && off(ii + 1) <= q) ++ii;
+  while (ii > 0 && off(ii) > q) --ii;
+  i = int(ii);
+  j = int(ii + (q - off(ii)));
 }
 
 // ---------------------------------------------------------------------------
@@ -139,88 +143,82 @@ __global__ __launch_bounds__(256) void gather_qq_kernel(const double* __restrict
 // ---------------------------------------------------------------------------
 // blocked Cholesky (lower, row-major, ld n), batched over blockIdx.z / .y
 // ---------------------------------------------------------------------------
-// Diagonal block at jb: factor in LDS with one wave (no workgroup barriers
-// beyond the wave), write L_jj and the inverse of its triangle.
+// Diagonal block at jb: Cholesky factor and inverse of the 64 x 64 block in
+// LDS, one workgroup per matrix, one barrier per column.  Step c reads the
+// unscaled column c of the working matrix T and its pivot d_c; it writes
+// column c of the factor F (sqrt(d_c) on the diagonal), updates the trailing
+// triangle T[i][l] -= T[i][c] T[l][c] / d_c, and applies the same elimination
+// to W (initially I): W[q][p] -= (T[q][c] / d_c) W[c][p] for q > c.  Nothing
+// that step c reads is written in step c.  W ends as M^{-1} for the unit
+// lower factor M of A = M diag(d) M^T, so L^{-1} = diag(d)^{-1/2} W.  Rows
+// beyond the matrix are identity rows.
 __global__ __launch_bounds__(256) void potf2_kernel(double* __restrict__ A, int64_t n, int64_t jb,
                                                     double* __restrict__ Linv, int* __restrict__ fail_flag) {
   __shared__ double T[NB][NB + 1];
-  __shared__ double Ti[NB][NB + 1];
+  __shared__ double F[NB][NB + 1];
+  __shared__ double W[NB][NB + 1];
   __shared__ int bad;
   const int u = blockIdx.x;
   const int tid = threadIdx.x;
   double* Au = A + size_t(u) * n * n;
   const int nb = int(min<int64_t>(NB, n - jb));
-  for (int e = tid; e < NB * NB; e += 256) {
-    const int i = e / NB, j = e % NB;
-    double v = 0.0;
-    if (i < nb && j <= i) v = Au[(jb + i) * n + jb + j];
-    else if (i == j) v = 1.0;  // identity padding beyond the matrix
-    T[i][j] = v;
-    Ti[i][j] = (i == j) ? 1.0 : 0.0;
+  {
+    // all 16 loads of a thread in flight together (clamped addresses, select)
+    const int j = tid % NB, i0 = tid / NB;
+    double v[NB / 4];
+#pragma unroll
+    for (int k = 0; k < NB / 4; ++k) {
+      const int i = i0 + 4 * k;
+      const int ic = i < nb ? i : 0, jc = j < nb ? j : 0;
+      v[k] = Au[(jb + ic) * n + jb + jc];
+    }
+#pragma unroll
+    for (int k = 0; k < NB / 4; ++k) {
+      const int i = i0 + 4 * k;
+      T[i][j] = (i < nb && j <= i) ? v[k] : (i == j ? 1.0 : 0.0);
+      F[i][j] = 0.0;
+      W[i][j] = (i == j) ? 1.0 : 0.0;
+    }
   }
   if (tid == 0) bad = 0;
   __syncthreads();
-  // right-looking Cholesky of the 64 x 64 block
   for (int c = 0; c < NB; ++c) {
     const double piv = T[c][c];
     const bool okp = (piv > 0.0) && isfinite(piv);
-    const double dc = sqrt(okp ? piv : 1.0);
-    __syncthreads();
-    if (tid == 0) {
-      T[c][c] = dc;
-      if (!okp) bad = 1;
+    const double pv = okp ? piv : 1.0;
+    const double d = sqrt(pv);
+    if (tid >= c && tid < NB) F[tid][c] = (tid == c) ? d : T[tid][c] / d;
+    if (tid == 0 && !okp) bad = 1;
+    const double rp = 1.0 / pv;
+    // thread -> column j = tid % 64 and rows c + 1 + tid / 64 + 4k: column
+    // j > c of T (lower part) or column j <= c of W, with one code path for
+    // both (no divergence) and all reads issued before the writes
+    const int j = tid % NB;
+    const bool onT = j > c;
+    double* dst = onT ? &T[0][0] : &W[0][0];
+    const double f = (onT ? T[j][c] : W[c][j]) * rp;
+    double a[NB / 4], b[NB / 4];
+#pragma unroll
+    for (int k = 0; k < NB / 4; ++k) {
+      const int i = c + 1 + tid / NB + 4 * k;
+      const int ic = i < NB ? i : NB - 1;
+      a[k] = T[ic][c];
+      b[k] = dst[ic * (NB + 1) + j];
     }
-    if (tid > c && tid < NB) T[tid][c] /= dc;
-    __syncthreads();
-    const int rem = NB - 1 - c;
-    for (int e = tid; e < rem * rem; e += 256) {
-      const int i = c + 1 + e / rem, l = c + 1 + e % rem;
-      if (l <= i) T[i][l] -= T[i][c] * T[l][c];
-    }
-    __syncthreads();
-  }
-  // inverse of the triangle: T Ti = I, right-looking over rows
-  for (int i = 0; i < NB; ++i) {
-    if (tid <= i) Ti[i][tid] /= T[i][i];
-    __syncthreads();
-    const int rem = NB - 1 - i, cols = i + 1;
-    for (int e = tid; e < rem * cols; e += 256) {
-      const int q = i + 1 + e / cols, c = e % cols;
-      Ti[q][c] -= T[q][i] * Ti[i][c];
+#pragma unroll
+    for (int k = 0; k < NB / 4; ++k) {
+      const int i = c + 1 + tid / NB + 4 * k;
+      if (i < NB && (!onT || j <= i)) dst[i * (NB + 1) + j] = b[k] - a[k] * f;
     }
     __syncthreads();
   }
   double* Lo = Linv + (size_t(u) * ((n + NB - 1) / NB) + jb / NB) * NB * NB;
   for (int e = tid; e < NB * NB; e += 256) {
     const int i = e / NB, j = e % NB;
-    if (i < nb && j <= i) Au[(jb + i) * n + jb + j] = T[i][j];
-    Lo[e] = Ti[i][j];
+    if (i < nb && j <= i) Au[(jb + i) * n + jb + j] = F[i][j];
+    Lo[e] = (j <= i) ? W[i][j] / F[i][i] : 0.0;
   }
   if (tid == 0 && bad) fail_flag[u] = 1;
-}
-
-// Rows below the diagonal block: A[i, jb:jb+nb] <- A[i, jb:jb+nb] L_jj^{-T}
-// = A[i, :] Linv^T, one thread per row.
-__global__ __launch_bounds__(256) void panel_kernel(double* __restrict__ A, int64_t n, int64_t jb,
-                                                    const double* __restrict__ Linv) {
-  __shared__ double Li[NB][NB + 1];
-  const int u = blockIdx.y;
-  double* Au = A + size_t(u) * n * n;
-  const double* Lu = Linv + (size_t(u) * ((n + NB - 1) / NB) + jb / NB) * NB * NB;
-  for (int e = threadIdx.x; e < NB * NB; e += 256) Li[e / NB][e % NB] = Lu[e];
-  __syncthreads();
-  const int64_t i = jb + NB + int64_t(blockIdx.x) * 256 + threadIdx.x;
-  if (i >= n) return;
-  const int nb = int(min<int64_t>(NB, n - jb));
-  double x[NB];
-#pragma unroll
-  for (int p = 0; p < NB; ++p) x[p] = (p < nb) ? Au[i * n + jb + p] : 0.0;
-  for (int c = 0; c < nb; ++c) {
-    double s = 0.0;
-#pragma unroll
-    for (int p = 0; p < NB; ++p) s += x[p] * Li[c][p];
-    Au[i * n + jb + c] = s;
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -260,6 +258,51 @@ __device__ __forceinline__ void tile_mma64(const double (*A)[TP], const double (
   }
 }
 
+// Rows below the diagonal block (called only when rows remain below it, so
+// the block is a full 64 wide): A[i, jb:jb+64] <- A[i, jb:jb+64] Linv^T,
+// one 64-row tile per workgroup on FP64 MFMA.
+__global__ __launch_bounds__(256) void panel_kernel(double* __restrict__ A, int64_t n, int64_t jb,
+                                                    const double* __restrict__ Linv) {
+  __shared__ double Xs[NB][TP];  // the tile's rows of the panel
+  __shared__ double Bs[NB][TP];  // Bs[p][c] = Linv[c][p]
+  const int u = blockIdx.y;
+  double* Au = A + size_t(u) * n * n;
+  const double* Lu = Linv + (size_t(u) * ((n + NB - 1) / NB) + jb / NB) * NB * NB;
+  const int64_t r0 = jb + NB + int64_t(blockIdx.x) * NB;
+  // all loads of a thread issued together (clamped rows), then the LDS stores
+  double xv[NB * NB / 256], lv[NB * NB / 256];
+#pragma unroll
+  for (int k = 0; k < NB * NB / 256; ++k) {
+    const int e = threadIdx.x + 256 * k, a = e / NB, p = e % NB;
+    xv[k] = Au[(r0 + a < n ? r0 + a : r0) * n + jb + p];
+    lv[k] = Lu[e];
+  }
+#pragma unroll
+  for (int k = 0; k < NB * NB / 256; ++k) {
+    const int e = threadIdx.x + 256 * k, a = e / NB, p = e % NB;
+    Xs[a][p] = (r0 + a < n) ? xv[k] : 0.0;
+    Bs[p][a] = lv[k];  // e = a * NB + p: Linv[a][p]
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, wm = wv >> 1, wn = wv & 1;
+  dbl4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+  tile_mma64(Xs, Bs, acc, lane, wm, wn);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t row = r0 + wm * 32 + i * 16 + (lane >> 4) + 4 * e;  // MFMA f64 output layout
+        const int64_t col = jb + wn * 32 + j * 16 + (lane & 15);
+        if (row < n) Au[row * n + col] = acc[i][j][e];
+      }
+}
+
 struct RhsMap {
   const int* e0;   // per group: first matrix (NULL: g)
   const int* cnt;  // per group: matrices (NULL: 1)
@@ -295,15 +338,26 @@ __global__ __launch_bounds__(256) void trsm_diag_kernel(const double* __restrict
   const int64_t nblk = (n + NB - 1) / NB;
   const double* Li = Linv + (size_t(g) * nblk + J) * NB * NB;
   const int64_t jb = J * NB, w = m.w;
-  for (int e = threadIdx.x; e < NB * NB; e += 256) {
-    const int a = e / NB, b = e % NB;
-    A[a][b] = TRANS ? Li[b * NB + a] : Li[a * NB + b];
-  }
   {
+    // all loads of a thread issued together (clamped addresses), then the LDS stores
     const int c = threadIdx.x % NB;  // fixed per thread (256 is a multiple of 64)
-    const int64_t off = rhs_offset(m, g, n, c0 + c);
-    for (int a = threadIdx.x / NB; a < NB; a += 256 / NB)
-      B[a][c] = (off >= 0 && jb + a < n) ? X[off + (jb + a) * w] : 0.0;
+    const int64_t off0 = rhs_offset(m, g, n, c0 + c);
+    const int64_t off = off0 >= 0 ? off0 : rhs_offset(m, g, n, c0);
+    double av[NB * NB / 256], bv[NB * NB / 256];
+#pragma unroll
+    for (int k = 0; k < NB * NB / 256; ++k) {
+      const int e = threadIdx.x + 256 * k, a = e / NB, b = e % NB;
+      av[k] = TRANS ? Li[b * NB + a] : Li[a * NB + b];
+      const int ar = threadIdx.x / NB + 4 * k;
+      bv[k] = X[off + (jb + ar < n ? jb + ar : jb) * w];
+    }
+#pragma unroll
+    for (int k = 0; k < NB * NB / 256; ++k) {
+      const int e = threadIdx.x + 256 * k, a = e / NB, b = e % NB;
+      A[a][b] = av[k];
+      const int ar = threadIdx.x / NB + 4 * k;
+      B[ar][c] = (off0 >= 0 && jb + ar < n) ? bv[k] : 0.0;
+    }
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, wm = wv >> 1, wn = wv & 1;
@@ -415,16 +469,26 @@ __global__ __launch_bounds__(256, 2) void trsm_update_t128_kernel(const double* 
     __syncthreads();
     buf ^= 1;
   }
+  // epilogue per column group: the 16 old values are loaded (clamped
+  // addresses) before any is written back
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    const int64_t off = rhs_offset(m, g, n, c0 + wn * 64 + j * 16 + (lane & 15));
-    if (off < 0) continue;
+    const int64_t off0 = rhs_offset(m, g, n, c0 + wn * 64 + j * 16 + (lane & 15));
+    const int64_t off = off0 >= 0 ? off0 : rhs_offset(m, g, n, c0);
+    double old[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int64_t row = tb + wm * 64 + i * 16 + (lane >> 4) + 4 * e;  // MFMA f64 output layout
-        if (row < r_hi) X[off + row * w] -= acc[i][j][e];
+        old[i][e] = X[off + (row < r_hi ? row : r_lo) * w];
+      }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t row = tb + wm * 64 + i * 16 + (lane >> 4) + 4 * e;
+        if (off0 >= 0 && row < r_hi) X[off + row * w] = old[i][e] - acc[i][j][e];
       }
   }
 }
@@ -500,16 +564,28 @@ __global__ __launch_bounds__(256, 2) void syrk_update128_kernel(double* __restri
     __syncthreads();
     buf ^= 1;
   }
+  // epilogue per column group: the 16 old values are loaded (clamped
+  // addresses) before any is written back
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int j = 0; j < 4; ++j) {
+    const int64_t col = cc0 + wn * 64 + j * 16 + (lane & 15);
+    const int64_t colc = col < n ? col : cc0;
+    double old[4][4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int64_t row = r0 + wm * 64 + i * 16 + (lane >> 4) + 4 * e;  // MFMA f64 output layout
-        const int64_t col = cc0 + wn * 64 + j * 16 + (lane & 15);
-        if (row < n && col <= row && col < c_hi) Au[row * n + col] -= acc[i][j][e];
+        old[i][e] = Au[(row < n ? row : r0) * n + colc];
       }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t row = r0 + wm * 64 + i * 16 + (lane >> 4) + 4 * e;
+        if (row < n && col <= row && col < c_hi) Au[row * n + col] = old[i][e] - acc[i][j][e];
+      }
+  }
 }
 
 inline int64_t syrk_tiles128(int64_t n, int64_t c_lo, int64_t c_hi) {
@@ -532,7 +608,7 @@ int cholesky_run(hipStream_t st, double* Lq, int64_t s, double* Linv, int* ufail
       DOPINF_LAUNCHED();
       const int64_t rest = s - jb - NB;
       if (rest <= 0) continue;
-      panel_kernel<<<dim3(unsigned((rest + 255) / 256), unsigned(nu)), 256, 0, st>>>(Lq, s, jb, Linv);
+      panel_kernel<<<dim3(unsigned((rest + NB - 1) / NB), unsigned(nu)), 256, 0, st>>>(Lq, s, jb, Linv);
       DOPINF_LAUNCHED();
       if (jb + NB < ce) {
         const int64_t nt = syrk_tiles128(s, jb + NB, ce);
@@ -657,10 +733,11 @@ __global__ __launch_bounds__(256) void pair_solve_kernel(PairArgs a) {
     const double dc = S[c * r1 + c];
     for (int i = c + 1 + threadIdx.x; i < r1; i += 256) S[i * r1 + c] /= dc;
     __syncthreads();
-    const int rem = r1 - c - 1;
-    for (int e = threadIdx.x; e < rem * rem; e += 256) {
-      const int i = c + 1 + e / rem, l = c + 1 + e % rem;
-      if (l <= i) S[i * r1 + l] -= S[i * r1 + c] * S[l * r1 + c];
+    // thread -> columns l = c + 1 + (tid % 64) + 64 t, rows i >= l in steps of 4
+    // (no integer division in the loops)
+    for (int l = c + 1 + (threadIdx.x & 63); l < r1; l += 64) {
+      const double sl = S[l * r1 + c];
+      for (int i = l + (threadIdx.x >> 6); i < r1; i += 4) S[i * r1 + l] -= S[i * r1 + c] * sl;
     }
     __syncthreads();
   }
@@ -669,19 +746,18 @@ __global__ __launch_bounds__(256) void pair_solve_kernel(PairArgs a) {
   for (int i = 0; i < r1; ++i) {
     for (int c = threadIdx.x; c < r; c += 256) X[i * r + c] /= S[i * r1 + i];
     __syncthreads();
-    const int rem = r1 - 1 - i;
-    for (int e = threadIdx.x; e < rem * r; e += 256) {
-      const int q = i + 1 + e / r, c = e % r;
-      X[q * r + c] -= S[q * r1 + i] * X[i * r + c];
+    for (int c = threadIdx.x & 63; c < r; c += 64) {
+      const double xc = X[i * r + c];
+      for (int q = i + 1 + (threadIdx.x >> 6); q < r1; q += 4) X[q * r + c] -= S[q * r1 + i] * xc;
     }
     __syncthreads();
   }
   for (int i = r1 - 1; i >= 0; --i) {
     for (int c = threadIdx.x; c < r; c += 256) X[i * r + c] /= S[i * r1 + i];
     __syncthreads();
-    for (int e = threadIdx.x; e < i * r; e += 256) {
-      const int q = e / r, c = e % r;
-      X[q * r + c] -= S[i * r1 + q] * X[i * r + c];
+    for (int c = threadIdx.x & 63; c < r; c += 64) {
+      const double xc = X[i * r + c];
+      for (int q = threadIdx.x >> 6; q < i; q += 4) X[q * r + c] -= S[i * r1 + q] * xc;
     }
     __syncthreads();
   }
@@ -692,7 +768,7 @@ __global__ __launch_bounds__(256) void pair_solve_kernel(PairArgs a) {
     const int64_t col = (c < r) ? c : (r + s);
     Op[i * d + col] = X[c * r + i];
   }
-  // X_l for the quadratic columns X_q = Z - P X_l (opq_kernel)
+  // X_l for the quadratic columns (vq_kernel)
   double* XLp = a.XL + size_t(p) * r1 * r;
   for (int e = threadIdx.x; e < r1 * r; e += 256) XLp[e] = X[e];
   if (threadIdx.x == 0) a.status[p] = bad ? DOPINF_E_NOTSPD : DOPINF_OK;
@@ -739,15 +815,27 @@ __global__ __launch_bounds__(256) void vq_kernel(QuadArgs a) {
     for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
   for (int k0 = 0; k0 < r1; k0 += NB) {
     __syncthreads();
-    for (int e = threadIdx.x; e < NB * NB; e += 256) {
-      const int a_ = e / NB, b_ = e % NB;
-      At[a_][b_] = (q0 + a_ < s && k0 + b_ < r1) ? R2u[(q0 + a_) * w + k0 + b_] : 0.0;   // W[q][c]
-      Bt[a_][b_] = (k0 + a_ < r1 && i0 + b_ < r) ? XLp[(k0 + a_) * r + i0 + b_] : 0.0;  // X_l[c][i]
+    // all loads of a thread issued together (clamped addresses), then the LDS stores
+    double av[NB * NB / 256], bv[NB * NB / 256];
+#pragma unroll
+    for (int k = 0; k < NB * NB / 256; ++k) {
+      const int e = threadIdx.x + 256 * k, a_ = e / NB, b_ = e % NB;
+      const int64_t qa = q0 + a_ < s ? q0 + a_ : q0;
+      const int ca = k0 + b_ < r1 ? k0 + b_ : k0;
+      av[k] = R2u[qa * w + ca];                                                   // W[q][c]
+      bv[k] = XLp[(k0 + a_ < r1 ? k0 + a_ : k0) * r + (i0 + b_ < r ? i0 + b_ : i0)];  // X_l[c][i]
+    }
+#pragma unroll
+    for (int k = 0; k < NB * NB / 256; ++k) {
+      const int e = threadIdx.x + 256 * k, a_ = e / NB, b_ = e % NB;
+      At[a_][b_] = (q0 + a_ < s && k0 + b_ < r1) ? av[k] : 0.0;
+      Bt[a_][b_] = (k0 + a_ < r1 && i0 + b_ < r) ? bv[k] : 0.0;
     }
     __syncthreads();
     tile_mma64(At, Bt, acc, lane, wm, wn);
   }
   double* Vb = a.V + size_t(bt) * s * r;
+  double yv[2][2][4];  // y entries, all loaded (clamped) before the writes
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -756,7 +844,17 @@ __global__ __launch_bounds__(256) void vq_kernel(QuadArgs a) {
       for (int e = 0; e < 4; ++e) {
         const int64_t q = q0 + wm * 32 + i * 16 + (lane >> 4) + 4 * e;  // MFMA f64 output layout
         const int ii = i0 + wn * 32 + j * 16 + (lane & 15);
-        if (q < s && ii < r) Vb[q * r + ii] = R2u[q * w + r1 + ii] - acc[i][j][e];
+        yv[i][j][e] = R2u[(q < s ? q : q0) * w + r1 + (ii < r ? ii : i0)];
+      }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t q = q0 + wm * 32 + i * 16 + (lane >> 4) + 4 * e;
+        const int ii = i0 + wn * 32 + j * 16 + (lane & 15);
+        if (q < s && ii < r) Vb[q * r + ii] = yv[i][j][e] - acc[i][j][e];
       }
 }
 
@@ -772,9 +870,16 @@ __global__ __launch_bounds__(256) void oq_kernel(QuadArgs a) {
   const int64_t q0 = int64_t(blockIdx.x) * NB;
   const int i0 = int(blockIdx.z) * NB;
   const double* Xb = a.Xq + size_t(bt) * s * r;
-  for (int e = threadIdx.x; e < NB * NB; e += 256) {
-    const int qq = e / NB, ii = e % NB;
-    if (q0 + qq < s && i0 + ii < r) T[ii][qq] = Xb[(q0 + qq) * r + i0 + ii];
+  double xv[NB * NB / 256];
+#pragma unroll
+  for (int k = 0; k < NB * NB / 256; ++k) {
+    const int e = threadIdx.x + 256 * k, qq = e / NB, ii = e % NB;
+    xv[k] = Xb[(q0 + qq < s ? q0 + qq : q0) * r + (i0 + ii < r ? i0 + ii : i0)];
+  }
+#pragma unroll
+  for (int k = 0; k < NB * NB / 256; ++k) {
+    const int e = threadIdx.x + 256 * k, qq = e / NB, ii = e % NB;
+    T[ii][qq] = xv[k];
   }
   __syncthreads();
   double* Op = a.O + size_t(p) * r * d;
@@ -808,11 +913,21 @@ __global__ __launch_bounds__(256) void cv_partial_kernel(const double* __restric
     for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
   for (int64_t k0 = lo; k0 < hi; k0 += NB) {
     __syncthreads();
-    for (int e = threadIdx.x; e < NB * NB; e += 256) {
-      const int p_ = e / NB, a_ = e % NB;
+    // all loads of a thread issued together (clamped addresses), then the LDS stores
+    double av[NB * NB / 256], bv[NB * NB / 256];
+#pragma unroll
+    for (int k = 0; k < NB * NB / 256; ++k) {
+      const int e = threadIdx.x + 256 * k, p_ = e / NB, a_ = e % NB;
+      const int64_t row = k0 + p_ < hi ? k0 + p_ : k0;
+      av[k] = Ru[row * w + (i0 + a_ < r1 ? i0 + a_ : i0)];
+      bv[k] = Ru[row * w + (c0 + a_ < w ? c0 + a_ : c0)];
+    }
+#pragma unroll
+    for (int k = 0; k < NB * NB / 256; ++k) {
+      const int e = threadIdx.x + 256 * k, p_ = e / NB, a_ = e % NB;
       const bool in = k0 + p_ < hi;
-      At[a_][p_] = (in && i0 + a_ < r1) ? Ru[(k0 + p_) * w + i0 + a_] : 0.0;
-      Bt[p_][a_] = (in && c0 + a_ < w) ? Ru[(k0 + p_) * w + c0 + a_] : 0.0;
+      At[a_][p_] = (in && i0 + a_ < r1) ? av[k] : 0.0;
+      Bt[p_][a_] = (in && c0 + a_ < w) ? bv[k] : 0.0;
     }
     __syncthreads();
     tile_mma64(At, Bt, acc, lane, wm, wn);
