@@ -318,9 +318,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device-to-device (reference for the HBM byte counters)")
-    ap.add_argument("--leg", choices=["all", "sweep"], default="all",
-                    help="sweep: only the regularization sweep on reduced data of the same input "
-                         "(prints its JSON object; for profiling)")
+    ap.add_argument("--leg", choices=["all", "sweep", "mixed"], default="all",
+                    help="sweep: only the regularization sweep on reduced data of the same input; "
+                         "mixed: only the reduced-precision forms against one float64 step "
+                         "(each prints its JSON object; for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the multi-GPU sharding is "
@@ -354,6 +355,13 @@ def main():
         torch.cuda.synchronize()
         log("reduced data at r = 80 ready")
         print(json.dumps({"sweep": sweep_bench(dp, torch, Qh80.contiguous(), reps=max(1, args.steps))}), flush=True)
+        return
+    if args.leg == "mixed":
+        timer = Timer(torch)
+        res = pipeline_step(dp, Q, var_rows, timer)
+        t64 = timer.ms("preprocess") + timer.ms("gram") + timer.ms("reduce")
+        log("float64 reference step done")
+        print(json.dumps({"mixed": mixed_bench(dp, torch, Q, var_rows, res["Qhat"], res["lam"], t64)}), flush=True)
         return
 
     timer = Timer(torch)

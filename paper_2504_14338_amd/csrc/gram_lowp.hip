@@ -78,41 +78,76 @@ __host__ __device__ inline int pos_b16(int rr, int cc) {
   return (((rr >> 3) ^ ((cc >> 2) & 3)) << 3) | (rr & 7);
 }
 
-// One workgroup packs a 32-row block x 128 columns: reads rows (coalesced),
-// transposes through LDS, writes [col][32] chunks (coalesced).
+// One workgroup packs a 32-row block x 128 columns: reads rows (coalesced,
+// all 16 loads of a thread in flight together), transforms with the block's
+// per-row mean and reciprocal scale (an LDS table), transposes through LDS,
+// and writes whole 16-byte slots of the packed layout: FP32 gathers the four
+// rows {g, g+4, g+8, g+12} (+16) of a slot, bfloat16 eight consecutive rows.
 __global__ __launch_bounds__(256) void pack_kernel(PackArgs a) {
   __shared__ float tile[KB][BT + 1];
+  __shared__ double rmu[KB], rinv[KB];
   const int64_t blk = blockIdx.x;
   const int64_t c0 = int64_t(blockIdx.y) * BT;
   const int tid = threadIdx.x;
-  for (int e = tid; e < KB * BT; e += 256) {
-    const int rr = e / BT, cc = e % BT;
-    const int64_t row = blk * KB + rr, col = c0 + cc;
+  if (tid < KB) {
+    const int64_t row = blk * KB + tid;
+    const int64_t rowc = row < a.n ? row : a.n - 1;
+    int vv = 0;
+    while (vv + 1 < a.nvars && rowc >= a.row0[vv + 1]) ++vv;
+    rmu[tid] = a.mean ? a.mean[rowc] : 0.0;
+    rinv[tid] = a.scale ? 1.0 / a.scale[vv] : 1.0;
+  }
+  const int cc = tid % BT;
+  const int64_t col = c0 + cc;
+  const bool cin = col < a.k;
+  const int64_t colc = cin ? col : 0;
+  float q[KB / 2];
+#pragma unroll
+  for (int i = 0; i < KB / 2; ++i) {
+    const int64_t row = blk * KB + tid / BT + 2 * i;
+    q[i] = a.Q[(row < a.n ? row : a.n - 1) * a.ldq + colc];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < KB / 2; ++i) {
+    const int rr = tid / BT + 2 * i;
+    const int64_t row = blk * KB + rr;
     float v = 0.f;
-    if (row < a.n && col < a.k) {
-      int vv = 0;
-      while (vv + 1 < a.nvars && row >= a.row0[vv + 1]) ++vv;
-      const double mu = a.mean ? a.mean[row] : 0.0;
-      const double inv = a.scale ? 1.0 / a.scale[vv] : 1.0;
-      v = static_cast<float>((static_cast<double>(a.Q[row * a.ldq + col]) - mu) * inv);
-    }
+    if (row < a.n && cin) v = static_cast<float>((static_cast<double>(q[i]) - rmu[rr]) * rinv[rr]);
     tile[rr][cc] = v;
   }
   __syncthreads();
-  // output element (col cc, row rr) at ((blk * kp + c0 + cc) * 32 + pos(rr, cc))
-  for (int e = tid; e < KB * BT; e += 256) {
-    const int cc = e / KB, rr = e % KB;
-    const float x = tile[rr][cc];
-    const size_t o = (size_t(blk) * a.kp + c0 + cc) * KB + (a.algo == 0 ? pos_f32(rr, cc) : pos_b16(rr, cc));
-    if (a.algo == 0) {
-      a.pf[o] = x;
-    } else {
-      const unsigned short h = bf16_rn_bits(x);
-      const float r1 = x - bf16_to_f(h);
-      const unsigned short m = bf16_rn_bits(r1);
-      a.p0[o] = h;
-      a.p1[o] = m;
-      if (a.algo == 2) a.p2[o] = bf16_rn_bits(r1 - bf16_to_f(m));
+  if (a.algo == 0) {
+    // slot g of column c holds rows (g >> 1) + 4 j + 16 (g & 1), j = 0..3 (pos_f32)
+#pragma unroll
+    for (int i = 0; i < BT * 8 / 256; ++i) {
+      const int t = tid + 256 * i, cw = t >> 3, g = t & 7;
+      flt4 x;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) x[j] = tile[(g >> 1) + 4 * j + 16 * (g & 1)][cw];
+      const size_t o = (size_t(blk) * a.kp + c0 + cw) * KB + ((g ^ ((cw >> 1) & 7)) << 2);
+      *reinterpret_cast<flt4*>(a.pf + o) = x;
+    }
+  } else {
+    // slot g of column c holds rows 8 g .. 8 g + 7 (pos_b16)
+#pragma unroll
+    for (int i = 0; i < BT * 4 / 256; ++i) {
+      const int t = tid + 256 * i, cw = t >> 2, g = t & 3;
+      us8 h, m, l;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const float x = tile[8 * g + j][cw];
+        const unsigned short hh = bf16_rn_bits(x);
+        const float r1 = x - bf16_to_f(hh);
+        const unsigned short mm = bf16_rn_bits(r1);
+        h[j] = hh;
+        m[j] = mm;
+        l[j] = bf16_rn_bits(r1 - bf16_to_f(mm));
+      }
+      const size_t o = (size_t(blk) * a.kp + c0 + cw) * KB + ((g ^ ((cw >> 2) & 3)) << 3);
+      *reinterpret_cast<us8*>(a.p0 + o) = h;
+      *reinterpret_cast<us8*>(a.p1 + o) = m;
+      if (a.algo == 2) *reinterpret_cast<us8*>(a.p2 + o) = l;
     }
   }
 }
