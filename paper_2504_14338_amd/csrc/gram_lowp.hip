@@ -193,6 +193,7 @@ struct PackedGeom {
   static constexpr int PANEL = BT * COLB;           // bytes of one panel part of a block
   static constexpr int CHUNKS = PANEL / 1024;       // 1 KB LDS-DMA chunks per panel part
   static constexpr int STAGE = 2 * NPART * PANEL;   // A and B panels, all parts
+  static constexpr int NSTAGE = 2;                  // LDS stages (loads of one in flight)
 };
 
 template <int ALGO, bool DIAG>
@@ -207,7 +208,7 @@ __device__ __forceinline__ void packed_tile(const MmaArgs& g, int64_t b_lo, int6
 
   // chunk q of panel part (part, side) of block blk -> LDS slot
   auto issue = [&](int64_t st) {
-    unsigned char* S = smem + (st & 1) * Gm::STAGE;
+    unsigned char* S = smem + (st % Gm::NSTAGE) * Gm::STAGE;
     const int64_t blk = b_lo + st;
 #pragma unroll
     for (int part = 0; part < NPART; ++part) {
@@ -232,12 +233,22 @@ __device__ __forceinline__ void packed_tile(const MmaArgs& g, int64_t b_lo, int6
 
   const int cm = lane & 15;
   const int gq = lane >> 4;
-  if (nst > 0) issue(0);
+  constexpr int NS = Gm::NSTAGE;
+  // LDS-DMA instructions one wave issues per stage
+  constexpr int PER = NPART * (DIAG ? 1 : 2) * (Gm::CHUNKS / 4);
+  for (int64_t p = 0; p < NS - 1 && p < nst; ++p) issue(p);
   for (int64_t st = 0; st < nst; ++st) {
-    wait_vmem<0>();
+    // stage st has landed once at most the later stages' loads are outstanding
+    // (loads to LDS complete in issue order)
+    if (NS > 2 && st + 1 < nst)
+      wait_vmem<PER>();
+    else
+      wait_vmem<0>();
     barrier_only();
-    if (st + 1 < nst) issue(st + 1);
-    const unsigned char* S = smem + (st & 1) * Gm::STAGE;
+    // the buffer of stage st + NS - 1 was read in iteration st - 1, which every
+    // wave has left at the barrier above
+    if (st + NS - 1 < nst) issue(st + NS - 1);
+    const unsigned char* S = smem + (st % NS) * Gm::STAGE;
     const unsigned char* SA = S;
     const unsigned char* SB = DIAG ? S : S + NPART * Gm::PANEL;
     if constexpr (ALGO == 0) {
@@ -279,20 +290,19 @@ __device__ __forceinline__ void packed_tile(const MmaArgs& g, int64_t b_lo, int6
           b[q][j] = __builtin_bit_cast(
               bf16x8, *reinterpret_cast<const us8*>(SB + q * Gm::PANEL + (wn * 64 + j * 16 + cm) * Gm::COLB + o));
       }
+      // products in the outer loop (smallest first): 16 independent blocks lie
+      // between two products into one accumulator, so no MFMA waits on the
+      // result of the previous one
+      constexpr int NPROD = ALGO == 2 ? 6 : 3;
+      constexpr int PA[6] = {2, 0, 1, 1, 0, 0}, PB[6] = {0, 2, 1, 0, 1, 0};
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int pr = (ALGO == 2 ? 0 : 3); pr < 6; ++pr)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          // smallest products first
-          if constexpr (ALGO == 2) {
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2][i], b[0][j], acc[i][j], 0, 0, 0);
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[2][j], acc[i][j], 0, 0, 0);
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[1][j], acc[i][j], 0, 0, 0);
-          }
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[0][j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[1][j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[0][j], acc[i][j], 0, 0, 0);
-        }
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[PA[pr]][i], b[PB[pr]][j], acc[i][j], 0, 0, 0);
+      (void)NPROD;
     }
     if ((st + 1) % SLAB_STAGES == 0 || st + 1 == nst) {
 #pragma unroll
@@ -309,7 +319,7 @@ __device__ __forceinline__ void packed_tile(const MmaArgs& g, int64_t b_lo, int6
 
 template <int ALGO>
 __global__ __launch_bounds__(NTH, ALGO == 2 ? 1 : 2) void gram_packed_kernel(MmaArgs g) {
-  __shared__ __attribute__((aligned(16))) unsigned char smem[2 * PackedGeom<ALGO>::STAGE];
+  __shared__ __attribute__((aligned(16))) unsigned char smem[PackedGeom<ALGO>::NSTAGE * PackedGeom<ALGO>::STAGE];
   int t, s;
   {
     const int bid = blockIdx.x;
