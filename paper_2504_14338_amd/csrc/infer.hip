@@ -32,10 +32,6 @@ int gram_f64_internal(hipStream_t st, const double* X, int64_t n, int64_t m, int
                       const double* scale, int nvars, const int64_t* var_rows_h, double* D, int64_t ldd, void* ws,
                       size_t ws_bytes);
 size_t gram_f64_workspace_internal(int64_t n, int64_t m, int nvars);
-int cross_gram_internal(hipStream_t st, const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t n,
-                        int64_t mx, int64_t my, double* C, int64_t ldc, void* ws, size_t ws_bytes,
-                        const double* mean, const double* scale, int nvars, const int64_t* var_rows_h);
-size_t cross_gram_workspace_internal(int64_t n, int64_t mx, int64_t my);
 
 namespace {
 
@@ -970,9 +966,6 @@ __global__ void zero_ints_kernel(int* p, int64_t n) {
   if (i < n) p[i] = 0;
 }
 
-__global__ void copy_kernel(const double* __restrict__ a, double* __restrict__ b, int64_t n) {
-  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) b[i] = a[i];
-}
 
 // ---------------------------------------------------------------------------
 // host-side planning
