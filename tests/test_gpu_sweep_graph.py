@@ -175,3 +175,33 @@ def test_captured_sweep_replays_eager_results(gpu_lib, qhat40, clean_tuning, aut
             assert best[g] == (g * n + exp if exp >= 0 else -1)
     finally:
         sw.close()
+
+
+def test_uneven_groups_and_several_chunks(gpu_lib, qhat40, clean_tuning):
+    """40 distinct beta2 values (two chunks of beta2 groups) with 1 to 3 pairs
+    per value: pair tables per chunk, batch order by group and right-hand sides
+    of different widths per group, against the oracle's solves."""
+    dp = gpu_lib
+    rng = np.random.default_rng(11)
+    b2_vals = synth.logspace_points(-6, 0, 40)
+    b1, b2 = [], []
+    for i, v in enumerate(b2_vals):
+        for _ in range(1 + i % 3):
+            b1.append(float(10.0 ** rng.uniform(-8, -2)))
+            b2.append(float(v))
+    order = rng.permutation(len(b1))  # pairs of one beta2 not adjacent
+    b1 = [b1[i] for i in order]
+    b2 = [b2[i] for i in order]
+    r_list = [10, 20]
+    for r in r_list:  # narrow blocks, so several block columns at s = 55 and 210
+        dp.tune_set(dp.TUNE_CHOL_KB, dp.n_quad(r), 64)
+        dp.tune_set(dp.TUNE_TRSM_KB, dp.n_quad(r), 128)
+    print(f"{len(b1)} pairs over 40 beta2 values, r in {r_list}", flush=True)
+    O, status, views = dp.infer(qhat40, r_list, b1, b2)
+    st = status.cpu().numpy()
+    Qh = qhat40.cpu().numpy()
+    for g, r in enumerate(r_list):
+        _, G, B = orc.opinf_data(Qh[:r])
+        for p in range(len(b1)):
+            assert st[g * len(b1) + p] == 0, (r, p)
+            check_operators(G, B, r, b1[p], b2[p], views[g][p].cpu().numpy(), (r, p), Qh.shape[1])
