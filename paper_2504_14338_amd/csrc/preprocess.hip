@@ -30,12 +30,16 @@ __global__ __launch_bounds__(256) void row_stats_kernel(
   if constexpr (NV > 0) {
     double v[NV];
     double s = 0.0;
+    // every load reads a valid address (clamped) and the value is selected
+    // after it, so the NV loads of a lane are in flight together
 #pragma unroll
     for (int j = 0; j < NV; ++j) {
-      int64_t t = lane + 64 * j;
-      v[j] = (t < k) ? ld(q + t) : 0.0;
-      s += v[j];
+      const int64_t t = lane + 64 * j;
+      const double x = ld(q + (t < k ? t : 0));
+      v[j] = (t < k) ? x : 0.0;
     }
+#pragma unroll
+    for (int j = 0; j < NV; ++j) s += v[j];
     s = wave_sum(s);
     mu = center ? s / static_cast<double>(k) : 0.0;
 #pragma unroll
