@@ -256,14 +256,16 @@ __global__ __launch_bounds__(TNT) void sytrd_reg_kernel(TridArgs a) {
       if (owns_next) make_reflector(a, row_ptr(int((j + 1) / P)), j + 1, &red[0][0]);
       continue;
     }
-    // this thread's entries of v_j; owned rows keep theirs in LDS
+    // this thread's entries of v_j, all loads in flight together (clamped
+    // addresses, selected after); the owned rows' v_i by a separate load
     double vr[NM];
 #pragma unroll
     for (int m = 0; m < NM; ++m) {
       const int64_t l = j + 1 + tid + int64_t(TNT) * m;
-      vr[m] = (l < k) ? ld_dev(v + l) : 0.0;
-      if (l < k && l >= g && (l - g) % P == 0) vown[(l - g) / P] = vr[m];
+      const double x = ld_dev(v + (l < k ? l : j + 1));
+      vr[m] = (l < k) ? x : 0.0;
     }
+    for (int q = q0 + tid; q < nown; q += TNT) vown[q] = ld_dev(v + g + int64_t(q) * P);
     __syncthreads();
     // ---- p_i = tau * A[i, j+1:] . v[j+1:] for owned rows i > j ----------------
     double mypart = 0.0;
@@ -318,7 +320,8 @@ __global__ __launch_bounds__(TNT) void sytrd_reg_kernel(TridArgs a) {
 #pragma unroll
     for (int m = 0; m < NM; ++m) {
       const int64_t l = j + 1 + tid + int64_t(TNT) * m;
-      wr[m] = (l < k) ? ld_dev(pj + l) - K * vr[m] : 0.0;
+      const double pl = ld_dev(pj + (l < k ? l : j + 1));
+      wr[m] = (l < k) ? pl - K * vr[m] : 0.0;
     }
     // ---- rank-2 update; the next reflector's row goes first ----------------
     auto update_row = [&](int q) {
