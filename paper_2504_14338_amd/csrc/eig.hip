@@ -627,6 +627,142 @@ __global__ __launch_bounds__(256) void backtransform_kernel(const double* A /* r
   for (int64_t i = threadIdx.x; i < k; i += 256) zg[i] = zs[i];
 }
 
+// Blocked form (k <= 2048): the reflectors go in blocks of 32,
+// H_{j0} H_{j0+1} ... H_{j0+31} = I - V T V^T (compact WY; T upper
+// triangular with T[i][i] = tau_i and T[0:i, i] = -tau_i T[0:i, 0:i] V^T v_i),
+// applied from the last block to the first, so each vector takes one
+// 32-wide dot pass, one T product and one update pass per block instead of
+// one reduction per reflector.  Row j of A holds v_j from column j + 1 on
+// (earlier columns are not written), so every read is masked by l > j.
+constexpr int BTB = 32;
+
+__global__ __launch_bounds__(256) void bt_tfactor_kernel(const double* __restrict__ A, const double* __restrict__ tau,
+                                                         int64_t k, double* __restrict__ Tb) {
+  __shared__ double Vs[BTB][64 + 1];
+  __shared__ double G[BTB][BTB + 1];
+  __shared__ double T[BTB][BTB + 1];
+  __shared__ double taus[BTB];
+  const int tid = threadIdx.x;
+  const int64_t j0 = int64_t(blockIdx.x) * BTB;
+  const int nref = int(min<int64_t>(BTB, (k - 1) - j0));  // reflectors j0 .. j0 + nref - 1 (j <= k - 2)
+  double g[BTB * BTB / 256];
+#pragma unroll
+  for (int q = 0; q < BTB * BTB / 256; ++q) g[q] = 0.0;
+  for (int64_t c0 = j0 + 1; c0 < k; c0 += 64) {
+    double x[BTB * 64 / 256];
+#pragma unroll
+    for (int q = 0; q < BTB * 64 / 256; ++q) {  // loads in flight together (clamped)
+      const int e = tid + 256 * q, i = e / 64;
+      const int64_t l = c0 + e % 64, j = j0 + i;
+      x[q] = A[(i < nref ? j : j0) * k + (l < k ? l : k - 1)];
+    }
+#pragma unroll
+    for (int q = 0; q < BTB * 64 / 256; ++q) {
+      const int e = tid + 256 * q, i = e / 64;
+      const int64_t l = c0 + e % 64, j = j0 + i;
+      Vs[i][e % 64] = (i < nref && l < k && l > j) ? x[q] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < BTB * BTB / 256; ++q) {
+      const int e = tid + 256 * q, i = e / BTB, i2 = e % BTB;
+      double acc = g[q];
+      for (int cc = 0; cc < 64; ++cc) acc += Vs[i][cc] * Vs[i2][cc];
+      g[q] = acc;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < BTB * BTB / 256; ++q) {
+    const int e = tid + 256 * q;
+    G[e / BTB][e % BTB] = g[q];
+    T[e / BTB][e % BTB] = 0.0;
+  }
+  if (tid < BTB) taus[tid] = (tid < nref) ? tau[j0 + tid] : 0.0;
+  __syncthreads();
+  for (int i = 0; i < BTB; ++i) {
+    if (tid < i) {
+      double acc = 0.0;
+      for (int c = tid; c < i; ++c) acc += T[tid][c] * G[c][i];
+      T[tid][i] = -taus[i] * acc;
+    } else if (tid == i) {
+      T[i][i] = taus[i];
+    }
+    __syncthreads();
+  }
+  double* Tout = Tb + size_t(blockIdx.x) * BTB * BTB;
+  for (int e = tid; e < BTB * BTB; e += 256) Tout[e] = T[e / BTB][e % BTB];
+}
+
+// one workgroup per vector; thread t keeps z[t + 256 m] in registers
+template <int NZ>
+__global__ __launch_bounds__(256) void bt_apply_kernel(const double* __restrict__ A, const double* __restrict__ Tb,
+                                                       int64_t k, double* __restrict__ Z) {
+  __shared__ double red[4][BTB];
+  __shared__ double sv[BTB], sp[BTB];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  double* zg = Z + size_t(blockIdx.x) * k;
+  double z[NZ];
+#pragma unroll
+  for (int m = 0; m < NZ; ++m) {
+    const int64_t l = tid + 256 * int64_t(m);
+    const double x = zg[l < k ? l : 0];
+    z[m] = (l < k) ? x : 0.0;
+  }
+  const int nblk = int((k - 1 + BTB - 1) / BTB);
+  for (int b = nblk - 1; b >= 0; --b) {
+    const int64_t j0 = int64_t(b) * BTB;
+    const int nref = int(min<int64_t>(BTB, (k - 1) - j0));
+    double s[BTB];
+#pragma unroll
+    for (int i = 0; i < BTB; ++i) s[i] = 0.0;
+#pragma unroll
+    for (int m = 0; m < NZ; ++m) {
+      const int64_t l = tid + 256 * int64_t(m);
+      if (j0 + 1 > int64_t(m) * 256 + 255) continue;  // this lane group's columns all lie left of the block
+      double x[BTB];
+#pragma unroll
+      for (int i = 0; i < BTB; ++i) x[i] = A[(j0 + (i < nref ? i : 0)) * k + (l < k ? l : k - 1)];
+#pragma unroll
+      for (int i = 0; i < BTB; ++i)
+        if (i < nref && l < k && l > j0 + i) s[i] += x[i] * z[m];
+    }
+#pragma unroll
+    for (int i = 0; i < BTB; ++i) {
+      const double t = wave_sum(s[i]);
+      if (lane == 0) red[wv][i] = t;
+    }
+    __syncthreads();
+    if (tid < BTB) sv[tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+    __syncthreads();
+    if (tid < BTB) {
+      const double* Tt = Tb + size_t(b) * BTB * BTB + size_t(tid) * BTB;
+      double acc = 0.0;
+      for (int c = tid; c < BTB; ++c) acc += Tt[c] * sv[c];
+      sp[tid] = acc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < NZ; ++m) {
+      const int64_t l = tid + 256 * int64_t(m);
+      if (j0 + 1 > int64_t(m) * 256 + 255) continue;
+      double x[BTB];
+#pragma unroll
+      for (int i = 0; i < BTB; ++i) x[i] = A[(j0 + (i < nref ? i : 0)) * k + (l < k ? l : k - 1)];
+      double acc = 0.0;
+#pragma unroll
+      for (int i = 0; i < BTB; ++i)
+        if (i < nref && l < k && l > j0 + i) acc += x[i] * sp[i];
+      z[m] -= acc;
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < NZ; ++m) {
+    const int64_t l = tid + 256 * int64_t(m);
+    if (l < k) zg[l] = z[m];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // 5. sign rule, Qhat = sqrt(lambda_j) u_j^T, T_r = u_j / sqrt(lambda_j)
 // ---------------------------------------------------------------------------
@@ -797,6 +933,7 @@ struct EigWs {
   double* bounds;
   double* Z;
   double* scratch;
+  double* tblk;  // T factors of the blocked back-transformation
   unsigned char* swaps;
   unsigned* words;  // [0] barrier, [1] abort, [2] r_out, [3] published reflectors
 };
@@ -814,6 +951,7 @@ EigWs carve_eig(void* ws, size_t bytes, int64_t k, int r_max, int P, Carver& c) 
   w.bounds = c.take<double>(8);
   w.Z = c.take<double>(size_t(r_max) * k);
   w.scratch = c.take<double>(size_t(r_max) * 5 * k);
+  w.tblk = c.take<double>(size_t((k + BTB - 1) / BTB) * BTB * BTB);
   w.swaps = c.take<unsigned char>(size_t(r_max) * k);
   w.words = c.take<unsigned>(8);
   (void)ws;
@@ -905,12 +1043,20 @@ extern "C" int dopinf_reduce(void* stream, const double* D, int64_t k, int64_t l
     }
     DOPINF_LAUNCHED();
   }
-  const size_t zl = size_t(k) * sizeof(double);
-  if (zl > 65536)
-    DOPINF_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(backtransform_kernel),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, int(zl)));
-  backtransform_kernel<<<unsigned(r), 256, zl, st>>>(w.A, w.tau, k, w.Z);
-  DOPINF_LAUNCHED();
+  if (k >= 2 && k <= 2048) {
+    const unsigned nblk = unsigned((k - 1 + BTB - 1) / BTB);
+    bt_tfactor_kernel<<<nblk, 256, 0, st>>>(w.A, w.tau, k, w.tblk);
+    DOPINF_LAUNCHED();
+    bt_apply_kernel<8><<<unsigned(r), 256, 0, st>>>(w.A, w.tblk, k, w.Z);
+    DOPINF_LAUNCHED();
+  } else {
+    const size_t zl = size_t(k) * sizeof(double);
+    if (zl > 65536)
+      DOPINF_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(backtransform_kernel),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(zl)));
+    backtransform_kernel<<<unsigned(r), 256, zl, st>>>(w.A, w.tau, k, w.Z);
+    DOPINF_LAUNCHED();
+  }
   form_qhat_kernel<<<unsigned(r), 256, 0, st>>>(w.Z, k, r, lambda, Qhat, ldqh, Tr, ldtr, info);
   DOPINF_LAUNCHED();
   return DOPINF_OK;
