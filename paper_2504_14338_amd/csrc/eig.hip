@@ -416,9 +416,24 @@ __global__ void tri_prep_kernel(const double* d, const double* e, int64_t k, dou
   }
 }
 
-// lambda_desc[k-1-m] = m-th smallest eigenvalue
-__global__ __launch_bounds__(256) void tri_bisect_kernel(const double* d, const double* e2, int64_t k,
+// lambda_desc[k-1-m] = m-th smallest eigenvalue.  With LDS_MODE the
+// workgroup first copies d and e2 into LDS, so the Sturm recurrence (one
+// dependent step per row) reads LDS instead of waiting on the cache.
+template <bool LDS_MODE>
+__global__ __launch_bounds__(256) void tri_bisect_kernel(const double* dg, const double* e2g, int64_t k,
                                                          const double* bounds, double* lambda_desc) {
+  extern __shared__ double tri_lds[];
+  const double* d = dg;
+  const double* e2 = e2g;
+  if (LDS_MODE) {
+    for (int64_t i = threadIdx.x; i < k; i += 256) {
+      tri_lds[i] = dg[i];
+      tri_lds[k + i] = (i + 1 < k) ? e2g[i] : 0.0;
+    }
+    __syncthreads();
+    d = tri_lds;
+    e2 = tri_lds + k;
+  }
   const int64_t m = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (m >= k) return;
@@ -1011,7 +1026,20 @@ extern "C" int dopinf_reduce(void* stream, const double* D, int64_t k, int64_t l
   DOPINF_HIP(hipLaunchCooperativeKernel(pl.kern, dim3(pl.P), dim3(TNT), args, unsigned(pl.lds_bytes), st));
   tri_prep_kernel<<<1, 256, 0, st>>>(w.d, w.e, k, w.e2, w.bounds);
   DOPINF_LAUNCHED();
-  tri_bisect_kernel<<<unsigned((k + 3) / 4), 256, 0, st>>>(w.d, w.e2, k, w.bounds, lambda);
+  {
+    int devb = 0, maxldsb = 0;
+    DOPINF_HIP(hipGetDevice(&devb));
+    DOPINF_HIP(hipDeviceGetAttribute(&maxldsb, hipDeviceAttributeMaxSharedMemoryPerBlock, devb));
+    const size_t tl = size_t(2 * k) * sizeof(double);
+    if (tl + 1024 <= size_t(maxldsb)) {
+      if (tl > 65536)
+        DOPINF_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(tri_bisect_kernel<true>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(tl)));
+      tri_bisect_kernel<true><<<unsigned((k + 3) / 4), 256, tl, st>>>(w.d, w.e2, k, w.bounds, lambda);
+    } else {
+      tri_bisect_kernel<false><<<unsigned((k + 3) / 4), 256, 0, st>>>(w.d, w.e2, k, w.bounds, lambda);
+    }
+  }
   DOPINF_LAUNCHED();
   finite_check_kernel<<<1, 64, 0, st>>>(w.bounds, reinterpret_cast<int*>(w.words + 1), info);
   DOPINF_LAUNCHED();
