@@ -165,7 +165,7 @@ int dopinf_infer(void* stream, const double* Qhat, int64_t ldqh, int64_t k,
 /* ---- Step IV: ROM rollouts, scoring and selection (Sec. 3.5) -------------
  * For every item of dopinf_infer's layout: qt_0 = Qhat[0:r_g, 0],
  * qt_{t+1} = A qt_t + H quad(qt_t) + c for n_states states (qt_0 included).
- * train_err[item] = max_{t < k_train} ||qt_t - qhat_t|| / ||qhat_t||;
+ * train_err[item] = max_{t < min(k_train, n_states)} ||qt_t - qhat_t|| / ||qhat_t||;
  * growth[item]    = max_{t,i} |qt_t[i] - m_i| / max_{t<k_train,i} |qhat_t[i] - m_i|
  *                   with m the temporal mean of Qhat[0:r_g, 0:k_train];
  * outcome[item]   = DOPINF_ITEM_*: pass iff every state is finite and
