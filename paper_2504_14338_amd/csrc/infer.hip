@@ -971,16 +971,46 @@ __global__ void zero_ints_kernel(int* p, int64_t n) {
 // host-side planning
 // ---------------------------------------------------------------------------
 struct InferLayout {
-  int rmax, uc;
+  int rmax, uc, n_r;
   int64_t smax, dmax, m, lde, km1;
   size_t e_off, g_off, gram_off, gram_bytes;
-  size_t chunk_off;  // per-chunk storage start
-  size_t l_bytes, r_bytes, linv_bytes, cv_bytes;  // per u, at rmax
-  size_t part_bytes;  // CV split partials of one chunk
-  size_t vq_bytes;    // per pair: v, and X_q, s x r at rmax
+  std::vector<size_t> grp_off;  // per group: start of its chunk storage
   size_t misc_off;
   size_t total;
 };
+
+// Per-group storage of one chunk of beta2 groups, at the group's own r; the
+// groups have separate regions so that they can run concurrently.
+struct ChunkBufs {
+  GroupGeom geo;
+  int64_t s, w, r1;
+  double *Lq, *R, *R2, *Linv, *CV, *part, *V, *Xq, *XL;
+  int* ufail;
+};
+
+ChunkBufs carve_chunk(Carver& cc, int r, int rmax, int64_t m, int64_t dmax, int uc, int n_pairs) {
+  ChunkBufs b{};
+  b.geo.r = r;
+  b.geo.rmax = rmax;
+  b.geo.s = nquad(r);
+  b.geo.m = m;
+  b.geo.dmax = dmax;
+  b.s = b.geo.s;
+  b.w = 2 * r + 1;
+  b.r1 = r + 1;
+  const int64_t nblk = (b.s + NB - 1) / NB;
+  b.Lq = cc.take<double>(size_t(uc) * b.s * b.s);
+  b.R = cc.take<double>(size_t(uc) * b.s * b.w);
+  b.R2 = cc.take<double>(size_t(uc) * b.s * b.w);
+  b.Linv = cc.take<double>(size_t(uc) * nblk * NB * NB);
+  b.CV = cc.take<double>(size_t(uc) * b.r1 * b.w);
+  b.part = cc.take<double>(size_t(uc) * CV_SPLIT_MAX * b.r1 * b.w);
+  b.V = cc.take<double>(size_t(n_pairs) * b.s * r);
+  b.Xq = cc.take<double>(size_t(n_pairs) * b.s * r);
+  b.XL = cc.take<double>(size_t(n_pairs) * b.r1 * r);
+  b.ufail = cc.take<int>(size_t(uc));
+  return b;
+}
 
 // Every table the kernels read from host data (beta values, the pair -> beta2
 // group map of every chunk) has a fixed place in the workspace, written once
@@ -988,17 +1018,16 @@ struct InferLayout {
 // of it replays without host memory.
 struct MiscPtrs {
   double* b2dev;  // distinct beta2 values (n_u <= n_pairs)
-  int* ufail;     // per u of a chunk
   int* pair_u;    // per chunk: pair -> u within the chunk, -1 outside
   int* border;    // per chunk: batch entry -> pair (pairs of the chunk, by u)
   int* ue0;       // per chunk: first batch entry of u
   int* ucnt;      // per chunk: batch entries of u
   double* b1dev;  // per pair
-  double* XL;     // per pair: X_l ((r+1) x r)
 };
 
 InferLayout layout(int64_t k, int n_r, const int* r_list, int n_pairs) {
   InferLayout L{};
+  L.n_r = n_r;
   int rmax = 0;
   for (int g = 0; g < n_r; ++g) rmax = r_list[g] > rmax ? r_list[g] : rmax;
   L.rmax = rmax;
@@ -1016,33 +1045,22 @@ InferLayout layout(int64_t k, int n_r, const int* r_list, int n_pairs) {
   L.gram_off = (c.used + 255) & ~size_t(255);
   L.gram_bytes = gram_f64_workspace_internal(L.km1, L.m, 1);
   c.take<char>(L.gram_bytes);
-  const int64_t s = L.smax, w = 2 * rmax + 1, nblk = (s + NB - 1) / NB;
-  L.l_bytes = size_t(s) * s * sizeof(double);
-  L.r_bytes = size_t(s) * w * sizeof(double);
-  L.linv_bytes = size_t(nblk) * NB * NB * sizeof(double);
-  L.cv_bytes = size_t(rmax + 1) * w * sizeof(double);
-  L.part_bytes = size_t(L.uc) * CV_SPLIT_MAX * L.cv_bytes;
-  L.vq_bytes = size_t(s) * rmax * sizeof(double);
   const int uc = L.uc;
-  L.chunk_off = (c.used + 255) & ~size_t(255);
-  c.take<char>(uc * L.l_bytes);
-  c.take<char>(uc * L.r_bytes);
-  c.take<char>(uc * L.r_bytes);
-  c.take<char>(uc * L.linv_bytes);
-  c.take<char>(uc * L.cv_bytes);
-  c.take<char>(L.part_bytes);
-  c.take<char>(size_t(n_pairs) * L.vq_bytes);
-  c.take<char>(size_t(n_pairs) * L.vq_bytes);
+  L.grp_off.resize(n_r);
+  for (int g = 0; g < n_r; ++g) {
+    L.grp_off[g] = (c.used + 255) & ~size_t(255);
+    Carver cg(nullptr, 0);
+    carve_chunk(cg, r_list[g], rmax, L.m, L.dmax, uc, n_pairs);
+    c.take<char>(cg.used);
+  }
   L.misc_off = (c.used + 255) & ~size_t(255);
   const int max_chunks = (n_pairs + uc - 1) / uc;
   c.take<double>(size_t(n_pairs));                    // distinct beta2
-  c.take<int>(size_t(uc));                            // fail flag per u
   c.take<int>(size_t(max_chunks) * n_pairs);          // pair -> u, per chunk
   c.take<int>(size_t(max_chunks) * n_pairs);          // batch entry -> pair, per chunk
   c.take<int>(size_t(max_chunks) * uc);               // first batch entry per u, per chunk
   c.take<int>(size_t(max_chunks) * uc);               // batch entries per u, per chunk
   c.take<double>(size_t(n_pairs));                    // beta1 per pair
-  c.take<double>(size_t(n_pairs) * (rmax + 1) * rmax);  // X_l per pair
   L.total = c.used;
   return L;
 }
@@ -1052,13 +1070,11 @@ MiscPtrs misc_ptrs(const InferLayout& L, void* ws, int n_pairs) {
   MiscPtrs m{};
   const int max_chunks = (n_pairs + L.uc - 1) / L.uc;
   m.b2dev = mc.take<double>(size_t(n_pairs));
-  m.ufail = mc.take<int>(size_t(L.uc));
   m.pair_u = mc.take<int>(size_t(max_chunks) * n_pairs);
   m.border = mc.take<int>(size_t(max_chunks) * n_pairs);
   m.ue0 = mc.take<int>(size_t(max_chunks) * L.uc);
   m.ucnt = mc.take<int>(size_t(max_chunks) * L.uc);
   m.b1dev = mc.take<double>(size_t(n_pairs));
-  m.XL = mc.take<double>(size_t(n_pairs) * (L.rmax + 1) * L.rmax);
   return m;
 }
 
@@ -1073,7 +1089,46 @@ struct InferPlan {
   std::vector<int> ue0, ucnt;      // n_chunks x uc
   std::vector<int> nbc, npu_max;   // per chunk: pairs, most pairs of one u
   int n_u, n_chunks;
+  // With several reduced sizes, each group runs on a stream of its own
+  // (forked from the caller's stream after the data Gram and joined back at
+  // the end; a stream capture turns this into parallel graph branches).
+  std::vector<hipStream_t> gst;
+  std::vector<hipEvent_t> gev;
+  hipEvent_t fork = nullptr;
+  InferPlan() = default;
+  InferPlan(const InferPlan&) = delete;
+  InferPlan& operator=(const InferPlan&) = delete;
+  ~InferPlan() {
+    for (hipEvent_t x : gev) (void)hipEventDestroy(x);
+    if (fork) (void)hipEventDestroy(fork);
+  }
 };
+
+// Streams of the group fork: created once per host thread and device
+// (default priority, non-blocking) and kept for the life of the process, so
+// that a call neither pays for creating them nor shares them with a call on
+// another host thread.  Events are per call.
+int infer_streams(InferPlan& P) {
+  if (P.n_r < 2 || !P.gst.empty()) return DOPINF_OK;
+  int dev = 0;
+  DOPINF_HIP(hipGetDevice(&dev));
+  static thread_local std::vector<std::vector<hipStream_t>> pool;
+  if (int(pool.size()) <= dev) pool.resize(dev + 1);
+  std::vector<hipStream_t>& mine = pool[dev];
+  while (int(mine.size()) < P.n_r) {
+    hipStream_t x = nullptr;
+    DOPINF_HIP(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+    mine.push_back(x);
+  }
+  DOPINF_HIP(hipEventCreateWithFlags(&P.fork, hipEventDisableTiming));
+  for (int g = 0; g < P.n_r; ++g) {
+    P.gst.push_back(mine[g]);
+    hipEvent_t e = nullptr;
+    DOPINF_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    P.gev.push_back(e);
+  }
+  return DOPINF_OK;
+}
 
 // block-column widths of the s x s Cholesky and of the triangular solves
 // with its factor: the tuned values, else the defaults
@@ -1182,37 +1237,10 @@ int infer_gram(hipStream_t st, const InferPlan& P, const double* Qhat, int64_t l
                            L.gram_bytes);
 }
 
-struct ChunkBufs {
-  GroupGeom geo;
-  int64_t s, w, r1;
-  double *Lq, *R, *R2, *Linv, *CV, *part, *V, *Xq;
-};
-
 ChunkBufs chunk_bufs(const InferPlan& P, int g, void* ws) {
   const InferLayout& L = P.L;
-  ChunkBufs b{};
-  b.geo.r = P.r_list[g];
-  b.geo.rmax = L.rmax;
-  b.geo.s = nquad(b.geo.r);
-  b.geo.m = L.m;
-  b.geo.dmax = L.dmax;
-  b.s = b.geo.s;
-  b.w = 2 * b.geo.r + 1;
-  b.r1 = b.geo.r + 1;
-  const int uc = L.uc;
-  // per-u storage at this r (packed tighter than at rmax)
-  const int64_t nblk = (b.s + NB - 1) / NB;
-  char* ch = static_cast<char*>(ws) + L.chunk_off;
-  Carver cc(ch, ~size_t(0));
-  b.Lq = cc.take<double>(size_t(uc) * b.s * b.s);
-  b.R = cc.take<double>(size_t(uc) * b.s * b.w);
-  b.R2 = cc.take<double>(size_t(uc) * b.s * b.w);
-  b.Linv = cc.take<double>(size_t(uc) * nblk * NB * NB);
-  b.CV = cc.take<double>(size_t(uc) * b.r1 * b.w);
-  b.part = cc.take<double>(size_t(uc) * CV_SPLIT_MAX * b.r1 * b.w);
-  b.V = cc.take<double>(size_t(P.n_pairs) * b.s * b.geo.r);
-  b.Xq = cc.take<double>(size_t(P.n_pairs) * b.s * b.geo.r);
-  return b;
+  Carver cc(static_cast<char*>(ws) + L.grp_off[g], ~size_t(0));
+  return carve_chunk(cc, P.r_list[g], L.rmax, L.m, L.dmax, L.uc, P.n_pairs);
 }
 
 // the chunk's beta2 groups: G_qq + beta2 I gathered and factored with block
@@ -1220,12 +1248,12 @@ ChunkBufs chunk_bufs(const InferPlan& P, int g, void* ws) {
 int chunk_factor(hipStream_t st, const InferPlan& P, const ChunkBufs& b, int c, int nu, int64_t kb, void* ws) {
   const MiscPtrs m = misc_ptrs(P.L, ws, P.n_pairs);
   const double* GE = reinterpret_cast<const double*>(static_cast<char*>(ws) + P.L.g_off);
-  zero_ints_kernel<<<1, 256, 0, st>>>(m.ufail, P.L.uc);
+  zero_ints_kernel<<<1, 256, 0, st>>>(b.ufail, P.L.uc);
   DOPINF_LAUNCHED();
   dim3 grid(unsigned((b.s + 255) / 256 > 64 ? 64 : (b.s + 255) / 256), unsigned(b.s), unsigned(nu));
   gather_qq_kernel<<<grid, 256, 0, st>>>(GE, b.geo, m.b2dev + size_t(c) * P.L.uc, b.Lq, b.R);
   DOPINF_LAUNCHED();
-  return cholesky_run(st, b.Lq, b.s, b.Linv, m.ufail, nu, kb);
+  return cholesky_run(st, b.Lq, b.s, b.Linv, b.ufail, nu, kb);
 }
 
 // [W | y] = L^{-1} [G_ql | B_q], CV = W^T [W | y], and per pair the Schur
@@ -1251,13 +1279,13 @@ int chunk_linear(hipStream_t st, const InferPlan& P, const ChunkBufs& b, int g, 
   pa.GE = GE;
   pa.geo = b.geo;
   pa.CV = b.CV;
-  pa.ufail = m.ufail;
+  pa.ufail = b.ufail;
   pa.pair_u = m.pair_u + size_t(c) * P.n_pairs;
   pa.beta1 = m.b1dev;
   pa.O = O + dopinf_operator_offset(P.n_r, P.r_list.data(), P.n_pairs, g * P.n_pairs);
   pa.status = status + g * P.n_pairs;
   pa.n_pairs = P.n_pairs;
-  pa.XL = m.XL;
+  pa.XL = b.XL;
   const size_t smem = size_t(r1) * (r1 + b.geo.r) * sizeof(double);
   pair_solve_kernel<<<P.n_pairs, 256, smem, st>>>(pa);
   DOPINF_LAUNCHED();
@@ -1268,7 +1296,7 @@ QuadArgs quad_args(const InferPlan& P, const ChunkBufs& b, int g, int c, double*
   const MiscPtrs m = misc_ptrs(P.L, ws, P.n_pairs);
   QuadArgs qa{};
   qa.R2 = b.R2;
-  qa.XL = m.XL;
+  qa.XL = b.XL;
   qa.border = m.border + size_t(c) * P.n_pairs;
   qa.pair_u = m.pair_u + size_t(c) * P.n_pairs;
   qa.V = b.V;
@@ -1300,22 +1328,41 @@ int infer_enqueue(hipStream_t st, const InferPlan& P, const double* Qhat, int64_
   int rc = infer_gram(st, P, Qhat, ldqh, ws);
   if (rc) return rc;
   const int uc = P.L.uc;
-  for (int g = 0; g < P.n_r; ++g) {
+  const bool forked = !P.gst.empty();
+  if (forked) DOPINF_HIP(hipEventRecord(P.fork, st));
+  // largest group first: it is the longest chain, the others fill its gaps
+  for (int gi = P.n_r - 1; gi >= 0 && !rc; --gi) {
+    int g = gi;
+    if (forked) {  // order of issue: by decreasing r
+      g = 0;
+      for (int h = 0; h < P.n_r; ++h) {
+        int rank = 0;
+        for (int q = 0; q < P.n_r; ++q) rank += (P.r_list[q] < P.r_list[h]) || (P.r_list[q] == P.r_list[h] && q < h);
+        if (rank == gi) g = h;
+      }
+    }
+    hipStream_t sg = forked ? P.gst[g] : st;
+    if (forked) DOPINF_HIP(hipStreamWaitEvent(sg, P.fork, 0));
     const ChunkBufs b = chunk_bufs(P, g, ws);
     const int64_t kc = chol_kb(b.s), kt = trsm_kb(b.s);
-    for (int c = 0; c < P.n_chunks; ++c) {
+    for (int c = 0; c < P.n_chunks && !rc; ++c) {
       const int nu = (P.n_u - c * uc) < uc ? (P.n_u - c * uc) : uc;
-      rc = chunk_factor(st, P, b, c, nu, kc, ws);
-      if (!rc) rc = chunk_linear(st, P, b, g, c, nu, kt, O, status, ws);
-      if (rc) return rc;
-      if (P.nbc[c] == 0) continue;
-      rc = chunk_quad_solve(st, P, b, g, c, nu, kt, ws);
-      if (rc) return rc;
-      oq_kernel<<<quad_grid(P, b, c), 256, 0, st>>>(quad_args(P, b, g, c, O, ws));
-      DOPINF_LAUNCHED();
+      rc = chunk_factor(sg, P, b, c, nu, kc, ws);
+      if (!rc) rc = chunk_linear(sg, P, b, g, c, nu, kt, O, status, ws);
+      if (rc || P.nbc[c] == 0) continue;
+      rc = chunk_quad_solve(sg, P, b, g, c, nu, kt, ws);
+      if (rc) continue;
+      oq_kernel<<<quad_grid(P, b, c), 256, 0, sg>>>(quad_args(P, b, g, c, O, ws));
+      if (hipGetLastError() != hipSuccess) rc = fail(DOPINF_E_HIP, "kernel launch failed (oq_kernel)");
+    }
+    if (forked) {
+      // join even after an error, so that no forked work is left outside
+      const hipError_t e1 = hipEventRecord(P.gev[g], sg);
+      const hipError_t e2 = hipStreamWaitEvent(st, P.gev[g], 0);
+      if (!rc && (e1 != hipSuccess || e2 != hipSuccess)) rc = fail(DOPINF_E_HIP, "joining the group streams failed");
     }
   }
-  return DOPINF_OK;
+  return rc;
 }
 
 }  // namespace
@@ -1427,6 +1474,7 @@ extern "C" int dopinf_infer(void* stream, const double* Qhat, int64_t ldqh, int6
   if (rc) return rc;
   hipStream_t st = static_cast<hipStream_t>(stream);
   rc = infer_upload(st, P, ws);
+  if (!rc) rc = infer_streams(P);
   if (rc) return rc;
   return infer_enqueue(st, P, Qhat, ldqh, O, status, ws);
 }
@@ -1488,6 +1536,7 @@ extern "C" int dopinf_sweep_create(void* stream, const double* Qhat, int64_t ldq
     if (rc) return rc;
   }
   rc = infer_upload(st, P, wsi);
+  if (!rc) rc = infer_streams(P);
   if (rc) return rc;
   DOPINF_HIP(hipStreamSynchronize(st));
   DOPINF_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
