@@ -385,6 +385,14 @@ constexpr int UT = 128;      // output tile edge
 constexpr int UK = 16;       // K slab
 constexpr int UP = UT + 4;   // LDS pitch in doubles
 
+// An operand staged transposed (16 lanes writing 16 different K rows) is
+// stored at column c ^ swz(k): with the 132-double pitch the 16 lanes of a
+// store then hit 16 different bank pairs (4-way conflicts without it); the
+// XOR only permutes inside 16-aligned groups, so fragment reads of 16
+// consecutive columns stay conflict-free.
+__device__ __forceinline__ int swz(int k) { return (k >> 2) & 3; }
+
+template <bool SWA, bool SWB>
 __device__ __forceinline__ void mma_slab128(const double (*As)[UP], const double (*Bs)[UP], dbl4 (&acc)[4][4],
                                             int lane, int wm, int wn) {
 #pragma unroll
@@ -392,9 +400,9 @@ __device__ __forceinline__ void mma_slab128(const double (*As)[UP], const double
     const int k = kk * 4 + (lane >> 4);
     double af[4], bf[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) af[i] = As[k][wm * 64 + i * 16 + (lane & 15)];
+    for (int i = 0; i < 4; ++i) af[i] = As[k][(wm * 64 + i * 16 + (lane & 15)) ^ (SWA ? swz(k) : 0)];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) bf[j] = Bs[k][wn * 64 + j * 16 + (lane & 15)];
+    for (int j = 0; j < 4; ++j) bf[j] = Bs[k][(wn * 64 + j * 16 + (lane & 15)) ^ (SWB ? swz(k) : 0)];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -443,7 +451,7 @@ __global__ __launch_bounds__(256, 2) void trsm_update_t128_kernel(const double* 
       if (TRANS)
         As[buf][kr0 + 2 * q][lc] = ra[q];
       else
-        As[buf][kl][ml + 16 * q] = ra[q];
+        As[buf][kl][(ml + 16 * q) ^ swz(kl)] = ra[q];
       Bs[buf][kr0 + 2 * q][lc] = rb[q];
     }
   };
@@ -460,7 +468,7 @@ __global__ __launch_bounds__(256, 2) void trsm_update_t128_kernel(const double* 
   for (int64_t kb = k0; kb < k1; kb += UK) {
     const bool more = kb + UK < k1;
     if (more) load(kb + UK);
-    mma_slab128(As[buf], Bs[buf], acc, lane, wm, wn);
+    mma_slab128<!TRANS, false>(As[buf], Bs[buf], acc, lane, wm, wn);
     if (more) store(buf ^ 1);
     __syncthreads();
     buf ^= 1;
@@ -538,8 +546,8 @@ __global__ __launch_bounds__(256, 2) void syrk_update128_kernel(double* __restri
   auto store = [&](int buf) {
 #pragma unroll
     for (int q = 0; q < UT / 16; ++q) {
-      As[buf][kl][ml + 16 * q] = ra[q];
-      if (!diag) Bs[buf][kl][ml + 16 * q] = rb[q];
+      As[buf][kl][(ml + 16 * q) ^ swz(kl)] = ra[q];
+      if (!diag) Bs[buf][kl][(ml + 16 * q) ^ swz(kl)] = rb[q];
     }
   };
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, wm = wv >> 1, wn = wv & 1;
@@ -555,7 +563,7 @@ __global__ __launch_bounds__(256, 2) void syrk_update128_kernel(double* __restri
   for (int64_t kb = a0; kb < k1; kb += UK) {
     const bool more = kb + UK < k1;
     if (more) load(kb + UK);
-    mma_slab128(As[buf], diag ? As[buf] : Bs[buf], acc, lane, wm, wn);
+    mma_slab128<true, true>(As[buf], diag ? As[buf] : Bs[buf], acc, lane, wm, wn);
     if (more) store(buf ^ 1);
     __syncthreads();
     buf ^= 1;
