@@ -237,7 +237,11 @@ __device__ __forceinline__ void packed_tile(const MmaArgs& g, int64_t b_lo, int6
   // LDS-DMA instructions one wave issues per stage
   constexpr int PER = NPART * (DIAG ? 1 : 2) * (Gm::CHUNKS / 4);
   for (int64_t p = 0; p < NS - 1 && p < nst; ++p) issue(p);
-  for (int64_t st = 0; st < nst; ++st) {
+  // slabs of SLAB_STAGES stages: the inner loop has no branch on the
+  // accumulators, so they stay in the registers the MFMAs write
+  for (int64_t s0 = 0; s0 < nst; s0 += SLAB_STAGES) {
+  const int64_t s1 = s0 + SLAB_STAGES < nst ? s0 + SLAB_STAGES : nst;
+  for (int64_t st = s0; st < s1; ++st) {
     // stage st has landed once at most the later stages' loads are outstanding
     // (loads to LDS complete in issue order)
     if (NS > 2 && st + 1 < nst)
@@ -304,15 +308,14 @@ __device__ __forceinline__ void packed_tile(const MmaArgs& g, int64_t b_lo, int6
             acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[PA[pr]][i], b[PB[pr]][j], acc[i][j], 0, 0, 0);
       (void)NPROD;
     }
-    if ((st + 1) % SLAB_STAGES == 0 || st + 1 == nst) {
+  }
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < 4; ++j) {
 #pragma unroll
-          for (int e = 0; e < 4; ++e) acc64[i][j][e] += static_cast<double>(acc[i][j][e]);
-          acc[i][j] = flt4{0.f, 0.f, 0.f, 0.f};
-        }
+      for (int e = 0; e < 4; ++e) acc64[i][j][e] += static_cast<double>(acc[i][j][e]);
+      acc[i][j] = flt4{0.f, 0.f, 0.f, 0.f};
     }
   }
 }
