@@ -23,6 +23,7 @@
 //    Triangular solves then reduce to products with the stored diagonal
 //    inverses.
 #include <algorithm>
+#include <cstdlib>
 #include <vector>
 
 #include "common.hpp"
@@ -1116,21 +1117,38 @@ struct InferPlan {
 // (default priority, non-blocking) and kept for the life of the process, so
 // that a call neither pays for creating them nor shares them with a call on
 // another host thread.  Events are per call.
+//
+// A process has GPU_MAX_HW_QUEUES hardware queues (4 unless set), and streams
+// beyond that share them: two groups whose streams land on one queue run one
+// after the other (measured: r = 60 and r = 80 on one queue, eager sweep
+// 74 ms).  So at most (queues - 1) group streams are used, the caller's
+// stream keeping one queue: the largest groups get a stream each and the
+// smallest groups share the last one.
 int infer_streams(InferPlan& P) {
   if (P.n_r < 2 || !P.gst.empty()) return DOPINF_OK;
+  int hwq = 4;
+  if (const char* e = std::getenv("GPU_MAX_HW_QUEUES")) {
+    const int v = std::atoi(e);
+    if (v >= 1) hwq = v;
+  }
+  const int ns = std::min(P.n_r, hwq - 1);
+  if (ns < 2) return DOPINF_OK;  // no fork: the groups run on the caller's stream
   int dev = 0;
   DOPINF_HIP(hipGetDevice(&dev));
   static thread_local std::vector<std::vector<hipStream_t>> pool;
   if (int(pool.size()) <= dev) pool.resize(dev + 1);
   std::vector<hipStream_t>& mine = pool[dev];
-  while (int(mine.size()) < P.n_r) {
+  while (int(mine.size()) < ns) {
     hipStream_t x = nullptr;
     DOPINF_HIP(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
     mine.push_back(x);
   }
   DOPINF_HIP(hipEventCreateWithFlags(&P.fork, hipEventDisableTiming));
   for (int g = 0; g < P.n_r; ++g) {
-    P.gst.push_back(mine[g]);
+    // rank by decreasing r (ties: lower index first)
+    int rank = 0;
+    for (int q = 0; q < P.n_r; ++q) rank += (P.r_list[q] > P.r_list[g]) || (P.r_list[q] == P.r_list[g] && q < g);
+    P.gst.push_back(mine[std::min(rank, ns - 1)]);
     hipEvent_t e = nullptr;
     DOPINF_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     P.gev.push_back(e);
@@ -1338,10 +1356,17 @@ int infer_enqueue(hipStream_t st, const InferPlan& P, const double* Qhat, int64_
   const int uc = P.L.uc;
   const bool forked = !P.gst.empty();
   if (forked) DOPINF_HIP(hipEventRecord(P.fork, st));
-  // largest group first: it is the longest chain, the others fill its gaps
-  for (int gi = P.n_r - 1; gi >= 0 && !rc; --gi) {
+  // Order of issue.  Eagerly, smallest r first: issued largest first, the
+  // smaller groups started only once the largest had drained part of its
+  // queue.  Under capture, largest r first: a graph's branches start in
+  // capture order, and the largest group is the longest chain.
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  DOPINF_HIP(hipStreamIsCapturing(st, &cap));
+  const bool largest_first = cap == hipStreamCaptureStatusActive;
+  for (int gi0 = 0; gi0 < P.n_r && !rc; ++gi0) {
+    const int gi = largest_first ? P.n_r - 1 - gi0 : gi0;
     int g = gi;
-    if (forked) {  // order of issue: by decreasing r
+    if (forked) {  // g: the group of rank gi in increasing r
       g = 0;
       for (int h = 0; h < P.n_r; ++h) {
         int rank = 0;
