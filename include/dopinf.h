@@ -152,7 +152,13 @@ int dopinf_reduce(void* stream, const double* D, int64_t k, int64_t ldd,
  * O + dopinf_operator_offset(n_r, r_list_h, n_pairs, g*n_pairs + p):
  * groups in r_list order, pairs inside a group in the given order.
  * status[item] (device ints, n_r * n_pairs) = DOPINF_OK or DOPINF_E_NOTSPD.
- * r_g >= 1, k >= 2, n_pairs >= 1. */
+ * r_g >= 1, k >= 2, n_pairs >= 1.
+ * With several reduced sizes the groups run concurrently on internal streams
+ * of the calling host thread (at most GPU_MAX_HW_QUEUES - 1 of them, 4 - 1
+ * when unset; the largest groups get one each), forked from `stream` after
+ * the shared data Gram and joined back before the call's work ends on
+ * `stream`; the results do not depend on the fork.  Under stream capture
+ * the fork becomes parallel graph branches. */
 size_t dopinf_operator_offset(int n_r, const int* r_list_h, int n_pairs,
                               int item);
 size_t dopinf_infer_workspace(int64_t k, int n_r, const int* r_list_h,

@@ -205,3 +205,24 @@ def test_uneven_groups_and_several_chunks(gpu_lib, qhat40, clean_tuning):
         for p in range(len(b1)):
             assert st[g * len(b1) + p] == 0, (r, p)
             check_operators(G, B, r, b1[p], b2[p], views[g][p].cpu().numpy(), (r, p), Qh.shape[1])
+
+
+def test_group_fork_does_not_change_results(gpu_lib, qhat40, clean_tuning, monkeypatch):
+    """Several reduced sizes run on internal streams (at most
+    GPU_MAX_HW_QUEUES - 1, read at every call): with no fork (2 queues), with
+    the two smallest of four groups sharing a stream (4 queues) and with a
+    stream per group (8 queues) the operators and statuses are bit for bit
+    the same, since every group's kernels and their order are unchanged."""
+    import torch
+    dp = gpu_lib
+    r_list = [10, 20, 30, 40]
+    out = {}
+    for q in ("2", "4", "8"):
+        monkeypatch.setenv("GPU_MAX_HW_QUEUES", q)
+        print(f"infer with GPU_MAX_HW_QUEUES={q}", flush=True)
+        O, status, _ = dp.infer(qhat40, r_list, B1, B2)
+        torch.cuda.synchronize()
+        out[q] = (O.cpu().numpy(), status.cpu().numpy())
+    for q in ("4", "8"):
+        assert np.array_equal(out[q][1], out["2"][1]), q
+        assert np.array_equal(out[q][0], out["2"][0]), q
