@@ -113,26 +113,25 @@ __device__ __forceinline__ int64_t gcol_l(const GroupGeom& g, int c) {
 __device__ __forceinline__ int64_t gcol_rhs(const GroupGeom& g, int c) { return g.dmax + c; }
 
 __global__ __launch_bounds__(256) void gather_qq_kernel(const double* __restrict__ GE, GroupGeom geo,
-                                                        const double* __restrict__ beta2u, double* __restrict__ L,
-                                                        double* __restrict__ R) {
-  const int u = blockIdx.z;
+                                                        const double* __restrict__ beta2u, int nu,
+                                                        double* __restrict__ L, double* __restrict__ R) {
+  // row a of G_qq (lower triangle) and of [G_ql | B_q], gathered once from
+  // G_E and written into every beta2 matrix of the chunk
   const int64_t a = blockIdx.y;
   const int64_t s = geo.s;
   const int64_t ca = gcol_q(geo, a);
   const double* grow = GE + ca * geo.m;
-  double* Lu = L + size_t(u) * s * s;
-  const double b2 = beta2u[u];
   for (int64_t b = int64_t(blockIdx.x) * 256 + threadIdx.x; b <= a; b += int64_t(gridDim.x) * 256) {
-    double v = grow[gcol_q(geo, b)];
-    if (b == a) v += b2;
-    Lu[a * s + b] = v;
+    const double v = grow[gcol_q(geo, b)];
+    double* dst = L + a * s + b;
+    for (int u = 0; u < nu; ++u) dst[size_t(u) * s * s] = (b == a) ? v + beta2u[u] : v;
   }
   const int w = 2 * geo.r + 1;
-  double* Ru = R + size_t(u) * s * w;
   if (blockIdx.x == 0) {
     for (int c = threadIdx.x; c < w; c += 256) {
       const int64_t col = (c <= geo.r) ? gcol_l(geo, c) : gcol_rhs(geo, c - geo.r - 1);
-      Ru[a * w + c] = grow[col];
+      const double v = grow[col];
+      for (int u = 0; u < nu; ++u) R[size_t(u) * s * w + a * w + c] = v;
     }
   }
 }
@@ -1276,8 +1275,8 @@ int chunk_factor(hipStream_t st, const InferPlan& P, const ChunkBufs& b, int c, 
   const double* GE = reinterpret_cast<const double*>(static_cast<char*>(ws) + P.L.g_off);
   zero_ints_kernel<<<1, 256, 0, st>>>(b.ufail, P.L.uc);
   DOPINF_LAUNCHED();
-  dim3 grid(unsigned((b.s + 255) / 256 > 64 ? 64 : (b.s + 255) / 256), unsigned(b.s), unsigned(nu));
-  gather_qq_kernel<<<grid, 256, 0, st>>>(GE, b.geo, m.b2dev + size_t(c) * P.L.uc, b.Lq, b.R);
+  dim3 grid(unsigned((b.s + 255) / 256 > 64 ? 64 : (b.s + 255) / 256), unsigned(b.s));
+  gather_qq_kernel<<<grid, 256, 0, st>>>(GE, b.geo, m.b2dev + size_t(c) * P.L.uc, nu, b.Lq, b.R);
   DOPINF_LAUNCHED();
   return cholesky_run(st, b.Lq, b.s, b.Linv, b.ufail, nu, kb);
 }
