@@ -24,6 +24,7 @@
 //    inverses.
 #include <algorithm>
 #include <cstdlib>
+#include <type_traits>
 #include <vector>
 
 #include "common.hpp"
@@ -193,19 +194,27 @@ __global__ __launch_bounds__(256) void potf2_kernel(double* __restrict__ A, int6
     const bool onT = j > c;
     double* dst = onT ? &T[0][0] : &W[0][0];
     const double f = (onT ? T[j][c] : W[c][j]) * rp;
-    double a[NB / 4], b[NB / 4];
+    // rows c + 1 .. NB - 1 in steps of 4: 16 per thread for c < 32, then 8
+    auto step = [&](auto kn) {
+      constexpr int KN = decltype(kn)::value;
+      double a[KN], b[KN];
 #pragma unroll
-    for (int k = 0; k < NB / 4; ++k) {
-      const int i = c + 1 + tid / NB + 4 * k;
-      const int ic = i < NB ? i : NB - 1;
-      a[k] = T[ic][c];
-      b[k] = dst[ic * (NB + 1) + j];
-    }
+      for (int k = 0; k < KN; ++k) {
+        const int i = c + 1 + tid / NB + 4 * k;
+        const int ic = i < NB ? i : NB - 1;
+        a[k] = T[ic][c];
+        b[k] = dst[ic * (NB + 1) + j];
+      }
 #pragma unroll
-    for (int k = 0; k < NB / 4; ++k) {
-      const int i = c + 1 + tid / NB + 4 * k;
-      if (i < NB && (!onT || j <= i)) dst[i * (NB + 1) + j] = b[k] - a[k] * f;
-    }
+      for (int k = 0; k < KN; ++k) {
+        const int i = c + 1 + tid / NB + 4 * k;
+        if (i < NB && (!onT || j <= i)) dst[i * (NB + 1) + j] = b[k] - a[k] * f;
+      }
+    };
+    if (c < NB / 2)
+      step(std::integral_constant<int, NB / 4>{});
+    else
+      step(std::integral_constant<int, NB / 8>{});
     __syncthreads();
   }
   double* Lo = Linv + (size_t(u) * ((n + NB - 1) / NB) + jb / NB) * NB * NB;
