@@ -166,8 +166,9 @@ def sweep_bench(dp, torch, Qhat80, reps=1):
     _, _, _, tune_ms = dp.autotune_infer(Qhat80, r_list, b1, b2)
     torch.cuda.synchronize()
     t_tune = time.perf_counter() - t0
-    chosen = {r: {"cholesky": dp.tune_get(dp.TUNE_CHOL_KB, dp.n_quad(r)),
-                  "solve": dp.tune_get(dp.TUNE_TRSM_KB, dp.n_quad(r))} for r in r_list}
+    chosen = {r: {"cholesky": [dp.tune_get(dp.TUNE_CHOL_KB, dp.n_quad(r)), dp.tune_get(dp.TUNE_CHOL_KB2, dp.n_quad(r))],
+                  "solve": [dp.tune_get(dp.TUNE_TRSM_KB, dp.n_quad(r)), dp.tune_get(dp.TUNE_TRSM_KB2, dp.n_quad(r))]}
+              for r in r_list}
     timer = Timer(torch)
     res = None
     for _ in range(reps + 1):  # first pass warms up
@@ -205,7 +206,8 @@ def sweep_bench(dp, torch, Qhat80, reps=1):
         "block_widths": chosen,
         "autotune_ms": {str(r): {"cholesky": [round(float(x), 3) for x in tune_ms[g, 0]],
                                  "solve": [round(float(x), 3) for x in tune_ms[g, 1]]} for g, r in enumerate(r_list)},
-        "autotune_candidates": dp.autotune_candidates(),
+        "autotune_candidates": [list(p) for p in zip(dp.autotune_candidates(dp.TUNE_CHOL_KB),
+                                                     dp.autotune_candidates(dp.TUNE_CHOL_KB2))],
         "autotune_s": round(t_tune, 2),
         "capture_s": round(t_capture, 2),
         "passing": int((oc == dp.ITEM_PASS).sum()),

@@ -208,24 +208,36 @@ int dopinf_rollout(void* stream, int n_r, const int* r_list_h, int n_pairs,
  * a blocked Cholesky, and solves triangular systems with that factor; both
  * are blocked in block columns whose width is a launch parameter: wider
  * blocks read the trailing matrix or the right-hand sides fewer times,
- * narrower ones start the trailing work sooner.  A process-wide table holds
- * the widths per s (untuned sizes use 256):
- *   DOPINF_TUNE_CHOL_KB  the Cholesky's block-column width,
- *   DOPINF_TUNE_TRSM_KB  the triangular solves' block-column depth.
+ * narrower ones start the trailing work sooner.  An optional inner width
+ * (a divisor of the outer one) blocks each block column once more: its
+ * 64-wide panels then update only their inner block, and the block column
+ * takes updates of the inner depth.  A process-wide table holds the widths
+ * per s (untuned sizes use 256 and no inner width):
+ *   DOPINF_TUNE_CHOL_KB   the Cholesky's block-column width,
+ *   DOPINF_TUNE_TRSM_KB   the triangular solves' block-column depth,
+ *   DOPINF_TUNE_CHOL_KB2  the Cholesky's inner width (0: none),
+ *   DOPINF_TUNE_TRSM_KB2  the triangular solves' inner depth (0: none).
+ * An inner width that is not smaller than the outer one or does not divide
+ * it is ignored.
  * dopinf_tune_set: value = width (multiple of 64 in [64, 4096]) or 0 to
  *   clear; returns DOPINF_E_ARG for an unknown parameter or a bad value.
  * dopinf_tune_get: the stored width, 0 when untuned.
- * dopinf_autotune_candidates: the widths the autotuner tries (the same list
- *   for both parameters); writes up to max_values of them to values_h (may
- *   be NULL) and returns their number.
+ * dopinf_autotune_candidates: the (outer, inner) width pairs the autotuner
+ *   tries, the same list for the Cholesky and the solves: the outer widths
+ *   for DOPINF_TUNE_CHOL_KB / _TRSM_KB, the inner ones (0: none), in the
+ *   same order, for DOPINF_TUNE_CHOL_KB2 / _TRSM_KB2; writes up to
+ *   max_values of them to values_h (may be NULL) and returns their number.
  * dopinf_autotune_infer: dopinf_infer with the same arguments and results,
  *   preceded by the autotuner: for every group, on its first beta2 chunk,
- *   every Cholesky width is timed, then every solve depth; the fastest are
- *   stored for that s.  The stream is synchronized while timing.  times_h
- *   (NULL or n_r x 2 x candidates floats, ms): per group the Cholesky
- *   timings, then the solve timings (0 where a group had nothing to time). */
+ *   every Cholesky width pair is timed, then every solve pair; the fastest
+ *   are stored for that s.  The stream is synchronized while timing.
+ *   times_h (NULL or n_r x 2 x candidates floats, ms): per group the
+ *   Cholesky timings, then the solve timings (0 where a group had nothing
+ *   to time). */
 #define DOPINF_TUNE_CHOL_KB 1
 #define DOPINF_TUNE_TRSM_KB 2
+#define DOPINF_TUNE_CHOL_KB2 3
+#define DOPINF_TUNE_TRSM_KB2 4
 int dopinf_tune_set(int param, int64_t key, int value);
 int dopinf_tune_get(int param, int64_t key);
 int dopinf_autotune_candidates(int param, int* values_h, int max_values);

@@ -19,7 +19,7 @@ __all__ = [
     "reduce", "infer", "operator_offset", "rollout", "traj_offset",
     "n_quad", "lib_path", "closure_param_count", "rom_residuals", "closure_fit", "closure_norms",
     "closure_grad", "closure_eval", "closure_rollout", "TUNE_CHOL_KB", "tune_set", "tune_get",
-    "autotune_candidates", "autotune_infer", "Sweep", "TUNE_TRSM_KB",
+    "autotune_candidates", "autotune_infer", "Sweep", "TUNE_TRSM_KB", "TUNE_CHOL_KB2", "TUNE_TRSM_KB2",
 ]
 
 OK, E_ARG, E_HIP, E_WORKSPACE, E_RANK, E_NOTSPD, E_NONFINITE, E_NOSTABLE, E_TIMEOUT = range(9)
@@ -31,6 +31,8 @@ ROLLOUT_FULL = 1
 ROLLOUT_ONE_WG = 2
 TUNE_CHOL_KB = 1
 TUNE_TRSM_KB = 2
+TUNE_CHOL_KB2 = 3
+TUNE_TRSM_KB2 = 4
 SWEEP_AUTOTUNE = 1
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -355,6 +357,9 @@ def tune_get(param, key):
 
 
 def autotune_candidates(param=TUNE_CHOL_KB):
+    """The autotuner's width candidates: outer widths for TUNE_CHOL_KB /
+    TUNE_TRSM_KB, the matching inner widths (0: none) for TUNE_CHOL_KB2 /
+    TUNE_TRSM_KB2."""
     lib = load()
     n = lib.dopinf_autotune_candidates(int(param), None, 0)
     if n < 0:

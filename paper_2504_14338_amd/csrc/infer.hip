@@ -607,42 +607,75 @@ inline int64_t syrk_tiles128(int64_t n, int64_t c_lo, int64_t c_hi) {
   return TC * TR - TC * (TC - 1) / 2;
 }
 
+// Block-column widths of the blocked Cholesky and triangular solves: an
+// outer width and an optional inner one (0: none) that must divide it; the
+// innermost level is always NB.
+struct Widths {
+  int64_t w[2];
+  int n;  // levels above NB
+};
+inline Widths widths(int64_t kb, int64_t kb2) {
+  Widths x{{kb, 0}, 1};
+  if (kb2 >= NB && kb2 < kb && kb % kb2 == 0) {
+    x.w[1] = kb2;
+    x.n = 2;
+  }
+  return x;
+}
+
 // Blocked Cholesky of nu matrices (s x s, row-major, lower triangle used) in
-// place.  Block columns of width kb (a multiple of NB): inside a block column
-// the 64-wide panels are factored left to right and each updates only the
-// rest of its block column; the columns right of the block column then take
-// one update of depth kb.  kb = NB is the plain right-looking algorithm;
-// larger kb reads and writes the trailing matrix kb / NB times less often.
-int cholesky_run(hipStream_t st, double* Lq, int64_t s, double* Linv, int* ufail, int nu, int64_t kb) {
-  for (int64_t cb = 0; cb < s; cb += kb) {
-    const int64_t ce = std::min<int64_t>(cb + kb, s);
-    for (int64_t jb = cb; jb < ce; jb += NB) {
+// place, recursive over the widths: columns [c0, c1) are factored in blocks
+// of the level's width; each block is factored one level down and then
+// updates the rest of [c0, c1), all rows below, with depth = its width.  At
+// the last level the 64-wide panels are factored left to right (diagonal
+// block, then the panel below it) and each updates the rest of its block.
+// One width kb is the classic scheme (panels update their block column of
+// kb, the trailing matrix takes one update of depth kb); an inner width
+// keeps the panels' shallow updates inside blocks of kb2 and gives the
+// block column of kb updates of depth kb2.
+int cholesky_run(hipStream_t st, double* Lq, int64_t s, double* Linv, int* ufail, int nu, int64_t kb, int64_t kb2) {
+  const Widths W = widths(kb, kb2);
+  auto syrk = [&](int64_t k0, int64_t kd, int64_t c0, int64_t c1) -> int {
+    const int64_t nt = syrk_tiles128(s, c0, c1);
+    syrk_update128_kernel<<<dim3(unsigned(nt), unsigned(nu)), 256, 0, st>>>(Lq, s, k0, kd, c0, c1);
+    DOPINF_LAUNCHED();
+    return DOPINF_OK;
+  };
+  auto leaf = [&](int64_t c0, int64_t c1) -> int {
+    for (int64_t jb = c0; jb < c1; jb += NB) {
       potf2_kernel<<<nu, 256, 0, st>>>(Lq, s, jb, Linv, ufail);
       DOPINF_LAUNCHED();
       const int64_t rest = s - jb - NB;
       if (rest <= 0) continue;
       panel_kernel<<<dim3(unsigned((rest + NB - 1) / NB), unsigned(nu)), 256, 0, st>>>(Lq, s, jb, Linv);
       DOPINF_LAUNCHED();
-      if (jb + NB < ce) {
-        const int64_t nt = syrk_tiles128(s, jb + NB, ce);
-        syrk_update128_kernel<<<dim3(unsigned(nt), unsigned(nu)), 256, 0, st>>>(Lq, s, jb, NB, jb + NB, ce);
-        DOPINF_LAUNCHED();
+      if (jb + NB < c1) {
+        const int rc = syrk(jb, NB, jb + NB, c1);
+        if (rc) return rc;
       }
     }
-    if (ce < s) {
-      const int64_t nt = syrk_tiles128(s, ce, s);
-      syrk_update128_kernel<<<dim3(unsigned(nt), unsigned(nu)), 256, 0, st>>>(Lq, s, cb, ce - cb, ce, s);
-      DOPINF_LAUNCHED();
+    return DOPINF_OK;
+  };
+  // columns [c0, c1) at level lev (0: outer width)
+  auto level = [&](auto&& self, int64_t c0, int64_t c1, int lev) -> int {
+    if (lev == W.n) return leaf(c0, c1);
+    for (int64_t cb = c0; cb < c1; cb += W.w[lev]) {
+      const int64_t ce = std::min<int64_t>(cb + W.w[lev], c1);
+      int rc = self(self, cb, ce, lev + 1);
+      if (!rc && ce < c1) rc = syrk(cb, ce - cb, ce, c1);
+      if (rc) return rc;
     }
-  }
-  return DOPINF_OK;
+    return DOPINF_OK;
+  };
+  return level(level, int64_t(0), s, 0);
 }
 
 // ng groups, each with at most max_cols virtual columns; block columns of kb
 // rows (a multiple of NB)
 int trsm_run(hipStream_t st, bool trans, const double* L, int64_t n, const double* Linv, double* X, double* Yout,
-             RhsMap m, int64_t max_cols, int ng, int64_t kb) {
-  const int64_t nblk = (n + NB - 1) / NB, kbb = kb / NB;
+             RhsMap m, int64_t max_cols, int ng, int64_t kb, int64_t kb2) {
+  const int64_t nblk = (n + NB - 1) / NB;
+  const Widths W = widths(kb, kb2);
   const unsigned nct = unsigned((max_cols + NB - 1) / NB);
   auto diag = [&](int64_t J) -> int {
     if (!trans)
@@ -664,27 +697,42 @@ int trsm_run(hipStream_t st, bool trans, const double* L, int64_t n, const doubl
     DOPINF_LAUNCHED();
     return DOPINF_OK;
   };
-  int rc = DOPINF_OK;
-  if (!trans) {
-    for (int64_t cb = 0; cb < nblk && !rc; cb += kbb) {
-      const int64_t ce = std::min(cb + kbb, nblk);
-      for (int64_t J = cb; J < ce && !rc; ++J) {
-        rc = diag(J);
-        if (!rc) rc = update(J + 1, ce, J * NB, (J + 1) * NB);
+  // blocks [b0, b1) at level lev, recursive over the widths as in
+  // cholesky_run: a solved block of the level's width updates the rest of
+  // [b0, b1) with depth = its width; at the last level single blocks
+  auto level = [&](auto&& self, int64_t b0, int64_t b1, int lev) -> int {
+    int rc = DOPINF_OK;
+    if (lev == W.n) {
+      if (!trans) {
+        for (int64_t J = b0; J < b1 && !rc; ++J) {
+          rc = diag(J);
+          if (!rc) rc = update(J + 1, b1, J * NB, (J + 1) * NB);
+        }
+      } else {
+        for (int64_t J = b1 - 1; J >= b0 && !rc; --J) {
+          rc = diag(J);
+          if (!rc) rc = update(b0, J, J * NB, (J + 1) * NB);
+        }
       }
-      if (!rc) rc = update(ce, nblk, cb * NB, ce * NB);
+      return rc;
     }
-  } else {
-    for (int64_t ce = nblk; ce > 0 && !rc; ce -= kbb) {
-      const int64_t cb = std::max<int64_t>(0, ce - kbb);
-      for (int64_t J = ce - 1; J >= cb && !rc; --J) {
-        rc = diag(J);
-        if (!rc) rc = update(cb, J, J * NB, (J + 1) * NB);
+    const int64_t kbb = W.w[lev] / NB;
+    if (!trans) {
+      for (int64_t cb = b0; cb < b1 && !rc; cb += kbb) {
+        const int64_t ce = std::min(cb + kbb, b1);
+        rc = self(self, cb, ce, lev + 1);
+        if (!rc) rc = update(ce, b1, cb * NB, ce * NB);
       }
-      if (!rc) rc = update(0, cb, cb * NB, ce * NB);
+    } else {
+      for (int64_t ce = b1; ce > b0 && !rc; ce -= kbb) {
+        const int64_t cb = std::max(b0, ce - kbb);
+        rc = self(self, cb, ce, lev + 1);
+        if (!rc) rc = update(b0, cb, cb * NB, ce * NB);
+      }
     }
-  }
-  return rc;
+    return rc;
+  };
+  return level(level, int64_t(0), nblk, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -1164,15 +1212,18 @@ int infer_streams(InferPlan& P) {
   return DOPINF_OK;
 }
 
-// block-column widths of the s x s Cholesky and of the triangular solves
-// with its factor: the tuned values, else the defaults
-int64_t chol_kb(int64_t s) {
+// block-column widths (outer, inner) of the s x s Cholesky and of the
+// triangular solves with its factor: the tuned values, else (256, none)
+struct Kb {
+  int64_t w, w2;
+};
+Kb chol_kb(int64_t s) {
   const int v = tune::get(DOPINF_TUNE_CHOL_KB, s);
-  return v > 0 ? v : 4 * NB;
+  return Kb{v > 0 ? v : 4 * NB, tune::get(DOPINF_TUNE_CHOL_KB2, s)};
 }
-int64_t trsm_kb(int64_t s) {
+Kb trsm_kb(int64_t s) {
   const int v = tune::get(DOPINF_TUNE_TRSM_KB, s);
-  return v > 0 ? v : 4 * NB;
+  return Kb{v > 0 ? v : 4 * NB, tune::get(DOPINF_TUNE_TRSM_KB2, s)};
 }
 
 int infer_plan(int64_t k, int64_t ldqh, int n_r, const int* r_list_h, int n_pairs, const double* beta1_h,
@@ -1279,7 +1330,7 @@ ChunkBufs chunk_bufs(const InferPlan& P, int g, void* ws) {
 
 // the chunk's beta2 groups: G_qq + beta2 I gathered and factored with block
 // columns of width kb
-int chunk_factor(hipStream_t st, const InferPlan& P, const ChunkBufs& b, int c, int nu, int64_t kb, void* ws) {
+int chunk_factor(hipStream_t st, const InferPlan& P, const ChunkBufs& b, int c, int nu, Kb kb, void* ws) {
   const MiscPtrs m = misc_ptrs(P.L, ws, P.n_pairs);
   const double* GE = reinterpret_cast<const double*>(static_cast<char*>(ws) + P.L.g_off);
   zero_ints_kernel<<<1, 256, 0, st>>>(b.ufail, P.L.uc);
@@ -1287,17 +1338,17 @@ int chunk_factor(hipStream_t st, const InferPlan& P, const ChunkBufs& b, int c, 
   dim3 grid(unsigned((b.s + 255) / 256 > 64 ? 64 : (b.s + 255) / 256), unsigned(b.s));
   gather_qq_kernel<<<grid, 256, 0, st>>>(GE, b.geo, m.b2dev + size_t(c) * P.L.uc, nu, b.Lq, b.R);
   DOPINF_LAUNCHED();
-  return cholesky_run(st, b.Lq, b.s, b.Linv, b.ufail, nu, kb);
+  return cholesky_run(st, b.Lq, b.s, b.Linv, b.ufail, nu, kb.w, kb.w2);
 }
 
 // [W | y] = L^{-1} [G_ql | B_q], CV = W^T [W | y], and per pair the Schur
 // complement solve for X_l (linear and constant columns of O, and XL)
-int chunk_linear(hipStream_t st, const InferPlan& P, const ChunkBufs& b, int g, int c, int nu, int64_t kb, double* O,
+int chunk_linear(hipStream_t st, const InferPlan& P, const ChunkBufs& b, int g, int c, int nu, Kb kb, double* O,
                  int* status, void* ws) {
   const MiscPtrs m = misc_ptrs(P.L, ws, P.n_pairs);
   const double* GE = reinterpret_cast<const double*>(static_cast<char*>(ws) + P.L.g_off);
   const int64_t s = b.s, w = b.w, r1 = b.r1;
-  int rc = trsm_run(st, false, b.Lq, s, b.Linv, b.R, b.R2, RhsMap{nullptr, nullptr, w}, w, nu, kb);
+  int rc = trsm_run(st, false, b.Lq, s, b.Linv, b.R, b.R2, RhsMap{nullptr, nullptr, w}, w, nu, kb.w, kb.w2);
   if (rc) return rc;
   {
     const int nspl = cv_splits(s, int(r1), int(w), nu);
@@ -1347,14 +1398,14 @@ dim3 quad_grid(const InferPlan& P, const ChunkBufs& b, int c) {
 
 // v = y - W X_l per pair, then L^T X_q = v with the pairs of each beta2 group
 // side by side as one right-hand side
-int chunk_quad_solve(hipStream_t st, const InferPlan& P, const ChunkBufs& b, int g, int c, int nu, int64_t kb,
+int chunk_quad_solve(hipStream_t st, const InferPlan& P, const ChunkBufs& b, int g, int c, int nu, Kb kb,
                      void* ws) {
   const MiscPtrs m = misc_ptrs(P.L, ws, P.n_pairs);
   const QuadArgs qa = quad_args(P, b, g, c, nullptr, ws);
   vq_kernel<<<quad_grid(P, b, c), 256, 0, st>>>(qa);
   DOPINF_LAUNCHED();
   const RhsMap rm{m.ue0 + size_t(c) * P.L.uc, m.ucnt + size_t(c) * P.L.uc, b.geo.r};
-  return trsm_run(st, true, b.Lq, b.s, b.Linv, b.V, b.Xq, rm, int64_t(P.npu_max[c]) * b.geo.r, nu, kb);
+  return trsm_run(st, true, b.Lq, b.s, b.Linv, b.V, b.Xq, rm, int64_t(P.npu_max[c]) * b.geo.r, nu, kb.w, kb.w2);
 }
 
 int infer_enqueue(hipStream_t st, const InferPlan& P, const double* Qhat, int64_t ldqh, double* O, int* status,
@@ -1385,7 +1436,7 @@ int infer_enqueue(hipStream_t st, const InferPlan& P, const double* Qhat, int64_
     hipStream_t sg = forked ? P.gst[g] : st;
     if (forked) DOPINF_HIP(hipStreamWaitEvent(sg, P.fork, 0));
     const ChunkBufs b = chunk_bufs(P, g, ws);
-    const int64_t kc = chol_kb(b.s), kt = trsm_kb(b.s);
+    const Kb kc = chol_kb(b.s), kt = trsm_kb(b.s);
     for (int c = 0; c < P.n_chunks && !rc; ++c) {
       const int nu = (P.n_u - c * uc) < uc ? (P.n_u - c * uc) : uc;
       rc = chunk_factor(sg, P, b, c, nu, kc, ws);
@@ -1408,10 +1459,11 @@ int infer_enqueue(hipStream_t st, const InferPlan& P, const double* Qhat, int64_
 
 }  // namespace
 
-// Candidate block-column widths, for the beta2-group Cholesky and for the
-// triangular solves with its factor.
-constexpr int kKbCand[] = {64, 128, 256, 512};
-constexpr int kNumKbCand = 4;
+// Candidate block-column widths (outer, inner; inner 0: one level), for the
+// beta2-group Cholesky and for the triangular solves with its factor.
+constexpr int kKbCand[][2] = {{64, 0},    {128, 0},    {256, 0},    {512, 0},
+                              {512, 128}, {1024, 128}, {1024, 256}, {2048, 256}};
+constexpr int kNumKbCand = 8;
 
 // Minimum over two timed runs of fn (after one warm-up run) on stream st.
 template <class F>
@@ -1452,33 +1504,39 @@ int infer_autotune(hipStream_t st, const InferPlan& P, const double* Qhat, int64
   for (int g = 0; g < P.n_r && !rc; ++g) {
     const ChunkBufs b = chunk_bufs(P, g, ws);
     float* tg = times_h ? times_h + size_t(g) * 2 * kNumKbCand : nullptr;
-    int best = 0;
+    int best = -1;
     float best_t = 0.f;
     for (int ci = 0; ci < kNumKbCand && !rc; ++ci) {
       float t = 0.f;
-      rc = time_min(st, e0, e1, [&] { return chunk_factor(st, P, b, 0, nu, kKbCand[ci], ws); }, t);
+      const Kb kb{kKbCand[ci][0], kKbCand[ci][1]};
+      rc = time_min(st, e0, e1, [&] { return chunk_factor(st, P, b, 0, nu, kb, ws); }, t);
       if (tg) tg[ci] = t;
-      if (!rc && (best == 0 || t < best_t)) {
-        best = kKbCand[ci];
+      if (!rc && (best < 0 || t < best_t)) {
+        best = ci;
         best_t = t;
       }
     }
     if (rc) break;
-    tune::set(DOPINF_TUNE_CHOL_KB, b.s, best);
-    rc = chunk_factor(st, P, b, 0, nu, best, ws);
+    tune::set(DOPINF_TUNE_CHOL_KB, b.s, kKbCand[best][0]);
+    tune::set(DOPINF_TUNE_CHOL_KB2, b.s, kKbCand[best][1]);
+    rc = chunk_factor(st, P, b, 0, nu, chol_kb(b.s), ws);
     if (!rc) rc = chunk_linear(st, P, b, g, 0, nu, trsm_kb(b.s), O, status, ws);
     if (rc || P.nbc[0] == 0) continue;
-    best = 0;
+    best = -1;
     for (int ci = 0; ci < kNumKbCand && !rc; ++ci) {
       float t = 0.f;
-      rc = time_min(st, e0, e1, [&] { return chunk_quad_solve(st, P, b, g, 0, nu, kKbCand[ci], ws); }, t);
+      const Kb kb{kKbCand[ci][0], kKbCand[ci][1]};
+      rc = time_min(st, e0, e1, [&] { return chunk_quad_solve(st, P, b, g, 0, nu, kb, ws); }, t);
       if (tg) tg[kNumKbCand + ci] = t;
-      if (!rc && (best == 0 || t < best_t)) {
-        best = kKbCand[ci];
+      if (!rc && (best < 0 || t < best_t)) {
+        best = ci;
         best_t = t;
       }
     }
-    if (!rc) tune::set(DOPINF_TUNE_TRSM_KB, b.s, best);
+    if (!rc) {
+      tune::set(DOPINF_TUNE_TRSM_KB, b.s, kKbCand[best][0]);
+      tune::set(DOPINF_TUNE_TRSM_KB2, b.s, kKbCand[best][1]);
+    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -1531,8 +1589,11 @@ extern "C" int dopinf_autotune_infer(void* stream, const double* Qhat, int64_t l
 }
 
 extern "C" int dopinf_autotune_candidates(int param, int* values_h, int max_values) {
-  DOPINF_REQUIRE(param == DOPINF_TUNE_CHOL_KB || param == DOPINF_TUNE_TRSM_KB, "unknown tuning parameter %d", param);
-  for (int i = 0; i < kNumKbCand && i < max_values && values_h; ++i) values_h[i] = kKbCand[i];
+  DOPINF_REQUIRE(param == DOPINF_TUNE_CHOL_KB || param == DOPINF_TUNE_TRSM_KB || param == DOPINF_TUNE_CHOL_KB2 ||
+                     param == DOPINF_TUNE_TRSM_KB2,
+                 "unknown tuning parameter %d", param);
+  const int col = (param == DOPINF_TUNE_CHOL_KB2 || param == DOPINF_TUNE_TRSM_KB2) ? 1 : 0;
+  for (int i = 0; i < kNumKbCand && i < max_values && values_h; ++i) values_h[i] = kKbCand[i][col];
   return kNumKbCand;
 }
 

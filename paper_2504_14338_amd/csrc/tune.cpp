@@ -39,7 +39,8 @@ void set(int param, int64_t key, int value) {
 }  // namespace dopinf
 
 extern "C" int dopinf_tune_set(int param, int64_t key, int value) {
-  if (param != DOPINF_TUNE_CHOL_KB && param != DOPINF_TUNE_TRSM_KB)
+  if (param != DOPINF_TUNE_CHOL_KB && param != DOPINF_TUNE_TRSM_KB && param != DOPINF_TUNE_CHOL_KB2 &&
+      param != DOPINF_TUNE_TRSM_KB2)
     return dopinf::fail(DOPINF_E_ARG, "unknown tuning parameter %d", param);
   if (key < 1) return dopinf::fail(DOPINF_E_ARG, "tuning key must be >= 1");
   if (value != 0 && (value < 64 || value > 4096 || value % 64 != 0))

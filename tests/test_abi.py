@@ -55,7 +55,12 @@ def test_tuning_table_and_sweep_argument_checks():
     import paper_2504_14338_amd as dp
     lib = dp.load()
     cands = dp.autotune_candidates(dp.TUNE_CHOL_KB)
+    inner = dp.autotune_candidates(dp.TUNE_CHOL_KB2)
     assert cands == sorted(cands) and all(c % 64 == 0 for c in cands)
+    # (outer, inner) pairs: an inner width is 0 or a proper divisor of the outer
+    assert len(inner) == len(cands) and len(set(zip(cands, inner))) == len(cands)
+    assert all(w2 == 0 or (w2 % 64 == 0 and w2 < w and w % w2 == 0) for w, w2 in zip(cands, inner))
+    assert dp.autotune_candidates(dp.TUNE_TRSM_KB2) == inner
     key = 123457
     assert dp.tune_get(dp.TUNE_CHOL_KB, key) == 0
     dp.tune_set(dp.TUNE_CHOL_KB, key, 192)
@@ -68,6 +73,13 @@ def test_tuning_table_and_sweep_argument_checks():
     dp.tune_set(dp.TUNE_TRSM_KB, key, 512)
     assert dp.tune_get(dp.TUNE_TRSM_KB, key) == 512 and dp.tune_get(dp.TUNE_CHOL_KB, key) == 0
     dp.tune_set(dp.TUNE_TRSM_KB, key, 0)
+    for param in (dp.TUNE_CHOL_KB2, dp.TUNE_TRSM_KB2):
+        dp.tune_set(param, key, 128)
+        assert dp.tune_get(param, key) == 128
+        dp.tune_set(param, key, 0)
+        assert dp.tune_get(param, key) == 0
+        assert lib.dopinf_tune_set(param, key, 100) == dp.E_ARG
+    assert lib.dopinf_tune_set(5, key, 64) == dp.E_ARG
     assert dp.autotune_candidates(dp.TUNE_TRSM_KB) == cands
     assert lib.dopinf_autotune_candidates(99, None, 0) == dp.E_ARG
     # the null stream is refused before anything is enqueued

@@ -71,18 +71,26 @@ B2 = [1e-4, 1e-4, 1e-1, 1e-1]
 def clean_tuning(gpu_lib):
     dp = gpu_lib
     yield
-    for r in R_LIST + [10]:
-        dp.tune_set(dp.TUNE_CHOL_KB, dp.n_quad(r), 0)
-        dp.tune_set(dp.TUNE_TRSM_KB, dp.n_quad(r), 0)
+    for r in R_LIST + [10, 30]:
+        for param in (dp.TUNE_CHOL_KB, dp.TUNE_TRSM_KB, dp.TUNE_CHOL_KB2, dp.TUNE_TRSM_KB2):
+            dp.tune_set(param, dp.n_quad(r), 0)
 
 
-@pytest.mark.parametrize("kc,kt", [(64, 64), (128, 128), (256, 256), (512, 512), (64, 512), (512, 128)])
+@pytest.mark.parametrize("kc,kt", [((64, 0), (64, 0)), ((128, 0), (128, 0)), ((256, 0), (256, 0)),
+                                   ((512, 0), (512, 0)), ((64, 0), (512, 0)), ((512, 0), (128, 0)),
+                                   ((512, 128), (512, 128)), ((1024, 256), (1024, 128)),
+                                   ((2048, 256), (1024, 256)), ((1024, 128), (2048, 256))])
 def test_every_block_width_gives_parity(gpu_lib, qhat40, clean_tuning, kc, kt):
+    """Every (outer, inner) width pair the autotuner may pick; at s = 210 and
+    820 the two-level pairs have ragged outer and inner blocks."""
     dp = gpu_lib
-    assert kc in dp.autotune_candidates(dp.TUNE_CHOL_KB) and kt in dp.autotune_candidates(dp.TUNE_TRSM_KB)
+    pairs = list(zip(dp.autotune_candidates(dp.TUNE_CHOL_KB), dp.autotune_candidates(dp.TUNE_CHOL_KB2)))
+    assert kc in pairs and kt in pairs
     for r in R_LIST:
-        dp.tune_set(dp.TUNE_CHOL_KB, dp.n_quad(r), kc)
-        dp.tune_set(dp.TUNE_TRSM_KB, dp.n_quad(r), kt)
+        dp.tune_set(dp.TUNE_CHOL_KB, dp.n_quad(r), kc[0])
+        dp.tune_set(dp.TUNE_CHOL_KB2, dp.n_quad(r), kc[1])
+        dp.tune_set(dp.TUNE_TRSM_KB, dp.n_quad(r), kt[0])
+        dp.tune_set(dp.TUNE_TRSM_KB2, dp.n_quad(r), kt[1])
     kb = (kc, kt)
     print(f"infer with block-column widths {kb}, r in {R_LIST}", flush=True)
     O, status, views = dp.infer(qhat40, R_LIST, B1, B2)
@@ -98,14 +106,15 @@ def test_every_block_width_gives_parity(gpu_lib, qhat40, clean_tuning, kc, kt):
 
 def test_autotuner_stores_a_candidate(gpu_lib, qhat40, clean_tuning):
     dp = gpu_lib
-    cands = dp.autotune_candidates()
+    cands = list(zip(dp.autotune_candidates(dp.TUNE_CHOL_KB), dp.autotune_candidates(dp.TUNE_CHOL_KB2)))
     print("autotune", flush=True)
     O, status, views, times = dp.autotune_infer(qhat40, R_LIST, B1, B2)
     assert times.shape == (len(R_LIST), 2, len(cands))
     assert np.all(times > 0) and np.all(np.isfinite(times))
     for g, r in enumerate(R_LIST):
-        kc = dp.tune_get(dp.TUNE_CHOL_KB, dp.n_quad(r))
-        kt = dp.tune_get(dp.TUNE_TRSM_KB, dp.n_quad(r))
+        s = dp.n_quad(r)
+        kc = (dp.tune_get(dp.TUNE_CHOL_KB, s), dp.tune_get(dp.TUNE_CHOL_KB2, s))
+        kt = (dp.tune_get(dp.TUNE_TRSM_KB, s), dp.tune_get(dp.TUNE_TRSM_KB2, s))
         assert kc == cands[int(np.argmin(times[g, 0]))], (r, kc, times[g])
         assert kt == cands[int(np.argmin(times[g, 1]))], (r, kt, times[g])
     # its results are infer's, with the tuned widths: the same values as a
