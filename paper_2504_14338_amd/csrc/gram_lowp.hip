@@ -58,6 +58,7 @@ struct PackArgs {
   int nvars;
   int64_t row0[DOPINF_MAX_VARS + 1];
   int algo;               // 0 FP32, 1 BF16X3, 2 BF16X6
+  int vec;                // Q and ldq allow 16-byte row loads
   float* pf;              // FP32 part
   unsigned short* p0;     // hi
   unsigned short* p1;     // lo (x3) / mid (x6)
@@ -97,24 +98,46 @@ __global__ __launch_bounds__(256) void pack_kernel(PackArgs a) {
     rmu[tid] = a.mean ? a.mean[rowc] : 0.0;
     rinv[tid] = a.scale ? 1.0 / a.scale[vv] : 1.0;
   }
-  const int cc = tid % BT;
-  const int64_t col = c0 + cc;
-  const bool cin = col < a.k;
-  const int64_t colc = cin ? col : 0;
-  float q[KB / 2];
+  if (a.vec && c0 + BT <= a.k) {
+    // whole tile in range, rows 16-byte aligned: thread -> 4 consecutive
+    // columns 4 cq.. of rows rq + 8 i (four 16-byte loads, all in flight)
+    const int cq = tid % (BT / 4), rq = tid / (BT / 4);
+    flt4 q4[KB / 8];
 #pragma unroll
-  for (int i = 0; i < KB / 2; ++i) {
-    const int64_t row = blk * KB + tid / BT + 2 * i;
-    q[i] = a.Q[(row < a.n ? row : a.n - 1) * a.ldq + colc];
-  }
-  __syncthreads();
+    for (int i = 0; i < KB / 8; ++i) {
+      const int64_t row = blk * KB + rq + 8 * i;
+      q4[i] = *reinterpret_cast<const flt4*>(a.Q + (row < a.n ? row : a.n - 1) * a.ldq + c0 + 4 * cq);
+    }
+    __syncthreads();
 #pragma unroll
-  for (int i = 0; i < KB / 2; ++i) {
-    const int rr = tid / BT + 2 * i;
-    const int64_t row = blk * KB + rr;
-    float v = 0.f;
-    if (row < a.n && cin) v = static_cast<float>((static_cast<double>(q[i]) - rmu[rr]) * rinv[rr]);
-    tile[rr][cc] = v;
+    for (int i = 0; i < KB / 8; ++i) {
+      const int rr = rq + 8 * i;
+      const bool rin = blk * KB + rr < a.n;
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        tile[rr][4 * cq + e] =
+            rin ? static_cast<float>((static_cast<double>(q4[i][e]) - rmu[rr]) * rinv[rr]) : 0.f;
+    }
+  } else {
+    const int cc = tid % BT;
+    const int64_t col = c0 + cc;
+    const bool cin = col < a.k;
+    const int64_t colc = cin ? col : 0;
+    float q[KB / 2];
+#pragma unroll
+    for (int i = 0; i < KB / 2; ++i) {
+      const int64_t row = blk * KB + tid / BT + 2 * i;
+      q[i] = a.Q[(row < a.n ? row : a.n - 1) * a.ldq + colc];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < KB / 2; ++i) {
+      const int rr = tid / BT + 2 * i;
+      const int64_t row = blk * KB + rr;
+      float v = 0.f;
+      if (row < a.n && cin) v = static_cast<float>((static_cast<double>(q[i]) - rmu[rr]) * rinv[rr]);
+      tile[rr][cc] = v;
+    }
   }
   __syncthreads();
   if (a.algo == 0) {
@@ -428,6 +451,7 @@ int gram_lowp(hipStream_t st, int algo, const float* Q, int64_t n, int64_t k, in
   pa.mean = mean;
   pa.scale = scale;
   pa.algo = algo;
+  pa.vec = (reinterpret_cast<uintptr_t>(Q) % 16 == 0 && ldq % 4 == 0) ? 1 : 0;
   if (var_rows_h && nvars >= 1) {
     pa.nvars = nvars;
     for (int v = 0; v <= nvars; ++v) pa.row0[v] = var_rows_h[v];
