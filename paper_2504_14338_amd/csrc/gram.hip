@@ -39,6 +39,15 @@ namespace {
 using gramplan::SplitPlan;
 using gramplan::choose_splits;
 
+// Resident workgroups of the FP64 Gram kernels on the current device (two
+// per CU; 0 if the device cannot be queried).
+int gram_slots() {
+  int dev = 0, ncu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  return 2 * ncu;
+}
+
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 constexpr int BT = 128;     // tile edge
@@ -430,7 +439,7 @@ int gram_f64_internal(hipStream_t st, const double* X, int64_t n, int64_t m, int
     nvars = 1;
     var_rows_h = one_var;
   }
-  SplitPlan sp = gramplan::make_plan(n, nvars, var_rows_h, choose_splits(n, ntiles), KC);
+  SplitPlan sp = gramplan::make_plan(n, nvars, var_rows_h, choose_splits(n, ntiles, 8192, gram_slots()), KC);
   if (ws_bytes < part_bytes(sp.nsplit, ntiles) || !ws)
     return fail(DOPINF_E_WORKSPACE, "gram workspace of %zu bytes needed, %zu given", part_bytes(sp.nsplit, ntiles),
                 ws_bytes);
@@ -453,7 +462,7 @@ size_t gram_f64_workspace_internal(int64_t n, int64_t m, int nvars) {
   const int T = tiles_of(m);
   const int ntiles = T * (T + 1) / 2;
   // per-variable rounding can add at most nvars splits
-  return part_bytes(choose_splits(n, ntiles) + nvars + 8, ntiles);
+  return part_bytes(choose_splits(n, ntiles, 8192, gram_slots()) + nvars + 8, ntiles);
 }
 
 }  // namespace dopinf
@@ -518,7 +527,7 @@ int cross_gram_internal(hipStream_t st, const double* X, int64_t ldx, const doub
     nvars = 1;
     var_rows_h = one_var;
   }
-  SplitPlan sp = gramplan::make_plan(n, nvars, var_rows_h, choose_splits(n, ntiles), KC);
+  SplitPlan sp = gramplan::make_plan(n, nvars, var_rows_h, choose_splits(n, ntiles, 8192, gram_slots()), KC);
   if (!ws || ws_bytes < part_bytes(sp.nsplit, ntiles))
     return fail(DOPINF_E_WORKSPACE, "cross gram workspace of %zu bytes needed, %zu given",
                 part_bytes(sp.nsplit, ntiles), ws_bytes);
@@ -539,7 +548,7 @@ int cross_gram_internal(hipStream_t st, const double* X, int64_t ldx, const doub
 
 size_t cross_gram_workspace_internal(int64_t n, int64_t mx, int64_t my) {
   const int ntiles = tiles_of(mx) * tiles_of(my);
-  return part_bytes(choose_splits(n, ntiles) + DOPINF_MAX_VARS + 8, ntiles);
+  return part_bytes(choose_splits(n, ntiles, 8192, gram_slots()) + DOPINF_MAX_VARS + 8, ntiles);
 }
 
 }  // namespace dopinf
