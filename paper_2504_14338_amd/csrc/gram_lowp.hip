@@ -414,7 +414,15 @@ LowpPlan plan(int algo, int64_t n, int64_t k) {
   p.T = tiles_of(k);
   p.kp = int64_t(p.T) * BT;
   p.ntiles = p.T * (p.T + 1) / 2;
-  int target = gramplan::choose_splits(n, p.ntiles);
+  // resident workgroups: two per CU, one for BF16X6 (96 KB of LDS)
+  int slots = 0;
+  {
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
+      slots = (algo == DOPINF_GRAM_BF16X6 ? 1 : 2) * ncu;
+  }
+  int target = gramplan::choose_splits(n, p.ntiles, 8192, slots);
   if (target < 1) target = 1;
   p.bps = (p.nb + target - 1) / target;
   p.nsplit = int((p.nb + p.bps - 1) / p.bps);
