@@ -235,8 +235,9 @@ __global__ __launch_bounds__(256) void potf2_kernel(double* __restrict__ A, int6
 // are taken in block columns of kb rows: inside one, each solved block
 // updates only the rest of the block column; the blocks outside then take a
 // single update of depth kb (fewer passes over X than one update per block).
-// All products run on FP64 MFMA tiles (64 x 64 output, 4 waves of 32 x 32)
-// with both operands staged in LDS.
+// The innermost runs of up to 4 blocks are solved by one fused launch that
+// keeps their rows of X in LDS.  All products run on FP64 MFMA tiles with
+// both operands staged in LDS.
 //
 // Right-hand sides of group g (one factor L_g): cnt[g] matrices of n x w,
 // row-major, stored one after the other from entry e0[g]; the tiles see them
@@ -322,64 +323,155 @@ __device__ __forceinline__ int64_t rhs_offset(const RhsMap& m, int g, int64_t n,
   return (e0 + vcol / m.w) * n * m.w + vcol % m.w;
 }
 
-__device__ __forceinline__ void zero_acc(dbl4 (&acc)[2][2]) {
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
-}
+// Fused leaf of the triangular solves: a run of up to LMAX diagonal blocks
+// [b0, b1) of one factor, for a slab of CW right-hand-side columns per
+// workgroup, held in LDS for the whole run.  Backward (TRANS, L^T Y = X): for
+// J = b1-1 down to b0, Y_J = Linv_J^T X_J, then X_T -= L[J, T]^T Y_J for
+// b0 <= T < J; forward: for J = b0 up, Y_J = Linv_J X_J, then
+// X_T -= L[T, J] Y_J for J < T < b1.  One launch per run instead of a
+// diagonal-block launch and a 64-deep update launch per block, and no round
+// trips of X through HBM between them.  The 64 x 64 blocks (Linv_J or
+// a block of L) are double buffered in LDS: the next block's loads are in
+// flight while the current one is multiplied.  4 waves; wave w computes rows
+// 16 w .. 16 w + 15 of each 64 x CW product (2 FP64 MFMA blocks).
+constexpr int LMAX = 4;       // diagonal blocks per leaf
+constexpr int CW = 32;        // right-hand-side columns per workgroup
+constexpr int CWP = CW + 2;   // LDS pitch of the slab
+constexpr int LBP = NB + 1;   // LDS pitch of a 64 x 64 block
 
-// Y rows of block J = Linv_J (or its transpose) times X rows of block J.
-// Workgroup = (64 virtual columns, group).
 template <bool TRANS>
-__global__ __launch_bounds__(256) void trsm_diag_kernel(const double* __restrict__ Linv, int64_t n,
-                                                        const double* __restrict__ X, double* __restrict__ Y,
-                                                        RhsMap m, int64_t J) {
-  __shared__ double A[NB][TP];
-  __shared__ double B[NB][TP];
+__global__ __launch_bounds__(256, 1) void trsm_leaf_kernel(const double* __restrict__ L, int64_t n,
+                                                           const double* __restrict__ Linv,
+                                                           const double* __restrict__ X, double* __restrict__ Y,
+                                                           RhsMap m, int64_t b0, int64_t b1) {
+  __shared__ double Xs[LMAX * NB][CWP];
+  __shared__ double Ls[2][NB][LBP];
   const int g = blockIdx.y;
-  const int64_t c0 = int64_t(blockIdx.x) * NB;
-  if (rhs_offset(m, g, n, c0) < 0) return;  // tile wholly past the group's columns
-  const int64_t nblk = (n + NB - 1) / NB;
-  const double* Li = Linv + (size_t(g) * nblk + J) * NB * NB;
-  const int64_t jb = J * NB, w = m.w;
+  const int64_t c0 = int64_t(blockIdx.x) * CW;
+  if (rhs_offset(m, g, n, c0) < 0) return;  // slab wholly past the group's columns
+  const int tid = threadIdx.x;
+  const int nbk = int(b1 - b0);
+  const int64_t r0 = b0 * NB, nblk = (n + NB - 1) / NB, w = m.w;
+  const double* Lg = L + size_t(g) * n * n;
+  const double* Lig = Linv + size_t(g) * nblk * NB * NB;
+  // the slab: thread -> column tid % CW, rows tid / CW + 8 q
   {
-    // all loads of a thread issued together (clamped addresses), then the LDS stores
-    const int c = threadIdx.x % NB;  // fixed per thread (256 is a multiple of 64)
+    const int c = tid % CW, rr0 = tid / CW;
     const int64_t off0 = rhs_offset(m, g, n, c0 + c);
     const int64_t off = off0 >= 0 ? off0 : rhs_offset(m, g, n, c0);
-    double av[NB * NB / 256], bv[NB * NB / 256];
+    for (int q0 = 0; q0 < nbk * NB / 8; q0 += 8) {
+      double v[8];
 #pragma unroll
-    for (int k = 0; k < NB * NB / 256; ++k) {
-      const int e = threadIdx.x + 256 * k, a = e / NB, b = e % NB;
-      av[k] = TRANS ? Li[b * NB + a] : Li[a * NB + b];
-      const int ar = threadIdx.x / NB + 4 * k;
-      bv[k] = X[off + (jb + ar < n ? jb + ar : jb) * w];
-    }
+      for (int u = 0; u < 8; ++u) {
+        const int64_t row = r0 + rr0 + 8 * (q0 + u);
+        v[u] = X[off + (row < n ? row : r0) * w];
+      }
 #pragma unroll
-    for (int k = 0; k < NB * NB / 256; ++k) {
-      const int e = threadIdx.x + 256 * k, a = e / NB, b = e % NB;
-      A[a][b] = av[k];
-      const int ar = threadIdx.x / NB + 4 * k;
-      B[ar][c] = (off0 >= 0 && jb + ar < n) ? bv[k] : 0.0;
+      for (int u = 0; u < 8; ++u) {
+        const int rr = rr0 + 8 * (q0 + u);
+        Xs[rr][c] = (off0 >= 0 && r0 + rr < n) ? v[u] : 0.0;
+      }
     }
   }
-  __syncthreads();
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, wm = wv >> 1, wn = wv & 1;
-  dbl4 acc[2][2];
-  zero_acc(acc);
-  tile_mma64(A, B, acc, lane, wm, wn);
+  // work items: t == J: the diagonal product; otherwise the update of block t
+  // from block J.  Item it -> (J, t).
+  const int nitems = nbk * (nbk + 1) / 2;
+  auto item = [&](int it, int& J, int& t) {
+    // items per J in processing order: 1 + (number of remaining blocks)
+    int jj = 0;
+    for (;;) {
+      const int cnt = nbk - jj;  // the jj-th block processed has nbk - jj items
+      if (it < cnt) break;
+      it -= cnt;
+      ++jj;
+    }
+    if (TRANS) {
+      J = nbk - 1 - jj;                  // blocks from the bottom
+      t = (it == 0) ? J : it - 1;        // then T = 0 .. J - 1
+    } else {
+      J = jj;                            // blocks from the top
+      t = (it == 0) ? J : J + it;        // then T = J + 1 .. nbk - 1
+    }
+  };
+  // global source of item (J, t): row-major 64 x 64 with row stride ld, rows
+  // valid below nrow (the rest read as 0)
+  const int lc = tid % NB, lr0 = tid / NB;
+  double pre[NB * NB / 256];
+  auto fetch = [&](int it) {
+    int J, t;
+    item(it, J, t);
+    const int64_t gJ = b0 + J, gt = b0 + t;
+    const double* src;
+    int64_t ld, rbase;
+    if (t == J) {
+      src = Lig + gJ * NB * NB;
+      ld = NB;
+      rbase = -1;  // all rows valid
+    } else if (TRANS) {
+      src = Lg + gJ * NB * n + gt * NB;  // rows k of block J, columns i of block t
+      ld = n;
+      rbase = gJ * NB;
+    } else {
+      src = Lg + gt * NB * n + gJ * NB;  // rows i of block t, columns k of block J
+      ld = n;
+      rbase = gt * NB;
+    }
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int64_t off = rhs_offset(m, g, n, c0 + wn * 32 + j * 16 + (lane & 15));
-    if (off < 0) continue;
+    for (int q = 0; q < NB * NB / 256; ++q) {
+      const int r = lr0 + 4 * q;
+      const bool ok = rbase < 0 || rbase + r < n;
+      pre[q] = src[int64_t(ok ? r : 0) * ld + lc];
+      if (!ok) pre[q] = 0.0;
+    }
+  };
+  auto stage = [&](int buf) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int q = 0; q < NB * NB / 256; ++q) Ls[buf][lr0 + 4 * q][lc] = pre[q];
+  };
+  const int lane = tid & 63, wv = tid >> 6;
+  fetch(0);
+  stage(0);
+  for (int it = 0; it < nitems; ++it) {
+    const int buf = it & 1;
+    __syncthreads();  // Ls[buf] and the slab are ready; Ls[buf ^ 1] is free
+    if (it + 1 < nitems) fetch(it + 1);
+    int J, t;
+    item(it, J, t);
+    // acc = A(J, t) . Xs[J], A[i][k] = Ls[k][i] (TRANS) or Ls[i][k]
+    dbl4 acc[2] = {dbl4{0.0, 0.0, 0.0, 0.0}, dbl4{0.0, 0.0, 0.0, 0.0}};
+    const int i = 16 * wv + (lane & 15);
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int64_t row = jb + wm * 32 + i * 16 + (lane >> 4) + 4 * e;  // MFMA f64 output layout
-        if (row < n) Y[off + row * w] = acc[i][j][e];
+    for (int kk = 0; kk < NB / 4; ++kk) {
+      const int k = 4 * kk + (lane >> 4);
+      const double a = TRANS ? Ls[buf][k][i] : Ls[buf][i][k];
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Xs[J * NB + k][16 * j + (lane & 15)], acc[j], 0, 0, 0);
+    }
+    if (t == J) {
+      __syncthreads();  // every wave has read X_J
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int c = 16 * j + (lane & 15);
+        const int64_t off = rhs_offset(m, g, n, c0 + c);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int rr = 16 * wv + (lane >> 4) + 4 * e;  // MFMA f64 output layout
+          const int64_t row = (b0 + J) * NB + rr;
+          Xs[J * NB + rr][c] = acc[j][e];
+          if (off >= 0 && row < n) Y[off + row * w] = acc[j][e];
+        }
       }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int rr = 16 * wv + (lane >> 4) + 4 * e;
+          Xs[t * NB + rr][16 * j + (lane & 15)] -= acc[j][e];
+        }
+    }
+    if (it + 1 < nitems) stage(buf ^ 1);
   }
 }
 
@@ -676,12 +768,12 @@ int trsm_run(hipStream_t st, bool trans, const double* L, int64_t n, const doubl
              RhsMap m, int64_t max_cols, int ng, int64_t kb, int64_t kb2) {
   const int64_t nblk = (n + NB - 1) / NB;
   const Widths W = widths(kb, kb2);
-  const unsigned nct = unsigned((max_cols + NB - 1) / NB);
-  auto diag = [&](int64_t J) -> int {
+  const unsigned nslab = unsigned((max_cols + CW - 1) / CW);
+  auto leaf = [&](int64_t cb, int64_t ce) -> int {
     if (!trans)
-      trsm_diag_kernel<false><<<dim3(nct, unsigned(ng)), 256, 0, st>>>(Linv, n, X, Yout, m, J);
+      trsm_leaf_kernel<false><<<dim3(nslab, unsigned(ng)), 256, 0, st>>>(L, n, Linv, X, Yout, m, cb, ce);
     else
-      trsm_diag_kernel<true><<<dim3(nct, unsigned(ng)), 256, 0, st>>>(Linv, n, X, Yout, m, J);
+      trsm_leaf_kernel<true><<<dim3(nslab, unsigned(ng)), 256, 0, st>>>(L, n, Linv, X, Yout, m, cb, ce);
     DOPINF_LAUNCHED();
     return DOPINF_OK;
   };
@@ -699,19 +791,23 @@ int trsm_run(hipStream_t st, bool trans, const double* L, int64_t n, const doubl
   };
   // blocks [b0, b1) at level lev, recursive over the widths as in
   // cholesky_run: a solved block of the level's width updates the rest of
-  // [b0, b1) with depth = its width; at the last level single blocks
+  // [b0, b1) with depth = its width; at the last level runs of LMAX blocks
   auto level = [&](auto&& self, int64_t b0, int64_t b1, int lev) -> int {
     int rc = DOPINF_OK;
     if (lev == W.n) {
+      // runs of up to LMAX blocks by the fused leaf kernel, the rest of
+      // [b0, b1) updated from each run
       if (!trans) {
-        for (int64_t J = b0; J < b1 && !rc; ++J) {
-          rc = diag(J);
-          if (!rc) rc = update(J + 1, b1, J * NB, (J + 1) * NB);
+        for (int64_t cb = b0; cb < b1 && !rc; cb += LMAX) {
+          const int64_t ce = std::min<int64_t>(cb + LMAX, b1);
+          rc = leaf(cb, ce);
+          if (!rc) rc = update(ce, b1, cb * NB, ce * NB);
         }
       } else {
-        for (int64_t J = b1 - 1; J >= b0 && !rc; --J) {
-          rc = diag(J);
-          if (!rc) rc = update(b0, J, J * NB, (J + 1) * NB);
+        for (int64_t ce = b1; ce > b0 && !rc; ce -= LMAX) {
+          const int64_t cb = std::max<int64_t>(b0, ce - LMAX);
+          rc = leaf(cb, ce);
+          if (!rc) rc = update(b0, cb, cb * NB, ce * NB);
         }
       }
       return rc;
