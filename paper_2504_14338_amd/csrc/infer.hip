@@ -598,6 +598,120 @@ __global__ __launch_bounds__(256, 2) void trsm_update_t128_kernel(const double* 
   }
 }
 
+// The same update for the backward solve (X[i][c] -= sum_k L[k][i] Y[k][c])
+// with both operands brought in by LDS-DMA (buffer loads that write LDS
+// directly, no register round trip), as in the FP64 Gram: per 16-row stage,
+// row k of L from column tb and row k of Y across the tile's columns, each a
+// 128-double LDS row, double-buffered, with the next stage's loads in flight
+// over the current stage's MFMAs.  A lane brings two adjacent right-hand-side
+// columns (16 bytes; they lie in one matrix since the width is even), at a
+// fixed offset from the tile's first column, so that the same offsets serve
+// every row.  Rows past k1, columns past the group's and L's columns past n
+// read as zero (buffer range checks).  Needs even n and width and 16-byte
+// aligned L and Y.
+constexpr int QK = 16;               // K rows per stage
+constexpr int QP = 144;              // LDS row pitch (doubles)
+constexpr int QSLOT = 2 * QK * QP;   // A rows, then B rows
+
+#define DOPINF_LDS(p) ((__attribute__((address_space(3))) void*)(p))
+
+// Buffer descriptor over [p, p + nbytes): reads past nbytes return zero.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t span_rsrc(const void* p, int64_t nbytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, int(nbytes), 0x00020000);
+}
+
+// Wait until none of this wave's vector-memory operations is in flight.
+__device__ __forceinline__ void wait_vmem_all() { __builtin_amdgcn_s_waitcnt(0 | (7 << 4) | (15 << 8)); }
+
+// Workgroup barrier that leaves the LDS-DMA loads alone (the explicit wait
+// above decides what must have landed).
+__device__ __forceinline__ void barrier_only() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+__global__ __launch_bounds__(256, 2) void trsm_update_dma_kernel(const double* __restrict__ L, int64_t n,
+                                                                double* __restrict__ X, const double* __restrict__ Y,
+                                                                RhsMap m, int64_t r_lo, int64_t r_hi, int64_t k0,
+                                                                int64_t k1) {
+  __shared__ double lds[2 * QSLOT];
+  const int g = blockIdx.z;
+  const int64_t c0 = int64_t(blockIdx.x) * UT;
+  const int64_t base = rhs_offset(m, g, n, c0);
+  if (base < 0) return;  // tile wholly past the group's columns
+  const int64_t tb = r_lo + int64_t(blockIdx.y) * UT;
+  const double* Lg = L + size_t(g) * n * n;
+  const int64_t w = m.w;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
+  const int wm = wv >> 1, wn = wv & 1;
+  const int64_t lo = rhs_offset(m, g, n, c0 + 2 * lane);
+  const uint32_t offb = lo >= 0 ? uint32_t((lo - base) * 8) : 0x80000000u;  // past the range: zero
+  const uint32_t offa = uint32_t(lane) * 16;
+  const int64_t nst = (k1 - k0 + QK - 1) / QK;
+  auto issue = [&](int64_t st) {
+    double* sl = lds + (st & 1) * QSLOT;
+    const int64_t kb = k0 + st * QK;
+#pragma unroll
+    for (int q = 0; q < QK / 4; ++q) {
+      const int r = wv * (QK / 4) + q;
+      const bool in = kb + r < k1;
+      const int64_t k = in ? kb + r : k0;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(span_rsrc(Lg + k * n + tb, in ? (n - tb) * 8 : 0),
+                                               DOPINF_LDS(sl + r * QP), 16, offa, 0, 0, 0);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(span_rsrc(Y + base + k * w, in ? 0x7ffffff0 : 0),
+                                               DOPINF_LDS(sl + (QK + r) * QP), 16, offb, 0, 0, 0);
+    }
+  };
+  dbl4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+  if (nst > 0) issue(0);
+  for (int64_t st = 0; st < nst; ++st) {
+    wait_vmem_all();
+    barrier_only();
+    if (st + 1 < nst) issue(st + 1);
+    const double* As = lds + (st & 1) * QSLOT;
+    const double* Bs = As + QK * QP;
+#pragma unroll
+    for (int kk = 0; kk < QK / 4; ++kk) {
+      const int krow = kk * 4 + (lane >> 4), cm = lane & 15;
+      double af[4], bf[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) af[i] = As[krow * QP + wm * 64 + i * 16 + cm];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bf[j] = Bs[krow * QP + wn * 64 + j * 16 + cm];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int64_t off0 = rhs_offset(m, g, n, c0 + wn * 64 + j * 16 + (lane & 15));
+    const int64_t off = off0 >= 0 ? off0 : base;
+    double old[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t row = tb + wm * 64 + i * 16 + (lane >> 4) + 4 * e;  // MFMA f64 output layout
+        old[i][e] = X[off + (row < r_hi ? row : r_lo) * w];
+      }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t row = tb + wm * 64 + i * 16 + (lane >> 4) + 4 * e;
+        if (off0 >= 0 && row < r_hi) X[off + row * w] = old[i][e] - acc[i][j][e];
+      }
+  }
+}
+
 // The Cholesky's update from the factored columns [a0, a0 + K) on 128 x 128
 // tiles: A[i][l] -= sum_{a0 <= p < a0+K} L[i][p] L[l][p] for c_lo <= l < c_hi,
 // l <= i < n (with c_hi = n the trailing update of the lower triangle), over
@@ -769,6 +883,9 @@ int trsm_run(hipStream_t st, bool trans, const double* L, int64_t n, const doubl
   const int64_t nblk = (n + NB - 1) / NB;
   const Widths W = widths(kb, kb2);
   const unsigned nslab = unsigned((max_cols + CW - 1) / CW);
+  // the backward updates load by LDS-DMA where rows are 16-byte aligned
+  const bool dma = n % 2 == 0 && m.w % 2 == 0 && (reinterpret_cast<uintptr_t>(L) & 15) == 0 &&
+                   (reinterpret_cast<uintptr_t>(Yout) & 15) == 0 && n < (int64_t(1) << 27);
   auto leaf = [&](int64_t cb, int64_t ce) -> int {
     if (!trans)
       trsm_leaf_kernel<false><<<dim3(nslab, unsigned(ng)), 256, 0, st>>>(L, n, Linv, X, Yout, m, cb, ce);
@@ -784,6 +901,8 @@ int trsm_run(hipStream_t st, bool trans, const double* L, int64_t n, const doubl
     const dim3 g128(unsigned((max_cols + UT - 1) / UT), unsigned((r_hi - r_lo + UT - 1) / UT), unsigned(ng));
     if (!trans)
       trsm_update_t128_kernel<false><<<g128, 256, 0, st>>>(L, n, X, Yout, m, r_lo, r_hi, k0, std::min<int64_t>(k1, n));
+    else if (dma)
+      trsm_update_dma_kernel<<<g128, 256, 0, st>>>(L, n, X, Yout, m, r_lo, r_hi, k0, std::min<int64_t>(k1, n));
     else
       trsm_update_t128_kernel<true><<<g128, 256, 0, st>>>(L, n, X, Yout, m, r_lo, r_hi, k0, std::min<int64_t>(k1, n));
     DOPINF_LAUNCHED();
