@@ -511,6 +511,36 @@ __device__ __forceinline__ void mma_slab128(const double (*As)[UP], const double
   }
 }
 
+// X rows [tb, tb + 128) n [r_lo, r_hi), virtual columns [c0, c0 + 128) of
+// group g -= the tile's accumulators (4 waves of 64 x 64, MFMA f64 output
+// layout); per column group the 16 old values are loaded (clamped addresses)
+// before any is written back.
+__device__ __forceinline__ void rhs_tile_subtract(double* __restrict__ X, const RhsMap& m, int g, int64_t n,
+                                                  int64_t c0, int64_t tb, int64_t r_lo, int64_t r_hi,
+                                                  const dbl4 (&acc)[4][4], int lane, int wm, int wn) {
+  const int64_t w = m.w;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int64_t off0 = rhs_offset(m, g, n, c0 + wn * 64 + j * 16 + (lane & 15));
+    const int64_t off = off0 >= 0 ? off0 : rhs_offset(m, g, n, c0);
+    double old[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t row = tb + wm * 64 + i * 16 + (lane >> 4) + 4 * e;  // MFMA f64 output layout
+        old[i][e] = X[off + (row < r_hi ? row : r_lo) * w];
+      }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t row = tb + wm * 64 + i * 16 + (lane >> 4) + 4 * e;
+        if (off0 >= 0 && row < r_hi) X[off + row * w] = old[i][e] - acc[i][j][e];
+      }
+  }
+}
+
 template <bool TRANS>
 __global__ __launch_bounds__(256, 2) void trsm_update_t128_kernel(const double* __restrict__ L, int64_t n,
                                                                double* __restrict__ X, const double* __restrict__ Y,
@@ -574,41 +604,22 @@ __global__ __launch_bounds__(256, 2) void trsm_update_t128_kernel(const double* 
     __syncthreads();
     buf ^= 1;
   }
-  // epilogue per column group: the 16 old values are loaded (clamped
-  // addresses) before any is written back
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int64_t off0 = rhs_offset(m, g, n, c0 + wn * 64 + j * 16 + (lane & 15));
-    const int64_t off = off0 >= 0 ? off0 : rhs_offset(m, g, n, c0);
-    double old[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int64_t row = tb + wm * 64 + i * 16 + (lane >> 4) + 4 * e;  // MFMA f64 output layout
-        old[i][e] = X[off + (row < r_hi ? row : r_lo) * w];
-      }
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int64_t row = tb + wm * 64 + i * 16 + (lane >> 4) + 4 * e;
-        if (off0 >= 0 && row < r_hi) X[off + row * w] = old[i][e] - acc[i][j][e];
-      }
-  }
+  rhs_tile_subtract(X, m, g, n, c0, tb, r_lo, r_hi, acc, lane, wm, wn);
 }
 
-// The same update for the backward solve (X[i][c] -= sum_k L[k][i] Y[k][c])
-// with both operands brought in by LDS-DMA (buffer loads that write LDS
-// directly, no register round trip), as in the FP64 Gram: per 16-row stage,
-// row k of L from column tb and row k of Y across the tile's columns, each a
-// 128-double LDS row, double-buffered, with the next stage's loads in flight
-// over the current stage's MFMAs.  A lane brings two adjacent right-hand-side
+// The same updates with both operands brought in by LDS-DMA (buffer loads
+// that write LDS directly, no register round trip), as in the FP64 Gram: per
+// 16-row stage of K, double-buffered, with the next stage's loads in flight
+// over the current stage's MFMAs.  B: row k of Y across the tile's columns
+// as one 128-double LDS row; a lane brings two adjacent right-hand-side
 // columns (16 bytes; they lie in one matrix since the width is even), at a
 // fixed offset from the tile's first column, so that the same offsets serve
-// every row.  Rows past k1, columns past the group's and L's columns past n
-// read as zero (buffer range checks).  Needs even n and width and 16-byte
-// aligned L and Y.
+// every row.  A, backward (TRANS, X[i][c] -= sum_k L[k][i] Y[k][c]): row k
+// of L from column tb, K-major like B; forward (X[i][c] -= sum_k L[i][k]
+// Y[k][c]): the tile's 128 rows of L, 16 values of k each, M-major
+// (issue_mmajor).  Rows past k1, columns past the group's, and L past row or
+// column n read as zero (buffer range checks).  Needs even n and width and
+// 16-byte aligned L and Y.
 constexpr int QK = 16;               // K rows per stage
 constexpr int QP = 144;              // LDS row pitch (doubles)
 constexpr int QSLOT = 2 * QK * QP;   // A rows, then B rows
@@ -631,6 +642,34 @@ __device__ __forceinline__ void barrier_only() {
   asm volatile("" ::: "memory");
 }
 
+// M-major LDS tile: 128 rows of 16 doubles (8 chunks of 16 bytes); chunk c
+// of row m sits at slot c ^ mswz(m), which spreads the 16 rows that one MFMA
+// fragment read touches over distinct banks.
+__device__ __forceinline__ int mswz(int m) { return (m ^ (m >> 3)) & 7; }
+
+__device__ __forceinline__ double mm_at(const double* tile, int m, int k) {
+  return tile[m * 16 + (((k >> 1) ^ mswz(m)) << 1) + (k & 1)];
+}
+
+// Issue the loads of rows [row0, row0 + 128) x columns [kb, kb + 16) of the
+// row-major P (leading dimension ld, at most 2^31 bytes in all) into an
+// M-major tile: wave wv brings rows 32 wv .. 32 wv + 31, 8 rows per
+// instruction, and lane l the chunk that belongs in slot l % 8 of row l / 8.
+// Rows at or past nrow and columns at or past k1 read as zero (k1 even).
+__device__ __forceinline__ void issue_mmajor(double* tile, const double* P, int64_t ld, int64_t row0, int64_t nrow,
+                                             int64_t kb, int64_t k1, int wv, int lane) {
+  const __amdgpu_buffer_rsrc_t rs = span_rsrc(P, 0x7ffffff0);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int mloc = wv * 32 + q * 8 + (lane >> 3);
+    const int c = (lane & 7) ^ mswz(mloc);
+    const int64_t row = row0 + mloc, k = kb + 2 * c;
+    const uint32_t off = (row < nrow && k < k1) ? uint32_t((row * ld + k) * 8) : 0x80000000u;
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, DOPINF_LDS(tile + (wv * 32 + q * 8) * 16), 16, off, 0, 0, 0);
+  }
+}
+
+template <bool TRANS>
 __global__ __launch_bounds__(256, 2) void trsm_update_dma_kernel(const double* __restrict__ L, int64_t n,
                                                                 double* __restrict__ X, const double* __restrict__ Y,
                                                                 RhsMap m, int64_t r_lo, int64_t r_hi, int64_t k0,
@@ -653,13 +692,15 @@ __global__ __launch_bounds__(256, 2) void trsm_update_dma_kernel(const double* _
   auto issue = [&](int64_t st) {
     double* sl = lds + (st & 1) * QSLOT;
     const int64_t kb = k0 + st * QK;
+    if (!TRANS) issue_mmajor(sl, Lg, n, tb, r_hi, kb, k1, wv, lane);
 #pragma unroll
     for (int q = 0; q < QK / 4; ++q) {
       const int r = wv * (QK / 4) + q;
       const bool in = kb + r < k1;
       const int64_t k = in ? kb + r : k0;
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(span_rsrc(Lg + k * n + tb, in ? (n - tb) * 8 : 0),
-                                               DOPINF_LDS(sl + r * QP), 16, offa, 0, 0, 0);
+      if (TRANS)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(span_rsrc(Lg + k * n + tb, in ? (n - tb) * 8 : 0),
+                                                 DOPINF_LDS(sl + r * QP), 16, offa, 0, 0, 0);
       __builtin_amdgcn_raw_ptr_buffer_load_lds(span_rsrc(Y + base + k * w, in ? 0x7ffffff0 : 0),
                                                DOPINF_LDS(sl + (QK + r) * QP), 16, offb, 0, 0, 0);
     }
@@ -681,7 +722,8 @@ __global__ __launch_bounds__(256, 2) void trsm_update_dma_kernel(const double* _
       const int krow = kk * 4 + (lane >> 4), cm = lane & 15;
       double af[4], bf[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) af[i] = As[krow * QP + wm * 64 + i * 16 + cm];
+      for (int i = 0; i < 4; ++i)
+        af[i] = TRANS ? As[krow * QP + wm * 64 + i * 16 + cm] : mm_at(As, wm * 64 + i * 16 + cm, krow);
 #pragma unroll
       for (int j = 0; j < 4; ++j) bf[j] = Bs[krow * QP + wn * 64 + j * 16 + cm];
 #pragma unroll
@@ -690,26 +732,7 @@ __global__ __launch_bounds__(256, 2) void trsm_update_dma_kernel(const double* _
         for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
     }
   }
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int64_t off0 = rhs_offset(m, g, n, c0 + wn * 64 + j * 16 + (lane & 15));
-    const int64_t off = off0 >= 0 ? off0 : base;
-    double old[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int64_t row = tb + wm * 64 + i * 16 + (lane >> 4) + 4 * e;  // MFMA f64 output layout
-        old[i][e] = X[off + (row < r_hi ? row : r_lo) * w];
-      }
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int64_t row = tb + wm * 64 + i * 16 + (lane >> 4) + 4 * e;
-        if (off0 >= 0 && row < r_hi) X[off + row * w] = old[i][e] - acc[i][j][e];
-      }
-  }
+  rhs_tile_subtract(X, m, g, n, c0, tb, r_lo, r_hi, acc, lane, wm, wn);
 }
 
 // The Cholesky's update from the factored columns [a0, a0 + K) on 128 x 128
@@ -719,15 +742,9 @@ __global__ __launch_bounds__(256, 2) void trsm_update_dma_kernel(const double* _
 // are rows of L (contiguous in p); they are staged transposed (K-major) into
 // the double-buffered LDS slabs of mma_slab128.  A diagonal tile loads its
 // rows once.
-__global__ __launch_bounds__(256, 2) void syrk_update128_kernel(double* __restrict__ A, int64_t n, int64_t a0, int64_t K,
-                                                             int64_t c_lo, int64_t c_hi) {
-  __shared__ double As[2][UK][UP];
-  __shared__ double Bs[2][UK][UP];
-  const int u = blockIdx.y;
-  double* Au = A + size_t(u) * n * n;
-  const int TR = int((n - c_lo + UT - 1) / UT), TC = int((c_hi - c_lo + UT - 1) / UT);
-  const int t = blockIdx.x;
-  int I, J;
+// Tile t of the trapezoid (TR tile rows from c_lo, TC tile columns): a
+// triangle of tiles when the columns reach the end, else column by column.
+__device__ __forceinline__ void syrk_tile_coords(int t, int TR, int TC, int& I, int& J) {
   if (TC >= TR) {
     I = int((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
     while ((I + 1) * (I + 2) / 2 <= t) ++I;
@@ -742,6 +759,45 @@ __global__ __launch_bounds__(256, 2) void syrk_update128_kernel(double* __restri
     }
     I = J + rem;
   }
+}
+
+// A[row][col] -= the tile's accumulators for rows [r0, r0 + 128) below n,
+// columns [cc0, cc0 + 128) below c_hi, on or below the diagonal; per column
+// group the 16 old values are loaded (clamped addresses) before any is
+// written back.
+__device__ __forceinline__ void syrk_tile_subtract(double* __restrict__ Au, int64_t n, int64_t r0, int64_t cc0,
+                                                   int64_t c_hi, const dbl4 (&acc)[4][4], int lane, int wm, int wn) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int64_t col = cc0 + wn * 64 + j * 16 + (lane & 15);
+    const int64_t colc = col < n ? col : cc0;
+    double old[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t row = r0 + wm * 64 + i * 16 + (lane >> 4) + 4 * e;  // MFMA f64 output layout
+        old[i][e] = Au[(row < n ? row : r0) * n + colc];
+      }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t row = r0 + wm * 64 + i * 16 + (lane >> 4) + 4 * e;
+        if (row < n && col <= row && col < c_hi) Au[row * n + col] = old[i][e] - acc[i][j][e];
+      }
+  }
+}
+
+__global__ __launch_bounds__(256, 2) void syrk_update128_kernel(double* __restrict__ A, int64_t n, int64_t a0, int64_t K,
+                                                             int64_t c_lo, int64_t c_hi) {
+  __shared__ double As[2][UK][UP];
+  __shared__ double Bs[2][UK][UP];
+  const int u = blockIdx.y;
+  double* Au = A + size_t(u) * n * n;
+  const int TR = int((n - c_lo + UT - 1) / UT), TC = int((c_hi - c_lo + UT - 1) / UT);
+  int I, J;
+  syrk_tile_coords(int(blockIdx.x), TR, TC, I, J);
   const bool diag = (I == J);
   const int64_t r0 = c_lo + int64_t(I) * UT, cc0 = c_lo + int64_t(J) * UT;
   const int64_t k1 = a0 + K;
@@ -783,28 +839,62 @@ __global__ __launch_bounds__(256, 2) void syrk_update128_kernel(double* __restri
     __syncthreads();
     buf ^= 1;
   }
-  // epilogue per column group: the 16 old values are loaded (clamped
-  // addresses) before any is written back
+  syrk_tile_subtract(Au, n, r0, cc0, c_hi, acc, lane, wm, wn);
+}
+
+// The Cholesky's update with both operands (rows of L, 16 values of p per
+// stage) brought in by LDS-DMA into M-major tiles (issue_mmajor), double
+// buffered, the next stage's loads in flight over the current MFMAs; a
+// diagonal tile loads its rows once.  Needs even n, n^2 8 < 2^31 bytes and a
+// 16-byte aligned A.
+__global__ __launch_bounds__(256, 2) void syrk_update_dma_kernel(double* __restrict__ A, int64_t n, int64_t a0,
+                                                                int64_t K, int64_t c_lo, int64_t c_hi) {
+  __shared__ double lds[2 * 2 * UT * 16];
+  const int u = blockIdx.y;
+  double* Au = A + size_t(u) * n * n;
+  const int TR = int((n - c_lo + UT - 1) / UT), TC = int((c_hi - c_lo + UT - 1) / UT);
+  int I, J;
+  syrk_tile_coords(int(blockIdx.x), TR, TC, I, J);
+  const bool diag = (I == J);
+  const int64_t r0 = c_lo + int64_t(I) * UT, cc0 = c_lo + int64_t(J) * UT;
+  const int64_t k1 = a0 + K;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
+  const int wm = wv >> 1, wn = wv & 1;
+  const int64_t nst = (K + QK - 1) / QK;
+  auto issue = [&](int64_t st) {
+    double* sl = lds + (st & 1) * (2 * UT * 16);
+    const int64_t kb = a0 + st * QK;
+    issue_mmajor(sl, Au, n, r0, n, kb, k1, wv, lane);
+    if (!diag) issue_mmajor(sl + UT * 16, Au, n, cc0, n, kb, k1, wv, lane);
+  };
+  dbl4 acc[4][4];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int64_t col = cc0 + wn * 64 + j * 16 + (lane & 15);
-    const int64_t colc = col < n ? col : cc0;
-    double old[4][4];
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+  if (nst > 0) issue(0);
+  for (int64_t st = 0; st < nst; ++st) {
+    wait_vmem_all();
+    barrier_only();
+    if (st + 1 < nst) issue(st + 1);
+    const double* As = lds + (st & 1) * (2 * UT * 16);
+    const double* Bs = diag ? As : As + UT * 16;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int64_t row = r0 + wm * 64 + i * 16 + (lane >> 4) + 4 * e;  // MFMA f64 output layout
-        old[i][e] = Au[(row < n ? row : r0) * n + colc];
-      }
+    for (int kk = 0; kk < QK / 4; ++kk) {
+      const int krow = kk * 4 + (lane >> 4), cm = lane & 15;
+      double af[4], bf[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 4; ++i) af[i] = mm_at(As, wm * 64 + i * 16 + cm, krow);
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int64_t row = r0 + wm * 64 + i * 16 + (lane >> 4) + 4 * e;
-        if (row < n && col <= row && col < c_hi) Au[row * n + col] = old[i][e] - acc[i][j][e];
-      }
+      for (int j = 0; j < 4; ++j) bf[j] = mm_at(Bs, wn * 64 + j * 16 + cm, krow);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+    }
   }
+  syrk_tile_subtract(Au, n, r0, cc0, c_hi, acc, lane, wm, wn);
 }
 
 inline int64_t syrk_tiles128(int64_t n, int64_t c_lo, int64_t c_hi) {
@@ -841,9 +931,15 @@ inline Widths widths(int64_t kb, int64_t kb2) {
 // block column of kb updates of depth kb2.
 int cholesky_run(hipStream_t st, double* Lq, int64_t s, double* Linv, int* ufail, int nu, int64_t kb, int64_t kb2) {
   const Widths W = widths(kb, kb2);
+  // the updates load by LDS-DMA where rows are 16-byte aligned and one
+  // buffer descriptor spans a factor
+  const bool dma = s % 2 == 0 && (reinterpret_cast<uintptr_t>(Lq) & 15) == 0 && s * s * 8 < 0x7ffffff0;
   auto syrk = [&](int64_t k0, int64_t kd, int64_t c0, int64_t c1) -> int {
     const int64_t nt = syrk_tiles128(s, c0, c1);
-    syrk_update128_kernel<<<dim3(unsigned(nt), unsigned(nu)), 256, 0, st>>>(Lq, s, k0, kd, c0, c1);
+    if (dma)
+      syrk_update_dma_kernel<<<dim3(unsigned(nt), unsigned(nu)), 256, 0, st>>>(Lq, s, k0, kd, c0, c1);
+    else
+      syrk_update128_kernel<<<dim3(unsigned(nt), unsigned(nu)), 256, 0, st>>>(Lq, s, k0, kd, c0, c1);
     DOPINF_LAUNCHED();
     return DOPINF_OK;
   };
@@ -883,9 +979,11 @@ int trsm_run(hipStream_t st, bool trans, const double* L, int64_t n, const doubl
   const int64_t nblk = (n + NB - 1) / NB;
   const Widths W = widths(kb, kb2);
   const unsigned nslab = unsigned((max_cols + CW - 1) / CW);
-  // the backward updates load by LDS-DMA where rows are 16-byte aligned
-  const bool dma = n % 2 == 0 && m.w % 2 == 0 && (reinterpret_cast<uintptr_t>(L) & 15) == 0 &&
-                   (reinterpret_cast<uintptr_t>(Yout) & 15) == 0 && n < (int64_t(1) << 27);
+  // the updates load by LDS-DMA where rows are 16-byte aligned (and, for
+  // the forward form, one buffer descriptor spans a factor)
+  const bool dma_b = n % 2 == 0 && m.w % 2 == 0 && (reinterpret_cast<uintptr_t>(L) & 15) == 0 &&
+                     (reinterpret_cast<uintptr_t>(Yout) & 15) == 0 && n < (int64_t(1) << 27);
+  const bool dma = trans ? dma_b : dma_b && n * n * 8 < 0x7ffffff0;
   auto leaf = [&](int64_t cb, int64_t ce) -> int {
     if (!trans)
       trsm_leaf_kernel<false><<<dim3(nslab, unsigned(ng)), 256, 0, st>>>(L, n, Linv, X, Yout, m, cb, ce);
@@ -899,12 +997,15 @@ int trsm_run(hipStream_t st, bool trans, const double* L, int64_t n, const doubl
     if (t1 <= t0) return DOPINF_OK;
     const int64_t r_lo = t0 * NB, r_hi = std::min<int64_t>(t1 * NB, n);
     const dim3 g128(unsigned((max_cols + UT - 1) / UT), unsigned((r_hi - r_lo + UT - 1) / UT), unsigned(ng));
-    if (!trans)
-      trsm_update_t128_kernel<false><<<g128, 256, 0, st>>>(L, n, X, Yout, m, r_lo, r_hi, k0, std::min<int64_t>(k1, n));
+    const int64_t kh = std::min<int64_t>(k1, n);
+    if (dma && trans)
+      trsm_update_dma_kernel<true><<<g128, 256, 0, st>>>(L, n, X, Yout, m, r_lo, r_hi, k0, kh);
     else if (dma)
-      trsm_update_dma_kernel<<<g128, 256, 0, st>>>(L, n, X, Yout, m, r_lo, r_hi, k0, std::min<int64_t>(k1, n));
+      trsm_update_dma_kernel<false><<<g128, 256, 0, st>>>(L, n, X, Yout, m, r_lo, r_hi, k0, kh);
+    else if (trans)
+      trsm_update_t128_kernel<true><<<g128, 256, 0, st>>>(L, n, X, Yout, m, r_lo, r_hi, k0, kh);
     else
-      trsm_update_t128_kernel<true><<<g128, 256, 0, st>>>(L, n, X, Yout, m, r_lo, r_hi, k0, std::min<int64_t>(k1, n));
+      trsm_update_t128_kernel<false><<<g128, 256, 0, st>>>(L, n, X, Yout, m, r_lo, r_hi, k0, kh);
     DOPINF_LAUNCHED();
     return DOPINF_OK;
   };
