@@ -330,22 +330,25 @@ __device__ __forceinline__ int64_t rhs_offset(const RhsMap& m, int g, int64_t n,
 // b0 <= T < J; forward: for J = b0 up, Y_J = Linv_J X_J, then
 // X_T -= L[T, J] Y_J for J < T < b1.  One launch per run instead of a
 // diagonal-block launch and a 64-deep update launch per block, and no round
-// trips of X through HBM between them.  The 64 x 64 blocks (Linv_J or
-// a block of L) are double buffered in LDS: the next block's loads are in
-// flight while the current one is multiplied.  4 waves; wave w computes rows
-// 16 w .. 16 w + 15 of each 64 x CW product (2 FP64 MFMA blocks).
+// trips of X through HBM between them.  4 waves; wave w computes rows
+// 16 w .. 16 w + 15 of each 64 x CW product (2 FP64 MFMA blocks), so it
+// alone uses those rows of the 64 x 64 coefficient block (Linv_J or a block
+// of L): it reads its A fragments straight from memory into registers, the
+// next item's while the current one is multiplied, and LDS holds only the
+// slab (70 KB: two workgroups per CU, and room beside other kernels).
+// Barriers: before each diagonal product (its rows were updated by every
+// wave), after it (before Y_J overwrites X_J) and before the first update
+// that reads Y_J; the updates from one J write disjoint rows.
 constexpr int LMAX = 4;       // diagonal blocks per leaf
 constexpr int CW = 32;        // right-hand-side columns per workgroup
 constexpr int CWP = CW + 2;   // LDS pitch of the slab
-constexpr int LBP = NB + 1;   // LDS pitch of a 64 x 64 block
 
 template <bool TRANS>
-__global__ __launch_bounds__(256, 1) void trsm_leaf_kernel(const double* __restrict__ L, int64_t n,
+__global__ __launch_bounds__(256, 2) void trsm_leaf_kernel(const double* __restrict__ L, int64_t n,
                                                            const double* __restrict__ Linv,
                                                            const double* __restrict__ X, double* __restrict__ Y,
                                                            RhsMap m, int64_t b0, int64_t b1) {
   __shared__ double Xs[LMAX * NB][CWP];
-  __shared__ double Ls[2][NB][LBP];
   const int g = blockIdx.y;
   const int64_t c0 = int64_t(blockIdx.x) * CW;
   if (rhs_offset(m, g, n, c0) < 0) return;  // slab wholly past the group's columns
@@ -373,11 +376,10 @@ __global__ __launch_bounds__(256, 1) void trsm_leaf_kernel(const double* __restr
       }
     }
   }
-  // work items: t == J: the diagonal product; otherwise the update of block t
-  // from block J.  Item it -> (J, t).
+  // work items in order: per J a diagonal product (t == J), then the
+  // updates of the run's other blocks t from it
   const int nitems = nbk * (nbk + 1) / 2;
   auto item = [&](int it, int& J, int& t) {
-    // items per J in processing order: 1 + (number of remaining blocks)
     int jj = 0;
     for (;;) {
       const int cnt = nbk - jj;  // the jj-th block processed has nbk - jj items
@@ -386,67 +388,54 @@ __global__ __launch_bounds__(256, 1) void trsm_leaf_kernel(const double* __restr
       ++jj;
     }
     if (TRANS) {
-      J = nbk - 1 - jj;                  // blocks from the bottom
-      t = (it == 0) ? J : it - 1;        // then T = 0 .. J - 1
+      J = nbk - 1 - jj;            // blocks from the bottom
+      t = (it == 0) ? J : it - 1;  // then T = 0 .. J - 1
     } else {
-      J = jj;                            // blocks from the top
-      t = (it == 0) ? J : J + it;        // then T = J + 1 .. nbk - 1
+      J = jj;                      // blocks from the top
+      t = (it == 0) ? J : J + it;  // then T = J + 1 .. nbk - 1
     }
   };
-  // global source of item (J, t): row-major 64 x 64 with row stride ld, rows
-  // valid below nrow (the rest read as 0)
-  const int lc = tid % NB, lr0 = tid / NB;
-  double pre[NB * NB / 256];
-  auto fetch = [&](int it) {
+  const int lane = tid & 63, wv = tid >> 6;
+  const int ia = 16 * wv + (lane & 15), kq = lane >> 4;  // A fragment: row ia, k = 4 kk + kq
+  // A fragments of item it: a[kk] = A[ia][4 kk + kq] with A = Linv_J (^T) or
+  // the block of L; rows of L past n read as 0
+  auto load_a = [&](int it, double (&a)[NB / 4]) {
     int J, t;
     item(it, J, t);
     const int64_t gJ = b0 + J, gt = b0 + t;
-    const double* src;
-    int64_t ld, rbase;
-    if (t == J) {
-      src = Lig + gJ * NB * NB;
-      ld = NB;
-      rbase = -1;  // all rows valid
-    } else if (TRANS) {
-      src = Lg + gJ * NB * n + gt * NB;  // rows k of block J, columns i of block t
-      ld = n;
-      rbase = gJ * NB;
-    } else {
-      src = Lg + gt * NB * n + gJ * NB;  // rows i of block t, columns k of block J
-      ld = n;
-      rbase = gt * NB;
-    }
-#pragma unroll
-    for (int q = 0; q < NB * NB / 256; ++q) {
-      const int r = lr0 + 4 * q;
-      const bool ok = rbase < 0 || rbase + r < n;
-      pre[q] = src[int64_t(ok ? r : 0) * ld + lc];
-      if (!ok) pre[q] = 0.0;
-    }
-  };
-  auto stage = [&](int buf) {
-#pragma unroll
-    for (int q = 0; q < NB * NB / 256; ++q) Ls[buf][lr0 + 4 * q][lc] = pre[q];
-  };
-  const int lane = tid & 63, wv = tid >> 6;
-  fetch(0);
-  stage(0);
-  for (int it = 0; it < nitems; ++it) {
-    const int buf = it & 1;
-    __syncthreads();  // Ls[buf] and the slab are ready; Ls[buf ^ 1] is free
-    if (it + 1 < nitems) fetch(it + 1);
-    int J, t;
-    item(it, J, t);
-    // acc = A(J, t) . Xs[J], A[i][k] = Ls[k][i] (TRANS) or Ls[i][k]
-    dbl4 acc[2] = {dbl4{0.0, 0.0, 0.0, 0.0}, dbl4{0.0, 0.0, 0.0, 0.0}};
-    const int i = 16 * wv + (lane & 15);
 #pragma unroll
     for (int kk = 0; kk < NB / 4; ++kk) {
-      const int k = 4 * kk + (lane >> 4);
-      const double a = TRANS ? Ls[buf][k][i] : Ls[buf][i][k];
+      const int k = 4 * kk + kq;
+      if (t == J) {
+        const double* Li = Lig + gJ * NB * NB;
+        a[kk] = TRANS ? Li[k * NB + ia] : Li[ia * NB + k];
+      } else if (TRANS) {
+        const int64_t row = gJ * NB + k;  // A[i][k] = L[J rows k][t columns i]
+        const double v = Lg[(row < n ? row : 0) * n + gt * NB + ia];
+        a[kk] = row < n ? v : 0.0;
+      } else {
+        const int64_t row = gt * NB + ia;  // A[i][k] = L[t rows i][J columns k]
+        const double v = Lg[(row < n ? row : 0) * n + gJ * NB + k];
+        a[kk] = row < n ? v : 0.0;
+      }
+    }
+  };
+  double a_cur[NB / 4], a_nxt[NB / 4];
+  load_a(0, a_cur);
+  bool after_diag = false;
+  for (int it = 0; it < nitems; ++it) {
+    int J, t;
+    item(it, J, t);
+    if (t == J || after_diag) __syncthreads();
+    if (it + 1 < nitems) load_a(it + 1, a_nxt);
+    dbl4 acc[2] = {dbl4{0.0, 0.0, 0.0, 0.0}, dbl4{0.0, 0.0, 0.0, 0.0}};
+#pragma unroll
+    for (int kk = 0; kk < NB / 4; ++kk) {
+      const int k = 4 * kk + kq;
 #pragma unroll
       for (int j = 0; j < 2; ++j)
-        acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Xs[J * NB + k][16 * j + (lane & 15)], acc[j], 0, 0, 0);
+        acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_cur[kk], Xs[J * NB + k][16 * j + (lane & 15)], acc[j], 0,
+                                                      0, 0);
     }
     if (t == J) {
       __syncthreads();  // every wave has read X_J
@@ -471,7 +460,9 @@ __global__ __launch_bounds__(256, 1) void trsm_leaf_kernel(const double* __restr
           Xs[t * NB + rr][16 * j + (lane & 15)] -= acc[j][e];
         }
     }
-    if (it + 1 < nitems) stage(buf ^ 1);
+    after_diag = (t == J);
+#pragma unroll
+    for (int kk = 0; kk < NB / 4; ++kk) a_cur[kk] = a_nxt[kk];
   }
 }
 
