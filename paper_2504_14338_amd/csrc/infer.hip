@@ -1160,11 +1160,17 @@ struct QuadArgs {
   int r;
 };
 
-// v = y - W X_l: workgroup = (64 quadratic rows, batch entry, 64 modes),
-// FP64 MFMA over K = r + 1 in chunks of 64
+// v = y - W X_l: workgroup = (64 quadratic rows, batch entry, up to 128
+// modes).  Wave w computes rows 16 w .. 16 w + 15 against every 16-mode block
+// of the tile (FP64 MFMA), over K = r + 1 in LDS chunks of 32 with only the
+// k-steps of 4 that K reaches, so neither the modes nor K are padded to 64.
+constexpr int VK = 32;        // K per LDS chunk
+constexpr int VAP = VK + 4;   // pitch of the W chunk (rows of 16 lanes in distinct banks)
+constexpr int VBP = 128 + 8;  // pitch of the X_l chunk
+
 __global__ __launch_bounds__(256) void vq_kernel(QuadArgs a) {
-  __shared__ double At[NB][TP];
-  __shared__ double Bt[NB][TP];
+  __shared__ double At[NB][VAP];   // W[q0 + m][k0 + k]
+  __shared__ double Bt[VK][VBP];   // X_l[k0 + k][i0 + i]
   const int bt = blockIdx.y;
   const int p = a.border[bt];
   const int u = a.pair_u[p];
@@ -1172,58 +1178,68 @@ __global__ __launch_bounds__(256) void vq_kernel(QuadArgs a) {
   const int r = a.r, r1 = r + 1, w = 2 * r + 1;
   const int64_t s = a.s;
   const int64_t q0 = int64_t(blockIdx.x) * NB;
-  const int i0 = int(blockIdx.z) * NB;
+  const int i0 = int(blockIdx.z) * 128;
+  const int nb = min(8, (r - i0 + 15) / 16);  // mode blocks of this tile
   const double* R2u = a.R2 + size_t(u) * s * w;
   const double* XLp = a.XL + size_t(p) * r1 * r;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, wm = wv >> 1, wn = wv & 1;
-  dbl4 acc[2][2];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  dbl4 acc[8];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < r1; k0 += NB) {
-    __syncthreads();
+  for (int b = 0; b < 8; ++b) acc[b] = dbl4{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < r1; k0 += VK) {
     // all loads of a thread issued together (clamped addresses), then the LDS stores
-    double av[NB * NB / 256], bv[NB * NB / 256];
+    double av[NB * VK / 256], bv[VK * 128 / 256];
 #pragma unroll
-    for (int k = 0; k < NB * NB / 256; ++k) {
-      const int e = threadIdx.x + 256 * k, a_ = e / NB, b_ = e % NB;
-      const int64_t qa = q0 + a_ < s ? q0 + a_ : q0;
-      const int ca = k0 + b_ < r1 ? k0 + b_ : k0;
-      av[k] = R2u[qa * w + ca];                                                   // W[q][c]
-      bv[k] = XLp[(k0 + a_ < r1 ? k0 + a_ : k0) * r + (i0 + b_ < r ? i0 + b_ : i0)];  // X_l[c][i]
+    for (int k = 0; k < NB * VK / 256; ++k) {
+      const int e = tid + 256 * k, m = e / VK, c = e % VK;
+      av[k] = R2u[(q0 + m < s ? q0 + m : q0) * w + (k0 + c < r1 ? k0 + c : k0)];
     }
 #pragma unroll
-    for (int k = 0; k < NB * NB / 256; ++k) {
-      const int e = threadIdx.x + 256 * k, a_ = e / NB, b_ = e % NB;
-      At[a_][b_] = (q0 + a_ < s && k0 + b_ < r1) ? av[k] : 0.0;
-      Bt[a_][b_] = (k0 + a_ < r1 && i0 + b_ < r) ? bv[k] : 0.0;
+    for (int k = 0; k < VK * 128 / 256; ++k) {
+      const int e = tid + 256 * k, kr = e / 128, i = e % 128;
+      bv[k] = XLp[(k0 + kr < r1 ? k0 + kr : k0) * r + (i0 + i < r ? i0 + i : i0)];
+    }
+    __syncthreads();  // the previous chunk's reads are done
+#pragma unroll
+    for (int k = 0; k < NB * VK / 256; ++k) {
+      const int e = tid + 256 * k, m = e / VK, c = e % VK;
+      At[m][c] = (q0 + m < s && k0 + c < r1) ? av[k] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < VK * 128 / 256; ++k) {
+      const int e = tid + 256 * k, kr = e / 128, i = e % 128;
+      Bt[kr][i] = (k0 + kr < r1 && i0 + i < r) ? bv[k] : 0.0;
     }
     __syncthreads();
-    tile_mma64(At, Bt, acc, lane, wm, wn);
+    const int nst = min(VK / 4, (r1 - k0 + 3) / 4);
+#pragma unroll
+    for (int kk = 0; kk < VK / 4; ++kk) {
+      if (kk < nst) {
+        const int k = 4 * kk + (lane >> 4);
+        const double af = At[16 * wv + (lane & 15)][k];
+#pragma unroll
+        for (int b = 0; b < 8; ++b)
+          if (b < nb) acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, Bt[k][16 * b + (lane & 15)], acc[b], 0, 0, 0);
+      }
+    }
   }
   double* Vb = a.V + size_t(bt) * s * r;
-  double yv[2][2][4];  // y entries, all loaded (clamped) before the writes
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int b = 0; b < 8; ++b) {
+    if (b >= nb) continue;
+    const int ii = i0 + 16 * b + (lane & 15);
+    double yv[4];  // y entries, all loaded (clamped) before the writes
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int e = 0; e < 4; ++e) {
+      const int64_t q = q0 + 16 * wv + (lane >> 4) + 4 * e;  // MFMA f64 output layout
+      yv[e] = R2u[(q < s ? q : q0) * w + r1 + (ii < r ? ii : i0)];
+    }
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int64_t q = q0 + wm * 32 + i * 16 + (lane >> 4) + 4 * e;  // MFMA f64 output layout
-        const int ii = i0 + wn * 32 + j * 16 + (lane & 15);
-        yv[i][j][e] = R2u[(q < s ? q : q0) * w + r1 + (ii < r ? ii : i0)];
-      }
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int64_t q = q0 + wm * 32 + i * 16 + (lane >> 4) + 4 * e;
-        const int ii = i0 + wn * 32 + j * 16 + (lane & 15);
-        if (q < s && ii < r) Vb[q * r + ii] = yv[i][j][e] - acc[i][j][e];
-      }
+    for (int e = 0; e < 4; ++e) {
+      const int64_t q = q0 + 16 * wv + (lane >> 4) + 4 * e;
+      if (q < s && ii < r) Vb[q * r + ii] = yv[e] - acc[b][e];
+    }
+  }
 }
 
 // O[i][r + q] = X_q[q][i], transposed through LDS so that rows of O are
@@ -1709,7 +1725,8 @@ int chunk_quad_solve(hipStream_t st, const InferPlan& P, const ChunkBufs& b, int
                      void* ws) {
   const MiscPtrs m = misc_ptrs(P.L, ws, P.n_pairs);
   const QuadArgs qa = quad_args(P, b, g, c, nullptr, ws);
-  vq_kernel<<<quad_grid(P, b, c), 256, 0, st>>>(qa);
+  vq_kernel<<<dim3(unsigned((b.s + NB - 1) / NB), unsigned(P.nbc[c]), unsigned((b.geo.r + 127) / 128)), 256, 0, st>>>(
+      qa);
   DOPINF_LAUNCHED();
   const RhsMap rm{m.ue0 + size_t(c) * P.L.uc, m.ucnt + size_t(c) * P.L.uc, b.geo.r};
   return trsm_run(st, true, b.Lq, b.s, b.Linv, b.V, b.Xq, rm, int64_t(P.npu_max[c]) * b.geo.r, nu, kb.w, kb.w2);
