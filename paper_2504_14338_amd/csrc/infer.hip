@@ -140,89 +140,88 @@ __global__ __launch_bounds__(256) void gather_qq_kernel(const double* __restrict
 // ---------------------------------------------------------------------------
 // blocked Cholesky (lower, row-major, ld n), batched over blockIdx.z / .y
 // ---------------------------------------------------------------------------
-// Diagonal block at jb: Cholesky factor and inverse of the 64 x 64 block,
-// one workgroup per matrix, one barrier per column.  Step c reads the
-// unscaled column c of the working matrix T and its pivot d_c, updates the
-// trailing triangle T[i][l] -= T[i][c] T[l][c] / d_c, and applies the same
-// elimination to W (initially I): W[q][p] -= (T[q][c] / d_c) W[c][p] for
-// q > c.  Column c of T is final after step c, so the factor is
-// F[i][c] = T[i][c] / sqrt(d_c) (sqrt(d_c) on the diagonal).  W ends as
-// M^{-1} for the unit lower factor M of A = M diag(d) M^T, so
-// L^{-1} = diag(d)^{-1/2} W.  Rows beyond the matrix are identity rows.
-// T and W live in registers: thread (wave v, lane j) holds column j of rows
-// 16 v .. 16 v + 15 of both.  Per step the owners publish column c of T and
-// row c of W through LDS (double-buffered by the parity of c, so one barrier
-// per step suffices) and every thread updates its 16 rows; 2 KB of LDS.
+// Diagonal block at jb: Cholesky factor and inverse of the 64 x 64 block in
+// LDS, one workgroup per matrix, one barrier per column.  Step c reads the
+// unscaled column c of the working matrix T and its pivot d_c; it writes
+// column c of the factor F (sqrt(d_c) on the diagonal), updates the trailing
+// triangle T[i][l] -= T[i][c] T[l][c] / d_c, and applies the same elimination
+// to W (initially I): W[q][p] -= (T[q][c] / d_c) W[c][p] for q > c.  Nothing
+// that step c reads is written in step c.  W ends as M^{-1} for the unit
+// lower factor M of A = M diag(d) M^T, so L^{-1} = diag(d)^{-1/2} W.  Rows
+// beyond the matrix are identity rows.
 __global__ __launch_bounds__(256) void potf2_kernel(double* __restrict__ A, int64_t n, int64_t jb,
                                                     double* __restrict__ Linv, int* __restrict__ fail_flag) {
-  __shared__ double colb[2][NB];  // column c of T
-  __shared__ double rowb[2][NB];  // row c of W
-  __shared__ double sd[NB];       // sqrt(d_c)
+  __shared__ double T[NB][NB + 1];
+  __shared__ double F[NB][NB + 1];
+  __shared__ double W[NB][NB + 1];
   __shared__ int bad;
   const int u = blockIdx.x;
-  const int tid = threadIdx.x, j = tid & 63, wv = tid >> 6;
+  const int tid = threadIdx.x;
   double* Au = A + size_t(u) * n * n;
   const int nb = int(min<int64_t>(NB, n - jb));
-  double t[16], wr[16];
   {
     // all 16 loads of a thread in flight together (clamped addresses, select)
-    double v[16];
+    const int j = tid % NB, i0 = tid / NB;
+    double v[NB / 4];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      const int i = 16 * wv + k;
+    for (int k = 0; k < NB / 4; ++k) {
+      const int i = i0 + 4 * k;
       const int ic = i < nb ? i : 0, jc = j < nb ? j : 0;
       v[k] = Au[(jb + ic) * n + jb + jc];
     }
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      const int i = 16 * wv + k;
-      t[k] = (i < nb && j <= i) ? v[k] : (i == j ? 1.0 : 0.0);
-      wr[k] = (i == j) ? 1.0 : 0.0;
+    for (int k = 0; k < NB / 4; ++k) {
+      const int i = i0 + 4 * k;
+      T[i][j] = (i < nb && j <= i) ? v[k] : (i == j ? 1.0 : 0.0);
+      F[i][j] = 0.0;
+      W[i][j] = (i == j) ? 1.0 : 0.0;
     }
   }
   if (tid == 0) bad = 0;
-#pragma unroll
+  __syncthreads();
   for (int c = 0; c < NB; ++c) {
-    const int pb = c & 1;
-    if (j == c) {
-#pragma unroll
-      for (int k = 0; k < 16; ++k) colb[pb][16 * wv + k] = t[k];
-    }
-    if (wv == c / 16) rowb[pb][j] = wr[c % 16];
-    __syncthreads();
-    const double piv = colb[pb][c];
+    const double piv = T[c][c];
     const bool okp = (piv > 0.0) && isfinite(piv);
     const double pv = okp ? piv : 1.0;
-    if (tid == 0) {
-      sd[c] = sqrt(pv);
-      if (!okp) bad = 1;
-    }
-    if (16 * wv + 15 > c) {  // this wave has rows below c
-      const double rp = 1.0 / pv;
-      // column j > c of T (lower part) or column j <= c of W, one code path
-      const bool onT = j > c;
-      const double f = (onT ? colb[pb][j] : rowb[pb][j]) * rp;
+    const double d = sqrt(pv);
+    if (tid >= c && tid < NB) F[tid][c] = (tid == c) ? d : T[tid][c] / d;
+    if (tid == 0 && !okp) bad = 1;
+    const double rp = 1.0 / pv;
+    // thread -> column j = tid % 64 and rows c + 1 + tid / 64 + 4k: column
+    // j > c of T (lower part) or column j <= c of W, with one code path for
+    // both (no divergence) and all reads issued before the writes
+    const int j = tid % NB;
+    const bool onT = j > c;
+    double* dst = onT ? &T[0][0] : &W[0][0];
+    const double f = (onT ? T[j][c] : W[c][j]) * rp;
+    // rows c + 1 .. NB - 1 in steps of 4: 16 per thread for c < 32, then 8
+    auto step = [&](auto kn) {
+      constexpr int KN = decltype(kn)::value;
+      double a[KN], b[KN];
 #pragma unroll
-      for (int k = 0; k < 16; ++k) {
-        const int i = 16 * wv + k;
-        if (i > c) {
-          const double upd = (onT ? t[k] : wr[k]) - colb[pb][i] * f;
-          if (onT) {
-            if (j <= i) t[k] = upd;
-          } else {
-            wr[k] = upd;
-          }
-        }
+      for (int k = 0; k < KN; ++k) {
+        const int i = c + 1 + tid / NB + 4 * k;
+        const int ic = i < NB ? i : NB - 1;
+        a[k] = T[ic][c];
+        b[k] = dst[ic * (NB + 1) + j];
       }
-    }
-  }
-  __syncthreads();
-  double* Lo = Linv + (size_t(u) * ((n + NB - 1) / NB) + jb / NB) * NB * NB;
 #pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    const int i = 16 * wv + k;
-    if (i < nb && j <= i) Au[(jb + i) * n + jb + j] = (i == j) ? sd[j] : t[k] / sd[j];
-    Lo[i * NB + j] = (j <= i) ? wr[k] / sd[i] : 0.0;
+      for (int k = 0; k < KN; ++k) {
+        const int i = c + 1 + tid / NB + 4 * k;
+        if (i < NB && (!onT || j <= i)) dst[i * (NB + 1) + j] = b[k] - a[k] * f;
+      }
+    };
+    if (c < NB / 2)
+      step(std::integral_constant<int, NB / 4>{});
+    else
+      step(std::integral_constant<int, NB / 8>{});
+    __syncthreads();
+  }
+  double* Lo = Linv + (size_t(u) * ((n + NB - 1) / NB) + jb / NB) * NB * NB;
+  for (int e = tid; e < NB * NB; e += 256) {
+    const int i = e / NB, j = e % NB;
+    if (i < nb && j <= i) Au[(jb + i) * n + jb + j] = F[i][j];
+    Lo[e] = (j <= i) ? W[i][j] / F[i][i] : 0.0;
   }
   if (tid == 0 && bad) fail_flag[u] = 1;
 }
