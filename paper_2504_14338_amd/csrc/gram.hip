@@ -65,6 +65,8 @@ struct GramArgs {
   int tiles_y;     // tiles along Y (rectangular mode)
   int ntiles;
   int triangle;    // X == Y: lower triangle of tiles only
+  int sel;         // tiles of an LDS-DMA launch: 0 all, 1 below the diagonal, 2 on it
+  int nlaunch;     // tiles per split in that launch
   const double* mean;   // may be null
   const double* scale;  // may be null
   double* part;
@@ -239,6 +241,16 @@ __device__ __forceinline__ void barrier_only() {
   asm volatile("" ::: "memory");
 }
 
+// Blocks of 16 x 16 computed by wave w (0..3) of a diagonal tile: the 9
+// blocks p = 0..8 of block columns w (block rows w..7) and 7 - w (block rows
+// 7 - w..7), which cover the tile's lower triangle of 8 x 8 blocks (36) with
+// 9 per wave.  Accumulator p is acc[p / 4][p % 4].
+__device__ __forceinline__ void diag_block(int w, int p, int& br, int& bc) {
+  const bool first = p < 8 - w;
+  br = first ? w + p : p - 1;
+  bc = first ? w : 7 - w;
+}
+
 template <bool DIAG, bool XF>
 __device__ __forceinline__ void dma_tile(const GramArgs& g, int64_t lo, int64_t hi, int64_t a0, int64_t b0, double* lds,
                                          dbl4 (&acc)[4][4]) {
@@ -275,16 +287,12 @@ __device__ __forceinline__ void dma_tile(const GramArgs& g, int64_t lo, int64_t 
     }
   };
 
-  // waves whose 64 x 64 block lies wholly above the diagonal have nothing to add
-  bool active = true;
-  if (DIAG) active = (a0 + wm * 64 + 63) >= (b0 + wn * 64);
 
   if (nst > 0) issue(0);
   for (int64_t st = 0; st < nst; ++st) {
     wait_vmem<0>();
     barrier_only();
     if (st + 1 < nst) issue(st + 1);
-    if (!active) continue;
     const double* sl = lds + (st & 1) * DSLOT;
     const double* As = sl;
     const double* Bs = DIAG ? sl : sl + DKC * DPD;
@@ -294,41 +302,72 @@ __device__ __forceinline__ void dma_tile(const GramArgs& g, int64_t lo, int64_t 
       const int krow = kk * 4 + (lane >> 4);
       const int cm = lane & 15;
       const double mu = XF ? Ms[krow] : 0.0;
-      double af[4], bf[4];
+      if (DIAG) {
+        // the 9 lower blocks of wave w (diag_block): columns w and 7 - w
+        const double b_lo = Bs[krow * DPD + w * 16 + cm] - mu;
+        const double b_hi = Bs[krow * DPD + (7 - w) * 16 + cm] - mu;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) af[i] = As[krow * DPD + wm * 64 + i * 16 + cm] - mu;
+        for (int p = 0; p < 9; ++p) {
+          int br, bc;
+          diag_block(w, p, br, bc);
+          const double a = As[krow * DPD + br * 16 + cm] - mu;
+          acc[p >> 2][p & 3] =
+              __builtin_amdgcn_mfma_f64_16x16x4f64(a, bc == w ? b_lo : b_hi, acc[p >> 2][p & 3], 0, 0, 0);
+        }
+      } else {
+        double af[4], bf[4];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bf[j] = Bs[krow * DPD + wn * 64 + j * 16 + cm] - mu;
+        for (int i = 0; i < 4; ++i) af[i] = As[krow * DPD + wm * 64 + i * 16 + cm] - mu;
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) bf[j] = Bs[krow * DPD + wn * 64 + j * 16 + cm] - mu;
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+      }
     }
   }
 }
 
+// One launch covers the tiles that g.sel selects: all of a rectangular
+// Gram, or, for the symmetric one, the tiles below the diagonal (DIAG false)
+// and then the diagonal tiles (DIAG true) in a launch of their own.  A
+// diagonal tile needs 36 of its 64 blocks, 9 per wave; in the launch of the
+// full tiles its workgroups would finish early and leave the rounds of
+// resident workgroups ragged, in a launch of their own they fill rounds of
+// equal work.
+template <bool DIAG>
 __global__ __launch_bounds__(NTH, 2) void gram_f64_dma_kernel(GramArgs g, SplitPlan sp) {
   __shared__ double lds[2 * DSLOT];
-  int t, s;
+  int tl, s;
   {
     const int bid = blockIdx.x;
     if (sp.xcd_map) {
       const int xcd = bid & 7;
       const int local = bid >> 3;
-      s = (local / g.ntiles) * 8 + xcd;
-      t = local % g.ntiles;
+      s = (local / g.nlaunch) * 8 + xcd;
+      tl = local % g.nlaunch;
     } else {
-      s = bid / g.ntiles;
-      t = bid % g.ntiles;
+      s = bid / g.nlaunch;
+      tl = bid % g.nlaunch;
     }
   }
-  int I, J;
-  tile_coords(g, t, I, J);
+  int I, J, t;  // tile coordinates and index of the partial tile
+  if (g.sel == 1) {
+    gramplan::tri_coords(tl, I, J);  // tl-th tile strictly below: (I + 1, J)
+    ++I;
+    t = I * (I + 1) / 2 + J;
+  } else if (g.sel == 2) {
+    I = J = tl;
+    t = I * (I + 1) / 2 + I;
+  } else {
+    tile_coords(g, tl, I, J);
+    t = tl;
+  }
   int64_t lo, hi;
   int v;
   gramplan::split_range(sp, s, DKC, lo, hi, v);
-  const bool diag = g.triangle && (I == J);
   const int64_t a0 = int64_t(I) * BT, b0 = int64_t(J) * BT;
 
   dbl4 acc[4][4];
@@ -337,13 +376,10 @@ __global__ __launch_bounds__(NTH, 2) void gram_f64_dma_kernel(GramArgs g, SplitP
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
 
-  if (g.mean) {
-    if (diag) dma_tile<true, true>(g, lo, hi, a0, b0, lds, acc);
-    else dma_tile<false, true>(g, lo, hi, a0, b0, lds, acc);
-  } else {
-    if (diag) dma_tile<true, false>(g, lo, hi, a0, b0, lds, acc);
-    else dma_tile<false, false>(g, lo, hi, a0, b0, lds, acc);
-  }
+  if (g.mean)
+    dma_tile<DIAG, true>(g, lo, hi, a0, b0, lds, acc);
+  else
+    dma_tile<DIAG, false>(g, lo, hi, a0, b0, lds, acc);
 
   // both operands carry 1/s_v: the partial tile takes 1/s_v^2
   double f = 1.0;
@@ -355,13 +391,29 @@ __global__ __launch_bounds__(NTH, 2) void gram_f64_dma_kernel(GramArgs g, SplitP
   const int w = threadIdx.x >> 6;
   const int wm = w >> 1, wn = w & 1;
   double* out = g.part + (size_t(s) * g.ntiles + t) * (BT * BT);
+  // v_mfma_f64_16x16x4: lane l, element e holds row (l / 16) + 4 e, column
+  // l % 16 of a 16 x 16 block.  A diagonal tile writes its lower blocks only
+  // (the reduction reads nothing above the diagonal).
+  if (DIAG) {
+#pragma unroll
+    for (int p = 0; p < 9; ++p) {
+      int br, bc;
+      diag_block(w, p, br, bc);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int rr = br * 16 + (lane >> 4) + 4 * e;
+        const int cc = bc * 16 + (lane & 15);
+        out[rr * BT + cc] = acc[p >> 2][p & 3][e] * f;
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        // v_mfma_f64_16x16x4: lane l, element e holds row (l / 16) + 4 e, column l % 16
         const int rr = wm * 64 + i * 16 + (lane >> 4) + 4 * e;
         const int cc = wn * 64 + j * 16 + (lane & 15);
         out[rr * BT + cc] = acc[i][j][e] * f;
@@ -406,10 +458,26 @@ size_t part_bytes(int nsplit, int ntiles) { return size_t(nsplit) * ntiles * BT 
 int run_gram(hipStream_t st, GramArgs g, const SplitPlan& sp, double* C, int64_t ldc, int tiles_y) {
   g.tiles_y = tiles_y;
   dim3 grid(unsigned(sp.nsplit) * unsigned(g.ntiles));
-  if (dma_ok(g.X, g.ldx) && dma_ok(g.Y, g.ldy))
-    gram_f64_dma_kernel<<<grid, NTH, 0, st>>>(g, sp);
-  else
+  if (dma_ok(g.X, g.ldx) && dma_ok(g.Y, g.ldy)) {
+    if (g.triangle) {
+      const int noff = tiles_y * (tiles_y - 1) / 2;
+      if (noff > 0) {
+        g.sel = 1;
+        g.nlaunch = noff;
+        gram_f64_dma_kernel<false><<<dim3(unsigned(sp.nsplit) * unsigned(noff)), NTH, 0, st>>>(g, sp);
+        DOPINF_LAUNCHED();
+      }
+      g.sel = 2;
+      g.nlaunch = tiles_y;
+      gram_f64_dma_kernel<true><<<dim3(unsigned(sp.nsplit) * unsigned(tiles_y)), NTH, 0, st>>>(g, sp);
+    } else {
+      g.sel = 0;
+      g.nlaunch = g.ntiles;
+      gram_f64_dma_kernel<false><<<grid, NTH, 0, st>>>(g, sp);
+    }
+  } else {
     gram_f64_mfma_kernel<<<grid, NTH, 0, st>>>(g, sp);
+  }
   DOPINF_LAUNCHED();
   dim3 rgrid(unsigned(g.ntiles), BT / 2);
   gram_reduce_kernel<<<rgrid, 256, 0, st>>>(g.part, sp.nsplit, g.ntiles, tiles_y, g.triangle, g.mx, g.my, C, ldc);
