@@ -251,9 +251,13 @@ __device__ __forceinline__ void diag_block(int w, int p, int& br, int& bc) {
   bc = first ? w : 7 - w;
 }
 
-template <bool DIAG, bool XF>
-__device__ __forceinline__ void dma_tile(const GramArgs& g, int64_t lo, int64_t hi, int64_t a0, int64_t b0, double* lds,
-                                         dbl4 (&acc)[4][4]) {
+// DIAG false: the tile (a0, b0), wave w the quadrant (w / 2, w % 2), acc[4 i + j]
+// its 4 x 4 blocks.  DIAG true: the diagonal tiles at a0 (from the A panel)
+// and at b0 (from the B panel; skipped when two is false), 9 blocks per wave
+// each (diag_block), acc[p] and acc[9 + p].
+template <bool DIAG, bool XF, int NACC>
+__device__ __forceinline__ void dma_tile(const GramArgs& g, int64_t lo, int64_t hi, int64_t a0, int64_t b0, bool two,
+                                         double* lds, dbl4 (&acc)[NACC]) {
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
   const int wm = w >> 1, wn = w & 1;
@@ -274,10 +278,8 @@ __device__ __forceinline__ void dma_tile(const GramArgs& g, int64_t lo, int64_t 
       const int64_t rr = in ? row : lo;
       const __amdgpu_buffer_rsrc_t ra = span_rsrc(g.X + rr * g.ldx, in ? bytes_x : 0);
       __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, DOPINF_LDS(sl + r * DPD), 16, offa, 0, 0, 0);
-      if (!DIAG) {
-        const __amdgpu_buffer_rsrc_t rb = span_rsrc(g.Y + rr * g.ldy, in ? bytes_y : 0);
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, DOPINF_LDS(sl + (DKC + r) * DPD), 16, offb, 0, 0, 0);
-      }
+      const __amdgpu_buffer_rsrc_t rb = span_rsrc(g.Y + rr * g.ldy, in ? bytes_y : 0);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, DOPINF_LDS(sl + (DKC + r) * DPD), 16, offb, 0, 0, 0);
     }
     if (XF) {
       // lane l brings half of mean[r0 + l / 2]; rows past the split read as 0
@@ -295,7 +297,7 @@ __device__ __forceinline__ void dma_tile(const GramArgs& g, int64_t lo, int64_t 
     if (st + 1 < nst) issue(st + 1);
     const double* sl = lds + (st & 1) * DSLOT;
     const double* As = sl;
-    const double* Bs = DIAG ? sl : sl + DKC * DPD;
+    const double* Bs = sl + DKC * DPD;
     const double* Ms = sl + 2 * DKC * DPD + w * 32;
 #pragma unroll
     for (int kk = 0; kk < DKC / 4; ++kk) {
@@ -303,16 +305,21 @@ __device__ __forceinline__ void dma_tile(const GramArgs& g, int64_t lo, int64_t 
       const int cm = lane & 15;
       const double mu = XF ? Ms[krow] : 0.0;
       if (DIAG) {
-        // the 9 lower blocks of wave w (diag_block): columns w and 7 - w
-        const double b_lo = Bs[krow * DPD + w * 16 + cm] - mu;
-        const double b_hi = Bs[krow * DPD + (7 - w) * 16 + cm] - mu;
+        // the 9 lower blocks of wave w (diag_block) of each tile: columns w
+        // and 7 - w of the tile's own panel
 #pragma unroll
-        for (int p = 0; p < 9; ++p) {
-          int br, bc;
-          diag_block(w, p, br, bc);
-          const double a = As[krow * DPD + br * 16 + cm] - mu;
-          acc[p >> 2][p & 3] =
-              __builtin_amdgcn_mfma_f64_16x16x4f64(a, bc == w ? b_lo : b_hi, acc[p >> 2][p & 3], 0, 0, 0);
+        for (int h = 0; h < 2; ++h) {
+          if (h == 1 && !two) break;
+          const double* P = h ? Bs : As;
+          const double p_lo = P[krow * DPD + w * 16 + cm] - mu;
+          const double p_hi = P[krow * DPD + (7 - w) * 16 + cm] - mu;
+#pragma unroll
+          for (int p = 0; p < 9; ++p) {
+            int br, bc;
+            diag_block(w, p, br, bc);
+            const double a = P[krow * DPD + br * 16 + cm] - mu;
+            acc[9 * h + p] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bc == w ? p_lo : p_hi, acc[9 * h + p], 0, 0, 0);
+          }
         }
       } else {
         double af[4], bf[4];
@@ -324,7 +331,7 @@ __device__ __forceinline__ void dma_tile(const GramArgs& g, int64_t lo, int64_t 
         for (int i = 0; i < 4; ++i)
 #pragma unroll
           for (int j = 0; j < 4; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+            acc[4 * i + j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[4 * i + j], 0, 0, 0);
       }
     }
   }
@@ -335,8 +342,9 @@ __device__ __forceinline__ void dma_tile(const GramArgs& g, int64_t lo, int64_t 
 // and then the diagonal tiles (DIAG true) in a launch of their own.  A
 // diagonal tile needs 36 of its 64 blocks, 9 per wave; in the launch of the
 // full tiles its workgroups would finish early and leave the rounds of
-// resident workgroups ragged, in a launch of their own they fill rounds of
-// equal work.
+// resident workgroups ragged.  A workgroup of the diagonal launch takes two
+// diagonal tiles (both panels loaded, as for a full tile): 18 blocks per
+// wave against 16, so its rounds are nearly as long as the others.
 template <bool DIAG>
 __global__ __launch_bounds__(NTH, 2) void gram_f64_dma_kernel(GramArgs g, SplitPlan sp) {
   __shared__ double lds[2 * DSLOT];
@@ -353,33 +361,36 @@ __global__ __launch_bounds__(NTH, 2) void gram_f64_dma_kernel(GramArgs g, SplitP
       tl = bid % g.nlaunch;
     }
   }
-  int I, J, t;  // tile coordinates and index of the partial tile
+  // tile coordinates and index of the partial tile; the diagonal launch
+  // takes the diagonal tiles in pairs (I, I + 1), I even
+  int I, J, t;
   if (g.sel == 1) {
     gramplan::tri_coords(tl, I, J);  // tl-th tile strictly below: (I + 1, J)
     ++I;
     t = I * (I + 1) / 2 + J;
   } else if (g.sel == 2) {
-    I = J = tl;
+    I = 2 * tl;
+    J = I + 1 < g.tiles_y ? I + 1 : I;
     t = I * (I + 1) / 2 + I;
   } else {
     tile_coords(g, tl, I, J);
     t = tl;
   }
+  const bool two = DIAG && J != I;
   int64_t lo, hi;
   int v;
   gramplan::split_range(sp, s, DKC, lo, hi, v);
   const int64_t a0 = int64_t(I) * BT, b0 = int64_t(J) * BT;
 
-  dbl4 acc[4][4];
+  constexpr int NACC = DIAG ? 18 : 16;
+  dbl4 acc[NACC];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+  for (int i = 0; i < NACC; ++i) acc[i] = dbl4{0.0, 0.0, 0.0, 0.0};
 
   if (g.mean)
-    dma_tile<DIAG, true>(g, lo, hi, a0, b0, lds, acc);
+    dma_tile<DIAG, true, NACC>(g, lo, hi, a0, b0, two, lds, acc);
   else
-    dma_tile<DIAG, false>(g, lo, hi, a0, b0, lds, acc);
+    dma_tile<DIAG, false, NACC>(g, lo, hi, a0, b0, two, lds, acc);
 
   // both operands carry 1/s_v: the partial tile takes 1/s_v^2
   double f = 1.0;
@@ -393,17 +404,23 @@ __global__ __launch_bounds__(NTH, 2) void gram_f64_dma_kernel(GramArgs g, SplitP
   double* out = g.part + (size_t(s) * g.ntiles + t) * (BT * BT);
   // v_mfma_f64_16x16x4: lane l, element e holds row (l / 16) + 4 e, column
   // l % 16 of a 16 x 16 block.  A diagonal tile writes its lower blocks only
-  // (the reduction reads nothing above the diagonal).
+  // (the reduction reads nothing above the diagonal); the second tile of a
+  // pair (J = I + 1) sits J + 1 tiles further on.
   if (DIAG) {
 #pragma unroll
-    for (int p = 0; p < 9; ++p) {
-      int br, bc;
-      diag_block(w, p, br, bc);
+    for (int h = 0; h < 2; ++h) {
+      if (h == 1 && !two) break;
+      double* o = out + (h ? size_t(J + 1) * BT * BT : 0);
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int rr = br * 16 + (lane >> 4) + 4 * e;
-        const int cc = bc * 16 + (lane & 15);
-        out[rr * BT + cc] = acc[p >> 2][p & 3][e] * f;
+      for (int p = 0; p < 9; ++p) {
+        int br, bc;
+        diag_block(w, p, br, bc);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int rr = br * 16 + (lane >> 4) + 4 * e;
+          const int cc = bc * 16 + (lane & 15);
+          o[rr * BT + cc] = acc[9 * h + p][e] * f;
+        }
       }
     }
     return;
@@ -416,7 +433,7 @@ __global__ __launch_bounds__(NTH, 2) void gram_f64_dma_kernel(GramArgs g, SplitP
       for (int e = 0; e < 4; ++e) {
         const int rr = wm * 64 + i * 16 + (lane >> 4) + 4 * e;
         const int cc = wn * 64 + j * 16 + (lane & 15);
-        out[rr * BT + cc] = acc[i][j][e] * f;
+        out[rr * BT + cc] = acc[4 * i + j][e] * f;
       }
 }
 
@@ -468,8 +485,8 @@ int run_gram(hipStream_t st, GramArgs g, const SplitPlan& sp, double* C, int64_t
         DOPINF_LAUNCHED();
       }
       g.sel = 2;
-      g.nlaunch = tiles_y;
-      gram_f64_dma_kernel<true><<<dim3(unsigned(sp.nsplit) * unsigned(tiles_y)), NTH, 0, st>>>(g, sp);
+      g.nlaunch = (tiles_y + 1) / 2;  // pairs of diagonal tiles
+      gram_f64_dma_kernel<true><<<dim3(unsigned(sp.nsplit) * unsigned(g.nlaunch)), NTH, 0, st>>>(g, sp);
     } else {
       g.sel = 0;
       g.nlaunch = g.ntiles;
