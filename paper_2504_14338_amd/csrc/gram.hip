@@ -251,13 +251,30 @@ __device__ __forceinline__ void diag_block(int w, int p, int& br, int& bc) {
   bc = first ? w : 7 - w;
 }
 
-// DIAG false: the tile (a0, b0), wave w the quadrant (w / 2, w % 2), acc[4 i + j]
-// its 4 x 4 blocks.  DIAG true: the diagonal tiles at a0 (from the A panel)
-// and at b0 (from the B panel; skipped when two is false), 9 blocks per wave
-// each (diag_block), acc[p] and acc[9 + p].
-template <bool DIAG, bool XF, int NACC>
-__device__ __forceinline__ void dma_tile(const GramArgs& g, int64_t lo, int64_t hi, int64_t a0, int64_t b0, bool two,
-                                         double* lds, dbl4 (&acc)[NACC]) {
+// One k-step of wave W of a diagonal tile: block columns W (block rows
+// W..7) and 7 - W (block rows 7 - W..7, a subset of the former), so the
+// fragments of rows W..7 are read once and serve both columns; accumulator
+// p = diag_block's index.  Ak points at (k-row, lane column) of the panel.
+template <int W>
+__device__ __forceinline__ void diag_step(const double* Ak, double mu, dbl4 (&acc)[4][4]) {
+  double af[8 - W];
+#pragma unroll
+  for (int i = 0; i < 8 - W; ++i) af[i] = Ak[(W + i) * 16] - mu;  // block row W + i (also column W + i)
+  const double b_lo = af[0];                                     // column W
+  const double b_hi = af[7 - 2 * W];                             // column 7 - W
+#pragma unroll
+  for (int p = 0; p < 8 - W; ++p)  // (W + p, W)
+    acc[p >> 2][p & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[p], b_lo, acc[p >> 2][p & 3], 0, 0, 0);
+#pragma unroll
+  for (int q = 0; q <= W; ++q) {  // (7 - W + q, 7 - W), p = 8 - W + q
+    const int p = 8 - W + q;
+    acc[p >> 2][p & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[7 - 2 * W + q], b_hi, acc[p >> 2][p & 3], 0, 0, 0);
+  }
+}
+
+template <bool DIAG, bool XF>
+__device__ __forceinline__ void dma_tile(const GramArgs& g, int64_t lo, int64_t hi, int64_t a0, int64_t b0, double* lds,
+                                         dbl4 (&acc)[4][4]) {
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
   const int wm = w >> 1, wn = w & 1;
@@ -278,8 +295,10 @@ __device__ __forceinline__ void dma_tile(const GramArgs& g, int64_t lo, int64_t 
       const int64_t rr = in ? row : lo;
       const __amdgpu_buffer_rsrc_t ra = span_rsrc(g.X + rr * g.ldx, in ? bytes_x : 0);
       __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, DOPINF_LDS(sl + r * DPD), 16, offa, 0, 0, 0);
-      const __amdgpu_buffer_rsrc_t rb = span_rsrc(g.Y + rr * g.ldy, in ? bytes_y : 0);
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, DOPINF_LDS(sl + (DKC + r) * DPD), 16, offb, 0, 0, 0);
+      if (!DIAG) {
+        const __amdgpu_buffer_rsrc_t rb = span_rsrc(g.Y + rr * g.ldy, in ? bytes_y : 0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, DOPINF_LDS(sl + (DKC + r) * DPD), 16, offb, 0, 0, 0);
+      }
     }
     if (XF) {
       // lane l brings half of mean[r0 + l / 2]; rows past the split read as 0
@@ -297,7 +316,7 @@ __device__ __forceinline__ void dma_tile(const GramArgs& g, int64_t lo, int64_t 
     if (st + 1 < nst) issue(st + 1);
     const double* sl = lds + (st & 1) * DSLOT;
     const double* As = sl;
-    const double* Bs = sl + DKC * DPD;
+    const double* Bs = DIAG ? sl : sl + DKC * DPD;
     const double* Ms = sl + 2 * DKC * DPD + w * 32;
 #pragma unroll
     for (int kk = 0; kk < DKC / 4; ++kk) {
@@ -305,21 +324,14 @@ __device__ __forceinline__ void dma_tile(const GramArgs& g, int64_t lo, int64_t 
       const int cm = lane & 15;
       const double mu = XF ? Ms[krow] : 0.0;
       if (DIAG) {
-        // the 9 lower blocks of wave w (diag_block) of each tile: columns w
-        // and 7 - w of the tile's own panel
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          if (h == 1 && !two) break;
-          const double* P = h ? Bs : As;
-          const double p_lo = P[krow * DPD + w * 16 + cm] - mu;
-          const double p_hi = P[krow * DPD + (7 - w) * 16 + cm] - mu;
-#pragma unroll
-          for (int p = 0; p < 9; ++p) {
-            int br, bc;
-            diag_block(w, p, br, bc);
-            const double a = P[krow * DPD + br * 16 + cm] - mu;
-            acc[9 * h + p] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bc == w ? p_lo : p_hi, acc[9 * h + p], 0, 0, 0);
-          }
+        // the 9 lower blocks of wave w (diag_block), with w a constant in
+        // each branch (w is wave-uniform)
+        const double* Ak = As + krow * DPD + cm;
+        switch (w) {
+          case 0: diag_step<0>(Ak, mu, acc); break;
+          case 1: diag_step<1>(Ak, mu, acc); break;
+          case 2: diag_step<2>(Ak, mu, acc); break;
+          default: diag_step<3>(Ak, mu, acc); break;
         }
       } else {
         double af[4], bf[4];
@@ -331,7 +343,7 @@ __device__ __forceinline__ void dma_tile(const GramArgs& g, int64_t lo, int64_t 
         for (int i = 0; i < 4; ++i)
 #pragma unroll
           for (int j = 0; j < 4; ++j)
-            acc[4 * i + j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[4 * i + j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
       }
     }
   }
@@ -342,9 +354,8 @@ __device__ __forceinline__ void dma_tile(const GramArgs& g, int64_t lo, int64_t 
 // and then the diagonal tiles (DIAG true) in a launch of their own.  A
 // diagonal tile needs 36 of its 64 blocks, 9 per wave; in the launch of the
 // full tiles its workgroups would finish early and leave the rounds of
-// resident workgroups ragged.  A workgroup of the diagonal launch takes two
-// diagonal tiles (both panels loaded, as for a full tile): 18 blocks per
-// wave against 16, so its rounds are nearly as long as the others.
+// resident workgroups ragged, in a launch of their own they fill rounds of
+// equal work.
 template <bool DIAG>
 __global__ __launch_bounds__(NTH, 2) void gram_f64_dma_kernel(GramArgs g, SplitPlan sp) {
   __shared__ double lds[2 * DSLOT];
@@ -361,36 +372,33 @@ __global__ __launch_bounds__(NTH, 2) void gram_f64_dma_kernel(GramArgs g, SplitP
       tl = bid % g.nlaunch;
     }
   }
-  // tile coordinates and index of the partial tile; the diagonal launch
-  // takes the diagonal tiles in pairs (I, I + 1), I even
-  int I, J, t;
+  int I, J, t;  // tile coordinates and index of the partial tile
   if (g.sel == 1) {
     gramplan::tri_coords(tl, I, J);  // tl-th tile strictly below: (I + 1, J)
     ++I;
     t = I * (I + 1) / 2 + J;
   } else if (g.sel == 2) {
-    I = 2 * tl;
-    J = I + 1 < g.tiles_y ? I + 1 : I;
+    I = J = tl;
     t = I * (I + 1) / 2 + I;
   } else {
     tile_coords(g, tl, I, J);
     t = tl;
   }
-  const bool two = DIAG && J != I;
   int64_t lo, hi;
   int v;
   gramplan::split_range(sp, s, DKC, lo, hi, v);
   const int64_t a0 = int64_t(I) * BT, b0 = int64_t(J) * BT;
 
-  constexpr int NACC = DIAG ? 18 : 16;
-  dbl4 acc[NACC];
+  dbl4 acc[4][4];
 #pragma unroll
-  for (int i = 0; i < NACC; ++i) acc[i] = dbl4{0.0, 0.0, 0.0, 0.0};
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
 
   if (g.mean)
-    dma_tile<DIAG, true, NACC>(g, lo, hi, a0, b0, two, lds, acc);
+    dma_tile<DIAG, true>(g, lo, hi, a0, b0, lds, acc);
   else
-    dma_tile<DIAG, false, NACC>(g, lo, hi, a0, b0, two, lds, acc);
+    dma_tile<DIAG, false>(g, lo, hi, a0, b0, lds, acc);
 
   // both operands carry 1/s_v: the partial tile takes 1/s_v^2
   double f = 1.0;
@@ -404,23 +412,17 @@ __global__ __launch_bounds__(NTH, 2) void gram_f64_dma_kernel(GramArgs g, SplitP
   double* out = g.part + (size_t(s) * g.ntiles + t) * (BT * BT);
   // v_mfma_f64_16x16x4: lane l, element e holds row (l / 16) + 4 e, column
   // l % 16 of a 16 x 16 block.  A diagonal tile writes its lower blocks only
-  // (the reduction reads nothing above the diagonal); the second tile of a
-  // pair (J = I + 1) sits J + 1 tiles further on.
+  // (the reduction reads nothing above the diagonal).
   if (DIAG) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      if (h == 1 && !two) break;
-      double* o = out + (h ? size_t(J + 1) * BT * BT : 0);
+    for (int p = 0; p < 9; ++p) {
+      int br, bc;
+      diag_block(w, p, br, bc);
 #pragma unroll
-      for (int p = 0; p < 9; ++p) {
-        int br, bc;
-        diag_block(w, p, br, bc);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int rr = br * 16 + (lane >> 4) + 4 * e;
-          const int cc = bc * 16 + (lane & 15);
-          o[rr * BT + cc] = acc[9 * h + p][e] * f;
-        }
+      for (int e = 0; e < 4; ++e) {
+        const int rr = br * 16 + (lane >> 4) + 4 * e;
+        const int cc = bc * 16 + (lane & 15);
+        out[rr * BT + cc] = acc[p >> 2][p & 3][e] * f;
       }
     }
     return;
@@ -433,7 +435,7 @@ __global__ __launch_bounds__(NTH, 2) void gram_f64_dma_kernel(GramArgs g, SplitP
       for (int e = 0; e < 4; ++e) {
         const int rr = wm * 64 + i * 16 + (lane >> 4) + 4 * e;
         const int cc = wn * 64 + j * 16 + (lane & 15);
-        out[rr * BT + cc] = acc[4 * i + j][e] * f;
+        out[rr * BT + cc] = acc[i][j][e] * f;
       }
 }
 
@@ -485,8 +487,8 @@ int run_gram(hipStream_t st, GramArgs g, const SplitPlan& sp, double* C, int64_t
         DOPINF_LAUNCHED();
       }
       g.sel = 2;
-      g.nlaunch = (tiles_y + 1) / 2;  // pairs of diagonal tiles
-      gram_f64_dma_kernel<true><<<dim3(unsigned(sp.nsplit) * unsigned(g.nlaunch)), NTH, 0, st>>>(g, sp);
+      g.nlaunch = tiles_y;
+      gram_f64_dma_kernel<true><<<dim3(unsigned(sp.nsplit) * unsigned(tiles_y)), NTH, 0, st>>>(g, sp);
     } else {
       g.sel = 0;
       g.nlaunch = g.ntiles;
