@@ -411,8 +411,8 @@ def main():
             "unit": "TFLOP/s",
             "frac": round(gram_tf / FP64_PEAK, 4),
             "traffic": measured_traffic(),
-            "traffic_unit": "bytes per launch (HBM read + write, rocprofv3 counters)",
-            "kernel": "gram_f64_dma_kernel (+ its split reduction)",
+            "traffic_unit": "bytes per Gram call (HBM read + write of both launches, rocprofv3 counters)",
+            "kernel": "gram_f64_dma_kernel: launch below the diagonal + diagonal launch (+ the split reduction)",
             "per_launch_flops": gram_flops,
         },
         "preprocess_GBps": round(n * k * 8 / (phases["preprocess"] * 1e-3) / 1e9, 1),
