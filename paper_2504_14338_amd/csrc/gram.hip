@@ -10,7 +10,10 @@
 //    One workgroup = (tile, split); the grid holds ~8k workgroups so the 256
 //    CUs see ~15 rounds of work and a small tail.
 //  * Workgroup: 4 waves in a 2 x 2 arrangement, each owning a 64 x 64
-//    sub-tile = 4 x 4 blocks of v_mfma_f64_16x16x4 (FP64 accumulate).
+//    sub-tile = 4 x 4 blocks of v_mfma_f64_16x16x4 (FP64 accumulate).  The
+//    symmetric Gram runs the tiles below the diagonal in one launch (whole
+//    rounds of resident workgroups) and the diagonal tiles in a second one,
+//    where each wave computes 9 of the 36 lower 16 x 16 blocks.
 //  * Main kernel (rows 16-byte aligned): panel rows go from HBM straight into
 //    LDS with buffer loads in LDS-DMA mode (no register staging).  A buffer
 //    descriptor spans one row, so columns past the row and rows past the split
