@@ -339,6 +339,16 @@ __device__ __forceinline__ int64_t rhs_offset(const RhsMap& m, int g, int64_t n,
 // Barriers: before each diagonal product (its rows were updated by every
 // wave), after it (before Y_J overwrites X_J) and before the first update
 // that reads Y_J; the updates from one J write disjoint rows.
+// Where the backward solve also writes its result transposed into the
+// operators: O[i][r + q] = X_q[q][i] for the pair of each right-hand-side
+// matrix (batch entry e -> pair border[e]); O == nullptr: no write.
+struct OWrite {
+  const int* border;  // batch entry -> pair
+  double* O;          // group base, pair stride r * d
+  int64_t d;          // columns of an operator
+  int r;
+};
+
 constexpr int LMAX = 4;       // diagonal blocks per leaf
 constexpr int CW = 32;        // right-hand-side columns per workgroup
 constexpr int CWP = CW + 2;   // LDS pitch of the slab
@@ -347,7 +357,7 @@ template <bool TRANS>
 __global__ __launch_bounds__(256, 2) void trsm_leaf_kernel(const double* __restrict__ L, int64_t n,
                                                            const double* __restrict__ Linv,
                                                            const double* __restrict__ X, double* __restrict__ Y,
-                                                           RhsMap m, int64_t b0, int64_t b1) {
+                                                           RhsMap m, int64_t b0, int64_t b1, OWrite ow) {
   __shared__ double Xs[LMAX * NB][CWP];
   const int g = blockIdx.y;
   const int64_t c0 = int64_t(blockIdx.x) * CW;
@@ -463,6 +473,25 @@ __global__ __launch_bounds__(256, 2) void trsm_leaf_kernel(const double* __restr
     after_diag = (t == J);
 #pragma unroll
     for (int kk = 0; kk < NB / 4; ++kk) a_cur[kk] = a_nxt[kk];
+  }
+  if (TRANS && ow.O) {
+    // the run's solved rows (Y_J stays in Xs after its diagonal product):
+    // wave w writes columns 8 w .. 8 w + 7, lane = row within the block, so
+    // every store covers 64 consecutive q of one operator row
+    __syncthreads();
+#pragma unroll 1
+    for (int cc = 0; cc < CW / 4; ++cc) {
+      const int c = (CW / 4) * wv + cc;
+      const int64_t vcol = c0 + c;
+      const int e0 = m.e0 ? m.e0[g] : g, cnt = m.cnt ? m.cnt[g] : 1;
+      if (vcol >= int64_t(cnt) * w) break;  // columns of a wave are consecutive
+      const int p = ow.border[e0 + int(vcol / w)];
+      double* Orow = ow.O + size_t(p) * ow.r * ow.d + (vcol % w) * ow.d + ow.r;
+      for (int J = 0; J < nbk; ++J) {
+        const int64_t q = (b0 + J) * NB + lane;
+        if (q < n) Orow[q] = Xs[J * NB + lane][c];
+      }
+    }
   }
 }
 
@@ -966,7 +995,7 @@ int cholesky_run(hipStream_t st, double* Lq, int64_t s, double* Linv, int* ufail
 // ng groups, each with at most max_cols virtual columns; block columns of kb
 // rows (a multiple of NB)
 int trsm_run(hipStream_t st, bool trans, const double* L, int64_t n, const double* Linv, double* X, double* Yout,
-             RhsMap m, int64_t max_cols, int ng, int64_t kb, int64_t kb2) {
+             RhsMap m, int64_t max_cols, int ng, int64_t kb, int64_t kb2, OWrite ow = OWrite{}) {
   const int64_t nblk = (n + NB - 1) / NB;
   const Widths W = widths(kb, kb2);
   const unsigned nslab = unsigned((max_cols + CW - 1) / CW);
@@ -977,9 +1006,9 @@ int trsm_run(hipStream_t st, bool trans, const double* L, int64_t n, const doubl
   const bool dma = trans ? dma_b : dma_b && n * n * 8 < 0x7ffffff0;
   auto leaf = [&](int64_t cb, int64_t ce) -> int {
     if (!trans)
-      trsm_leaf_kernel<false><<<dim3(nslab, unsigned(ng)), 256, 0, st>>>(L, n, Linv, X, Yout, m, cb, ce);
+      trsm_leaf_kernel<false><<<dim3(nslab, unsigned(ng)), 256, 0, st>>>(L, n, Linv, X, Yout, m, cb, ce, OWrite{});
     else
-      trsm_leaf_kernel<true><<<dim3(nslab, unsigned(ng)), 256, 0, st>>>(L, n, Linv, X, Yout, m, cb, ce);
+      trsm_leaf_kernel<true><<<dim3(nslab, unsigned(ng)), 256, 0, st>>>(L, n, Linv, X, Yout, m, cb, ce, ow);
     DOPINF_LAUNCHED();
     return DOPINF_OK;
   };
@@ -1153,8 +1182,7 @@ struct QuadArgs {
   const double* XL;     // per pair: X_l ((r+1) x r)
   const int* border;    // batch entry -> pair
   const int* pair_u;    // pair -> u within the chunk
-  double* V;            // per batch entry: v, then (other buffer) X_q
-  const double* Xq;
+  double* V;            // per batch entry: v (the solve writes X_q to another buffer)
   double* O;            // group base, pair stride r*d
   int64_t s;
   int r;
@@ -1239,37 +1267,6 @@ __global__ __launch_bounds__(256) void vq_kernel(QuadArgs a) {
       const int64_t q = q0 + 16 * wv + (lane >> 4) + 4 * e;
       if (q < s && ii < r) Vb[q * r + ii] = yv[e] - acc[b][e];
     }
-  }
-}
-
-// O[i][r + q] = X_q[q][i], transposed through LDS so that rows of O are
-// written contiguously; workgroup = (64 quadratic columns, batch entry, 64 modes)
-__global__ __launch_bounds__(256) void oq_kernel(QuadArgs a) {
-  __shared__ double T[NB][NB + 1];
-  const int bt = blockIdx.y;
-  const int p = a.border[bt];
-  if (a.pair_u[p] < 0) return;
-  const int r = a.r;
-  const int64_t s = a.s, d = ncols(r);
-  const int64_t q0 = int64_t(blockIdx.x) * NB;
-  const int i0 = int(blockIdx.z) * NB;
-  const double* Xb = a.Xq + size_t(bt) * s * r;
-  double xv[NB * NB / 256];
-#pragma unroll
-  for (int k = 0; k < NB * NB / 256; ++k) {
-    const int e = threadIdx.x + 256 * k, qq = e / NB, ii = e % NB;
-    xv[k] = Xb[(q0 + qq < s ? q0 + qq : q0) * r + (i0 + ii < r ? i0 + ii : i0)];
-  }
-#pragma unroll
-  for (int k = 0; k < NB * NB / 256; ++k) {
-    const int e = threadIdx.x + 256 * k, qq = e / NB, ii = e % NB;
-    T[ii][qq] = xv[k];
-  }
-  __syncthreads();
-  double* Op = a.O + size_t(p) * r * d;
-  for (int e = threadIdx.x; e < NB * NB; e += 256) {
-    const int ii = e / NB, qq = e % NB;
-    if (q0 + qq < s && i0 + ii < r) Op[int64_t(i0 + ii) * d + r + q0 + qq] = T[ii][qq];
   }
 }
 
@@ -1708,28 +1705,26 @@ QuadArgs quad_args(const InferPlan& P, const ChunkBufs& b, int g, int c, double*
   qa.border = m.border + size_t(c) * P.n_pairs;
   qa.pair_u = m.pair_u + size_t(c) * P.n_pairs;
   qa.V = b.V;
-  qa.Xq = b.Xq;
   qa.O = O ? O + dopinf_operator_offset(P.n_r, P.r_list.data(), P.n_pairs, g * P.n_pairs) : nullptr;
   qa.s = b.s;
   qa.r = b.geo.r;
   return qa;
 }
 
-dim3 quad_grid(const InferPlan& P, const ChunkBufs& b, int c) {
-  return dim3(unsigned((b.s + NB - 1) / NB), unsigned(P.nbc[c]), unsigned((b.geo.r + NB - 1) / NB));
-}
-
 // v = y - W X_l per pair, then L^T X_q = v with the pairs of each beta2 group
-// side by side as one right-hand side
+// side by side as one right-hand side; the solve's leaves also write X_q into
+// the quadratic columns of O (O == nullptr: X_q only)
 int chunk_quad_solve(hipStream_t st, const InferPlan& P, const ChunkBufs& b, int g, int c, int nu, Kb kb,
-                     void* ws) {
+                     double* O, void* ws) {
   const MiscPtrs m = misc_ptrs(P.L, ws, P.n_pairs);
-  const QuadArgs qa = quad_args(P, b, g, c, nullptr, ws);
+  const QuadArgs qa = quad_args(P, b, g, c, O, ws);
   vq_kernel<<<dim3(unsigned((b.s + NB - 1) / NB), unsigned(P.nbc[c]), unsigned((b.geo.r + 127) / 128)), 256, 0, st>>>(
       qa);
   DOPINF_LAUNCHED();
   const RhsMap rm{m.ue0 + size_t(c) * P.L.uc, m.ucnt + size_t(c) * P.L.uc, b.geo.r};
-  return trsm_run(st, true, b.Lq, b.s, b.Linv, b.V, b.Xq, rm, int64_t(P.npu_max[c]) * b.geo.r, nu, kb.w, kb.w2);
+  const OWrite ow{qa.border, qa.O, ncols(b.geo.r), b.geo.r};
+  return trsm_run(st, true, b.Lq, b.s, b.Linv, b.V, b.Xq, rm, int64_t(P.npu_max[c]) * b.geo.r, nu, kb.w, kb.w2,
+                  ow);
 }
 
 int infer_enqueue(hipStream_t st, const InferPlan& P, const double* Qhat, int64_t ldqh, double* O, int* status,
@@ -1766,10 +1761,7 @@ int infer_enqueue(hipStream_t st, const InferPlan& P, const double* Qhat, int64_
       rc = chunk_factor(sg, P, b, c, nu, kc, ws);
       if (!rc) rc = chunk_linear(sg, P, b, g, c, nu, kt, O, status, ws);
       if (rc || P.nbc[c] == 0) continue;
-      rc = chunk_quad_solve(sg, P, b, g, c, nu, kt, ws);
-      if (rc) continue;
-      oq_kernel<<<quad_grid(P, b, c), 256, 0, sg>>>(quad_args(P, b, g, c, O, ws));
-      if (hipGetLastError() != hipSuccess) rc = fail(DOPINF_E_HIP, "kernel launch failed (oq_kernel)");
+      rc = chunk_quad_solve(sg, P, b, g, c, nu, kt, O, ws);
     }
     if (forked) {
       // join even after an error, so that no forked work is left outside
@@ -1850,7 +1842,7 @@ int infer_autotune(hipStream_t st, const InferPlan& P, const double* Qhat, int64
     for (int ci = 0; ci < kNumKbCand && !rc; ++ci) {
       float t = 0.f;
       const Kb kb{kKbCand[ci][0], kKbCand[ci][1]};
-      rc = time_min(st, e0, e1, [&] { return chunk_quad_solve(st, P, b, g, 0, nu, kb, ws); }, t);
+      rc = time_min(st, e0, e1, [&] { return chunk_quad_solve(st, P, b, g, 0, nu, kb, nullptr, ws); }, t);
       if (tg) tg[kNumKbCand + ci] = t;
       if (!rc && (best < 0 || t < best_t)) {
         best = ci;
