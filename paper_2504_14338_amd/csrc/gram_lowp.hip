@@ -179,6 +179,8 @@ struct MmaArgs {
   int64_t nb;     // row blocks
   int64_t kp;
   int ntiles, nsplit, xcd_map;
+  int sel;        // tiles of the launch: 0 the whole lower triangle, 1 below the diagonal, 2 on it
+  int nlaunch;    // tiles per split in the launch
   int64_t blocks_per_split;
   const float* pf;
   const unsigned short* p0;
@@ -219,7 +221,44 @@ struct PackedGeom {
   static constexpr int NSTAGE = 2;                  // LDS stages (loads of one in flight)
 };
 
-template <int ALGO, bool DIAG>
+// Blocks of 16 x 16 that wave w (0..3) computes in a diagonal tile of the
+// FP32 form: block columns w (block rows w..7) and 7 - w (block rows
+// 7 - w..7), 9 blocks that cover the tile's 36 lower blocks over the four
+// waves; block p sits in accumulator p (acc[p / 4][p % 4]).
+__device__ __forceinline__ void diag_block(int w, int p, int& br, int& bc) {
+  const bool first = p < 8 - w;
+  br = first ? w + p : p - 1;
+  bc = first ? w : 7 - w;
+}
+
+// One FP32 stage of wave W of a diagonal tile: the fragments of block rows
+// W..7 are read once and serve as A and as the two B columns (rows W and
+// 7 - W).  SA: the stage's panel, (o0, o1): the lane's two 16-byte slots.
+template <int W, int COLB>
+__device__ __forceinline__ void diag_stage_f32(const unsigned char* SA, int cm, int o0, int o1, flt4 (&acc)[4][4]) {
+  flt4 f[8 - W][2];
+#pragma unroll
+  for (int i = 0; i < 8 - W; ++i) {
+    const unsigned char* colp = SA + ((W + i) * 16 + cm) * COLB;
+    f[i][0] = *reinterpret_cast<const flt4*>(colp + o0);
+    f[i][1] = *reinterpret_cast<const flt4*>(colp + o1);
+  }
+#pragma unroll
+  for (int kk = 0; kk < KB / 4; ++kk) {
+#pragma unroll
+    for (int p = 0; p < 8 - W; ++p)  // (W + p, W)
+      acc[p >> 2][p & 3] =
+          __builtin_amdgcn_mfma_f32_16x16x4f32(f[p][kk >> 2][kk & 3], f[0][kk >> 2][kk & 3], acc[p >> 2][p & 3], 0, 0, 0);
+#pragma unroll
+    for (int q = 0; q <= W; ++q) {  // (7 - W + q, 7 - W), p = 8 - W + q
+      const int p = 8 - W + q;
+      acc[p >> 2][p & 3] = __builtin_amdgcn_mfma_f32_16x16x4f32(f[7 - 2 * W + q][kk >> 2][kk & 3],
+                                                                f[7 - 2 * W][kk >> 2][kk & 3], acc[p >> 2][p & 3], 0, 0, 0);
+    }
+  }
+}
+
+template <int ALGO, bool DIAG, bool D9 = false>
 __device__ __forceinline__ void packed_tile(const MmaArgs& g, int64_t b_lo, int64_t nst, int64_t a0, int64_t c0,
                                             unsigned char* smem, flt4 (&acc)[4][4], double (&acc64)[4][4][4]) {
   using Gm = PackedGeom<ALGO>;
@@ -278,7 +317,16 @@ __device__ __forceinline__ void packed_tile(const MmaArgs& g, int64_t b_lo, int6
     const unsigned char* S = smem + (st % NS) * Gm::STAGE;
     const unsigned char* SA = S;
     const unsigned char* SB = DIAG ? S : S + NPART * Gm::PANEL;
-    if constexpr (ALGO == 0) {
+    if constexpr (ALGO == 0 && D9) {
+      const int h = (cm >> 1) & 7;
+      const int o0 = 16 * ((2 * gq) ^ h), o1 = 16 * ((2 * gq + 1) ^ h);
+      switch (w) {  // w is wave-uniform: each wave runs the schedule of its own w
+        case 0: diag_stage_f32<0, Gm::COLB>(SA, cm, o0, o1, acc); break;
+        case 1: diag_stage_f32<1, Gm::COLB>(SA, cm, o0, o1, acc); break;
+        case 2: diag_stage_f32<2, Gm::COLB>(SA, cm, o0, o1, acc); break;
+        default: diag_stage_f32<3, Gm::COLB>(SA, cm, o0, o1, acc); break;
+      }
+    } else if constexpr (ALGO == 0) {
       // lane group gq holds rows gq, gq+4, ..., gq+28 of its column in slots 2gq, 2gq+1
       const int h = (cm >> 1) & 7;
       const int o0 = 16 * ((2 * gq) ^ h), o1 = 16 * ((2 * gq + 1) ^ h);
@@ -343,20 +391,34 @@ __device__ __forceinline__ void packed_tile(const MmaArgs& g, int64_t b_lo, int6
   }
 }
 
-template <int ALGO>
+// sel 0: every lower-triangle tile, diagonal ones in the quadrant layout.
+// The FP32 form splits the triangle like the FP64 Gram: the tiles below the
+// diagonal (sel 1) fill whole rounds of resident workgroups, and the
+// diagonal tiles (sel 2, D9) take a launch of their own in which each wave
+// computes only 9 of the 36 lower 16 x 16 blocks.
+template <int ALGO, bool D9 = false>
 __global__ __launch_bounds__(NTH, ALGO == 2 ? 1 : 2) void gram_packed_kernel(MmaArgs g) {
   __shared__ __attribute__((aligned(16))) unsigned char smem[PackedGeom<ALGO>::NSTAGE * PackedGeom<ALGO>::STAGE];
   int t, s;
   {
     const int bid = blockIdx.x;
+    int tl;
     if (g.xcd_map) {
       const int xcd = bid & 7;
       const int local = bid >> 3;
-      s = (local / g.ntiles) * 8 + xcd;
-      t = local % g.ntiles;
+      s = (local / g.nlaunch) * 8 + xcd;
+      tl = local % g.nlaunch;
     } else {
-      s = bid / g.ntiles;
-      t = bid % g.ntiles;
+      s = bid / g.nlaunch;
+      tl = bid % g.nlaunch;
+    }
+    t = tl;
+    if (g.sel == 1) {  // tl-th tile strictly below the diagonal
+      int i, j;
+      gramplan::tri_coords(tl, i, j);
+      t = (i + 1) * (i + 2) / 2 + j;
+    } else if (g.sel == 2) {
+      t = tl * (tl + 1) / 2 + tl;
     }
   }
   int I, J;
@@ -376,7 +438,9 @@ __global__ __launch_bounds__(NTH, ALGO == 2 ? 1 : 2) void gram_packed_kernel(Mma
 #pragma unroll
       for (int e = 0; e < 4; ++e) acc64[i][j][e] = 0.0;
     }
-  if (I == J)
+  if (D9)
+    packed_tile<ALGO, true, true>(g, b_lo, nst, a0, c0, smem, acc, acc64);
+  else if (I == J)
     packed_tile<ALGO, true>(g, b_lo, nst, a0, c0, smem, acc, acc64);
   else
     packed_tile<ALGO, false>(g, b_lo, nst, a0, c0, smem, acc, acc64);
@@ -385,6 +449,17 @@ __global__ __launch_bounds__(NTH, ALGO == 2 ? 1 : 2) void gram_packed_kernel(Mma
   const int w = threadIdx.x >> 6;
   const int wm = w >> 1, wn = w & 1;
   double* out = g.part + (size_t(s) * g.ntiles + t) * (BT * BT);
+  if (D9) {  // the diagonal tile's lower blocks only (the reduction reads nothing above)
+#pragma unroll
+    for (int p = 0; p < 9; ++p) {
+      int br, bc;
+      diag_block(w, p, br, bc);
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        out[(br * 16 + out_row(lane, e)) * BT + bc * 16 + (lane & 15)] = acc64[p >> 2][p & 3][e];
+    }
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -487,9 +562,20 @@ int gram_lowp(hipStream_t st, int algo, const float* Q, int64_t n, int64_t k, in
   g.p2 = pa.p2;
   g.part = reinterpret_cast<double*>(base + p.pack_bytes);
   dim3 grid(unsigned(p.nsplit) * unsigned(p.ntiles));
-  if (algo == DOPINF_GRAM_NATIVE)
-    gram_packed_kernel<0><<<grid, NTH, 0, st>>>(g);
-  else if (algo == DOPINF_GRAM_BF16X3)
+  g.sel = 0;
+  g.nlaunch = p.ntiles;
+  if (algo == DOPINF_GRAM_NATIVE) {
+    const int noff = p.T * (p.T - 1) / 2;
+    if (noff > 0) {
+      g.sel = 1;
+      g.nlaunch = noff;
+      gram_packed_kernel<0><<<dim3(unsigned(p.nsplit) * unsigned(noff)), NTH, 0, st>>>(g);
+      DOPINF_LAUNCHED();
+    }
+    g.sel = 2;
+    g.nlaunch = p.T;
+    gram_packed_kernel<0, true><<<dim3(unsigned(p.nsplit) * unsigned(p.T)), NTH, 0, st>>>(g);
+  } else if (algo == DOPINF_GRAM_BF16X3)
     gram_packed_kernel<1><<<grid, NTH, 0, st>>>(g);
   else
     gram_packed_kernel<2><<<grid, NTH, 0, st>>>(g);
