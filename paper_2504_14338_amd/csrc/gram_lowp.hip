@@ -65,19 +65,13 @@ struct PackArgs {
   unsigned short* p2;     // lo (x6)
 };
 
-// Place of row rr of a 32-row block inside column cc of the packed layout.
-// FP32: the four rows {g, g+4, ..., g+28} of k-step lane group g become
-// positions 8g..8g+7; the eight 16-byte slots of the column are XORed with
-// (cc >> 1) & 7.  bfloat16: the four 16-byte slots of eight rows are XORed
-// with (cc >> 2) & 3.  Sixteen consecutive columns reading the same logical
-// slot then hit sixteen different 16-byte bank groups.
-__host__ __device__ inline int pos_f32(int rr, int cc) {
-  const int p = (rr & 3) * 8 + (rr >> 2);
-  return (((p >> 2) ^ ((cc >> 1) & 7)) << 2) | (p & 3);
-}
-__host__ __device__ inline int pos_b16(int rr, int cc) {
-  return (((rr >> 3) ^ ((cc >> 2) & 3)) << 3) | (rr & 7);
-}
+// The packed layout of a 32-row block in column cc.  FP32: the rows
+// {g, g+4, ..., g+28} of k-step lane group g take positions 8g..8g+7, and
+// the column's eight 16-byte slots are XORed with (cc >> 1) & 7 (row rr sits
+// at position p = 8 (rr & 3) + (rr >> 2), slot (p >> 2) ^ ((cc >> 1) & 7)).
+// bfloat16: rows 8s..8s+7 fill 16-byte slot s, XORed with (cc >> 2) & 3.
+// Sixteen consecutive columns reading the same logical slot then hit sixteen
+// different 16-byte bank groups.
 
 // One workgroup packs a 32-row block x 128 columns: reads rows (coalesced,
 // all 16 loads of a thread in flight together), transforms with the block's
@@ -141,7 +135,7 @@ __global__ __launch_bounds__(256) void pack_kernel(PackArgs a) {
   }
   __syncthreads();
   if (a.algo == 0) {
-    // slot g of column c holds rows (g >> 1) + 4 j + 16 (g & 1), j = 0..3 (pos_f32)
+    // slot g of column c holds rows (g >> 1) + 4 j + 16 (g & 1), j = 0..3 (the FP32 layout above)
 #pragma unroll
     for (int i = 0; i < BT * 8 / 256; ++i) {
       const int t = tid + 256 * i, cw = t >> 3, g = t & 7;
@@ -152,7 +146,7 @@ __global__ __launch_bounds__(256) void pack_kernel(PackArgs a) {
       *reinterpret_cast<flt4*>(a.pf + o) = x;
     }
   } else {
-    // slot g of column c holds rows 8 g .. 8 g + 7 (pos_b16)
+    // slot g of column c holds rows 8 g .. 8 g + 7 (the bfloat16 layout above)
 #pragma unroll
     for (int i = 0; i < BT * 4 / 256; ++i) {
       const int t = tid + 256 * i, cw = t >> 2, g = t & 3;
