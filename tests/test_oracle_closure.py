@@ -107,3 +107,98 @@ def test_fit_reduces_loss():
     p0 = rng.standard_normal(cl.n_params(r)) * 0.05
     p, norms, log = cl.fit(p0, X, Y, r, epochs=20, batch=64, lr=3e-3)
     assert log[-1] < 0.5 * log[0]
+
+
+def test_standardization_population_std_and_zero_variance():
+    # column 0: values 1, 3, 5 -> mean 3, population variance (4 + 0 + 4) / 3;
+    # column 1 is constant -> its deviation counts as 1 (a sample deviation
+    # would give variance 8 / 2 = 4)
+    X = np.array([[1.0, 5.0], [3.0, 5.0], [5.0, 5.0]])
+    Y = np.array([[0.0, -2.0], [0.0, 2.0], [3.0, 0.0]])
+    mx, sx, my, sy = cl.standardization(X, Y)
+    assert mx.tolist() == [3.0, 5.0]
+    assert sx[0] == pytest.approx(math.sqrt(8.0 / 3.0), rel=1e-15) and sx[1] == 1.0
+    assert my.tolist() == [1.0, 0.0]
+    # Y column 0: deviations -1, -1, 2 -> variance 6 / 3 = 2; column 1: 8 / 3
+    assert sy[0] == pytest.approx(math.sqrt(2.0), rel=1e-15)
+    assert sy[1] == pytest.approx(math.sqrt(8.0 / 3.0), rel=1e-15)
+
+
+def test_adam_bias_correction_constant_gradient():
+    # with a constant gradient g the bias-corrected moments are exactly g and
+    # g^2 at every step, so step t moves by lr * g / (|g| + eps): after t steps
+    # p = -t lr sign(g) |g| / (|g| + eps).  Without the correction the first
+    # steps would be (1 - b1^t) / sqrt(1 - b2^t) times as long (0.1 / 0.0316).
+    lr, b1, b2, eps = 1e-2, 0.9, 0.999, 1e-8
+    g = np.array([0.5, -3.0])
+    p, m, v = np.zeros(2), np.zeros(2), np.zeros(2)
+    for t in (1, 2, 3):
+        p, m, v = cl.adam_step(p, g, m, v, t, lr, b1, b2, eps)
+        assert np.allclose(p, -t * lr * g / (np.abs(g) + eps), rtol=1e-12, atol=0)
+        assert np.allclose(m, (1 - 0.9 ** t) * g, rtol=1e-13)
+
+
+def test_adam_second_step_hand_values():
+    # g1 = 1, g2 = -1: m1 = 0.1, v1 = 0.001; m2 = 0.09 - 0.1 = -0.01,
+    # v2 = 0.000999 + 0.001 = 0.001999; bias corrections 1 - 0.81 = 0.19 and
+    # 1 - 0.998001 = 0.001999, so mhat2 = -1/19 and vhat2 = 1 exactly:
+    # p2 = -lr / (1 + eps) + (lr / 19) / (1 + eps)
+    lr, eps = 1e-3, 1e-8
+    p, m, v = cl.adam_step(np.zeros(1), np.ones(1), np.zeros(1), np.zeros(1), 1, lr, 0.9, 0.999, eps)
+    assert p[0] == pytest.approx(-lr / (1 + eps), rel=1e-14)
+    p, m, v = cl.adam_step(p, -np.ones(1), m, v, 2, lr, 0.9, 0.999, eps)
+    assert m[0] == pytest.approx(-0.01, rel=1e-13) and v[0] == pytest.approx(0.001999, rel=1e-13)
+    assert p[0] == pytest.approx(-lr / (1 + eps) + (lr / 19.0) / (1 + eps), rel=1e-11)
+
+
+def _fit_data(seed=4, r=3, N=40):
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((N, r)) * np.array([2.0, 0.5, 1.0]) + 1.0
+    Y = np.tanh(X @ rng.standard_normal((r, r))) * 0.2 - 0.1
+    p0 = (rng.standard_normal(cl.n_params(r)) * 0.05).astype(np.float32).astype(np.float64)
+    return X, Y, p0
+
+
+def test_fit_with_zero_rate_keeps_weights_and_logs_the_mean_loss():
+    r = 3
+    X, Y, p0 = _fit_data(r=r)
+    p, norms, log = cl.fit(p0, X, Y, r, epochs=3, batch=16, lr=0.0)
+    assert np.array_equal(p, p0)
+    mx, sx, my, sy = norms
+    full, _ = cl.loss_and_grad(p0, (X - mx) / sx, (Y - my) / sy, r)
+    # batches of 16, 16, 8 rows: the size-weighted mean of batch means is the
+    # mean over all rows
+    assert np.allclose(log, full, rtol=1e-12, atol=0)
+
+
+def test_fit_one_full_batch_epoch_is_one_adam_step():
+    r, lr = 3, 1e-2
+    X, Y, p0 = _fit_data(seed=5, r=r, N=24)
+    p, norms, log = cl.fit(p0, X, Y, r, epochs=1, batch=X.shape[0], lr=lr)
+    mx, sx, my, sy = norms
+    # the full-batch gradient does not depend on the visiting order (the
+    # gradient itself is pinned by central differences above)
+    _, g = cl.loss_and_grad(p0, (X - mx) / sx, (Y - my) / sy, r)
+    exp, _, _ = cl.adam_step(p0, g, np.zeros_like(p0), np.zeros_like(p0), 1, lr, 0.9, 0.999, 1e-8)
+    exp = exp.astype(np.float32).astype(np.float64)
+    # equal up to one float32 rounding step of the master weights
+    assert np.max(np.abs(p - exp) / np.maximum(np.abs(exp), 1e-30)) <= 2.0 ** -23
+    # and every weight moved by lr |g| / (|g| + eps) (first Adam step), up to
+    # the float32 rounding of the master weight
+    moved = np.abs(p - p0)
+    tol = 2.0 ** -23 * (np.abs(p0) + lr)
+    assert np.all(np.abs(moved - lr * np.abs(g) / (np.abs(g) + 1e-8)) <= tol)
+
+
+def test_closure_eval_constant_output_unstandardizes():
+    # zero weights, output bias b3 = beta: g(x) = beta * s_y + m_y for every x
+    r = 3
+    p = np.zeros(cl.n_params(r))
+    beta = np.array([0.5, -1.0, 2.0])
+    p[-r:] = beta
+    norms = (np.array([1.0, 2.0, 3.0]), np.array([0.5, 4.0, 1.0]),
+             np.array([10.0, -20.0, 0.25]), np.array([3.0, 0.5, 8.0]))
+    X = np.random.default_rng(6).standard_normal((7, r))
+    G = cl.closure_eval(p, norms, X, r)
+    exp = beta * norms[3] + norms[2]
+    assert np.allclose(G, np.broadcast_to(exp, G.shape), rtol=1e-15, atol=0)

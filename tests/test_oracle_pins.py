@@ -161,6 +161,26 @@ def test_reduce_rejects_nonpositive_lambda():
         orc.reduce_basis_free(np.array([2.0, 0.0]), np.eye(2), 2)
 
 
+def test_reduce_rank_threshold_is_rounding_level_of_the_spectrum():
+    # the threshold is k u lambda_1 with u = 2^-52: at it, rejected; above, kept
+    k = 3
+    thr = k * 2.0 ** -52
+    with pytest.raises(ValueError):
+        orc.reduce_basis_free(np.array([1.0, thr, 0.0]), np.eye(3), 2)
+    Tr, Qh = orc.reduce_basis_free(np.array([1.0, 1.5 * thr, 0.0]), np.eye(3), 2)
+    assert Qh.shape == (2, 3)
+    # an exactly rank-2 Q: the third eigenvalue of D = Q^T Q is zero in exact
+    # arithmetic and rounding-level in float64, so r = 3 must be refused
+    # (a test of lambda_r > 0 alone would accept it about half the time)
+    rng = np.random.default_rng(12)
+    Q = rng.standard_normal((40, 2)) @ rng.standard_normal((2, 5))
+    lam, U = orc.eig_desc(orc.gram(Q))
+    assert abs(lam[2]) <= 5 * 2.0 ** -52 * lam[0]
+    orc.reduce_basis_free(lam, U, 2)
+    with pytest.raises(ValueError):
+        orc.reduce_basis_free(lam, U, 3)
+
+
 # ---------------------------------------------------------------- step IV ----
 
 def test_quad_features_are_kron_subset():
