@@ -202,6 +202,29 @@ int dopinf_rollout(void* stream, int n_r, const int* r_list_h, int n_pairs,
                    double* train_err, double* growth, int* outcome, int* best,
                    void* ws, size_t ws_bytes);
 
+/* ---- Allocation-free rollout ---------------------------------------------
+ * For callers that cannot allocate device memory or bring a workspace: code
+ * under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  dopinf_rollout_noalloc takes the arguments and gives the
+ * results of dopinf_rollout (the same kernels), but its scratch is a fixed
+ * array in the library's device memory, one copy per GPU, held until the
+ * process ends: dopinf_rollout_noalloc_max_bytes() bytes (4 MiB).  A call
+ * whose dopinf_rollout_workspace size exceeds that returns
+ * DOPINF_E_WORKSPACE with nothing enqueued.  The call allocates nothing and
+ * calls no allocating routine; the first call with a device current looks up
+ * that device's copy of the array.  Every call on one GPU uses the same
+ * array, whatever its stream: calls that overlap on one GPU (concurrent
+ * streams, or host threads) race and give undefined results; order them on
+ * one stream or with events. */
+size_t dopinf_rollout_noalloc_max_bytes(void);
+int dopinf_rollout_noalloc(void* stream, int n_r, const int* r_list_h,
+                           int n_pairs, const double* O, const double* Qhat,
+                           int64_t ldqh, int64_t k_train, int n_states,
+                           double max_growth, unsigned flags,
+                           const int* solve_status, double* traj,
+                           double* train_err, double* growth, int* outcome,
+                           int* best);
+
 /* ---- Tuned launch parameters and the autotuner (batched form) ------------
  * The regularization sweep of Sec. 3.5 (every (r, beta1, beta2) of a grid)
  * factors G_qq + beta2 I (s x s, s = r(r+1)/2) once per distinct beta2 with

@@ -17,7 +17,7 @@ __all__ = [
     "GRAM_NATIVE", "GRAM_BF16X3", "GRAM_BF16X6", "ITEM_PASS", "ITEM_NONFINITE",
     "ITEM_GROWTH", "ITEM_SOLVE", "ITEM_TIMEOUT", "preprocess", "gram", "cross_gram",
     "reduce", "infer", "operator_offset", "rollout", "traj_offset",
-    "n_quad", "lib_path", "closure_param_count", "rom_residuals", "closure_fit", "closure_norms",
+    "n_quad", "lib_path", "rollout_noalloc", "rollout_noalloc_max_bytes", "closure_param_count", "rom_residuals", "closure_fit", "closure_norms",
     "closure_grad", "closure_eval", "closure_rollout", "TUNE_CHOL_KB", "tune_set", "tune_get",
     "autotune_candidates", "autotune_infer", "Sweep", "TUNE_TRSM_KB", "TUNE_CHOL_KB2", "TUNE_TRSM_KB2",
 ]
@@ -69,6 +69,9 @@ _SIGS = {
     "dopinf_rollout_workspace": ([_i32, _vp, _i32, _i64], _sz),
     "dopinf_rollout": ([_vp, _i32, _vp, _i32, _vp, _vp, _i64, _i64, _i32, _f64, _u32, _vp, _vp, _vp, _vp, _vp, _vp,
                         _vp, _sz], _i32),
+    "dopinf_rollout_noalloc_max_bytes": ([], _sz),
+    "dopinf_rollout_noalloc": ([_vp, _i32, _vp, _i32, _vp, _vp, _i64, _i64, _i32, _f64, _u32, _vp, _vp, _vp, _vp, _vp,
+                                _vp], _i32),
     "dopinf_tune_set": ([_i32, _i64, _i32], _i32),
     "dopinf_tune_get": ([_i32, _i64], _i32),
     "dopinf_autotune_candidates": ([_i32, _vp, _i32], _i32),
@@ -344,6 +347,36 @@ def rollout(O, Qhat, r_list, n_pairs, n_states, k_train=None, max_growth=1.2, so
             views.append(row)
         out["traj_views"] = views
     return out
+
+
+def rollout_noalloc(O, Qhat, r_list, n_pairs, n_states, k_train=None, max_growth=1.2, solve_status=None,
+                    full=False, one_wg=False, out=None):
+    """dopinf_rollout_noalloc: rollout() with the library's fixed scratch
+    instead of a workspace.  `out` (optional) holds preallocated result
+    tensors (keys train_err, growth, outcome, best; traj is not kept), so a
+    loop can run without any allocation."""
+    torch = _torch()
+    lib = load()
+    dev = O.device
+    rl, rlp = _host_i32(r_list)
+    n_items = len(rl) * n_pairs
+    if k_train is None:
+        k_train = Qhat.shape[1]
+    if out is None:
+        out = {"train_err": torch.empty(n_items, dtype=torch.float64, device=dev),
+               "growth": torch.empty(n_items, dtype=torch.float64, device=dev),
+               "outcome": torch.empty(n_items, dtype=torch.int32, device=dev),
+               "best": torch.empty(len(rl), dtype=torch.int32, device=dev)}
+    _check(lib.dopinf_rollout_noalloc(_stream(dev), len(rl), rlp, n_pairs, _ptr(O), _ptr(Qhat),
+                                      _rowmajor(Qhat, "Qhat"), k_train, n_states, float(max_growth),
+                                      (ROLLOUT_FULL if full else 0) | (ROLLOUT_ONE_WG if one_wg else 0),
+                                      _ptr(solve_status), None, _ptr(out["train_err"]), _ptr(out["growth"]),
+                                      _ptr(out["outcome"]), _ptr(out["best"])))
+    return out
+
+
+def rollout_noalloc_max_bytes():
+    return int(load().dopinf_rollout_noalloc_max_bytes())
 
 
 # ------------------------------------------ tuning and the captured sweep ---

@@ -22,6 +22,8 @@
 // a running maximum, so crossing the bound (or meeting a non-finite value) is
 // final and the selection is unchanged.  Team members score the same state
 // with the same code and so take the same decision without talking.
+#include <mutex>
+
 #include "common.hpp"
 #include "xwg_sync.hpp"
 
@@ -485,22 +487,30 @@ extern "C" size_t dopinf_rollout_workspace(int n_r, const int* r_list_h, int n_p
   return c.used;
 }
 
-extern "C" int dopinf_rollout(void* stream, int n_r, const int* r_list_h, int n_pairs, const double* O,
-                              const double* Qhat, int64_t ldqh, int64_t k_train, int n_states, double max_growth,
-                              unsigned flags, const int* solve_status, double* traj, double* train_err,
-                              double* growth, int* outcome, int* best, void* ws, size_t ws_bytes) {
+namespace dopinf {
+namespace {
+
+int check_rollout_args(int n_r, const int* r_list_h, int n_pairs, const double* O, const double* Qhat,
+                       int64_t ldqh, int64_t k_train, int n_states, double max_growth, unsigned flags,
+                       const double* train_err, const double* growth, const int* outcome, const int* best) {
   DOPINF_REQUIRE(O && Qhat && train_err && growth && outcome && best && r_list_h, "NULL argument");
   DOPINF_REQUIRE(n_r >= 1 && n_pairs >= 1 && n_states >= 1, "need n_r, n_pairs, n_states >= 1");
   DOPINF_REQUIRE(k_train >= 1 && ldqh >= k_train, "need k_train >= 1 and ldqh >= k_train");
   DOPINF_REQUIRE(max_growth > 0.0, "max_growth must be > 0");
   DOPINF_REQUIRE((flags & ~(DOPINF_ROLLOUT_FULL | DOPINF_ROLLOUT_ONE_WG)) == 0, "unknown flag bits");
   for (int g = 0; g < n_r; ++g) DOPINF_REQUIRE(r_list_h[g] >= 1 && r_list_h[g] <= 512, "r must be in [1, 512]");
-  const size_t need = dopinf_rollout_workspace(n_r, r_list_h, n_pairs, k_train);
-  if (!ws || ws_bytes < need) return fail(DOPINF_E_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+  return DOPINF_OK;
+}
+
+// The launches of a rollout call on a checked argument set, with its scratch
+// (dopinf_rollout_workspace bytes) at `ws`.
+int rollout_launch(hipStream_t st, int n_r, const int* r_list_h, int n_pairs, const double* O,
+                   const double* Qhat, int64_t ldqh, int64_t k_train, int n_states, double max_growth,
+                   unsigned flags, const int* solve_status, double* traj, double* train_err, double* growth,
+                   int* outcome, int* best, void* ws, size_t ws_bytes) {
   int dev = 0, maxlds = 0;
   DOPINF_HIP(hipGetDevice(&dev));
   DOPINF_HIP(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-  hipStream_t st = static_cast<hipStream_t>(stream);
   Carver c(ws, ws_bytes);
   for (int g = 0; g < n_r; ++g) {
     const int r = r_list_h[g];
@@ -565,4 +575,69 @@ extern "C" int dopinf_rollout(void* stream, int n_r, const int* r_list_h, int n_
   select_kernel<<<n_r, 64, 0, st>>>(train_err, outcome, n_pairs, best);
   DOPINF_LAUNCHED();
   return DOPINF_OK;
+}
+
+// Scratch of the allocation-free rollout: one copy per GPU, alive until the
+// process ends.  Host code never passes `scratch` itself to a kernel (on the
+// host it names a stand-in, not device memory); it passes the device address
+// that hipGetSymbolAddress returns for the current device.
+constexpr size_t kRolloutScratchBytes = size_t(4) << 20;
+__device__ __align__(256) unsigned char scratch[kRolloutScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device, looked up on the
+// first call made with that device current.
+int scratch_address(void** out) {
+  int dev = 0;
+  DOPINF_HIP(hipGetDevice(&dev));
+  DOPINF_REQUIRE(dev >= 0 && dev < kMaxDevices, "device index %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    DOPINF_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    DOPINF_REQUIRE(p != nullptr, "no device address for the rollout scratch");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return DOPINF_OK;
+}
+
+}  // namespace
+}  // namespace dopinf
+
+extern "C" int dopinf_rollout(void* stream, int n_r, const int* r_list_h, int n_pairs, const double* O,
+                              const double* Qhat, int64_t ldqh, int64_t k_train, int n_states, double max_growth,
+                              unsigned flags, const int* solve_status, double* traj, double* train_err,
+                              double* growth, int* outcome, int* best, void* ws, size_t ws_bytes) {
+  int rc = check_rollout_args(n_r, r_list_h, n_pairs, O, Qhat, ldqh, k_train, n_states, max_growth, flags, train_err,
+                              growth, outcome, best);
+  if (rc) return rc;
+  const size_t need = dopinf_rollout_workspace(n_r, r_list_h, n_pairs, k_train);
+  if (!ws || ws_bytes < need) return fail(DOPINF_E_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+  return rollout_launch(static_cast<hipStream_t>(stream), n_r, r_list_h, n_pairs, O, Qhat, ldqh, k_train, n_states,
+                        max_growth, flags, solve_status, traj, train_err, growth, outcome, best, ws, ws_bytes);
+}
+
+extern "C" size_t dopinf_rollout_noalloc_max_bytes(void) { return dopinf::kRolloutScratchBytes; }
+
+extern "C" int dopinf_rollout_noalloc(void* stream, int n_r, const int* r_list_h, int n_pairs, const double* O,
+                                      const double* Qhat, int64_t ldqh, int64_t k_train, int n_states,
+                                      double max_growth, unsigned flags, const int* solve_status, double* traj,
+                                      double* train_err, double* growth, int* outcome, int* best) {
+  int rc = check_rollout_args(n_r, r_list_h, n_pairs, O, Qhat, ldqh, k_train, n_states, max_growth, flags, train_err,
+                              growth, outcome, best);
+  if (rc) return rc;
+  const size_t need = dopinf_rollout_workspace(n_r, r_list_h, n_pairs, k_train);
+  if (need > dopinf::kRolloutScratchBytes)
+    return fail(DOPINF_E_WORKSPACE, "rollout needs %zu bytes of scratch, the allocation-free form holds %zu", need,
+                dopinf::kRolloutScratchBytes);
+  void* ws = nullptr;
+  rc = dopinf::scratch_address(&ws);
+  if (rc) return rc;
+  return rollout_launch(static_cast<hipStream_t>(stream), n_r, r_list_h, n_pairs, O, Qhat, ldqh, k_train, n_states,
+                        max_growth, flags, solve_status, traj, train_err, growth, outcome, best, ws,
+                        dopinf::kRolloutScratchBytes);
 }
