@@ -23,3 +23,4 @@ import numpy as np
 
 from .pipeline import *  # noqa: F401,F403
 from .pipeline import __all__  # noqa: F401
+from . import continuous  # noqa: F401

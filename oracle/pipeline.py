@@ -13,6 +13,7 @@ __all__ = [
     "quad_features", "quad_pairs", "n_quad", "opinf_data", "regularizer",
     "solve_operators", "split_operators", "rollout", "train_error",
     "growth_ratio", "score", "select_best", "sweep", "pipeline",
+    "lift", "LIFT_COPY", "LIFT_PRODUCT", "LIFT_RECIPROCAL", "basis_rows", "postprocess",
 ]
 
 
@@ -73,6 +74,42 @@ def preprocess(Q, var_rows, center=True, scale=True):
     s_rows = np.repeat(s, np.diff(np.asarray(var_rows)))
     Qs = apply_statistics(Q, mu, s_rows)
     return mu, s, Qs, zr
+
+
+LIFT_COPY, LIFT_PRODUCT, LIFT_RECIPROCAL = 0, 1, 2
+
+
+def lift(Q, n_cells, spec):
+    """Lifting transformation (Sec. 3.3: new variables that expose polynomial
+    structure, applied point by point before centering).
+
+    Q holds the input variables as consecutive blocks of n_cells rows (one
+    row per cell, one column per snapshot).  spec lists the output variables
+    in order, each (op, a, b): LIFT_COPY -> variable a; LIFT_PRODUCT ->
+    variable a times variable b; LIFT_RECIPROCAL -> 1 / variable a.  Returns
+    the lifted snapshots, len(spec) blocks of n_cells rows.
+    """
+    Q = np.asarray(Q, dtype=np.float64)
+    k = Q.shape[1]
+    nv = Q.shape[0] // n_cells
+    if nv * n_cells != Q.shape[0]:
+        raise ValueError("Q must hold whole blocks of n_cells rows")
+    out = np.empty((len(spec) * n_cells, k))
+    for j, (op, a, b) in enumerate(spec):
+        if not (0 <= a < nv and (op != LIFT_PRODUCT or 0 <= b < nv)):
+            raise ValueError(f"lifting output {j} names a variable outside [0, {nv})")
+        va = Q[a * n_cells:(a + 1) * n_cells, :]
+        if op == LIFT_COPY:
+            y = va.copy()
+        elif op == LIFT_PRODUCT:
+            y = va * Q[b * n_cells:(b + 1) * n_cells, :]
+        elif op == LIFT_RECIPROCAL:
+            with np.errstate(divide="ignore"):
+                y = 1.0 / va
+        else:
+            raise ValueError(f"unknown lifting op {op}")
+        out[j * n_cells:(j + 1) * n_cells, :] = y
+    return out
 
 
 # ---------------------------------------------------------------------------
@@ -323,6 +360,33 @@ def sweep(Qhat_full, r_list, beta1s, beta2s, n_states, max_growth=1.2,
                 oks.append(ok)
         out["best"].append(select_best(errs, oks))
     return out
+
+
+# ---------------------------------------------------------------------------
+# Step V (Sec. 3.6): postprocessing of the reduced solution
+# ---------------------------------------------------------------------------
+
+def basis_rows(Qs, Tr, rows):
+    """Rows of the rank-r POD basis, V_r[rows] = Qs[rows] T_r (Eq. (7) with
+    the method of snapshots: V_r = Qs T_r), from the transformed snapshots
+    Qs of Step II; the basis itself is never formed."""
+    return np.asarray(Qs)[np.asarray(rows, dtype=np.int64), :] @ Tr
+
+
+def postprocess(Q, mu, s, var_rows, Tr, rows, Qtilde):
+    """Step V: the reduced solution Qtilde (r x N) mapped back to the original
+    coordinates at the given rows (Sec. 3.6): V_r[rows] Qtilde, then the
+    inverse of Step II's transformation, x = s_v * y + mu (the listing adds
+    the temporal mean; the scale factor undoes max-abs scaling).
+
+    Returns (Vrows (m x r), prediction (m x N))."""
+    rows = np.asarray(rows, dtype=np.int64)
+    s_rows = np.repeat(np.asarray(s, dtype=np.float64), np.diff(np.asarray(var_rows)))
+    # Step II's transform of the requested rows only (row by row, as for Qs)
+    Qs_sel = apply_statistics(np.asarray(Q)[rows, :], np.asarray(mu)[rows], s_rows[rows])
+    V = basis_rows(Qs_sel, Tr, np.arange(len(rows)))
+    pred = s_rows[rows][:, None] * (V @ Qtilde) + np.asarray(mu)[rows][:, None]
+    return V, pred
 
 
 def pipeline(Q, var_rows, r, beta1, beta2, n_states, center=True, scale=True,
