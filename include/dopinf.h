@@ -81,12 +81,33 @@ const char* dopinf_version(void);
  * Q: n x k, leading dimension ldq >= k, element type `dtype`; statistics are
  * accumulated in double.  var_rows_h[0..nvars]: host array, var_rows_h[0] = 0,
  * strictly increasing, var_rows_h[nvars] = n; nvars <= DOPINF_MAX_VARS.
- * mean: n doubles; scale: nvars doubles; zero_range: nvars ints or NULL. */
+ * mean: n doubles; scale: nvars doubles; zero_range: nvars ints or NULL.
+ * info (device int, may be NULL): DOPINF_OK, or DOPINF_E_NONFINITE when Q
+ * holds a NaN or an infinity; then the means of the rows concerned are not
+ * finite, the scale of each variable concerned is NaN (with SCALE; 1
+ * without), and its zero_range entry is 0. */
 size_t dopinf_preprocess_workspace(int64_t n, int64_t k, int nvars);
 int dopinf_preprocess(void* stream, int dtype, void* Q, int64_t n, int64_t k,
                       int64_t ldq, int nvars, const int64_t* var_rows_h,
                       unsigned flags, double* mean, double* scale,
-                      int* zero_range, void* ws, size_t ws_bytes);
+                      int* zero_range, int* info, void* ws, size_t ws_bytes);
+
+/* ---- Step II: lifting transformations (Sec. 3.3) ---------------------------
+ * New variables that expose polynomial structure, formed point by point
+ * before centering.  Q holds nvars_in input variables as consecutive blocks
+ * of n_cells rows (row = one cell, k snapshots, ldq >= k).  spec_h (host,
+ * 3 n_out ints) lists the output variables in order as (op, a, b):
+ *   DOPINF_LIFT_COPY        L_j = Q_a
+ *   DOPINF_LIFT_PRODUCT     L_j = Q_a * Q_b   (elementwise)
+ *   DOPINF_LIFT_RECIPROCAL  L_j = 1 / Q_a     (IEEE: 1/0 = Inf)
+ * L: n_out blocks of n_cells rows (ldl >= k), written; must not overlap Q.
+ * n_out <= DOPINF_MAX_VARS; a, b in [0, nvars_in) (b read for PRODUCT only). */
+#define DOPINF_LIFT_COPY 0
+#define DOPINF_LIFT_PRODUCT 1
+#define DOPINF_LIFT_RECIPROCAL 2
+int dopinf_lift(void* stream, const double* Q, int64_t n_cells, int64_t k,
+                int64_t ldq, int nvars_in, int n_out, const int* spec_h,
+                double* L, int64_t ldl);
 
 /* ---- Step III: Gram matrix D = Qs^T Qs (Eq. (5)) ---------------------------
  * Qs[i,t] = (Q[i,t] - mean[i]) * (1 / scale[v(i)]) formed on load when mean
@@ -139,6 +160,25 @@ int dopinf_reduce(void* stream, const double* D, int64_t k, int64_t ldd,
                   int r_req, double tau, int r_max, int* r_out_h,
                   double* lambda, double* Tr, int64_t ldtr, double* Qhat,
                   int64_t ldqh, int* info, void* ws, size_t ws_bytes);
+
+/* Partial eigendecomposition for a prescribed r (Sec. 3.4: only the r
+ * leading eigenpairs enter Eqs. (7)-(8)).  Same outputs as dopinf_reduce with
+ * r_req = r (same sign rule, Qhat = Lambda_r^{1/2} U_r^T, T_r), except that
+ * lambda receives only the r leading eigenvalues.  Method: block subspace
+ * iteration on a block of p = min(128, max(r + 16, 2 r) rounded up to 16)
+ * vectors with shifted Cholesky QR, and Rayleigh-Ritz steps solved by the
+ * dense eigensolver; the iteration count comes from the Ritz values of a
+ * first Rayleigh-Ritz step (theta_p / theta_r)^m <= 1e-17, so the call
+ * synchronizes `stream` once.  When r does not fit the block (r > 120, or
+ * k < 64) or the spectrum decays too slowly (more than 80 iterations), the
+ * full eigensolver of dopinf_reduce runs instead.
+ * iters_h (host, may be NULL): subspace iterations used, 0 when the full
+ * eigensolver ran.  info: as for dopinf_reduce. */
+size_t dopinf_reduce_topr_workspace(int64_t k, int r);
+int dopinf_reduce_topr(void* stream, const double* D, int64_t k, int64_t ldd,
+                       int r, double* lambda, double* Tr, int64_t ldtr,
+                       double* Qhat, int64_t ldqh, int* info, int* iters_h,
+                       void* ws, size_t ws_bytes);
 
 /* ---- Step IV: regularized operator inference (Eqs. (11)-(13)) ------------
  * For every reduced size r_g in r_list_h[0..n_r) (group g uses the first r_g
@@ -202,6 +242,30 @@ int dopinf_rollout(void* stream, int n_r, const int* r_list_h, int n_pairs,
                    double* train_err, double* growth, int* outcome, int* best,
                    void* ws, size_t ws_bytes);
 
+/* ---- Step V: postprocessing of the reduced solution (Sec. 3.6) ------------
+ * The reduced solution Qtilde (r x n_out, ldqt) mapped back to the original
+ * coordinates at m selected rows, with the basis formed only at those rows
+ * (Eq. (7) with the method of snapshots, V_r = Qs T_r):
+ *   V[i, :]    = Qs[rows[i], :] T_r,  Qs = (Q - mean 1^T) / scale_v (Step II;
+ *                mean / scale may be NULL: no centering / no scaling)
+ *   pred[i, t] = scale_v(rows[i]) (V[i, :] Qtilde[:, t]) + mean[rows[i]]
+ * Q: n x k (ldq), element type dtype (F64 or F32; arithmetic in double).
+ * rows: device array of m row indices, or NULL for rows 0 .. m-1 (m <= n).
+ * Tr: k x r (ldtr), as written by dopinf_reduce.  V: m x r (ldv), written.
+ * pred: NULL (basis rows only) or m x n_out (ldp).  var_rows_h as for
+ * dopinf_preprocess (read only when scale is given).
+ * info (device int, may be NULL): DOPINF_OK, or DOPINF_E_ARG when a row
+ * index lies outside [0, n) (those rows of V and pred are NaN).
+ * No workspace; nothing is allocated. */
+int dopinf_postprocess(void* stream, int dtype, const void* Q, int64_t n,
+                       int64_t k, int64_t ldq, const double* mean,
+                       const double* scale, int nvars,
+                       const int64_t* var_rows_h, const int64_t* rows,
+                       int64_t m, const double* Tr, int64_t ldtr, int r,
+                       const double* Qtilde, int64_t ldqt, int64_t n_out,
+                       double* V, int64_t ldv, double* pred, int64_t ldp,
+                       int* info);
+
 /* ---- Allocation-free rollout ---------------------------------------------
  * For callers that cannot allocate device memory or bring a workspace: code
  * under stream capture, tight serving loops, harnesses that forbid
@@ -224,6 +288,34 @@ int dopinf_rollout_noalloc(void* stream, int n_r, const int* r_list_h,
                            const int* solve_status, double* traj,
                            double* train_err, double* growth, int* outcome,
                            int* best);
+
+/* ---- Continuous-time variant (Sec. 3.5, Eq. (10)) -------------------------
+ * dq/dt = A q + H quad(q) + c inferred from the same reduced data: the data
+ * matrix uses all k snapshots, Dhat = [Qhat^T | quad(Qhat^T) | 1] (k x d),
+ * and the right-hand side is the time derivative of Qhat by second-order
+ * finite differences at snapshot spacing dt (central inside, one-sided
+ * three-point at both ends; k >= 3).  Regularizer, solver, layout of O and
+ * status as for dopinf_infer.
+ * dopinf_rollout_continuous: as dopinf_rollout, with state t+1 one classical
+ * fourth-order Runge-Kutta step of size dt from state t (state t is scored
+ * against snapshot t); one workgroup per candidate; same workspace query. */
+size_t dopinf_infer_continuous_workspace(int64_t k, int n_r,
+                                         const int* r_list_h, int n_pairs);
+int dopinf_infer_continuous(void* stream, const double* Qhat, int64_t ldqh,
+                            int64_t k, double dt, int n_r,
+                            const int* r_list_h, int n_pairs,
+                            const double* beta1_h, const double* beta2_h,
+                            double* O, int* status, void* ws,
+                            size_t ws_bytes);
+int dopinf_rollout_continuous(void* stream, int n_r, const int* r_list_h,
+                              int n_pairs, const double* O,
+                              const double* Qhat, int64_t ldqh,
+                              int64_t k_train, int n_states, double dt,
+                              double max_growth, unsigned flags,
+                              const int* solve_status, double* traj,
+                              double* train_err, double* growth,
+                              int* outcome, int* best, void* ws,
+                              size_t ws_bytes);
 
 /* ---- Tuned launch parameters and the autotuner (batched form) ------------
  * The regularization sweep of Sec. 3.5 (every (r, beta1, beta2) of a grid)

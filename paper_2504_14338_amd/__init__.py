@@ -17,7 +17,8 @@ __all__ = [
     "GRAM_NATIVE", "GRAM_BF16X3", "GRAM_BF16X6", "ITEM_PASS", "ITEM_NONFINITE",
     "ITEM_GROWTH", "ITEM_SOLVE", "ITEM_TIMEOUT", "preprocess", "gram", "cross_gram",
     "reduce", "infer", "operator_offset", "rollout", "traj_offset",
-    "n_quad", "lib_path", "rollout_noalloc", "rollout_noalloc_max_bytes", "closure_param_count", "rom_residuals", "closure_fit", "closure_norms",
+    "n_quad", "lib_path", "rollout_noalloc", "rollout_noalloc_max_bytes", "postprocess", "reduce_topr", "lift", "infer_continuous",
+    "rollout_continuous", "LIFT_COPY", "LIFT_PRODUCT", "LIFT_RECIPROCAL", "closure_param_count", "rom_residuals", "closure_fit", "closure_norms",
     "closure_grad", "closure_eval", "closure_rollout", "TUNE_CHOL_KB", "tune_set", "tune_get",
     "autotune_candidates", "autotune_infer", "Sweep", "TUNE_TRSM_KB", "TUNE_CHOL_KB2", "TUNE_TRSM_KB2",
 ]
@@ -54,7 +55,7 @@ _SIGS = {
     "dopinf_last_error": ([], C.c_char_p),
     "dopinf_version": ([], C.c_char_p),
     "dopinf_preprocess_workspace": ([_i64, _i64, _i32], _sz),
-    "dopinf_preprocess": ([_vp, _i32, _vp, _i64, _i64, _i64, _i32, _vp, _u32, _vp, _vp, _vp, _vp, _sz], _i32),
+    "dopinf_preprocess": ([_vp, _i32, _vp, _i64, _i64, _i64, _i32, _vp, _u32, _vp, _vp, _vp, _vp, _vp, _sz], _i32),
     "dopinf_gram_workspace": ([_i32, _i32, _i64, _i64], _sz),
     "dopinf_gram": ([_vp, _i32, _i32, _vp, _i64, _i64, _i64, _vp, _vp, _i32, _vp, _vp, _i64, _vp, _sz], _i32),
     "dopinf_cross_gram_workspace": ([_i64, _i64, _i64], _sz),
@@ -62,6 +63,8 @@ _SIGS = {
                           _i32),
     "dopinf_reduce_workspace": ([_i64, _i32], _sz),
     "dopinf_reduce": ([_vp, _vp, _i64, _i64, _i32, _f64, _i32, _vp, _vp, _vp, _i64, _vp, _i64, _vp, _vp, _sz], _i32),
+    "dopinf_reduce_topr_workspace": ([_i64, _i32], _sz),
+    "dopinf_reduce_topr": ([_vp, _vp, _i64, _i64, _i32, _vp, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _sz], _i32),
     "dopinf_operator_offset": ([_i32, _vp, _i32, _i32], _sz),
     "dopinf_infer_workspace": ([_i64, _i32, _vp, _i32], _sz),
     "dopinf_infer": ([_vp, _vp, _i64, _i64, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _vp, _sz], _i32),
@@ -69,6 +72,13 @@ _SIGS = {
     "dopinf_rollout_workspace": ([_i32, _vp, _i32, _i64], _sz),
     "dopinf_rollout": ([_vp, _i32, _vp, _i32, _vp, _vp, _i64, _i64, _i32, _f64, _u32, _vp, _vp, _vp, _vp, _vp, _vp,
                         _vp, _sz], _i32),
+    "dopinf_lift": ([_vp, _vp, _i64, _i64, _i64, _i32, _i32, _vp, _vp, _i64], _i32),
+    "dopinf_infer_continuous_workspace": ([_i64, _i32, _vp, _i32], _sz),
+    "dopinf_infer_continuous": ([_vp, _vp, _i64, _i64, _f64, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _vp, _sz], _i32),
+    "dopinf_rollout_continuous": ([_vp, _i32, _vp, _i32, _vp, _vp, _i64, _i64, _i32, _f64, _f64, _u32, _vp, _vp, _vp,
+                                   _vp, _vp, _vp, _vp, _sz], _i32),
+    "dopinf_postprocess": ([_vp, _i32, _vp, _i64, _i64, _i64, _vp, _vp, _i32, _vp, _vp, _i64, _vp, _i64, _i32, _vp,
+                            _i64, _i64, _vp, _i64, _vp, _i64, _vp], _i32),
     "dopinf_rollout_noalloc_max_bytes": ([], _sz),
     "dopinf_rollout_noalloc": ([_vp, _i32, _vp, _i32, _vp, _vp, _i64, _i64, _i32, _f64, _u32, _vp, _vp, _vp, _vp, _vp,
                                 _vp], _i32),
@@ -179,8 +189,10 @@ def n_quad(r):
 
 
 # ---------------------------------------------------------------- Step II ---
-def preprocess(Q, var_rows, flags=CENTER | SCALE):
-    """Per-row temporal means and per-variable scales; returns (mean, scale, zero_range)."""
+def preprocess(Q, var_rows, flags=CENTER | SCALE, info=None):
+    """Per-row temporal means and per-variable scales; returns (mean, scale,
+    zero_range).  `info` (optional device int32 tensor of one element)
+    receives OK or E_NONFINITE."""
     torch = _torch()
     lib = load()
     n, k = Q.shape
@@ -194,7 +206,7 @@ def preprocess(Q, var_rows, flags=CENTER | SCALE):
     nb = lib.dopinf_preprocess_workspace(n, k, nvars)
     ws = _ws(nb, dev)
     _check(lib.dopinf_preprocess(_stream(dev), _dtype_code(Q), _ptr(Q), n, k, ldq, nvars, vrp, flags, _ptr(mean),
-                                 _ptr(scale), _ptr(zr), _ptr(ws), ws.numel()))
+                                 _ptr(scale), _ptr(zr), _ptr(info), _ptr(ws), ws.numel()))
     return mean, scale, zr
 
 
@@ -263,6 +275,25 @@ def reduce(D, r=0, tau=0.9996, r_max=None, want_tr=True):
                              _ptr(info), _ptr(ws), ws.numel()))
     rr = r_out.value
     return lam, (Tr[:, :rr] if Tr is not None else None), Qhat[:rr], info, rr
+
+
+def reduce_topr(D, r, want_tr=True):
+    """Partial eigendecomposition for a prescribed r: returns (lam_r, Tr,
+    Qhat, info, iters) with iters = subspace iterations (0: full solver)."""
+    torch = _torch()
+    lib = load()
+    k = D.shape[0]
+    dev = D.device
+    lam = torch.empty(r, dtype=torch.float64, device=dev)
+    Qhat = torch.empty((r, k), dtype=torch.float64, device=dev)
+    Tr = torch.empty((k, r), dtype=torch.float64, device=dev) if want_tr else None
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    ws = _ws(lib.dopinf_reduce_topr_workspace(k, r), dev)
+    iters = C.c_int(0)
+    _check(lib.dopinf_reduce_topr(_stream(dev), _ptr(D), k, _rowmajor(D, "D"), int(r), _ptr(lam), _ptr(Tr),
+                                  r if Tr is not None else 0, _ptr(Qhat), k, _ptr(info), C.byref(iters), _ptr(ws),
+                                  ws.numel()))
+    return lam, Tr, Qhat, info, iters.value
 
 
 # ---------------------------------------------------------------- Step IV ---
@@ -347,6 +378,117 @@ def rollout(O, Qhat, r_list, n_pairs, n_states, k_train=None, max_growth=1.2, so
             views.append(row)
         out["traj_views"] = views
     return out
+
+
+LIFT_COPY, LIFT_PRODUCT, LIFT_RECIPROCAL = 0, 1, 2
+
+
+def lift(Q, n_cells, spec):
+    """Lifted variables (Sec. 3.3): spec = [(op, a, b), ...] over the input
+    variables (blocks of n_cells rows of Q); returns len(spec) blocks."""
+    torch = _torch()
+    lib = load()
+    n, k = Q.shape
+    sp = np.asarray(spec, dtype=np.int32).reshape(-1, 3)
+    sp_c, sp_p = _host_i32(sp.ravel())
+    L = torch.empty((len(sp) * n_cells, k), dtype=torch.float64, device=Q.device)
+    _check(lib.dopinf_lift(_stream(Q.device), _ptr(Q), n_cells, k, _rowmajor(Q, "Q"), n // n_cells, len(sp), sp_p,
+                           _ptr(L), k))
+    return L
+
+
+def infer_continuous(Qhat, dt, r_list, beta1, beta2):
+    """Continuous-time operators (Eq. (10)) from finite-difference derivative
+    data at spacing dt; returns (O_flat, status, views) as infer()."""
+    torch = _torch()
+    lib = load()
+    dev = Qhat.device
+    k = Qhat.shape[1]
+    rl, rlp = _host_i32(r_list)
+    b1, b1p = _host_f64(beta1)
+    b2, b2p = _host_f64(beta2)
+    n_pairs = len(b1)
+    if len(b2) != n_pairs:
+        raise ValueError("beta1 and beta2 must have the same length")
+    n_items = len(rl) * n_pairs
+    total = lib.dopinf_operator_offset(len(rl), rlp, n_pairs, n_items)
+    O = torch.empty(total, dtype=torch.float64, device=dev)
+    status = torch.empty(n_items, dtype=torch.int32, device=dev)
+    ws = _ws(lib.dopinf_infer_continuous_workspace(k, len(rl), rlp, n_pairs), dev)
+    _check(lib.dopinf_infer_continuous(_stream(dev), _ptr(Qhat), _rowmajor(Qhat, "Qhat"), k, float(dt), len(rl), rlp,
+                                       n_pairs, b1p, b2p, _ptr(O), _ptr(status), _ptr(ws), ws.numel()))
+    views = []
+    for g, r in enumerate(rl):
+        d = int(r) + n_quad(int(r)) + 1
+        row = []
+        for p in range(n_pairs):
+            off = lib.dopinf_operator_offset(len(rl), rlp, n_pairs, g * n_pairs + p)
+            row.append(O[off:off + int(r) * d].view(int(r), d))
+        views.append(row)
+    return O, status, views
+
+
+def rollout_continuous(O, Qhat, r_list, n_pairs, n_states, dt, k_train=None, max_growth=1.2, solve_status=None,
+                       keep_traj=False, full=False):
+    """RK4 rollouts of continuous-time ROMs, scored like rollout()."""
+    torch = _torch()
+    lib = load()
+    dev = O.device
+    rl, rlp = _host_i32(r_list)
+    n_items = len(rl) * n_pairs
+    if k_train is None:
+        k_train = Qhat.shape[1]
+    traj = None
+    if keep_traj:
+        traj = torch.empty(lib.dopinf_traj_offset(len(rl), rlp, n_pairs, n_states, n_items), dtype=torch.float64,
+                           device=dev)
+    te = torch.empty(n_items, dtype=torch.float64, device=dev)
+    gr = torch.empty(n_items, dtype=torch.float64, device=dev)
+    oc = torch.empty(n_items, dtype=torch.int32, device=dev)
+    best = torch.empty(len(rl), dtype=torch.int32, device=dev)
+    ws = _ws(lib.dopinf_rollout_workspace(len(rl), rlp, n_pairs, k_train), dev)
+    _check(lib.dopinf_rollout_continuous(_stream(dev), len(rl), rlp, n_pairs, _ptr(O), _ptr(Qhat),
+                                         _rowmajor(Qhat, "Qhat"), k_train, n_states, float(dt), float(max_growth),
+                                         ROLLOUT_FULL if full else 0, _ptr(solve_status), _ptr(traj), _ptr(te),
+                                         _ptr(gr), _ptr(oc), _ptr(best), _ptr(ws), ws.numel()))
+    out = {"train_err": te, "growth": gr, "outcome": oc, "best": best, "traj": traj}
+    if keep_traj:
+        out["traj_views"] = [[traj[lib.dopinf_traj_offset(len(rl), rlp, n_pairs, n_states, g * n_pairs + p):][
+            :n_states * int(r)].view(n_states, int(r)) for p in range(n_pairs)] for g, r in enumerate(rl)]
+    return out
+
+
+def postprocess(Q, Tr, rows=None, Qtilde=None, mean=None, scale=None, var_rows=None, m=None):
+    """Step V: basis rows V (m x r) at `rows` (device int64 tensor, or None for
+    rows 0..m-1) and, with Qtilde (r x N), the prediction s_v V Qtilde + mean
+    in original coordinates.  Returns (V, pred or None, info)."""
+    torch = _torch()
+    lib = load()
+    dev = Q.device
+    n, k = Q.shape
+    r = Tr.shape[1]
+    if rows is not None:
+        m = rows.numel()
+    elif m is None:
+        m = n
+    dtype = F64 if Q.dtype == torch.float64 else F32
+    V = torch.empty((m, r), dtype=torch.float64, device=dev)
+    pred = None
+    n_out = 0
+    if Qtilde is not None:
+        n_out = Qtilde.shape[1]
+        pred = torch.empty((m, n_out), dtype=torch.float64, device=dev)
+    info = torch.empty(1, dtype=torch.int32, device=dev)
+    nv = 1
+    vr_p = None
+    if scale is not None:
+        vr, vr_p = _host_i64(var_rows)
+        nv = len(vr) - 1
+    _check(lib.dopinf_postprocess(_stream(dev), dtype, _ptr(Q), n, k, _rowmajor(Q, "Q"), _ptr(mean), _ptr(scale),
+                                  nv, vr_p, _ptr(rows), m, _ptr(Tr), _rowmajor(Tr, "Tr"), r, _ptr(Qtilde),
+                                  _rowmajor(Qtilde, "Qtilde") if Qtilde is not None else 0, n_out, _ptr(V), r,
+                                  _ptr(pred), n_out, _ptr(info)))
+    return V, pred, info
 
 
 def rollout_noalloc(O, Qhat, r_list, n_pairs, n_states, k_train=None, max_growth=1.2, solve_status=None,

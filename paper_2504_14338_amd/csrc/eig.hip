@@ -13,9 +13,12 @@
 //  2. All k eigenvalues of T by multisection: one wave per eigenvalue, the
 //     64 lanes evaluate Sturm counts at 64 interior points per round.
 //  3. The top r eigenvectors of T by inverse iteration with partial-pivoting
-//     LU of T - lambda I (one wave per cluster, factors in LDS); eigenvalues
-//     closer than 1e-10 ||T|| form a cluster whose vectors are orthogonalized
-//     against each other inside the iteration.
+//     LU of T - lambda I (one wave per cluster, factors in LDS).  As in
+//     LAPACK's inverse-iteration routine xSTEIN, neighbouring eigenvalues
+//     closer than 1e-3 ||T|| form a cluster whose vectors are orthogonalized
+//     (modified Gram-Schmidt) against the cluster's earlier vectors inside
+//     every iteration: vectors computed one by one lose orthogonality like
+//     u ||T|| / gap, which would break Qhat Qhat^T = Lambda_r.
 //  4. Back-transformation u = P z (reflectors applied in reverse order), one
 //     workgroup per vector with z in LDS.
 //  5. Sign rule and Qhat / T_r formation.
@@ -491,7 +494,7 @@ __global__ __launch_bounds__(64) void tri_invit_kernel(const double* d, const do
   const int lane = threadIdx.x;
   const double tnorm = bounds[3];
   const double eps = 2.220446049250313e-16;
-  const double ctol = 1e-10 * fmax(tnorm, 1e-300);
+  const double ctol = 1e-3 * fmax(tnorm, 1e-300);  // cluster separation of xSTEIN
   if (j0 > 0 && fabs(lambda_desc[j0 - 1] - lambda_desc[j0]) <= ctol) return;  // not first of its cluster
   int j1 = j0 + 1;
   while (j1 < r && fabs(lambda_desc[j1 - 1] - lambda_desc[j1]) <= ctol) ++j1;
@@ -985,25 +988,13 @@ extern "C" size_t dopinf_reduce_workspace(int64_t k, int r_max) {
   return c.used;
 }
 
-extern "C" int dopinf_reduce(void* stream, const double* D, int64_t k, int64_t ldd, int r_req, double tau,
-                             int r_max, int* r_out_h, double* lambda, double* Tr, int64_t ldtr, double* Qhat,
-                             int64_t ldqh, int* info, void* ws, size_t ws_bytes) {
-  DOPINF_REQUIRE(D && lambda && Qhat && info, "D, lambda, Qhat and info must be non-NULL");
-  DOPINF_REQUIRE(k >= 1 && ldd >= k && ldqh >= k, "need k >= 1, ldd >= k, ldqh >= k");
-  DOPINF_REQUIRE(k <= 65536, "k > 65536 is not supported");
-  DOPINF_REQUIRE(r_max >= 1 && r_max <= k, "need 1 <= r_max <= k");
-  DOPINF_REQUIRE(r_req >= 0 && r_req <= r_max, "need 0 <= r_req <= r_max");
-  DOPINF_REQUIRE(r_req > 0 || (tau > 0.0 && tau < 1.0), "energy threshold tau must be in (0, 1)");
-  DOPINF_REQUIRE(!Tr || ldtr >= r_max, "ldtr must be >= r_max");
-  const size_t need = dopinf_reduce_workspace(k, r_max);
-  if (!ws || ws_bytes < need) return fail(DOPINF_E_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  EigPlan pl{};
-  int rc = plan_sytrd(k, pl);
-  if (rc) return rc;
-  Carver c(ws, ws_bytes);
-  EigWs w = carve_eig(ws, ws_bytes, k, r_max, 1024, c);
+namespace dopinf {
+namespace {
 
+// Tridiagonalization, all eigenvalues (descending, into lambda) and the
+// finiteness / time-out status (into info) of the symmetric k x k matrix D.
+int eig_values_stage(hipStream_t st, const double* D, int64_t k, int64_t ldd, double* lambda, int* info,
+                     const EigWs& w, const EigPlan& pl) {
   zero_words_kernel<<<1, 64, 0, st>>>(w.words, 8);
   DOPINF_LAUNCHED();
   TridArgs ta{};
@@ -1043,19 +1034,12 @@ extern "C" int dopinf_reduce(void* stream, const double* D, int64_t k, int64_t l
   DOPINF_LAUNCHED();
   finite_check_kernel<<<1, 64, 0, st>>>(w.bounds, reinterpret_cast<int*>(w.words + 1), info);
   DOPINF_LAUNCHED();
+  return DOPINF_OK;
+}
 
-  int r = r_req;
-  if (r == 0) {
-    int* r_dev = reinterpret_cast<int*>(w.words + 2);
-    energy_rank_kernel<<<1, 64, 0, st>>>(lambda, k, tau, r_dev);
-    DOPINF_LAUNCHED();
-    int r_h = 0;
-    DOPINF_HIP(hipMemcpyAsync(&r_h, r_dev, sizeof(int), hipMemcpyDeviceToHost, st));
-    DOPINF_HIP(hipStreamSynchronize(st));
-    if (r_h > r_max) return fail(DOPINF_E_RANK, "energy criterion needs r = %d > r_max = %d", r_h, r_max);
-    r = r_h;
-  }
-  if (r_out_h) *r_out_h = r;
+// The top r eigenvectors of D into w.Z (r x k, one per row), from the
+// tridiagonal form and the eigenvalues of eig_values_stage.
+int eig_vectors_stage(hipStream_t st, int64_t k, int r, const double* lambda, const EigWs& w) {
   {
     int maxlds = 0, devi = 0;
     DOPINF_HIP(hipGetDevice(&devi));
@@ -1085,7 +1069,73 @@ extern "C" int dopinf_reduce(void* stream, const double* D, int64_t k, int64_t l
     backtransform_kernel<<<unsigned(r), 256, zl, st>>>(w.A, w.tau, k, w.Z);
     DOPINF_LAUNCHED();
   }
-  form_qhat_kernel<<<unsigned(r), 256, 0, st>>>(w.Z, k, r, lambda, Qhat, ldqh, Tr, ldtr, info);
+  return DOPINF_OK;
+}
+
+}  // namespace
+
+// All eigenvalues (descending) and the top r eigenvectors (rows of *Z, r x k,
+// inside ws) of the symmetric k x k matrix D; info as for dopinf_reduce.
+size_t eig_vectors_workspace(int64_t k, int r) { return dopinf_reduce_workspace(k, r); }
+
+int eig_vectors_internal(hipStream_t st, const double* D, int64_t k, int64_t ldd, int r, double* lambda, int* info,
+                         void* ws, size_t ws_bytes, double** Z) {
+  EigPlan pl{};
+  int rc = plan_sytrd(k, pl);
+  if (rc) return rc;
+  Carver c(ws, ws_bytes);
+  EigWs w = carve_eig(ws, ws_bytes, k, r, 1024, c);
+  rc = eig_values_stage(st, D, k, ldd, lambda, info, w, pl);
+  if (!rc) rc = eig_vectors_stage(st, k, r, lambda, w);
+  *Z = w.Z;
+  return rc;
+}
+
+// Sign rule, Qhat = Lambda_r^{1/2} U_r^T and T_r = U_r Lambda_r^{-1/2} from
+// the eigenvector rows Z (r x k) and the descending eigenvalues.
+int form_qhat_internal(hipStream_t st, const double* Z, int64_t k, int r, const double* lambda, double* Qhat,
+                       int64_t ldqh, double* Tr, int64_t ldtr, int* info) {
+  form_qhat_kernel<<<unsigned(r), 256, 0, st>>>(Z, k, r, lambda, Qhat, ldqh, Tr, ldtr, info);
   DOPINF_LAUNCHED();
   return DOPINF_OK;
+}
+
+}  // namespace dopinf
+
+extern "C" int dopinf_reduce(void* stream, const double* D, int64_t k, int64_t ldd, int r_req, double tau,
+                             int r_max, int* r_out_h, double* lambda, double* Tr, int64_t ldtr, double* Qhat,
+                             int64_t ldqh, int* info, void* ws, size_t ws_bytes) {
+  DOPINF_REQUIRE(D && lambda && Qhat && info, "D, lambda, Qhat and info must be non-NULL");
+  DOPINF_REQUIRE(k >= 1 && ldd >= k && ldqh >= k, "need k >= 1, ldd >= k, ldqh >= k");
+  DOPINF_REQUIRE(k <= 65536, "k > 65536 is not supported");
+  DOPINF_REQUIRE(r_max >= 1 && r_max <= k, "need 1 <= r_max <= k");
+  DOPINF_REQUIRE(r_req >= 0 && r_req <= r_max, "need 0 <= r_req <= r_max");
+  DOPINF_REQUIRE(r_req > 0 || (tau > 0.0 && tau < 1.0), "energy threshold tau must be in (0, 1)");
+  DOPINF_REQUIRE(!Tr || ldtr >= r_max, "ldtr must be >= r_max");
+  const size_t need = dopinf_reduce_workspace(k, r_max);
+  if (!ws || ws_bytes < need) return fail(DOPINF_E_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  EigPlan pl{};
+  int rc = plan_sytrd(k, pl);
+  if (rc) return rc;
+  Carver c(ws, ws_bytes);
+  EigWs w = carve_eig(ws, ws_bytes, k, r_max, 1024, c);
+  rc = eig_values_stage(st, D, k, ldd, lambda, info, w, pl);
+  if (rc) return rc;
+
+  int r = r_req;
+  if (r == 0) {
+    int* r_dev = reinterpret_cast<int*>(w.words + 2);
+    energy_rank_kernel<<<1, 64, 0, st>>>(lambda, k, tau, r_dev);
+    DOPINF_LAUNCHED();
+    int r_h = 0;
+    DOPINF_HIP(hipMemcpyAsync(&r_h, r_dev, sizeof(int), hipMemcpyDeviceToHost, st));
+    DOPINF_HIP(hipStreamSynchronize(st));
+    if (r_h > r_max) return fail(DOPINF_E_RANK, "energy criterion needs r = %d > r_max = %d", r_h, r_max);
+    r = r_h;
+  }
+  if (r_out_h) *r_out_h = r;
+  rc = eig_vectors_stage(st, k, r, lambda, w);
+  if (rc) return rc;
+  return form_qhat_internal(st, w.Z, k, r, lambda, Qhat, ldqh, Tr, ldtr, info);
 }

@@ -11,19 +11,25 @@
 //  * The normal matrix is factored in the permuted column order
 //    [quadratic (s) | linear (r), constant (1)].  Its leading s x s block
 //    G_qq + beta2 I depends on beta2 only, so its Cholesky factor L, the
-//    solves [W | y] = L^{-1} [G_ql | B_q] and [P | Z] = L^{-T} [W | y], and
-//    the products W^T [W | y] are computed once per (r, beta2).  Each pair
-//    then factors the small Schur complement
+//    forward solve [W | y] = L^{-1} [G_ql | B_q] and the products
+//    W^T [W | y] are computed once per (r, beta2).  Each pair then factors
+//    the small Schur complement
 //       S = G_ll + beta1 I - W^T W           ((r+1) x (r+1))
-//    solves S X_l = B_l - W^T y and recovers X_q = Z - P X_l.  This is
-//    Cholesky factorization of the same matrix under a symmetric permutation.
+//    solves S X_l = B_l - W^T y, forms v = y - W X_l and solves
+//    L^T X_q = v by back substitution.  This is Cholesky factorization of
+//    the same matrix under a symmetric permutation (backward stable; the
+//    shortcut X_q = L^{-T} y - (L^{-T} W) X_l is not: it cancels
+//    |L^{-T} W| |X_l| down to |X_q|).
 //  * The s x s factorization is blocked right-looking (64-wide panels): a
 //    diagonal-block kernel also inverts its 64 x 64 triangle, a panel kernel
 //    solves the rows below, and the trailing update runs on FP64 MFMA tiles.
 //    Triangular solves then reduce to products with the stored diagonal
 //    inverses.
 #include <algorithm>
+#include <cmath>
 #include <cstdlib>
+#include <mutex>
+#include <utility>
 #include <type_traits>
 #include <vector>
 
@@ -68,12 +74,23 @@ __device__ __forceinline__ void qpair(int64_t q, int r, int& i, int& j) {
 
 // ---------------------------------------------------------------------------
 // E = [Qhat_1^T | quad(Qhat_1^T) | 1 | Qhat_2^T] at r_max, (k-1) x m, ld lde
+// (discrete form, dt == 0), or, for the continuous-time form of Eq. (10),
+// E = [Qhat^T | quad(Qhat^T) | 1 | Qdot^T], k x m, with the time derivative
+// by second-order finite differences at snapshot spacing dt: central
+// differences inside the window, the one-sided three-point formulas at its
+// two ends (exact for quadratics in t).
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ double fd_derivative(const double* __restrict__ q, int64_t t, int64_t k, double dt) {
+  if (t == 0) return (-3.0 * q[0] + 4.0 * q[1] - q[2]) / (2.0 * dt);
+  if (t == k - 1) return (3.0 * q[k - 1] - 4.0 * q[k - 2] + q[k - 3]) / (2.0 * dt);
+  return (q[t + 1] - q[t - 1]) / (2.0 * dt);
+}
+
 __global__ __launch_bounds__(256) void assemble_kernel(const double* __restrict__ Qhat, int64_t ldqh, int64_t k,
-                                                       int rmax, double* __restrict__ E, int64_t lde) {
+                                                       int rmax, double* __restrict__ E, int64_t lde, double dt) {
   const int64_t c = blockIdx.y;                    // column of E
-  const int64_t t = int64_t(blockIdx.x) * 256 + threadIdx.x;  // row (time index of Qhat_1)
-  if (t >= k - 1) return;
+  const int64_t t = int64_t(blockIdx.x) * 256 + threadIdx.x;  // row (time index of Qhat_1, or of Qhat)
+  if (t >= (dt > 0.0 ? k : k - 1)) return;
   const int64_t s = nquad(rmax);
   const int64_t d = rmax + s + 1;
   double v;
@@ -85,6 +102,8 @@ __global__ __launch_bounds__(256) void assemble_kernel(const double* __restrict_
     v = Qhat[int64_t(i) * ldqh + t] * Qhat[int64_t(j) * ldqh + t];
   } else if (c == rmax + s) {
     v = 1.0;
+  } else if (dt > 0.0) {
+    v = fd_derivative(Qhat + (c - d) * ldqh, t, k, dt);
   } else {
     v = Qhat[(c - d) * ldqh + t + 1];
   }
@@ -1410,7 +1429,9 @@ struct MiscPtrs {
   double* b1dev;  // per pair
 };
 
-InferLayout layout(int64_t k, int n_r, const int* r_list, int n_pairs) {
+// erows: rows of the data matrix E (k - 1 for the discrete form, k for the
+// continuous-time form)
+InferLayout layout(int64_t k, int n_r, const int* r_list, int n_pairs, int64_t erows) {
   InferLayout L{};
   L.n_r = n_r;
   int rmax = 0;
@@ -1421,7 +1442,7 @@ InferLayout layout(int64_t k, int n_r, const int* r_list, int n_pairs) {
   L.dmax = ncols(rmax);
   L.m = L.dmax + rmax;
   L.lde = (L.m + 1) / 2 * 2;
-  L.km1 = k - 1;
+  L.km1 = erows;
   Carver c(nullptr, 0);
   c.take<double>(size_t(L.km1) * L.lde);
   L.e_off = 0;
@@ -1466,6 +1487,7 @@ MiscPtrs misc_ptrs(const InferLayout& L, void* ws, int n_pairs) {
 struct InferPlan {
   InferLayout L;
   int64_t k;
+  double dt = 0.0;  // > 0: continuous-time form (derivative data at spacing dt)
   int n_r, n_pairs;
   std::vector<int> r_list;
   std::vector<double> beta1, b2u;  // per pair; distinct beta2 in first-appearance order
@@ -1492,7 +1514,11 @@ struct InferPlan {
 // Streams of the group fork: created once per host thread and device
 // (default priority, non-blocking) and kept for the life of the process, so
 // that a call neither pays for creating them nor shares them with a call on
-// another host thread.  Events are per call.
+// another host thread.  Events are per call.  Every such stream is also
+// entered in a process-wide list, and an exit handler (registered after the
+// HIP runtime has loaded, so it runs before the runtime's own teardown)
+// destroys them: no stream of the library is left for the runtime to tear
+// down at process exit, after profiling tools have finalized.
 //
 // A process has GPU_MAX_HW_QUEUES hardware queues (4 unless set), and streams
 // beyond that share them: two groups whose streams land on one queue run one
@@ -1500,6 +1526,22 @@ struct InferPlan {
 // 74 ms).  So at most (queues - 1) group streams are used, the caller's
 // stream keeping one queue: the largest groups get a stream each and the
 // smallest groups share the last one.
+std::mutex g_stream_mu;
+std::vector<std::pair<int, hipStream_t>> g_all_streams;
+
+void destroy_pool_streams() {
+  std::lock_guard<std::mutex> lock(g_stream_mu);
+  int cur = 0;
+  const bool have_dev = hipGetDevice(&cur) == hipSuccess;
+  for (auto& ds : g_all_streams) {
+    if (hipSetDevice(ds.first) != hipSuccess) continue;
+    (void)hipStreamSynchronize(ds.second);
+    (void)hipStreamDestroy(ds.second);
+  }
+  g_all_streams.clear();
+  if (have_dev) (void)hipSetDevice(cur);
+}
+
 int infer_streams(InferPlan& P) {
   if (P.n_r < 2 || !P.gst.empty()) return DOPINF_OK;
   int hwq = 4;
@@ -1518,6 +1560,10 @@ int infer_streams(InferPlan& P) {
     hipStream_t x = nullptr;
     DOPINF_HIP(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
     mine.push_back(x);
+    std::lock_guard<std::mutex> lock(g_stream_mu);
+    static const bool registered = (std::atexit(destroy_pool_streams) == 0);
+    (void)registered;
+    g_all_streams.emplace_back(dev, x);
   }
   DOPINF_HIP(hipEventCreateWithFlags(&P.fork, hipEventDisableTiming));
   for (int g = 0; g < P.n_r; ++g) {
@@ -1547,14 +1593,16 @@ Kb trsm_kb(int64_t s) {
 }
 
 int infer_plan(int64_t k, int64_t ldqh, int n_r, const int* r_list_h, int n_pairs, const double* beta1_h,
-               const double* beta2_h, size_t ws_bytes, const void* ws, InferPlan& P) {
+               const double* beta2_h, size_t ws_bytes, const void* ws, InferPlan& P, double dt = 0.0) {
   DOPINF_REQUIRE(r_list_h && beta1_h && beta2_h, "NULL argument");
   DOPINF_REQUIRE(k >= 2 && ldqh >= k, "need k >= 2 and ldqh >= k");
   DOPINF_REQUIRE(n_r >= 1 && n_pairs >= 1, "need n_r >= 1 and n_pairs >= 1");
   for (int g = 0; g < n_r; ++g) DOPINF_REQUIRE(r_list_h[g] >= 1 && r_list_h[g] <= 512, "r must be in [1, 512]");
   for (int p = 0; p < n_pairs; ++p)
     DOPINF_REQUIRE(beta1_h[p] >= 0.0 && beta2_h[p] >= 0.0, "regularization parameters must be >= 0");
-  P.L = layout(k, n_r, r_list_h, n_pairs);
+  if (dt != 0.0) DOPINF_REQUIRE(dt > 0.0 && std::isfinite(dt) && k >= 3, "continuous form: need dt > 0 and k >= 3");
+  P.dt = dt;
+  P.L = layout(k, n_r, r_list_h, n_pairs, dt > 0.0 ? k : k - 1);
   if (!ws || ws_bytes < P.L.total)
     return fail(DOPINF_E_WORKSPACE, "workspace of %zu bytes needed, %zu given", P.L.total, ws_bytes);
   int dev = 0, maxlds = 0;
@@ -1636,7 +1684,7 @@ int infer_gram(hipStream_t st, const InferPlan& P, const double* Qhat, int64_t l
   double* E = reinterpret_cast<double*>(base + L.e_off);
   double* GE = reinterpret_cast<double*>(base + L.g_off);
   dim3 grid(unsigned((L.km1 + 255) / 256), unsigned(L.m));
-  assemble_kernel<<<grid, 256, 0, st>>>(Qhat, ldqh, P.k, L.rmax, E, L.lde);
+  assemble_kernel<<<grid, 256, 0, st>>>(Qhat, ldqh, P.k, L.rmax, E, L.lde, P.dt);
   DOPINF_LAUNCHED();
   return gram_f64_internal(st, E, L.km1, L.m, L.lde, nullptr, nullptr, 0, nullptr, GE, L.m, base + L.gram_off,
                            L.gram_bytes);
@@ -1877,7 +1925,7 @@ extern "C" size_t dopinf_operator_offset(int n_r, const int* r_list_h, int n_pai
 
 extern "C" size_t dopinf_infer_workspace(int64_t k, int n_r, const int* r_list_h, int n_pairs) {
   if (k < 2 || n_r <= 0 || !r_list_h || n_pairs <= 0) return 0;
-  return layout(k, n_r, r_list_h, n_pairs).total;
+  return layout(k, n_r, r_list_h, n_pairs, k - 1).total;
 }
 
 extern "C" int dopinf_infer(void* stream, const double* Qhat, int64_t ldqh, int64_t k, int n_r, const int* r_list_h,
@@ -1886,6 +1934,26 @@ extern "C" int dopinf_infer(void* stream, const double* Qhat, int64_t ldqh, int6
   DOPINF_REQUIRE(Qhat && O && status, "NULL argument");
   InferPlan P;
   int rc = infer_plan(k, ldqh, n_r, r_list_h, n_pairs, beta1_h, beta2_h, ws_bytes, ws, P);
+  if (rc) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  rc = infer_upload(st, P, ws);
+  if (!rc) rc = infer_streams(P);
+  if (rc) return rc;
+  return infer_enqueue(st, P, Qhat, ldqh, O, status, ws);
+}
+
+extern "C" size_t dopinf_infer_continuous_workspace(int64_t k, int n_r, const int* r_list_h, int n_pairs) {
+  if (k < 3 || n_r <= 0 || !r_list_h || n_pairs <= 0) return 0;
+  return layout(k, n_r, r_list_h, n_pairs, k).total;
+}
+
+extern "C" int dopinf_infer_continuous(void* stream, const double* Qhat, int64_t ldqh, int64_t k, double dt, int n_r,
+                                       const int* r_list_h, int n_pairs, const double* beta1_h,
+                                       const double* beta2_h, double* O, int* status, void* ws, size_t ws_bytes) {
+  DOPINF_REQUIRE(Qhat && O && status, "NULL argument");
+  DOPINF_REQUIRE(dt > 0.0 && std::isfinite(dt), "dt must be finite and > 0");
+  InferPlan P;
+  int rc = infer_plan(k, ldqh, n_r, r_list_h, n_pairs, beta1_h, beta2_h, ws_bytes, ws, P, dt);
   if (rc) return rc;
   hipStream_t st = static_cast<hipStream_t>(stream);
   rc = infer_upload(st, P, ws);

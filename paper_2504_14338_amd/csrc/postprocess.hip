@@ -1,0 +1,281 @@
+// Step V of dOpInf (arXiv:2504.14338, Sec. 3.6): the reduced solution mapped
+// back to the original coordinates at selected rows, without forming the
+// POD basis of all rows.
+//
+//   V[i, :]    = Qs[row_i, :] T_r                  (rows of V_r, Eq. (7))
+//   pred[i, t] = s_v(row_i) (V[i, :] Qtilde[:, t]) + mean[row_i]
+//
+// Both are products of a tall operand (gathered snapshot rows, or V) with a
+// short one (T_r, k x r, or Qtilde, r x N) and run on one FP64 MFMA tile
+// kernel: 64 output rows per workgroup, wave w owns rows 16w..16w+15 and
+// NJ blocks of 16 columns; K is staged through LDS in chunks of 32 with the
+// next chunk's global loads in registers while the current one is used.
+// Centering is a subtraction as the snapshot values are staged; the division
+// by the variable's scale is applied once per output entry (exact in exact
+// arithmetic, and one division per V entry instead of one per Q entry).
+#include "common.hpp"
+
+namespace dopinf {
+int check_var_rows(int64_t n, int nvars, const int64_t* var_rows_h);
+
+namespace {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+constexpr int PT = 256;   // threads: 4 waves
+constexpr int PM = 64;    // output rows per workgroup
+constexpr int PK = 32;    // K chunk staged in LDS
+constexpr int PAS = PK + 1;  // padded row of the A stage
+
+struct VarTable {
+  int nvars;
+  int64_t row0[DOPINF_MAX_VARS + 1];
+};
+
+__device__ __forceinline__ int var_of(const VarTable& vt, int64_t row) {
+  int v = 0;
+  while (v + 1 < vt.nvars && row >= vt.row0[v + 1]) ++v;
+  return v;
+}
+
+template <class T>
+struct RowGemmArgs {
+  const T* A;              // A row i = A[arow(i) * lda + 0 .. K)
+  int64_t lda;
+  const int64_t* a_rows;   // gather map for A, or null (identity)
+  const double* a_shift;   // per source row, subtracted from A's values, or null
+  const double* B;         // K x ncol, row-major
+  int64_t ldb;
+  int64_t m, K, ncol, n_src;
+  double* C;               // m x ncol
+  int64_t ldc;
+  const int64_t* e_rows;   // source row of output row i for the epilogue, or null (identity)
+  const double* e_scale;   // per variable: divide (div = 1) or multiply (div = 0), or null
+  int div;
+  const double* e_add;     // per source row, added after scaling, or null
+  VarTable vt;
+  int* info;               // receives DOPINF_E_ARG for a row index outside [0, n_src)
+};
+
+template <class T, int NJ>
+__global__ __launch_bounds__(PT) void row_gemm_kernel(RowGemmArgs<T> a) {
+  __shared__ double As[PM][PAS];
+  __shared__ double Bs[PK][16 * NJ];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int64_t i0 = int64_t(blockIdx.x) * PM;
+  const int64_t c0 = int64_t(blockIdx.y) * 16 * NJ;
+
+  // A staging: thread -> tile row tid / 4, 8 consecutive k at 8 (tid % 4)
+  const int ar = tid >> 2, ak = (tid & 3) * 8;
+  const int64_t gi = i0 + ar;
+  int64_t src = -1;
+  if (gi < a.m) {
+    src = a.a_rows ? a.a_rows[gi] : gi;
+    if (src < 0 || src >= a.n_src) {
+      if (a.info) atomicExch(a.info, DOPINF_E_ARG);
+      src = -1;
+    }
+  }
+  const double shift = (src >= 0 && a.a_shift) ? a.a_shift[src] : 0.0;
+  const T* arow = a.A + (src >= 0 ? src : 0) * a.lda;
+  // B staging: thread -> chunk row tid / 8, 2 NJ consecutive columns
+  constexpr int BW = 2 * NJ;
+  const int br = tid >> 3, bc = (tid & 7) * BW;
+
+  double ra[8], rb[BW];
+  auto load = [&](int64_t kc) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int64_t kk = kc + ak + q;
+      const bool ok = src >= 0 && kk < a.K;
+      const double x = static_cast<double>(arow[ok ? kk : 0]);
+      ra[q] = ok ? x - shift : 0.0;
+    }
+    const int64_t kb = kc + br;
+#pragma unroll
+    for (int q = 0; q < BW; ++q) {
+      const int64_t c = c0 + bc + q;
+      const bool ok = kb < a.K && c < a.ncol;
+      const double x = a.B[(ok ? kb : 0) * a.ldb + (ok ? c : 0)];
+      rb[q] = ok ? x : 0.0;
+    }
+  };
+
+  dbl4 acc[NJ];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) acc[j] = dbl4{0.0, 0.0, 0.0, 0.0};
+
+  load(0);
+  for (int64_t kc = 0; kc < a.K; kc += PK) {
+    __syncthreads();  // the previous chunk has been read
+#pragma unroll
+    for (int q = 0; q < 8; ++q) As[ar][ak + q] = ra[q];
+#pragma unroll
+    for (int q = 0; q < BW; ++q) Bs[br][bc + q] = rb[q];
+    __syncthreads();
+    if (kc + PK < a.K) load(kc + PK);
+    const int kmax = (a.K - kc) < PK ? int(a.K - kc) : PK;
+    for (int kk = 0; kk < kmax; kk += 4) {
+      const int k = kk + (lane >> 4);  // rows past K hold zeros
+      const double af = As[16 * wv + (lane & 15)][k];
+#pragma unroll
+      for (int j = 0; j < NJ; ++j)
+        acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, Bs[k][16 * j + (lane & 15)], acc[j], 0, 0, 0);
+    }
+  }
+
+  // epilogue: acc[j][e] is C[16 wv + (lane >> 4) + 4 e][16 j + (lane & 15)]
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int64_t i = i0 + 16 * wv + (lane >> 4) + 4 * e;
+    if (i >= a.m) continue;
+    const int64_t es = a.e_rows ? a.e_rows[i] : i;
+    const bool ok = es >= 0 && es < a.n_src;
+    double sc = 1.0, ad = 0.0;
+    if (ok) {
+      if (a.e_scale) sc = a.e_scale[var_of(a.vt, es)];
+      if (a.e_add) ad = a.e_add[es];
+    }
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int64_t c = c0 + 16 * j + (lane & 15);
+      if (c >= a.ncol) continue;
+      double v = acc[j][e];
+      v = a.div ? v / sc : v * sc;
+      a.C[i * a.ldc + c] = ok ? v + ad : NAN;
+    }
+  }
+}
+
+template <class T>
+int launch_row_gemm(hipStream_t st, const RowGemmArgs<T>& a) {
+  const unsigned gx = unsigned((a.m + PM - 1) / PM);
+  if (a.ncol <= 16) {
+    row_gemm_kernel<T, 1><<<dim3(gx, 1), PT, 0, st>>>(a);
+  } else if (a.ncol <= 32) {
+    row_gemm_kernel<T, 2><<<dim3(gx, 1), PT, 0, st>>>(a);
+  } else if (a.ncol <= 64) {
+    row_gemm_kernel<T, 4><<<dim3(gx, 1), PT, 0, st>>>(a);
+  } else {
+    row_gemm_kernel<T, 8><<<dim3(gx, unsigned((a.ncol + 127) / 128)), PT, 0, st>>>(a);
+  }
+  DOPINF_LAUNCHED();
+  return DOPINF_OK;
+}
+
+__global__ void set_int_kernel(int* p, int v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+template <class T>
+int postprocess_t(hipStream_t st, const T* Q, int64_t n, int64_t k, int64_t ldq, const double* mean,
+                  const double* scale, const VarTable& vt, const int64_t* rows, int64_t m, const double* Tr,
+                  int64_t ldtr, int r, const double* Qtilde, int64_t ldqt, int64_t n_out, double* V, int64_t ldv,
+                  double* pred, int64_t ldp, int* info) {
+  RowGemmArgs<T> b{};
+  b.A = Q;
+  b.lda = ldq;
+  b.a_rows = rows;
+  b.a_shift = mean;
+  b.B = Tr;
+  b.ldb = ldtr;
+  b.m = m;
+  b.K = k;
+  b.ncol = r;
+  b.n_src = n;
+  b.C = V;
+  b.ldc = ldv;
+  b.e_rows = rows;
+  b.e_scale = scale;
+  b.div = 1;
+  b.e_add = nullptr;
+  b.vt = vt;
+  b.info = info;
+  int rc = launch_row_gemm(st, b);
+  if (rc || !pred) return rc;
+  RowGemmArgs<double> p{};
+  p.A = V;
+  p.lda = ldv;
+  p.a_rows = nullptr;
+  p.a_shift = nullptr;
+  p.B = Qtilde;
+  p.ldb = ldqt;
+  p.m = m;
+  p.K = r;
+  p.ncol = n_out;
+  p.n_src = n;
+  p.C = pred;
+  p.ldc = ldp;
+  p.e_rows = rows;
+  p.e_scale = scale;
+  p.div = 0;
+  p.e_add = mean;
+  p.vt = vt;
+  p.info = nullptr;
+  return launch_row_gemm(st, p);
+}
+
+}  // namespace
+
+// C (m x ncol) = A (m x K) B (K x ncol), all row-major float64: the same tile
+// kernel, for other parts of the library.
+int row_gemm_f64(hipStream_t st, const double* A, int64_t lda, int64_t m, int64_t K, const double* B, int64_t ldb,
+                 int64_t ncol, double* C, int64_t ldc) {
+  RowGemmArgs<double> g{};
+  g.A = A;
+  g.lda = lda;
+  g.B = B;
+  g.ldb = ldb;
+  g.m = m;
+  g.K = K;
+  g.ncol = ncol;
+  g.n_src = m;
+  g.C = C;
+  g.ldc = ldc;
+  g.div = 0;
+  g.vt.nvars = 1;
+  g.vt.row0[0] = 0;
+  g.vt.row0[1] = m;
+  return launch_row_gemm(st, g);
+}
+
+}  // namespace dopinf
+
+using namespace dopinf;
+
+extern "C" int dopinf_postprocess(void* stream, int dtype, const void* Q, int64_t n, int64_t k, int64_t ldq,
+                                  const double* mean, const double* scale, int nvars, const int64_t* var_rows_h,
+                                  const int64_t* rows, int64_t m, const double* Tr, int64_t ldtr, int r,
+                                  const double* Qtilde, int64_t ldqt, int64_t n_out, double* V, int64_t ldv,
+                                  double* pred, int64_t ldp, int* info) {
+  DOPINF_REQUIRE(dtype == DOPINF_F64 || dtype == DOPINF_F32, "dtype must be DOPINF_F64 or DOPINF_F32");
+  DOPINF_REQUIRE(Q && Tr && V, "Q, Tr and V must be non-NULL");
+  DOPINF_REQUIRE(n >= 1 && k >= 1 && ldq >= k, "need n >= 1, k >= 1, ldq >= k");
+  DOPINF_REQUIRE(m >= 1 && (rows || m <= n), "need m >= 1 (and m <= n when rows is NULL)");
+  DOPINF_REQUIRE(r >= 1 && r <= k && ldtr >= r, "need 1 <= r <= k and ldtr >= r");
+  DOPINF_REQUIRE(ldv >= r, "need ldv >= r");
+  if (pred) {
+    DOPINF_REQUIRE(Qtilde && n_out >= 1 && ldqt >= n_out && ldp >= n_out,
+                   "pred needs Qtilde, n_out >= 1, ldqt >= n_out and ldp >= n_out");
+  }
+  VarTable vt{};
+  vt.nvars = 1;
+  vt.row0[0] = 0;
+  vt.row0[1] = n;
+  if (scale) {
+    const int rc = check_var_rows(n, nvars, var_rows_h);
+    if (rc) return rc;
+    vt.nvars = nvars;
+    for (int v = 0; v <= nvars; ++v) vt.row0[v] = var_rows_h[v];
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (info) {
+    set_int_kernel<<<1, 64, 0, st>>>(info, DOPINF_OK);
+    DOPINF_LAUNCHED();
+  }
+  if (dtype == DOPINF_F64)
+    return postprocess_t(st, static_cast<const double*>(Q), n, k, ldq, mean, scale, vt, rows, m, Tr, ldtr, r,
+                         Qtilde, ldqt, n_out, V, ldv, pred, ldp, info);
+  return postprocess_t(st, static_cast<const float*>(Q), n, k, ldq, mean, scale, vt, rows, m, Tr, ldtr, r, Qtilde,
+                       ldqt, n_out, V, ldv, pred, ldp, info);
+}

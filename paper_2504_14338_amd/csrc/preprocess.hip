@@ -6,6 +6,11 @@
 // and reduces sum and max |x - mean| across the 64 lanes.  Per-variable maxima
 // come from a deterministic two-stage max over the per-row maxima (max is
 // exact, so the result is independent of order).
+//
+// Non-finite data: a row holding NaN or Inf gets a NaN row maximum, and every
+// max here propagates NaN (fmax would drop it), so the variable's scale is
+// NaN, as the plain definition gives it; the call's status word then reads
+// DOPINF_E_NONFINITE.
 #include "common.hpp"
 
 namespace dopinf {
@@ -15,6 +20,15 @@ constexpr int kRowsPerBlock = 4;  // one 64-lane wave per row
 
 template <class T>
 __device__ __forceinline__ double ld(const T* p) { return static_cast<double>(*p); }
+
+// max that keeps NaN once it has been seen (either argument)
+__device__ __forceinline__ double max_nan(double a, double b) { return (a != a || b > a || b != b) ? (a != a ? a : b) : a; }
+
+__device__ __forceinline__ double wave_max_nan(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = max_nan(v, __shfl_xor(v, o, 64));
+  return v;
+}
 
 // NV > 0: the row is kept in registers (k <= 64*NV); NV == 0: re-read.
 template <class T, int NV>
@@ -45,16 +59,20 @@ __global__ __launch_bounds__(256) void row_stats_kernel(
 #pragma unroll
     for (int j = 0; j < NV; ++j) {
       int64_t t = lane + 64 * j;
-      if (t < k) m = fmax(m, fabs(v[j] - mu));
+      if (t < k) m = max_nan(m, fabs(v[j] - mu));
     }
   } else {
     double s = 0.0;
     for (int64_t t = lane; t < k; t += 64) s += ld(q + t);
     s = wave_sum(s);
     mu = center ? s / static_cast<double>(k) : 0.0;
-    for (int64_t t = lane; t < k; t += 64) m = fmax(m, fabs(ld(q + t) - mu));
+    for (int64_t t = lane; t < k; t += 64) m = max_nan(m, fabs(ld(q + t) - mu));
   }
-  m = wave_max(m);
+  // an infinite value with a finite mean gives an infinite deviation; with
+  // centering the mean is then infinite too and the deviation NaN: either way
+  // the row is flagged by a NaN maximum
+  m = wave_max_nan(m);
+  if (isinf(m) || isinf(mu)) m = NAN;
   if (lane == 0) {
     mean[row] = mu;
     rowmax[row] = m;
@@ -84,34 +102,43 @@ __global__ __launch_bounds__(256) void var_max_partial_kernel(
   const int64_t lo = vr.row0[v] + int64_t(c - vr.chunk0[v]) * kChunkRows;
   const int64_t hi = min(vr.row0[v + 1], lo + kChunkRows);
   double m = 0.0;
-  for (int64_t i = lo + threadIdx.x; i < hi; i += 256) m = fmax(m, rowmax[i]);
-  m = wave_max(m);
+  for (int64_t i = lo + threadIdx.x; i < hi; i += 256) m = max_nan(m, rowmax[i]);
+  m = wave_max_nan(m);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
   __syncthreads();
-  if (threadIdx.x == 0) part[c] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  if (threadIdx.x == 0) part[c] = max_nan(max_nan(red[0], red[1]), max_nan(red[2], red[3]));
 }
 
-// Stage 2: one wave per variable; zero range -> scale 1 and a flag.
+// Stage 2: one wave per variable; zero range -> scale 1 and a flag; a NaN
+// maximum (non-finite data in the variable) -> scale NaN and the status word
+// DOPINF_E_NONFINITE (set, never cleared, by any variable).
 __global__ void var_max_final_kernel(const double* __restrict__ part, VarRanges vr,
                                      int do_scale, double* __restrict__ scale,
-                                     int* __restrict__ zero_range) {
+                                     int* __restrict__ zero_range, int* __restrict__ info) {
   const int v = blockIdx.x;
   double m = 0.0;
-  for (int c = vr.chunk0[v] + threadIdx.x; c < vr.chunk0[v + 1]; c += 64) m = fmax(m, part[c]);
-  m = wave_max(m);
+  for (int c = vr.chunk0[v] + threadIdx.x; c < vr.chunk0[v + 1]; c += 64) m = max_nan(m, part[c]);
+  m = wave_max_nan(m);
   if (threadIdx.x == 0) {
     int zr = 0;
     double s = 1.0;
-    if (do_scale) {
+    if (m != m) {
+      if (info) atomicExch(info, DOPINF_E_NONFINITE);
+      if (do_scale) s = m;
+    } else if (do_scale) {
       if (m == 0.0) {
         zr = 1;
       } else {
-        s = m;  // NaN propagates: fmax drops NaN, so a NaN row gives a finite max
+        s = m;
       }
     }
     scale[v] = s;
     if (zero_range) zero_range[v] = zr;
   }
+}
+
+__global__ void set_info_kernel(int* info) {
+  if (threadIdx.x == 0) *info = DOPINF_OK;
 }
 
 template <class T>
@@ -126,6 +153,36 @@ __global__ __launch_bounds__(256) void apply_kernel(T* __restrict__ Q, int64_t n
   const double s = scale[v];
   T* q = Q + row * ldq;
   for (int64_t t = threadIdx.x & 63; t < k; t += 64) q[t] = static_cast<T>((ld(q + t) - mu) / s);
+}
+
+// Lifting (Sec. 3.3): output variable j, cell i, snapshot t from the input
+// variables' values at the same cell and snapshot.  One wave per output row.
+struct LiftSpec {
+  int n_out;
+  int op[DOPINF_MAX_VARS], a[DOPINF_MAX_VARS], b[DOPINF_MAX_VARS];
+};
+
+__global__ __launch_bounds__(256) void lift_kernel(const double* __restrict__ Q, int64_t n_cells, int64_t k,
+                                                   int64_t ldq, LiftSpec sp, double* __restrict__ L, int64_t ldl) {
+  const int64_t row = int64_t(blockIdx.x) * kRowsPerBlock + (threadIdx.x >> 6);
+  if (row >= int64_t(sp.n_out) * n_cells) return;
+  const int j = int(row / n_cells);
+  const int64_t i = row - int64_t(j) * n_cells;
+  const double* qa = Q + (int64_t(sp.a[j]) * n_cells + i) * ldq;
+  const double* qb = Q + (int64_t(sp.b[j]) * n_cells + i) * ldq;
+  double* out = L + row * ldl;
+  const int op = sp.op[j];
+  for (int64_t t = threadIdx.x & 63; t < k; t += 64) {
+    const double x = qa[t];
+    double y;
+    if (op == DOPINF_LIFT_PRODUCT)
+      y = x * qb[t];
+    else if (op == DOPINF_LIFT_RECIPROCAL)
+      y = 1.0 / x;
+    else
+      y = x;
+    out[t] = y;
+  }
 }
 
 VarRanges make_ranges(int nvars, const int64_t* var_rows_h) {
@@ -179,7 +236,7 @@ extern "C" size_t dopinf_preprocess_workspace(int64_t n, int64_t /*k*/, int nvar
 
 extern "C" int dopinf_preprocess(void* stream, int dtype, void* Q, int64_t n, int64_t k, int64_t ldq,
                                  int nvars, const int64_t* var_rows_h, unsigned flags, double* mean,
-                                 double* scale, int* zero_range, void* ws, size_t ws_bytes) {
+                                 double* scale, int* zero_range, int* info, void* ws, size_t ws_bytes) {
   DOPINF_REQUIRE(dtype == DOPINF_F64 || dtype == DOPINF_F32, "dtype must be DOPINF_F64 or DOPINF_F32");
   DOPINF_REQUIRE(Q && mean && scale, "Q, mean and scale must be non-NULL");
   DOPINF_REQUIRE(n >= 1 && k >= 1 && ldq >= k, "need n >= 1, k >= 1, ldq >= k");
@@ -195,6 +252,10 @@ extern "C" int dopinf_preprocess(void* stream, int dtype, void* Q, int64_t n, in
   double* part = c.take<double>(size_t(n / kChunkRows + nvars + 1));
   VarRanges vr = make_ranges(nvars, var_rows_h);
   const int center = (flags & DOPINF_CENTER) ? 1 : 0;
+  if (info) {
+    set_info_kernel<<<1, 64, 0, st>>>(info);
+    DOPINF_LAUNCHED();
+  }
   if (dtype == DOPINF_F64)
     launch_row_stats(st, static_cast<const double*>(Q), n, k, ldq, center, mean, rowmax);
   else
@@ -202,7 +263,7 @@ extern "C" int dopinf_preprocess(void* stream, int dtype, void* Q, int64_t n, in
   DOPINF_LAUNCHED();
   var_max_partial_kernel<<<vr.chunk0[nvars], 256, 0, st>>>(rowmax, vr, part);
   DOPINF_LAUNCHED();
-  var_max_final_kernel<<<nvars, 64, 0, st>>>(part, vr, (flags & DOPINF_SCALE) ? 1 : 0, scale, zero_range);
+  var_max_final_kernel<<<nvars, 64, 0, st>>>(part, vr, (flags & DOPINF_SCALE) ? 1 : 0, scale, zero_range, info);
   DOPINF_LAUNCHED();
   if (flags & DOPINF_APPLY) {
     dim3 grid(unsigned((n + kRowsPerBlock - 1) / kRowsPerBlock));
@@ -212,5 +273,31 @@ extern "C" int dopinf_preprocess(void* stream, int dtype, void* Q, int64_t n, in
       apply_kernel<float><<<grid, 256, 0, st>>>(static_cast<float*>(Q), n, k, ldq, mean, scale, vr);
     DOPINF_LAUNCHED();
   }
+  return DOPINF_OK;
+}
+
+extern "C" int dopinf_lift(void* stream, const double* Q, int64_t n_cells, int64_t k, int64_t ldq, int nvars_in,
+                           int n_out, const int* spec_h, double* L, int64_t ldl) {
+  DOPINF_REQUIRE(Q && L && spec_h, "Q, L and spec_h must be non-NULL");
+  DOPINF_REQUIRE(n_cells >= 1 && k >= 1 && ldq >= k && ldl >= k, "need n_cells, k >= 1, ldq >= k, ldl >= k");
+  DOPINF_REQUIRE(nvars_in >= 1 && n_out >= 1 && n_out <= DOPINF_MAX_VARS,
+                 "need nvars_in >= 1 and 1 <= n_out <= %d", DOPINF_MAX_VARS);
+  LiftSpec sp{};
+  sp.n_out = n_out;
+  for (int j = 0; j < n_out; ++j) {
+    const int op = spec_h[3 * j], a = spec_h[3 * j + 1], b = spec_h[3 * j + 2];
+    DOPINF_REQUIRE(op == DOPINF_LIFT_COPY || op == DOPINF_LIFT_PRODUCT || op == DOPINF_LIFT_RECIPROCAL,
+                   "lifting output %d: unknown op %d", j, op);
+    DOPINF_REQUIRE(a >= 0 && a < nvars_in, "lifting output %d: variable %d outside [0, %d)", j, a, nvars_in);
+    DOPINF_REQUIRE(op != DOPINF_LIFT_PRODUCT || (b >= 0 && b < nvars_in),
+                   "lifting output %d: variable %d outside [0, %d)", j, b, nvars_in);
+    sp.op[j] = op;
+    sp.a[j] = a;
+    sp.b[j] = (op == DOPINF_LIFT_PRODUCT) ? b : a;
+  }
+  const int64_t rows = int64_t(n_out) * n_cells;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  lift_kernel<<<unsigned((rows + kRowsPerBlock - 1) / kRowsPerBlock), 256, 0, st>>>(Q, n_cells, k, ldq, sp, L, ldl);
+  DOPINF_LAUNCHED();
   return DOPINF_OK;
 }

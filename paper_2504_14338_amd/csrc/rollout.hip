@@ -22,6 +22,7 @@
 // a running maximum, so crossing the bound (or meeting a non-finite value) is
 // final and the selection is unchanged.  Team members score the same state
 // with the same code and so take the same decision without talking.
+#include <cmath>
 #include <mutex>
 
 #include "common.hpp"
@@ -71,6 +72,7 @@ struct RollArgs {
   int n_states;
   double max_growth;
   int full;
+  double dt;             // > 0: continuous-time ROM stepped by RK4 with this step
   const double* mean;    // r
   const double* maxdev;  // r
   const int* solve_status;  // group base or null
@@ -80,15 +82,65 @@ struct RollArgs {
   int* outcome;
 };
 
+// The ROM's map of the state in f[0:r]: builds the features f = [q |
+// quad(q) | 1] in LDS, then qn[i] = O[i, :] . f for every row i.  Each wave
+// owns rows w*RPW + 16*RPW*m; per lane CU8 x RPW operator loads are issued
+// before their FMAs so that enough L2 traffic is in flight per CU.  Ends
+// with a workgroup barrier (qn complete, f no longer read).
+__device__ __forceinline__ void rom_map(const double* __restrict__ Op, double* f, double* qn, int r, int64_t s,
+                                        int64_t d, const unsigned short* qi, const unsigned short* qj, int tid,
+                                        int lane, int w) {
+  for (int64_t c = tid; c < s; c += RT) f[r + c] = f[qi[c]] * f[qj[c]];
+  if (tid == 0) f[d - 1] = 1.0;
+  __syncthreads();
+  for (int i0 = w * RPW; i0 < r; i0 += (RT / 64) * RPW) {
+    double acc[RPW];
+#pragma unroll
+    for (int u = 0; u < RPW; ++u) acc[u] = 0.0;
+    int64_t c = lane;
+    for (; c + 64 * (CU8 - 1) < d; c += 64 * CU8) {
+      double ov[RPW][CU8];
+#pragma unroll
+      for (int u = 0; u < RPW; ++u)
+#pragma unroll
+        for (int q = 0; q < CU8; ++q) ov[u][q] = (i0 + u < r) ? Op[int64_t(i0 + u) * d + c + 64 * q] : 0.0;
+#pragma unroll
+      for (int q = 0; q < CU8; ++q) {
+        const double fc = f[c + 64 * q];
+#pragma unroll
+        for (int u = 0; u < RPW; ++u) acc[u] += ov[u][q] * fc;
+      }
+    }
+    for (; c < d; c += 64) {
+      const double fc = f[c];
+#pragma unroll
+      for (int u = 0; u < RPW; ++u)
+        if (i0 + u < r) acc[u] += Op[int64_t(i0 + u) * d + c] * fc;
+    }
+#pragma unroll
+    for (int u = 0; u < RPW; ++u) {
+      const double v = wave_sum(acc[u]);
+      if (lane == 0 && i0 + u < r) qn[i0 + u] = v;
+    }
+  }
+  __syncthreads();
+}
+
+// RK4 = false: the discrete ROM of Eq. (11), q_{t+1} = O [q | quad(q) | 1].
+// RK4 = true: the continuous-time ROM of Eq. (10), dq/dt = O [q | quad(q) | 1],
+// advanced by one classical fourth-order Runge-Kutta step of a.dt per state.
+template <bool RK4>
 __global__ __launch_bounds__(RT) void rollout_kernel(RollArgs a) {
   extern __shared__ double sm[];
   const int p = blockIdx.x;
   const int r = a.r;
   const int64_t s = a.s, d = a.d;
   double* f = sm;                  // d features: [q | quad(q) | 1]
-  double* qn = sm + d;             // r next state
+  double* qn = sm + d;             // r next state (RK4: the stage's right-hand side)
   double* mean = qn + r;           // r
-  unsigned short* qi = reinterpret_cast<unsigned short*>(mean + r);
+  double* q0s = mean + r;          // RK4: r, the state at the start of the step
+  double* ksum = q0s + (RK4 ? r : 0);  // RK4: r, k1 + 2 k2 + 2 k3 + k4
+  unsigned short* qi = reinterpret_cast<unsigned short*>(ksum + (RK4 ? r : 0));
   unsigned short* qj = qi + s;
   __shared__ double red[RT / 64][4];
   __shared__ int stop_sh;
@@ -189,46 +241,25 @@ __global__ __launch_bounds__(RT) void rollout_kernel(RollArgs a) {
       break;
     }
     if (t + 1 == a.n_states) break;
-    // ---- features of state t ----
-    for (int64_t c = tid; c < s; c += RT) f[r + c] = f[qi[c]] * f[qj[c]];
-    if (tid == 0) f[d - 1] = 1.0;
-    __syncthreads();
-    // ---- next state: q_{t+1}[i] = O[i, :] . f ----
-    // each wave owns rows w*RPW + 16*RPW*m; per lane CU8 x RPW loads are issued
-    // before their FMAs so that enough L2 traffic is in flight per CU
-    for (int i0 = w * RPW; i0 < r; i0 += (RT / 64) * RPW) {
-      double acc[RPW];
-#pragma unroll
-      for (int u = 0; u < RPW; ++u) acc[u] = 0.0;
-      int64_t c = lane;
-      for (; c + 64 * (CU8 - 1) < d; c += 64 * CU8) {
-        double ov[RPW][CU8];
-#pragma unroll
-        for (int u = 0; u < RPW; ++u)
-#pragma unroll
-          for (int q = 0; q < CU8; ++q) ov[u][q] = (i0 + u < r) ? Op[int64_t(i0 + u) * d + c + 64 * q] : 0.0;
-#pragma unroll
-        for (int q = 0; q < CU8; ++q) {
-          const double fc = f[c + 64 * q];
-#pragma unroll
-          for (int u = 0; u < RPW; ++u) acc[u] += ov[u][q] * fc;
+    if constexpr (RK4) {
+      for (int i = tid; i < r; i += RT) q0s[i] = f[i];
+      for (int stage = 0; stage < 4; ++stage) {
+        // f[0:r] holds the stage state; qn receives its right-hand side
+        rom_map(Op, f, qn, r, s, d, qi, qj, tid, lane, w);
+        for (int i = tid; i < r; i += RT) {
+          const double kv = qn[i];
+          ksum[i] = (stage == 0) ? kv : ksum[i] + ((stage == 3) ? kv : 2.0 * kv);
+          if (stage < 3) f[i] = q0s[i] + ((stage == 2) ? a.dt : 0.5 * a.dt) * kv;
         }
+        __syncthreads();
       }
-      for (; c < d; c += 64) {
-        const double fc = f[c];
-#pragma unroll
-        for (int u = 0; u < RPW; ++u)
-          if (i0 + u < r) acc[u] += Op[int64_t(i0 + u) * d + c] * fc;
-      }
-#pragma unroll
-      for (int u = 0; u < RPW; ++u) {
-        const double v = wave_sum(acc[u]);
-        if (lane == 0 && i0 + u < r) qn[i0 + u] = v;
-      }
+      for (int i = tid; i < r; i += RT) f[i] = q0s[i] + (a.dt / 6.0) * ksum[i];
+      __syncthreads();
+    } else {
+      rom_map(Op, f, qn, r, s, d, qi, qj, tid, lane, w);
+      for (int i = tid; i < r; i += RT) f[i] = qn[i];
+      __syncthreads();
     }
-    __syncthreads();
-    for (int i = tid; i < r; i += RT) f[i] = qn[i];
-    __syncthreads();
   }
   if (trj)
     for (int64_t e = int64_t(t_done) * r + tid; e < int64_t(a.n_states) * r; e += RT) trj[e] = NAN;
@@ -238,6 +269,7 @@ __global__ __launch_bounds__(RT) void rollout_kernel(RollArgs a) {
     a.growth[p] = (oc == DOPINF_ITEM_NONFINITE) ? NAN : run_dev / maxdev;
   }
 }
+
 
 // ---- team rollout -------------------------------------------------------------
 
@@ -507,7 +539,7 @@ int check_rollout_args(int n_r, const int* r_list_h, int n_pairs, const double* 
 int rollout_launch(hipStream_t st, int n_r, const int* r_list_h, int n_pairs, const double* O,
                    const double* Qhat, int64_t ldqh, int64_t k_train, int n_states, double max_growth,
                    unsigned flags, const int* solve_status, double* traj, double* train_err, double* growth,
-                   int* outcome, int* best, void* ws, size_t ws_bytes) {
+                   int* outcome, int* best, void* ws, size_t ws_bytes, double dt = 0.0) {
   int dev = 0, maxlds = 0;
   DOPINF_HIP(hipGetDevice(&dev));
   DOPINF_HIP(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
@@ -520,11 +552,14 @@ int rollout_launch(hipStream_t st, int n_r, const int* r_list_h, int n_pairs, co
     double* maxdev = w.maxdev;
     train_stats_kernel<<<r, 256, 0, st>>>(Qhat, ldqh, k_train, mean, maxdev);
     DOPINF_LAUNCHED();
-    const size_t smem = size_t(d + 2 * r) * sizeof(double) + size_t(2 * s) * sizeof(unsigned short) + 64;
+    const bool rk4 = dt > 0.0;
+    const size_t smem =
+        size_t(d + (rk4 ? 4 : 2) * r) * sizeof(double) + size_t(2 * s) * sizeof(unsigned short) + 64;
     DOPINF_REQUIRE(smem + 1024 <= size_t(maxlds), "r too large for the rollout workgroup");
+    const void* one_wg = rk4 ? reinterpret_cast<const void*>(rollout_kernel<true>)
+                             : reinterpret_cast<const void*>(rollout_kernel<false>);
     if (smem > 65536)
-      DOPINF_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(rollout_kernel),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(smem)));
+      DOPINF_HIP(hipFuncSetAttribute(one_wg, hipFuncAttributeMaxDynamicSharedMemorySize, int(smem)));
     RollArgs ra{};
     ra.r = r;
     ra.s = s;
@@ -536,6 +571,7 @@ int rollout_launch(hipStream_t st, int n_r, const int* r_list_h, int n_pairs, co
     ra.n_states = n_states;
     ra.max_growth = max_growth;
     ra.full = (flags & DOPINF_ROLLOUT_FULL) ? 1 : 0;
+    ra.dt = dt;
     ra.mean = mean;
     ra.maxdev = maxdev;
     ra.solve_status = solve_status ? solve_status + g * n_pairs : nullptr;
@@ -543,7 +579,7 @@ int rollout_launch(hipStream_t st, int n_r, const int* r_list_h, int n_pairs, co
     ra.train_err = train_err + g * n_pairs;
     ra.growth = growth + g * n_pairs;
     ra.outcome = outcome + g * n_pairs;
-    const int P = team_size(r, n_pairs, flags);
+    const int P = rk4 ? 0 : team_size(r, n_pairs, flags);
     bool launched = false;
     if (P > 0) {
       const int tnj = (d <= 64 * 32) ? 32 : 64;
@@ -568,7 +604,10 @@ int rollout_launch(hipStream_t st, int n_r, const int* r_list_h, int n_pairs, co
         (void)hipGetLastError();
     }
     if (!launched) {
-      rollout_kernel<<<n_pairs, RT, smem, st>>>(ra);
+      if (rk4)
+        rollout_kernel<true><<<n_pairs, RT, smem, st>>>(ra);
+      else
+        rollout_kernel<false><<<n_pairs, RT, smem, st>>>(ra);
       DOPINF_LAUNCHED();
     }
   }
@@ -619,6 +658,21 @@ extern "C" int dopinf_rollout(void* stream, int n_r, const int* r_list_h, int n_
   if (!ws || ws_bytes < need) return fail(DOPINF_E_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
   return rollout_launch(static_cast<hipStream_t>(stream), n_r, r_list_h, n_pairs, O, Qhat, ldqh, k_train, n_states,
                         max_growth, flags, solve_status, traj, train_err, growth, outcome, best, ws, ws_bytes);
+}
+
+extern "C" int dopinf_rollout_continuous(void* stream, int n_r, const int* r_list_h, int n_pairs, const double* O,
+                                         const double* Qhat, int64_t ldqh, int64_t k_train, int n_states, double dt,
+                                         double max_growth, unsigned flags, const int* solve_status, double* traj,
+                                         double* train_err, double* growth, int* outcome, int* best, void* ws,
+                                         size_t ws_bytes) {
+  int rc = check_rollout_args(n_r, r_list_h, n_pairs, O, Qhat, ldqh, k_train, n_states, max_growth, flags, train_err,
+                              growth, outcome, best);
+  if (rc) return rc;
+  DOPINF_REQUIRE(dt > 0.0 && std::isfinite(dt), "dt must be finite and > 0");
+  const size_t need = dopinf_rollout_workspace(n_r, r_list_h, n_pairs, k_train);
+  if (!ws || ws_bytes < need) return fail(DOPINF_E_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+  return rollout_launch(static_cast<hipStream_t>(stream), n_r, r_list_h, n_pairs, O, Qhat, ldqh, k_train, n_states,
+                        max_growth, flags, solve_status, traj, train_err, growth, outcome, best, ws, ws_bytes, dt);
 }
 
 extern "C" size_t dopinf_rollout_noalloc_max_bytes(void) { return dopinf::kRolloutScratchBytes; }

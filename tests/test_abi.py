@@ -93,3 +93,24 @@ def test_tuning_table_and_sweep_argument_checks():
     assert h.value is None
     assert lib.dopinf_sweep_destroy(None) == dp.OK
     assert lib.dopinf_sweep_workspace(100, 1, r, 1) >= lib.dopinf_infer_workspace(100, 1, r, 1)
+
+
+def test_lift_and_continuous_argument_errors():
+    import paper_2504_14338_amd as dp
+    lib = dp.load()
+    spec = (ctypes.c_int * 3)(dp.LIFT_PRODUCT, 0, 2)   # variable 2 of 2
+    rc = lib.dopinf_lift(None, ctypes.c_void_p(8), 10, 4, 4, 2, 1, spec, ctypes.c_void_p(8), 4)
+    assert rc == dp.E_ARG and "outside" in lib.dopinf_last_error().decode()
+    spec = (ctypes.c_int * 3)(7, 0, 0)
+    assert lib.dopinf_lift(None, ctypes.c_void_p(8), 10, 4, 4, 2, 1, spec, ctypes.c_void_p(8), 4) == dp.E_ARG
+    r = (ctypes.c_int * 1)(3)
+    b = (ctypes.c_double * 1)(1e-3)
+    # dt must be positive and the continuous form needs 3 snapshots
+    rc = lib.dopinf_infer_continuous(None, ctypes.c_void_p(8), 10, 10, 0.0, 1, r, 1, b, b, ctypes.c_void_p(8),
+                                     ctypes.c_void_p(8), ctypes.c_void_p(8), 1 << 30)
+    assert rc == dp.E_ARG
+    rc = lib.dopinf_infer_continuous(None, ctypes.c_void_p(8), 2, 2, 0.1, 1, r, 1, b, b, ctypes.c_void_p(8),
+                                     ctypes.c_void_p(8), ctypes.c_void_p(8), 1 << 30)
+    assert rc == dp.E_ARG
+    assert lib.dopinf_infer_continuous_workspace(2, 1, r, 1) == 0
+    assert lib.dopinf_infer_continuous_workspace(10, 1, r, 1) > lib.dopinf_infer_workspace(10, 1, r, 1)

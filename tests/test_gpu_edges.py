@@ -2,11 +2,12 @@
 row or of fewer rows than one 16-row stage, one snapshot column; operator
 inference at r = 1 and 2 (s = 1 and 3 quadratic columns) with k = 2 and 3
 snapshots (one or two data rows), and rollouts and scores of the resulting
-r = 1 and r = 2 ROMs.  Operator tolerances as in test_gpu_step4.py."""
+r = 1 and r = 2 ROMs.  Operator tolerances: tests/opcheck.py."""
 import numpy as np
 import pytest
 
 import oracle as orc
+from opcheck import check_operators
 
 pytestmark = pytest.mark.gpu
 
@@ -39,21 +40,6 @@ def test_gram_tiny(gpu_lib, n, k):
     assert np.max(np.abs(D - Dref)) <= 1e-13 * max(1.0, np.max(np.abs(Dref)))
     D0 = dp.gram(Qd).cpu().numpy()
     assert np.max(np.abs(D0 - Q.T @ Q)) <= 1e-13 * np.max(np.abs(Q.T @ Q))
-
-
-def check_operators(G, B, r, b1, b2, O_gpu, k, where):
-    M = G + np.diag(orc.regularizer(r, b1, b2))
-    O_ref = orc.solve_operators(G, B, r, b1, b2, method="lu")
-
-    def eta(O):
-        X = O.T
-        return np.linalg.norm(M @ X - B) / (np.linalg.norm(M) * np.linalg.norm(X) + np.linalg.norm(B))
-
-    d = M.shape[0]
-    e_gpu, e_ref = eta(O_gpu), eta(O_ref)
-    assert e_gpu <= U * ((k - 1) * np.sqrt(d) + 10 * d), (where, e_gpu)
-    tol = max(1e-10, 2 * np.linalg.cond(M) * max(e_gpu, e_ref, U))
-    assert rel(O_gpu, O_ref) <= tol, (where, rel(O_gpu, O_ref), tol)
 
 
 @pytest.mark.parametrize("k", [2, 3, 6])

@@ -25,6 +25,7 @@ import pytest
 
 import oracle as orc
 import synth
+from opcheck import check_solver_only, gpu_normal_equations, normal_equations_at
 
 pytestmark = pytest.mark.gpu
 
@@ -58,7 +59,7 @@ def c2(gpu_lib):
     O, status, views = dp.infer(Qh, [R], [BETA[0]], [BETA[1]])
     out = dp.rollout(O, Qh, [R], 1, N_STATES, solve_status=status, keep_traj=True)
     torch.cuda.synchronize()
-    yield dict(Q=Q, var_rows=var_rows, mean=mean, scale=scale, zr=zr, D=D, lam=lam, Qhat=Qh, info=info,
+    yield dict(Q=Q, var_rows=var_rows, mean=mean, scale=scale, zr=zr, D=D, lam=lam, Tr=Tr, Qhat=Qh, info=info,
                O=O, status=status, views=views, out=out)
     del Q
     torch.cuda.empty_cache()
@@ -141,6 +142,10 @@ def test_fullsize_operators_and_rollout(gpu_lib, c2):
     e_gpu, e_ref = eta(O_gpu), eta(O_ref)
     assert e_gpu <= eta_bound(K, M.shape[0])
     assert rel(O_gpu, O_ref) <= max(1e-10, 2 * np.linalg.cond(M) * max(e_gpu, e_ref, U))
+    # the solver alone, on the G and B the GPU forms itself
+    GE = gpu_normal_equations(dp, Qh, R)
+    Gg, Bg = normal_equations_at(GE, R, R)
+    check_solver_only(Gg, Bg, R, *BETA, O_gpu, "full size (1e-2, 1e8)")
     # the oracle's rollout of the GPU's operators
     Qt = orc.rollout(O_gpu, R, Qh[:, 0], N_STATES)
     fin, te, g, ok = orc.score(Qt, Qh, Qh.shape[1], 1.2)
@@ -211,3 +216,63 @@ def test_fullsize_sweep_sampled_items(gpu_lib, c2):
             if ok:
                 assert te[it] == pytest.approx(e, rel=1e-8), (r, p)
                 assert gr[it] == pytest.approx(gg, rel=1e-9), (r, p)
+
+
+def test_fullsize_postprocess(gpu_lib, c2):
+    """Step V at full size: basis rows and the lifted 4000-state rollout at
+    sampled rows against the oracle on those rows (the same bytes, the GPU's
+    statistics and T_r); all 4,000,000 basis rows orthonormal (V^T V by the
+    cross-Gram kernel)."""
+    import torch
+    dp = gpu_lib
+    Q, var_rows = c2["Q"], c2["var_rows"]
+    rng = np.random.default_rng(50)
+    rows = np.sort(np.concatenate([rng.choice(N_VAR * N_CELL, 59, replace=False),
+                                   [0, N_CELL - 1, N_CELL, 3 * N_CELL + 7, N_VAR * N_CELL - 1]])).astype(np.int64)
+    rows_d = torch.from_numpy(rows).cuda()
+    traj = c2["out"]["traj_views"][0][0]          # n_states x r
+    Qt = traj.t().contiguous()
+    V, pred, info = dp.postprocess(Q, c2["Tr"], rows=rows_d, Qtilde=Qt, mean=c2["mean"], scale=c2["scale"],
+                                   var_rows=var_rows)
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0
+    Qr = Q[rows_d].cpu().numpy()
+    mean, scale = c2["mean"].cpu().numpy(), c2["scale"].cpu().numpy()
+    Tr = c2["Tr"].cpu().numpy()
+    s_rows = np.repeat(scale, N_CELL)[rows]
+    Qs = orc.apply_statistics(Qr, mean[rows], s_rows)
+    Vref = orc.basis_rows(Qs, Tr, np.arange(len(rows)))
+    gam = K * U / (1 - K * U)
+    bound = 2 * gam * (np.abs(Qs) @ np.abs(Tr)) + 4 * U * np.abs(Vref)
+    Vg = V.cpu().numpy()
+    assert np.all(np.abs(Vg - Vref) <= bound), float(np.max(np.abs(Vg - Vref) / bound))
+    Qtn = Qt.cpu().numpy()
+    fin = np.all(np.isfinite(Qtn), axis=0)
+    pref = s_rows[:, None] * (Vref @ Qtn[:, fin]) + mean[rows][:, None]
+    assert rel(pred.cpu().numpy()[:, fin], pref) <= 1e-12
+    # every basis row: V_r = Qs T_r is orthonormal (Eq. (7))
+    Vall, _, info = dp.postprocess(Q, c2["Tr"], rows=None, m=N_VAR * N_CELL, mean=c2["mean"], scale=c2["scale"],
+                                   var_rows=var_rows)
+    G = dp.cross_gram(Vall, Vall)
+    torch.cuda.synchronize()
+    assert rel(G.cpu().numpy(), np.eye(R)) <= 1e-10
+    del Vall
+
+
+def test_fullsize_partial_eig(gpu_lib, c2):
+    """The partial eigendecomposition at r = 60 on the full-size D: the same
+    Qhat as the full eigensolver within each mode's sensitivity, far fewer
+    operations (block subspace iteration)."""
+    import torch
+    dp = gpu_lib
+    lam_p, Tr_p, Qh_p, info, iters = dp.reduce_topr(c2["D"], R)
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0 and 0 < iters <= 80
+    lam = c2["lam"].cpu().numpy()
+    assert np.max(np.abs(lam_p.cpu().numpy() - lam[:R])) <= 1e-13 * lam[0]
+    gaps = np.abs(np.diff(lam[:R + 1]))
+    gaps = np.minimum(np.concatenate([[np.inf], gaps[:-1]]), gaps)
+    Qf, Qp = c2["Qhat"].cpu().numpy(), Qh_p.cpu().numpy()
+    for i in range(R):
+        bound = max(1e-10, 200 * U * lam[0] / gaps[i])
+        assert rel(Qp[i], Qf[i]) <= bound, (i, rel(Qp[i], Qf[i]), bound)

@@ -1,0 +1,114 @@
+"""Partial eigendecomposition for a prescribed r (dopinf_reduce_topr: block
+subspace iteration with Rayleigh-Ritz), through the C ABI, against the
+oracle's full eigendecomposition (Sec. 3.4, Eqs. (6)-(8)): the r leading
+eigenvalues, Qhat and T_r with the same sign rule.  Tolerances as for the
+full solver: eigenvalues 1e-13 lambda_1; Qhat per mode within
+max(1e-10, 100 u lambda_1 / gap_i) (the eigenvector's own sensitivity)."""
+import numpy as np
+import pytest
+
+import oracle as orc
+import synth
+
+pytestmark = pytest.mark.gpu
+
+U = 2.0 ** -53
+
+
+def dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def check_against_oracle(D, r, lam, Tr, Qhat):
+    lam_o, U_o = orc.eig_desc(D)
+    Tr_o, Qh_o = orc.reduce_basis_free(lam_o, U_o, r)
+    assert np.max(np.abs(lam - lam_o[:r])) <= 1e-13 * lam_o[0]
+    gaps = np.abs(np.diff(lam_o[:r + 1]))
+    gaps = np.minimum(np.concatenate([[np.inf], gaps[:-1]]), gaps)
+    for i in range(r):
+        bound = max(1e-10, 100 * U * lam_o[0] / gaps[i])
+        assert rel(Qhat[i], Qh_o[i]) <= bound, (i, rel(Qhat[i], Qh_o[i]), bound)
+        assert rel(Tr[:, i], Tr_o[:, i]) <= bound, (i, rel(Tr[:, i], Tr_o[:, i]), bound)
+
+
+def test_topr_small_configuration(gpu_lib):
+    import torch
+    dp = gpu_lib
+    Q, var_rows, _, _ = synth.c1_snapshots(seed=1)
+    Qd = dev(Q)
+    mean, scale, _ = dp.preprocess(Qd, var_rows)
+    D = dp.gram(Qd, mean, scale, var_rows)
+    lam, Tr, Qhat, info, iters = dp.reduce_topr(D, 10)
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0 and iters > 0
+    ref = orc.pipeline(Q, var_rows, 10, 1e-6, 1e-4, 1200)
+    assert rel(Qhat.cpu().numpy(), ref["Qhat"]) <= 1e-10
+    check_against_oracle(D.cpu().numpy(), 10, lam.cpu().numpy(), Tr.cpu().numpy(), Qhat.cpu().numpy())
+
+
+@pytest.mark.parametrize("r", [20, 60, 80])
+def test_topr_wave_spectrum(gpu_lib, r):
+    # the spectrum of the wave workload: lambda_i ~ exp(-2 i / 40), 200 modes,
+    # then a noise floor, in a random orthonormal basis of R^2000
+    import torch
+    dp = gpu_lib
+    k = 2000
+    rng = np.random.default_rng(r)
+    W, _ = np.linalg.qr(rng.normal(size=(k, k)))
+    lam = np.concatenate([4e8 * np.exp(-2.0 * np.arange(1, 201) / 40.0), 1e-2 * rng.uniform(0.5, 1.0, k - 200)])
+    lam = np.sort(lam)[::-1]
+    D = (W * lam[None, :]) @ W.T
+    D = 0.5 * (D + D.T)
+    Dd = dev(D)
+    l, Tr, Qh, info, iters = dp.reduce_topr(Dd, r)
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0 and 0 < iters <= 80, iters
+    check_against_oracle(D, r, l.cpu().numpy(), Tr.cpu().numpy(), Qh.cpu().numpy())
+
+
+def test_topr_near_degenerate_clusters(gpu_lib):
+    import torch
+    dp = gpu_lib
+    k = 600
+    rng = np.random.default_rng(5)
+    W, _ = np.linalg.qr(rng.normal(size=(k, k)))
+    top = np.array([100.0, 100.0 * (1 - 1e-9), 100.0 * (1 - 1e-6), 50.0, 50.0 * (1 - 1e-8), 20.0])
+    lam = np.concatenate([top, 1e-3 * np.linspace(1.0, 0.01, k - len(top))])
+    D = (W * lam[None, :]) @ W.T
+    D = 0.5 * (D + D.T)
+    l, Tr, Qh, info, iters = dp.reduce_topr(dev(D), 6)
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0 and iters > 0
+    Qn = Qh.cpu().numpy()
+    lg = l.cpu().numpy()
+    assert np.max(np.abs(lg - top)) <= 1e-13 * 100
+    assert rel(Qn @ Qn.T, np.diag(lg)) <= 1e-10
+    Ug = (Qn / np.sqrt(lg)[:, None]).T
+    for c in (slice(0, 3), slice(3, 5), slice(5, 6)):
+        assert np.linalg.norm(Ug[:, c] @ Ug[:, c].T - W[:, c] @ W[:, c].T, 2) <= 1e-10
+
+
+def test_topr_slow_decay_uses_full_solver(gpu_lib):
+    # lambda_{p+1} / lambda_r close to 1: the subspace iteration would need
+    # hundreds of steps, so the full eigensolver runs and gives its bits
+    import torch
+    dp = gpu_lib
+    k = 300
+    rng = np.random.default_rng(8)
+    W, _ = np.linalg.qr(rng.normal(size=(k, k)))
+    lam = np.linspace(10.0, 9.0, k)
+    D = (W * lam[None, :]) @ W.T
+    D = 0.5 * (D + D.T)
+    Dd = dev(D)
+    l, Tr, Qh, info, iters = dp.reduce_topr(Dd, 10)
+    lf, Trf, Qhf, infof, _ = dp.reduce(Dd, r=10)
+    torch.cuda.synchronize()
+    assert iters == 0
+    assert np.array_equal(Qh.cpu().numpy(), Qhf.cpu().numpy())
+    assert np.array_equal(l.cpu().numpy(), lf.cpu().numpy()[:10])

@@ -1,18 +1,10 @@
 """GPU parity of Step IV (regularized operator inference, rollouts, scoring
 and selection) against the CPU oracle, through the C ABI.
 
-Operator checks, from the arithmetic of a linear solve M X = B with
-M = G + diag(beta1, beta2, beta1) (d unknowns per right-hand side):
-  * backward error on the oracle's own M and B: the GPU forms G = Dhat^T Dhat
-    and B itself with (k-1)-term sums, |dG| <= gamma_{k-1} |Dhat|^T |Dhat|,
-    so ||dG||_F <= gamma_{k-1} ||Dhat||_F^2 = gamma_{k-1} trace(G)
-    <= gamma_{k-1} sqrt(d) ||G||_F; the Cholesky solve adds a backward error of
-    order d u.  Hence ||M X - B|| <= eta (||M|| ||X|| + ||B||) with
-    eta <= u ((k - 1) sqrt(d) + 10 d);
-  * forward error: to first order ||dX|| / ||X|| <= 2 kappa_2(M) eta (the
-    standard perturbation bound for linear systems), so the GPU and the
-    oracle's LU solution (the paper's listing) may differ by up to
-    2 kappa_2(M) max(eta_gpu, eta_oracle, u), and at least 1e-10 is allowed.
+Operator checks (tests/opcheck.py): the backward error on the oracle's own
+normal equations, the forward error against the oracle's LU solution within
+the first-order perturbation bound, and the solver alone on the G and B the
+GPU forms itself, within ten times the oracle's own LU-vs-Cholesky spread.
 """
 import numpy as np
 import pytest
@@ -33,26 +25,12 @@ def dev(x):
     return torch.from_numpy(np.ascontiguousarray(x)).cuda()
 
 
-U = 2.0 ** -53
-
-
-def eta_bound(k, d):
-    return U * ((k - 1) * np.sqrt(d) + 10 * d)
+from opcheck import U, check_operators as _check_ops, check_solver_only, gpu_normal_equations, \
+    normal_equations_at
 
 
 def check_operators(G, B, r, b1, b2, O_gpu, where=None, k=None):
-    M = G + np.diag(orc.regularizer(r, b1, b2))
-    O_ref = orc.solve_operators(G, B, r, b1, b2, method="lu")
-
-    def eta(O):
-        X = O.T
-        return np.linalg.norm(M @ X - B) / (np.linalg.norm(M) * np.linalg.norm(X) + np.linalg.norm(B))
-
-    d = M.shape[0]
-    e_gpu, e_ref = eta(O_gpu), eta(O_ref)
-    assert e_gpu <= eta_bound(k, d), (where, e_gpu)
-    tol = max(1e-10, 2 * np.linalg.cond(M) * max(e_gpu, e_ref, U))
-    assert rel(O_gpu, O_ref) <= tol, (where, rel(O_gpu, O_ref), tol)
+    _check_ops(G, B, r, b1, b2, O_gpu, k, where)
 
 
 @pytest.fixture(scope="module")
@@ -75,6 +53,10 @@ def test_infer_single_pair_c1(gpu_lib, c1_qhat):
     Qh = Qhat.cpu().numpy()
     _, G, B = orc.opinf_data(Qh)
     check_operators(G, B, 10, 1e-6, 1e-4, views[0][0].cpu().numpy(), k=Qh.shape[1])
+    # the solver alone, on the G and B that the GPU forms itself
+    GE = gpu_normal_equations(dp, Qh, 10)
+    Gg, Bg = normal_equations_at(GE, 10, 10)
+    check_solver_only(Gg, Bg, 10, 1e-6, 1e-4, views[0][0].cpu().numpy(), "C1 (1e-6, 1e-4)")
 
 
 def test_infer_grid_of_sizes_and_pairs(gpu_lib, c1_qhat):
@@ -86,10 +68,13 @@ def test_infer_grid_of_sizes_and_pairs(gpu_lib, c1_qhat):
     b2 = [1e-6, 1e-1, 1e-6, 1e-1, 1e-6, 1e-1]
     O, status, views = dp.infer(Qhat, r_list, b1, b2)
     assert np.all(status.cpu().numpy() == 0)
+    GE = gpu_normal_equations(dp, Qh, max(r_list))
     for g, r in enumerate(r_list):
         _, G, B = orc.opinf_data(Qh[:r])
+        Gg, Bg = normal_equations_at(GE, r, max(r_list))
         for p in range(len(b1)):
             check_operators(G, B, r, b1[p], b2[p], views[g][p].cpu().numpy(), (r, p), k=Qh.shape[1])
+            check_solver_only(Gg, Bg, r, b1[p], b2[p], views[g][p].cpu().numpy(), (r, b1[p], b2[p]))
 
 
 def test_infer_exact_recovery(gpu_lib):

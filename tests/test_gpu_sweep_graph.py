@@ -18,6 +18,7 @@ import pytest
 
 import oracle as orc
 import synth
+from opcheck import check_operators as _check_ops
 
 pytestmark = pytest.mark.gpu
 
@@ -29,22 +30,8 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def eta_bound(k, d):
-    return U * ((k - 1) * np.sqrt(d) + 10 * d)
-
-
 def check_operators(G, B, r, b1, b2, O_gpu, where, k):
-    M = G + np.diag(orc.regularizer(r, b1, b2))
-    O_ref = orc.solve_operators(G, B, r, b1, b2, method="lu")
-
-    def eta(O):
-        X = O.T
-        return np.linalg.norm(M @ X - B) / (np.linalg.norm(M) * np.linalg.norm(X) + np.linalg.norm(B))
-
-    e_gpu, e_ref = eta(O_gpu), eta(O_ref)
-    assert e_gpu <= eta_bound(k, M.shape[0]), (where, e_gpu)
-    tol = max(1e-10, 2 * np.linalg.cond(M) * max(e_gpu, e_ref, U))
-    assert rel(O_gpu, O_ref) <= tol, (where, rel(O_gpu, O_ref), tol)
+    _check_ops(G, B, r, b1, b2, O_gpu, k, where)
 
 
 @pytest.fixture(scope="module")
