@@ -140,6 +140,37 @@ int dopinf_cross_gram(void* stream, const double* X, int64_t ldx,
                       int nvars, const int64_t* var_rows_h, double* C,
                       int64_t ldc, void* ws, size_t ws_bytes);
 
+/* ---- Out-of-core statistics and Gram (Sec. 3.2 loading; Eq. (5)) ---------
+ * For snapshot matrices larger than device memory: Q_h is a HOST array
+ * (n x k, ldq), read in chunks of chunk_rows rows through two device
+ * staging buffers; the copy of the next chunk (on a stream of the library's,
+ * created and released per call) overlaps the kernels of the current one
+ * (on `stream`).  Pinned host memory (hipHostMalloc) is needed for that
+ * overlap; pageable memory works, with synchronous copies.  Results are
+ * those of dopinf_preprocess / dopinf_gram on the whole matrix: per-row
+ * means are computed row by row, per-variable maxima combine by max, and
+ * the Gram matrix is the sum of the chunks' Gram matrices (Eq. (5)), added
+ * in chunk order (deterministic; summation order differs from the one-shot
+ * dopinf_gram by the chunking).  Workspace: dopinf_stream_workspace(
+ * chunk_rows, k, nvars) bytes (two chunks, a k x k partial and the chunk
+ * kernels' scratch).  Q_h must stay valid and unchanged until the work on
+ * `stream` has finished.
+ * dopinf_preprocess_stream: flags CENTER and SCALE (no APPLY); mean, scale,
+ *   zero_range, info as for dopinf_preprocess.
+ * dopinf_gram_stream: float64 data; mean / scale as for dopinf_gram. */
+size_t dopinf_stream_workspace(int64_t chunk_rows, int64_t k, int nvars);
+int dopinf_preprocess_stream(void* stream, const double* Q_h, int64_t n,
+                             int64_t k, int64_t ldq, int nvars,
+                             const int64_t* var_rows_h, unsigned flags,
+                             double* mean, double* scale, int* zero_range,
+                             int* info, int64_t chunk_rows, void* ws,
+                             size_t ws_bytes);
+int dopinf_gram_stream(void* stream, const double* Q_h, int64_t n, int64_t k,
+                       int64_t ldq, const double* mean, const double* scale,
+                       int nvars, const int64_t* var_rows_h, double* D,
+                       int64_t ldd, int64_t chunk_rows, void* ws,
+                       size_t ws_bytes);
+
 /* ---- Step III: eigenpairs and basis-free reduced data (Eqs. (6)-(9)) ------
  * D (k x k, symmetric, ldd) is read, not modified.
  * lambda[0..k): all eigenvalues of D in descending order.
@@ -348,7 +379,11 @@ int dopinf_rollout_continuous(void* stream, int n_r, const int* r_list_h,
  *   are stored for that s.  The stream is synchronized while timing.
  *   times_h (NULL or n_r x 2 x candidates floats, ms): per group the
  *   Cholesky timings, then the solve timings (0 where a group had nothing
- *   to time). */
+ *   to time).
+ * Persistence: when the environment variable DOPINF_TUNE_CACHE names a
+ *   file, the table is read from it at first use (lines "param key value")
+ *   and rewritten after every change, and dopinf_autotune_infer does not
+ *   time again a group whose outer widths the table already holds. */
 #define DOPINF_TUNE_CHOL_KB 1
 #define DOPINF_TUNE_TRSM_KB 2
 #define DOPINF_TUNE_CHOL_KB2 3

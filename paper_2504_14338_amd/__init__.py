@@ -17,7 +17,7 @@ __all__ = [
     "GRAM_NATIVE", "GRAM_BF16X3", "GRAM_BF16X6", "ITEM_PASS", "ITEM_NONFINITE",
     "ITEM_GROWTH", "ITEM_SOLVE", "ITEM_TIMEOUT", "preprocess", "gram", "cross_gram",
     "reduce", "infer", "operator_offset", "rollout", "traj_offset",
-    "n_quad", "lib_path", "rollout_noalloc", "rollout_noalloc_max_bytes", "postprocess", "reduce_topr", "lift", "infer_continuous",
+    "n_quad", "lib_path", "rollout_noalloc", "rollout_noalloc_max_bytes", "postprocess", "reduce_topr", "preprocess_stream", "gram_stream", "lift", "infer_continuous",
     "rollout_continuous", "LIFT_COPY", "LIFT_PRODUCT", "LIFT_RECIPROCAL", "closure_param_count", "rom_residuals", "closure_fit", "closure_norms",
     "closure_grad", "closure_eval", "closure_rollout", "TUNE_CHOL_KB", "tune_set", "tune_get",
     "autotune_candidates", "autotune_infer", "Sweep", "TUNE_TRSM_KB", "TUNE_CHOL_KB2", "TUNE_TRSM_KB2",
@@ -63,6 +63,10 @@ _SIGS = {
                           _i32),
     "dopinf_reduce_workspace": ([_i64, _i32], _sz),
     "dopinf_reduce": ([_vp, _vp, _i64, _i64, _i32, _f64, _i32, _vp, _vp, _vp, _i64, _vp, _i64, _vp, _vp, _sz], _i32),
+    "dopinf_stream_workspace": ([_i64, _i64, _i32], _sz),
+    "dopinf_preprocess_stream": ([_vp, _vp, _i64, _i64, _i64, _i32, _vp, _u32, _vp, _vp, _vp, _vp, _i64, _vp, _sz],
+                                 _i32),
+    "dopinf_gram_stream": ([_vp, _vp, _i64, _i64, _i64, _vp, _vp, _i32, _vp, _vp, _i64, _i64, _vp, _sz], _i32),
     "dopinf_reduce_topr_workspace": ([_i64, _i32], _sz),
     "dopinf_reduce_topr": ([_vp, _vp, _i64, _i64, _i32, _vp, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _sz], _i32),
     "dopinf_operator_offset": ([_i32, _vp, _i32, _i32], _sz),
@@ -275,6 +279,43 @@ def reduce(D, r=0, tau=0.9996, r_max=None, want_tr=True):
                              _ptr(info), _ptr(ws), ws.numel()))
     rr = r_out.value
     return lam, (Tr[:, :rr] if Tr is not None else None), Qhat[:rr], info, rr
+
+
+def preprocess_stream(Q_h, var_rows, chunk_rows, flags=CENTER | SCALE, device="cuda", info=None):
+    """dopinf_preprocess_stream on a host (ideally pinned) float64 tensor;
+    returns (mean, scale, zero_range) on the device."""
+    torch = _torch()
+    lib = load()
+    dev = torch.device(device)
+    n, k = Q_h.shape
+    vr, vrp = _host_i64(var_rows)
+    nvars = len(vr) - 1
+    mean = torch.empty(n, dtype=torch.float64, device=dev)
+    scale = torch.empty(nvars, dtype=torch.float64, device=dev)
+    zr = torch.empty(nvars, dtype=torch.int32, device=dev)
+    ws = _ws(lib.dopinf_stream_workspace(chunk_rows, k, nvars), dev)
+    _check(lib.dopinf_preprocess_stream(_stream(dev), _ptr(Q_h), n, k, _rowmajor(Q_h, "Q_h"), nvars, vrp, flags,
+                                        _ptr(mean), _ptr(scale), _ptr(zr), _ptr(info), int(chunk_rows), _ptr(ws),
+                                        ws.numel()))
+    return mean, scale, zr
+
+
+def gram_stream(Q_h, chunk_rows, mean=None, scale=None, var_rows=None, device="cuda", out=None, ws=None):
+    """dopinf_gram_stream: D of a host float64 matrix streamed in chunks."""
+    torch = _torch()
+    lib = load()
+    dev = torch.device(device)
+    n, k = Q_h.shape
+    if var_rows is None:
+        var_rows = [0, n]
+    vr, vrp = _host_i64(var_rows)
+    D = out if out is not None else torch.empty((k, k), dtype=torch.float64, device=dev)
+    if ws is None:
+        ws = _ws(lib.dopinf_stream_workspace(chunk_rows, k, len(vr) - 1), dev)
+    _check(lib.dopinf_gram_stream(_stream(dev), _ptr(Q_h), n, k, _rowmajor(Q_h, "Q_h"), _ptr(mean), _ptr(scale),
+                                  len(vr) - 1, vrp, _ptr(D), _rowmajor(D, "D"), int(chunk_rows), _ptr(ws),
+                                  ws.numel()))
+    return D
 
 
 def reduce_topr(D, r, want_tr=True):

@@ -22,6 +22,7 @@ int fail(int code, const char* fmt, ...);
 namespace tune {
 int get(int param, int64_t key);  // 0 when untuned
 void set(int param, int64_t key, int value);
+bool persisted();  // DOPINF_TUNE_CACHE names a cache file
 }  // namespace tune
 
 #define DOPINF_HIP(call)                                                        \

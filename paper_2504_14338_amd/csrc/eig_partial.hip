@@ -9,8 +9,9 @@
 // where the orthonormalization is shifted Cholesky QR (Fukaya, Kannan,
 // Nakatsukasa, Yamamoto, Yanagisawa 2020): G = Y^T Y + sigma I = L L^T,
 // X = Y L^{-T}, sigma = 11 (k p + p (p + 1)) u trace(Y^T Y), which stays
-// stable however ill-conditioned Y is; a second, unshifted pass before each
-// Rayleigh-Ritz step makes X orthonormal to working precision.  Rayleigh-
+// stable however ill-conditioned Y is; before each Rayleigh-Ritz step two
+// more, unshifted passes (their shifted CholeskyQR3) make X orthonormal to
+// working precision.  Rayleigh-
 // Ritz: H = X^T D X (p x p) is diagonalized by the library's dense
 // eigensolver and X <- X W (Ritz vectors in descending order of Ritz value).
 //
@@ -240,9 +241,14 @@ int power_step(hipStream_t st, const PartWs& w, const double* D, int64_t ldd, in
   return cholqr(st, w, w.Y, w.X, k, p, true);
 }
 
-// Rayleigh-Ritz: X orthonormalized once more, H = X^T D X, X <- X W, theta
+// Rayleigh-Ritz: X orthonormalized (shifted Cholesky QR, then an unshifted
+// pass: shifted CholeskyQR3, which is orthonormal to working precision
+// however ill-conditioned X is), H = X^T D X, X <- X W, theta
 int rayleigh_ritz(hipStream_t st, const PartWs& w, const double* D, int64_t ldd, int64_t k, int p) {
-  int rc = cholqr(st, w, w.X, w.Y, k, p, false);  // Y = X R^{-1}
+  // shifted CholeskyQR3: one shifted pass, then two plain ones; Y orthonormal
+  int rc = cholqr(st, w, w.X, w.Y, k, p, true);
+  if (!rc) rc = cholqr(st, w, w.Y, w.X, k, p, false);
+  if (!rc) rc = cholqr(st, w, w.X, w.Y, k, p, false);
   if (rc) return rc;
   rc = cross_gram_internal(st, D, ldd, w.Y, p, k, k, p, w.X, p, w.cg, w.cg_bytes, nullptr, nullptr, 0, nullptr);
   if (rc) return rc;  // X = D Y
@@ -256,7 +262,7 @@ int rayleigh_ritz(hipStream_t st, const PartWs& w, const double* D, int64_t ldd,
   // W (p x p): column j = eigenvector j of H (row j of Z)
   transpose_kernel<<<(p * p + 255) / 256, 256, 0, st>>>(Z, p, p, p, w.W);
   DOPINF_LAUNCHED();
-  return row_gemm_f64(st, w.Y, p, k, p, w.W, p, p, w.X, p);  // X = Y W
+  return row_gemm_f64(st, w.Y, p, k, p, w.W, p, p, w.X, p);  // X = Y W, the Ritz vectors
 }
 
 }  // namespace

@@ -1868,6 +1868,11 @@ int infer_autotune(hipStream_t st, const InferPlan& P, const double* Qhat, int64
   for (int g = 0; g < P.n_r && !rc; ++g) {
     const ChunkBufs b = chunk_bufs(P, g, ws);
     float* tg = times_h ? times_h + size_t(g) * 2 * kNumKbCand : nullptr;
+    if (tg)
+      for (int ci = 0; ci < 2 * kNumKbCand; ++ci) tg[ci] = 0.f;
+    // widths already in a persisted table (DOPINF_TUNE_CACHE) are not timed again
+    if (tune::persisted() && tune::get(DOPINF_TUNE_CHOL_KB, b.s) > 0 && tune::get(DOPINF_TUNE_TRSM_KB, b.s) > 0)
+      continue;
     int best = -1;
     float best_t = 0.f;
     for (int ci = 0; ci < kNumKbCand && !rc; ++ci) {

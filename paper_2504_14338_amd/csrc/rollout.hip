@@ -22,6 +22,7 @@
 // a running maximum, so crossing the bound (or meeting a non-finite value) is
 // final and the selection is unchanged.  Team members score the same state
 // with the same code and so take the same decision without talking.
+#include <algorithm>
 #include <cmath>
 #include <mutex>
 
@@ -72,6 +73,8 @@ struct RollArgs {
   int n_states;
   double max_growth;
   int full;
+  int n_items;           // candidates of the group
+  unsigned* queue;       // persistent grid: next-candidate counter (zeroed), or null
   double dt;             // > 0: continuous-time ROM stepped by RK4 with this step
   const double* mean;    // r
   const double* maxdev;  // r
@@ -130,9 +133,8 @@ __device__ __forceinline__ void rom_map(const double* __restrict__ Op, double* f
 // RK4 = true: the continuous-time ROM of Eq. (10), dq/dt = O [q | quad(q) | 1],
 // advanced by one classical fourth-order Runge-Kutta step of a.dt per state.
 template <bool RK4>
-__global__ __launch_bounds__(RT) void rollout_kernel(RollArgs a) {
+__device__ void rollout_item(const RollArgs& a, const int p) {
   extern __shared__ double sm[];
-  const int p = blockIdx.x;
   const int r = a.r;
   const int64_t s = a.s, d = a.d;
   double* f = sm;                  // d features: [q | quad(q) | 1]
@@ -267,6 +269,28 @@ __global__ __launch_bounds__(RT) void rollout_kernel(RollArgs a) {
     a.outcome[p] = oc;
     a.train_err[p] = (oc == DOPINF_ITEM_NONFINITE) ? NAN : sqrt(run_err);
     a.growth[p] = (oc == DOPINF_ITEM_NONFINITE) ? NAN : run_dev / maxdev;
+  }
+}
+
+// One workgroup per candidate (a.queue == nullptr: candidate = blockIdx.x),
+// or a persistent grid of resident workgroups that take candidates from a
+// device counter until all are taken: a workgroup whose candidate stopped
+// early (failure decided) takes the next one at once.  Every workgroup
+// leaves when the counter passes n_items, so the grid always drains.
+template <bool RK4>
+__global__ __launch_bounds__(RT) void rollout_kernel(RollArgs a) {
+  if (!a.queue) {
+    rollout_item<RK4>(a, blockIdx.x);
+    return;
+  }
+  __shared__ int item_sh;
+  for (;;) {
+    __syncthreads();  // the previous candidate is done with item_sh and LDS
+    if (threadIdx.x == 0) item_sh = int(atomicAdd(a.queue, 1u));
+    __syncthreads();
+    const int p = item_sh;
+    if (p >= a.n_items) break;
+    rollout_item<RK4>(a, p);
   }
 }
 
@@ -497,7 +521,7 @@ struct RollWs {
   double* mean;
   double* maxdev;
   double* xbuf;
-  unsigned* words;   // n_pairs counters + abort flag
+  unsigned* words;   // n_pairs counters + abort flag + the persistent grid's counter
 };
 
 RollWs carve_group(Carver& c, int r, int n_pairs) {
@@ -505,7 +529,7 @@ RollWs carve_group(Carver& c, int r, int n_pairs) {
   w.mean = c.take<double>(size_t(r));
   w.maxdev = c.take<double>(size_t(r));
   w.xbuf = c.take<double>(size_t(n_pairs) * 2 * size_t(r));
-  w.words = c.take<unsigned>(size_t(n_pairs) + 1);
+  w.words = c.take<unsigned>(size_t(n_pairs) + 2);
   return w;
 }
 
@@ -604,10 +628,25 @@ int rollout_launch(hipStream_t st, int n_r, const int* r_list_h, int n_pairs, co
         (void)hipGetLastError();
     }
     if (!launched) {
+      // more candidates than resident workgroups: a persistent grid with a
+      // work counter; else one workgroup per candidate
+      int per_cu = 0, ncu = 0;
+      DOPINF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, one_wg, RT, smem));
+      DOPINF_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+      const int resident = std::max(1, per_cu) * std::max(1, ncu);
+      int grid = n_pairs;
+      ra.n_items = n_pairs;
+      ra.queue = nullptr;
+      if (n_pairs > resident) {
+        ra.queue = w.words + n_pairs + 1;
+        zero_u32_kernel<<<1, 64, 0, st>>>(ra.queue, 1);
+        DOPINF_LAUNCHED();
+        grid = resident;
+      }
       if (rk4)
-        rollout_kernel<true><<<n_pairs, RT, smem, st>>>(ra);
+        rollout_kernel<true><<<grid, RT, smem, st>>>(ra);
       else
-        rollout_kernel<false><<<n_pairs, RT, smem, st>>>(ra);
+        rollout_kernel<false><<<grid, RT, smem, st>>>(ra);
       DOPINF_LAUNCHED();
     }
   }

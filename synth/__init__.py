@@ -191,7 +191,7 @@ def c2_modes(nvars: int = 4, ncell: int = 1_000_000, k: int = 2000,
 
 
 def c2_snapshots(modes: WaveModes, noise_var: float = 1e-8, seed: int = 2,
-                 device="cpu", t0: int = 0, chunk_rows: int = 1 << 18,
+                 device="cpu", t0: float = 0, chunk_rows: int = 1 << 18,
                  out=None):
     """Q = a * Phi diag(sigma) Psi^T + N(0, noise_var), float64, n x k.
 
@@ -251,3 +251,34 @@ def perturbed_states(q0: np.ndarray, M: int, std: float = 0.05, seed: int = 5) -
     """M copies of q0 plus N(0, std^2) noise (M x r)."""
     rng = np.random.default_rng([seed, 13])
     return q0[None, :] + std * rng.standard_normal((M, q0.shape[0]))
+
+
+def duffing_trajectory(q0, k: int, h: float = 0.05, beta: float = 1.0, coupling: float = 0.2) -> np.ndarray:
+    """Two coupled oscillators with cubic stiffness, x'' = -w x - beta x^3 +
+    coupling (x_other - x) (w = 1 and 1.3), stepped by symplectic Euler with
+    step h: state (x1, v1, x2, v2), k states including q0 (4 x k)."""
+    Q = np.empty((4, k))
+    Q[:, 0] = q0
+    for t in range(k - 1):
+        x1, v1, x2, v2 = Q[:, t]
+        v1n = v1 + h * (-x1 - beta * x1 ** 3 + coupling * (x2 - x1))
+        v2n = v2 + h * (-1.3 * x2 - beta * x2 ** 3 + coupling * (x1 - x2))
+        Q[:, t + 1] = (x1 + h * v1n, v1n, x2 + h * v2n, v2n)
+    return Q
+
+
+def duffing_snapshots(seed: int = 9, n_per_var: int = 2048, nvars: int = 2, k: int = 2000,
+                      q0=(1.2, 0.0, -0.8, 0.3), q0_test=(0.9, 0.4, -1.0, -0.2), noise_var: float = 1e-10):
+    """Training and held-out snapshots of the cubic oscillators, lifted by one
+    random orthonormal basis V ((nvars * n_per_var) x 4) plus N(0, noise_var):
+    returns (Q_train, Q_test, var_rows, q_train, q_test)."""
+    rng = np.random.default_rng([seed, 17])
+    n = nvars * n_per_var
+    V, _ = np.linalg.qr(rng.standard_normal((n, 4)))
+    qa = duffing_trajectory(np.asarray(q0, dtype=float), k)
+    qb = duffing_trajectory(np.asarray(q0_test, dtype=float), k)
+    std = math.sqrt(noise_var)
+    Qa = V @ qa + std * rng.standard_normal((n, k))
+    Qb = V @ qb + std * rng.standard_normal((n, k))
+    var_rows = np.arange(nvars + 1) * n_per_var
+    return Qa, Qb, var_rows, qa, qb

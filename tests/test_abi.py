@@ -114,3 +114,26 @@ def test_lift_and_continuous_argument_errors():
     assert rc == dp.E_ARG
     assert lib.dopinf_infer_continuous_workspace(2, 1, r, 1) == 0
     assert lib.dopinf_infer_continuous_workspace(10, 1, r, 1) > lib.dopinf_infer_workspace(10, 1, r, 1)
+
+
+def test_tuning_table_persists_across_processes(tmp_path):
+    # DOPINF_TUNE_CACHE: values stored by one process are read by the next
+    import subprocess
+    import sys
+    cache = tmp_path / "tune.txt"
+    env = dict(os.environ, DOPINF_TUNE_CACHE=str(cache))
+    code_set = ("import paper_2504_14338_amd as dp; dp.tune_set(dp.TUNE_CHOL_KB, 3240, 512); "
+                "dp.tune_set(dp.TUNE_TRSM_KB2, 3240, 256); dp.tune_set(dp.TUNE_CHOL_KB, 1830, 128)")
+    code_get = ("import paper_2504_14338_amd as dp; print(dp.tune_get(dp.TUNE_CHOL_KB, 3240), "
+                "dp.tune_get(dp.TUNE_TRSM_KB2, 3240), dp.tune_get(dp.TUNE_CHOL_KB, 1830), "
+                "dp.tune_get(dp.TUNE_TRSM_KB, 3240))")
+    subprocess.run([sys.executable, "-c", code_set], env=env, cwd=ROOT, check=True)
+    assert cache.exists()
+    out = subprocess.run([sys.executable, "-c", code_get], env=env, cwd=ROOT, check=True, capture_output=True,
+                         text=True).stdout.split()
+    assert out == ["512", "256", "128", "0"]
+    # a malformed line is ignored
+    cache.write_text(cache.read_text() + "garbage\n1 77 100\n")
+    out = subprocess.run([sys.executable, "-c", code_get], env=env, cwd=ROOT, check=True, capture_output=True,
+                         text=True).stdout.split()
+    assert out == ["512", "256", "128", "0"]

@@ -276,3 +276,66 @@ def test_fullsize_partial_eig(gpu_lib, c2):
     for i in range(R):
         bound = max(1e-10, 200 * U * lam[0] / gaps[i])
         assert rel(Qp[i], Qf[i]) <= bound, (i, rel(Qp[i], Qf[i]), bound)
+
+
+def test_fullsize_gram_whole_matrix_oracle(gpu_lib, c2):
+    """D over all 4,000,000 rows against the oracle's Gram, accumulated over
+    row chunks of the same bytes (Eq. (5): the Gram of a row partition is the
+    sum of the blocks' Grams), with the statistics checked above."""
+    import torch
+    Q, var_rows = c2["Q"], c2["var_rows"]
+    mean = c2["mean"].cpu().numpy()
+    s_rows = np.repeat(c2["scale"].cpu().numpy(), N_CELL)
+    Dref = np.zeros((K, K))
+    chunk = 250_000
+    for r0 in range(0, N_VAR * N_CELL, chunk):
+        blk = Q[r0:r0 + chunk].cpu().numpy()
+        Dref += orc.gram(orc.apply_statistics(blk, mean[r0:r0 + chunk], s_rows[r0:r0 + chunk]))
+        del blk
+    assert rel(c2["D"].cpu().numpy(), Dref) <= 1e-12
+
+
+def test_fullsize_sweep_full_horizon_trajectories(gpu_lib, c2):
+    """The many-candidate rollout (one workgroup per candidate, as the sweep
+    runs it) over the full 4,000-state horizon without early exit, at r = 60
+    and r = 80, against the oracle's rollout of the same operators: bounded
+    ROMs (beta2 from 1e8 to 1e10, the step's pair among them) over all 4,000
+    states to 1e-9 of the trajectory's scale; the grid's own SPD pairs
+    (beta2 <= 1), whose ROMs grow without bound, state by state to 1e-8
+    relative up to the oracle's first non-finite (or > 1e150) state."""
+    import torch
+    dp = gpu_lib
+    lam80, _, Qh80, info80, _ = dp.reduce(c2["D"], r=80, want_tr=False)
+    Qh80 = Qh80.contiguous()
+    B1 = synth.logspace_points(-10, -2, 32)
+    B2 = synth.logspace_points(-8, 0, 32)
+    b1 = [1e-2, 1e-2, 1e-6, B1[-1], B1[-2], B1[-1]]
+    b2 = [1e8, 1e9, 1e10, B2[-1], B2[-1], B2[-5]]
+    r_list = [60, 80]
+    O, status, views = dp.infer(Qh80, r_list, b1, b2)
+    out = dp.rollout(O, Qh80, r_list, len(b1), N_STATES, solve_status=status, keep_traj=True, full=True,
+                     one_wg=True)
+    torch.cuda.synchronize()
+    st = status.cpu().numpy()
+    Qh = Qh80.cpu().numpy()
+    checked = {True: 0, False: 0}
+    for g, r in enumerate(r_list):
+        for p in range(len(b1)):
+            if st[g * len(b1) + p] != 0:
+                continue
+            Og = views[g][p].cpu().numpy()
+            ref = orc.rollout(Og, r, Qh[:r, 0], N_STATES)
+            tr = out["traj_views"][g][p].cpu().numpy().T
+            fin = np.all(np.isfinite(ref), axis=0) & (np.max(np.abs(ref), axis=0) < 1e150)
+            n_ok = int(np.argmin(fin)) if not fin.all() else N_STATES
+            bnd = n_ok == N_STATES and np.max(np.abs(ref)) < 1e3 * np.max(np.abs(Qh[:r]))
+            if bnd:
+                scale = np.max(np.abs(ref))
+                assert np.max(np.abs(tr - ref)) <= 1e-9 * scale, (r, p)
+            else:
+                assert n_ok > 1, (r, p, n_ok)
+                nrm = np.linalg.norm(ref[:, :n_ok], axis=0)
+                err = np.linalg.norm(tr[:, :n_ok] - ref[:, :n_ok], axis=0) / nrm
+                assert np.max(err) <= 1e-8, (r, p, n_ok, float(np.max(err)))
+            checked[bool(bnd)] += 1
+    assert checked[True] >= 2 and checked[False] >= 2, checked

@@ -82,6 +82,43 @@ def test_fullsize_lowp_gram(gpu_lib, c3, algo_name):
     assert np.max(np.abs(D[np.ix_(cols, cols)] - Dref) / cs) <= tol
 
 
+def test_fullsize_lowp_against_oracle_of_rounded_data(gpu_lib, c3):
+    """Each reduced-precision form against the oracle on the float32-rounded
+    data (the reference that isolates the Gram's arithmetic): the oracle's
+    Gram over all 4,000,000 rows accumulated in row chunks (Eq. (5)), its
+    eigenpairs and Qhat at r = 60; the forms' D within their tolerance, and
+    Qhat within 1e-6 for the forms that meet it (float32, split-BF16x6).
+    Errors against the float64 data itself are the float64 path's, which is
+    within 1e-12 (D) of the oracle, plus these."""
+    import torch
+    dp = gpu_lib
+    Q32, var_rows = c3["Q32"], c3["var_rows"]
+    mean = c3["mean32"].cpu().numpy()
+    s_rows = np.repeat(c3["scale32"].cpu().numpy(), 1_000_000)
+    Dref = np.zeros((2000, 2000))
+    chunk = 250_000
+    for r0 in range(0, 4_000_000, chunk):
+        blk = Q32[r0:r0 + chunk].cpu().numpy().astype(np.float64)
+        Dref += orc.gram(orc.apply_statistics(blk, mean[r0:r0 + chunk], s_rows[r0:r0 + chunk]))
+        del blk
+    lam_o, U_o = orc.eig_desc(Dref)
+    _, Qh_o = orc.reduce_basis_free(lam_o, U_o, 60)
+    sel = lam_o >= 1e-10 * lam_o[0]
+    for name, algo in (("native", dp.GRAM_NATIVE), ("bf16x3", dp.GRAM_BF16X3), ("bf16x6", dp.GRAM_BF16X6)):
+        D = dp.gram(Q32, c3["mean32"], c3["scale32"], var_rows, algo=algo)
+        lam, _, Qh, info, _ = dp.reduce(D, r=60, want_tr=False)
+        torch.cuda.synchronize()
+        Dn = D.cpu().numpy()
+        assert rel(Dn, Dref) <= TOLS[name], (name, rel(Dn, Dref))
+        ln = lam.cpu().numpy()
+        lerr = np.abs(ln[sel] - lam_o[sel]) / lam_o[sel]
+        qerr = rel(Qh.cpu().numpy(), Qh_o)
+        print(f"{name}: D {rel(Dn, Dref):.3g}, lambda max {lerr.max():.3g} median {np.median(lerr):.3g}, "
+              f"Qhat {qerr:.3g}", flush=True)
+        if name in ("native", "bf16x6"):
+            assert qerr <= 1e-6, (name, qerr)
+
+
 @pytest.fixture(scope="module")
 def c5(gpu_lib):
     import torch
@@ -95,9 +132,16 @@ def c5(gpu_lib):
     Qh = Qhat.contiguous()
     O, status, views = dp.infer(Qh, [r], [1e-2], [1e8])
     assert int(status.item()) == 0 and int(info.item()) == 0
-    del Q
+    # held-out snapshots at the half-sample times t = 2000.5 .. 3999.5 (the
+    # training window's integer frequencies repeat every 2000 samples, so
+    # whole-sample times would revisit training states), projected without a
+    # basis: Qhat_test = T_r^T (Qs^T Qs_test) (Eq. (8), training statistics)
+    Qt = synth.c2_snapshots(m, noise_var=1e-8, seed=3, device=torch.device("cuda:0"), t0=k + 0.5)
+    C = dp.cross_gram(Q, Qt, mean=mean, scale=scale, var_rows=var_rows)
+    Qh_test = dp.cross_gram(Tr.contiguous(), C).contiguous()
+    del Q, Qt, C
     torch.cuda.empty_cache()
-    return dict(r=r, Qh=Qh, O=views[0][0].contiguous())
+    return dict(r=r, Qh=Qh, O=views[0][0].contiguous(), Qh_test=Qh_test)
 
 
 def test_fullsize_closure(gpu_lib, c5):
@@ -159,3 +203,38 @@ def test_fullsize_closure(gpu_lib, c5):
     # every member of the closure ensemble ends with a defined outcome code
     oc_c = out_c["outcome"].cpu().numpy()
     assert oc_c.shape == (M,) and np.all((oc_c >= 0) & (oc_c <= 4))
+
+
+def test_fullsize_closure_on_heldout_residuals(gpu_lib, c5):
+    """The trained closure on snapshots it was not trained on: the one-step
+    residual RMS of the method's own r = 40 ROM on held-out half-sample
+    snapshots, without and with the closure, and the 2000-state held-out
+    rollout errors.  On this workload the residual is not a function of the
+    resolved state (the truncated modes are independent oscillators), so the
+    closure does not generalize: measured 0.43 -> 0.69 (one step) and
+    0.23 -> 0.33 (rollout), i.e. it hurts.  Asserted: the held-out residuals
+    against the oracle and finite, reported numbers; the gain where the model
+    error is a function of the state is asserted on the cubic oscillators
+    (test_gpu_closure.py)."""
+    import torch
+    dp = gpu_lib
+    r, Qh, O, Qt = c5["r"], c5["Qh"], c5["O"], c5["Qh_test"]
+    X = Qh[:, :-1].T.contiguous()
+    Y = dp.rom_residuals(O, Qh)
+    p0 = torch.from_numpy(synth.mlp_init(r, seed=5))
+    params, norm, log = dp.closure_fit(X, Y, p0, epochs=200, batch=256, lr=1e-3)
+    Rt = dp.rom_residuals(O, Qt)
+    Gt, _ = dp.closure_eval(params, norm, Qt[:, :-1].T.contiguous())
+    rms_plain = float(torch.sqrt(torch.mean(Rt * Rt)).item())
+    rms_closed = float(torch.sqrt(torch.mean((Rt - Gt) ** 2)).item())
+    _, gmax = dp.closure_eval(params, norm, X)
+    thr = 3.0 * float(gmax.item())
+    q0t = Qt[:, 0].reshape(1, r).contiguous()
+    e_c = float(dp.closure_rollout(O, params, norm, thr, q0t, 2000, Qt)["err"].item())
+    e_p = float(dp.closure_rollout(O, params, norm, 0.0, q0t, 2000, Qt)["err"].item())
+    print(f"held-out one-step residual RMS: plain {rms_plain:.4g}, closure {rms_closed:.4g}; "
+          f"2000-state rollout error: plain {e_p:.4g}, closure {e_c:.4g}", flush=True)
+    # the oracle's residuals of the same ROM on the same held-out data
+    Rref = cl.residuals(O.cpu().numpy(), r, Qt.cpu().numpy())
+    assert np.max(np.abs(Rt.cpu().numpy() - Rref)) <= 1e-10 * np.max(np.abs(Qt.cpu().numpy()))
+    assert np.isfinite(rms_closed) and np.isfinite(rms_plain) and np.isfinite(e_c) and np.isfinite(e_p)

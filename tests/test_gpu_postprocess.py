@@ -60,12 +60,8 @@ def test_postprocess_rows_parity_c1(gpu_lib, c1, m):
     if m > 4:
         rows[:4] = [0, 4095, 4096, n - 1]
     rows_d = torch.from_numpy(rows.astype(np.int64)).cuda()
-    # Qtilde: a 1200-state rollout of the inferred ROM (r x N, N not a
-    # multiple of the 128-column tile)
-    Qh = c1["Qhat"]
-    O, status, _ = dp.infer(Qh, [10], [1e-6], [1e-4])
-    out = dp.rollout(O, Qh, [10], 1, 1200, solve_status=status, keep_traj=True, full=True)
-    Qt = out["traj_views"][0][0].t().contiguous()
+    # Qtilde: the reduced training data, r x 600 (600 = 4 x 128 + 88 columns)
+    Qt = c1["Qhat"]
     V, pred, info = dp.postprocess(c1["Qd"], c1["Tr"], rows=rows_d, Qtilde=Qt, mean=c1["mean"],
                                    scale=c1["scale"], var_rows=c1["var_rows"])
     torch.cuda.synchronize()
@@ -74,19 +70,16 @@ def test_postprocess_rows_parity_c1(gpu_lib, c1, m):
     Tr = c1["Tr"].cpu().numpy()
     check_V(c1["Q"], mean, scale, np.asarray(c1["var_rows"]), Tr, rows, V.cpu().numpy())
     Qtn = Qt.cpu().numpy()
-    # this pair's rollout leaves the finite range after a few hundred states:
-    # NaN columns of Qtilde give NaN columns of pred on both sides
-    fin = np.all(np.isfinite(Qtn), axis=0)
-    assert fin.sum() >= 100
     pg = pred.cpu().numpy()
-    assert np.all(np.isnan(pg[:, ~fin]))
-    Vr, pr = orc.postprocess(c1["Q"], mean, scale, c1["var_rows"], Tr, rows, Qtn[:, fin])
-    assert rel(pg[:, fin], pr) <= 1e-12
-    # the whole chain against the oracle's own statistics and basis
+    Vr, pr = orc.postprocess(c1["Q"], mean, scale, c1["var_rows"], Tr, rows, Qtn)
+    assert rel(pg, pr) <= 1e-12
+    # the whole chain against the oracle's own statistics, basis and Qhat
     ref = orc.pipeline(c1["Q"], c1["var_rows"], 10, 1e-6, 1e-4, 1200)
-    Vo, po = orc.postprocess(c1["Q"], ref["mu"], ref["s"], c1["var_rows"], ref["Tr"], rows, Qtn[:, fin])
+    Vo, po = orc.postprocess(c1["Q"], ref["mu"], ref["s"], c1["var_rows"], ref["Tr"], rows, ref["Qhat"])
     assert rel(V.cpu().numpy(), Vo) <= 1e-9
-    assert rel(pg[:, fin], po) <= 1e-9
+    assert rel(pg, po) <= 1e-9
+    # lifting the training data reproduces the snapshots to the noise level
+    assert np.max(np.abs(pg - c1["Q"][rows])) <= 10 * 1e-3
 
 
 def test_postprocess_all_rows_reconstructs_training_data(gpu_lib, c1):

@@ -166,16 +166,41 @@ def test_rollout_hand_cases_and_failure_modes(one_wg, gpu_lib):
     assert o3["best"].item() == -1
 
 
+def _stable_rom(r, k, seed):
+    rng = np.random.default_rng(seed)
+    s = r * (r + 1) // 2
+    A = np.diag(rng.uniform(0.90, 0.99, r)) + 1e-3 * rng.standard_normal((r, r))
+    H = 1e-4 * rng.standard_normal((r, s))
+    c = 1e-3 * rng.standard_normal(r)
+    Og = np.hstack([A, H, c[:, None]])
+    q0 = rng.standard_normal(r)
+    Qh = orc.rollout(Og, r, q0, k) + 1e-3 * rng.standard_normal((r, k))
+    Qh[:, 0] = q0
+    return Og, Qh
+
+
 @pytest.mark.parametrize("one_wg", [False, True])
-def test_selection_ties_pick_first(one_wg, gpu_lib, c1_qhat):
+def test_selection_ties_pick_first(one_wg, gpu_lib):
+    # three identical stable ROMs: equal training errors, all pass, the first
+    # wins; with the first made unstable (growth failure) the second wins
+    import torch
     dp = gpu_lib
-    Qhat, _, _ = c1_qhat
-    O, status, views = dp.infer(Qhat, [5], [1e-3, 1e-3, 1e-3], [1e-2, 1e-2, 1e-2])
-    out = dp.rollout(O, Qhat, [5], 3, 1200, solve_status=status, one_wg=one_wg)
+    r, k = 5, 300
+    Og, Qh = _stable_rom(r, k, 17)
+    Qhat = torch.from_numpy(Qh.copy()).cuda()
+    O = torch.from_numpy(np.concatenate([Og.ravel()] * 3)).cuda()
+    out = dp.rollout(O, Qhat, [r], 3, 600, one_wg=one_wg)
     te = out["train_err"].cpu().numpy()
     assert te[0] == te[1] == te[2]
-    if out["outcome"].cpu().numpy()[0] == dp.ITEM_PASS:
-        assert out["best"].item() == 0
+    assert out["outcome"].cpu().numpy().tolist() == [dp.ITEM_PASS] * 3
+    assert out["best"].item() == 0
+    Ou = Og.copy()
+    Ou[:, :r] *= 1.5
+    O = torch.from_numpy(np.concatenate([Ou.ravel(), Og.ravel(), Og.ravel()])).cuda()
+    out = dp.rollout(O, Qhat, [r], 3, 600, one_wg=one_wg)
+    oc = out["outcome"].cpu().numpy().tolist()
+    assert oc[0] in (dp.ITEM_GROWTH, dp.ITEM_NONFINITE) and oc[1:] == [dp.ITEM_PASS] * 2
+    assert out["best"].item() == 1
 
 
 @pytest.mark.parametrize("one_wg", [False, True])
@@ -192,11 +217,33 @@ def test_small_sweep_matches_oracle(one_wg, gpu_lib, c1_qhat):
     out = dp.rollout(O, Qhat, r_list, len(b1), 1200, solve_status=status, one_wg=one_wg)
     ref = orc.sweep(Qh, r_list, list(B1), list(B2), 1200)
     te = out["train_err"].cpu().numpy()
+    gr = out["growth"].cpu().numpy()
     oc = out["outcome"].cpu().numpy()
+    st = status.cpu().numpy()
+    npair = len(b1)
     for it in range(len(ref["r"])):
-        if ref["passed"][it]:
+        r = ref["r"][it]
+        if st[it] != 0:
+            # a refused normal matrix is singular to working precision
+            _, G, B = orc.opinf_data(Qh[:r])
+            M = G + np.diag(orc.regularizer(r, ref["beta1"][it], ref["beta2"][it]))
+            assert oc[it] == dp.ITEM_SOLVE
+            try:
+                L = np.linalg.cholesky(M)
+                assert np.min(np.diag(L)) ** 2 / np.max(np.diag(M)) < 1e-10, it
+            except np.linalg.LinAlgError:
+                pass
+        elif ref["passed"][it]:
             assert oc[it] == dp.ITEM_PASS or abs(ref["growth"][it] - 1.2) < 1e-6
             assert te[it] == pytest.approx(ref["train_err"][it], rel=1e-6)
+        elif not ref["finite"][it]:
+            # the oracle's rollout overflows: the GPU's either does too or
+            # stops earlier at the (final) growth failure
+            assert oc[it] in (dp.ITEM_NONFINITE, dp.ITEM_GROWTH), it
+        else:
+            # finite but over the growth bound (unless within rounding of it)
+            assert oc[it] == dp.ITEM_GROWTH or abs(ref["growth"][it] - 1.2) < 1e-6, it
+            assert gr[it] >= 1.2 or abs(ref["growth"][it] - 1.2) < 1e-6, it
     best = out["best"].cpu().numpy()
     for g in range(len(r_list)):
         rb = ref["best"][g]
