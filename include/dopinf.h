@@ -255,7 +255,11 @@ int dopinf_infer(void* stream, const double* Qhat, int64_t ldqh, int64_t k,
  * Few items (n_r * n_pairs small) are rolled out by teams of workgroups that
  * keep the operator rows on chip and exchange the state every step; a team
  * whose exchange does not complete within seconds gives up with outcome
- * DOPINF_ITEM_TIMEOUT (and train_err = growth = NaN).
+ * DOPINF_ITEM_TIMEOUT (and train_err = growth = NaN).  Many items are
+ * rolled out one workgroup per item (a persistent grid of resident
+ * workgroups taking items from a device counter when there are more items
+ * than resident workgroups), the operator streamed from memory every step.
+ * DOPINF_ROLLOUT_ONE_WG forces the one-workgroup form.
  * best[g] (device ints, n_r): item index (within the whole layout) of the
  * smallest train_err among passing items of group g, the first in layout
  * order on ties, -1 if none passes.

@@ -7,8 +7,10 @@ binding refuses to run when the library is missing: there is no fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 
@@ -669,6 +671,7 @@ class Sweep:
                                        _ptr(self.train_err), _ptr(self.growth), _ptr(self.outcome), _ptr(self.best),
                                        _ptr(self._ws), self._ws.numel(), C.byref(handle)))
         self._h = handle
+        _LIVE_SWEEPS.add(self)
         self.views = []
         for g, r in enumerate(self._rl):
             d = int(r) + n_quad(int(r)) + 1
@@ -691,10 +694,30 @@ class Sweep:
             self._h = None
 
     def __del__(self):
+        # no HIP call once the interpreter is shutting down: _close_sweeps
+        # (an exit handler) has closed every live sweep before that
+        if _SHUTTING_DOWN:
+            return
         try:
             self.close()
         except Exception:
             pass
+
+
+_LIVE_SWEEPS = weakref.WeakSet()
+_SHUTTING_DOWN = False
+
+
+@atexit.register
+def _close_sweeps():
+    """Release every captured sweep while the HIP runtime is still up."""
+    global _SHUTTING_DOWN
+    for sw in list(_LIVE_SWEEPS):
+        try:
+            sw.close()
+        except Exception:
+            pass
+    _SHUTTING_DOWN = True
 
 
 # ------------------------------------------------------- learned closure ---

@@ -15,10 +15,13 @@
 //  3. The top r eigenvectors of T by inverse iteration with partial-pivoting
 //     LU of T - lambda I (one wave per cluster, factors in LDS).  As in
 //     LAPACK's inverse-iteration routine xSTEIN, neighbouring eigenvalues
-//     closer than 1e-3 ||T|| form a cluster whose vectors are orthogonalized
-//     (modified Gram-Schmidt) against the cluster's earlier vectors inside
-//     every iteration: vectors computed one by one lose orthogonality like
-//     u ||T|| / gap, which would break Qhat Qhat^T = Lambda_r.
+//     closer than a separation tolerance form a cluster whose vectors are
+//     orthogonalized (modified Gram-Schmidt) against the cluster's earlier
+//     vectors inside every iteration.  Vectors computed one by one lose
+//     orthogonality like u ||T|| / gap; the tolerance 1e-5 ||T|| keeps that
+//     loss below ~1e-11 between clusters (xSTEIN's more conservative 1e-3
+//     ||T|| chains dozens of well-separated eigenvalues of a decaying
+//     spectrum into one cluster, which one wave then has to walk alone).
 //  4. Back-transformation u = P z (reflectors applied in reverse order), one
 //     workgroup per vector with z in LDS.
 //  5. Sign rule and Qhat / T_r formation.
@@ -494,7 +497,7 @@ __global__ __launch_bounds__(64) void tri_invit_kernel(const double* d, const do
   const int lane = threadIdx.x;
   const double tnorm = bounds[3];
   const double eps = 2.220446049250313e-16;
-  const double ctol = 1e-3 * fmax(tnorm, 1e-300);  // cluster separation of xSTEIN
+  const double ctol = 1e-5 * fmax(tnorm, 1e-300);  // cluster separation (header)
   if (j0 > 0 && fabs(lambda_desc[j0 - 1] - lambda_desc[j0]) <= ctol) return;  // not first of its cluster
   int j1 = j0 + 1;
   while (j1 < r && fabs(lambda_desc[j1 - 1] - lambda_desc[j1]) <= ctol) ++j1;
@@ -1089,6 +1092,18 @@ int eig_vectors_internal(hipStream_t st, const double* D, int64_t k, int64_t ldd
   if (!rc) rc = eig_vectors_stage(st, k, r, lambda, w);
   *Z = w.Z;
   return rc;
+}
+
+// All eigenvalues (descending) of the symmetric k x k matrix D, no vectors;
+// workspace eig_vectors_workspace(k, 1).
+int eig_values_internal(hipStream_t st, const double* D, int64_t k, int64_t ldd, double* lambda, int* info, void* ws,
+                        size_t ws_bytes) {
+  EigPlan pl{};
+  int rc = plan_sytrd(k, pl);
+  if (rc) return rc;
+  Carver c(ws, ws_bytes);
+  EigWs w = carve_eig(ws, ws_bytes, k, 1, 1024, c);
+  return eig_values_stage(st, D, k, ldd, lambda, info, w, pl);
 }
 
 // Sign rule, Qhat = Lambda_r^{1/2} U_r^T and T_r = U_r Lambda_r^{-1/2} from

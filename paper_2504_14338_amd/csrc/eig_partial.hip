@@ -16,18 +16,23 @@
 // eigensolver and X <- X W (Ritz vectors in descending order of Ritz value).
 //
 // Iteration count: the error of the j-th Ritz vector decays like
-// (lambda_{p+1} / lambda_j)^m.  After m0 iterations and a first Rayleigh-
-// Ritz step, rho = theta_p / theta_r (Ritz values) bounds that rate for all
-// j <= r, and the iteration continues until rho^m <= 1e-17, plus two extra
-// steps, then ends with a second Rayleigh-Ritz step.  When rho is too close
-// to 1 for that (more than kMaxIter iterations), or r is too large for the
-// block size, the full eigensolver runs instead.
+// (lambda_{p+1} / lambda_j)^m.  After m0 iterations a first Rayleigh-Ritz
+// step computes the Ritz values only: rho = theta_p / theta_r bounds that
+// rate for all j <= r, and the iteration continues until rho^m <= 1e-17,
+// plus two extra steps, then ends with a second Rayleigh-Ritz step that
+// computes the r leading Ritz vectors.  The shift damps directions whose
+// share of the block is near its relative size (see the driver), which
+// decides whether two products D (D X) may share one orthonormalization and
+// whether the r-th direction survives the iteration at all.  When it does
+// not, when rho is too close to 1 (more than kMaxIter iterations), or when r
+// is too large for the block size, the full eigensolver runs instead.
 //
 // Products: D X and X^T (D X) use the cross-Gram kernel (D is symmetric, so
 // D X = D^T X), Y^T Y the Gram kernel, X L^{-T} and X W the row-GEMM tile
 // kernel; the p x p Cholesky factor and its inverse come from one
 // workgroup with the packed triangles in LDS.
 #include <cmath>
+#include <utility>
 #include <vector>
 
 #include "common.hpp"
@@ -46,6 +51,8 @@ int row_gemm_f64(hipStream_t st, const double* A, int64_t lda, int64_t m, int64_
 size_t eig_vectors_workspace(int64_t k, int r);
 int eig_vectors_internal(hipStream_t st, const double* D, int64_t k, int64_t ldd, int r, double* lambda, int* info,
                          void* ws, size_t ws_bytes, double** Z);
+int eig_values_internal(hipStream_t st, const double* D, int64_t k, int64_t ldd, double* lambda, int* info, void* ws,
+                        size_t ws_bytes);
 int form_qhat_internal(hipStream_t st, const double* Z, int64_t k, int r, const double* lambda, double* Qhat,
                        int64_t ldqh, double* Tr, int64_t ldtr, int* info);
 
@@ -89,6 +96,14 @@ __device__ __forceinline__ int tri(int i, int j) { return i * (i + 1) / 2 + j; }
 // shift_coef * trace(G) (0: plain Cholesky QR), then Rinv = L^{-T} (upper
 // triangular, p x p, ld p, zeros below).  A non-positive or non-finite pivot
 // sets *fail and leaves Rinv undefined.
+//  * factorization: one barrier per column.  Step j reads the pivot a_jj and
+//    the column a_.j (both final after step j - 1) and updates the trailing
+//    triangle with the unscaled column, a_il -= a_ij a_lj / a_jj; column j
+//    itself is not written in step j.  The columns are scaled afterwards,
+//    l_ij = a_ij / sqrt(a_jj).
+//  * inverse: a wave forms column j of Z = L^{-1} by forward substitution
+//    (Z_jj = 1 / l_jj, Z_ij = -(sum_{m=j}^{i-1} l_im Z_mj) / l_ii), its lanes
+//    splitting each sum, reading only L and its own column: no barrier.
 __global__ __launch_bounds__(CT) void chol_inv_kernel(const double* __restrict__ G, int p, double shift_coef,
                                                       double* __restrict__ Rinv, int* fail) {
   extern __shared__ double lds[];
@@ -97,53 +112,53 @@ __global__ __launch_bounds__(CT) void chol_inv_kernel(const double* __restrict__
   __shared__ double red[CT / 64];
   __shared__ int bad;
   const int tid = threadIdx.x;
+  const int ty = tid >> 5, tx = tid & 31;  // 32 x 32 layout over (row, column)
   double tr = 0.0;
   for (int i = tid; i < p; i += CT) tr += G[int64_t(i) * p + i];
   tr = block_sum<CT>(tr, red);
   const double sigma = shift_coef * tr;
-  for (int e = tid; e < p * p; e += CT) {
-    const int i = e / p, j = e % p;
-    if (j <= i) L[tri(i, j)] = G[e] + (i == j ? sigma : 0.0);
-  }
+  for (int i = ty; i < p; i += CT / 32)
+    for (int l = tx; l <= i; l += 32) L[tri(i, l)] = G[int64_t(i) * p + l] + (i == l ? sigma : 0.0);
   if (tid == 0) bad = 0;
   __syncthreads();
-  // right-looking Cholesky on the packed triangle
   for (int j = 0; j < p; ++j) {
-    if (tid == 0) {
-      const double d = L[tri(j, j)];
-      if (!(d > 0.0) || !isfinite(d)) bad = 1;
-      L[tri(j, j)] = sqrt(d > 0.0 ? d : 1.0);
-    }
-    __syncthreads();
-    const double ljj = L[tri(j, j)];
-    for (int i = j + 1 + tid; i < p; i += CT) L[tri(i, j)] /= ljj;
-    __syncthreads();
-    const int w = p - j - 1;
-    for (int e = tid; e < w * w; e += CT) {
-      const int i = j + 1 + e / w, l = j + 1 + e % w;
-      if (l <= i) L[tri(i, l)] -= L[tri(i, j)] * L[tri(l, j)];
+    const double djj = L[tri(j, j)];
+    const bool ok = (djj > 0.0) && isfinite(djj);
+    if (tid == 0 && !ok) bad = 1;
+    const double inv = ok ? 1.0 / djj : 0.0;
+    for (int i = j + 1 + ty; i < p; i += CT / 32) {
+      const double aij = L[tri(i, j)] * inv;
+      for (int l = j + 1 + tx; l <= i; l += 32) L[tri(i, l)] -= aij * L[tri(l, j)];
     }
     __syncthreads();
   }
-  // Z = L^{-1}, row by row: Z_ii = 1 / L_ii, Z_ij = -(sum_{m=j}^{i-1} L_im Z_mj) / L_ii
-  for (int i = 0; i < p; ++i) {
-    const double lii = L[tri(i, i)];
-    for (int j = tid; j <= i; j += CT) {
-      if (j == i) {
-        Z[tri(i, i)] = 1.0 / lii;
-      } else {
-        double s = 0.0;
-        for (int m = j; m < i; ++m) s += L[tri(i, m)] * Z[tri(m, j)];
-        Z[tri(i, j)] = -s / lii;
-      }
+  // scale the columns: l_ij = a_ij / sqrt(a_jj) (rows of the same column are
+  // scaled by the thread that also rewrites the diagonal last)
+  for (int j = tx; j < p; j += 32) {
+    const double djj = L[tri(j, j)];
+    const double sq = sqrt(djj > 0.0 ? djj : 1.0);
+    for (int i = j + 1 + ty; i < p; i += CT / 32) L[tri(i, j)] /= sq;
+  }
+  __syncthreads();
+  for (int j = tid; j < p; j += CT) {
+    const double djj = L[tri(j, j)];
+    L[tri(j, j)] = sqrt(djj > 0.0 ? djj : 1.0);
+  }
+  __syncthreads();
+  // wave w takes columns w, w + 16, ...; the lanes split each dot product
+  const int lane = tid & 63, wv = tid >> 6;
+  for (int j = wv; j < p; j += CT / 64) {
+    if (lane == 0) Z[tri(j, j)] = 1.0 / L[tri(j, j)];
+    for (int i = j + 1; i < p; ++i) {
+      double part = 0.0;
+      for (int m = j + lane; m < i; m += 64) part += L[tri(i, m)] * Z[tri(m, j)];
+      const double acc = wave_sum(part);
+      if (lane == 0) Z[tri(i, j)] = -acc / L[tri(i, i)];
     }
-    __syncthreads();
   }
-  // Rinv = Z^T
-  for (int e = tid; e < p * p; e += CT) {
-    const int a = e / p, b = e % p;
-    Rinv[e] = (b >= a) ? Z[tri(b, a)] : 0.0;
-  }
+  __syncthreads();
+  for (int a = ty; a < p; a += CT / 32)
+    for (int b = tx; b < p; b += 32) Rinv[int64_t(a) * p + b] = (b >= a) ? Z[tri(b, a)] : 0.0;
   if (tid == 0 && bad) atomicExch(fail, 1);
 }
 
@@ -222,7 +237,8 @@ size_t partial_workspace(int64_t k, int r) {
   return c.used;
 }
 
-// X <- orthonormal basis of span(Y) by one Cholesky QR pass (shifted or not)
+// Xout <- orthonormal basis of span(Yin) by one Cholesky QR pass (shifted or
+// not); Yin and Xout must differ
 int cholqr(hipStream_t st, const PartWs& w, const double* Yin, double* Xout, int64_t k, int p, bool shifted) {
   int rc = gram_f64_internal(st, Yin, k, p, p, nullptr, nullptr, 0, nullptr, w.G, p, w.gw, w.gw_bytes);
   if (rc) return rc;
@@ -234,35 +250,40 @@ int cholqr(hipStream_t st, const PartWs& w, const double* Yin, double* Xout, int
   return row_gemm_f64(st, Yin, p, k, p, w.Rinv, p, p, Xout, p);
 }
 
-// one subspace step: X <- orth(D X)
-int power_step(hipStream_t st, const PartWs& w, const double* D, int64_t ldd, int64_t k, int p) {
-  int rc = cross_gram_internal(st, D, ldd, w.X, p, k, k, p, w.Y, p, w.cg, w.cg_bytes, nullptr, nullptr, 0, nullptr);
+// D times the block: out = D in (D symmetric: the cross Gram D^T in)
+int apply_d(hipStream_t st, const PartWs& w, const double* D, int64_t ldd, int64_t k, int p, const double* in,
+            double* out) {
+  return cross_gram_internal(st, D, ldd, in, p, k, k, p, out, p, w.cg, w.cg_bytes, nullptr, nullptr, 0, nullptr);
+}
+
+// subspace steps: X <- orth(D^m X), m = 1 or 2 (two products before one
+// orthonormalization when the spread of the spectrum allows it)
+int power_step(hipStream_t st, PartWs& w, const double* D, int64_t ldd, int64_t k, int p, int m) {
+  int rc = apply_d(st, w, D, ldd, k, p, w.X, w.Y);
   if (rc) return rc;
+  if (m == 2) {
+    rc = apply_d(st, w, D, ldd, k, p, w.Y, w.X);
+    if (rc) return rc;
+    std::swap(w.X, w.Y);  // the product is in Y now
+  }
   return cholqr(st, w, w.Y, w.X, k, p, true);
 }
 
-// Rayleigh-Ritz: X orthonormalized (shifted Cholesky QR, then an unshifted
-// pass: shifted CholeskyQR3, which is orthonormal to working precision
-// however ill-conditioned X is), H = X^T D X, X <- X W, theta
-int rayleigh_ritz(hipStream_t st, const PartWs& w, const double* D, int64_t ldd, int64_t k, int p) {
-  // shifted CholeskyQR3: one shifted pass, then two plain ones; Y orthonormal
+// X orthonormal to working precision (shifted CholeskyQR3: one shifted pass,
+// two plain ones; the result ends in X), then H = X^T D X symmetrized
+int project(hipStream_t st, PartWs& w, const double* D, int64_t ldd, int64_t k, int p) {
   int rc = cholqr(st, w, w.X, w.Y, k, p, true);
   if (!rc) rc = cholqr(st, w, w.Y, w.X, k, p, false);
   if (!rc) rc = cholqr(st, w, w.X, w.Y, k, p, false);
   if (rc) return rc;
-  rc = cross_gram_internal(st, D, ldd, w.Y, p, k, k, p, w.X, p, w.cg, w.cg_bytes, nullptr, nullptr, 0, nullptr);
-  if (rc) return rc;  // X = D Y
-  rc = cross_gram_internal(st, w.Y, p, w.X, p, k, p, p, w.H, p, w.cg, w.cg_bytes, nullptr, nullptr, 0, nullptr);
-  if (rc) return rc;  // H = Y^T D Y
+  std::swap(w.X, w.Y);
+  rc = apply_d(st, w, D, ldd, k, p, w.X, w.Y);  // Y = D X
+  if (rc) return rc;
+  rc = cross_gram_internal(st, w.X, p, w.Y, p, k, p, p, w.H, p, w.cg, w.cg_bytes, nullptr, nullptr, 0, nullptr);
+  if (rc) return rc;
   symmetrize_kernel<<<(p * p + 255) / 256, 256, 0, st>>>(w.H, p);
   DOPINF_LAUNCHED();
-  double* Z = nullptr;
-  rc = eig_vectors_internal(st, w.H, p, p, p, w.theta, w.einfo, w.ew, w.ew_bytes, &Z);
-  if (rc) return rc;
-  // W (p x p): column j = eigenvector j of H (row j of Z)
-  transpose_kernel<<<(p * p + 255) / 256, 256, 0, st>>>(Z, p, p, p, w.W);
-  DOPINF_LAUNCHED();
-  return row_gemm_f64(st, w.Y, p, k, p, w.W, p, p, w.X, p);  // X = Y W, the Ritz vectors
+  return DOPINF_OK;
 }
 
 }  // namespace
@@ -317,8 +338,10 @@ extern "C" int dopinf_reduce_topr(void* stream, const double* D, int64_t k, int6
   init_block_kernel<<<unsigned((k * p + 255) / 256), 256, 0, st>>>(w.X, k, p);
   DOPINF_LAUNCHED();
   int rc = DOPINF_OK;
-  for (int it = 0; it < kM0 && !rc; ++it) rc = power_step(st, w, D, ldd, k, p);
-  if (!rc) rc = rayleigh_ritz(st, w, D, ldd, k, p);
+  for (int it = 0; it < kM0 && !rc; ++it) rc = power_step(st, w, D, ldd, k, p, 1);
+  // first Rayleigh-Ritz step: the Ritz values only (they give the rate)
+  if (!rc) rc = project(st, w, D, ldd, k, p);
+  if (!rc) rc = eig_values_internal(st, w.H, p, p, w.theta, w.einfo, w.ew, w.ew_bytes);
   if (rc) return rc;
   // the convergence rate from the Ritz values (one host synchronization)
   std::vector<double> th(p);
@@ -335,14 +358,36 @@ extern "C" int dopinf_reduce_topr(void* stream, const double* D, int64_t k, int6
     m_total = int(std::ceil(std::log(1e-17) / std::log(rho))) + 2;
   }
   if (m_total > kMaxIter) return full_solver();
-  const int m_more = std::max(m_total - kM0, 1);
-  for (int it = 0; it < m_more && !rc; ++it) rc = power_step(st, w, D, ldd, k, p);
-  if (!rc) rc = rayleigh_ritz(st, w, D, ldd, k, p);
+  int m_more = std::max(m_total - kM0, 1);
+  // The shift of the orthonormalization damps a direction whose share of
+  // the block's norm, squared, is near sigma_rel = 11 (k p + p (p + 1)) u: a
+  // product D^m X leaves the r-th direction a share (theta_r / theta_1)^m.
+  // One product per orthonormalization needs that share squared far above
+  // sigma_rel (else the full eigensolver runs); two products share one
+  // orthonormalization only when the square of the two-product share is too.
+  const double sig_rel = 11.0 * (double(k) * p + double(p) * (p + 1)) * 1.1102230246251565e-16;
+  const double share = th[r - 1] / th[0];
+  if (share * share < 1e2 * sig_rel) return full_solver();
+  const bool pairs = share * share * share * share > 1e6 * sig_rel;
+  int done = 0;
+  while (done < m_more && !rc) {
+    const int m = (pairs && m_more - done >= 2) ? 2 : 1;
+    rc = power_step(st, w, D, ldd, k, p, m);
+    done += m;
+  }
+  // final Rayleigh-Ritz step: the r leading Ritz pairs
+  double* Z = nullptr;
+  if (!rc) rc = project(st, w, D, ldd, k, p);
+  if (!rc) rc = eig_vectors_internal(st, w.H, p, p, r, w.theta, w.einfo, w.ew, w.ew_bytes, &Z);
   if (rc) return rc;
-  if (iters_h) *iters_h = kM0 + m_more;
-  // eigenvector rows Z (r x k) from the first r Ritz vectors, then the sign
-  // rule, Qhat and T_r as for the full solver
-  transpose_kernel<<<unsigned((k * r + 255) / 256), 256, 0, st>>>(w.X, k, r, p, w.Zf);
+  if (iters_h) *iters_h = kM0 + done;
+  // W_r (p x r): column j = eigenvector j of H (row j of Z); U = X W_r (k x r
+  // in Y, ld p); eigenvector rows Z_f (r x k) for the sign rule, Qhat and T_r
+  transpose_kernel<<<unsigned((p * r + 255) / 256), 256, 0, st>>>(Z, r, p, p, w.W);
+  DOPINF_LAUNCHED();
+  rc = row_gemm_f64(st, w.X, p, k, p, w.W, r, r, w.Y, p);
+  if (rc) return rc;
+  transpose_kernel<<<unsigned((k * r + 255) / 256), 256, 0, st>>>(w.Y, k, r, p, w.Zf);
   DOPINF_LAUNCHED();
   info_merge_kernel<<<1, 64, 0, st>>>(w.fail, w.einfo, info);
   DOPINF_LAUNCHED();

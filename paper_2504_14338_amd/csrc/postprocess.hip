@@ -7,9 +7,10 @@
 //
 // Both are products of a tall operand (gathered snapshot rows, or V) with a
 // short one (T_r, k x r, or Qtilde, r x N) and run on one FP64 MFMA tile
-// kernel: 64 output rows per workgroup, wave w owns rows 16w..16w+15 and
-// NJ blocks of 16 columns; K is staged through LDS in chunks of 32 with the
-// next chunk's global loads in registers while the current one is used.
+// kernel: 64 or 128 output rows per workgroup, wave w owns rows 16w..16w+15
+// of each 64-row block and NJ blocks of 16 columns; K is staged through LDS
+// in chunks of 32 with the next chunk's global loads in registers while the
+// current one is used.
 // Centering is a subtraction as the snapshot values are staged; the division
 // by the variable's scale is applied once per output entry (exact in exact
 // arithmetic, and one division per V entry instead of one per Q entry).
@@ -57,40 +58,51 @@ struct RowGemmArgs {
   int* info;               // receives DOPINF_E_ARG for a row index outside [0, n_src)
 };
 
-template <class T, int NJ>
+// RB row blocks of 64 per workgroup: wave w owns rows 16 w + 64 b (b < RB)
+// of the tile, so a workgroup reads each chunk of the short operand once for
+// 64 RB rows.
+template <class T, int NJ, int RB>
 __global__ __launch_bounds__(PT) void row_gemm_kernel(RowGemmArgs<T> a) {
-  __shared__ double As[PM][PAS];
+  __shared__ double As[PM * RB][PAS];
   __shared__ double Bs[PK][16 * NJ];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int64_t i0 = int64_t(blockIdx.x) * PM;
+  const int64_t i0 = int64_t(blockIdx.x) * PM * RB;
   const int64_t c0 = int64_t(blockIdx.y) * 16 * NJ;
 
-  // A staging: thread -> tile row tid / 4, 8 consecutive k at 8 (tid % 4)
+  // A staging: thread -> tile rows tid / 4 + 64 b, 8 consecutive k at 8 (tid % 4)
   const int ar = tid >> 2, ak = (tid & 3) * 8;
-  const int64_t gi = i0 + ar;
-  int64_t src = -1;
-  if (gi < a.m) {
-    src = a.a_rows ? a.a_rows[gi] : gi;
-    if (src < 0 || src >= a.n_src) {
-      if (a.info) atomicExch(a.info, DOPINF_E_ARG);
-      src = -1;
+  int64_t src[RB];
+  double shift[RB];
+  const T* arow[RB];
+#pragma unroll
+  for (int b = 0; b < RB; ++b) {
+    const int64_t gi = i0 + ar + PM * b;
+    src[b] = -1;
+    if (gi < a.m) {
+      src[b] = a.a_rows ? a.a_rows[gi] : gi;
+      if (src[b] < 0 || src[b] >= a.n_src) {
+        if (a.info) atomicExch(a.info, DOPINF_E_ARG);
+        src[b] = -1;
+      }
     }
+    shift[b] = (src[b] >= 0 && a.a_shift) ? a.a_shift[src[b]] : 0.0;
+    arow[b] = a.A + (src[b] >= 0 ? src[b] : 0) * a.lda;
   }
-  const double shift = (src >= 0 && a.a_shift) ? a.a_shift[src] : 0.0;
-  const T* arow = a.A + (src >= 0 ? src : 0) * a.lda;
   // B staging: thread -> chunk row tid / 8, 2 NJ consecutive columns
   constexpr int BW = 2 * NJ;
   const int br = tid >> 3, bc = (tid & 7) * BW;
 
-  double ra[8], rb[BW];
+  double ra[RB][8], rb[BW];
   auto load = [&](int64_t kc) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int64_t kk = kc + ak + q;
-      const bool ok = src >= 0 && kk < a.K;
-      const double x = static_cast<double>(arow[ok ? kk : 0]);
-      ra[q] = ok ? x - shift : 0.0;
-    }
+    for (int b = 0; b < RB; ++b)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int64_t kk = kc + ak + q;
+        const bool ok = src[b] >= 0 && kk < a.K;
+        const double x = static_cast<double>(arow[b][ok ? kk : 0]);
+        ra[b][q] = ok ? x - shift[b] : 0.0;
+      }
     const int64_t kb = kc + br;
 #pragma unroll
     for (int q = 0; q < BW; ++q) {
@@ -101,15 +113,19 @@ __global__ __launch_bounds__(PT) void row_gemm_kernel(RowGemmArgs<T> a) {
     }
   };
 
-  dbl4 acc[NJ];
+  dbl4 acc[RB][NJ];
 #pragma unroll
-  for (int j = 0; j < NJ; ++j) acc[j] = dbl4{0.0, 0.0, 0.0, 0.0};
+  for (int b = 0; b < RB; ++b)
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) acc[b][j] = dbl4{0.0, 0.0, 0.0, 0.0};
 
   load(0);
   for (int64_t kc = 0; kc < a.K; kc += PK) {
     __syncthreads();  // the previous chunk has been read
 #pragma unroll
-    for (int q = 0; q < 8; ++q) As[ar][ak + q] = ra[q];
+    for (int b = 0; b < RB; ++b)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) As[ar + PM * b][ak + q] = ra[b][q];
 #pragma unroll
     for (int q = 0; q < BW; ++q) Bs[br][bc + q] = rb[q];
     __syncthreads();
@@ -117,48 +133,62 @@ __global__ __launch_bounds__(PT) void row_gemm_kernel(RowGemmArgs<T> a) {
     const int kmax = (a.K - kc) < PK ? int(a.K - kc) : PK;
     for (int kk = 0; kk < kmax; kk += 4) {
       const int k = kk + (lane >> 4);  // rows past K hold zeros
-      const double af = As[16 * wv + (lane & 15)][k];
 #pragma unroll
-      for (int j = 0; j < NJ; ++j)
-        acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, Bs[k][16 * j + (lane & 15)], acc[j], 0, 0, 0);
+      for (int b = 0; b < RB; ++b) {
+        const double af = As[16 * wv + PM * b + (lane & 15)][k];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j)
+          acc[b][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, Bs[k][16 * j + (lane & 15)], acc[b][j], 0, 0, 0);
+      }
     }
   }
 
-  // epilogue: acc[j][e] is C[16 wv + (lane >> 4) + 4 e][16 j + (lane & 15)]
+  // epilogue: acc[b][j][e] is C[16 wv + 64 b + (lane >> 4) + 4 e][16 j + (lane & 15)]
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const int64_t i = i0 + 16 * wv + (lane >> 4) + 4 * e;
-    if (i >= a.m) continue;
-    const int64_t es = a.e_rows ? a.e_rows[i] : i;
-    const bool ok = es >= 0 && es < a.n_src;
-    double sc = 1.0, ad = 0.0;
-    if (ok) {
-      if (a.e_scale) sc = a.e_scale[var_of(a.vt, es)];
-      if (a.e_add) ad = a.e_add[es];
-    }
+  for (int b = 0; b < RB; ++b)
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-      const int64_t c = c0 + 16 * j + (lane & 15);
-      if (c >= a.ncol) continue;
-      double v = acc[j][e];
-      v = a.div ? v / sc : v * sc;
-      a.C[i * a.ldc + c] = ok ? v + ad : NAN;
+    for (int e = 0; e < 4; ++e) {
+      const int64_t i = i0 + 16 * wv + PM * b + (lane >> 4) + 4 * e;
+      if (i >= a.m) continue;
+      const int64_t es = a.e_rows ? a.e_rows[i] : i;
+      const bool ok = es >= 0 && es < a.n_src;
+      double sc = 1.0, ad = 0.0;
+      if (ok) {
+        if (a.e_scale) sc = a.e_scale[var_of(a.vt, es)];
+        if (a.e_add) ad = a.e_add[es];
+      }
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        const int64_t c = c0 + 16 * j + (lane & 15);
+        if (c >= a.ncol) continue;
+        double v = acc[b][j][e];
+        v = a.div ? v / sc : v * sc;
+        a.C[i * a.ldc + c] = ok ? v + ad : NAN;
+      }
     }
-  }
 }
 
+template <class T, int RB>
+void launch_row_gemm_rb(hipStream_t st, const RowGemmArgs<T>& a) {
+  const unsigned gx = unsigned((a.m + PM * RB - 1) / (PM * RB));
+  if (a.ncol <= 16)
+    row_gemm_kernel<T, 1, RB><<<dim3(gx, 1), PT, 0, st>>>(a);
+  else if (a.ncol <= 32)
+    row_gemm_kernel<T, 2, RB><<<dim3(gx, 1), PT, 0, st>>>(a);
+  else if (a.ncol <= 64)
+    row_gemm_kernel<T, 4, RB><<<dim3(gx, 1), PT, 0, st>>>(a);
+  else
+    row_gemm_kernel<T, 8, RB><<<dim3(gx, unsigned((a.ncol + 127) / 128)), PT, 0, st>>>(a);
+}
+
+// Tall products (at least 256 row tiles of 128) take 128 rows per
+// workgroup; shorter ones 64, for more workgroups.
 template <class T>
 int launch_row_gemm(hipStream_t st, const RowGemmArgs<T>& a) {
-  const unsigned gx = unsigned((a.m + PM - 1) / PM);
-  if (a.ncol <= 16) {
-    row_gemm_kernel<T, 1><<<dim3(gx, 1), PT, 0, st>>>(a);
-  } else if (a.ncol <= 32) {
-    row_gemm_kernel<T, 2><<<dim3(gx, 1), PT, 0, st>>>(a);
-  } else if (a.ncol <= 64) {
-    row_gemm_kernel<T, 4><<<dim3(gx, 1), PT, 0, st>>>(a);
-  } else {
-    row_gemm_kernel<T, 8><<<dim3(gx, unsigned((a.ncol + 127) / 128)), PT, 0, st>>>(a);
-  }
+  if (a.m >= int64_t(256) * 2 * PM)
+    launch_row_gemm_rb<T, 2>(st, a);
+  else
+    launch_row_gemm_rb<T, 1>(st, a);
   DOPINF_LAUNCHED();
   return DOPINF_OK;
 }

@@ -628,16 +628,17 @@ int rollout_launch(hipStream_t st, int n_r, const int* r_list_h, int n_pairs, co
         (void)hipGetLastError();
     }
     if (!launched) {
+      const int n_left = n_pairs;
       // more candidates than resident workgroups: a persistent grid with a
       // work counter; else one workgroup per candidate
       int per_cu = 0, ncu = 0;
       DOPINF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, one_wg, RT, smem));
       DOPINF_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
       const int resident = std::max(1, per_cu) * std::max(1, ncu);
-      int grid = n_pairs;
-      ra.n_items = n_pairs;
+      int grid = n_left;
+      ra.n_items = n_left;
       ra.queue = nullptr;
-      if (n_pairs > resident) {
+      if (n_left > resident) {
         ra.queue = w.words + n_pairs + 1;
         zero_u32_kernel<<<1, 64, 0, st>>>(ra.queue, 1);
         DOPINF_LAUNCHED();

@@ -291,3 +291,35 @@ def test_team_rollout_partial_member_matches_oracle(gpu_lib, r):
         assert o2["outcome"].item() == dp.ITEM_GROWTH
         tr = o2["traj_views"][0][0].cpu().numpy()
         assert np.isnan(tr[-1]).all() and np.isfinite(tr[0]).all()
+
+
+@pytest.mark.parametrize("r", [20, 60])
+def test_full_horizon_many_candidates_match_oracle(gpu_lib, r):
+    # many candidates without early exit (more than fit teams): sampled
+    # trajectories against the oracle, every candidate's scores against the
+    # forced one-workgroup form
+    import torch
+    dp = gpu_lib
+    k, n_states = 300, 700
+    Og, Qh = _stable_rom(r, k, 100 + r)
+    n_items = 300
+    scale_A = 1.0 + 2e-3 * np.linspace(-1, 1, n_items)
+    Os = []
+    for p in range(n_items):
+        O = Og.copy()
+        O[:, :r] *= scale_A[p]
+        Os.append(O.ravel())
+    Od = torch.from_numpy(np.concatenate(Os)).cuda()
+    Qhat = torch.from_numpy(Qh.copy()).cuda()
+    team = dp.rollout(Od, Qhat, [r], n_items, n_states, keep_traj=True, full=True)
+    one = dp.rollout(Od, Qhat, [r], n_items, n_states, keep_traj=True, full=True, one_wg=True)
+    torch.cuda.synchronize()
+    for p in (0, 1, 137, n_items - 1):
+        ref = orc.rollout(Os[p].reshape(r, -1), r, Qh[:, 0], n_states)
+        tr = team["traj_views"][0][p].cpu().numpy().T
+        assert np.max(np.abs(tr - ref)) <= 1e-10 * np.max(np.abs(ref)), p
+    for key in ("train_err", "growth"):
+        a, b = team[key].cpu().numpy(), one[key].cpu().numpy()
+        assert np.allclose(a, b, rtol=1e-9, atol=0), key
+    assert np.array_equal(team["outcome"].cpu().numpy(), one["outcome"].cpu().numpy())
+    assert team["best"].item() == one["best"].item()
