@@ -10,6 +10,7 @@
 //     device-wide barrier publishes it, every workgroup forms its entries of
 //     p = tau * A v plus a partial v^T p, a second barrier, then every
 //     workgroup applies the rank-2 update A -= v w^T + w v^T to its rows.
+//     Orders up to 128 are reduced by one workgroup with the matrix in LDS.
 //  2. All k eigenvalues of T by multisection: one wave per eigenvalue, the
 //     64 lanes evaluate Sturm counts at 64 interior points per round.
 //  3. The top r eigenvectors of T by inverse iteration with partial-pivoting
@@ -357,6 +358,99 @@ __global__ __launch_bounds__(TNT) void sytrd_reg_kernel(TridArgs a) {
       a.d[k - 1] = row[k - 1];
       a.tau[k - 1] = 0.0;
     }
+  }
+}
+
+// Same reduction for k <= SK by one workgroup holding the whole matrix in LDS
+// (row stride k + 1 doubles spreads neighbouring rows over the banks).  The
+// Rayleigh-Ritz matrices of the partial eigensolver are this small, and at
+// this size the device-wide barriers of the cooperative kernel cost far more
+// than the arithmetic.  Per column, four workgroup barriers: wave 0 forms the
+// reflector from row j; p = tau A v with 8 lanes per row; wave 0 forms
+// K = tau / 2 v^T p and w = p - K v; every thread applies the rank-2 update
+// A -= v w^T + w v^T to the trailing block.  Outputs as the cooperative
+// kernel's: v_j in row j of Aout (entry j + 1 = 1), tau, d, e.
+constexpr int SK = 128;
+constexpr int STN = 1024;
+
+size_t sytrd_small_lds(int64_t k) { return (size_t(k) * size_t(k + 1) + 2 * size_t(k)) * sizeof(double); }
+
+__global__ __launch_bounds__(STN) void sytrd_small_kernel(const double* __restrict__ D, int64_t ldd, int k,
+                                                          double* __restrict__ Aout, double* __restrict__ d,
+                                                          double* __restrict__ e, double* __restrict__ tau) {
+  extern __shared__ double sm[];
+  __shared__ double bc;  // tau_j
+  const int ld = k + 1;
+  double* A = sm;          // k x k, row stride ld
+  double* v = A + k * ld;  // v_j, entries j + 1 .. k - 1
+  double* pw = v + k;      // p, then w = p - K v
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int i = wv; i < k; i += STN / 64)
+    for (int l = lane; l < k; l += 64) A[i * ld + l] = D[int64_t(i) * ldd + l];
+  __syncthreads();
+  for (int j = 0; j + 1 < k; ++j) {
+    if (wv == 0) {
+      const double* row = A + j * ld;
+      double ss = 0.0;
+      for (int l = j + 2 + lane; l < k; l += 64) ss += row[l] * row[l];
+      ss = lane_value(wave_sum(ss), 0);  // one rounding for every lane
+      const double alpha = row[j + 1];
+      double beta, tj, scal;
+      if (ss == 0.0) {
+        beta = alpha;
+        tj = 0.0;
+        scal = 0.0;
+      } else {
+        beta = -copysign(sqrt(alpha * alpha + ss), alpha);
+        tj = (beta - alpha) / beta;
+        scal = 1.0 / (alpha - beta);
+      }
+      for (int l = j + 2 + lane; l < k; l += 64) {
+        const double x = (tj == 0.0) ? 0.0 : row[l] * scal;
+        v[l] = x;
+        Aout[int64_t(j) * k + l] = x;
+      }
+      if (lane == 0) {
+        v[j + 1] = 1.0;
+        Aout[int64_t(j) * k + j + 1] = 1.0;
+        tau[j] = tj;
+        d[j] = row[j];
+        e[j] = beta;
+        bc = tj;
+      }
+    }
+    __syncthreads();
+    const double tj = bc;
+    {  // p_i = tau A[i, j+1:] . v[j+1:], rows i > j, 8 lanes per row
+      const int i = j + 1 + (tid >> 3), part = tid & 7;
+      double s = 0.0;
+      if (i < k) {
+        const double* row = A + i * ld;
+        for (int l = j + 1 + part; l < k; l += 8) s += row[l] * v[l];
+      }
+      s += __shfl_xor(s, 1, 64);
+      s += __shfl_xor(s, 2, 64);
+      s += __shfl_xor(s, 4, 64);
+      if (i < k && part == 0) pw[i] = tj * s;
+    }
+    __syncthreads();
+    if (wv == 0) {
+      double s = 0.0;
+      for (int i = j + 1 + lane; i < k; i += 64) s += v[i] * pw[i];
+      const double K = 0.5 * tj * lane_value(wave_sum(s), 0);
+      for (int i = j + 1 + lane; i < k; i += 64) pw[i] -= K * v[i];
+    }
+    __syncthreads();
+    for (int i = j + 1 + wv; i < k; i += STN / 64) {
+      const double vi = v[i], wi = pw[i];
+      double* row = A + i * ld;
+      for (int l = j + 1 + lane; l < k; l += 64) row[l] -= vi * pw[l] + wi * v[l];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    d[k - 1] = A[(k - 1) * ld + k - 1];
+    tau[k - 1] = 0.0;
   }
 }
 
@@ -1016,8 +1110,17 @@ int eig_values_stage(hipStream_t st, const double* D, int64_t k, int64_t ldd, do
   ta.bar = w.words;
   ta.vflag = w.words + 3;
   ta.abort_flag = reinterpret_cast<int*>(w.words + 1);
-  void* args[] = {&ta};
-  DOPINF_HIP(hipLaunchCooperativeKernel(pl.kern, dim3(pl.P), dim3(TNT), args, unsigned(pl.lds_bytes), st));
+  if (k <= SK) {
+    const size_t lb = sytrd_small_lds(k);
+    if (lb > 65536)
+      DOPINF_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(sytrd_small_kernel),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(lb)));
+    sytrd_small_kernel<<<1, STN, lb, st>>>(D, ldd, int(k), w.A, w.d, w.e, w.tau);
+    DOPINF_LAUNCHED();
+  } else {
+    void* args[] = {&ta};
+    DOPINF_HIP(hipLaunchCooperativeKernel(pl.kern, dim3(pl.P), dim3(TNT), args, unsigned(pl.lds_bytes), st));
+  }
   tri_prep_kernel<<<1, 256, 0, st>>>(w.d, w.e, k, w.e2, w.bounds);
   DOPINF_LAUNCHED();
   {

@@ -92,23 +92,25 @@ __global__ __launch_bounds__(256) void init_block_kernel(double* X, int64_t k, i
 
 __device__ __forceinline__ int tri(int i, int j) { return i * (i + 1) / 2 + j; }  // j <= i
 
-// One workgroup: L L^T = G + sigma I (G p x p symmetric, ld p), with sigma =
-// shift_coef * trace(G) (0: plain Cholesky QR), then Rinv = L^{-T} (upper
-// triangular, p x p, ld p, zeros below).  A non-positive or non-finite pivot
-// sets *fail and leaves Rinv undefined.
-//  * factorization: one barrier per column.  Step j reads the pivot a_jj and
-//    the column a_.j (both final after step j - 1) and updates the trailing
-//    triangle with the unscaled column, a_il -= a_ij a_lj / a_jj; column j
-//    itself is not written in step j.  The columns are scaled afterwards,
-//    l_ij = a_ij / sqrt(a_jj).
-//  * inverse: a wave forms column j of Z = L^{-1} by forward substitution
-//    (Z_jj = 1 / l_jj, Z_ij = -(sum_{m=j}^{i-1} l_im Z_mj) / l_ii), its lanes
-//    splitting each sum, reading only L and its own column: no barrier.
+// One workgroup: G + sigma I = Lt Dg Lt^T (G p x p symmetric, ld p; sigma =
+// shift_coef * trace(G), 0 for plain Cholesky QR) by symmetric Gaussian
+// elimination, so that L = Lt Dg^{1/2}, and Rinv = L^{-T} = Lt^{-T} Dg^{-1/2}
+// (upper triangular, p x p, ld p, zeros below).  A non-positive or
+// non-finite pivot sets *fail and leaves Rinv undefined.
+//  * step j, one barrier: with the pivot a_jj and the multipliers
+//    f_i = a_ij / a_jj (i > j), both final after step j - 1, the trailing
+//    triangle is updated a_il -= f_i a_lj (j < l <= i), and the same row
+//    operations applied to the identity give Z = Lt^{-1}: z_ic -= f_i z_jc
+//    (c <= j), i.e. column-oriented forward substitution for all right-hand
+//    sides at once.  Row i's i + 1 entries in the two packed triangles (LDS)
+//    are split over 32 lanes; step j writes neither column j of A nor row j
+//    of Z.
+//  * Rinv[a][b] = z_ba / sqrt(a_bb) for b >= a.
 __global__ __launch_bounds__(CT) void chol_inv_kernel(const double* __restrict__ G, int p, double shift_coef,
                                                       double* __restrict__ Rinv, int* fail) {
   extern __shared__ double lds[];
-  double* L = lds;                    // packed lower triangle, p(p+1)/2
-  double* Z = lds + p * (p + 1) / 2;  // packed lower triangle of L^{-1}
+  double* A = lds;                    // packed lower triangle of the working matrix
+  double* Z = lds + p * (p + 1) / 2;  // packed unit lower triangle of Lt^{-1}
   __shared__ double red[CT / 64];
   __shared__ int bad;
   const int tid = threadIdx.x;
@@ -118,47 +120,37 @@ __global__ __launch_bounds__(CT) void chol_inv_kernel(const double* __restrict__
   tr = block_sum<CT>(tr, red);
   const double sigma = shift_coef * tr;
   for (int i = ty; i < p; i += CT / 32)
-    for (int l = tx; l <= i; l += 32) L[tri(i, l)] = G[int64_t(i) * p + l] + (i == l ? sigma : 0.0);
+    for (int l = tx; l <= i; l += 32) {
+      A[tri(i, l)] = G[int64_t(i) * p + l] + (i == l ? sigma : 0.0);
+      Z[tri(i, l)] = (i == l) ? 1.0 : 0.0;
+    }
   if (tid == 0) bad = 0;
   __syncthreads();
   for (int j = 0; j < p; ++j) {
-    const double djj = L[tri(j, j)];
+    const double djj = A[tri(j, j)];
     const bool ok = (djj > 0.0) && isfinite(djj);
     if (tid == 0 && !ok) bad = 1;
     const double inv = ok ? 1.0 / djj : 0.0;
     for (int i = j + 1 + ty; i < p; i += CT / 32) {
-      const double aij = L[tri(i, j)] * inv;
-      for (int l = j + 1 + tx; l <= i; l += 32) L[tri(i, l)] -= aij * L[tri(l, j)];
+      const double f = A[tri(i, j)] * inv;
+      for (int c = tx; c <= i; c += 32) {
+        if (c <= j)
+          Z[tri(i, c)] -= f * Z[tri(j, c)];
+        else
+          A[tri(i, c)] -= f * A[tri(c, j)];
+      }
     }
     __syncthreads();
   }
-  // scale the columns: l_ij = a_ij / sqrt(a_jj) (rows of the same column are
-  // scaled by the thread that also rewrites the diagonal last)
-  for (int j = tx; j < p; j += 32) {
-    const double djj = L[tri(j, j)];
-    const double sq = sqrt(djj > 0.0 ? djj : 1.0);
-    for (int i = j + 1 + ty; i < p; i += CT / 32) L[tri(i, j)] /= sq;
-  }
-  __syncthreads();
-  for (int j = tid; j < p; j += CT) {
-    const double djj = L[tri(j, j)];
-    L[tri(j, j)] = sqrt(djj > 0.0 ? djj : 1.0);
-  }
-  __syncthreads();
-  // wave w takes columns w, w + 16, ...; the lanes split each dot product
-  const int lane = tid & 63, wv = tid >> 6;
-  for (int j = wv; j < p; j += CT / 64) {
-    if (lane == 0) Z[tri(j, j)] = 1.0 / L[tri(j, j)];
-    for (int i = j + 1; i < p; ++i) {
-      double part = 0.0;
-      for (int m = j + lane; m < i; m += 64) part += L[tri(i, m)] * Z[tri(m, j)];
-      const double acc = wave_sum(part);
-      if (lane == 0) Z[tri(i, j)] = -acc / L[tri(i, i)];
-    }
-  }
-  __syncthreads();
   for (int a = ty; a < p; a += CT / 32)
-    for (int b = tx; b < p; b += 32) Rinv[int64_t(a) * p + b] = (b >= a) ? Z[tri(b, a)] : 0.0;
+    for (int b = tx; b < p; b += 32) {
+      double x = 0.0;
+      if (b >= a) {
+        const double dbb = A[tri(b, b)];
+        x = Z[tri(b, a)] / sqrt(dbb > 0.0 ? dbb : 1.0);
+      }
+      Rinv[int64_t(a) * p + b] = x;
+    }
   if (tid == 0 && bad) atomicExch(fail, 1);
 }
 
