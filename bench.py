@@ -525,10 +525,11 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device-to-device (reference for the HBM byte counters)")
-    ap.add_argument("--leg", choices=["all", "sweep", "mixed", "post"], default="all",
+    ap.add_argument("--leg", choices=["all", "sweep", "mixed", "post", "closure"], default="all",
                     help="sweep: only the regularization sweep on reduced data of the same input; "
                          "mixed: only the reduced-precision forms against one float64 step; "
-                         "post: one float64 step, then Step V and the streamed Gram "
+                         "post: one float64 step, then Step V and the streamed Gram; "
+                         "closure: only the learned-closure leg "
                          "(each prints its JSON object; for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -551,6 +552,9 @@ def main():
         torch.cuda.synchronize()
         log("copy calibration: 1 GiB read + 1 GiB written by one copy kernel")
         del src, dst
+    if args.leg == "closure":
+        print(json.dumps({"closure": closure_bench(dp, torch, dev)}), flush=True)
+        return
     m, Q, var_rows = make_c2(torch, dev)
     n, k = Q.shape
     torch.cuda.synchronize()

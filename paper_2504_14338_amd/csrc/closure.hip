@@ -11,10 +11,12 @@
 // Kernels:
 //  * residual_kernel      rho_t = qhat_{t+1} - f_ROM(qhat_t)
 //  * norm_kernel          per-mode mean / population std of inputs and targets
-//  * train_kernel         ONE persistent workgroup of 1024 threads runs every
-//                         epoch: per minibatch forward, backward (weight
-//                         gradients register-blocked from LDS tiles), Adam.
-//  * grad_kernel          one forward/backward over a batch (gradient checks)
+//  * train_kernel         ONE persistent workgroup of 8 waves runs every
+//                         epoch on the matrix cores: per minibatch forward,
+//                         backward and weight gradients in chunks of 32 rows,
+//                         Adam applied by the lanes that own each gradient.
+//  * grad_kernel          the same forward/backward over one batch (gradient
+//                         checks)
 //  * eval_kernel          g(x) for a batch of states and max ||g||
 //  * closure_rollout_kernel  4 rollouts per workgroup: MLP and ROM per step,
 //                         latched fallback to the plain ROM when ||g|| exceeds
@@ -25,11 +27,9 @@ namespace dopinf {
 namespace {
 
 constexpr int H = 128;       // hidden width
-constexpr int TT = 1024;     // trainer threads
 constexpr int BMAX = 256;    // largest minibatch
 constexpr int RG = 16;       // rollouts (or eval rows) per workgroup
 constexpr int ET = 256;      // eval / rollout threads
-constexpr int BT = 16;       // minibatch rows per LDS tile in the backward pass
 
 typedef float flt4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -107,159 +107,6 @@ __device__ void mlp_fwd(int R, int r, const unsigned short* Wb, const float* __r
   __syncthreads();
 }
 
-struct Scratch {  // trainer / gradient activations, each BMAX rows
-  float *x, *y, *z1, *a1, *z2, *a2, *out, *dout, *dz2, *dz1;
-};
-
-// Load standardized (x, bf16) and (y, float) rows idx(b) into s.x / s.y.
-template <int NT>
-__device__ void load_batch(int R, int r, const double* __restrict__ X, const double* __restrict__ Y,
-                           const double* __restrict__ norm, const int64_t* idx, int64_t base, Scratch s, int tid) {
-  for (int e = tid; e < R * r; e += NT) {
-    const int b = e / r, i = e % r;
-    const int64_t row = idx ? idx[b] : base + b;
-    s.x[e] = bf16f(static_cast<float>((X[row * r + i] - norm[i]) / norm[r + i]));
-    if (Y) s.y[e] = static_cast<float>((Y[row * r + i] - norm[2 * r + i]) / norm[3 * r + i]);
-  }
-  __syncthreads();
-}
-
-// Backward of the mean squared error; gradients are ADDED to G.  Returns the
-// batch loss (mean over R*r) to every thread.
-template <int NT>
-__device__ float mlp_bwd(int R, int r, const unsigned short* Wb, Scratch s, float* G, float* tile, float* red, int tid) {
-  const Off o(r);
-  const unsigned short* W2 = Wb + int64_t(H) * r;
-  const unsigned short* W3 = W2 + int64_t(H) * H;
-  const float scale = 2.0f / float(R * r);
-  float lsum = 0.f;
-  for (int e = tid; e < R * r; e += NT) {
-    const float d = s.out[e] - s.y[e];
-    lsum += d * d;
-    s.dout[e] = scale * d;
-  }
-  // block sum of the loss
-  lsum = wave_sum(double(lsum));
-  __syncthreads();
-  if ((tid & 63) == 0) red[tid >> 6] = lsum;
-  __syncthreads();
-  float loss = 0.f;
-  for (int w = 0; w < NT / 64; ++w) loss += red[w];
-  loss /= float(R * r);
-  // dz2 = (dout W3) * gelu'(z2)
-  for (int e = tid; e < R * H; e += NT) {
-    const int b = e / H, j = e % H;
-    float acc = 0.f;
-    for (int i = 0; i < r; ++i) acc += s.dout[b * r + i] * wb(W3, int64_t(i) * H + j);
-    s.dz2[e] = acc * gelu_grad_f(s.z2[e]);
-  }
-  __syncthreads();
-  // dz1 = (dz2 W2) * gelu'(z1)
-  for (int e = tid; e < R * H; e += NT) {
-    const int b = e / H, k = e % H;
-    float acc = 0.f;
-    for (int j = 0; j < H; ++j) acc += s.dz2[b * H + j] * wb(W2, int64_t(j) * H + k);
-    s.dz1[e] = acc * gelu_grad_f(s.z1[e]);
-  }
-  __syncthreads();
-  // weight gradients: sums over the batch, tiles of BT rows staged in LDS
-  //   dW2 = dz2^T a1 (4 x 4 register blocks), dW3 = dout^T a2, dW1 = dz1^T x
-  const int jb = (tid / 32) * 4, kb = (tid % 32) * 4;  // dW2 block (NT == 1024)
-  float g2[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) g2[a][c] = 0.f;
-  float g3[8], g1[8], gb[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-  for (int q = 0; q < 8; ++q) g3[q] = g1[q] = 0.f;
-  float* Tdz2 = tile;                 // BT x H
-  float* Ta1 = tile + BT * H;         // BT x H
-  float* Tdo = Ta1 + BT * H;          // BT x r
-  float* Ta2 = Tdo + BT * 128;        // BT x H
-  float* Tdz1 = Ta2 + BT * H;         // BT x H
-  float* Tx = Tdz1 + BT * H;          // BT x r
-  for (int b0 = 0; b0 < R; b0 += BT) {
-    const int nb = min(BT, R - b0);
-    __syncthreads();
-    for (int e = tid; e < BT * H; e += NT) {
-      const int b = e / H;
-      const bool ok = b < nb;
-      Tdz2[e] = ok ? s.dz2[(b0 + b) * H + e % H] : 0.f;
-      Ta1[e] = ok ? s.a1[(b0 + b) * H + e % H] : 0.f;
-      Ta2[e] = ok ? s.a2[(b0 + b) * H + e % H] : 0.f;
-      Tdz1[e] = ok ? s.dz1[(b0 + b) * H + e % H] : 0.f;
-    }
-    for (int e = tid; e < BT * r; e += NT) {
-      const int b = e / r;
-      const bool ok = b < nb;
-      Tdo[(e / r) * 128 + e % r] = ok ? s.dout[(b0 + b) * r + e % r] : 0.f;
-      Tx[e] = ok ? s.x[(b0 + b) * r + e % r] : 0.f;
-    }
-    __syncthreads();
-    for (int b = 0; b < nb; ++b) {
-      float dv[4], av[4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a) dv[a] = Tdz2[b * H + jb + a];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) av[c] = Ta1[b * H + kb + c];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) g2[a][c] += dv[a] * av[c];
-    }
-    // dW3 (r x H) and dW1 (H x r): thread handles entries e = tid + NT*q
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int e = tid + NT * q;
-      if (e < r * H) {
-        const int i = e / H, j = e % H;  // dW3[i][j]
-        float acc = 0.f;
-        for (int b = 0; b < nb; ++b) acc += Tdo[b * 128 + i] * Ta2[b * H + j];
-        g3[q] += acc;
-        const int j1 = e / r, i1 = e % r;  // dW1[j1][i1]
-        float acc1 = 0.f;
-        for (int b = 0; b < nb; ++b) acc1 += Tdz1[b * H + j1] * Tx[b * r + i1];
-        g1[q] += acc1;
-      }
-    }
-    // bias gradients: db1 (H), db2 (H), db3 (r)
-    if (tid < H) {
-      float a = 0.f, c = 0.f;
-      for (int b = 0; b < nb; ++b) {
-        a += Tdz1[b * H + tid];
-        c += Tdz2[b * H + tid];
-      }
-      gb[0] += a;
-      gb[1] += c;
-    } else if (tid < H + r) {
-      float a = 0.f;
-      for (int b = 0; b < nb; ++b) a += Tdo[b * 128 + (tid - H)];
-      gb[2] += a;
-    }
-  }
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) G[o.w2 + int64_t(jb + a) * H + kb + c] += g2[a][c];
-#pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const int e = tid + NT * q;
-    if (e < r * H) {
-      G[o.w3 + e] += g3[q];
-      G[o.w1 + e] += g1[q];
-    }
-  }
-  if (tid < H) {
-    G[o.b1 + tid] += gb[0];
-    G[o.b2 + tid] += gb[1];
-  } else if (tid < H + r) {
-    G[o.b3 + tid - H] += gb[2];
-  }
-  __syncthreads();
-  return loss;
-}
-
 __device__ int64_t gcd64(int64_t a, int64_t b) {
   while (b) {
     const int64_t t = a % b;
@@ -282,6 +129,378 @@ __device__ void epoch_coeffs(int64_t N, int64_t e, int64_t& a, int64_t& c) {
   c = int64_t((uint64_t(e) * 40503ull + 17ull) % uint64_t(N));
 }
 
+// ---- trainer and gradient on the matrix cores --------------------------------
+// One workgroup of 8 waves runs a minibatch in chunks of CB = 32 rows.  Per
+// chunk (all operands in LDS, r padded with zeros to RP = 32 or 64):
+//   forward  z1 = x W1^T + b1, a1 = bf16(gelu(z1)); z2, a2 likewise;
+//            out = a2 W3^T + b3               (v_mfma_f32_16x16x32_bf16:
+//            bf16 x bf16 products are exact, sums in float32)
+//   backward dout = 2 (out - y) / (R r); dz2 = (dout W3) * gelu'(z2);
+//            dz1 = (dz2 W2) * gelu'(z1)      (v_mfma_f32_16x16x4f32)
+//   weights  dW3 += dout^T a2, dW2 += dz2^T a1, dW1 += dz1^T x, bias sums
+// gelu'(z) is kept instead of z and overwritten by dz in place.  The weight
+// gradients stay in the accumulators of their owning lanes across chunks
+// (wave w owns column block w of dW3 and dW2 and row block w of dW1), so the
+// owner applies Adam to its entries and writes their new bfloat16 copies
+// straight into the LDS weights of the next step.
+constexpr int MT = 512;  // trainer threads
+constexpr int CB = 32;   // rows per chunk
+constexpr int BPAD = 8;  // bf16 row padding (16 bytes)
+constexpr int FPAD = 4;  // fp32 row padding
+constexpr int ADAM_W = 8;  // Adam entries per thread with their loads in flight together
+
+
+template <int RP>
+struct TL {  // LDS layout (byte offsets); pitches in elements
+  static constexpr int LW1 = RP + BPAD, LW2 = H + BPAD, LW3 = H + BPAD;
+  static constexpr int LX = RP + BPAD, LA = H + BPAD;
+  static constexpr int LG = H + FPAD, LD = RP + FPAD, LY = RP;
+  static constexpr size_t w1 = 0;
+  static constexpr size_t w2 = w1 + size_t(H) * LW1 * 2;
+  static constexpr size_t w3 = w2 + size_t(H) * LW2 * 2;
+  static constexpr size_t bias = w3 + size_t(RP) * LW3 * 2;  // b1 (H) | b2 (H) | b3 (RP), float
+  static constexpr size_t xs = bias + size_t(2 * H + RP) * 4;
+  static constexpr size_t a1 = xs + size_t(CB) * LX * 2;
+  static constexpr size_t a2 = a1 + size_t(CB) * LA * 2;
+  static constexpr size_t g1 = a2 + size_t(CB) * LA * 2;
+  static constexpr size_t g2 = g1 + size_t(CB) * LG * 4;
+  static constexpr size_t dd = g2 + size_t(CB) * LG * 4;
+  static constexpr size_t ys = dd + size_t(CB) * LD * 4;
+  static constexpr size_t total = ys + size_t(CB) * LY * 4;
+};
+
+template <int RP>
+struct TPtr {
+  unsigned short *w1, *w2, *w3, *xs, *a1, *a2;
+  float *bias, *g1, *g2, *dd, *ys;
+  __device__ explicit TPtr(unsigned char* sm) {
+    using L = TL<RP>;
+    w1 = reinterpret_cast<unsigned short*>(sm + L::w1);
+    w2 = reinterpret_cast<unsigned short*>(sm + L::w2);
+    w3 = reinterpret_cast<unsigned short*>(sm + L::w3);
+    bias = reinterpret_cast<float*>(sm + L::bias);
+    xs = reinterpret_cast<unsigned short*>(sm + L::xs);
+    a1 = reinterpret_cast<unsigned short*>(sm + L::a1);
+    a2 = reinterpret_cast<unsigned short*>(sm + L::a2);
+    g1 = reinterpret_cast<float*>(sm + L::g1);
+    g2 = reinterpret_cast<float*>(sm + L::g2);
+    dd = reinterpret_cast<float*>(sm + L::dd);
+    ys = reinterpret_cast<float*>(sm + L::ys);
+  }
+};
+
+// bfloat16 weights and float biases of params into LDS (padding zero)
+template <int RP>
+__device__ void load_weights(const float* __restrict__ p, int r, const TPtr<RP>& t, int tid) {
+  using L = TL<RP>;
+  const Off o(r);
+  for (int e = tid; e < H * L::LW1; e += MT) {
+    const int j = e / L::LW1, i = e % L::LW1;
+    t.w1[e] = (i < r) ? bf16_bits(p[o.w1 + int64_t(j) * r + i]) : 0;
+  }
+  for (int e = tid; e < H * L::LW2; e += MT) {
+    const int j = e / L::LW2, k = e % L::LW2;
+    t.w2[e] = (k < H) ? bf16_bits(p[o.w2 + int64_t(j) * H + k]) : 0;
+  }
+  for (int e = tid; e < RP * L::LW3; e += MT) {
+    const int i = e / L::LW3, j = e % L::LW3;
+    t.w3[e] = (i < r && j < H) ? bf16_bits(p[o.w3 + int64_t(i) * H + j]) : 0;
+  }
+  for (int e = tid; e < 2 * H + RP; e += MT) {
+    float b = 0.f;
+    if (e < H)
+      b = p[o.b1 + e];
+    else if (e < 2 * H)
+      b = p[o.b2 + e - H];
+    else if (e - 2 * H < r)
+      b = p[o.b3 + e - 2 * H];
+    t.bias[e] = b;
+  }
+}
+
+__device__ __forceinline__ float bfv(const unsigned short* p, int i) { return __uint_as_float(unsigned(p[i]) << 16); }
+
+// 16 x 16 block (rb, cb) of A W^T with A (rows) and W (rows = output columns)
+// bfloat16 row-major in LDS, K a multiple of 32
+template <int K>
+__device__ __forceinline__ flt4 mm_bf16(const unsigned short* A, int lda, const unsigned short* W, int ldw, int rb,
+                                        int cb, int lane) {
+  flt4 acc = {0.f, 0.f, 0.f, 0.f};
+  const unsigned short* ap = A + (rb * 16 + (lane & 15)) * lda + 8 * (lane >> 4);
+  const unsigned short* wp = W + (cb * 16 + (lane & 15)) * ldw + 8 * (lane >> 4);
+#pragma unroll
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    const bf16x8 a = __builtin_bit_cast(bf16x8, *reinterpret_cast<const us8*>(ap + k0));
+    const bf16x8 b = __builtin_bit_cast(bf16x8, *reinterpret_cast<const us8*>(wp + k0));
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+// Per-step state of a lane: weight-gradient blocks and bias sums.
+template <int RP>
+struct GAcc {
+  flt4 w3[RP / 16];  // dW3 (row block u, column block w)
+  flt4 w2[8];        // dW2 (row block u, column block w)
+  flt4 w1[RP / 16];  // dW1 (row block w, column block u)
+  float db;          // tid < H: db1[tid]; H <= tid < 2H: db2; 2H <= tid < 2H + RP: db3
+  float loss;        // this lane's share of sum (out - y)^2
+};
+
+// One minibatch of R rows (row b of the batch = data row rowof(b)): gradient
+// sums of the mean loss into g.
+template <int RP, class RowOf>
+__device__ void batch_grad(int r, const double* __restrict__ X, const double* __restrict__ Y,
+                           const double* __restrict__ norm, int R, RowOf rowof, const TPtr<RP>& t, GAcc<RP>& g) {
+  using L = TL<RP>;
+  const int tid = threadIdx.x, lane0 = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const float scale = 2.0f / float(R * r);
+#pragma unroll
+  for (int u = 0; u < RP / 16; ++u) g.w3[u] = g.w1[u] = flt4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int u = 0; u < 8; ++u) g.w2[u] = flt4{0.f, 0.f, 0.f, 0.f};
+  g.db = 0.f;
+  g.loss = 0.f;
+  const int fr = w & 1, fc = w >> 1;  // forward / dz block coordinates: rows fr, columns fc and fc + 4
+  // this thread's entries of a chunk (element e = tid + MT q of CB x RP):
+  // fetched into registers one chunk ahead, so their global loads fly while
+  // the previous chunk is computed
+  constexpr int NQ = CB * RP / MT;
+  double xr[NQ], yr[NQ];
+  auto fetch = [&](int c0) {
+    const int Rc = min(CB, R - c0);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int e = tid + MT * q, b = e / RP, i = e % RP;
+      xr[q] = 0.0;
+      yr[q] = 0.0;
+      if (b < Rc && i < r) {
+        const int64_t row = rowof(c0 + b);
+        xr[q] = X[row * r + i];
+        yr[q] = Y[row * r + i];
+      }
+    }
+  };
+  fetch(0);
+  for (int c0 = 0; c0 < R; c0 += CB) {
+    const int Rc = min(CB, R - c0);
+    // the lane index made opaque per chunk: keeps the compiler from hoisting
+    // the chunk's many LDS addresses out of the batch and epoch loops, where
+    // they would stay live (and spill) across the whole step
+    int lane = lane0;
+    asm volatile("" : "+v"(lane));
+    // ---- chunk rows: standardized x (bf16) and y ---------------------------
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int e = tid + MT * q, b = e / RP, i = e % RP;
+      float xv = 0.f, yv = 0.f;
+      if (b < Rc && i < r) {
+        xv = bf16f(static_cast<float>((xr[q] - norm[i]) / norm[r + i]));
+        yv = static_cast<float>((yr[q] - norm[2 * r + i]) / norm[3 * r + i]);
+      }
+      t.xs[b * L::LX + i] = bf16_bits(xv);
+      t.ys[b * L::LY + i] = yv;
+    }
+    __syncthreads();
+    if (c0 + CB < R) fetch(c0 + CB);
+    // ---- forward ------------------------------------------------------------
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int cb = fc + 4 * h;
+      const flt4 acc = mm_bf16<RP>(t.xs, L::LX, t.w1, L::LW1, fr, cb, lane);
+      const int col = cb * 16 + (lane & 15);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = fr * 16 + 4 * (lane >> 4) + e;
+        const float z = acc[e] + t.bias[col];
+        t.a1[row * L::LA + col] = bf16_bits(gelu_f(z));
+        t.g1[row * L::LG + col] = gelu_grad_f(z);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int cb = fc + 4 * h;
+      const flt4 acc = mm_bf16<H>(t.a1, L::LA, t.w2, L::LW2, fr, cb, lane);
+      const int col = cb * 16 + (lane & 15);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = fr * 16 + 4 * (lane >> 4) + e;
+        const float z = acc[e] + t.bias[H + col];
+        t.a2[row * L::LA + col] = bf16_bits(gelu_f(z));
+        t.g2[row * L::LG + col] = gelu_grad_f(z);
+      }
+    }
+    __syncthreads();
+    if (w < 2 * (RP / 16)) {  // out and dout, blocks (w & 1, w >> 1)
+      const flt4 acc = mm_bf16<H>(t.a2, L::LA, t.w3, L::LW3, fr, fc, lane);
+      const int col = fc * 16 + (lane & 15);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = fr * 16 + 4 * (lane >> 4) + e;
+        float d = 0.f;
+        if (row < Rc && col < r) d = (acc[e] + t.bias[2 * H + col]) - t.ys[row * L::LY + col];
+        g.loss += d * d;
+        t.dd[row * L::LD + col] = scale * d;
+      }
+    }
+    __syncthreads();
+    // ---- dz2 = (dout W3) * gelu'(z2) in place; dW3 += dout^T a2 -------------
+    {  // blocks (fr, fc) and (fr, fc + 4) share their A fragments
+      flt4 acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+#pragma unroll 4
+      for (int k0 = 0; k0 < RP; k0 += 4) {
+        const int k = k0 + (lane >> 4);
+        const float av = t.dd[(fr * 16 + (lane & 15)) * L::LD + k];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+          acc[h] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bfv(t.w3, k * L::LW3 + (fc + 4 * h) * 16 + (lane & 15)),
+                                                        acc[h], 0, 0, 0);
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int col = (fc + 4 * h) * 16 + (lane & 15);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int row = fr * 16 + 4 * (lane >> 4) + e;
+          t.g2[row * L::LG + col] *= acc[h][e];
+        }
+      }
+    }
+#pragma unroll 2
+    for (int k0 = 0; k0 < CB; k0 += 4) {
+      const int b = k0 + (lane >> 4);
+      const float bv = bfv(t.a2, b * L::LA + w * 16 + (lane & 15));
+#pragma unroll
+      for (int u = 0; u < RP / 16; ++u)
+        g.w3[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(t.dd[b * L::LD + u * 16 + (lane & 15)], bv, g.w3[u], 0, 0, 0);
+    }
+    __syncthreads();
+    // ---- dz1 = (dz2 W2) * gelu'(z1) in place; dW2 += dz2^T a1 ----------------
+    {
+      flt4 acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+#pragma unroll 4
+      for (int k0 = 0; k0 < H; k0 += 4) {
+        const int k = k0 + (lane >> 4);
+        const float av = t.g2[(fr * 16 + (lane & 15)) * L::LG + k];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+          acc[h] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bfv(t.w2, k * L::LW2 + (fc + 4 * h) * 16 + (lane & 15)),
+                                                        acc[h], 0, 0, 0);
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int col = (fc + 4 * h) * 16 + (lane & 15);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int row = fr * 16 + 4 * (lane >> 4) + e;
+          t.g1[row * L::LG + col] *= acc[h][e];
+        }
+      }
+    }
+#pragma unroll 2
+    for (int k0 = 0; k0 < CB; k0 += 4) {
+      const int b = k0 + (lane >> 4);
+      const float bv = bfv(t.a1, b * L::LA + w * 16 + (lane & 15));
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        g.w2[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(t.g2[b * L::LG + u * 16 + (lane & 15)], bv, g.w2[u], 0, 0, 0);
+    }
+    __syncthreads();
+    // ---- dW1 += dz1^T x; bias sums --------------------------------------------
+#pragma unroll 2
+    for (int k0 = 0; k0 < CB; k0 += 4) {
+      const int b = k0 + (lane >> 4);
+      const float av = t.g1[b * L::LG + w * 16 + (lane & 15)];
+#pragma unroll
+      for (int u = 0; u < RP / 16; ++u)
+        g.w1[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bfv(t.xs, b * L::LX + u * 16 + (lane & 15)), g.w1[u], 0, 0, 0);
+    }
+    // bias sums over all CB rows (rows past the batch hold zero gradients),
+    // every load in flight before the adds: threads 0..127 db1, 128..255
+    // db2, 256..256+RP-1 db3
+    if (tid < 2 * H + RP) {
+      const float* src = tid < H ? t.g1 + tid : (tid < 2 * H ? t.g2 + (tid - H) : t.dd + (tid - 2 * H));
+      const int pitch = tid < 2 * H ? L::LG : L::LD;
+      float va[CB];
+#pragma unroll
+      for (int b = 0; b < CB; ++b) va[b] = src[b * pitch];
+      float sa = 0.f;
+#pragma unroll
+      for (int b = 0; b < CB; ++b) sa += va[b];
+      g.db += sa;
+    }
+    __syncthreads();
+  }
+}
+
+// Visit every gradient entry this lane owns: f(parameter index, gradient).
+template <int RP, class F>
+__device__ void for_owned(int r, const TPtr<RP>& t, const GAcc<RP>& g, F f) {
+  const Off o(r);
+  const int tid = threadIdx.x, w = tid >> 6;
+  int lane = tid & 63;
+  asm volatile("" : "+v"(lane));  // no index hoisted out of the caller's loops
+#pragma unroll
+  for (int u = 0; u < RP / 16; ++u)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int i = u * 16 + 4 * (lane >> 4) + e, j = w * 16 + (lane & 15);  // dW3[i][j]
+      if (i < r) f(o.w3 + int64_t(i) * H + j, g.w3[u][e]);
+      const int j1 = w * 16 + 4 * (lane >> 4) + e, i1 = u * 16 + (lane & 15);  // dW1[j1][i1]
+      if (i1 < r) f(o.w1 + int64_t(j1) * r + i1, g.w1[u][e]);
+    }
+#pragma unroll
+  for (int u = 0; u < 8; ++u)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int j = u * 16 + 4 * (lane >> 4) + e, k = w * 16 + (lane & 15);  // dW2[j][k]
+      f(o.w2 + int64_t(j) * H + k, g.w2[u][e]);
+    }
+  if (tid < H)
+    f(o.b1 + tid, g.db);
+  else if (tid < 2 * H)
+    f(o.b2 + tid - H, g.db);
+  else if (tid < 2 * H + r)
+    f(o.b3 + tid - 2 * H, g.db);
+  (void)t;
+}
+
+// parameter e's new value into the LDS weights (bfloat16) or biases (float)
+template <int RP>
+__device__ void store_weight(int r, int e, float pn, const TPtr<RP>& t) {
+  using L = TL<RP>;
+  const int b1 = H * r, w2 = b1 + H, b2 = w2 + H * H, w3 = b2 + H, b3 = w3 + r * H;
+  if (e < b1) {
+    const int j = e / r, i = e - j * r;
+    t.w1[j * L::LW1 + i] = bf16_bits(pn);
+  } else if (e < w2) {
+    t.bias[e - b1] = pn;
+  } else if (e < b2) {
+    const int j = (e - w2) / H, k = (e - w2) % H;
+    t.w2[j * L::LW2 + k] = bf16_bits(pn);
+  } else if (e < w3) {
+    t.bias[H + (e - b2)] = pn;
+  } else if (e < b3) {
+    const int i = (e - w3) / H, j = (e - w3) % H;
+    t.w3[i * L::LW3 + j] = bf16_bits(pn);
+  } else {
+    t.bias[2 * H + (e - b3)] = pn;
+  }
+}
+
+// workgroup sum of the lanes' loss shares (every thread gets it)
+__device__ float block_loss(float v, float* red) {
+  v = float(wave_sum(double(v)));
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  float s = 0.f;
+  for (int i = 0; i < MT / 64; ++i) s += red[i];
+  return s;
+}
+
 struct TrainArgs {
   int r;
   const double* X;
@@ -293,53 +512,80 @@ struct TrainArgs {
   const double* norm;
   float* m;
   float* v;
-  float* G;
+  float* G;  // batch gradient (P floats)
   float* loss_log;
-  int64_t* idx;
-  Scratch s;
 };
 
-__global__ __launch_bounds__(TT) void train_kernel(TrainArgs a) {
-  extern __shared__ unsigned char smem[];
-  __shared__ float red[TT / 64];
+template <int RP>
+__global__ __launch_bounds__(MT) void train_kernel(TrainArgs a) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  __shared__ float red[MT / 64];
   const int tid = threadIdx.x;
   const int r = a.r;
   const Off o(r);
-  unsigned short* Wb = reinterpret_cast<unsigned short*>(smem);
-  float* tile = reinterpret_cast<float*>(smem + round_up(size_t(o.P - 2 * H - r) * 2, 16));
-  for (int64_t e = tid; e < o.P; e += TT) {
+  const TPtr<RP> t(smem);
+  for (int64_t e = tid; e < o.P; e += MT) {
     a.m[e] = 0.f;
     a.v[e] = 0.f;
-    a.G[e] = 0.f;
   }
+  load_weights<RP>(a.params, r, t, tid);
+  __syncthreads();
+  GAcc<RP> g;
   int64_t step = 0;
+  __shared__ int rows_sh[BMAX];  // the minibatch's data rows
+  const int P = int(o.P);
+  float* __restrict__ Gp = a.G;
+  float* __restrict__ mp = a.m;
+  float* __restrict__ vp = a.v;
+  float* __restrict__ pp = a.params;
   for (int ep = 0; ep < a.epochs; ++ep) {
     int64_t ca, cc;
     epoch_coeffs(a.N, ep, ca, cc);
     double ltot = 0.0;
     for (int64_t s0 = 0; s0 < a.N; s0 += a.batch) {
       const int R = int(min<int64_t>(a.batch, a.N - s0));
+      for (int b = tid; b < R; b += MT) rows_sh[b] = int((ca * (s0 + b) + cc) % a.N);
       __syncthreads();
-      for (int b = tid; b < R; b += TT) a.idx[b] = (ca * (s0 + b) + cc) % a.N;
-      load_wb(a.params, r, Wb, tid, TT);
-      __syncthreads();
-      load_batch<TT>(R, r, a.X, a.Y, a.norm, a.idx, 0, a.s, tid);
-      mlp_fwd<TT>(R, r, Wb, a.params, a.s.x, a.s.z1, a.s.a1, a.s.z2, a.s.a2, a.s.out, tid);
-      const float loss = mlp_bwd<TT>(R, r, Wb, a.s, a.G, tile, red, tid);
+      batch_grad<RP>(r, a.X, a.Y, a.norm, R, [&](int b) { return int64_t(rows_sh[b]); }, t, g);
+      const float loss = block_loss(g.loss, red) / float(R * r);
       ltot += double(loss) * R;
       ++step;
-      // Adam (Kingma & Ba 2015): bias corrections in double
+      // the owners store the batch gradient; then Adam (Kingma & Ba 2015,
+      // bias corrections in double) over all entries, ADAM_W per thread in
+      // flight, each written back to the master weights and as bfloat16 into
+      // the LDS weights
+      for_owned<RP>(r, t, g, [&](int64_t e, float gr) { Gp[e] = gr; });
+      __syncthreads();
       const float c1 = static_cast<float>(1.0 - pow(double(a.beta1), double(step)));
       const float c2 = static_cast<float>(1.0 - pow(double(a.beta2), double(step)));
-      for (int64_t e = tid; e < o.P; e += TT) {
-        const float g = a.G[e];
-        const float mm = a.beta1 * a.m[e] + (1.0f - a.beta1) * g;
-        const float vv = a.beta2 * a.v[e] + (1.0f - a.beta2) * g * g;
-        a.m[e] = mm;
-        a.v[e] = vv;
-        a.params[e] -= a.lr * (mm / c1) / (sqrtf(vv / c2) + a.eps);
-        a.G[e] = 0.f;
+      for (int e0 = tid; e0 < P; e0 += ADAM_W * MT) {
+        float gr[ADAM_W], mo[ADAM_W], vo[ADAM_W], po[ADAM_W];
+#pragma unroll
+        for (int u = 0; u < ADAM_W; ++u) {
+          const int e = e0 + u * MT;
+          gr[u] = mo[u] = vo[u] = po[u] = 0.f;
+          if (e < P) {
+            gr[u] = Gp[e];
+            mo[u] = mp[e];
+            vo[u] = vp[e];
+            po[u] = pp[e];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < ADAM_W; ++u) {
+          const int e = e0 + u * MT;
+          if (e < P) {
+            const float mm = a.beta1 * mo[u] + (1.0f - a.beta1) * gr[u];
+            const float vv = a.beta2 * vo[u] + (1.0f - a.beta2) * gr[u] * gr[u];
+            mp[e] = mm;
+            vp[e] = vv;
+            const float pn = po[u] - a.lr * (mm / c1) / (sqrtf(vv / c2) + a.eps);
+            pp[e] = pn;
+            store_weight<RP>(r, e, pn, t);
+          }
+        }
       }
+      __syncthreads();
     }
     if (tid == 0 && a.loss_log) a.loss_log[ep] = static_cast<float>(ltot / double(a.N));
   }
@@ -354,29 +600,23 @@ struct GradArgs {
   const double* norm;
   float* G;
   float* loss;
-  Scratch s;
 };
 
 // gradient of the mean loss over N <= BMAX rows
-__global__ __launch_bounds__(TT) void grad_kernel(GradArgs a) {
-  extern __shared__ unsigned char smem[];
-  __shared__ float red[TT / 64];
+template <int RP>
+__global__ __launch_bounds__(MT) void grad_kernel(GradArgs a) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  __shared__ float red[MT / 64];
   const int tid = threadIdx.x;
-  const int r = a.r;
-  const Off o(r);
-  unsigned short* Wb = reinterpret_cast<unsigned short*>(smem);
-  float* tile = reinterpret_cast<float*>(smem + round_up(size_t(o.P - 2 * H - r) * 2, 16));
-  for (int64_t e = tid; e < o.P; e += TT) a.G[e] = 0.f;
-  load_wb(a.params, r, Wb, tid, TT);
+  const TPtr<RP> t(smem);
+  load_weights<RP>(a.params, a.r, t, tid);
   __syncthreads();
-  double ltot = 0.0;
-  {  // N <= BMAX: one batch, the gradient of its mean loss
-    const int R = int(a.N);
-    load_batch<TT>(R, r, a.X, a.Y, a.norm, nullptr, 0, a.s, tid);
-    mlp_fwd<TT>(R, r, Wb, a.params, a.s.x, a.s.z1, a.s.a1, a.s.z2, a.s.a2, a.s.out, tid);
-    ltot = double(mlp_bwd<TT>(R, r, Wb, a.s, a.G, tile, red, tid)) * R;
-  }
-  if (tid == 0) *a.loss = static_cast<float>(ltot / double(a.N));
+  GAcc<RP> g;
+  const int R = int(a.N);
+  batch_grad<RP>(a.r, a.X, a.Y, a.norm, R, [](int b) { return int64_t(b); }, t, g);
+  const float loss = block_loss(g.loss, red) / float(R * a.r);
+  for_owned<RP>(a.r, t, g, [&](int64_t e, float gr) { a.G[e] = gr; });
+  if (tid == 0) *a.loss = loss;
 }
 
 // per-mode statistics of X and Y (N x r each): norm = [mx | sx | my | sy]
@@ -798,24 +1038,9 @@ __global__ __launch_bounds__(256) void ref_stats_kernel(const double* __restrict
 }
 
 size_t wb_bytes(int r) { return round_up(size_t(Off(r).P - 2 * H - r) * 2, 16); }
-size_t train_lds(int r) { return wb_bytes(r) + size_t(BT) * (4 * H + 128 + r) * 4; }
+size_t train_lds(int r) { return r <= 32 ? TL<32>::total : TL<64>::total; }
 size_t eval_lds(int r) { return wb_bytes(r) + round_up(size_t(RG) * r * 4, 16) + size_t(RG) * 2 * H * 4 + round_up(size_t(RG) * r * 4, 16); }
 size_t roll_lds(int r, bool res) { return RollLds(r, res ? CR_RES : CR_STREAM).total; }
-
-Scratch carve_scratch(Carver& c, int r) {
-  Scratch s;
-  s.x = c.take<float>(size_t(BMAX) * r);
-  s.y = c.take<float>(size_t(BMAX) * r);
-  s.z1 = c.take<float>(size_t(BMAX) * H);
-  s.a1 = c.take<float>(size_t(BMAX) * H);
-  s.z2 = c.take<float>(size_t(BMAX) * H);
-  s.a2 = c.take<float>(size_t(BMAX) * H);
-  s.out = c.take<float>(size_t(BMAX) * r);
-  s.dout = c.take<float>(size_t(BMAX) * r);
-  s.dz2 = c.take<float>(size_t(BMAX) * H);
-  s.dz1 = c.take<float>(size_t(BMAX) * H);
-  return s;
-}
 
 int set_lds(const void* fn, size_t bytes) {
   int dev = 0, maxlds = 0;
@@ -846,12 +1071,8 @@ extern "C" int dopinf_rom_residuals(void* stream, const double* O, int r, const 
 }
 
 extern "C" size_t dopinf_closure_fit_workspace(int r, int64_t /*N*/) {
-  if (r < 1 || r > 64) return 0;
-  Carver c(nullptr, 0);
-  carve_scratch(c, r);
-  c.take<float>(size_t(Off(r).P));
-  c.take<int64_t>(BMAX);
-  return c.used;
+  // the batch gradient (activations live in LDS)
+  return (r >= 1 && r <= 64) ? round_up(size_t(Off(r).P) * sizeof(float), 256) : 0;
 }
 
 extern "C" int dopinf_closure_fit(void* stream, int r, const double* X, const double* Y, int64_t N, int epochs,
@@ -865,13 +1086,11 @@ extern "C" int dopinf_closure_fit(void* stream, int r, const double* X, const do
   const size_t need = dopinf_closure_fit_workspace(r, N);
   if (!ws || ws_bytes < need) return fail(DOPINF_E_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  int rc = set_lds(reinterpret_cast<const void*>(train_kernel), train_lds(r));
+  const void* kern = r <= 32 ? reinterpret_cast<const void*>(train_kernel<32>)
+                             : reinterpret_cast<const void*>(train_kernel<64>);
+  int rc = set_lds(kern, train_lds(r));
   if (rc) return rc;
-  Carver c(ws, ws_bytes);
   TrainArgs a{};
-  a.s = carve_scratch(c, r);
-  a.G = c.take<float>(size_t(Off(r).P));
-  a.idx = c.take<int64_t>(BMAX);
   a.r = r;
   a.X = X;
   a.Y = Y;
@@ -887,9 +1106,13 @@ extern "C" int dopinf_closure_fit(void* stream, int r, const double* X, const do
   a.m = adam_m;
   a.v = adam_v;
   a.loss_log = loss_log;
+  a.G = static_cast<float*>(ws);
   norm_kernel<<<2 * r, 256, 0, st>>>(X, Y, N, r, norm);
   DOPINF_LAUNCHED();
-  train_kernel<<<1, TT, train_lds(r), st>>>(a);
+  if (r <= 32)
+    train_kernel<32><<<1, MT, train_lds(r), st>>>(a);
+  else
+    train_kernel<64><<<1, MT, train_lds(r), st>>>(a);
   DOPINF_LAUNCHED();
   return DOPINF_OK;
 }
@@ -907,11 +1130,11 @@ extern "C" int dopinf_closure_grad(void* stream, int r, const float* params, con
   DOPINF_REQUIRE(r >= 1 && r <= 64 && N >= 1 && N <= BMAX, "need 1 <= r <= 64 and 1 <= N <= 256");
   const size_t need = dopinf_closure_fit_workspace(r, N);
   if (!ws || ws_bytes < need) return fail(DOPINF_E_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
-  int rc = set_lds(reinterpret_cast<const void*>(grad_kernel), train_lds(r));
+  const void* kern = r <= 32 ? reinterpret_cast<const void*>(grad_kernel<32>)
+                             : reinterpret_cast<const void*>(grad_kernel<64>);
+  int rc = set_lds(kern, train_lds(r));
   if (rc) return rc;
-  Carver c(ws, ws_bytes);
   GradArgs a{};
-  a.s = carve_scratch(c, r);
   a.r = r;
   a.X = X;
   a.Y = Y;
@@ -920,7 +1143,11 @@ extern "C" int dopinf_closure_grad(void* stream, int r, const float* params, con
   a.norm = norm;
   a.G = grad;
   a.loss = loss;
-  grad_kernel<<<1, TT, train_lds(r), static_cast<hipStream_t>(stream)>>>(a);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (r <= 32)
+    grad_kernel<32><<<1, MT, train_lds(r), st>>>(a);
+  else
+    grad_kernel<64><<<1, MT, train_lds(r), st>>>(a);
   DOPINF_LAUNCHED();
   return DOPINF_OK;
 }
