@@ -22,11 +22,15 @@ int check_var_rows(int64_t n, int nvars, const int64_t* var_rows_h);
 namespace {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef double dbl2 __attribute__((ext_vector_type(2)));
 
 constexpr int PT = 256;   // threads: 4 waves
 constexpr int PM = 64;    // output rows per workgroup
 constexpr int PK = 32;    // K chunk staged in LDS
-constexpr int PAS = PK + 1;  // padded row of the A stage
+// Both stages hold rows of PK = 32 values (A: output rows, B: output
+// columns, i.e. B transposed) padded to 34 doubles: the 16 rows x 2 k of a
+// half-wave's fragment reads then fall on 64 different 4-byte banks.
+constexpr int PAS = PK + 2;
 
 struct VarTable {
   int nvars;
@@ -64,7 +68,7 @@ struct RowGemmArgs {
 template <class T, int NJ, int RB>
 __global__ __launch_bounds__(PT) void row_gemm_kernel(RowGemmArgs<T> a) {
   __shared__ double As[PM * RB][PAS];
-  __shared__ double Bs[PK][16 * NJ];
+  __shared__ double Bs[16 * NJ][PAS];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int64_t i0 = int64_t(blockIdx.x) * PM * RB;
   const int64_t c0 = int64_t(blockIdx.y) * 16 * NJ;
@@ -93,23 +97,49 @@ __global__ __launch_bounds__(PT) void row_gemm_kernel(RowGemmArgs<T> a) {
   const int br = tid >> 3, bc = (tid & 7) * BW;
 
   double ra[RB][8], rb[BW];
+  // 16-byte loads where a thread's eight A values (or 2 NJ B values) lie
+  // inside the matrix and 16-byte aligned; element loads otherwise
+  const bool avec = sizeof(T) == 8 && (a.lda % 2) == 0 && (reinterpret_cast<uintptr_t>(a.A) % 16) == 0;
+  const bool bvec = (a.ldb % 2) == 0 && (reinterpret_cast<uintptr_t>(a.B) % 16) == 0;
   auto load = [&](int64_t kc) {
 #pragma unroll
-    for (int b = 0; b < RB; ++b)
+    for (int b = 0; b < RB; ++b) {
+      const int64_t k0 = kc + ak;
+      if (avec && src[b] >= 0 && k0 + 8 <= a.K) {
+        const double* p = reinterpret_cast<const double*>(arow[b]) + k0;
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int64_t kk = kc + ak + q;
-        const bool ok = src[b] >= 0 && kk < a.K;
-        const double x = static_cast<double>(arow[b][ok ? kk : 0]);
-        ra[b][q] = ok ? x - shift[b] : 0.0;
+        for (int h = 0; h < 4; ++h) {
+          const dbl2 x = *reinterpret_cast<const dbl2*>(p + 2 * h);
+          ra[b][2 * h] = x[0] - shift[b];
+          ra[b][2 * h + 1] = x[1] - shift[b];
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int64_t kk = k0 + q;
+          const bool ok = src[b] >= 0 && kk < a.K;
+          const double x = static_cast<double>(arow[b][ok ? kk : 0]);
+          ra[b][q] = ok ? x - shift[b] : 0.0;
+        }
       }
+    }
     const int64_t kb = kc + br;
+    if (bvec && kb < a.K && c0 + bc + BW <= a.ncol) {
+      const double* p = a.B + kb * a.ldb + c0 + bc;
 #pragma unroll
-    for (int q = 0; q < BW; ++q) {
-      const int64_t c = c0 + bc + q;
-      const bool ok = kb < a.K && c < a.ncol;
-      const double x = a.B[(ok ? kb : 0) * a.ldb + (ok ? c : 0)];
-      rb[q] = ok ? x : 0.0;
+      for (int h = 0; h < BW / 2; ++h) {
+        const dbl2 x = *reinterpret_cast<const dbl2*>(p + 2 * h);
+        rb[2 * h] = x[0];
+        rb[2 * h + 1] = x[1];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < BW; ++q) {
+        const int64_t c = c0 + bc + q;
+        const bool ok = kb < a.K && c < a.ncol;
+        const double x = a.B[(ok ? kb : 0) * a.ldb + (ok ? c : 0)];
+        rb[q] = ok ? x : 0.0;
+      }
     }
   };
 
@@ -127,7 +157,7 @@ __global__ __launch_bounds__(PT) void row_gemm_kernel(RowGemmArgs<T> a) {
 #pragma unroll
       for (int q = 0; q < 8; ++q) As[ar + PM * b][ak + q] = ra[b][q];
 #pragma unroll
-    for (int q = 0; q < BW; ++q) Bs[br][bc + q] = rb[q];
+    for (int q = 0; q < BW; ++q) Bs[bc + q][br] = rb[q];
     __syncthreads();
     if (kc + PK < a.K) load(kc + PK);
     const int kmax = (a.K - kc) < PK ? int(a.K - kc) : PK;
@@ -138,7 +168,7 @@ __global__ __launch_bounds__(PT) void row_gemm_kernel(RowGemmArgs<T> a) {
         const double af = As[16 * wv + PM * b + (lane & 15)][k];
 #pragma unroll
         for (int j = 0; j < NJ; ++j)
-          acc[b][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, Bs[k][16 * j + (lane & 15)], acc[b][j], 0, 0, 0);
+          acc[b][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, Bs[16 * j + (lane & 15)][k], acc[b][j], 0, 0, 0);
       }
     }
   }
