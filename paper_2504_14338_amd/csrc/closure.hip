@@ -22,6 +22,7 @@
 //                         latched fallback to the plain ROM when ||g|| exceeds
 //                         the threshold, growth / error / finiteness scores.
 #include "common.hpp"
+#include "xwg_sync.hpp"
 
 namespace dopinf {
 namespace {
@@ -189,33 +190,40 @@ struct TPtr {
   }
 };
 
-// bfloat16 weights and float biases of params into LDS (padding zero)
-template <int RP>
-__device__ void load_weights(const float* __restrict__ p, int r, const TPtr<RP>& t, int tid) {
+// bfloat16 weights and float biases of params into LDS (padding zero);
+// ld(index) reads one parameter
+template <int RP, class Ld>
+__device__ void load_weights(Ld ld, int r, const TPtr<RP>& t, int tid) {
   using L = TL<RP>;
   const Off o(r);
   for (int e = tid; e < H * L::LW1; e += MT) {
     const int j = e / L::LW1, i = e % L::LW1;
-    t.w1[e] = (i < r) ? bf16_bits(p[o.w1 + int64_t(j) * r + i]) : 0;
+    t.w1[e] = (i < r) ? bf16_bits(ld(o.w1 + int64_t(j) * r + i)) : 0;
   }
   for (int e = tid; e < H * L::LW2; e += MT) {
     const int j = e / L::LW2, k = e % L::LW2;
-    t.w2[e] = (k < H) ? bf16_bits(p[o.w2 + int64_t(j) * H + k]) : 0;
+    t.w2[e] = (k < H) ? bf16_bits(ld(o.w2 + int64_t(j) * H + k)) : 0;
   }
   for (int e = tid; e < RP * L::LW3; e += MT) {
     const int i = e / L::LW3, j = e % L::LW3;
-    t.w3[e] = (i < r && j < H) ? bf16_bits(p[o.w3 + int64_t(i) * H + j]) : 0;
+    t.w3[e] = (i < r && j < H) ? bf16_bits(ld(o.w3 + int64_t(i) * H + j)) : 0;
   }
   for (int e = tid; e < 2 * H + RP; e += MT) {
     float b = 0.f;
     if (e < H)
-      b = p[o.b1 + e];
+      b = ld(o.b1 + e);
     else if (e < 2 * H)
-      b = p[o.b2 + e - H];
+      b = ld(o.b2 + e - H);
     else if (e - 2 * H < r)
-      b = p[o.b3 + e - 2 * H];
+      b = ld(o.b3 + e - 2 * H);
     t.bias[e] = b;
   }
+}
+
+// float stores that reach the level coherent between workgroups on different
+// XCDs (relaxed device-scope atomics, as for the other persistent kernels)
+__device__ __forceinline__ void st_coh(float* p, float v) {
+  __hip_atomic_store(reinterpret_cast<unsigned*>(p), __float_as_uint(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ float bfv(const unsigned short* p, int i) { return __uint_as_float(unsigned(p[i]) << 16); }
@@ -247,11 +255,13 @@ struct GAcc {
   float loss;        // this lane's share of sum (out - y)^2
 };
 
-// One minibatch of R rows (row b of the batch = data row rowof(b)): gradient
-// sums of the mean loss into g.
+// Rows [c_begin, c_end) of a minibatch of R rows (row b of the batch = data
+// row rowof(b)), in chunks of CB: their share of the gradient of the
+// minibatch's mean loss into g (zero when the range holds no rows).
 template <int RP, class RowOf>
 __device__ void batch_grad(int r, const double* __restrict__ X, const double* __restrict__ Y,
-                           const double* __restrict__ norm, int R, RowOf rowof, const TPtr<RP>& t, GAcc<RP>& g) {
+                           const double* __restrict__ norm, int R, int c_begin, int c_end, RowOf rowof,
+                           const TPtr<RP>& t, GAcc<RP>& g) {
   using L = TL<RP>;
   const int tid = threadIdx.x, lane0 = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -282,8 +292,9 @@ __device__ void batch_grad(int r, const double* __restrict__ X, const double* __
       }
     }
   };
-  fetch(0);
-  for (int c0 = 0; c0 < R; c0 += CB) {
+  const int c_stop = min(R, c_end);
+  if (c_begin < c_stop) fetch(c_begin);
+  for (int c0 = c_begin; c0 < c_stop; c0 += CB) {
     const int Rc = min(CB, R - c0);
     // the lane index made opaque per chunk: keeps the compiler from hoisting
     // the chunk's many LDS addresses out of the batch and epoch loops, where
@@ -303,7 +314,7 @@ __device__ void batch_grad(int r, const double* __restrict__ X, const double* __
       t.ys[b * L::LY + i] = yv;
     }
     __syncthreads();
-    if (c0 + CB < R) fetch(c0 + CB);
+    if (c0 + CB < c_stop) fetch(c0 + CB);
     // ---- forward ------------------------------------------------------------
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -467,26 +478,62 @@ __device__ void for_owned(int r, const TPtr<RP>& t, const GAcc<RP>& g, F f) {
   (void)t;
 }
 
-// parameter e's new value into the LDS weights (bfloat16) or biases (float)
+// Float image of the LDS weights: the bfloat16 arrays w1 | w2 | w3 (with
+// their padding, same order) as floats, then b1 | b2 | b3.  The Adam step
+// writes each parameter's new value at its place; every workgroup then
+// converts the whole image into its LDS with 16-byte loads.
 template <int RP>
-__device__ void store_weight(int r, int e, float pn, const TPtr<RP>& t) {
+struct Img {
+  using L = TL<RP>;
+  static constexpr int NWB = H * L::LW1 + H * L::LW2 + RP * L::LW3;  // weight entries
+  static constexpr int N = NWB + 2 * H + RP;
+};
+
+// image position of parameter e
+template <int RP>
+__device__ int img_index(int r, int e) {
   using L = TL<RP>;
   const int b1 = H * r, w2 = b1 + H, b2 = w2 + H * H, w3 = b2 + H, b3 = w3 + r * H;
+  constexpr int o2 = H * L::LW1, o3 = o2 + H * L::LW2, ob = Img<RP>::NWB;
   if (e < b1) {
-    const int j = e / r, i = e - j * r;
-    t.w1[j * L::LW1 + i] = bf16_bits(pn);
-  } else if (e < w2) {
-    t.bias[e - b1] = pn;
-  } else if (e < b2) {
-    const int j = (e - w2) / H, k = (e - w2) % H;
-    t.w2[j * L::LW2 + k] = bf16_bits(pn);
-  } else if (e < w3) {
-    t.bias[H + (e - b2)] = pn;
-  } else if (e < b3) {
-    const int i = (e - w3) / H, j = (e - w3) % H;
-    t.w3[i * L::LW3 + j] = bf16_bits(pn);
-  } else {
-    t.bias[2 * H + (e - b3)] = pn;
+    const int j = e / r;
+    return j * L::LW1 + (e - j * r);
+  }
+  if (e < w2) return ob + (e - b1);
+  if (e < b2) return o2 + ((e - w2) / H) * L::LW2 + (e - w2) % H;
+  if (e < w3) return ob + H + (e - b2);
+  if (e < b3) return o3 + ((e - w3) / H) * L::LW3 + (e - w3) % H;
+  return ob + 2 * H + (e - b3);
+}
+
+// the image into the LDS weights and biases (all of a thread's loads in
+// flight); the caller has invalidated its caches (acquire fence) after the
+// other workgroups' device-coherent stores
+template <int RP>
+__device__ void reload_weights(const float* img, const TPtr<RP>& t, int tid) {
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  typedef unsigned short u4 __attribute__((ext_vector_type(4)));
+  constexpr int Q = Img<RP>::N / 4, QW = Img<RP>::NWB / 4;
+  constexpr int RW = 9;  // loads per thread in flight; two passes cover r <= 64
+  for (int q0 = tid; q0 < Q; q0 += RW * MT) {
+    f4 v[RW];
+#pragma unroll
+    for (int u = 0; u < RW; ++u) {
+      const int q = q0 + u * MT;
+      v[u] = (q < Q) ? reinterpret_cast<const f4*>(img)[q] : f4{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int u = 0; u < RW; ++u) {
+      const int q = q0 + u * MT;
+      if (q < QW) {
+        u4 b;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) b[c] = bf16_bits(v[u][c]);
+        *reinterpret_cast<u4*>(t.w1 + 4 * q) = b;  // w1 | w2 | w3 are contiguous
+      } else if (q < Q) {
+        *reinterpret_cast<f4*>(t.bias + 4 * (q - QW)) = v[u];
+      }
+    }
   }
 }
 
@@ -512,82 +559,130 @@ struct TrainArgs {
   const double* norm;
   float* m;
   float* v;
-  float* G;  // batch gradient (P floats)
+  float* Gpart;     // per workgroup: its share of the minibatch gradient (P floats each)
+  float* lpart;     // per workgroup: its share of the minibatch's squared error
+  float* img;       // float image of the LDS weights (Img)
+  unsigned* words;  // [0] barrier counter, [1] abort flag (zero at launch)
   float* loss_log;
 };
 
+// One cooperative launch of ceil(batch / CB) workgroups runs every epoch.
+// Per minibatch, workgroup w takes rows [CB w, CB w + CB): forward, backward
+// and its share of the gradient (batch_grad), stored to Gpart[w]; a
+// device-wide barrier; then each workgroup sums the shares of its slice of
+// the P parameters in workgroup order (deterministic) and applies Adam to
+// that slice (m and v stay with their workgroup); a second barrier; then
+// every workgroup reads the new parameters into its LDS weights.  Shared
+// data is stored with device-coherent stores and read with plain loads
+// after an acquire fence that invalidates the reader's caches.  A barrier that times
+// out raises the abort flag: every workgroup leaves and the loss log reads
+// NaN from that epoch on.
 template <int RP>
 __global__ __launch_bounds__(MT) void train_kernel(TrainArgs a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   __shared__ float red[MT / 64];
+  __shared__ int rows_sh[BMAX];  // the minibatch's data rows
   const int tid = threadIdx.x;
+  const int wg = blockIdx.x, nw = gridDim.x;
   const int r = a.r;
   const Off o(r);
   const TPtr<RP> t(smem);
-  for (int64_t e = tid; e < o.P; e += MT) {
-    a.m[e] = 0.f;
-    a.v[e] = 0.f;
-  }
-  load_weights<RP>(a.params, r, t, tid);
-  __syncthreads();
-  GAcc<RP> g;
-  int64_t step = 0;
-  __shared__ int rows_sh[BMAX];  // the minibatch's data rows
   const int P = int(o.P);
-  float* __restrict__ Gp = a.G;
+  const int lo = int(int64_t(P) * wg / nw), hi = int(int64_t(P) * (wg + 1) / nw);  // this workgroup's Adam slice
   float* __restrict__ mp = a.m;
   float* __restrict__ vp = a.v;
-  float* __restrict__ pp = a.params;
+  for (int e = lo + tid; e < hi; e += MT) {
+    mp[e] = 0.f;
+    vp[e] = 0.f;
+  }
+  load_weights<RP>([&](int64_t e) { return a.params[e]; }, r, t, tid);
+  __syncthreads();
+  if (wg == 0) {  // the image of the initial weights, padding included
+    const unsigned short* wb = t.w1;
+    for (int q = tid; q < Img<RP>::NWB; q += MT) st_coh(a.img + q, bfv(wb, q));
+    for (int q = tid; q < 2 * H + RP; q += MT) st_coh(a.img + Img<RP>::NWB + q, t.bias[q]);
+  }
+  unsigned gen = 0;
+  unsigned* bar = a.words;
+  int* abort_flag = reinterpret_cast<int*>(a.words + 1);
+  GAcc<RP> g;
+  int64_t step = 0;
   for (int ep = 0; ep < a.epochs; ++ep) {
     int64_t ca, cc;
     epoch_coeffs(a.N, ep, ca, cc);
     double ltot = 0.0;
-    for (int64_t s0 = 0; s0 < a.N; s0 += a.batch) {
+    bool ok = true;
+    for (int64_t s0 = 0; s0 < a.N && ok; s0 += a.batch) {
       const int R = int(min<int64_t>(a.batch, a.N - s0));
       for (int b = tid; b < R; b += MT) rows_sh[b] = int((ca * (s0 + b) + cc) % a.N);
       __syncthreads();
-      batch_grad<RP>(r, a.X, a.Y, a.norm, R, [&](int b) { return int64_t(rows_sh[b]); }, t, g);
-      const float loss = block_loss(g.loss, red) / float(R * r);
-      ltot += double(loss) * R;
+      batch_grad<RP>(r, a.X, a.Y, a.norm, R, wg * CB, wg * CB + CB, [&](int b) { return int64_t(rows_sh[b]); }, t,
+                     g);
+      const float lsum = block_loss(g.loss, red);
+      float* gmine = a.Gpart + int64_t(wg) * P;
+      for_owned<RP>(r, t, g, [&](int64_t e, float gr) { st_coh(gmine + e, gr); });
+      if (tid == 0) st_coh(a.lpart + wg, lsum);
+      if (!xwg::team_barrier(bar, unsigned(nw), gen, abort_flag)) {
+        ok = false;
+        break;
+      }
+      // drop this CU's and this XCD's cached copies of data that other
+      // workgroups stored (their stores went to the coherent level), so
+      // plain loads, which the compiler may batch, read the new values
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      float ls = 0.f;
+      for (int q = 0; q < nw; ++q) ls += a.lpart[q];
+      ltot += double(ls / float(R * r)) * R;
       ++step;
-      // the owners store the batch gradient; then Adam (Kingma & Ba 2015,
-      // bias corrections in double) over all entries, ADAM_W per thread in
-      // flight, each written back to the master weights and as bfloat16 into
-      // the LDS weights
-      for_owned<RP>(r, t, g, [&](int64_t e, float gr) { Gp[e] = gr; });
-      __syncthreads();
+      // Adam (Kingma & Ba 2015; bias corrections in double) on this
+      // workgroup's slice, ADAM_W entries per thread with their loads in flight
       const float c1 = static_cast<float>(1.0 - pow(double(a.beta1), double(step)));
       const float c2 = static_cast<float>(1.0 - pow(double(a.beta2), double(step)));
-      for (int e0 = tid; e0 < P; e0 += ADAM_W * MT) {
+      for (int e0 = lo + tid; e0 < hi; e0 += ADAM_W * MT) {
         float gr[ADAM_W], mo[ADAM_W], vo[ADAM_W], po[ADAM_W];
 #pragma unroll
         for (int u = 0; u < ADAM_W; ++u) {
           const int e = e0 + u * MT;
           gr[u] = mo[u] = vo[u] = po[u] = 0.f;
-          if (e < P) {
-            gr[u] = Gp[e];
+          if (e < hi) {
+            float sh[BMAX / CB];  // the shares, all loads in flight, summed in order
+#pragma unroll
+            for (int q = 0; q < BMAX / CB; ++q) sh[q] = (q < nw) ? a.Gpart[int64_t(q) * P + e] : 0.f;
+#pragma unroll
+            for (int q = 0; q < BMAX / CB; ++q) gr[u] += sh[q];
             mo[u] = mp[e];
             vo[u] = vp[e];
-            po[u] = pp[e];
+            po[u] = a.params[e];
           }
         }
 #pragma unroll
         for (int u = 0; u < ADAM_W; ++u) {
           const int e = e0 + u * MT;
-          if (e < P) {
+          if (e < hi) {
             const float mm = a.beta1 * mo[u] + (1.0f - a.beta1) * gr[u];
             const float vv = a.beta2 * vo[u] + (1.0f - a.beta2) * gr[u] * gr[u];
             mp[e] = mm;
             vp[e] = vv;
             const float pn = po[u] - a.lr * (mm / c1) / (sqrtf(vv / c2) + a.eps);
-            pp[e] = pn;
-            store_weight<RP>(r, e, pn, t);
+            st_coh(a.params + e, pn);
+            st_coh(a.img + img_index<RP>(r, e), pn);
           }
         }
       }
+      if (!xwg::team_barrier(bar, unsigned(nw), gen, abort_flag)) {
+        ok = false;
+        break;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      reload_weights<RP>(a.img, t, tid);
       __syncthreads();
     }
-    if (tid == 0 && a.loss_log) a.loss_log[ep] = static_cast<float>(ltot / double(a.N));
+    if (!ok) {
+      if (wg == 0 && tid == 0 && a.loss_log)
+        for (int e = ep; e < a.epochs; ++e) a.loss_log[e] = __builtin_nanf("");
+      return;
+    }
+    if (wg == 0 && tid == 0 && a.loss_log) a.loss_log[ep] = static_cast<float>(ltot / double(a.N));
   }
 }
 
@@ -609,14 +704,18 @@ __global__ __launch_bounds__(MT) void grad_kernel(GradArgs a) {
   __shared__ float red[MT / 64];
   const int tid = threadIdx.x;
   const TPtr<RP> t(smem);
-  load_weights<RP>(a.params, a.r, t, tid);
+  load_weights<RP>([&](int64_t e) { return a.params[e]; }, a.r, t, tid);
   __syncthreads();
   GAcc<RP> g;
   const int R = int(a.N);
-  batch_grad<RP>(a.r, a.X, a.Y, a.norm, R, [](int b) { return int64_t(b); }, t, g);
+  batch_grad<RP>(a.r, a.X, a.Y, a.norm, R, 0, R, [](int b) { return int64_t(b); }, t, g);
   const float loss = block_loss(g.loss, red) / float(R * a.r);
   for_owned<RP>(a.r, t, g, [&](int64_t e, float gr) { a.G[e] = gr; });
   if (tid == 0) *a.loss = loss;
+}
+
+__global__ void zero_u32_kernel(unsigned* p, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
 }
 
 // per-mode statistics of X and Y (N x r each): norm = [mx | sx | my | sy]
@@ -1070,9 +1169,23 @@ extern "C" int dopinf_rom_residuals(void* stream, const double* O, int r, const 
   return DOPINF_OK;
 }
 
+// the trainer's workgroups exchange gradient shares (one P-vector each, at
+// most BMAX / CB workgroups), loss shares and a barrier word through this
+// (activations live in LDS)
+Carver carve_fit(void* ws, int r, float** gpart, float** lpart, float** img, unsigned** words) {
+  Carver c(ws, ~size_t(0));
+  *gpart = c.take<float>(size_t(BMAX / CB) * size_t(Off(r).P));
+  *lpart = c.take<float>(BMAX / CB);
+  *img = c.take<float>(size_t(Img<64>::N));
+  *words = c.take<unsigned>(8);
+  return c;
+}
+
 extern "C" size_t dopinf_closure_fit_workspace(int r, int64_t /*N*/) {
-  // the batch gradient (activations live in LDS)
-  return (r >= 1 && r <= 64) ? round_up(size_t(Off(r).P) * sizeof(float), 256) : 0;
+  if (r < 1 || r > 64) return 0;
+  float *g, *l, *im;
+  unsigned* w;
+  return carve_fit(nullptr, r, &g, &l, &im, &w).used;
 }
 
 extern "C" int dopinf_closure_fit(void* stream, int r, const double* X, const double* Y, int64_t N, int epochs,
@@ -1090,6 +1203,12 @@ extern "C" int dopinf_closure_fit(void* stream, int r, const double* X, const do
                              : reinterpret_cast<const void*>(train_kernel<64>);
   int rc = set_lds(kern, train_lds(r));
   if (rc) return rc;
+  {
+    int dev = 0, coop = 0;
+    DOPINF_HIP(hipGetDevice(&dev));
+    DOPINF_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+    if (!coop) return fail(DOPINF_E_HIP, "device does not support cooperative launches");
+  }
   TrainArgs a{};
   a.r = r;
   a.X = X;
@@ -1106,14 +1225,14 @@ extern "C" int dopinf_closure_fit(void* stream, int r, const double* X, const do
   a.m = adam_m;
   a.v = adam_v;
   a.loss_log = loss_log;
-  a.G = static_cast<float*>(ws);
+  carve_fit(ws, r, &a.Gpart, &a.lpart, &a.img, &a.words);
+  zero_u32_kernel<<<1, 64, 0, st>>>(a.words, 8);
+  DOPINF_LAUNCHED();
   norm_kernel<<<2 * r, 256, 0, st>>>(X, Y, N, r, norm);
   DOPINF_LAUNCHED();
-  if (r <= 32)
-    train_kernel<32><<<1, MT, train_lds(r), st>>>(a);
-  else
-    train_kernel<64><<<1, MT, train_lds(r), st>>>(a);
-  DOPINF_LAUNCHED();
+  const unsigned nw = unsigned((batch + CB - 1) / CB);
+  void* args[] = {&a};
+  DOPINF_HIP(hipLaunchCooperativeKernel(kern, dim3(nw), dim3(MT), args, unsigned(train_lds(r)), st));
   return DOPINF_OK;
 }
 
