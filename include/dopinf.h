@@ -458,8 +458,14 @@ int dopinf_closure_norms(void* stream, int r, const double* X,
  * N, c = (e*40503 + 17) mod N; minibatches are consecutive runs of `batch`
  * (<= 256) positions.  params: in = initial, out = trained; norm: out;
  * adam_m, adam_v: P floats each (zeroed by the call); loss_log (NULL or
- * `epochs` floats): mean loss per epoch.  One workgroup runs the whole
- * training on `stream`. */
+ * `epochs` floats): mean loss per epoch.  One cooperative launch of
+ * ceil(batch / 32) workgroups runs the whole training on `stream` (the
+ * workgroups meet at two device-wide barriers per minibatch); the workspace
+ * (dopinf_closure_fit_workspace, about 0.9 MB at r = 64) holds their
+ * gradient shares, a float image of the weights and the barrier words.  A
+ * barrier that times out (bounded spin) ends the training early and the
+ * loss log reads NaN from that epoch on.  DOPINF_E_HIP if the device has no
+ * cooperative launches. */
 size_t dopinf_closure_fit_workspace(int r, int64_t N);
 int dopinf_closure_fit(void* stream, int r, const double* X, const double* Y,
                        int64_t N, int epochs, int batch, double lr,
