@@ -489,6 +489,56 @@ def postprocess_bench(dp, torch, Q, mean, scale, var_rows, Tr, traj, reps=3):
     }
 
 
+def continuous_bench(dp, torch, Q, var_rows, Qhat, reps=3):
+    """Continuous-time form and lifting (Sec. 3.5 Eq. (10); Sec. 3.3) on the
+    same input: one lifted variable (the product of variables 0 and 1, 1e6
+    cells x k: reads 32 GB, writes 16 GB), continuous-time operators at
+    r = 60 from finite-difference derivative data (dt = 1), and RK4 rollouts
+    of 4000 states: the r = 60 item alone, and 3 x 32 items at r = 20/40/60
+    (beta1 = 1e-2, beta2 = logspace(4, 12, 32)) at full horizon."""
+    import numpy as np
+    ncell = var_rows[1] - var_rows[0]
+    k = Q.shape[1]
+    timer = Timer(torch)
+    for _ in range(reps):
+        L = timer.run("lift", lambda: dp.lift(Q, ncell, [(dp.LIFT_PRODUCT, 0, 1)]))
+    t_lift = timer.ms("lift")
+    del L
+    torch.cuda.empty_cache()
+    Qh = Qhat.contiguous()
+    for _ in range(reps):
+        O1, st1, _ = timer.run("infer", lambda: dp.infer_continuous(Qh, 1.0, [60], [1e-2], [1e8]))
+    t_inf = timer.ms("infer")
+    for _ in range(reps):
+        o1 = timer.run("roll1", lambda: dp.rollout_continuous(O1, Qh, [60], 1, 4000, 1.0, solve_status=st1, full=True))
+    t_r1 = timer.ms("roll1")
+    b2 = synth_logspace(4, 12, 32)
+    O3, st3, _ = dp.infer_continuous(Qh, 1.0, [20, 40, 60], [1e-2] * 32, list(b2))
+    for _ in range(reps):
+        o3 = timer.run("roll96", lambda: dp.rollout_continuous(O3, Qh, [20, 40, 60], 32, 4000, 1.0, solve_status=st3,
+                                                               full=True))
+    t_r96 = timer.ms("roll96")
+    oc = o3["outcome"].cpu().numpy()
+    d60 = 60 + 60 * 61 // 2 + 1
+    return {
+        "lift_product_ms": t_lift,
+        "lift_GBps": 3 * ncell * k * 8 / (t_lift * 1e-3) / 1e9,
+        "infer_r60_ms": t_inf,
+        "solve_status_r60": int(st1[0].item()),
+        "rk4_rollout_r60_4000_states_ms": t_r1,
+        "rk4_outcome_r60": int(o1["outcome"][0].item()),
+        "rk4_rollouts_96_items_4000_states_ms": t_r96,
+        "rk4_outcomes_96": {"pass": int(np.sum(oc == dp.ITEM_PASS)), "nonfinite": int(np.sum(oc == dp.ITEM_NONFINITE)),
+                            "growth": int(np.sum(oc == dp.ITEM_GROWTH)), "not_solved": int(np.sum(oc == dp.ITEM_SOLVE))},
+        "rk4_flops_per_state_r60": 4 * 2 * 60 * d60,
+    }
+
+
+def synth_logspace(lo, hi, num):
+    import synth
+    return synth.logspace_points(lo, hi, num)
+
+
 def stream_bench(dp, torch, Q, var_rows, rows=1_000_000, chunk=65536):
     """Out-of-core Gram: the first 1,000,000 rows (16 GB) in pinned host
     memory, streamed through two device buffers (copy overlapping the chunk
@@ -525,11 +575,12 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device-to-device (reference for the HBM byte counters)")
-    ap.add_argument("--leg", choices=["all", "sweep", "mixed", "post", "closure"], default="all",
+    ap.add_argument("--leg", choices=["all", "sweep", "mixed", "post", "closure", "continuous"], default="all",
                     help="sweep: only the regularization sweep on reduced data of the same input; "
                          "mixed: only the reduced-precision forms against one float64 step; "
                          "post: one float64 step, then Step V and the streamed Gram; "
-                         "closure: only the learned-closure leg "
+                         "closure: only the learned-closure leg; "
+                         "continuous: one float64 step, then the continuous-time form and lifting "
                          "(each prints its JSON object; for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -575,6 +626,13 @@ def main():
         t64 = timer.ms("preprocess") + timer.ms("gram") + timer.ms("reduce")
         log("float64 reference step done")
         print(json.dumps({"mixed": mixed_bench(dp, torch, Q, var_rows, res["Qhat"], lam_full, t64)}), flush=True)
+        return
+
+    if args.leg == "continuous":
+        timer = Timer(torch)
+        res = pipeline_step(dp, Q, var_rows, timer)
+        log("float64 step done")
+        print(json.dumps({"continuous": continuous_bench(dp, torch, Q, var_rows, res["Qhat"])}), flush=True)
         return
 
     if args.leg == "post":
@@ -678,6 +736,11 @@ def main():
         except Exception as e:
             line["stream"] = {"error": repr(e)}
         log("stream done")
+        try:
+            line["continuous"] = continuous_bench(dp, torch, Q, var_rows, res["Qhat"])
+        except Exception as e:
+            line["continuous"] = {"error": repr(e)}
+        log("continuous done")
         try:
             line["cpu_baseline"] = cpu_baseline(Q, var_rows, args.cpu_seconds, D=D, Qh80=Qh80)
         except Exception as e:
