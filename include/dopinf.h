@@ -333,7 +333,10 @@ int dopinf_rollout_noalloc(void* stream, int n_r, const int* r_list_h,
  * status as for dopinf_infer.
  * dopinf_rollout_continuous: as dopinf_rollout, with state t+1 one classical
  * fourth-order Runge-Kutta step of size dt from state t (state t is scored
- * against snapshot t); one workgroup per candidate; same workspace query. */
+ * against snapshot t); teams of workgroups (one exchange per stage, four per
+ * step) while a group's teams fit one workgroup per CU, else one workgroup
+ * per candidate; flags, time-out and workspace query as for
+ * dopinf_rollout. */
 size_t dopinf_infer_continuous_workspace(int64_t k, int n_r,
                                          const int* r_list_h, int n_pairs);
 int dopinf_infer_continuous(void* stream, const double* Qhat, int64_t ldqh,

@@ -472,8 +472,9 @@ def infer_continuous(Qhat, dt, r_list, beta1, beta2):
 
 
 def rollout_continuous(O, Qhat, r_list, n_pairs, n_states, dt, k_train=None, max_growth=1.2, solve_status=None,
-                       keep_traj=False, full=False):
-    """RK4 rollouts of continuous-time ROMs, scored like rollout()."""
+                       keep_traj=False, full=False, one_wg=False):
+    """RK4 rollouts of continuous-time ROMs, scored like rollout() (one_wg:
+    one workgroup per item instead of the multi-workgroup team form)."""
     torch = _torch()
     lib = load()
     dev = O.device
@@ -492,7 +493,8 @@ def rollout_continuous(O, Qhat, r_list, n_pairs, n_states, dt, k_train=None, max
     ws = _ws(lib.dopinf_rollout_workspace(len(rl), rlp, n_pairs, k_train), dev)
     _check(lib.dopinf_rollout_continuous(_stream(dev), len(rl), rlp, n_pairs, _ptr(O), _ptr(Qhat),
                                          _rowmajor(Qhat, "Qhat"), k_train, n_states, float(dt), float(max_growth),
-                                         ROLLOUT_FULL if full else 0, _ptr(solve_status), _ptr(traj), _ptr(te),
+                                         (ROLLOUT_FULL if full else 0) | (ROLLOUT_ONE_WG if one_wg else 0),
+                                         _ptr(solve_status), _ptr(traj), _ptr(te),
                                          _ptr(gr), _ptr(oc), _ptr(best), _ptr(ws), ws.numel()))
     out = {"train_err": te, "growth": gr, "outcome": oc, "best": best, "traj": traj}
     if keep_traj:

@@ -314,7 +314,11 @@ __global__ void zero_u32_kernel(unsigned* p, int n) {
   if (i < n) p[i] = 0u;
 }
 
-template <int TNJ>
+// RK4 = true: the continuous-time ROM stepped by classical RK4; each of the
+// four stages publishes the members' entries of its right-hand side and
+// passes one team barrier (the exchange slots alternate with the barrier
+// count), then every member forms the next stage state from the full vector.
+template <int TNJ, bool RK4>
 __global__ __launch_bounds__(TNT) void rollout_team_kernel(TeamArgs ta) {
   extern __shared__ double sm[];
   const RollArgs& a = ta.a;
@@ -325,7 +329,9 @@ __global__ __launch_bounds__(TNT) void rollout_team_kernel(TeamArgs ta) {
   const int64_t dpad = int64_t(TNJ) * 64;
   double* f = sm;                  // dpad features [q | quad(q) | 1 | 0...]
   double* mean = f + dpad;         // r
-  unsigned short* qi = reinterpret_cast<unsigned short*>(mean + r);
+  double* q0s = mean + r;          // RK4: r, the state at the start of the step
+  double* ksum = q0s + (RK4 ? r : 0);  // RK4: r, k1 + 2 k2 + 2 k3 + k4
+  unsigned short* qi = reinterpret_cast<unsigned short*>(ksum + (RK4 ? r : 0));
   unsigned short* qj = qi + s;
   __shared__ double red[TW][4];
   __shared__ int stop_sh;
@@ -438,25 +444,48 @@ __global__ __launch_bounds__(TNT) void rollout_team_kernel(TeamArgs ta) {
       break;
     }
     if (t + 1 == a.n_states) break;
-    // features of state t
-    for (int64_t c = tid; c < s; c += TNT) f[r + c] = f[qi[c]] * f[qj[c]];
-    if (tid == 0) f[d - 1] = 1.0;
-    __syncthreads();
-    // this wave's entry of the next state
-    double acc = 0.0;
-#pragma unroll
-    for (int j = 0; j < TNJ; ++j) acc += o[j] * f[lane + 64 * j];
-    acc = wave_sum_dpp(acc);
-    double* slot = xb + ((t + 1) & 1) * r;
-    if (lane == 0 && row < r) xwg::st_dev(slot + row, acc);
-    // next training snapshot, in flight during the barrier
+    // next training snapshot, in flight during the exchanges
     h = (tid < r && t + 1 < a.k_train) ? a.Qhat[int64_t(tid) * a.ldqh + t + 1] : 0.0;
-    if (!xwg::team_barrier(bar, unsigned(ta.P), gen, ta.abort_flag)) {
+    // one evaluation of the ROM map at the state in f[0:r): this wave's entry
+    // goes to the exchange slot of barrier round gen, and after the barrier
+    // every member reads the whole vector from it
+    auto exchange = [&](double& kv) -> bool {
+      for (int64_t c = tid; c < s; c += TNT) f[r + c] = f[qi[c]] * f[qj[c]];
+      if (tid == 0) f[d - 1] = 1.0;
+      __syncthreads();
+      double acc = 0.0;
+#pragma unroll
+      for (int j = 0; j < TNJ; ++j) acc += o[j] * f[lane + 64 * j];
+      acc = wave_sum_dpp(acc);
+      double* slot = xb + ((gen + 1) & 1) * r;
+      if (lane == 0 && row < r) xwg::st_dev(slot + row, acc);
+      if (!xwg::team_barrier(bar, unsigned(ta.P), gen, ta.abort_flag)) return false;
+      kv = (tid < r) ? xwg::ld_dev(slot + tid) : 0.0;
+      return true;
+    };
+    bool ok = true;
+    if constexpr (RK4) {
+      if (tid < r) q0s[tid] = f[tid];
+      for (int stage = 0; stage < 4 && ok; ++stage) {
+        double kv = 0.0;
+        ok = exchange(kv);
+        if (ok && tid < r) {
+          ksum[tid] = (stage == 0) ? kv : ksum[tid] + ((stage == 3) ? kv : 2.0 * kv);
+          if (stage < 3) f[tid] = q0s[tid] + ((stage == 2) ? a.dt : 0.5 * a.dt) * kv;
+        }
+        __syncthreads();
+      }
+      if (ok && tid < r) f[tid] = q0s[tid] + (a.dt / 6.0) * ksum[tid];
+    } else {
+      double kv = 0.0;
+      ok = exchange(kv);
+      if (ok && tid < r) f[tid] = kv;
+    }
+    if (!ok) {
       oc = DOPINF_ITEM_TIMEOUT;
       t_done = t + 1;
       break;
     }
-    if (tid < r) f[tid] = xwg::ld_dev(slot + tid);
     __syncthreads();
   }
   if (trj)
@@ -508,13 +537,17 @@ namespace dopinf {
 namespace {
 
 // Team form for group of size r with n_pairs items: co-resident teams of
-// ceil(r / 8) workgroups while the teams fit on the chip at once.
+// ceil(r / 8) workgroups while the teams fit on the chip at once (up to 128
+// workgroups for the discrete map; RK4, which makes four team exchanges per
+// step and reads its operator four times per step in the one-workgroup form,
+// takes teams up to one workgroup per CU).
 constexpr int kTeamMaxWorkgroups = 128;
-int team_size(int r, int n_pairs, unsigned flags) {
+constexpr int kTeamMaxWorkgroupsRK4 = 256;
+int team_size(int r, int n_pairs, unsigned flags, bool rk4) {
   if (flags & DOPINF_ROLLOUT_ONE_WG) return 0;
   if (ncols(r) > int64_t(64) * TNJ_MAX) return 0;
   const int P = (r + TW - 1) / TW;
-  return (int64_t(P) * n_pairs <= kTeamMaxWorkgroups) ? P : 0;
+  return (int64_t(P) * n_pairs <= (rk4 ? kTeamMaxWorkgroupsRK4 : kTeamMaxWorkgroups)) ? P : 0;
 }
 
 struct RollWs {
@@ -603,11 +636,12 @@ int rollout_launch(hipStream_t st, int n_r, const int* r_list_h, int n_pairs, co
     ra.train_err = train_err + g * n_pairs;
     ra.growth = growth + g * n_pairs;
     ra.outcome = outcome + g * n_pairs;
-    const int P = rk4 ? 0 : team_size(r, n_pairs, flags);
+    const int P = team_size(r, n_pairs, flags, rk4);
     bool launched = false;
     if (P > 0) {
       const int tnj = (d <= 64 * 32) ? 32 : 64;
-      const size_t tsm = size_t(int64_t(tnj) * 64 + r) * sizeof(double) + size_t(2 * s) * sizeof(unsigned short) + 64;
+      const size_t tsm = size_t(int64_t(tnj) * 64 + (rk4 ? 3 : 1) * r) * sizeof(double) +
+                         size_t(2 * s) * sizeof(unsigned short) + 64;
       zero_u32_kernel<<<(n_pairs + 1 + 255) / 256, 256, 0, st>>>(w.words, n_pairs + 1);
       DOPINF_LAUNCHED();
       TeamArgs ta{};
@@ -619,8 +653,11 @@ int rollout_launch(hipStream_t st, int n_r, const int* r_list_h, int n_pairs, co
       void* args[] = {&ta};
       // co-residency of the team members is what the counter barrier needs;
       // if the runtime cannot promise it, the one-workgroup form runs instead
-      const void* kern = (tnj == 32) ? reinterpret_cast<const void*>(rollout_team_kernel<32>)
-                                     : reinterpret_cast<const void*>(rollout_team_kernel<64>);
+      const void* kern =
+          rk4 ? ((tnj == 32) ? reinterpret_cast<const void*>(rollout_team_kernel<32, true>)
+                             : reinterpret_cast<const void*>(rollout_team_kernel<64, true>))
+              : ((tnj == 32) ? reinterpret_cast<const void*>(rollout_team_kernel<32, false>)
+                             : reinterpret_cast<const void*>(rollout_team_kernel<64, false>));
       if (hipLaunchCooperativeKernel(kern, dim3(unsigned(n_pairs * P)), dim3(TNT), args, unsigned(tsm), st) ==
           hipSuccess)
         launched = true;

@@ -62,7 +62,10 @@ def test_continuous_inference_parity(gpu_lib, data):
     assert rel(views[1][0].cpu().numpy(), O_true) < 1e-3
 
 
-def test_continuous_rollout_parity(gpu_lib, data):
+@pytest.mark.parametrize("one_wg", [False, True], ids=["team", "one_wg"])
+def test_continuous_rollout_parity(gpu_lib, data, one_wg):
+    # both forms: co-resident teams of ceil(r / 8) workgroups exchanging each
+    # RK4 stage's right-hand side, and one workgroup per item
     import torch
     dp = gpu_lib
     O_true, Qh = data
@@ -71,7 +74,8 @@ def test_continuous_rollout_parity(gpu_lib, data):
     Qd = dev(Qh)
     O, status, views = dp.infer_continuous(Qd, DT, r_list, b1, b2)
     n_states = 6000   # 1.5x the training window
-    out = dp.rollout_continuous(O, Qd, r_list, 2, n_states, DT, solve_status=status, keep_traj=True, full=True)
+    out = dp.rollout_continuous(O, Qd, r_list, 2, n_states, DT, solve_status=status, keep_traj=True, full=True,
+                                one_wg=one_wg)
     torch.cuda.synchronize()
     te, gr, oc = (out[k].cpu().numpy() for k in ("train_err", "growth", "outcome"))
     for g, r in enumerate(r_list):
