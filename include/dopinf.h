@@ -240,7 +240,10 @@ int dopinf_infer(void* stream, const double* Qhat, int64_t ldqh, int64_t k,
                  int* status, void* ws, size_t ws_bytes);
 
 /* ---- Step IV: ROM rollouts, scoring and selection (Sec. 3.5) -------------
- * For every item of dopinf_infer's layout: qt_0 = Qhat[0:r_g, 0],
+ * For every item of dopinf_infer's layout: qt_0 = Qhat[0:r_g, 0] (or, when
+ * q0 is not NULL, the item's r_g entries of q0: device float64, the items'
+ * initial states packed in item order, item i at dopinf_traj_offset(n_r,
+ * r_list_h, n_pairs, 1, i)),
  * qt_{t+1} = A qt_t + H quad(qt_t) + c for n_states states (qt_0 included).
  * train_err[item] = max_{t < min(k_train, n_states)} ||qt_t - qhat_t|| / ||qhat_t||;
  * growth[item]    = max_{t,i} |qt_t[i] - m_i| / max_{t<k_train,i} |qhat_t[i] - m_i|
@@ -272,7 +275,7 @@ size_t dopinf_rollout_workspace(int n_r, const int* r_list_h, int n_pairs,
                                 int64_t k_train);
 int dopinf_rollout(void* stream, int n_r, const int* r_list_h, int n_pairs,
                    const double* O, const double* Qhat, int64_t ldqh,
-                   int64_t k_train, int n_states, double max_growth,
+                   const double* q0, int64_t k_train, int n_states, double max_growth,
                    unsigned flags, const int* solve_status, double* traj,
                    double* train_err, double* growth, int* outcome, int* best,
                    void* ws, size_t ws_bytes);

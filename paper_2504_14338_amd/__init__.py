@@ -76,7 +76,7 @@ _SIGS = {
     "dopinf_infer": ([_vp, _vp, _i64, _i64, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _vp, _sz], _i32),
     "dopinf_traj_offset": ([_i32, _vp, _i32, _i32, _i32], _sz),
     "dopinf_rollout_workspace": ([_i32, _vp, _i32, _i64], _sz),
-    "dopinf_rollout": ([_vp, _i32, _vp, _i32, _vp, _vp, _i64, _i64, _i32, _f64, _u32, _vp, _vp, _vp, _vp, _vp, _vp,
+    "dopinf_rollout": ([_vp, _i32, _vp, _i32, _vp, _vp, _i64, _vp, _i64, _i32, _f64, _u32, _vp, _vp, _vp, _vp, _vp, _vp,
                         _vp, _sz], _i32),
     "dopinf_lift": ([_vp, _vp, _i64, _i64, _i64, _i32, _i32, _vp, _vp, _i64], _i32),
     "dopinf_infer_continuous_workspace": ([_i64, _i32, _vp, _i32], _sz),
@@ -386,9 +386,11 @@ def traj_offset(r_list, n_pairs, n_states, item):
 
 
 def rollout(O, Qhat, r_list, n_pairs, n_states, k_train=None, max_growth=1.2, solve_status=None,
-            keep_traj=False, full=False, one_wg=False):
+            keep_traj=False, full=False, one_wg=False, q0=None):
     """Roll out, score and select.  Returns dict of device tensors.  Few items
-    are rolled out by teams of workgroups unless one_wg is set."""
+    are rolled out by teams of workgroups unless one_wg is set.  q0: None
+    (every item starts at Qhat[:, 0]) or a float64 device vector of the
+    items' initial states packed in item order (r_g entries each)."""
     torch = _torch()
     lib = load()
     dev = O.device
@@ -406,8 +408,12 @@ def rollout(O, Qhat, r_list, n_pairs, n_states, k_train=None, max_growth=1.2, so
     best = torch.empty(len(rl), dtype=torch.int32, device=dev)
     nb = lib.dopinf_rollout_workspace(len(rl), rlp, n_pairs, k_train)
     ws = _ws(nb, dev)
+    if q0 is not None:
+        need = lib.dopinf_traj_offset(len(rl), rlp, n_pairs, 1, n_items)
+        if q0.dtype != torch.float64 or q0.numel() != need or not q0.is_contiguous():
+            raise ValueError(f"q0 must be a contiguous float64 tensor of {need} entries")
     _check(lib.dopinf_rollout(_stream(dev), len(rl), rlp, n_pairs, _ptr(O), _ptr(Qhat), _rowmajor(Qhat, "Qhat"),
-                              k_train, n_states, float(max_growth), (ROLLOUT_FULL if full else 0) | (ROLLOUT_ONE_WG if one_wg else 0),
+                              _ptr(q0), k_train, n_states, float(max_growth), (ROLLOUT_FULL if full else 0) | (ROLLOUT_ONE_WG if one_wg else 0),
                               _ptr(solve_status), _ptr(traj), _ptr(te), _ptr(gr), _ptr(oc), _ptr(best), _ptr(ws),
                               ws.numel()))
     out = {"train_err": te, "growth": gr, "outcome": oc, "best": best, "traj": traj}

@@ -2033,7 +2033,8 @@ extern "C" int dopinf_sweep_create(void* stream, const double* Qhat, int64_t ldq
   DOPINF_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
   rc = infer_enqueue(st, P, Qhat, ldqh, O, status, wsi);
   if (!rc)
-    rc = dopinf_rollout(stream, n_r, r_list_h, n_pairs, O, Qhat, ldqh, k, n_states, max_growth, DOPINF_ROLLOUT_ONE_WG,
+    rc = dopinf_rollout(stream, n_r, r_list_h, n_pairs, O, Qhat, ldqh, nullptr, k, n_states, max_growth,
+                        DOPINF_ROLLOUT_ONE_WG,
                         status, nullptr, train_err, growth, outcome, best, wsr, ws_bytes - ia);
   hipGraph_t graph = nullptr;
   const hipError_t ec = hipStreamEndCapture(st, &graph);

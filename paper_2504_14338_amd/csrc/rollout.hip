@@ -76,6 +76,7 @@ struct RollArgs {
   int n_items;           // candidates of the group
   unsigned* queue;       // persistent grid: next-candidate counter (zeroed), or null
   double dt;             // > 0: continuous-time ROM stepped by RK4 with this step
+  const double* q0;      // initial states of the group's items (r each), or null: Qhat[:, 0]
   const double* mean;    // r
   const double* maxdev;  // r
   const int* solve_status;  // group base or null
@@ -175,7 +176,7 @@ __device__ void rollout_item(const RollArgs& a, const int p) {
   }
   for (int i = tid; i < r; i += RT) {
     mean[i] = a.mean[i];
-    f[i] = a.Qhat[int64_t(i) * a.ldqh];  // state 0 = first training snapshot
+    f[i] = a.q0 ? a.q0[int64_t(p) * r + i] : a.Qhat[int64_t(i) * a.ldqh];  // state 0
   }
   if (tid == 0) {
     double md = 0.0;
@@ -370,7 +371,7 @@ __global__ __launch_bounds__(TNT) void rollout_team_kernel(TeamArgs ta) {
   for (int64_t c = d + tid; c < dpad; c += TNT) f[c] = 0.0;
   for (int i = tid; i < r; i += TNT) {
     mean[i] = a.mean[i];
-    f[i] = a.Qhat[int64_t(i) * a.ldqh];
+    f[i] = a.q0 ? a.q0[int64_t(item) * r + i] : a.Qhat[int64_t(i) * a.ldqh];
   }
   if (tid == 0) {
     double md = 0.0;
@@ -596,7 +597,8 @@ int check_rollout_args(int n_r, const int* r_list_h, int n_pairs, const double* 
 int rollout_launch(hipStream_t st, int n_r, const int* r_list_h, int n_pairs, const double* O,
                    const double* Qhat, int64_t ldqh, int64_t k_train, int n_states, double max_growth,
                    unsigned flags, const int* solve_status, double* traj, double* train_err, double* growth,
-                   int* outcome, int* best, void* ws, size_t ws_bytes, double dt = 0.0) {
+                   int* outcome, int* best, void* ws, size_t ws_bytes, double dt = 0.0,
+                   const double* q0 = nullptr) {
   int dev = 0, maxlds = 0;
   DOPINF_HIP(hipGetDevice(&dev));
   DOPINF_HIP(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
@@ -629,6 +631,7 @@ int rollout_launch(hipStream_t st, int n_r, const int* r_list_h, int n_pairs, co
     ra.max_growth = max_growth;
     ra.full = (flags & DOPINF_ROLLOUT_FULL) ? 1 : 0;
     ra.dt = dt;
+    ra.q0 = q0 ? q0 + dopinf_traj_offset(n_r, r_list_h, n_pairs, 1, g * n_pairs) : nullptr;
     ra.mean = mean;
     ra.maxdev = maxdev;
     ra.solve_status = solve_status ? solve_status + g * n_pairs : nullptr;
@@ -725,16 +728,18 @@ int scratch_address(void** out) {
 }  // namespace dopinf
 
 extern "C" int dopinf_rollout(void* stream, int n_r, const int* r_list_h, int n_pairs, const double* O,
-                              const double* Qhat, int64_t ldqh, int64_t k_train, int n_states, double max_growth,
-                              unsigned flags, const int* solve_status, double* traj, double* train_err,
-                              double* growth, int* outcome, int* best, void* ws, size_t ws_bytes) {
+                              const double* Qhat, int64_t ldqh, const double* q0, int64_t k_train, int n_states,
+                              double max_growth, unsigned flags, const int* solve_status, double* traj,
+                              double* train_err, double* growth, int* outcome, int* best, void* ws,
+                              size_t ws_bytes) {
   int rc = check_rollout_args(n_r, r_list_h, n_pairs, O, Qhat, ldqh, k_train, n_states, max_growth, flags, train_err,
                               growth, outcome, best);
   if (rc) return rc;
   const size_t need = dopinf_rollout_workspace(n_r, r_list_h, n_pairs, k_train);
   if (!ws || ws_bytes < need) return fail(DOPINF_E_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
   return rollout_launch(static_cast<hipStream_t>(stream), n_r, r_list_h, n_pairs, O, Qhat, ldqh, k_train, n_states,
-                        max_growth, flags, solve_status, traj, train_err, growth, outcome, best, ws, ws_bytes);
+                        max_growth, flags, solve_status, traj, train_err, growth, outcome, best, ws, ws_bytes, 0.0,
+                        q0);
 }
 
 extern "C" int dopinf_rollout_continuous(void* stream, int n_r, const int* r_list_h, int n_pairs, const double* O,

@@ -137,6 +137,48 @@ def test_rollout_parity_given_operators(one_wg, gpu_lib, c1_qhat):
 
 
 @pytest.mark.parametrize("one_wg", [False, True])
+def test_rollout_from_given_initial_states(one_wg, gpu_lib, c1_qhat):
+    # q0 per item (packed in item order): each rollout starts from its own
+    # state, a perturbation of the first snapshot, and is scored against
+    # the training data as before
+    import torch
+    dp = gpu_lib
+    Qhat, _, _ = c1_qhat
+    Qh = Qhat.cpu().numpy()
+    r_list = [4, 10]
+    b1 = [1e-2, 1e-2, 1e-3]
+    b2 = [1e-1, 1.0, 1e-1]
+    n_pairs = len(b1)
+    O, status, views = dp.infer(Qhat, r_list, b1, b2)
+    rng = np.random.default_rng(17)
+    q0s = []
+    for g, r in enumerate(r_list):
+        for p in range(n_pairs):
+            q0s.append(Qh[:r, 0] * (1.0 + 0.01 * rng.standard_normal(r)))
+    q0 = torch.from_numpy(np.concatenate(q0s)).cuda()
+    n_states = 900
+    out = dp.rollout(O, Qhat, r_list, n_pairs, n_states, solve_status=status, keep_traj=True, full=True,
+                     one_wg=one_wg, q0=q0)
+    te, gr, oc = (out[k].cpu().numpy() for k in ("train_err", "growth", "outcome"))
+    for g, r in enumerate(r_list):
+        for p in range(n_pairs):
+            it = g * n_pairs + p
+            Qt = orc.rollout(views[g][p].cpu().numpy(), r, q0s[it], n_states)
+            fin, e, gg, ok = orc.score(Qt, Qh[:r], Qh.shape[1], 1.2)
+            traj = out["traj_views"][g][p].cpu().numpy().T
+            assert np.array_equal(traj[:, 0], q0s[it])
+            if fin:
+                assert np.max(np.abs(traj - Qt)) <= 1e-9 * np.max(np.abs(Qt)), (r, p)
+                assert te[it] == pytest.approx(e, rel=1e-8, abs=1e-14)
+                assert gr[it] == pytest.approx(gg, rel=1e-10)
+                assert (oc[it] == dp.ITEM_PASS) == ok
+            else:
+                assert oc[it] == dp.ITEM_NONFINITE
+    with pytest.raises(ValueError):
+        dp.rollout(O, Qhat, r_list, n_pairs, n_states, q0=q0[:-1].contiguous())
+
+
+@pytest.mark.parametrize("one_wg", [False, True])
 def test_rollout_hand_cases_and_failure_modes(one_wg, gpu_lib):
     import torch
     dp = gpu_lib
