@@ -369,6 +369,7 @@ __global__ __launch_bounds__(TNT) void rollout_team_kernel(TeamArgs ta) {
     qj[c] = static_cast<unsigned short>(ii + (c - off));
   }
   for (int64_t c = d + tid; c < dpad; c += TNT) f[c] = 0.0;
+  if (tid == 0) f[d - 1] = 1.0;
   for (int i = tid; i < r; i += TNT) {
     mean[i] = a.mean[i];
     f[i] = a.q0 ? a.q0[int64_t(item) * r + i] : a.Qhat[int64_t(i) * a.ldqh];
@@ -406,25 +407,43 @@ __global__ __launch_bounds__(TNT) void rollout_team_kernel(TeamArgs ta) {
       }
       if (trj && tid >= i_lo && tid < i_hi) trj[int64_t(t) * r + tid] = x;
     }
-    e2 = wave_sum(e2);
-    n2 = wave_sum(n2);
-    dv = wave_max(dv);
-    bad = wave_max(bad);
-    if (lane == 0) {
-      red[w][0] = e2;
-      red[w][1] = n2;
-      red[w][2] = dv;
-      red[w][3] = bad;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      double E2 = 0.0, N2 = 0.0, DV = 0.0, BAD = 0.0;
-      for (int q = 0; q < TW; ++q) {
-        E2 += red[q][0];
-        N2 += red[q][1];
-        DV = fmax(DV, red[q][2]);
-        BAD = fmax(BAD, red[q][3]);
+    // quadratic features of state t (read by the first evaluation below),
+    // formed in the same phase as the scores: both only read f[0:r)
+    if (t + 1 < a.n_states)
+      for (int64_t c = tid; c < s; c += TNT) f[r + c] = f[qi[c]] * f[qj[c]];
+    // the state's entries sit in lanes tid < r: for r <= 64 wave 0 alone
+    // reduces them (DPP sums, no cross-wave step); else every wave, then
+    // thread 0 over the waves
+    double E2 = 0.0, N2 = 0.0, DV = 0.0, BAD = 0.0;
+    if (r <= 64) {
+      if (w == 0) {
+        E2 = wave_sum_dpp(e2);
+        N2 = wave_sum_dpp(n2);
+        DV = wave_max_dpp(dv);
+        BAD = wave_max_dpp(bad);
       }
+    } else {
+      e2 = wave_sum(e2);
+      n2 = wave_sum(n2);
+      dv = wave_max(dv);
+      bad = wave_max(bad);
+      if (lane == 0) {
+        red[w][0] = e2;
+        red[w][1] = n2;
+        red[w][2] = dv;
+        red[w][3] = bad;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        for (int q = 0; q < TW; ++q) {
+          E2 += red[q][0];
+          N2 += red[q][1];
+          DV = fmax(DV, red[q][2]);
+          BAD = fmax(BAD, red[q][3]);
+        }
+      }
+    }
+    if (tid == 0) {
       int stop = 0;
       if (BAD != 0.0) {
         oc = DOPINF_ITEM_NONFINITE;
@@ -445,15 +464,16 @@ __global__ __launch_bounds__(TNT) void rollout_team_kernel(TeamArgs ta) {
       break;
     }
     if (t + 1 == a.n_states) break;
-    // next training snapshot, in flight during the exchanges
-    h = (tid < r && t + 1 < a.k_train) ? a.Qhat[int64_t(tid) * a.ldqh + t + 1] : 0.0;
     // one evaluation of the ROM map at the state in f[0:r): this wave's entry
     // goes to the exchange slot of barrier round gen, and after the barrier
     // every member reads the whole vector from it
-    auto exchange = [&](double& kv) -> bool {
-      for (int64_t c = tid; c < s; c += TNT) f[r + c] = f[qi[c]] * f[qj[c]];
-      if (tid == 0) f[d - 1] = 1.0;
-      __syncthreads();
+    // (the features of the step's first evaluation are already in f; the
+    // constant feature f[d-1] = 1 is set once)
+    auto exchange = [&](double& kv, bool features, bool last) -> bool {
+      if (features) {
+        for (int64_t c = tid; c < s; c += TNT) f[r + c] = f[qi[c]] * f[qj[c]];
+        __syncthreads();
+      }
       double acc = 0.0;
 #pragma unroll
       for (int j = 0; j < TNJ; ++j) acc += o[j] * f[lane + 64 * j];
@@ -461,6 +481,9 @@ __global__ __launch_bounds__(TNT) void rollout_team_kernel(TeamArgs ta) {
       double* slot = xb + ((gen + 1) & 1) * r;
       if (lane == 0 && row < r) xwg::st_dev(slot + row, acc);
       if (!xwg::team_barrier(bar, unsigned(ta.P), gen, ta.abort_flag)) return false;
+      // the next training snapshot after the step's last barrier (whose
+      // drain would otherwise wait for it), in flight with the exchange load
+      if (last) h = (tid < r && t + 1 < a.k_train) ? a.Qhat[int64_t(tid) * a.ldqh + t + 1] : 0.0;
       kv = (tid < r) ? xwg::ld_dev(slot + tid) : 0.0;
       return true;
     };
@@ -469,7 +492,7 @@ __global__ __launch_bounds__(TNT) void rollout_team_kernel(TeamArgs ta) {
       if (tid < r) q0s[tid] = f[tid];
       for (int stage = 0; stage < 4 && ok; ++stage) {
         double kv = 0.0;
-        ok = exchange(kv);
+        ok = exchange(kv, stage > 0, stage == 3);
         if (ok && tid < r) {
           ksum[tid] = (stage == 0) ? kv : ksum[tid] + ((stage == 3) ? kv : 2.0 * kv);
           if (stage < 3) f[tid] = q0s[tid] + ((stage == 2) ? a.dt : 0.5 * a.dt) * kv;
@@ -479,7 +502,7 @@ __global__ __launch_bounds__(TNT) void rollout_team_kernel(TeamArgs ta) {
       if (ok && tid < r) f[tid] = q0s[tid] + (a.dt / 6.0) * ksum[tid];
     } else {
       double kv = 0.0;
-      ok = exchange(kv);
+      ok = exchange(kv, false, true);
       if (ok && tid < r) f[tid] = kv;
     }
     if (!ok) {
