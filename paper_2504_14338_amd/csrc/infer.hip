@@ -168,7 +168,10 @@ __global__ __launch_bounds__(256) void gather_qq_kernel(const double* __restrict
 // that step c reads is written in step c.  W ends as M^{-1} for the unit
 // lower factor M of A = M diag(d) M^T, so L^{-1} = diag(d)^{-1/2} W.  Rows
 // beyond the matrix are identity rows.
-__global__ __launch_bounds__(256) void potf2_kernel(double* __restrict__ A, int64_t n, int64_t jb,
+constexpr int PF2 = 1024;      // threads of the diagonal-block kernel
+constexpr int PR = PF2 / NB;    // row groups (one column per thread)
+
+__global__ __launch_bounds__(PF2) void potf2_kernel(double* __restrict__ A, int64_t n, int64_t jb,
                                                     double* __restrict__ Linv, int* __restrict__ fail_flag) {
   __shared__ double T[NB][NB + 1];
   __shared__ double F[NB][NB + 1];
@@ -181,16 +184,16 @@ __global__ __launch_bounds__(256) void potf2_kernel(double* __restrict__ A, int6
   {
     // all 16 loads of a thread in flight together (clamped addresses, select)
     const int j = tid % NB, i0 = tid / NB;
-    double v[NB / 4];
+    double v[NB / PR];
 #pragma unroll
-    for (int k = 0; k < NB / 4; ++k) {
-      const int i = i0 + 4 * k;
+    for (int k = 0; k < NB / PR; ++k) {
+      const int i = i0 + PR * k;
       const int ic = i < nb ? i : 0, jc = j < nb ? j : 0;
       v[k] = Au[(jb + ic) * n + jb + jc];
     }
 #pragma unroll
-    for (int k = 0; k < NB / 4; ++k) {
-      const int i = i0 + 4 * k;
+    for (int k = 0; k < NB / PR; ++k) {
+      const int i = i0 + PR * k;
       T[i][j] = (i < nb && j <= i) ? v[k] : (i == j ? 1.0 : 0.0);
       F[i][j] = 0.0;
       W[i][j] = (i == j) ? 1.0 : 0.0;
@@ -206,38 +209,38 @@ __global__ __launch_bounds__(256) void potf2_kernel(double* __restrict__ A, int6
     if (tid >= c && tid < NB) F[tid][c] = (tid == c) ? d : T[tid][c] / d;
     if (tid == 0 && !okp) bad = 1;
     const double rp = 1.0 / pv;
-    // thread -> column j = tid % 64 and rows c + 1 + tid / 64 + 4k: column
+    // thread -> column j = tid % 64 and rows c + 1 + tid / 64 + PR k: column
     // j > c of T (lower part) or column j <= c of W, with one code path for
     // both (no divergence) and all reads issued before the writes
     const int j = tid % NB;
     const bool onT = j > c;
     double* dst = onT ? &T[0][0] : &W[0][0];
     const double f = (onT ? T[j][c] : W[c][j]) * rp;
-    // rows c + 1 .. NB - 1 in steps of 4: 16 per thread for c < 32, then 8
+    // rows c + 1 .. NB - 1 in steps of PR
     auto step = [&](auto kn) {
       constexpr int KN = decltype(kn)::value;
       double a[KN], b[KN];
 #pragma unroll
       for (int k = 0; k < KN; ++k) {
-        const int i = c + 1 + tid / NB + 4 * k;
+        const int i = c + 1 + tid / NB + PR * k;
         const int ic = i < NB ? i : NB - 1;
         a[k] = T[ic][c];
         b[k] = dst[ic * (NB + 1) + j];
       }
 #pragma unroll
       for (int k = 0; k < KN; ++k) {
-        const int i = c + 1 + tid / NB + 4 * k;
+        const int i = c + 1 + tid / NB + PR * k;
         if (i < NB && (!onT || j <= i)) dst[i * (NB + 1) + j] = b[k] - a[k] * f;
       }
     };
     if (c < NB / 2)
-      step(std::integral_constant<int, NB / 4>{});
+      step(std::integral_constant<int, NB / PR>{});
     else
-      step(std::integral_constant<int, NB / 8>{});
+      step(std::integral_constant<int, NB / (2 * PR)>{});
     __syncthreads();
   }
   double* Lo = Linv + (size_t(u) * ((n + NB - 1) / NB) + jb / NB) * NB * NB;
-  for (int e = tid; e < NB * NB; e += 256) {
+  for (int e = tid; e < NB * NB; e += PF2) {
     const int i = e / NB, j = e % NB;
     if (i < nb && j <= i) Au[(jb + i) * n + jb + j] = F[i][j];
     Lo[e] = (j <= i) ? W[i][j] / F[i][i] : 0.0;
@@ -984,7 +987,7 @@ int cholesky_run(hipStream_t st, double* Lq, int64_t s, double* Linv, int* ufail
   };
   auto leaf = [&](int64_t c0, int64_t c1) -> int {
     for (int64_t jb = c0; jb < c1; jb += NB) {
-      potf2_kernel<<<nu, 256, 0, st>>>(Lq, s, jb, Linv, ufail);
+      potf2_kernel<<<nu, PF2, 0, st>>>(Lq, s, jb, Linv, ufail);
       DOPINF_LAUNCHED();
       const int64_t rest = s - jb - NB;
       if (rest <= 0) continue;
