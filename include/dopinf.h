@@ -56,6 +56,7 @@ extern "C" {
 #define DOPINF_GRAM_NATIVE 0  /* MFMA in the storage type (F64 or F32)       */
 #define DOPINF_GRAM_BF16X3 1  /* F32 data, split hi+lo bfloat16, 3 products  */
 #define DOPINF_GRAM_BF16X6 2  /* F32 data, split hi+mid+lo bfloat16, 6 products */
+#define DOPINF_GRAM_I8X6 3    /* F32 data, three int8 fixed-point slices, 6 products */
 
 #define DOPINF_MAX_VARS 64
 
@@ -114,10 +115,15 @@ int dopinf_lift(void* stream, const double* Q, int64_t n_cells, int64_t k,
  * and scale are given (either may be NULL: no centering / no scaling).
  * D: k x k doubles, leading dimension ldd >= k, written in full (symmetric).
  * algo: DOPINF_GRAM_NATIVE (F64: FP64 MFMA; F32: FP32 MFMA),
- * DOPINF_GRAM_BF16X3 or DOPINF_GRAM_BF16X6 (F32 data only).  The reduced-
- * precision forms first pack the transformed data (rounded to float32, split
- * into bfloat16 parts) into the workspace, then accumulate in float over row
- * slabs of at most 512 rows and sum slabs in double.
+ * DOPINF_GRAM_BF16X3, DOPINF_GRAM_BF16X6 or DOPINF_GRAM_I8X6 (F32 data
+ * only).  The bfloat16 forms first pack the transformed data (rounded to
+ * float32, split into bfloat16 parts) into the workspace, then accumulate in
+ * float over row slabs of at most 512 rows and sum slabs in double.
+ * DOPINF_GRAM_I8X6 scales column j of the transformed data (in double) by
+ * 127 / a_j with a_j its max-abs, splits it into three int8 slices of radix
+ * 254 and sums six slice products exactly in int32 on the int8 matrix cores;
+ * the error per entry is |dD_jl| <= 2.5e-7 a_j a_l per row of Q, and a
+ * non-finite input value makes its column's entries of D NaN.
  * Deterministic: no floating-point atomics; repeated calls give identical
  * bits. */
 size_t dopinf_gram_workspace(int dtype, int algo, int64_t n, int64_t k);

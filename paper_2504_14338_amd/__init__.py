@@ -16,7 +16,7 @@ import numpy as np
 
 __all__ = [
     "load", "DopinfError", "CENTER", "SCALE", "APPLY", "F64", "F32",
-    "GRAM_NATIVE", "GRAM_BF16X3", "GRAM_BF16X6", "ITEM_PASS", "ITEM_NONFINITE",
+    "GRAM_NATIVE", "GRAM_BF16X3", "GRAM_BF16X6", "GRAM_I8X6", "ITEM_PASS", "ITEM_NONFINITE",
     "ITEM_GROWTH", "ITEM_SOLVE", "ITEM_TIMEOUT", "preprocess", "gram", "cross_gram",
     "reduce", "infer", "operator_offset", "rollout", "traj_offset",
     "n_quad", "lib_path", "rollout_noalloc", "rollout_noalloc_max_bytes", "postprocess", "reduce_topr", "preprocess_stream", "gram_stream", "lift", "infer_continuous",
@@ -28,7 +28,7 @@ __all__ = [
 OK, E_ARG, E_HIP, E_WORKSPACE, E_RANK, E_NOTSPD, E_NONFINITE, E_NOSTABLE, E_TIMEOUT = range(9)
 F64, F32 = 0, 1
 CENTER, SCALE, APPLY = 1, 2, 4
-GRAM_NATIVE, GRAM_BF16X3, GRAM_BF16X6 = 0, 1, 2
+GRAM_NATIVE, GRAM_BF16X3, GRAM_BF16X6, GRAM_I8X6 = 0, 1, 2, 3
 ITEM_PASS, ITEM_NONFINITE, ITEM_GROWTH, ITEM_SOLVE, ITEM_TIMEOUT = 0, 1, 2, 3, 4
 ROLLOUT_FULL = 1
 ROLLOUT_ONE_WG = 2

@@ -561,6 +561,10 @@ using namespace dopinf;
 
 namespace dopinf {
 size_t cross_gram_workspace_internal(int64_t n, int64_t mx, int64_t my);
+size_t gram_i8_workspace(int64_t n, int64_t k);
+int gram_i8(hipStream_t st, const float* Q, int64_t n, int64_t k, int64_t ldq, const double* mean,
+            const double* scale, int nvars, const int64_t* var_rows_h, double* D, int64_t ldd, void* ws,
+            size_t ws_bytes);
 }
 
 size_t gram_lowp_workspace(int algo, int64_t n, int64_t k);
@@ -571,6 +575,7 @@ int gram_lowp(hipStream_t st, int algo, const float* Q, int64_t n, int64_t k, in
 extern "C" size_t dopinf_gram_workspace(int dtype, int algo, int64_t n, int64_t k) {
   if (n <= 0 || k <= 0) return 0;
   if (dtype == DOPINF_F64) return gram_f64_workspace_internal(n, k, DOPINF_MAX_VARS);
+  if (algo == DOPINF_GRAM_I8X6) return gram_i8_workspace(n, k);
   return gram_lowp_workspace(algo, n, k);
 }
 
@@ -594,8 +599,12 @@ extern "C" int dopinf_gram(void* stream, int dtype, int algo, const void* Q, int
                              scale ? var_rows_h : nullptr, D, ldd, ws, ws_bytes);
   }
   DOPINF_REQUIRE(dtype == DOPINF_F32, "dtype must be DOPINF_F64 or DOPINF_F32");
-  DOPINF_REQUIRE(algo == DOPINF_GRAM_NATIVE || algo == DOPINF_GRAM_BF16X3 || algo == DOPINF_GRAM_BF16X6,
+  DOPINF_REQUIRE(algo == DOPINF_GRAM_NATIVE || algo == DOPINF_GRAM_BF16X3 || algo == DOPINF_GRAM_BF16X6 ||
+                     algo == DOPINF_GRAM_I8X6,
                  "unknown gram algorithm");
+  if (algo == DOPINF_GRAM_I8X6)
+    return gram_i8(st, static_cast<const float*>(Q), n, k, ldq, mean, scale, scale ? nvars : 0,
+                   scale ? var_rows_h : nullptr, D, ldd, ws, ws_bytes);
   return gram_lowp(st, algo, static_cast<const float*>(Q), n, k, ldq, mean, scale, scale ? nvars : 0,
                    scale ? var_rows_h : nullptr, D, ldd, ws, ws_bytes);
 }

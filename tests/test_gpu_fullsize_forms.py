@@ -30,6 +30,8 @@ pytestmark = pytest.mark.gpu
 
 U32 = 2.0 ** -24
 TOLS = {"native": 3e-5, "bf16x3": 2e-4, "bf16x6": 3e-5}
+I8_ROW = 2.5e-7  # I8X6: |dD_jl| <= n I8_ROW a_j a_l (derived in test_gpu_precision.py)
+ALGOS = {"native": 0, "bf16x3": 1, "bf16x6": 2, "i8x6": 3}
 
 
 def rel(a, b):
@@ -63,21 +65,27 @@ def c3(gpu_lib):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("algo_name", ["native", "bf16x3", "bf16x6"])
+@pytest.mark.parametrize("algo_name", ["native", "bf16x3", "bf16x6", "i8x6"])
 def test_fullsize_lowp_gram(gpu_lib, c3, algo_name):
     import torch
     dp = gpu_lib
-    algo = {"native": dp.GRAM_NATIVE, "bf16x3": dp.GRAM_BF16X3, "bf16x6": dp.GRAM_BF16X6}[algo_name]
-    tol = TOLS[algo_name]
+    algo = ALGOS[algo_name]
     Q32, var_rows = c3["Q32"], c3["var_rows"]
     D = dp.gram(Q32, c3["mean32"], c3["scale32"], var_rows, algo=algo).cpu().numpy()
     assert np.array_equal(D, D.T)
-    assert rel(D, c3["D64"]) <= tol + 2 * U32
     # sampled entries against the oracle's Gram of the float32 columns
     cols = np.array([0, 127, 128, 1023, 1500, 1919, 1920, 1999])
     Qc = Q32[:, torch.from_numpy(cols).cuda()].cpu().numpy().astype(np.float64)
     s_rows = np.repeat(c3["scale32"].cpu().numpy(), 1_000_000)
-    Dref = orc.gram(orc.apply_statistics(Qc, c3["mean32"].cpu().numpy(), s_rows))
+    Qs = orc.apply_statistics(Qc, c3["mean32"].cpu().numpy(), s_rows)
+    Dref = orc.gram(Qs)
+    if algo_name == "i8x6":
+        a = np.max(np.abs(Qs), axis=0)
+        assert np.max(np.abs(D[np.ix_(cols, cols)] - Dref) / (Qs.shape[0] * np.outer(a, a))) <= I8_ROW
+        print(f"i8x6: D {rel(D, c3['D64']):.3g} from the float64 D", flush=True)
+        return
+    tol = TOLS[algo_name]
+    assert rel(D, c3["D64"]) <= tol + 2 * U32
     cs = np.sqrt(np.outer(np.diag(Dref), np.diag(Dref)))
     assert np.max(np.abs(D[np.ix_(cols, cols)] - Dref) / cs) <= tol
 
@@ -87,7 +95,8 @@ def test_fullsize_lowp_against_oracle_of_rounded_data(gpu_lib, c3):
     data (the reference that isolates the Gram's arithmetic): the oracle's
     Gram over all 4,000,000 rows accumulated in row chunks (Eq. (5)), its
     eigenpairs and Qhat at r = 60; the forms' D within their tolerance, and
-    Qhat within 1e-6 for the forms that meet it (float32, split-BF16x6).
+    Qhat within 1e-6 for the forms that meet it (float32, split-BF16x6,
+    int8 slices I8X6).
     Errors against the float64 data itself are the float64 path's, which is
     within 1e-12 (D) of the oracle, plus these."""
     import torch
@@ -104,18 +113,27 @@ def test_fullsize_lowp_against_oracle_of_rounded_data(gpu_lib, c3):
     lam_o, U_o = orc.eig_desc(Dref)
     _, Qh_o = orc.reduce_basis_free(lam_o, U_o, 60)
     sel = lam_o >= 1e-10 * lam_o[0]
-    for name, algo in (("native", dp.GRAM_NATIVE), ("bf16x3", dp.GRAM_BF16X3), ("bf16x6", dp.GRAM_BF16X6)):
-        D = dp.gram(Q32, c3["mean32"], c3["scale32"], var_rows, algo=algo)
+    # I8X6 as a relative Frobenius bound: ||dD||_F <= n I8_ROW ||a||^2 with a
+    # the column max-abs values (<= 1 after the per-variable max-abs scaling)
+    amax = np.zeros(2000)
+    for r0 in range(0, 4_000_000, chunk):
+        blk = Q32[r0:r0 + chunk].cpu().numpy().astype(np.float64)
+        amax = np.maximum(amax, np.max(np.abs(orc.apply_statistics(blk, mean[r0:r0 + chunk],
+                                                                   s_rows[r0:r0 + chunk])), axis=0))
+        del blk
+    tols = dict(TOLS, i8x6=4_000_000 * I8_ROW * float(amax @ amax) / np.linalg.norm(Dref))
+    for name in ("native", "bf16x3", "bf16x6", "i8x6"):
+        D = dp.gram(Q32, c3["mean32"], c3["scale32"], var_rows, algo=ALGOS[name])
         lam, _, Qh, info, _ = dp.reduce(D, r=60, want_tr=False)
         torch.cuda.synchronize()
         Dn = D.cpu().numpy()
-        assert rel(Dn, Dref) <= TOLS[name], (name, rel(Dn, Dref))
+        assert rel(Dn, Dref) <= tols[name], (name, rel(Dn, Dref))
         ln = lam.cpu().numpy()
         lerr = np.abs(ln[sel] - lam_o[sel]) / lam_o[sel]
         qerr = rel(Qh.cpu().numpy(), Qh_o)
         print(f"{name}: D {rel(Dn, Dref):.3g}, lambda max {lerr.max():.3g} median {np.median(lerr):.3g}, "
               f"Qhat {qerr:.3g}", flush=True)
-        if name in ("native", "bf16x6"):
+        if name in ("native", "bf16x6", "i8x6"):
             assert qerr <= 1e-6, (name, qerr)
 
 
