@@ -28,11 +28,13 @@
 //     (the bfloat16 layout of the FP32/BF16 forms with one-byte elements:
 //     sixteen consecutive columns reading one logical slot hit sixteen
 //     different bank groups);
-//  3. MFMA: 128 x 128 lower-triangle tiles, split-K over row blocks, 4 waves x
-//     (4 x 4 blocks of 16 x 16) x 3 levels of int32 accumulators; a row block
-//     of a panel is one 8 KB chunk per slice brought into LDS by LDS-DMA,
-//     double buffered; the split's float64 partial is formed once at the end
-//     and the splits are summed in float64 by the shared reduction.
+//  3. MFMA: 256 x 128 tiles covering the lower triangle, split-K over row
+//     blocks, 8 waves (two per SIMD) x (4 x 4 blocks of 16 x 16) x 3 levels
+//     of int32 accumulators; a row block of a panel is one contiguous chunk
+//     per slice (16 KB for the 256 columns, 8 KB for the 128) brought into LDS
+//     by LDS-DMA, double buffered; the split's float64 partial is formed once
+//     at the end and the splits are summed in float64 by the shared
+//     reduction.
 #include "common.hpp"
 
 namespace dopinf {
@@ -193,19 +195,33 @@ __global__ __launch_bounds__(NTH) void pack_i8_kernel(PackArgs a) {
 
 struct MmaArgs {
   int64_t nb, kp;
-  int ntiles, nsplit, xcd_map;
+  int T;                       // 128-column tiles of D (the reduction's tile grid)
+  int nwide;                   // 256 x 128 tiles per split
+  int nsplit, xcd_map;
   int64_t bps;                 // row blocks per split
   const unsigned char* p;      // slices
   int64_t slice_bytes;
   const double* amax;
-  double* part;
+  double* part;                // per split, the T (T + 1) / 2 lower 128 x 128 tiles
 };
 
+// A workgroup of 8 waves computes a 256 x 128 tile: rows [256 I, 256 I + 256)
+// (panel A) by columns [128 J, 128 J + 128) (panel B), J <= 2 I + 1, i.e.
+// the 128 x 128 tiles (2 I, J) and (2 I + 1, J) of the lower triangle (the
+// upper one is skipped when J = 2 I + 1).  Row I holds 2 I + 2 tiles (fewer
+// only in the last row when T is odd), so tile t lies in row
+// I = floor((sqrt(4 t + 1) - 1) / 2), J = t - I (I + 1).  Wave w computes
+// rows 64 (w / 2) .. + 63 and columns 64 (w % 2) .. + 63 of the tile: one wave
+// per SIMD pair shares a panel row, and two waves per SIMD hide each other's
+// LDS reads.
+constexpr int MT = 512;                  // threads per workgroup
 constexpr int COLB = IK;                 // bytes of one column of a block (one slice)
-constexpr int PANEL = IT * COLB;         // bytes of one panel slice of a block
-constexpr int CHUNKS = PANEL / 1024;     // 1 KB LDS-DMA chunks per panel slice
-constexpr int STAGE = 2 * NSL * PANEL;   // A and B panels, all slices
+constexpr int PA_BYTES = 2 * IT * COLB;  // panel A slice of a block (256 columns)
+constexpr int PB_BYTES = IT * COLB;      // panel B slice of a block (128 columns)
+constexpr int STAGE = NSL * (PA_BYTES + PB_BYTES);
+constexpr int CHUNKS = STAGE / 1024;     // 1 KB LDS-DMA chunks per stage
 constexpr int NSTAGE = 2;
+static_assert(CHUNKS % (MT / 64) == 0, "chunks per wave");
 
 #define DOPINF_LDS(p) ((__attribute__((address_space(3))) void*)(p))
 
@@ -213,7 +229,12 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t span_rsrc(const void* p, int n
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, nbytes, 0x00020000);
 }
 
-__device__ __forceinline__ void wait_vmem_all() { __builtin_amdgcn_s_waitcnt(0 | (7 << 4) | (15 << 8)); }
+// Wait until at most N of this wave's vector-memory operations are in flight.
+template <int N>
+__device__ __forceinline__ void wait_vmem() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
 
 __device__ __forceinline__ void barrier_only() {
   asm volatile("" ::: "memory");
@@ -224,50 +245,79 @@ __device__ __forceinline__ void barrier_only() {
 // i32 16x16 MFMA output layout: lane l, element e -> row 4 (l / 16) + e, column l % 16
 __device__ __forceinline__ int out_row(int lane, int e) { return 4 * (lane >> 4) + e; }
 
-template <bool DIAG>
-__device__ __forceinline__ void i8_tile(const MmaArgs& g, int64_t b_lo, int64_t nst, int64_t a0, int64_t c0,
-                                        unsigned char* smem, i32x4 (&acc)[3][4][4]) {
+__global__ __launch_bounds__(MT, 1) void gram_i8_kernel(MmaArgs g) {
+  __shared__ __attribute__((aligned(16))) unsigned char smem[NSTAGE * STAGE];
+  int t, s;
+  {
+    const int bid = blockIdx.x;
+    if (g.xcd_map) {  // each XCD walks its own splits, all tiles of a split together
+      const int xcd = bid & 7, local = bid >> 3;
+      s = (local / g.nwide) * 8 + xcd;
+      t = local % g.nwide;
+    } else {
+      s = bid / g.nwide;
+      t = bid % g.nwide;
+    }
+  }
+  int I = int((sqrt(4.0 * t + 1.0) - 1.0) * 0.5);
+  while ((I + 1) * (I + 2) <= t) ++I;
+  while (I * (I + 1) > t) --I;
+  const int J = t - I * (I + 1);
+  const int64_t b_lo = int64_t(s) * g.bps;
+  const int64_t b_hi = min(g.nb, b_lo + g.bps);
+  const int64_t nst = b_hi > b_lo ? b_hi - b_lo : 0;
+  const int64_t a0 = int64_t(I) * 2 * IT, c0 = int64_t(J) * IT;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
   const int wm = w >> 1, wn = w & 1;
+  // the 128 x 128 tile of D this wave's quadrant belongs to
+  const int sub = 2 * I + (wm >> 1);
+  const bool live = sub < g.T && J <= sub;
   const uint32_t voff = uint32_t(lane) * 16;
+  // stage layout: A slices (16 chunks each), then B slices (8 chunks each);
+  // wave w issues chunks w, w + 8, ...
   auto issue = [&](int64_t st) {
     unsigned char* S = smem + (st % NSTAGE) * STAGE;
-    const int64_t blk = b_lo + st;
+    const size_t blk = size_t(b_lo + st);
 #pragma unroll
-    for (int s = 0; s < NSL; ++s) {
-      const unsigned char* rowblk = g.p + s * g.slice_bytes + size_t(blk) * size_t(g.kp) * COLB;
-#pragma unroll
-      for (int side = 0; side < (DIAG ? 1 : 2); ++side) {
-        const unsigned char* src = rowblk + size_t(side == 0 ? a0 : c0) * COLB;
-        unsigned char* dst = S + (side * NSL + s) * PANEL;
-#pragma unroll
-        for (int q = w; q < CHUNKS; q += 4) {
-          const __amdgpu_buffer_rsrc_t rs = span_rsrc(src + q * 1024, 1024);
-          __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, DOPINF_LDS(dst + q * 1024), 16, voff, 0, 0, 0);
-        }
-      }
+    for (int q = w; q < CHUNKS; q += MT / 64) {
+      const bool isa = q < NSL * (PA_BYTES / 1024);
+      const int qa = isa ? q : q - NSL * (PA_BYTES / 1024);
+      const int sl = isa ? qa / (PA_BYTES / 1024) : qa / (PB_BYTES / 1024);
+      const int qc = isa ? qa % (PA_BYTES / 1024) : qa % (PB_BYTES / 1024);
+      const unsigned char* src =
+          g.p + sl * g.slice_bytes + (blk * size_t(g.kp) + size_t(isa ? a0 : c0)) * COLB + qc * 1024;
+      const __amdgpu_buffer_rsrc_t rs = span_rsrc(src, 1024);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, DOPINF_LDS(S + q * 1024), 16, voff, 0, 0, 0);
     }
   };
+  i32x4 acc[3][4][4];
+#pragma unroll
+  for (int l = 0; l < 3; ++l)
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[l][i][j] = i32x4{0, 0, 0, 0};
   const int cm = lane & 15, gq = lane >> 4;
   const int o = 16 * (gq ^ ((cm >> 2) & 3));
   if (nst > 0) issue(0);
   for (int64_t st = 0; st < nst; ++st) {
-    wait_vmem_all();
+    wait_vmem<0>();
     barrier_only();
     // the other buffer was read in iteration st - 1, which every wave has left
     if (st + 1 < nst) issue(st + 1);
+    if (!live) continue;  // wave-uniform: the quadrant lies above the diagonal or past k
     const unsigned char* SA = smem + (st % NSTAGE) * STAGE;
-    const unsigned char* SB = DIAG ? SA : SA + NSL * PANEL;
+    const unsigned char* SB = SA + NSL * PA_BYTES;
     i32x4 fa[NSL][4], fb[NSL][4];
 #pragma unroll
-    for (int s = 0; s < NSL; ++s) {
+    for (int sl = 0; sl < NSL; ++sl) {
 #pragma unroll
       for (int i = 0; i < 4; ++i)
-        fa[s][i] = *reinterpret_cast<const i32x4*>(SA + s * PANEL + (wm * 64 + i * 16 + cm) * COLB + o);
+        fa[sl][i] = *reinterpret_cast<const i32x4*>(SA + sl * PA_BYTES + (wm * 64 + i * 16 + cm) * COLB + o);
 #pragma unroll
       for (int j = 0; j < 4; ++j)
-        fb[s][j] = *reinterpret_cast<const i32x4*>(SB + s * PANEL + (wn * 64 + j * 16 + cm) * COLB + o);
+        fb[sl][j] = *reinterpret_cast<const i32x4*>(SB + sl * PB_BYTES + (wn * 64 + j * 16 + cm) * COLB + o);
     }
     // products in the outer loop: 16 independent blocks lie between two
     // products into one accumulator
@@ -281,45 +331,10 @@ __device__ __forceinline__ void i8_tile(const MmaArgs& g, int64_t b_lo, int64_t 
           acc[LV[pr]][i][j] =
               __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[PA[pr]][i], fb[PB[pr]][j], acc[LV[pr]][i][j], 0, 0, 0);
   }
-}
-
-__global__ __launch_bounds__(NTH, 1) void gram_i8_kernel(MmaArgs g) {
-  __shared__ __attribute__((aligned(16))) unsigned char smem[NSTAGE * STAGE];
-  int t, s;
-  {
-    const int bid = blockIdx.x;
-    if (g.xcd_map) {  // each XCD walks its own splits, all tiles of a split together
-      const int xcd = bid & 7, local = bid >> 3;
-      s = (local / g.ntiles) * 8 + xcd;
-      t = local % g.ntiles;
-    } else {
-      s = bid / g.ntiles;
-      t = bid % g.ntiles;
-    }
-  }
-  int I = int((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-  while ((I + 1) * (I + 2) / 2 <= t) ++I;
-  while (I * (I + 1) / 2 > t) --I;
-  const int J = t - I * (I + 1) / 2;
-  const int64_t b_lo = int64_t(s) * g.bps;
-  const int64_t b_hi = min(g.nb, b_lo + g.bps);
-  const int64_t nst = b_hi > b_lo ? b_hi - b_lo : 0;
-  const int64_t a0 = int64_t(I) * IT, c0 = int64_t(J) * IT;
-  i32x4 acc[3][4][4];
-#pragma unroll
-  for (int l = 0; l < 3; ++l)
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[l][i][j] = i32x4{0, 0, 0, 0};
-  if (I == J)
-    i8_tile<true>(g, b_lo, nst, a0, c0, smem, acc);
-  else
-    i8_tile<false>(g, b_lo, nst, a0, c0, smem, acc);
-  const int lane = threadIdx.x & 63;
-  const int w = threadIdx.x >> 6;
-  const int wm = w >> 1, wn = w & 1;
-  double* out = g.part + (size_t(s) * g.ntiles + t) * (IT * IT);
+  if (!live) return;
+  const int ntiles = g.T * (g.T + 1) / 2;
+  double* out = g.part + (size_t(s) * ntiles + size_t(sub) * (sub + 1) / 2 + J) * (IT * IT);
+  const int r0 = (wm & 1) * 64;  // rows of the quadrant within its 128 x 128 tile
   constexpr double INV = 1.0 / (TOP * TOP);
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
@@ -329,17 +344,17 @@ __global__ __launch_bounds__(NTH, 1) void gram_i8_kernel(MmaArgs g) {
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int rr = wm * 64 + i * 16 + out_row(lane, e);
+        const int rr = r0 + i * 16 + out_row(lane, e);
         const double v = (static_cast<double>(acc[2][i][j][e]) / RADIX + static_cast<double>(acc[1][i][j][e])) / RADIX +
                          static_cast<double>(acc[0][i][j][e]);
-        out[rr * IT + cc] = v * (g.amax[a0 + rr] * ac);
+        out[rr * IT + cc] = v * (g.amax[int64_t(sub) * IT + rr] * ac);
       }
   }
 }
 
 struct I8Plan {
   int64_t nb, kp;
-  int T, ntiles, nsplit;
+  int T, T2, ntiles, nwide, nsplit;
   int64_t bps;
   size_t slice_bytes, amax_bytes, part_bytes;
 };
@@ -348,11 +363,13 @@ I8Plan plan(int64_t n, int64_t k) {
   I8Plan p{};
   p.nb = (n + IK - 1) / IK;
   p.T = int((k + IT - 1) / IT);
-  p.kp = int64_t(p.T) * IT;
+  p.T2 = (p.T + 1) / 2;
+  p.kp = int64_t(p.T2) * 2 * IT;
   p.ntiles = p.T * (p.T + 1) / 2;
+  p.nwide = p.T2 * (p.T2 + 1) - (p.T % 2);
   // about 8192 workgroups, at least nb / MAXB splits (exact int32 sums), a
   // multiple of 8 (XCD map) and, where it costs at most a quarter more, whole
-  // rounds of the resident workgroups (one per CU: 96 KB of LDS)
+  // rounds of the resident workgroups (one per CU: 144 KB of LDS)
   int ncu = 0;
   {
     int dev = 0;
@@ -360,13 +377,13 @@ I8Plan plan(int64_t n, int64_t k) {
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
       ncu = 0;
   }
-  int64_t target = (8192 + p.ntiles - 1) / p.ntiles;
+  int64_t target = (8192 + p.nwide - 1) / p.nwide;
   const int64_t need = (p.nb + MAXB - 1) / MAXB;
   if (target < need) target = need;
   if (target > p.nb) target = p.nb;
   if (target >= 8) target = (target + 7) / 8 * 8;
   if (ncu > 0 && target >= 8) {
-    int64_t a = p.ntiles, b = ncu;
+    int64_t a = p.nwide, b = ncu;
     while (b) {
       const int64_t r = a % b;
       a = b;
@@ -436,12 +453,13 @@ int gram_i8(hipStream_t st, const float* Q, int64_t n, int64_t k, int64_t ldq, c
   pa.amax = reinterpret_cast<const double*>(amax);
   pa.p = slices;
   pa.slice_bytes = int64_t(p.slice_bytes);
-  pack_i8_kernel<<<dim3(unsigned(p.nb), unsigned(p.T)), NTH, 0, st>>>(pa);
+  pack_i8_kernel<<<dim3(unsigned(p.nb), unsigned(p.kp / IT)), NTH, 0, st>>>(pa);
   DOPINF_LAUNCHED();
   MmaArgs g{};
   g.nb = p.nb;
   g.kp = p.kp;
-  g.ntiles = p.ntiles;
+  g.T = p.T;
+  g.nwide = p.nwide;
   g.nsplit = p.nsplit;
   g.xcd_map = (p.nsplit % 8 == 0) ? 1 : 0;
   g.bps = p.bps;
@@ -449,7 +467,7 @@ int gram_i8(hipStream_t st, const float* Q, int64_t n, int64_t k, int64_t ldq, c
   g.slice_bytes = int64_t(p.slice_bytes);
   g.amax = pa.amax;
   g.part = part;
-  gram_i8_kernel<<<dim3(unsigned(p.nsplit) * unsigned(p.ntiles)), NTH, 0, st>>>(g);
+  gram_i8_kernel<<<dim3(unsigned(p.nsplit) * unsigned(p.nwide)), MT, 0, st>>>(g);
   DOPINF_LAUNCHED();
   return gram_reduce_launch(st, part, p.nsplit, p.ntiles, p.T, 1, k, k, D, ldd);
 }
