@@ -65,27 +65,49 @@ struct XArgs {
 
 __device__ __forceinline__ double rinv_of(const XArgs& a, int v) { return a.scale ? 1.0 / a.scale[v] : 1.0; }
 
+typedef float flt4 __attribute__((ext_vector_type(4)));
+
+// Values of row r at columns c .. c + CPT - 1: one 16-byte load when VEC
+// (Q 16-byte aligned, ldq a multiple of 4) and the columns lie inside k,
+// else one load per column inside k (0 past it).
+template <bool VEC, int CPT>
+__device__ __forceinline__ void load_cols(const XArgs& a, int64_t r, int64_t c, float (&q)[CPT]) {
+  const float* row = a.Q + r * a.ldq + c;
+  if (VEC && CPT == 4 && c + 4 <= a.k) {
+    const flt4 v = *reinterpret_cast<const flt4*>(row);
+#pragma unroll
+    for (int e = 0; e < CPT; ++e) q[e] = v[e];
+  } else {
+#pragma unroll
+    for (int e = 0; e < CPT; ++e) q[e] = c + e < a.k ? row[e] : 0.f;
+  }
+}
+
 // a_j = max_i |x_ij| over the workgroup's rows, folded into amax (the bit
 // patterns of non-negative doubles order like the values; NaN above all).
-// Thread -> column; 8 rows' loads in flight together.
+// Thread -> CPT consecutive columns; 8 rows' loads in flight together.
+template <bool VEC>
 __global__ __launch_bounds__(NTH) void colmax_kernel(XArgs a, int64_t rows_per_wg,
                                                      unsigned long long* __restrict__ amax) {
-  const int64_t c = int64_t(blockIdx.x) * NTH + threadIdx.x;
+  constexpr int CPT = VEC ? 4 : 1;
+  const int64_t c = (int64_t(blockIdx.x) * NTH + threadIdx.x) * CPT;
   const int64_t r0 = int64_t(blockIdx.y) * rows_per_wg;
   const int64_t r1 = min(a.n, r0 + rows_per_wg);
   if (c >= a.k || r0 >= r1) return;
   int v = 0;
   while (v + 1 < a.nvars && r0 >= a.row0[v + 1]) ++v;
   double rinv = rinv_of(a, v);
-  double m = 0.0;
-  bool bad = false;
-  for (int64_t rb = r0; rb < r1; rb += 8) {
-    float q[8];
+  double m[CPT];
+  bool bad[CPT];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int64_t r = rb + u;
-      q[u] = a.Q[(r < r1 ? r : rb) * a.ldq + c];
-    }
+  for (int e = 0; e < CPT; ++e) {
+    m[e] = 0.0;
+    bad[e] = false;
+  }
+  for (int64_t rb = r0; rb < r1; rb += 8) {
+    float q[8][CPT];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) load_cols<VEC, CPT>(a, rb + u < r1 ? rb + u : rb, c, q[u]);
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int64_t r = rb + u;
@@ -94,13 +116,20 @@ __global__ __launch_bounds__(NTH) void colmax_kernel(XArgs a, int64_t rows_per_w
         while (v + 1 < a.nvars && r >= a.row0[v + 1]) ++v;
         rinv = rinv_of(a, v);
       }
-      const double x = fabs((static_cast<double>(q[u]) - (a.mean ? a.mean[r] : 0.0)) * rinv);
-      bad |= !(x <= 1.7976931348623157e308);
-      m = x > m ? x : m;
+      const double mu = a.mean ? a.mean[r] : 0.0;
+#pragma unroll
+      for (int e = 0; e < CPT; ++e) {
+        const double x = fabs((static_cast<double>(q[u][e]) - mu) * rinv);
+        bad[e] |= !(x <= 1.7976931348623157e308);
+        m[e] = x > m[e] ? x : m[e];
+      }
     }
   }
-  const unsigned long long bits = bad ? 0x7ff8000000000000ull : static_cast<unsigned long long>(__double_as_longlong(m));
-  atomicMax(amax + c, bits);
+#pragma unroll
+  for (int e = 0; e < CPT; ++e)
+    if (c + e < a.k)
+      atomicMax(amax + c + e,
+                bad[e] ? 0x7ff8000000000000ull : static_cast<unsigned long long>(__double_as_longlong(m[e])));
 }
 
 __global__ void zero_u64_kernel(unsigned long long* p, int64_t n) {
@@ -127,14 +156,16 @@ struct PackArgs {
   int64_t slice_bytes;
 };
 
-constexpr int PB = 80;  // LDS pitch of a column's 64 bytes (16-byte aligned)
+constexpr int PW = IK / 4 + 1;  // LDS pitch of a column in 32-bit words (16 + 1: stores conflict at most 2-way)
 
-// One workgroup packs a 64-row block x 128 columns: thread -> column
-// tid % 128 and the row quads tid / 128 + 2 j (32 loads in flight), each
-// quad's three slices stored as one 32-bit word per slice into a
-// column-major LDS tile, then whole 16-byte slots written out.
+// One workgroup packs a 64-row block x 128 columns: thread -> columns
+// 4 (tid % 32) .. + 3 and the row quads tid / 32 and tid / 32 + 8 (eight
+// 16-byte loads in flight when VEC), each column's quad of rows stored as
+// one 32-bit word per slice into a column-major LDS tile, then whole 16-byte
+// slots written out.
+template <bool VEC>
 __global__ __launch_bounds__(NTH) void pack_i8_kernel(PackArgs a) {
-  __shared__ __attribute__((aligned(16))) unsigned char t8[NSL][IT][PB];
+  __shared__ unsigned t8[NSL][IT][PW];
   __shared__ double rmu[IK], rinv[IK], cs[IT];
   const int64_t blk = blockIdx.x;
   const int64_t c0 = int64_t(blockIdx.y) * IT;
@@ -151,44 +182,47 @@ __global__ __launch_bounds__(NTH) void pack_i8_kernel(PackArgs a) {
     const double am = a.amax[c0 + tid - IK];
     cs[tid - IK] = (am > 0.0 && am <= 1.7976931348623157e308) ? TOP / am : 0.0;
   }
-  const int cc = tid % IT, rq0 = tid / IT;
-  const int64_t col = c0 + cc;
-  const bool cin = col < x.k;
-  const int64_t colc = cin ? col : 0;
-  float q[IK / 2];
+  const int cq = tid % 32, rq0 = tid / 32;
+  float q[2][4][4];  // [row quad][row of the quad][column]
 #pragma unroll
-  for (int j = 0; j < IK / 8; ++j)
+  for (int h = 0; h < 2; ++h)
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const int64_t row = blk * IK + 4 * (rq0 + 2 * j) + e;
-      q[4 * j + e] = x.Q[(row < x.n ? row : x.n - 1) * x.ldq + colc];
+      const int64_t row = blk * IK + 4 * (rq0 + 8 * h) + e;
+      load_cols<VEC, 4>(x, row < x.n ? row : x.n - 1, c0 + 4 * cq, q[h][e]);
     }
   __syncthreads();
-  const double sc = cs[cc];
 #pragma unroll
-  for (int j = 0; j < IK / 8; ++j) {
-    const int rq = rq0 + 2 * j;
-    unsigned w[NSL] = {0u, 0u, 0u};
+  for (int h = 0; h < 2; ++h) {
+    const int rq = rq0 + 8 * h;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int rr = 4 * rq + e;
-      const bool in = cin && blk * IK + rr < x.n;
-      const double xs = in ? (static_cast<double>(q[4 * j + e]) - rmu[rr]) * rinv[rr] * sc : 0.0;
-      int t[NSL];
-      split3(xs, t[0], t[1], t[2]);
+    for (int c = 0; c < 4; ++c) {
+      const int cc = 4 * cq + c;
+      const double sc = cs[cc];
+      const bool cin = c0 + cc < x.k;
+      unsigned w[NSL] = {0u, 0u, 0u};
 #pragma unroll
-      for (int s = 0; s < NSL; ++s) w[s] |= (unsigned(t[s]) & 0xffu) << (8 * e);
+      for (int e = 0; e < 4; ++e) {
+        const int rr = 4 * rq + e;
+        const bool in = cin && blk * IK + rr < x.n;
+        const double xs = in ? (static_cast<double>(q[h][e][c]) - rmu[rr]) * rinv[rr] * sc : 0.0;
+        int t[NSL];
+        split3(xs, t[0], t[1], t[2]);
+#pragma unroll
+        for (int sl = 0; sl < NSL; ++sl) w[sl] |= (unsigned(t[sl]) & 0xffu) << (8 * e);
+      }
+#pragma unroll
+      for (int sl = 0; sl < NSL; ++sl) t8[sl][cc][rq] = w[sl];
     }
-#pragma unroll
-    for (int s = 0; s < NSL; ++s) *reinterpret_cast<unsigned*>(&t8[s][cc][4 * rq]) = w[s];
   }
   __syncthreads();
   // 3 slices x 128 columns x 4 slots
 #pragma unroll
   for (int i = 0; i < NSL * IT * 4 / NTH; ++i) {
-    const int t = tid + NTH * i, s = t / (IT * 4), cw = (t / 4) % IT, g = t & 3;
-    const u32x4 v = *reinterpret_cast<const u32x4*>(&t8[s][cw][16 * g]);
-    unsigned char* dst = a.p + s * a.slice_bytes + (size_t(blk) * a.kp + c0 + cw) * IK + ((g ^ ((cw >> 2) & 3)) << 4);
+    const int t = tid + NTH * i, sl = t / (IT * 4), cw = (t / 4) % IT, g = t & 3;
+    const u32x4 v = {t8[sl][cw][4 * g], t8[sl][cw][4 * g + 1], t8[sl][cw][4 * g + 2], t8[sl][cw][4 * g + 3]};
+    unsigned char* dst =
+        a.p + sl * a.slice_bytes + (size_t(blk) * a.kp + c0 + cw) * IK + ((g ^ ((cw >> 2) & 3)) << 4);
     *reinterpret_cast<u32x4*>(dst) = v;
   }
 }
@@ -438,14 +472,19 @@ int gram_i8(hipStream_t st, const float* Q, int64_t n, int64_t k, int64_t ldq, c
   }
   zero_u64_kernel<<<unsigned((p.kp + 255) / 256), 256, 0, st>>>(amax, p.kp);
   DOPINF_LAUNCHED();
+  // 16-byte row loads where every row start is 16-byte aligned
+  const bool vec = reinterpret_cast<uintptr_t>(Q) % 16 == 0 && ldq % 4 == 0;
   // about 8 row chunks per CU and column group
-  const int64_t col_groups = (k + NTH - 1) / NTH;
+  const int64_t col_groups = (k + NTH * (vec ? 4 : 1) - 1) / (NTH * (vec ? 4 : 1));
   int64_t chunks = (2048 + col_groups - 1) / col_groups;
   int64_t rows_per_wg = (n + chunks - 1) / chunks;
   rows_per_wg = (rows_per_wg + 7) / 8 * 8;
   if (rows_per_wg < 64) rows_per_wg = 64;
   chunks = (n + rows_per_wg - 1) / rows_per_wg;
-  colmax_kernel<<<dim3(unsigned(col_groups), unsigned(chunks)), NTH, 0, st>>>(x, rows_per_wg, amax);
+  if (vec)
+    colmax_kernel<true><<<dim3(unsigned(col_groups), unsigned(chunks)), NTH, 0, st>>>(x, rows_per_wg, amax);
+  else
+    colmax_kernel<false><<<dim3(unsigned(col_groups), unsigned(chunks)), NTH, 0, st>>>(x, rows_per_wg, amax);
   DOPINF_LAUNCHED();
   PackArgs pa{};
   pa.x = x;
@@ -453,7 +492,10 @@ int gram_i8(hipStream_t st, const float* Q, int64_t n, int64_t k, int64_t ldq, c
   pa.amax = reinterpret_cast<const double*>(amax);
   pa.p = slices;
   pa.slice_bytes = int64_t(p.slice_bytes);
-  pack_i8_kernel<<<dim3(unsigned(p.nb), unsigned(p.kp / IT)), NTH, 0, st>>>(pa);
+  if (vec)
+    pack_i8_kernel<true><<<dim3(unsigned(p.nb), unsigned(p.kp / IT)), NTH, 0, st>>>(pa);
+  else
+    pack_i8_kernel<false><<<dim3(unsigned(p.nb), unsigned(p.kp / IT)), NTH, 0, st>>>(pa);
   DOPINF_LAUNCHED();
   MmaArgs g{};
   g.nb = p.nb;
