@@ -23,6 +23,8 @@
 //     loads of block b+1 fly while block b feeds the matrix cores); float32
 //     accumulation over slabs of 512 rows, slabs added into float64
 //     accumulators; split partials summed in float64 by the shared kernel.
+//     BF16X6 runs the same stages on 256 x 128 tiles with 8 waves (two per
+//     SIMD), which bring in half the panel bytes per product.
 #include "common.hpp"
 #include "gram_plan.hpp"
 
@@ -391,7 +393,8 @@ __device__ __forceinline__ void packed_tile(const MmaArgs& g, int64_t b_lo, int6
 // diagonal tiles (sel 2, D9) take a launch of their own in which each wave
 // computes only 9 of the 36 lower 16 x 16 blocks.
 template <int ALGO, bool D9 = false>
-__global__ __launch_bounds__(NTH, ALGO == 2 ? 1 : 2) void gram_packed_kernel(MmaArgs g) {
+__global__ __launch_bounds__(NTH, 2) void gram_packed_kernel(MmaArgs g) {
+  static_assert(ALGO < 2, "BF16X6 runs on gram_wide_kernel");
   __shared__ __attribute__((aligned(16))) unsigned char smem[PackedGeom<ALGO>::NSTAGE * PackedGeom<ALGO>::STAGE];
   int t, s;
   {
@@ -466,13 +469,161 @@ __global__ __launch_bounds__(NTH, ALGO == 2 ? 1 : 2) void gram_packed_kernel(Mma
       }
 }
 
+// The BF16X6 form on 256 x 128 tiles: a workgroup of 8 waves (two per
+// SIMD) computes rows [256 I, 256 I + 256) (panel A) by columns
+// [128 J, 128 J + 128) (panel B), J <= 2 I + 1, i.e. the 128 x 128 tiles
+// (2 I, J) and (2 I + 1, J) of the lower triangle; tile t lies in row
+// I = floor((sqrt(4 t + 1) - 1) / 2), J = t - I (I + 1).  Wave w computes rows
+// 64 (w / 2) .. + 63 and columns 64 (w % 2) .. + 63 of the tile, skipping the
+// stage's work when its quadrant lies above the diagonal or past k.  Against
+// 128 x 128 tiles a row block's panels feed twice the products per byte
+// brought in, and two waves per SIMD hide each other's LDS reads.
+constexpr int WMT = 512;
+
+template <int ALGO>
+struct WideGeom {
+  static constexpr int NPART = ALGO == 1 ? 2 : 3;
+  static constexpr int COLB = KB * 2;            // bytes of one column of a block (one part)
+  static constexpr int PA = 2 * BT * COLB;       // panel A part of a block (256 columns)
+  static constexpr int PB = BT * COLB;           // panel B part of a block (128 columns)
+  static constexpr int STAGE = NPART * (PA + PB);
+  static constexpr int CHUNKS = STAGE / 1024;    // 1 KB LDS-DMA chunks per stage
+  static_assert(CHUNKS % (WMT / 64) == 0, "chunks per wave");
+};
+
+struct WideArgs {
+  int64_t nb, kp;
+  int T, nwide, nsplit, xcd_map;
+  int64_t bps;
+  const unsigned short* part_p[3];  // hi, mid/lo, lo
+  double* part;                     // per split, the T (T + 1) / 2 lower 128 x 128 tiles
+};
+
+template <int ALGO>
+__global__ __launch_bounds__(WMT, 1) void gram_wide_kernel(WideArgs g) {
+  using Gm = WideGeom<ALGO>;
+  constexpr int NPART = Gm::NPART;
+  __shared__ __attribute__((aligned(16))) unsigned char smem[2 * Gm::STAGE];
+  int t, s;
+  {
+    const int bid = blockIdx.x;
+    if (g.xcd_map) {  // each XCD walks its own splits, all tiles of a split together
+      const int xcd = bid & 7, local = bid >> 3;
+      s = (local / g.nwide) * 8 + xcd;
+      t = local % g.nwide;
+    } else {
+      s = bid / g.nwide;
+      t = bid % g.nwide;
+    }
+  }
+  int I = int((sqrt(4.0 * t + 1.0) - 1.0) * 0.5);
+  while ((I + 1) * (I + 2) <= t) ++I;
+  while (I * (I + 1) > t) --I;
+  const int J = t - I * (I + 1);
+  const int64_t b_lo = int64_t(s) * g.bps;
+  const int64_t b_hi = min(g.nb, b_lo + g.bps);
+  const int64_t nst = b_hi > b_lo ? b_hi - b_lo : 0;
+  const int64_t a0 = int64_t(I) * 2 * BT, c0 = int64_t(J) * BT;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
+  const int wm = w >> 1, wn = w & 1;
+  const int sub = 2 * I + (wm >> 1);
+  const bool live = sub < g.T && J <= sub;
+  const uint32_t voff = uint32_t(lane) * 16;
+  // stage layout: A parts (16 chunks each), then B parts (8 chunks each);
+  // wave w issues chunks w, w + 8, ...
+  auto issue = [&](int64_t st) {
+    unsigned char* S = smem + (st & 1) * Gm::STAGE;
+    const size_t blk = size_t(b_lo + st);
+#pragma unroll
+    for (int q = w; q < Gm::CHUNKS; q += WMT / 64) {
+      const bool isa = q < NPART * (Gm::PA / 1024);
+      const int qa = isa ? q : q - NPART * (Gm::PA / 1024);
+      const int pt = isa ? qa / (Gm::PA / 1024) : qa / (Gm::PB / 1024);
+      const int qc = isa ? qa % (Gm::PA / 1024) : qa % (Gm::PB / 1024);
+      const unsigned char* src = reinterpret_cast<const unsigned char*>(g.part_p[pt]) +
+                                 (blk * size_t(g.kp) + size_t(isa ? a0 : c0)) * Gm::COLB + qc * 1024;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(span_rsrc(src, 1024), DOPINF_LDS(S + q * 1024), 16, voff, 0, 0, 0);
+    }
+  };
+  flt4 acc[4][4];
+  double acc64[4][4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      acc[i][j] = flt4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc64[i][j][e] = 0.0;
+    }
+  const int cm = lane & 15, gq = lane >> 4;
+  const int o = 16 * (gq ^ ((cm >> 2) & 3));
+  if (nst > 0) issue(0);
+  // slabs of SLAB_STAGES stages: float32 sums over at most 512 rows, then the
+  // float64 accumulators
+  for (int64_t s0 = 0; s0 < nst; s0 += SLAB_STAGES) {
+    const int64_t s1 = s0 + SLAB_STAGES < nst ? s0 + SLAB_STAGES : nst;
+    for (int64_t st = s0; st < s1; ++st) {
+      wait_vmem<0>();
+      barrier_only();
+      // the other buffer was read in iteration st - 1, which every wave has left
+      if (st + 1 < nst) issue(st + 1);
+      if (!live) continue;  // wave-uniform
+      const unsigned char* SA = smem + (st & 1) * Gm::STAGE;
+      const unsigned char* SB = SA + NPART * Gm::PA;
+      bf16x8 a[NPART][4], b[NPART][4];
+#pragma unroll
+      for (int q = 0; q < NPART; ++q) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          a[q][i] = __builtin_bit_cast(
+              bf16x8, *reinterpret_cast<const us8*>(SA + q * Gm::PA + (wm * 64 + i * 16 + cm) * Gm::COLB + o));
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          b[q][j] = __builtin_bit_cast(
+              bf16x8, *reinterpret_cast<const us8*>(SB + q * Gm::PB + (wn * 64 + j * 16 + cm) * Gm::COLB + o));
+      }
+      // products in the outer loop (smallest first), as in packed_tile
+      constexpr int PA_[6] = {2, 0, 1, 1, 0, 0}, PB_[6] = {0, 2, 1, 0, 1, 0};
+#pragma unroll
+      for (int pr = (ALGO == 2 ? 0 : 3); pr < 6; ++pr)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[PA_[pr]][i], b[PB_[pr]][j], acc[i][j], 0, 0, 0);
+    }
+    if (live) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) acc64[i][j][e] += static_cast<double>(acc[i][j][e]);
+          acc[i][j] = flt4{0.f, 0.f, 0.f, 0.f};
+        }
+    }
+  }
+  if (!live) return;
+  const int ntiles = g.T * (g.T + 1) / 2;
+  double* out = g.part + (size_t(s) * ntiles + size_t(sub) * (sub + 1) / 2 + J) * (BT * BT);
+  const int r0 = (wm & 1) * 64;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        out[(r0 + i * 16 + out_row(lane, e)) * BT + wn * 64 + j * 16 + (lane & 15)] = acc64[i][j][e];
+}
+
 int tiles_of(int64_t m) { return int((m + BT - 1) / BT); }
 int nparts(int algo) { return algo == DOPINF_GRAM_NATIVE ? 1 : (algo == DOPINF_GRAM_BF16X3 ? 2 : 3); }
 size_t part_elt(int algo) { return algo == DOPINF_GRAM_NATIVE ? 4 : 2; }
 
 struct LowpPlan {
   int64_t nb, kp;
-  int T, ntiles, nsplit;
+  int T, ntiles, nwide, nsplit;
   int64_t bps;
   size_t pack_bytes, part_bytes;
 };
@@ -481,17 +632,24 @@ LowpPlan plan(int algo, int64_t n, int64_t k) {
   LowpPlan p{};
   p.nb = (n + KB - 1) / KB;
   p.T = tiles_of(k);
-  p.kp = int64_t(p.T) * BT;
+  // BF16X6 on 256 x 128 tiles (one workgroup of 8 waves per CU): 107 -> 97 ms
+  // at n = 4e6, k = 2000; BF16X3, which already runs two 4-wave workgroups
+  // per CU on 128 x 128 tiles, measured slower on them (61 -> 64 ms)
+  const bool wide = algo == DOPINF_GRAM_BF16X6;
+  const int T2 = (p.T + 1) / 2;
+  p.kp = wide ? int64_t(T2) * 2 * BT : int64_t(p.T) * BT;
   p.ntiles = p.T * (p.T + 1) / 2;
-  // resident workgroups: two per CU, one for BF16X6 (96 KB of LDS)
+  p.nwide = T2 * (T2 + 1) - (p.T % 2);
+  // resident workgroups: two per CU (FP32, BF16X3), one for BF16X6 (8 waves,
+  // 144 KB of LDS)
   int slots = 0;
   {
     int dev = 0, ncu = 0;
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
-      slots = (algo == DOPINF_GRAM_BF16X6 ? 1 : 2) * ncu;
+      slots = (wide ? 1 : 2) * ncu;
   }
-  int target = gramplan::choose_splits(n, p.ntiles, 8192, slots);
+  int target = gramplan::choose_splits(n, wide ? p.nwide : p.ntiles, 8192, slots);
   if (target < 1) target = 1;
   p.bps = (p.nb + target - 1) / target;
   p.nsplit = int((p.nb + p.bps - 1) / p.bps);
@@ -541,7 +699,7 @@ int gram_lowp(hipStream_t st, int algo, const float* Q, int64_t n, int64_t k, in
   pa.p0 = reinterpret_cast<unsigned short*>(base);
   pa.p1 = reinterpret_cast<unsigned short*>(base + one);
   pa.p2 = reinterpret_cast<unsigned short*>(base + 2 * one);
-  pack_kernel<<<dim3(unsigned(p.nb), unsigned(p.T)), 256, 0, st>>>(pa);
+  pack_kernel<<<dim3(unsigned(p.nb), unsigned(p.kp / BT)), 256, 0, st>>>(pa);
   DOPINF_LAUNCHED();
   MmaArgs g{};
   g.nb = p.nb;
@@ -569,10 +727,23 @@ int gram_lowp(hipStream_t st, int algo, const float* Q, int64_t n, int64_t k, in
     g.sel = 2;
     g.nlaunch = p.T;
     gram_packed_kernel<0, true><<<dim3(unsigned(p.nsplit) * unsigned(p.T)), NTH, 0, st>>>(g);
-  } else if (algo == DOPINF_GRAM_BF16X3)
+  } else if (algo == DOPINF_GRAM_BF16X3) {
     gram_packed_kernel<1><<<grid, NTH, 0, st>>>(g);
-  else
-    gram_packed_kernel<2><<<grid, NTH, 0, st>>>(g);
+  } else {
+    WideArgs wa{};
+    wa.nb = p.nb;
+    wa.kp = p.kp;
+    wa.T = p.T;
+    wa.nwide = p.nwide;
+    wa.nsplit = p.nsplit;
+    wa.xcd_map = g.xcd_map;
+    wa.bps = p.bps;
+    wa.part_p[0] = pa.p0;
+    wa.part_p[1] = pa.p1;
+    wa.part_p[2] = pa.p2;
+    wa.part = g.part;
+    gram_wide_kernel<2><<<dim3(unsigned(p.nsplit) * unsigned(p.nwide)), WMT, 0, st>>>(wa);
+  }
   DOPINF_LAUNCHED();
   return gram_reduce_launch(st, g.part, p.nsplit, p.ntiles, p.T, 1, k, k, D, ldd);
 }
