@@ -174,3 +174,26 @@ def test_i8x6_nonfinite_column(gpu_lib):
         keep = np.arange(40) != 7
         # row 123 of the other columns is unchanged, so are their entries
         assert np.array_equal(D[np.ix_(keep, keep)], D0[np.ix_(keep, keep)])
+
+
+def test_i8x6_degenerate_shapes(gpu_lib):
+    """One row, one column, and an all-zero column (a_j = 0: its slices are
+    zero and its entries of D exactly 0, not NaN); each against the
+    emulation of the form's arithmetic."""
+    import torch
+    dp = gpu_lib
+    rng = np.random.default_rng(17)
+    cases = [rng.standard_normal((1, 7)), rng.standard_normal((300, 1)), rng.standard_normal((129, 33))]
+    cases[2][:, 5] = 0.0
+    for Q in cases:
+        Q = Q.astype(np.float32)
+        n, k = Q.shape
+        D = dp.gram(torch.from_numpy(Q).cuda(), algo=dp.GRAM_I8X6).cpu().numpy()
+        De, x = i8_emulate(Q, np.zeros(n), np.ones(1), [0, n])
+        a = np.max(np.abs(x), axis=0)
+        assert np.all(np.isfinite(D))
+        assert np.max(np.abs(D - De) / np.maximum(n * np.outer(a, a), 1e-300)) <= 1e-13
+        if k == 33:
+            assert np.all(D[5, :] == 0.0) and np.all(D[:, 5] == 0.0)
+        Dref = orc.gram(Q.astype(np.float64))
+        assert i8_excess(D, Dref, Q.astype(np.float64)) <= I8_ROW
