@@ -361,19 +361,18 @@ __device__ __forceinline__ void packed_tile(const MmaArgs& g, int64_t b_lo, int6
           b[q][j] = __builtin_bit_cast(
               bf16x8, *reinterpret_cast<const us8*>(SB + q * Gm::PANEL + (wn * 64 + j * 16 + cm) * Gm::COLB + o));
       }
-      // products in the outer loop (smallest first): 16 independent blocks lie
-      // between two products into one accumulator, so no MFMA waits on the
-      // result of the previous one
-      constexpr int NPROD = ALGO == 2 ? 6 : 3;
-      constexpr int PA[6] = {2, 0, 1, 1, 0, 0}, PB[6] = {0, 2, 1, 0, 1, 0};
+      // BF16X3's products lo.hi, hi.lo, hi.hi in the outer loop (smallest
+      // first): 16 independent blocks lie between two products into one
+      // accumulator, so no MFMA waits on the result of the previous one
+      // (BF16X6 runs on gram_wide_kernel)
+      constexpr int PA[3] = {1, 0, 0}, PB[3] = {0, 1, 0};
 #pragma unroll
-      for (int pr = (ALGO == 2 ? 0 : 3); pr < 6; ++pr)
+      for (int pr = 0; pr < 3; ++pr)
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
           for (int j = 0; j < 4; ++j)
             acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[PA[pr]][i], b[PB[pr]][j], acc[i][j], 0, 0, 0);
-      (void)NPROD;
     }
   }
 #pragma unroll

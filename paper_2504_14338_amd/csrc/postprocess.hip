@@ -198,6 +198,141 @@ __global__ __launch_bounds__(PT) void row_gemm_kernel(RowGemmArgs<T> a) {
     }
 }
 
+// The basis at all rows (contiguous float64 rows, 33 <= ncol <= 64, even K
+// and ncol): both operands go from memory straight into LDS by LDS-DMA
+// (buffer loads that write LDS, no register round trip), double buffered in
+// stages of 16 values of K, one workgroup barrier per stage, three
+// workgroups per CU (48 KB of LDS).  A (128 rows x 16 k, 128 bytes per row)
+// is M-major with the eight 16-byte chunks of row m at slots c ^ ((m / 2) % 8),
+// so the 16 rows of a fragment read fall on 16 different bank groups; B
+// (16 k x 64 columns, 512 bytes per row) is K-major with the chunks of odd
+// rows at c ^ 8, so the two k of a fragment read use both halves of the
+// banks.  Out-of-range rows, K past its end and columns past ncol read as
+// zero (buffer range checks and an out-of-range offset).  The mean is
+// subtracted from the A fragments (zero K entries meet zero B entries).
+constexpr int DK = 16;                  // K per stage
+constexpr int DROWS = 2 * PM;           // output rows per workgroup
+constexpr int DA = DROWS * DK;          // doubles of an A stage
+constexpr int DB = DK * 64;             // doubles of a B stage
+constexpr int DSTAGE = DA + DB;         // 24 KB
+
+#define DOPINF_LDS(p) ((__attribute__((address_space(3))) void*)(p))
+
+__device__ __forceinline__ void wait_vmem_all() { __builtin_amdgcn_s_waitcnt(0 | (7 << 4) | (15 << 8)); }
+
+__device__ __forceinline__ void barrier_only() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+__global__ __launch_bounds__(PT) void row_gemm_dma_kernel(RowGemmArgs<double> a) {
+  __shared__ __attribute__((aligned(16))) double sm[2 * DSTAGE];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t i0 = int64_t(blockIdx.x) * DROWS;
+  const int64_t mrows = a.m - i0 < DROWS ? a.m - i0 : DROWS;
+  const __amdgpu_buffer_rsrc_t rsa =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(a.A + i0 * a.lda), 0, int(mrows * a.lda * 8), 0x00020000);
+  const __amdgpu_buffer_rsrc_t rsb =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(a.B), 0, int(a.K * a.ldb * 8), 0x00020000);
+  const int64_t nst = (a.K + DK - 1) / DK;
+  // wave wv issues the A instructions q = wv + 4 t (8 rows each) and the B
+  // instructions q = wv + 4 t (2 k rows each) of a stage
+  auto issue = [&](int64_t st) {
+    double* S = sm + (st & 1) * DSTAGE;
+    const int64_t kb = st * DK;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int q = wv + 4 * t;
+      const int m = 8 * q + (lane >> 3);
+      const int c = (lane & 7) ^ ((m >> 1) & 7);
+      const int64_t k = kb + 2 * c;
+      const uint32_t off = (m < mrows && k < a.K) ? uint32_t((int64_t(m) * a.lda + k) * 8) : 0x80000000u;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rsa, DOPINF_LDS(S + q * 128), 16, off, 0, 0, 0);
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int q = wv + 4 * t;
+      const int kk = 2 * q + (lane >> 5);
+      const int c = (lane & 31) ^ ((kk & 1) << 3);
+      const int64_t k = kb + kk;
+      const uint32_t off = (k < a.K && 2 * c < a.ncol) ? uint32_t((k * a.ldb + 2 * c) * 8) : 0x80000000u;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rsb, DOPINF_LDS(S + DA + q * 128), 16, off, 0, 0, 0);
+    }
+  };
+  double shift[2];
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    const int64_t gi = i0 + 16 * wv + PM * b + (lane & 15);
+    shift[b] = (a.a_shift && gi < a.m) ? a.a_shift[gi] : 0.0;
+  }
+  dbl4 acc[2][4];
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[b][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+  if (nst > 0) issue(0);
+  for (int64_t st = 0; st < nst; ++st) {
+    wait_vmem_all();
+    barrier_only();
+    // the other buffer was read in iteration st - 1, which every wave has left
+    if (st + 1 < nst) issue(st + 1);
+    const double* SA = sm + (st & 1) * DSTAGE;
+    const double* SB = SA + DA;
+#pragma unroll
+    for (int kk = 0; kk < DK / 4; ++kk) {
+      const int k = 4 * kk + (lane >> 4);
+      double bf[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int col = 16 * j + (lane & 15);
+        bf[j] = SB[k * 64 + 2 * ((col >> 1) ^ ((k & 1) << 3)) + (col & 1)];
+      }
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int m = 16 * wv + PM * b + (lane & 15);
+        const double af = SA[m * DK + 2 * ((k >> 1) ^ ((m >> 1) & 7)) + (k & 1)] - shift[b];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[b][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, bf[j], acc[b][j], 0, 0, 0);
+      }
+    }
+  }
+  // epilogue as in row_gemm_kernel: acc[b][j][e] is C[16 wv + 64 b + (lane >> 4) + 4 e][16 j + (lane & 15)]
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t i = i0 + 16 * wv + PM * b + (lane >> 4) + 4 * e;
+      if (i >= a.m) continue;
+      const int64_t es = a.e_rows ? a.e_rows[i] : i;
+      const bool ok = es >= 0 && es < a.n_src;
+      double sc = 1.0, ad = 0.0;
+      if (ok) {
+        if (a.e_scale) sc = a.e_scale[var_of(a.vt, es)];
+        if (a.e_add) ad = a.e_add[es];
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t c = 16 * j + (lane & 15);
+        if (c >= a.ncol) continue;
+        double v = acc[b][j][e];
+        v = a.div ? v / sc : v * sc;
+        a.C[i * a.ldc + c] = ok ? v + ad : NAN;
+      }
+    }
+}
+
+// The DMA form applies to contiguous float64 rows of a tall product with
+// 33..64 columns, even K and ncol, 16-byte aligned rows and buffer ranges
+// below 2 GB.
+bool dma_eligible(const RowGemmArgs<double>& a) {
+  return !a.a_rows && a.ncol > 32 && a.ncol <= 64 && a.m >= int64_t(256) * DROWS && a.K % 2 == 0 &&
+         a.ncol % 2 == 0 && a.lda % 2 == 0 && a.ldb % 2 == 0 && (reinterpret_cast<uintptr_t>(a.A) % 16) == 0 &&
+         (reinterpret_cast<uintptr_t>(a.B) % 16) == 0 && int64_t(DROWS) * a.lda * 8 < (int64_t(1) << 31) &&
+         a.K * a.ldb * 8 < (int64_t(1) << 31);
+}
+
 template <class T, int RB>
 void launch_row_gemm_rb(hipStream_t st, const RowGemmArgs<T>& a) {
   const unsigned gx = unsigned((a.m + PM * RB - 1) / (PM * RB));
@@ -215,6 +350,13 @@ void launch_row_gemm_rb(hipStream_t st, const RowGemmArgs<T>& a) {
 // workgroup; shorter ones 64, for more workgroups.
 template <class T>
 int launch_row_gemm(hipStream_t st, const RowGemmArgs<T>& a) {
+  if constexpr (sizeof(T) == 8) {
+    if (dma_eligible(a)) {
+      row_gemm_dma_kernel<<<unsigned((a.m + DROWS - 1) / DROWS), PT, 0, st>>>(a);
+      DOPINF_LAUNCHED();
+      return DOPINF_OK;
+    }
+  }
   if (a.m >= int64_t(256) * 2 * PM)
     launch_row_gemm_rb<T, 2>(st, a);
   else

@@ -256,6 +256,8 @@ def test_fullsize_postprocess(gpu_lib, c2):
     G = dp.cross_gram(Vall, Vall)
     torch.cuda.synchronize()
     assert rel(G.cpu().numpy(), np.eye(R)) <= 1e-10
+    # the all-rows form (a kernel of its own) at the sampled rows, entry by entry
+    assert np.all(np.abs(Vall[rows_d].cpu().numpy() - Vref) <= bound)
     del Vall
 
 

@@ -130,3 +130,29 @@ def test_postprocess_bad_row_flags_and_nans(gpu_lib, c1):
     Vn, pn = V.cpu().numpy(), pred.cpu().numpy()
     assert np.all(np.isnan(Vn[[1, 3]])) and np.all(np.isnan(pn[[1, 3]]))
     assert np.all(np.isfinite(Vn[[0, 2]])) and np.all(np.isfinite(pn[[0, 2]]))
+
+
+@pytest.mark.parametrize("n,k,r", [(40_001, 130, 60), (32_768, 64, 34)])
+def test_postprocess_all_rows_tall_parity(gpu_lib, n, k, r):
+    """The basis at all rows of a tall float64 Q (the LDS-DMA form of the
+    row product: >= 32,768 rows, 33 <= r <= 64, even k), entry by entry
+    against the oracle: a ragged last row tile (40,001 rows), a ragged last
+    K stage (k = 130), variable boundaries inside row tiles."""
+    import torch
+    dp = gpu_lib
+    rng = np.random.default_rng(n + k + r)
+    Q = rng.standard_normal((n, k)) * rng.uniform(0.5, 2.0, k) + rng.standard_normal((n, 1))
+    var_rows = [0, n // 3 + 5, 2 * n // 3 - 7, n]
+    Tr = rng.standard_normal((k, r)) / np.sqrt(k)
+    Qd = dev(Q)
+    mean, scale, _ = dp.preprocess(Qd, var_rows)
+    V, _, info = dp.postprocess(Qd, dev(Tr), rows=None, m=n, mean=mean, scale=scale, var_rows=var_rows)
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0
+    s_rows = np.repeat(scale.cpu().numpy(), np.diff(var_rows))
+    Qs = orc.apply_statistics(Q, mean.cpu().numpy(), s_rows)
+    Vref = orc.basis_rows(Qs, Tr, np.arange(n))
+    gam = k * U / (1 - k * U)
+    bound = 2 * gam * (np.abs(Qs) @ np.abs(Tr)) + 4 * U * np.abs(Vref)
+    Vg = V.cpu().numpy()
+    assert np.all(np.abs(Vg - Vref) <= bound), float(np.max(np.abs(Vg - Vref) / bound))
