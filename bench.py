@@ -591,8 +591,8 @@ def main():
                          "(each prints its JSON object; for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the multi-GPU sharding is "
-              f"described in DESIGN.md but not built).", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the row sharding over "
+              f"several GPUs is designed but not built).", file=sys.stderr)
         sys.exit(2)
 
     import torch
