@@ -1545,15 +1545,17 @@ void destroy_pool_streams() {
   if (have_dev) (void)hipSetDevice(cur);
 }
 
-int infer_streams(InferPlan& P) {
-  if (P.n_r < 2 || !P.gst.empty()) return DOPINF_OK;
+// Up to `want` streams of the calling thread's pool on the current device,
+// at most (hardware queues - 1); *got receives how many.
+int pool_streams_impl(int want, std::vector<hipStream_t>*& out, int* got) {
+  *got = 0;
   int hwq = 4;
   if (const char* e = std::getenv("GPU_MAX_HW_QUEUES")) {
     const int v = std::atoi(e);
     if (v >= 1) hwq = v;
   }
-  const int ns = std::min(P.n_r, hwq - 1);
-  if (ns < 2) return DOPINF_OK;  // no fork: the groups run on the caller's stream
+  const int ns = std::min(want, hwq - 1);
+  if (ns < 1) return DOPINF_OK;
   int dev = 0;
   DOPINF_HIP(hipGetDevice(&dev));
   static thread_local std::vector<std::vector<hipStream_t>> pool;
@@ -1568,6 +1570,19 @@ int infer_streams(InferPlan& P) {
     (void)registered;
     g_all_streams.emplace_back(dev, x);
   }
+  out = &mine;
+  *got = ns;
+  return DOPINF_OK;
+}
+
+int infer_streams(InferPlan& P) {
+  if (P.n_r < 2 || !P.gst.empty()) return DOPINF_OK;
+  std::vector<hipStream_t>* pool = nullptr;
+  int ns = 0;
+  const int rc = pool_streams_impl(P.n_r, pool, &ns);
+  if (rc) return rc;
+  if (ns < 2) return DOPINF_OK;  // no fork: the groups run on the caller's stream
+  std::vector<hipStream_t>& mine = *pool;
   DOPINF_HIP(hipEventCreateWithFlags(&P.fork, hipEventDisableTiming));
   for (int g = 0; g < P.n_r; ++g) {
     // rank by decreasing r (ties: lower index first)
@@ -1825,6 +1840,17 @@ int infer_enqueue(hipStream_t st, const InferPlan& P, const double* Qhat, int64_
 }
 
 }  // namespace
+
+// The pool streams for other grouped launches of the library (the rollout
+// groups): up to `want` of them into out[]; returns how many (0 on error,
+// with the error message set).
+int pool_streams(int want, hipStream_t* out) {
+  std::vector<hipStream_t>* pool = nullptr;
+  int ns = 0;
+  if (pool_streams_impl(want, pool, &ns) != DOPINF_OK) return 0;
+  for (int i = 0; i < ns; ++i) out[i] = (*pool)[i];
+  return ns;
+}
 
 // Candidate block-column widths (outer, inner; inner 0: one level), for the
 // beta2-group Cholesky and for the triangular solves with its factor.

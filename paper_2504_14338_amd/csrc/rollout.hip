@@ -565,6 +565,8 @@ extern "C" size_t dopinf_traj_offset(int n_r, const int* r_list_h, int n_pairs, 
 }
 
 namespace dopinf {
+int pool_streams(int want, hipStream_t* out);
+
 namespace {
 
 // Team form for group of size r with n_pairs items: co-resident teams of
@@ -624,22 +626,71 @@ int check_rollout_args(int n_r, const int* r_list_h, int n_pairs, const double* 
 
 // The launches of a rollout call on a checked argument set, with its scratch
 // (dopinf_rollout_workspace bytes) at `ws`.
+// Events of one call's group fork, destroyed when the call returns (a
+// recorded event is released once it completes).
+struct ForkEvents {
+  std::vector<hipEvent_t> ev;
+  ~ForkEvents() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  }
+  int make(hipEvent_t* out) {
+    DOPINF_HIP(hipEventCreateWithFlags(out, hipEventDisableTiming));
+    ev.push_back(*out);
+    return DOPINF_OK;
+  }
+};
+
+// fork: with several reduced sizes each group's launches go to a library
+// stream of its own (forked from st, joined back before the selection), so
+// the groups' rollouts overlap (a stream capture turns this into parallel
+// graph branches); the allocation-free entry point keeps everything on st,
+// and so do calls with a group in the cooperative team form.
 int rollout_launch(hipStream_t st, int n_r, const int* r_list_h, int n_pairs, const double* O,
                    const double* Qhat, int64_t ldqh, int64_t k_train, int n_states, double max_growth,
                    unsigned flags, const int* solve_status, double* traj, double* train_err, double* growth,
                    int* outcome, int* best, void* ws, size_t ws_bytes, double dt = 0.0,
-                   const double* q0 = nullptr) {
+                   const double* q0 = nullptr, bool fork = true) {
   int dev = 0, maxlds = 0;
   DOPINF_HIP(hipGetDevice(&dev));
   DOPINF_HIP(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  // every argument error is raised before anything is enqueued; groups that
+  // run as cooperative teams keep the caller's stream (the runtime runs
+  // cooperative launches one at a time, and two partly resident team grids
+  // must never wait on each other)
+  for (int g = 0; g < n_r; ++g) {
+    const int r = r_list_h[g];
+    const size_t smem = size_t(ncols(r) + (dt > 0.0 ? 4 : 2) * r) * sizeof(double) +
+                        size_t(2 * nquad(r)) * sizeof(unsigned short) + 64;
+    DOPINF_REQUIRE(smem + 1024 <= size_t(maxlds), "r too large for the rollout workgroup");
+    if (team_size(r, n_pairs, flags, dt > 0.0) > 0) fork = false;
+  }
+  hipStream_t gs[8];
+  int ns = 0;
+  ForkEvents fe;
+  if (fork && n_r >= 2) {
+    ns = pool_streams(std::min(n_r, 8), gs);
+    if (ns >= 2) {
+      hipEvent_t f = nullptr;
+      int rc = fe.make(&f);
+      if (rc) return rc;
+      DOPINF_HIP(hipEventRecord(f, st));
+      for (int i = 0; i < ns; ++i) DOPINF_HIP(hipStreamWaitEvent(gs[i], f, 0));
+    } else {
+      ns = 0;
+    }
+  }
   Carver c(ws, ws_bytes);
   for (int g = 0; g < n_r; ++g) {
     const int r = r_list_h[g];
+    // the largest groups get a stream each, the smallest share the last one
+    int rank = 0;
+    for (int q = 0; q < n_r; ++q) rank += (r_list_h[q] > r) || (r_list_h[q] == r && q < g);
+    const hipStream_t sg = ns ? gs[std::min(rank, ns - 1)] : st;
     const int64_t s = nquad(r), d = ncols(r);
     const RollWs w = carve_group(c, r, n_pairs);
     double* mean = w.mean;
     double* maxdev = w.maxdev;
-    train_stats_kernel<<<r, 256, 0, st>>>(Qhat, ldqh, k_train, mean, maxdev);
+    train_stats_kernel<<<r, 256, 0, sg>>>(Qhat, ldqh, k_train, mean, maxdev);
     DOPINF_LAUNCHED();
     const bool rk4 = dt > 0.0;
     const size_t smem =
@@ -675,7 +726,7 @@ int rollout_launch(hipStream_t st, int n_r, const int* r_list_h, int n_pairs, co
       const int tnj = (d <= 64 * 32) ? 32 : 64;
       const size_t tsm = size_t(int64_t(tnj) * 64 + (rk4 ? 3 : 1) * r) * sizeof(double) +
                          size_t(2 * s) * sizeof(unsigned short) + 64;
-      zero_u32_kernel<<<(n_pairs + 1 + 255) / 256, 256, 0, st>>>(w.words, n_pairs + 1);
+      zero_u32_kernel<<<(n_pairs + 1 + 255) / 256, 256, 0, sg>>>(w.words, n_pairs + 1);
       DOPINF_LAUNCHED();
       TeamArgs ta{};
       ta.a = ra;
@@ -693,7 +744,7 @@ int rollout_launch(hipStream_t st, int n_r, const int* r_list_h, int n_pairs, co
               : ((tnj == 32) ? reinterpret_cast<const void*>(rollout_team_kernel<32, false>)
                              : reinterpret_cast<const void*>(rollout_team_kernel<64, false>));
       const unsigned tgrid = unsigned(8 * P * ((n_pairs + 7) / 8));
-      if (hipLaunchCooperativeKernel(kern, dim3(tgrid), dim3(TNT), args, unsigned(tsm), st) ==
+      if (hipLaunchCooperativeKernel(kern, dim3(tgrid), dim3(TNT), args, unsigned(tsm), sg) ==
           hipSuccess)
         launched = true;
       else
@@ -712,16 +763,23 @@ int rollout_launch(hipStream_t st, int n_r, const int* r_list_h, int n_pairs, co
       ra.queue = nullptr;
       if (n_left > resident) {
         ra.queue = w.words + n_pairs + 1;
-        zero_u32_kernel<<<1, 64, 0, st>>>(ra.queue, 1);
+        zero_u32_kernel<<<1, 64, 0, sg>>>(ra.queue, 1);
         DOPINF_LAUNCHED();
         grid = resident;
       }
       if (rk4)
-        rollout_kernel<true><<<grid, RT, smem, st>>>(ra);
+        rollout_kernel<true><<<grid, RT, smem, sg>>>(ra);
       else
-        rollout_kernel<false><<<grid, RT, smem, st>>>(ra);
+        rollout_kernel<false><<<grid, RT, smem, sg>>>(ra);
       DOPINF_LAUNCHED();
     }
+  }
+  for (int i = 0; i < ns; ++i) {
+    hipEvent_t j = nullptr;
+    int rc = fe.make(&j);
+    if (rc) return rc;
+    DOPINF_HIP(hipEventRecord(j, gs[i]));
+    DOPINF_HIP(hipStreamWaitEvent(st, j, 0));
   }
   select_kernel<<<n_r, 64, 0, st>>>(train_err, outcome, n_pairs, best);
   DOPINF_LAUNCHED();
@@ -807,5 +865,5 @@ extern "C" int dopinf_rollout_noalloc(void* stream, int n_r, const int* r_list_h
   if (rc) return rc;
   return rollout_launch(static_cast<hipStream_t>(stream), n_r, r_list_h, n_pairs, O, Qhat, ldqh, k_train, n_states,
                         max_growth, flags, solve_status, traj, train_err, growth, outcome, best, ws,
-                        dopinf::kRolloutScratchBytes);
+                        dopinf::kRolloutScratchBytes, 0.0, nullptr, false);
 }
