@@ -311,6 +311,17 @@ struct TeamArgs {
   int* abort_flag;
 };
 
+// The team groups of one call (reduced sizes with the same operator width
+// class) in one cooperative launch: group g owns workgroups
+// [off[g], off[g + 1]), a multiple of 8 each.
+constexpr int kMaxTeamGroups = 8;
+struct TeamSet {
+  TeamArgs g[kMaxTeamGroups];
+  int off[kMaxTeamGroups + 1];
+  int n_g;
+};
+static_assert(sizeof(TeamSet) <= 4096, "kernel arguments are limited to 4 KB");
+
 __global__ void zero_u32_kernel(unsigned* p, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0u;
@@ -321,16 +332,21 @@ __global__ void zero_u32_kernel(unsigned* p, int n) {
 // passes one team barrier (the exchange slots alternate with the barrier
 // count), then every member forms the next stage state from the full vector.
 template <int TNJ, bool RK4>
-__global__ __launch_bounds__(TNT) void rollout_team_kernel(TeamArgs ta) {
+__global__ __launch_bounds__(TNT) void rollout_team_kernel(TeamSet ts) {
   extern __shared__ double sm[];
+  int grp = 0;
+  while (grp + 1 < ts.n_g && int(blockIdx.x) >= ts.off[grp + 1]) ++grp;
+  const TeamArgs& ta = ts.g[grp];
   const RollArgs& a = ta.a;
   // each team on one XCD: workgroup b runs on XCD b % 8 (the dispatcher
-  // deals workgroups to the 8 XCDs in turn), so team i takes workgroups
-  // 8 (P (i / 8) + m) + i % 8, m < P, and its counter barrier and exchange
-  // stay inside one L2 (1.06 against 1.35 us per barrier across XCDs);
-  // workgroups past the last team leave at once
-  const int item = (int(blockIdx.x >> 3) / ta.P) * 8 + int(blockIdx.x & 7);
-  const int pm = int(blockIdx.x >> 3) % ta.P;
+  // deals workgroups to the 8 XCDs in turn), so team i of a group takes its
+  // workgroups 8 (P (i / 8) + m) + i % 8, m < P (the group's first workgroup
+  // is a multiple of 8), and its counter barrier and exchange stay inside one
+  // L2 (1.06 against 1.35 us per barrier across XCDs); workgroups past the
+  // group's last team leave at once
+  const int lb = int(blockIdx.x) - ts.off[grp];
+  const int item = ((lb >> 3) / ta.P) * 8 + (lb & 7);
+  const int pm = (lb >> 3) % ta.P;
   if (item >= ta.n_items) return;
   const int r = a.r;
   const int64_t s = a.s, d = a.d;
@@ -680,6 +696,39 @@ int rollout_launch(hipStream_t st, int n_r, const int* r_list_h, int n_pairs, co
     }
   }
   Carver c(ws, ws_bytes);
+  struct Pending {
+    TeamArgs ta;
+    size_t smem, tsm;
+    RollWs w;
+    hipStream_t sg;
+  };
+  std::vector<Pending> teams32, teams64;
+  // the one-workgroup form: more candidates than resident workgroups take a
+  // persistent grid with a work counter, else one workgroup per candidate
+  auto one_wg_launch = [&](RollArgs ra, size_t smem, const RollWs& w, hipStream_t sg) -> int {
+    const bool rk4 = dt > 0.0;
+    const void* one_wg = rk4 ? reinterpret_cast<const void*>(rollout_kernel<true>)
+                             : reinterpret_cast<const void*>(rollout_kernel<false>);
+    int per_cu = 0, ncu = 0;
+    DOPINF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, one_wg, RT, smem));
+    DOPINF_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    const int resident = std::max(1, per_cu) * std::max(1, ncu);
+    int grid = n_pairs;
+    ra.n_items = n_pairs;
+    ra.queue = nullptr;
+    if (n_pairs > resident) {
+      ra.queue = w.words + n_pairs + 1;
+      zero_u32_kernel<<<1, 64, 0, sg>>>(ra.queue, 1);
+      DOPINF_LAUNCHED();
+      grid = resident;
+    }
+    if (rk4)
+      rollout_kernel<true><<<grid, RT, smem, sg>>>(ra);
+    else
+      rollout_kernel<false><<<grid, RT, smem, sg>>>(ra);
+    DOPINF_LAUNCHED();
+    return DOPINF_OK;
+  };
   for (int g = 0; g < n_r; ++g) {
     const int r = r_list_h[g];
     // the largest groups get a stream each, the smallest share the last one
@@ -721,57 +770,65 @@ int rollout_launch(hipStream_t st, int n_r, const int* r_list_h, int n_pairs, co
     ra.growth = growth + g * n_pairs;
     ra.outcome = outcome + g * n_pairs;
     const int P = team_size(r, n_pairs, flags, rk4);
-    bool launched = false;
     if (P > 0) {
       const int tnj = (d <= 64 * 32) ? 32 : 64;
-      const size_t tsm = size_t(int64_t(tnj) * 64 + (rk4 ? 3 : 1) * r) * sizeof(double) +
-                         size_t(2 * s) * sizeof(unsigned short) + 64;
       zero_u32_kernel<<<(n_pairs + 1 + 255) / 256, 256, 0, sg>>>(w.words, n_pairs + 1);
       DOPINF_LAUNCHED();
-      TeamArgs ta{};
-      ta.a = ra;
-      ta.P = P;
-      ta.n_items = n_pairs;
-      ta.xbuf = w.xbuf;
-      ta.bar = w.words;
-      ta.abort_flag = reinterpret_cast<int*>(w.words + n_pairs);
-      void* args[] = {&ta};
-      // co-residency of the team members is what the counter barrier needs;
-      // if the runtime cannot promise it, the one-workgroup form runs instead
-      const void* kern =
-          rk4 ? ((tnj == 32) ? reinterpret_cast<const void*>(rollout_team_kernel<32, true>)
-                             : reinterpret_cast<const void*>(rollout_team_kernel<64, true>))
-              : ((tnj == 32) ? reinterpret_cast<const void*>(rollout_team_kernel<32, false>)
-                             : reinterpret_cast<const void*>(rollout_team_kernel<64, false>));
-      const unsigned tgrid = unsigned(8 * P * ((n_pairs + 7) / 8));
-      if (hipLaunchCooperativeKernel(kern, dim3(tgrid), dim3(TNT), args, unsigned(tsm), sg) ==
-          hipSuccess)
-        launched = true;
-      else
-        (void)hipGetLastError();
+      Pending pg{};
+      pg.ta.a = ra;
+      pg.ta.P = P;
+      pg.ta.n_items = n_pairs;
+      pg.ta.xbuf = w.xbuf;
+      pg.ta.bar = w.words;
+      pg.ta.abort_flag = reinterpret_cast<int*>(w.words + n_pairs);
+      pg.smem = smem;
+      pg.tsm = size_t(int64_t(tnj) * 64 + (rk4 ? 3 : 1) * r) * sizeof(double) +
+               size_t(2 * s) * sizeof(unsigned short) + 64;
+      pg.w = w;
+      pg.sg = sg;
+      (tnj == 32 ? teams32 : teams64).push_back(pg);
+    } else {
+      int rc = one_wg_launch(ra, smem, w, sg);
+      if (rc) return rc;
     }
-    if (!launched) {
-      const int n_left = n_pairs;
-      // more candidates than resident workgroups: a persistent grid with a
-      // work counter; else one workgroup per candidate
-      int per_cu = 0, ncu = 0;
-      DOPINF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, one_wg, RT, smem));
-      DOPINF_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-      const int resident = std::max(1, per_cu) * std::max(1, ncu);
-      int grid = n_left;
-      ra.n_items = n_left;
-      ra.queue = nullptr;
-      if (n_left > resident) {
-        ra.queue = w.words + n_pairs + 1;
-        zero_u32_kernel<<<1, 64, 0, sg>>>(ra.queue, 1);
-        DOPINF_LAUNCHED();
-        grid = resident;
+  }
+  // the team groups of each operator width class in one cooperative launch
+  // (the runtime runs cooperative launches one after the other); if the
+  // runtime cannot make a whole set co-resident, group by group, and a group
+  // it cannot place runs in the one-workgroup form
+  for (int cls = 0; cls < 2; ++cls) {
+    const std::vector<Pending>& v = cls ? teams64 : teams32;
+    const void* kern = dt > 0.0 ? (cls ? reinterpret_cast<const void*>(rollout_team_kernel<64, true>)
+                                       : reinterpret_cast<const void*>(rollout_team_kernel<32, true>))
+                                : (cls ? reinterpret_cast<const void*>(rollout_team_kernel<64, false>)
+                                       : reinterpret_cast<const void*>(rollout_team_kernel<32, false>));
+    for (size_t c0 = 0; c0 < v.size(); c0 += kMaxTeamGroups) {
+      const size_t c1 = std::min(v.size(), c0 + kMaxTeamGroups);
+      auto launch_set = [&](size_t a0, size_t a1) -> bool {
+        TeamSet ts{};
+        ts.n_g = int(a1 - a0);
+        int off = 0;
+        size_t tsm = 0;
+        for (size_t q = a0; q < a1; ++q) {
+          ts.g[q - a0] = v[q].ta;
+          ts.off[q - a0] = off;
+          off += 8 * v[q].ta.P * ((v[q].ta.n_items + 7) / 8);
+          tsm = std::max(tsm, v[q].tsm);
+        }
+        ts.off[a1 - a0] = off;
+        void* args[] = {&ts};
+        if (hipLaunchCooperativeKernel(kern, dim3(unsigned(off)), dim3(TNT), args, unsigned(tsm), st) ==
+            hipSuccess)
+          return true;
+        (void)hipGetLastError();
+        return false;
+      };
+      if (launch_set(c0, c1)) continue;
+      for (size_t q = c0; q < c1; ++q) {
+        if (c1 - c0 > 1 && launch_set(q, q + 1)) continue;
+        int rc = one_wg_launch(v[q].ta.a, v[q].smem, v[q].w, v[q].sg);
+        if (rc) return rc;
       }
-      if (rk4)
-        rollout_kernel<true><<<grid, RT, smem, sg>>>(ra);
-      else
-        rollout_kernel<false><<<grid, RT, smem, sg>>>(ra);
-      DOPINF_LAUNCHED();
     }
   }
   for (int i = 0; i < ns; ++i) {

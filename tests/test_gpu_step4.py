@@ -365,3 +365,38 @@ def test_full_horizon_many_candidates_match_oracle(gpu_lib, r):
         assert np.allclose(a, b, rtol=1e-9, atol=0), key
     assert np.array_equal(team["outcome"].cpu().numpy(), one["outcome"].cpu().numpy())
     assert team["best"].item() == one["best"].item()
+
+
+def test_rollout_teams_of_both_operator_widths(gpu_lib):
+    """Team rollouts of two reduced sizes whose operators take different
+    register widths per lane (r = 12: d = 91; r = 64: d = 2145 > 2048), so
+    one call makes two cooperative launches, each a set of team groups, against
+    the oracle's rollouts of the same operators."""
+    import torch
+    dp = gpu_lib
+    rng = np.random.default_rng(64)
+    k, rmax = 300, 64
+    # a damped linear system observed in 64 coordinates
+    A = rng.standard_normal((rmax, rmax))
+    A *= 0.97 / np.max(np.abs(np.linalg.eigvals(A)))
+    Qh = np.zeros((rmax, k))
+    Qh[:, 0] = rng.standard_normal(rmax)
+    for t in range(1, k):
+        Qh[:, t] = A @ Qh[:, t - 1] + 1e-3 * rng.standard_normal(rmax)
+    Qhat = dev(Qh)
+    r_list = [12, 64]
+    O, status, views = dp.infer(Qhat, r_list, [1e-2], [1e-1])
+    n_states = 600
+    out = dp.rollout(O, Qhat, r_list, 1, n_states, max_growth=1.2, solve_status=status, keep_traj=True, full=True)
+    torch.cuda.synchronize()
+    oc = out["outcome"].cpu().numpy()
+    for g, r in enumerate(r_list):
+        Og = views[g][0].cpu().numpy()
+        Qt = orc.rollout(Og, r, Qh[:r, 0], n_states)
+        fin, e, gg, ok = orc.score(Qt, Qh[:r], k, 1.2)
+        traj = out["traj_views"][g][0].cpu().numpy().T
+        if fin:
+            assert np.max(np.abs(traj - Qt)) <= 1e-9 * np.max(np.abs(Qt)), r
+            assert (oc[g] == dp.ITEM_PASS) == ok
+        else:
+            assert oc[g] == dp.ITEM_NONFINITE
