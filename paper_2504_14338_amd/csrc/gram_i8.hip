@@ -314,7 +314,8 @@ __global__ __launch_bounds__(MT, 1) void gram_i8_kernel(MmaArgs g) {
     unsigned char* S = smem + (st % NSTAGE) * STAGE;
     const size_t blk = size_t(b_lo + st);
 #pragma unroll
-    for (int q = w; q < CHUNKS; q += MT / 64) {
+    for (int t = 0; t < CHUNKS / (MT / 64); ++t) {
+      const int q = w + (MT / 64) * t;
       const bool isa = q < NSL * (PA_BYTES / 1024);
       const int qa = isa ? q : q - NSL * (PA_BYTES / 1024);
       const int sl = isa ? qa / (PA_BYTES / 1024) : qa / (PB_BYTES / 1024);

@@ -535,7 +535,8 @@ __global__ __launch_bounds__(WMT, 1) void gram_wide_kernel(WideArgs g) {
     unsigned char* S = smem + (st & 1) * Gm::STAGE;
     const size_t blk = size_t(b_lo + st);
 #pragma unroll
-    for (int q = w; q < Gm::CHUNKS; q += WMT / 64) {
+    for (int t = 0; t < Gm::CHUNKS / (WMT / 64); ++t) {
+      const int q = w + (WMT / 64) * t;
       const bool isa = q < NPART * (Gm::PA / 1024);
       const int qa = isa ? q : q - NPART * (Gm::PA / 1024);
       const int pt = isa ? qa / (Gm::PA / 1024) : qa / (Gm::PB / 1024);
