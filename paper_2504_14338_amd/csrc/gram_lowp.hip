@@ -215,6 +215,7 @@ struct PackedGeom {
   static constexpr int CHUNKS = PANEL / 1024;       // 1 KB LDS-DMA chunks per panel part
   static constexpr int STAGE = 2 * NPART * PANEL;   // A and B panels, all parts
   static constexpr int NSTAGE = 2;                  // LDS stages (loads of one in flight)
+  static_assert(CHUNKS % 4 == 0, "chunks per wave");
 };
 
 // Blocks of 16 x 16 that wave w (0..3) computes in a diagonal tile of the
@@ -281,7 +282,8 @@ __device__ __forceinline__ void packed_tile(const MmaArgs& g, int64_t b_lo, int6
         unsigned char* dst = S + (side * NPART + part) * Gm::PANEL;
         // the wave's share of the panel's chunks
 #pragma unroll
-        for (int q = w; q < Gm::CHUNKS; q += 4) {
+        for (int t = 0; t < Gm::CHUNKS / 4; ++t) {
+          const int q = w + 4 * t;
           const __amdgpu_buffer_rsrc_t rs = span_rsrc(src + q * 1024, 1024);
           __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, DOPINF_LDS(dst + q * 1024), 16, voff, 0, 0, 0);
         }
