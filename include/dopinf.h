@@ -10,7 +10,8 @@
  *    passed as void*; NULL means the default stream).  The library never
  *    allocates or frees device memory: scratch comes from a caller-provided
  *    workspace `ws` of at least the size returned by the matching
- *    `*_workspace` query, aligned to 256 bytes.
+ *    `*_workspace` query, aligned to 256 bytes (a misaligned workspace
+ *    returns DOPINF_E_WORKSPACE with nothing enqueued).
  *  - Calls only enqueue work on `stream` and return; they do not synchronize
  *    unless documented (dopinf_reduce with r_req == 0).  Separate streams may
  *    be used concurrently with separate workspaces.
@@ -38,7 +39,7 @@ extern "C" {
 #define DOPINF_OK 0
 #define DOPINF_E_ARG 1         /* invalid argument; nothing enqueued          */
 #define DOPINF_E_HIP 2         /* a HIP runtime call or launch failed         */
-#define DOPINF_E_WORKSPACE 3   /* workspace missing or too small               */
+#define DOPINF_E_WORKSPACE 3   /* workspace missing, too small or not 256-byte aligned */
 #define DOPINF_E_RANK 4        /* lambda_r <= 0 or r > k                       */
 #define DOPINF_E_NOTSPD 5      /* non-positive Cholesky pivot                  */
 #define DOPINF_E_NONFINITE 6   /* NaN/Inf in data or results                   */

@@ -1192,6 +1192,7 @@ extern "C" int dopinf_closure_fit(void* stream, int r, const double* X, const do
                                   int batch, double lr, double beta1, double beta2, double eps, float* params,
                                   double* norm, float* adam_m, float* adam_v, float* loss_log, void* ws,
                                   size_t ws_bytes) {
+  DOPINF_REQUIRE_WS_ALIGNED(ws);
   DOPINF_REQUIRE(X && Y && params && norm && adam_m && adam_v, "NULL argument");
   DOPINF_REQUIRE(r >= 1 && r <= 64, "closure supports 1 <= r <= 64");
   DOPINF_REQUIRE(N >= 1 && epochs >= 0 && batch >= 1 && batch <= BMAX, "need N >= 1, epochs >= 0, 1 <= batch <= 256");
@@ -1245,6 +1246,7 @@ extern "C" int dopinf_closure_norms(void* stream, int r, const double* X, const 
 
 extern "C" int dopinf_closure_grad(void* stream, int r, const float* params, const double* norm, const double* X,
                                    const double* Y, int64_t N, float* grad, float* loss, void* ws, size_t ws_bytes) {
+  DOPINF_REQUIRE_WS_ALIGNED(ws);
   DOPINF_REQUIRE(params && norm && X && Y && grad && loss, "NULL argument");
   DOPINF_REQUIRE(r >= 1 && r <= 64 && N >= 1 && N <= BMAX, "need 1 <= r <= 64 and 1 <= N <= 256");
   const size_t need = dopinf_closure_fit_workspace(r, N);
@@ -1275,6 +1277,7 @@ extern "C" size_t dopinf_closure_eval_workspace(int64_t N) { return N > 0 ? roun
 
 extern "C" int dopinf_closure_eval(void* stream, int r, const float* params, const double* norm, const double* X,
                                    int64_t N, double* G, double* gmax, void* ws, size_t ws_bytes) {
+  DOPINF_REQUIRE_WS_ALIGNED(ws);
   DOPINF_REQUIRE(params && norm && X && (G || gmax), "NULL argument");
   DOPINF_REQUIRE(r >= 1 && r <= 64 && N >= 1, "need 1 <= r <= 64, N >= 1");
   if (!ws || ws_bytes < dopinf_closure_eval_workspace(N)) return fail(DOPINF_E_WORKSPACE, "workspace too small");
@@ -1297,6 +1300,7 @@ extern "C" int dopinf_closure_rollout(void* stream, int r, const double* O, cons
                                       double threshold, const double* q0, int64_t M, int n_states, const double* Qref,
                                       int64_t ldref, int64_t k_ref, double max_growth, double* traj, double* err,
                                       double* growth, int* outcome, int* fallback_at, void* ws, size_t ws_bytes) {
+  DOPINF_REQUIRE_WS_ALIGNED(ws);
   DOPINF_REQUIRE(O && q0 && Qref && err && growth && outcome && fallback_at, "NULL argument");
   DOPINF_REQUIRE(threshold <= 0.0 || (params && norm), "params and norm are needed when the closure is on");
   DOPINF_REQUIRE(r >= 1 && r <= 64 && M >= 1 && n_states >= 1 && k_ref >= 1 && ldref >= k_ref && max_growth > 0,

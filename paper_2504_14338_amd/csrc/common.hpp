@@ -46,6 +46,15 @@ bool persisted();  // DOPINF_TUNE_CACHE names a cache file
     if (!(cond)) return ::dopinf::fail(DOPINF_E_ARG, __VA_ARGS__);              \
   } while (0)
 
+// Workspaces must be 256-byte aligned: blocks carved from them feed 16-byte
+// vector and LDS-DMA loads and 8-byte atomics.  Checked before anything else,
+// so a misaligned workspace returns with nothing enqueued.
+#define DOPINF_REQUIRE_WS_ALIGNED(ws)                                                    \
+  do {                                                                                   \
+    if (reinterpret_cast<uintptr_t>(ws) % 256 != 0)                                      \
+      return ::dopinf::fail(DOPINF_E_WORKSPACE, "workspace must be 256-byte aligned");   \
+  } while (0)
+
 // ---- workspace carving -----------------------------------------------------
 
 // Bump allocator over a caller-provided workspace; every block 256-B aligned.

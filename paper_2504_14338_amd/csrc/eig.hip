@@ -1223,6 +1223,7 @@ int form_qhat_internal(hipStream_t st, const double* Z, int64_t k, int r, const 
 extern "C" int dopinf_reduce(void* stream, const double* D, int64_t k, int64_t ldd, int r_req, double tau,
                              int r_max, int* r_out_h, double* lambda, double* Tr, int64_t ldtr, double* Qhat,
                              int64_t ldqh, int* info, void* ws, size_t ws_bytes) {
+  DOPINF_REQUIRE_WS_ALIGNED(ws);
   DOPINF_REQUIRE(D && lambda && Qhat && info, "D, lambda, Qhat and info must be non-NULL");
   DOPINF_REQUIRE(k >= 1 && ldd >= k && ldqh >= k, "need k >= 1, ldd >= k, ldqh >= k");
   DOPINF_REQUIRE(k <= 65536, "k > 65536 is not supported");

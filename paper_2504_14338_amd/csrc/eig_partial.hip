@@ -293,6 +293,7 @@ extern "C" size_t dopinf_reduce_topr_workspace(int64_t k, int r) {
 extern "C" int dopinf_reduce_topr(void* stream, const double* D, int64_t k, int64_t ldd, int r, double* lambda,
                                   double* Tr, int64_t ldtr, double* Qhat, int64_t ldqh, int* info, int* iters_h,
                                   void* ws, size_t ws_bytes) {
+  DOPINF_REQUIRE_WS_ALIGNED(ws);
   DOPINF_REQUIRE(D && lambda && Qhat && info, "D, lambda, Qhat and info must be non-NULL");
   DOPINF_REQUIRE(k >= 1 && k <= 65536 && ldd >= k && ldqh >= k, "need 1 <= k <= 65536, ldd >= k, ldqh >= k");
   DOPINF_REQUIRE(r >= 1 && r <= k, "need 1 <= r <= k");

@@ -582,6 +582,7 @@ extern "C" size_t dopinf_gram_workspace(int dtype, int algo, int64_t n, int64_t 
 extern "C" int dopinf_gram(void* stream, int dtype, int algo, const void* Q, int64_t n, int64_t k, int64_t ldq,
                            const double* mean, const double* scale, int nvars, const int64_t* var_rows_h,
                            double* D, int64_t ldd, void* ws, size_t ws_bytes) {
+  DOPINF_REQUIRE_WS_ALIGNED(ws);
   DOPINF_REQUIRE(Q && D, "Q and D must be non-NULL");
   DOPINF_REQUIRE(n >= 1 && k >= 1 && ldq >= k && ldd >= k, "need n >= 1, k >= 1, ldq >= k, ldd >= k");
   DOPINF_REQUIRE(k <= (int64_t(1) << 20), "k too large");
@@ -656,6 +657,7 @@ extern "C" int dopinf_cross_gram(void* stream, const double* X, int64_t ldx, con
                                  int64_t n, int64_t mx, int64_t my, const double* mean, const double* scale,
                                  int nvars, const int64_t* var_rows_h, double* C, int64_t ldc, void* ws,
                                  size_t ws_bytes) {
+  DOPINF_REQUIRE_WS_ALIGNED(ws);
   DOPINF_REQUIRE(X && Y && C, "X, Y and C must be non-NULL");
   DOPINF_REQUIRE(n >= 1 && mx >= 1 && my >= 1 && ldx >= mx && ldy >= my && ldc >= my,
                  "need n, mx, my >= 1 and ldx >= mx, ldy >= my, ldc >= my");

@@ -1970,6 +1970,7 @@ extern "C" size_t dopinf_infer_workspace(int64_t k, int n_r, const int* r_list_h
 extern "C" int dopinf_infer(void* stream, const double* Qhat, int64_t ldqh, int64_t k, int n_r, const int* r_list_h,
                             int n_pairs, const double* beta1_h, const double* beta2_h, double* O, int* status,
                             void* ws, size_t ws_bytes) {
+  DOPINF_REQUIRE_WS_ALIGNED(ws);
   DOPINF_REQUIRE(Qhat && O && status, "NULL argument");
   InferPlan P;
   int rc = infer_plan(k, ldqh, n_r, r_list_h, n_pairs, beta1_h, beta2_h, ws_bytes, ws, P);
@@ -1989,6 +1990,7 @@ extern "C" size_t dopinf_infer_continuous_workspace(int64_t k, int n_r, const in
 extern "C" int dopinf_infer_continuous(void* stream, const double* Qhat, int64_t ldqh, int64_t k, double dt, int n_r,
                                        const int* r_list_h, int n_pairs, const double* beta1_h,
                                        const double* beta2_h, double* O, int* status, void* ws, size_t ws_bytes) {
+  DOPINF_REQUIRE_WS_ALIGNED(ws);
   DOPINF_REQUIRE(Qhat && O && status, "NULL argument");
   DOPINF_REQUIRE(dt > 0.0 && std::isfinite(dt), "dt must be finite and > 0");
   InferPlan P;
@@ -2004,6 +2006,7 @@ extern "C" int dopinf_infer_continuous(void* stream, const double* Qhat, int64_t
 extern "C" int dopinf_autotune_infer(void* stream, const double* Qhat, int64_t ldqh, int64_t k, int n_r,
                                      const int* r_list_h, int n_pairs, const double* beta1_h, const double* beta2_h,
                                      double* O, int* status, void* ws, size_t ws_bytes, float* times_h) {
+  DOPINF_REQUIRE_WS_ALIGNED(ws);
   DOPINF_REQUIRE(Qhat && O && status, "NULL argument");
   InferPlan P;
   int rc = infer_plan(k, ldqh, n_r, r_list_h, n_pairs, beta1_h, beta2_h, ws_bytes, ws, P);
@@ -2042,6 +2045,7 @@ extern "C" int dopinf_sweep_create(void* stream, const double* Qhat, int64_t ldq
                                    size_t ws_bytes, dopinf_sweep_t* sweep_out) {
   DOPINF_REQUIRE(sweep_out, "NULL sweep_out");
   *sweep_out = nullptr;
+  DOPINF_REQUIRE_WS_ALIGNED(ws);
   DOPINF_REQUIRE(stream, "the null stream cannot be captured; pass a stream created by the caller");
   DOPINF_REQUIRE(Qhat && O && status && train_err && growth && outcome && best, "NULL argument");
   DOPINF_REQUIRE((flags & ~DOPINF_SWEEP_AUTOTUNE) == 0, "unknown flag bits");

@@ -237,6 +237,7 @@ extern "C" size_t dopinf_preprocess_workspace(int64_t n, int64_t /*k*/, int nvar
 extern "C" int dopinf_preprocess(void* stream, int dtype, void* Q, int64_t n, int64_t k, int64_t ldq,
                                  int nvars, const int64_t* var_rows_h, unsigned flags, double* mean,
                                  double* scale, int* zero_range, int* info, void* ws, size_t ws_bytes) {
+  DOPINF_REQUIRE_WS_ALIGNED(ws);
   DOPINF_REQUIRE(dtype == DOPINF_F64 || dtype == DOPINF_F32, "dtype must be DOPINF_F64 or DOPINF_F32");
   DOPINF_REQUIRE(Q && mean && scale, "Q, mean and scale must be non-NULL");
   DOPINF_REQUIRE(n >= 1 && k >= 1 && ldq >= k, "need n >= 1, k >= 1, ldq >= k");

@@ -879,6 +879,7 @@ extern "C" int dopinf_rollout(void* stream, int n_r, const int* r_list_h, int n_
                               double max_growth, unsigned flags, const int* solve_status, double* traj,
                               double* train_err, double* growth, int* outcome, int* best, void* ws,
                               size_t ws_bytes) {
+  DOPINF_REQUIRE_WS_ALIGNED(ws);
   int rc = check_rollout_args(n_r, r_list_h, n_pairs, O, Qhat, ldqh, k_train, n_states, max_growth, flags, train_err,
                               growth, outcome, best);
   if (rc) return rc;
@@ -894,6 +895,7 @@ extern "C" int dopinf_rollout_continuous(void* stream, int n_r, const int* r_lis
                                          double max_growth, unsigned flags, const int* solve_status, double* traj,
                                          double* train_err, double* growth, int* outcome, int* best, void* ws,
                                          size_t ws_bytes) {
+  DOPINF_REQUIRE_WS_ALIGNED(ws);
   int rc = check_rollout_args(n_r, r_list_h, n_pairs, O, Qhat, ldqh, k_train, n_states, max_growth, flags, train_err,
                               growth, outcome, best);
   if (rc) return rc;

@@ -192,6 +192,7 @@ extern "C" size_t dopinf_stream_workspace(int64_t chunk_rows, int64_t k, int nva
 extern "C" int dopinf_preprocess_stream(void* stream, const double* Q_h, int64_t n, int64_t k, int64_t ldq, int nvars,
                                         const int64_t* var_rows_h, unsigned flags, double* mean, double* scale,
                                         int* zero_range, int* info, int64_t chunk_rows, void* ws, size_t ws_bytes) {
+  DOPINF_REQUIRE_WS_ALIGNED(ws);
   int rc = check_stream_args(Q_h, n, k, ldq, nvars, var_rows_h, chunk_rows);
   if (rc) return rc;
   DOPINF_REQUIRE(mean && scale, "mean and scale must be non-NULL");
@@ -235,6 +236,7 @@ extern "C" int dopinf_preprocess_stream(void* stream, const double* Q_h, int64_t
 extern "C" int dopinf_gram_stream(void* stream, const double* Q_h, int64_t n, int64_t k, int64_t ldq,
                                   const double* mean, const double* scale, int nvars, const int64_t* var_rows_h,
                                   double* D, int64_t ldd, int64_t chunk_rows, void* ws, size_t ws_bytes) {
+  DOPINF_REQUIRE_WS_ALIGNED(ws);
   int rc = check_stream_args(Q_h, n, k, ldq, nvars, var_rows_h, chunk_rows);
   if (rc) return rc;
   DOPINF_REQUIRE(D && ldd >= k, "D must be non-NULL with ldd >= k");

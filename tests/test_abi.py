@@ -51,6 +51,51 @@ def test_argument_errors_enqueue_nothing():
     assert rc == dp.E_ARG
 
 
+
+def declared_params():
+    """name -> parameter names of every function dopinf.h declares."""
+    txt = open(os.path.join(ROOT, "include", "dopinf.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    out = {}
+    for m in re.finditer(r"\b(dopinf_[a-z0-9_]+)\s*\(([^;{]*?)\)\s*;", txt, flags=re.S):
+        params = [p.strip() for p in m.group(2).split(",") if p.strip() and p.strip() != "void"]
+        out[m.group(1)] = [re.findall(r"\w+", p)[-1] for p in params]
+    return out
+
+
+def test_misaligned_workspace_is_rejected_first():
+    """Every call that takes a workspace rejects one that is not 256-byte
+    aligned with DOPINF_E_WORKSPACE before touching any other argument or the
+    device (all other arguments here are NULL or zero)."""
+    import paper_2504_14338_amd as dp
+    lib = dp.load()
+    takes_ws = {n: p for n, p in declared_params().items() if "ws" in p and n in dp._SIGS}
+    assert len(takes_ws) >= 17, sorted(takes_ws)
+    for name, params in sorted(takes_ws.items()):
+        argtypes, _ = dp._SIGS[name]
+        assert len(argtypes) == len(params), name
+        for bad in (8, 4096 + 16, 4096 + 128):
+            out = ctypes.c_void_p(1234)
+            args = []
+            for pname, t in zip(params, argtypes):
+                if pname == "ws":
+                    args.append(ctypes.c_void_p(bad))
+                elif pname == "ws_bytes":
+                    args.append(1 << 40)
+                elif pname == "sweep_out":
+                    args.append(ctypes.byref(out))
+                elif t in (ctypes.c_double, ctypes.c_float):
+                    args.append(0.0)
+                elif t == ctypes.c_void_p:
+                    args.append(None)
+                else:
+                    args.append(0)
+            rc = getattr(lib, name)(*args)
+            assert rc == dp.E_WORKSPACE, (name, bad, rc)
+            assert "256-byte aligned" in lib.dopinf_last_error().decode(), name
+            if name == "dopinf_sweep_create":
+                assert out.value is None
+
 def test_tuning_table_and_sweep_argument_checks():
     import paper_2504_14338_amd as dp
     lib = dp.load()
@@ -107,10 +152,10 @@ def test_lift_and_continuous_argument_errors():
     b = (ctypes.c_double * 1)(1e-3)
     # dt must be positive and the continuous form needs 3 snapshots
     rc = lib.dopinf_infer_continuous(None, ctypes.c_void_p(8), 10, 10, 0.0, 1, r, 1, b, b, ctypes.c_void_p(8),
-                                     ctypes.c_void_p(8), ctypes.c_void_p(8), 1 << 30)
+                                     ctypes.c_void_p(8), ctypes.c_void_p(4096), 1 << 30)
     assert rc == dp.E_ARG
     rc = lib.dopinf_infer_continuous(None, ctypes.c_void_p(8), 2, 2, 0.1, 1, r, 1, b, b, ctypes.c_void_p(8),
-                                     ctypes.c_void_p(8), ctypes.c_void_p(8), 1 << 30)
+                                     ctypes.c_void_p(8), ctypes.c_void_p(4096), 1 << 30)
     assert rc == dp.E_ARG
     assert lib.dopinf_infer_continuous_workspace(2, 1, r, 1) == 0
     assert lib.dopinf_infer_continuous_workspace(10, 1, r, 1) > lib.dopinf_infer_workspace(10, 1, r, 1)
