@@ -28,6 +28,7 @@ import pytest
 
 import oracle as orc
 import synth
+from lowp_emu import i8_emulate
 
 pytestmark = pytest.mark.gpu
 
@@ -47,31 +48,6 @@ def i8_excess(D, Dref, Qs):
     a = np.max(np.abs(Qs), axis=0)
     den = Qs.shape[0] * np.outer(a, a)
     return float(np.max(np.abs(D - Dref) / np.where(den > 0, den, 1.0)))
-
-
-def i8_emulate(Q, mean, scale, var_rows):
-    """The I8X6 arithmetic on the CPU from its definition: the same float64
-    transform, column max-abs, radix-254 slices (round half to even, as the
-    kernel's rint), the six kept products summed exactly (integer-valued
-    float64 sums stay below 2^53) and combined per level."""
-    n, k = Q.shape
-    rinv = np.empty(n)
-    for v in range(len(var_rows) - 1):
-        rinv[var_rows[v]:var_rows[v + 1]] = 1.0 / scale[v]
-    x = (Q.astype(np.float64) - mean[:, None]) * rinv[:, None]
-    a = np.max(np.abs(x), axis=0)
-    sc = np.where(a > 0, 127.0 / np.where(a > 0, a, 1.0), 0.0)
-    xs = x * sc[None, :]
-    t1 = np.rint(xs)
-    e = (xs - t1) * 254.0
-    t2 = np.rint(e)
-    t3 = np.rint((e - t2) * 254.0)
-    for t in (t1, t2, t3):
-        assert np.max(np.abs(t)) <= 127
-    L0 = t1.T @ t1
-    L1 = t1.T @ t2 + t2.T @ t1
-    L2 = t1.T @ t3 + t2.T @ t2 + t3.T @ t1
-    return ((L2 / 254.0 + L1) / 254.0 + L0) * np.outer(a, a) / 127.0 ** 2, x
 
 
 @pytest.mark.parametrize("n,k,nvars", [(8192, 600, 2), (3001, 130, 3), (777, 64, 1)])
