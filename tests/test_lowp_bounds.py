@@ -10,7 +10,9 @@ check the per-product constant by dense sampling (it holds, and a value
 just off a half unit loses within 3% of it), the slice ranges and the reconstruction, the
 bound on data whose columns span twelve decades, and that planted mistakes
 (a dropped level, one max-abs for all columns) exceed it, so the GPU tests'
-bound can tell a correct kernel from those mistakes.  CPU only."""
+bound can tell a correct kernel from those mistakes.  The last test pins
+the splits of the two bfloat16 forms that their GPU tolerances rest on.
+CPU only."""
 import numpy as np
 
 from lowp_emu import RADIX, TOP, i8_gram, split3
@@ -111,3 +113,46 @@ def test_planted_mistakes_exceed_the_bound():
     assert excess(i8_gram(x, drop_level=1), x) > 4 * I8_ROW
     # one max-abs for all columns loses the small columns entirely
     assert excess(i8_gram(x, global_scale=True), x) > 4 * I8_ROW
+
+
+def bf16_rn(x):
+    """float32 -> nearest bfloat16 (ties to even) -> float32, by torch's CPU
+    conversion."""
+    import torch
+    return torch.from_numpy(x).to(torch.bfloat16).to(torch.float32).numpy()
+
+
+def test_bfloat16_splits_of_the_two_split_forms():
+    """The split-bfloat16 forms write a float32 value x as hi = bf16(x),
+    lo = bf16(x - hi) (BF16X3) and further mid, lo (BF16X6), each
+    difference exact in float32.  Their GPU tolerances rest on
+    |x - hi - lo| <= 2^-16 |x| and on the three parts holding x with an error
+    of at most 2^-24 |x|; while all parts are normal float32 values the
+    three parts are exact, which this pins together with the two-part bound,
+    on random values over the whole exponent range and on low-bit patterns
+    at rounding ties."""
+    rng = np.random.default_rng(9)
+    x = (rng.standard_normal(400_000) * np.exp2(rng.integers(-100, 100, 400_000))).astype(np.float32)
+    bits = rng.integers(0, 1 << 23, 20_000).astype(np.uint32)
+    ties = ((bits & ~np.uint32(0xFFFF)) | np.uint32(0x8000) | (np.uint32(127) << 23)).view(np.float32)
+    x = np.concatenate([x, ties, -ties, ties * np.float32(2.0 ** -60)])
+    hi = bf16_rn(x)
+    r1 = x - hi
+    assert np.array_equal(r1.astype(np.float64), x.astype(np.float64) - hi.astype(np.float64))
+    lo2 = bf16_rn(r1)
+    ax = np.abs(x.astype(np.float64))
+    err2 = np.abs(x.astype(np.float64) - hi.astype(np.float64) - lo2.astype(np.float64))
+    assert np.max(err2 / ax) <= 2.0 ** -16
+    mid = bf16_rn(r1)
+    r2 = r1 - mid
+    lo3 = bf16_rn(r2)
+    err3 = x.astype(np.float64) - hi.astype(np.float64) - mid.astype(np.float64) - lo3.astype(np.float64)
+    # while the last part stays a normal float32 (|x| >= 2^-110; the data
+    # the forms see are scaled to at most 1, and values below 2^-110 of a
+    # column's max-abs do not move its Gram entries)
+    big = ax >= 2.0 ** -110
+    assert np.count_nonzero(~big) > 0
+    assert np.max(np.abs(err3[big]) / ax[big]) <= 2.0 ** -24
+    assert np.all(err3[big] == 0.0)
+    # the two-part remainder is not vacuous: it reaches ~2^-17 relative
+    assert np.max(err2 / ax) >= 2.0 ** -18
